@@ -189,6 +189,29 @@ def test_ewald_beta_invariance_mutual_and_permanent():
             assert np.abs(g - f[0]).max() < 1e-11 * scale
 
 
+@pytest.mark.parametrize("sep", [2.2, 4.5])
+def test_exclusion_removes_exactly_the_pair(sep):
+    """Excluding a pair (scale 0) must change the periodic field at its atoms by exactly the
+    pair's direct damped interaction (minimum image), whether the pair lies inside the
+    real-space cutoff (3 A) or beyond it; a half scale removes half of it."""
+    s = synth.tiny_cell(8, 12.0, 33, min_dist=1.5)
+    s.pos[1] = (s.pos[0] + np.array([sep, 0.0, 0.0])) % 12.0
+    s.cutoff, s.ewald_alpha = 3.0, 2.0
+    full = O.perm_field(s, 'ksum')
+    two = synth.tiny_cell(2, 100.0, 1)
+    two.pos = np.array([[0.0, 0.0, 0.0], [sep, 0.0, 0.0]])
+    for f in ("alpha", "thole", "q", "dip", "quad"):
+        setattr(two, f, getattr(s, f)[:2].copy())
+    direct = O.real_perm(two, idx=[0, 1], free_space=True, scaled=False)
+    for sc in (0.0, 0.5):
+        ptr, sj, ss = synth.build_csr(8, [(0, 1)], [sc])
+        s.sc_ptr, s.sc_j, s.sc_s = ptr, sj, ss
+        ex = O.perm_field(s, 'ksum')
+        assert np.allclose(full[:2] - ex[:2], (1 - sc) * direct, rtol=1e-9, atol=1e-12)
+        assert np.allclose(full[2:], ex[2:], rtol=1e-12, atol=1e-14)
+        s.sc_ptr, s.sc_j, s.sc_s = np.zeros(9, np.int32), np.zeros(0, np.int32), np.zeros(0)
+
+
 def _brute_dipole_lattice(s, mu, radius):
     L = s.box[0]
     m = int(np.ceil(radius))
