@@ -1,0 +1,171 @@
+/*
+ * amoeba.h — C ABI of the MI355X induced-dipole solver.
+ *
+ * The library solves for the induced dipoles mu of a Thole-damped point-dipole
+ * polarizable force field (AMOEBA type) in a periodic orthorhombic box,
+ *
+ *     (alpha^-1 - T) mu = E_perm,
+ *
+ * by preconditioned conjugate gradient with the diagonal preconditioner
+ * (paper: "Optimizations opportunities", the PCG of the polarization solver,
+ * and "Performance and Scalability Results" for the diagonal preconditioner
+ * and the convergence threshold).  T mu is the full Ewald field of the
+ * dipoles: a real-space, Thole-damped, erfc-screened pair sum within a sharp
+ * cutoff over a blocked neighbour list (paper: "Neighbor list", "Box
+ * partitioning", "List filtering"), a smooth-PME reciprocal part (paper:
+ * "Reciprocal space scheme": B-spline spread, forward FFT, scalar product,
+ * backward FFT, gather), and the Gaussian self field 4 beta^3/(3 sqrt(pi)) mu.
+ * Mixed precision (paper: "Precision study and Validation") computes pair and
+ * PME arithmetic in FP32 and accumulates fields in 64-bit fixed point, while
+ * the PCG vectors, dot products and convergence test stay FP64.
+ *
+ * Conventions for every entry point:
+ *  - Array arguments are DEVICE pointers (HIP device memory, e.g. from a torch
+ *    tensor), contiguous, row-major, in the caller's atom order; the library
+ *    permutes internally and never keeps or frees caller memory.  Scalar
+ *    outputs (energy, iteration count) are HOST pointers.
+ *  - Per-atom vectors are FP64 N x 3 (x,y,z); quadrupoles FP64 N x 6 as the
+ *    traceless Theta (point potential Theta:rr / r^5), order xx,xy,xz,yy,yz,zz.
+ *  - Units: Angstrom, e, e*A, e*A^2, A^3; fields in e/A^2; energies in
+ *    kcal/mol (C = 332.0637133 kcal*A/(mol e^2)); Debye only in tolerances
+ *    (1 e*A = 4.80320 D).
+ *  - All work is enqueued on the HIP stream given to amoeba_create; every call
+ *    returns after its outputs are complete.  A context is not thread-safe: use
+ *    one context per host thread.
+ *  - Errors: every call returns an amoeba_status; negative values are errors
+ *    with a message in amoeba_last_error().  Arguments are validated before
+ *    any output is written; on an error the outputs are unspecified.
+ */
+#ifndef AMOEBA_H
+#define AMOEBA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct amoeba_ctx amoeba_ctx;
+
+typedef enum amoeba_status {
+    AMOEBA_OK = 0,
+    AMOEBA_NOT_CONVERGED = 1,  /* outputs valid: mu is the last iterate, iterations = max_iter */
+    AMOEBA_E_INVALID = -1,     /* bad argument or parameter (message says which)               */
+    AMOEBA_E_NOMEM = -2,       /* device allocation failed or max_workspace_bytes exceeded      */
+    AMOEBA_E_DEVICE = -3,      /* no usable gfx950 device, or a HIP / rocFFT call failed        */
+    AMOEBA_E_LIST = -4,        /* block list missing or stale (an atom moved > buffer/2)        */
+    AMOEBA_E_OVERFLOW = -5,    /* a fixed-point field accumulator left its range                */
+    AMOEBA_E_NUMERIC = -6,     /* NaN/Inf in an input, or a PCG breakdown                       */
+    AMOEBA_E_STATE = -7        /* call order violated (e.g. no amoeba_set_atoms yet)             */
+} amoeba_status;
+
+typedef enum amoeba_precision {
+    AMOEBA_FP64 = 0,   /* all arithmetic in FP64, FP64 atomics                                 */
+    AMOEBA_MIXED = 1   /* FP32 pair/PME math, 64-bit fixed-point fields, FP64 PCG               */
+} amoeba_precision;
+
+typedef enum amoeba_guess_mode {
+    AMOEBA_GUESS_ZERO = 0,     /* mu0 = 0                                                      */
+    AMOEBA_GUESS_GIVEN = 1,    /* mu0 = mu_guess (e.g. the previous configuration's dipoles)   */
+    AMOEBA_GUESS_LEARNED = 2,  /* mu0 from the learned per-atom network (amoeba_guess_*)       */
+    AMOEBA_GUESS_BEST = 3      /* learned and given guesses both evaluated; the one with the
+                                  smaller preconditioned initial residual is used (zero if
+                                  mu_guess is NULL)                                           */
+} amoeba_guess_mode;
+
+typedef struct amoeba_params {
+    int32_t n_atoms;       /* N >= 1                                                          */
+    double box[3];         /* orthorhombic box edges (A)                                      */
+    double cutoff;         /* real-space cutoff rc (A); pairs with |r| < rc                   */
+    double buffer;         /* neighbour-list buffer (A) >= 0; list is valid while every atom
+                              stays within buffer/2 of its position at the last build        */
+    double ewald_alpha;    /* Ewald splitting beta (1/A) > 0                                  */
+    int32_t grid[3];       /* PME grid points per edge, each >= 2*order and 2,3,5,7-smooth    */
+    int32_t order;         /* B-spline order; must be 5                                      */
+    int32_t precision;     /* amoeba_precision                                                */
+    int64_t max_workspace_bytes; /* cap on device memory the context may allocate; 0 = none  */
+} amoeba_params;
+
+typedef struct amoeba_info {
+    int32_t n_atoms;
+    int32_t n_blocks;          /* 64-atom blocks (last one padded with phantom atoms)           */
+    int32_t n_tiles;           /* block x 64-atom tiles in the list (diagonal tiles included)  */
+    int32_t precision;
+    int64_t n_pairs;           /* in-cutoff unordered pairs at the last configuration           */
+    int64_t workspace_bytes;   /* device memory held by the context                             */
+    int32_t last_iterations;   /* PCG iterations of the last amoeba_polarize                    */
+    double last_rms_debye;     /* final preconditioned-residual rms of the last solve (D)      */
+} amoeba_info;
+
+/* Create a context for one system size and one parameter set on the current HIP device,
+ * enqueueing on `hip_stream` (a hipStream_t; NULL = the default stream).  Validates the
+ * parameters on the host first (AMOEBA_E_INVALID, no device touched), then checks the device
+ * (AMOEBA_E_DEVICE unless it is gfx950), allocates the workspace and builds the PME tables and
+ * FFT plans.  *out is set only on success. */
+int amoeba_create(const amoeba_params* params, void* hip_stream, amoeba_ctx** out);
+
+/* Release every device buffer and plan of the context.  NULL is accepted. */
+int amoeba_destroy(amoeba_ctx* ctx);
+
+/* Message of the last error on this context ("" if none); valid until the next call. */
+const char* amoeba_last_error(const amoeba_ctx* ctx);
+
+/* Message of the last amoeba_create failure in this thread (no context exists then). */
+const char* amoeba_create_error(void);
+
+/* Per-atom polarization parameters and the scaled pairs of the permanent field.
+ *   alpha[N]  polarizabilities (A^3) > 0;  thole[N] Thole a >= 0 (pair uses min(a_i, a_j)).
+ *   sc_ptr[N+1], sc_j[n_scaled], sc_s[n_scaled]: CSR of pairs whose permanent-field interaction
+ *   is multiplied by s (s = 0 excludes the pair; AMOEBA's polarization p-scale).  Both
+ *   directions of every pair must be listed with the same s; j != i.  The correction is applied
+ *   at any separation (paper, final real-space scheme: scaled interactions are corrected in a
+ *   separate pass).  The mutual dipole field T is never scaled (every pair Thole-damped).
+ * Validated on the device (AMOEBA_E_INVALID names the first violation). */
+int amoeba_set_atoms(amoeba_ctx* ctx, const double* alpha, const double* thole,
+                     const int32_t* sc_ptr, const int32_t* sc_j, const double* sc_s,
+                     int64_t n_scaled);
+
+/* Build the blocked neighbour list for positions pos[N][3] (paper "Box partitioning",
+ * "List filtering"): atoms are sorted along a column-serpentine cell order into 64-atom blocks,
+ * block pairs within cutoff + buffer are found, and for every block the atoms of later blocks
+ * within cutoff + buffer of any of its atoms are packed into 64-atom tiles.  Positions may lie
+ * outside the box (they are wrapped). */
+int amoeba_build_blocklist(amoeba_ctx* ctx, const double* pos);
+
+/* Permanent field E_perm[N][3] (e/A^2) of charges q[N], dipoles dip[N][3] and traceless
+ * quadrupoles quad[N][6] at positions pos (paper "Global scheme": real space + reciprocal
+ * space): real-space tiles with Thole damping lambda3/5/7, the scaled-pair correction at any
+ * separation, smooth PME of the multipolar density, and the dipole self field. */
+int amoeba_perm_field(amoeba_ctx* ctx, const double* pos, const double* q, const double* dip,
+                      const double* quad, double* e_perm);
+
+/* out[N][3] = (alpha^-1 - T) mu for dipoles mu[N][3] (e*A) at positions pos: one matrix-vector
+ * product of the PCG (paper "Optimizations opportunities": the polarization matrix-vector
+ * product of every iteration). */
+int amoeba_dipole_matvec(amoeba_ctx* ctx, const double* pos, const double* mu, double* out);
+
+/* The two parts of T mu separately: e_real[N][3] the real-space pair field and e_recip[N][3]
+ * the smooth-PME reciprocal field (without the self term).  Either pointer may be NULL.
+ * Diagnostic entry: the same kernels as amoeba_dipole_matvec. */
+int amoeba_dipole_field_parts(amoeba_ctx* ctx, const double* pos, const double* mu,
+                              double* e_real, double* e_recip);
+
+/* Solve (alpha^-1 - T) mu = e_perm by PCG with z = alpha r, stopping when the rms over atoms
+ * of z is below tol_debye (Debye), or after max_iter iterations (AMOEBA_NOT_CONVERGED; mu_out
+ * is then the last iterate).  guess_mode selects mu0 (mu_guess may be NULL for ZERO/LEARNED).
+ * Outputs: mu_out[N][3] (device, e*A); *e_pol_out = -1/2 C sum_i mu_i . e_perm_i (host,
+ * kcal/mol); *iters_out = matrix-vector products after the initial residual (host).  In mixed
+ * precision the true residual e_perm - A mu is recomputed once the recursive one passes the
+ * tolerance, and iteration continues if it does not. */
+int amoeba_polarize(amoeba_ctx* ctx, const double* pos, const double* e_perm,
+                    const double* mu_guess, int32_t guess_mode, double tol_debye, int32_t max_iter,
+                    double* mu_out, double* e_pol_out, int32_t* iters_out);
+
+/* Sizes and counters of the context (host struct). */
+int amoeba_get_info(const amoeba_ctx* ctx, amoeba_info* out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* AMOEBA_H */

@@ -1,0 +1,221 @@
+"""ctypes binding of libamoeba.so (include/amoeba.h).
+
+Argument marshalling only: tensors are checked for device, dtype, shape and contiguity and
+their device pointers are handed to the C entry points of the same names; every step of the
+computation runs in the library's HIP kernels.  There is no fallback: if the built library or
+a GPU is missing, the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libamoeba.so")
+
+AMOEBA_OK = 0
+AMOEBA_NOT_CONVERGED = 1
+AMOEBA_E_INVALID = -1
+AMOEBA_E_NOMEM = -2
+AMOEBA_E_DEVICE = -3
+AMOEBA_E_LIST = -4
+AMOEBA_E_OVERFLOW = -5
+AMOEBA_E_NUMERIC = -6
+AMOEBA_E_STATE = -7
+STATUS_NAMES = {0: "OK", 1: "NOT_CONVERGED", -1: "E_INVALID", -2: "E_NOMEM", -3: "E_DEVICE", -4: "E_LIST",
+                -5: "E_OVERFLOW", -6: "E_NUMERIC", -7: "E_STATE"}
+
+AMOEBA_FP64 = 0
+AMOEBA_MIXED = 1
+AMOEBA_GUESS_ZERO = 0
+AMOEBA_GUESS_GIVEN = 1
+AMOEBA_GUESS_LEARNED = 2
+AMOEBA_GUESS_BEST = 3
+
+
+class amoeba_params(ctypes.Structure):
+    _fields_ = [("n_atoms", ctypes.c_int32), ("box", ctypes.c_double * 3), ("cutoff", ctypes.c_double),
+                ("buffer", ctypes.c_double), ("ewald_alpha", ctypes.c_double), ("grid", ctypes.c_int32 * 3),
+                ("order", ctypes.c_int32), ("precision", ctypes.c_int32), ("max_workspace_bytes", ctypes.c_int64)]
+
+
+class amoeba_info(ctypes.Structure):
+    _fields_ = [("n_atoms", ctypes.c_int32), ("n_blocks", ctypes.c_int32), ("n_tiles", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("n_pairs", ctypes.c_int64), ("workspace_bytes", ctypes.c_int64),
+                ("last_iterations", ctypes.c_int32), ("last_rms_debye", ctypes.c_double)]
+
+
+class AmoebaError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+_P = ctypes.c_void_p
+
+
+def lib() -> ctypes.CDLL:
+    """Load libamoeba.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2011_01207_amd/build.py "
+                               "(or __graft_entry__.build())")
+        L = ctypes.CDLL(LIB_PATH)
+        L.amoeba_create.argtypes = [ctypes.POINTER(amoeba_params), _P, ctypes.POINTER(_P)]
+        L.amoeba_destroy.argtypes = [_P]
+        L.amoeba_last_error.argtypes = [_P]
+        L.amoeba_last_error.restype = ctypes.c_char_p
+        L.amoeba_create_error.argtypes = []
+        L.amoeba_create_error.restype = ctypes.c_char_p
+        L.amoeba_set_atoms.argtypes = [_P, _P, _P, _P, _P, _P, ctypes.c_int64]
+        L.amoeba_build_blocklist.argtypes = [_P, _P]
+        L.amoeba_perm_field.argtypes = [_P, _P, _P, _P, _P, _P]
+        L.amoeba_dipole_matvec.argtypes = [_P, _P, _P, _P]
+        L.amoeba_dipole_field_parts.argtypes = [_P, _P, _P, _P, _P]
+        L.amoeba_polarize.argtypes = [_P, _P, _P, _P, ctypes.c_int32, ctypes.c_double, ctypes.c_int32, _P,
+                                      ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32)]
+        L.amoeba_get_info.argtypes = [_P, ctypes.POINTER(amoeba_info)]
+        _lib = L
+    return _lib
+
+
+def _ptr(t, dtype, shape=None, name="array"):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    return t.data_ptr()
+
+
+class Context:
+    """One amoeba_ctx: a fixed system size, box and parameter set on the current device/stream."""
+
+    def __init__(self, n_atoms, box, cutoff=7.0, buffer=0.0, ewald_alpha=0.545, grid=(24, 24, 24), order=5,
+                 precision="fp64", max_workspace_bytes=0, stream=None):
+        L = lib()
+        p = amoeba_params()
+        p.n_atoms = int(n_atoms)
+        for a in range(3):
+            p.box[a] = float(box[a])
+            p.grid[a] = int(grid[a])
+        p.cutoff, p.buffer, p.ewald_alpha = float(cutoff), float(buffer), float(ewald_alpha)
+        p.order = int(order)
+        p.precision = {"fp64": AMOEBA_FP64, "mixed": AMOEBA_MIXED}[precision] if isinstance(precision, str) \
+            else int(precision)
+        p.max_workspace_bytes = int(max_workspace_bytes)
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream if torch.cuda.is_available() else 0
+        self.stream = stream
+        h = _P()
+        st = L.amoeba_create(ctypes.byref(p), _P(stream), ctypes.byref(h))
+        if st != AMOEBA_OK:
+            raise AmoebaError(st, L.amoeba_create_error().decode())
+        self.h = h
+        self.n = int(n_atoms)
+        self.params = p
+
+    def _check(self, st, ok=(AMOEBA_OK,)):
+        if st not in ok:
+            raise AmoebaError(st, lib().amoeba_last_error(self.h).decode())
+        return st
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().amoeba_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # entry points ---------------------------------------------------------------------------
+    def set_atoms(self, alpha, thole, sc_ptr, sc_j, sc_s):
+        n = self.n
+        nnz = int(sc_j.numel())
+        return self._check(lib().amoeba_set_atoms(
+            self.h, _ptr(alpha, torch.float64, (n,), "alpha"), _ptr(thole, torch.float64, (n,), "thole"),
+            _ptr(sc_ptr, torch.int32, (n + 1,), "sc_ptr"),
+            _ptr(sc_j, torch.int32, (nnz,), "sc_j") if nnz else None,
+            _ptr(sc_s, torch.float64, (nnz,), "sc_s") if nnz else None, nnz))
+
+    def build_blocklist(self, pos):
+        return self._check(lib().amoeba_build_blocklist(self.h, _ptr(pos, torch.float64, (self.n, 3), "pos")))
+
+    def perm_field(self, pos, q, dip, quad, out=None):
+        n = self.n
+        out = torch.empty((n, 3), dtype=torch.float64, device=pos.device) if out is None else out
+        self._check(lib().amoeba_perm_field(
+            self.h, _ptr(pos, torch.float64, (n, 3), "pos"), _ptr(q, torch.float64, (n,), "q"),
+            _ptr(dip, torch.float64, (n, 3), "dip"), _ptr(quad, torch.float64, (n, 6), "quad"),
+            _ptr(out, torch.float64, (n, 3), "e_perm")))
+        return out
+
+    def dipole_matvec(self, pos, mu, out=None):
+        n = self.n
+        out = torch.empty((n, 3), dtype=torch.float64, device=pos.device) if out is None else out
+        self._check(lib().amoeba_dipole_matvec(self.h, _ptr(pos, torch.float64, (n, 3), "pos"),
+                                               _ptr(mu, torch.float64, (n, 3), "mu"),
+                                               _ptr(out, torch.float64, (n, 3), "out")))
+        return out
+
+    def dipole_field_parts(self, pos, mu):
+        n = self.n
+        er = torch.empty((n, 3), dtype=torch.float64, device=pos.device)
+        ek = torch.empty((n, 3), dtype=torch.float64, device=pos.device)
+        self._check(lib().amoeba_dipole_field_parts(self.h, _ptr(pos, torch.float64, (n, 3), "pos"),
+                                                    _ptr(mu, torch.float64, (n, 3), "mu"), er.data_ptr(),
+                                                    ek.data_ptr()))
+        return er, ek
+
+    def polarize(self, pos, e_perm, mu_guess=None, guess_mode=None, tol_debye=1e-5, max_iter=500, out=None):
+        """Returns (mu, e_pol kcal/mol, iterations, status); status is OK or NOT_CONVERGED."""
+        n = self.n
+        if guess_mode is None:
+            guess_mode = AMOEBA_GUESS_ZERO if mu_guess is None else AMOEBA_GUESS_GIVEN
+        out = torch.empty((n, 3), dtype=torch.float64, device=pos.device) if out is None else out
+        ep = ctypes.c_double(0.0)
+        it = ctypes.c_int32(0)
+        st = self._check(lib().amoeba_polarize(
+            self.h, _ptr(pos, torch.float64, (n, 3), "pos"), _ptr(e_perm, torch.float64, (n, 3), "e_perm"),
+            _ptr(mu_guess, torch.float64, (n, 3), "mu_guess"), int(guess_mode), float(tol_debye), int(max_iter),
+            _ptr(out, torch.float64, (n, 3), "mu_out"), ctypes.byref(ep), ctypes.byref(it)),
+            ok=(AMOEBA_OK, AMOEBA_NOT_CONVERGED))
+        return out, ep.value, it.value, st
+
+    def info(self) -> dict:
+        inf = amoeba_info()
+        self._check(lib().amoeba_get_info(self.h, ctypes.byref(inf)))
+        return {k: getattr(inf, k) for k, _ in amoeba_info._fields_}
+
+
+def context_for(system, precision="fp64", device="cuda", **kw):
+    """Create a Context for a synthetic System and upload its parameters; returns
+    (ctx, tensors dict) with pos, q, dip, quad, alpha, thole and the scaled-pair CSR on device."""
+    t = {
+        "pos": torch.tensor(system.pos, dtype=torch.float64, device=device),
+        "q": torch.tensor(system.q, dtype=torch.float64, device=device),
+        "dip": torch.tensor(system.dip, dtype=torch.float64, device=device),
+        "quad": torch.tensor(system.quad, dtype=torch.float64, device=device),
+        "alpha": torch.tensor(system.alpha, dtype=torch.float64, device=device),
+        "thole": torch.tensor(system.thole, dtype=torch.float64, device=device),
+        "sc_ptr": torch.tensor(system.sc_ptr, dtype=torch.int32, device=device),
+        "sc_j": torch.tensor(system.sc_j, dtype=torch.int32, device=device),
+        "sc_s": torch.tensor(system.sc_s, dtype=torch.float64, device=device),
+    }
+    ctx = Context(system.n, system.box, cutoff=system.cutoff, buffer=system.buffer,
+                  ewald_alpha=system.ewald_alpha, grid=system.grid, order=system.order, precision=precision, **kw)
+    ctx.set_atoms(t["alpha"], t["thole"], t["sc_ptr"], t["sc_j"], t["sc_s"])
+    ctx.build_blocklist(t["pos"])
+    return ctx, t

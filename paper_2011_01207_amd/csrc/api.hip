@@ -1,0 +1,589 @@
+// C ABI of the induced-dipole library: context, validation, and the entry points declared in
+// include/amoeba.h.  Host code here only validates, allocates and sequences kernels; every
+// step of the computation runs in the HIP kernels of this directory.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+
+#include "common.h"
+#include "reduce.h"
+
+namespace amoeba {
+
+int set_error(amoeba_ctx* c, int code, const std::string& msg)
+{
+    if (c)
+        c->err = msg;
+    return code;
+}
+
+int hip_check(amoeba_ctx* c, hipError_t e, const char* what)
+{
+    if (e == hipSuccess)
+        return AMOEBA_OK;
+    std::string m = std::string(what) + ": " + hipGetErrorString(e);
+    return set_error(c, e == hipErrorOutOfMemory ? AMOEBA_E_NOMEM : AMOEBA_E_DEVICE, m);
+}
+
+int ctx_alloc(amoeba_ctx* c, void** p, size_t bytes)
+{
+    if (bytes == 0)
+        bytes = 16;
+    if (c->prm.max_workspace_bytes > 0 && c->ws_bytes + (int64_t)bytes > c->prm.max_workspace_bytes)
+        return set_error(c, AMOEBA_E_NOMEM, "device workspace would exceed max_workspace_bytes (" +
+                                                std::to_string(c->ws_bytes + (int64_t)bytes) + " > " +
+                                                std::to_string(c->prm.max_workspace_bytes) + ")");
+    void* q = nullptr;
+    hipError_t e = hipMalloc(&q, bytes);
+    if (e != hipSuccess)
+        return set_error(c, AMOEBA_E_NOMEM, std::string("hipMalloc failed: ") + hipGetErrorString(e));
+    hipMemsetAsync(q, 0, bytes, c->stream);
+    c->allocs.push_back(q);
+    c->ws_bytes += (int64_t)bytes;
+    *p = q;
+    return AMOEBA_OK;
+}
+
+// ------------------------------------------------------------------------------------------
+// validation kernels
+// ------------------------------------------------------------------------------------------
+__global__ void k_validate_atoms(int n, const double* __restrict__ alpha, const double* __restrict__ thole,
+                                 const int* __restrict__ ptr, const int* __restrict__ sj,
+                                 const double* __restrict__ ss, long long nnz, int* __restrict__ flags)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i > n)
+        return;
+    if (i == n) {
+        if (ptr[0] != 0 || (long long)ptr[n] != nnz)
+            atomicOr(flags, kFlagBadCsr);
+        return;
+    }
+    double a = alpha[i], t = thole[i];
+    if (!(a > 0.0) || !isfinite(a))
+        atomicOr(flags, kFlagBadAlpha);
+    if (!(t >= 0.0) || !isfinite(t))
+        atomicOr(flags, kFlagBadThole);
+    int b = ptr[i], e = ptr[i + 1];
+    if (b > e || b < 0 || (long long)e > nnz) {
+        atomicOr(flags, kFlagBadCsr);
+        return;
+    }
+    for (int k = b; k < e; ++k) {
+        int j = sj[k];
+        double s = ss[k];
+        if (j < 0 || j >= n || j == i || !isfinite(s)) {
+            atomicOr(flags, kFlagBadCsr);
+            return;
+        }
+        // the reverse entry must exist with the same scale
+        int jb = ptr[j], je = ptr[j + 1];
+        bool found = false;
+        if (jb >= 0 && je <= nnz && jb <= je)
+            for (int m = jb; m < je; ++m)
+                if (sj[m] == i && ss[m] == s) {
+                    found = true;
+                    break;
+                }
+        if (!found) {
+            atomicOr(flags, kFlagBadCsr);
+            return;
+        }
+    }
+}
+
+__global__ void k_check_finite(size_t n, const double* __restrict__ v, int* __restrict__ flags)
+{
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n && !isfinite(v[i]))
+        atomicOr(flags, kFlagNonFinite);
+}
+
+__global__ void k_check_overflow(size_t n, const double* __restrict__ v, double lim, int* __restrict__ flags)
+{
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n && !(fabs(v[i]) < lim))
+        atomicOr(flags, isfinite(v[i]) ? kFlagOverflow : kFlagNonFinite);
+}
+
+// multipoles into slot order: (q, d), (Txx, Txy, Txz, Tyy), (Tyz, Tzz, 0, 0); traceless check
+__global__ void k_gather_mpole(int npad, const int* __restrict__ perm, const double* __restrict__ q,
+                               const double* __restrict__ dip, const double* __restrict__ quad,
+                               double4* __restrict__ md, float4* __restrict__ mf, int* __restrict__ flags)
+{
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= npad)
+        return;
+    int a = perm[s];
+    double v[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    if (a >= 0) {
+        v[0] = q[a];
+        for (int c = 0; c < 3; ++c)
+            v[1 + c] = dip[3 * (size_t)a + c];
+        for (int c = 0; c < 6; ++c)
+            v[4 + c] = quad[6 * (size_t)a + c];
+        for (int c = 0; c < 10; ++c)
+            if (!isfinite(v[c]))
+                atomicOr(flags, kFlagNonFinite);
+        double tr = v[4] + v[7] + v[9];
+        double sc = fabs(v[4]) + fabs(v[7]) + fabs(v[9]);
+        if (fabs(tr) > 1e-10 * (1.0 + sc))
+            atomicOr(flags, kFlagBadCsr);  // reported as "quadrupole not traceless"
+    }
+    md[3 * (size_t)s] = make_double4(v[0], v[1], v[2], v[3]);
+    md[3 * (size_t)s + 1] = make_double4(v[4], v[5], v[6], v[7]);
+    md[3 * (size_t)s + 2] = make_double4(v[8], v[9], 0.0, 0.0);
+    if (mf) {
+        mf[3 * (size_t)s] = make_float4((float)v[0], (float)v[1], (float)v[2], (float)v[3]);
+        mf[3 * (size_t)s + 1] = make_float4((float)v[4], (float)v[5], (float)v[6], (float)v[7]);
+        mf[3 * (size_t)s + 2] = make_float4((float)v[8], (float)v[9], 0.f, 0.f);
+    }
+}
+
+__global__ void k_acc_to_vec(size_t n3, const unsigned long long* __restrict__ fx, const double* __restrict__ d,
+                             double* __restrict__ out)
+{
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n3)
+        return;
+    out[i] = fx ? (double)(long long)fx[i] * kFixInv : d[i];
+}
+
+static inline int nblk(size_t n, int b) { return (int)((n + b - 1) / b); }
+
+int sort_params(amoeba_ctx* c);
+
+static int read_flags(amoeba_ctx* c, int* out)
+{
+    hipMemcpyAsync(c->flags_host, c->flags, sizeof(int), hipMemcpyDeviceToHost, c->stream);
+    int rc = hip_check(c, hipStreamSynchronize(c->stream), "flags");
+    *out = c->flags_host[0];
+    return rc;
+}
+
+static int check_vec_finite(amoeba_ctx* c, const double* v, size_t n, const char* what)
+{
+    hipMemsetAsync(c->flags, 0, sizeof(int), c->stream);
+    hipLaunchKernelGGL(k_check_finite, dim3(nblk(n, 256)), dim3(256), 0, c->stream, n, v, c->flags);
+    int f = 0, rc = read_flags(c, &f);
+    if (rc)
+        return rc;
+    if (f & kFlagNonFinite)
+        return set_error(c, AMOEBA_E_NUMERIC, std::string("non-finite value in ") + what);
+    return AMOEBA_OK;
+}
+
+static int ready(amoeba_ctx* c, const char* who)
+{
+    if (!c->atoms_set)
+        return set_error(c, AMOEBA_E_STATE, std::string(who) + ": amoeba_set_atoms has not been called");
+    if (!c->list_built)
+        return set_error(c, AMOEBA_E_LIST, std::string(who) + ": amoeba_build_blocklist has not been called");
+    return AMOEBA_OK;
+}
+
+static int check_overflow(amoeba_ctx* c, const double* v_slot)
+{
+    if (!c->mixed)
+        return AMOEBA_OK;
+    size_t n3 = 3 * (size_t)c->npad;
+    hipMemsetAsync(c->flags, 0, sizeof(int), c->stream);
+    hipLaunchKernelGGL(k_check_overflow, dim3(nblk(n3, 256)), dim3(256), 0, c->stream, n3, v_slot, 4.0e6, c->flags);
+    int f = 0, rc = read_flags(c, &f);
+    if (rc)
+        return rc;
+    if (f & kFlagNonFinite)
+        return set_error(c, AMOEBA_E_NUMERIC, "non-finite field");
+    if (f & kFlagOverflow)
+        return set_error(c, AMOEBA_E_OVERFLOW, "field outside the fixed-point range (|E| >= 4e6 e/A^2)");
+    return AMOEBA_OK;
+}
+
+}  // namespace amoeba
+
+using namespace amoeba;
+
+static thread_local std::string g_create_error;
+
+extern "C" {
+
+const char* amoeba_create_error(void) { return g_create_error.c_str(); }
+
+int amoeba_create(const amoeba_params* p, void* hip_stream, amoeba_ctx** out)
+{
+    g_create_error.clear();
+    auto bad = [](int code, const std::string& m) {
+        g_create_error = m;
+        return code;
+    };
+    if (!p || !out)
+        return bad(AMOEBA_E_INVALID, "amoeba_create: NULL params or out");
+    *out = nullptr;
+    if (p->n_atoms < 1 || p->n_atoms > (1 << 26))
+        return bad(AMOEBA_E_INVALID, "n_atoms must be in [1, 2^26]");
+    double bmin = 1e300;
+    for (int a = 0; a < 3; ++a) {
+        if (!(p->box[a] > 0.0) || !std::isfinite(p->box[a]))
+            return bad(AMOEBA_E_INVALID, "box edges must be positive and finite");
+        bmin = std::fmin(bmin, p->box[a]);
+    }
+    if (!(p->cutoff > 0.0) || !std::isfinite(p->cutoff))
+        return bad(AMOEBA_E_INVALID, "cutoff must be positive");
+    if (!(p->buffer >= 0.0) || !std::isfinite(p->buffer))
+        return bad(AMOEBA_E_INVALID, "buffer must be >= 0");
+    if (!(p->cutoff + p->buffer < 0.5 * bmin))
+        return bad(AMOEBA_E_INVALID, "cutoff + buffer must be smaller than half the smallest box edge");
+    if (!(p->ewald_alpha > 0.0) || !std::isfinite(p->ewald_alpha))
+        return bad(AMOEBA_E_INVALID, "ewald_alpha must be positive");
+    if (p->order != 5)
+        return bad(AMOEBA_E_INVALID, "only B-spline order 5 is supported");
+    for (int a = 0; a < 3; ++a)
+        if (p->grid[a] < 2 * p->order || p->grid[a] > 2048)
+            return bad(AMOEBA_E_INVALID, "grid sizes must be in [2*order, 2048]");
+    if (p->precision != AMOEBA_FP64 && p->precision != AMOEBA_MIXED)
+        return bad(AMOEBA_E_INVALID, "precision must be AMOEBA_FP64 or AMOEBA_MIXED");
+    if (p->max_workspace_bytes < 0)
+        return bad(AMOEBA_E_INVALID, "max_workspace_bytes must be >= 0");
+
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1)
+        return bad(AMOEBA_E_DEVICE, "no HIP device available");
+    int dev = 0;
+    hipGetDevice(&dev);
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess)
+        return bad(AMOEBA_E_DEVICE, "hipGetDeviceProperties failed");
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return bad(AMOEBA_E_DEVICE, std::string("this library is built for gfx950; device is ") + prop.gcnArchName);
+
+    amoeba_ctx* c = new amoeba_ctx();
+    c->prm = *p;
+    c->stream = (hipStream_t)hip_stream;
+    c->device = dev;
+    c->n = p->n_atoms;
+    c->nb = (c->n + kBlock - 1) / kBlock;
+    c->npad = c->nb * kBlock;
+    c->mixed = p->precision == AMOEBA_MIXED;
+    int rc = AMOEBA_OK;
+    size_t np = c->npad, n3 = 3 * np;
+    size_t part_n = (size_t)std::max(nblk(np, 256), kRedBlocks) * 4;
+    do {
+        if ((rc = ctx_alloc(c, (void**)&c->perm, sizeof(int) * np)) ||
+            (rc = ctx_alloc(c, (void**)&c->slot, sizeof(int) * c->n)) ||
+            (rc = ctx_alloc(c, (void**)&c->par_d, sizeof(double4) * np)) ||
+            (rc = ctx_alloc(c, (void**)&c->par_f, sizeof(float4) * np)) ||
+            (rc = ctx_alloc(c, (void**)&c->sc_ptr, sizeof(int) * (np + 1))) ||
+            (rc = ctx_alloc(c, (void**)&c->sc_ptr_in, sizeof(int) * (c->n + 1))) ||
+            (rc = ctx_alloc(c, (void**)&c->alpha_in, sizeof(double) * c->n)) ||
+            (rc = ctx_alloc(c, (void**)&c->thole_in, sizeof(double) * c->n)) ||
+            (rc = ctx_alloc(c, (void**)&c->pos_s, sizeof(double4) * np)) ||
+            (rc = ctx_alloc(c, (void**)&c->pos_ref, sizeof(double4) * np)) ||
+            (rc = ctx_alloc(c, (void**)&c->blk_org, sizeof(double4) * c->nb)) ||
+            (rc = ctx_alloc(c, (void**)&c->off_d, sizeof(double4) * np)) ||
+            (rc = ctx_alloc(c, (void**)&c->off_f, sizeof(float4) * np)) ||
+            (rc = ctx_alloc(c, (void**)&c->blk_tile0, sizeof(int) * (c->nb + 1))) ||
+            (rc = ctx_alloc(c, (void**)&c->erec, sizeof(double) * n3)) ||
+            (rc = ctx_alloc(c, (void**)&c->v_mu, sizeof(double) * n3)) ||
+            (rc = ctx_alloc(c, (void**)&c->v_r, sizeof(double) * n3)) ||
+            (rc = ctx_alloc(c, (void**)&c->v_z, sizeof(double) * n3)) ||
+            (rc = ctx_alloc(c, (void**)&c->v_p, sizeof(double) * n3)) ||
+            (rc = ctx_alloc(c, (void**)&c->v_q, sizeof(double) * n3)) ||
+            (rc = ctx_alloc(c, (void**)&c->v_e, sizeof(double) * n3)) ||
+            (rc = ctx_alloc(c, (void**)&c->sc, sizeof(PcgScalars))) ||
+            (rc = ctx_alloc(c, (void**)&c->red.part, sizeof(double) * part_n)) ||
+            (rc = ctx_alloc(c, (void**)&c->red.ticket, sizeof(unsigned int) * 4)) ||
+            (rc = ctx_alloc(c, (void**)&c->flags, sizeof(int) * 4)) ||
+            (rc = ctx_alloc(c, (void**)&c->counter, sizeof(unsigned long long) * 2)))
+            break;
+        if (c->mixed) {
+            if ((rc = ctx_alloc(c, (void**)&c->acc_fx, sizeof(unsigned long long) * n3)) ||
+                (rc = ctx_alloc(c, (void**)&c->pv_f, sizeof(float4) * np)))
+                break;
+        } else {
+            if ((rc = ctx_alloc(c, (void**)&c->acc_d, sizeof(double) * n3)) ||
+                (rc = ctx_alloc(c, (void**)&c->pv_d, sizeof(double4) * np)))
+                break;
+        }
+        if (hipHostMalloc((void**)&c->sc_host, sizeof(PcgScalars) * 2, hipHostMallocDefault) != hipSuccess ||
+            hipHostMalloc((void**)&c->flags_host, 64, hipHostMallocDefault) != hipSuccess) {
+            rc = set_error(c, AMOEBA_E_NOMEM, "pinned host allocation failed");
+            break;
+        }
+        if (hipEventCreateWithFlags(&c->ev[0], hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&c->ev[1], hipEventDisableTiming) != hipSuccess) {
+            rc = set_error(c, AMOEBA_E_DEVICE, "hipEventCreate failed");
+            break;
+        }
+        if ((rc = pme_setup(c)))
+            break;
+        rc = hip_check(c, hipStreamSynchronize(c->stream), "amoeba_create");
+    } while (false);
+    if (rc != AMOEBA_OK) {
+        g_create_error = c->err;
+        amoeba_destroy(c);
+        return rc;
+    }
+    *out = c;
+    return AMOEBA_OK;
+}
+
+int amoeba_destroy(amoeba_ctx* c)
+{
+    if (!c)
+        return AMOEBA_OK;
+    if (c->stream || true)
+        hipStreamSynchronize(c->stream);
+    if (c->plan_fwd)
+        rocfft_plan_destroy(c->plan_fwd);
+    if (c->plan_bwd)
+        rocfft_plan_destroy(c->plan_bwd);
+    if (c->exec_fwd)
+        rocfft_execution_info_destroy(c->exec_fwd);
+    if (c->exec_bwd)
+        rocfft_execution_info_destroy(c->exec_bwd);
+    for (void* p : c->allocs)
+        hipFree(p);
+    if (c->sc_host)
+        hipHostFree(c->sc_host);
+    if (c->flags_host)
+        hipHostFree(c->flags_host);
+    for (auto& e : c->ev)
+        if (e)
+            hipEventDestroy(e);
+    delete c;
+    return AMOEBA_OK;
+}
+
+const char* amoeba_last_error(const amoeba_ctx* c) { return c ? c->err.c_str() : "NULL context"; }
+
+int amoeba_set_atoms(amoeba_ctx* c, const double* alpha, const double* thole, const int32_t* sc_ptr,
+                     const int32_t* sc_j, const double* sc_s, int64_t n_scaled)
+{
+    if (!c)
+        return AMOEBA_E_INVALID;
+    c->err.clear();
+    if (!alpha || !thole || !sc_ptr)
+        return set_error(c, AMOEBA_E_INVALID, "amoeba_set_atoms: NULL alpha, thole or sc_ptr");
+    if (n_scaled < 0 || n_scaled > (int64_t)1 << 31)
+        return set_error(c, AMOEBA_E_INVALID, "amoeba_set_atoms: n_scaled out of range");
+    if (n_scaled > 0 && (!sc_j || !sc_s))
+        return set_error(c, AMOEBA_E_INVALID, "amoeba_set_atoms: NULL sc_j or sc_s with n_scaled > 0");
+    hipStream_t st = c->stream;
+    int rc;
+    if (n_scaled > c->n_scaled || !c->sc_j_in) {
+        size_t cap = (size_t)std::max<int64_t>(n_scaled, 1);
+        if ((rc = ctx_alloc(c, (void**)&c->sc_j_in, sizeof(int) * cap)) ||
+            (rc = ctx_alloc(c, (void**)&c->sc_s_in, sizeof(double) * cap)) ||
+            (rc = ctx_alloc(c, (void**)&c->sc_j, sizeof(int) * cap)) ||
+            (rc = ctx_alloc(c, (void**)&c->sc_s, sizeof(double) * cap)))
+            return rc;
+    }
+    hipMemsetAsync(c->flags, 0, sizeof(int), st);
+    hipLaunchKernelGGL(k_validate_atoms, dim3(nblk(c->n + 1, 256)), dim3(256), 0, st, c->n, alpha, thole, sc_ptr,
+                       n_scaled ? sc_j : c->sc_j_in, n_scaled ? sc_s : c->sc_s_in, (long long)n_scaled, c->flags);
+    int f = 0;
+    if ((rc = read_flags(c, &f)))
+        return rc;
+    if (f & kFlagBadAlpha)
+        return set_error(c, AMOEBA_E_INVALID, "amoeba_set_atoms: polarizabilities must be positive and finite");
+    if (f & kFlagBadThole)
+        return set_error(c, AMOEBA_E_INVALID, "amoeba_set_atoms: Thole parameters must be >= 0 and finite");
+    if (f & kFlagBadCsr)
+        return set_error(c, AMOEBA_E_INVALID,
+                         "amoeba_set_atoms: scaled-pair CSR invalid (ptr not monotone from 0 to n_scaled, "
+                         "partner out of range or equal to the atom, non-finite scale, or a pair not listed "
+                         "in both directions with the same scale)");
+    hipMemcpyAsync(c->alpha_in, alpha, sizeof(double) * c->n, hipMemcpyDeviceToDevice, st);
+    hipMemcpyAsync(c->thole_in, thole, sizeof(double) * c->n, hipMemcpyDeviceToDevice, st);
+    hipMemcpyAsync(c->sc_ptr_in, sc_ptr, sizeof(int) * (c->n + 1), hipMemcpyDeviceToDevice, st);
+    if (n_scaled) {
+        hipMemcpyAsync(c->sc_j_in, sc_j, sizeof(int) * n_scaled, hipMemcpyDeviceToDevice, st);
+        hipMemcpyAsync(c->sc_s_in, sc_s, sizeof(double) * n_scaled, hipMemcpyDeviceToDevice, st);
+    }
+    c->n_scaled = n_scaled;
+    c->atoms_set = true;
+    if (c->list_built && (rc = sort_params(c)))
+        return rc;
+    return hip_check(c, hipStreamSynchronize(st), "amoeba_set_atoms");
+}
+
+int amoeba_build_blocklist(amoeba_ctx* c, const double* pos)
+{
+    if (!c)
+        return AMOEBA_E_INVALID;
+    c->err.clear();
+    if (!pos)
+        return set_error(c, AMOEBA_E_INVALID, "amoeba_build_blocklist: NULL pos");
+    int rc = build_blocklist(c, pos);
+    if (rc)
+        c->list_built = false;
+    return rc;
+}
+
+static int begin_config(amoeba_ctx* c, const double* pos, const char* who)
+{
+    int rc = ready(c, who);
+    if (rc)
+        return rc;
+    if (!pos)
+        return set_error(c, AMOEBA_E_INVALID, std::string(who) + ": NULL pos");
+    return prepare_config(c, pos);
+}
+
+int amoeba_perm_field(amoeba_ctx* c, const double* pos, const double* q, const double* dip, const double* quad,
+                      double* e_perm)
+{
+    if (!c)
+        return AMOEBA_E_INVALID;
+    c->err.clear();
+    if (!q || !dip || !quad || !e_perm)
+        return set_error(c, AMOEBA_E_INVALID, "amoeba_perm_field: NULL argument");
+    int rc = begin_config(c, pos, "amoeba_perm_field");
+    if (rc)
+        return rc;
+    if (!c->mp_d) {
+        if ((rc = ctx_alloc(c, (void**)&c->mp_d, sizeof(double4) * 3 * c->npad)))
+            return rc;
+        if (c->mixed && (rc = ctx_alloc(c, (void**)&c->mp_f, sizeof(float4) * 3 * c->npad)))
+            return rc;
+    }
+    hipStream_t st = c->stream;
+    hipMemsetAsync(c->flags, 0, sizeof(int), st);
+    hipLaunchKernelGGL(k_gather_mpole, dim3(nblk(c->npad, 256)), dim3(256), 0, st, c->npad, c->perm, q, dip, quad,
+                       c->mp_d, c->mixed ? c->mp_f : nullptr, c->flags);
+    int f = 0;
+    if ((rc = read_flags(c, &f)))
+        return rc;
+    if (f & kFlagNonFinite)
+        return set_error(c, AMOEBA_E_NUMERIC, "amoeba_perm_field: non-finite multipole");
+    if (f & kFlagBadCsr)
+        return set_error(c, AMOEBA_E_INVALID, "amoeba_perm_field: quadrupole not traceless (|tr| > 1e-10)");
+    launch_zero_acc(c);
+    launch_perm_tiles(c);
+    if ((rc = pme_perm_potential(c)))
+        return rc;
+    launch_gather(c, c->erec);
+    hipMemsetAsync(c->flags, 0, sizeof(int), st);
+    launch_perm_assemble(c, c->v_q);
+    launch_zero_acc(c);
+    if ((rc = check_overflow(c, c->v_q)))
+        return rc;
+    launch_scatter(c, c->v_q, e_perm);
+    return hip_check(c, hipStreamSynchronize(st), "amoeba_perm_field");
+}
+
+int amoeba_dipole_matvec(amoeba_ctx* c, const double* pos, const double* mu, double* out)
+{
+    if (!c)
+        return AMOEBA_E_INVALID;
+    c->err.clear();
+    if (!mu || !out)
+        return set_error(c, AMOEBA_E_INVALID, "amoeba_dipole_matvec: NULL argument");
+    int rc = begin_config(c, pos, "amoeba_dipole_matvec");
+    if (rc)
+        return rc;
+    if ((rc = check_vec_finite(c, mu, 3 * (size_t)c->n, "mu")))
+        return rc;
+    launch_gather_vec(c, mu, c->v_mu);
+    launch_set_direction(c, c->v_mu);
+    launch_zero_acc(c);
+    if ((rc = matvec_slot(c, false, false)))
+        return rc;
+    if ((rc = check_overflow(c, c->v_q)))
+        return rc;
+    launch_scatter(c, c->v_q, out);
+    return hip_check(c, hipStreamSynchronize(c->stream), "amoeba_dipole_matvec");
+}
+
+int amoeba_dipole_field_parts(amoeba_ctx* c, const double* pos, const double* mu, double* e_real, double* e_recip)
+{
+    if (!c)
+        return AMOEBA_E_INVALID;
+    c->err.clear();
+    if (!mu)
+        return set_error(c, AMOEBA_E_INVALID, "amoeba_dipole_field_parts: NULL mu");
+    int rc = begin_config(c, pos, "amoeba_dipole_field_parts");
+    if (rc)
+        return rc;
+    launch_gather_vec(c, mu, c->v_mu);
+    launch_set_direction(c, c->v_mu);
+    launch_zero_acc(c);
+    launch_mutual_tiles(c, false);
+    size_t n3 = 3 * (size_t)c->npad;
+    hipLaunchKernelGGL(k_acc_to_vec, dim3(nblk(n3, 256)), dim3(256), 0, c->stream, n3, c->mixed ? c->acc_fx : nullptr,
+                       c->mixed ? nullptr : c->acc_d, c->v_q);
+    launch_zero_acc(c);
+    if (e_real)
+        launch_scatter(c, c->v_q, e_real);
+    if ((rc = pme_dipole_field(c, false)))
+        return rc;
+    launch_gather(c, c->erec);
+    if (e_recip)
+        launch_scatter(c, c->erec, e_recip);
+    return hip_check(c, hipStreamSynchronize(c->stream), "amoeba_dipole_field_parts");
+}
+
+int amoeba_polarize(amoeba_ctx* c, const double* pos, const double* e_perm, const double* mu_guess,
+                    int32_t guess_mode, double tol_debye, int32_t max_iter, double* mu_out, double* e_pol_out,
+                    int32_t* iters_out)
+{
+    if (!c)
+        return AMOEBA_E_INVALID;
+    c->err.clear();
+    if (!e_perm || !mu_out)
+        return set_error(c, AMOEBA_E_INVALID, "amoeba_polarize: NULL e_perm or mu_out");
+    if (!(tol_debye > 0.0) || !std::isfinite(tol_debye))
+        return set_error(c, AMOEBA_E_INVALID, "amoeba_polarize: tol_debye must be positive");
+    if (max_iter < 0)
+        return set_error(c, AMOEBA_E_INVALID, "amoeba_polarize: max_iter must be >= 0");
+    if (guess_mode < AMOEBA_GUESS_ZERO || guess_mode > AMOEBA_GUESS_BEST)
+        return set_error(c, AMOEBA_E_INVALID, "amoeba_polarize: unknown guess_mode");
+    if (guess_mode == AMOEBA_GUESS_GIVEN && !mu_guess)
+        return set_error(c, AMOEBA_E_INVALID, "amoeba_polarize: AMOEBA_GUESS_GIVEN needs mu_guess");
+    if (guess_mode == AMOEBA_GUESS_LEARNED || guess_mode == AMOEBA_GUESS_BEST)
+        return set_error(c, AMOEBA_E_STATE, "amoeba_polarize: no learned guess model loaded");
+    int rc = begin_config(c, pos, "amoeba_polarize");
+    if (rc)
+        return rc;
+    if ((rc = check_vec_finite(c, e_perm, 3 * (size_t)c->n, "e_perm")))
+        return rc;
+    launch_gather_vec(c, e_perm, c->v_e);
+    bool have_guess = guess_mode == AMOEBA_GUESS_GIVEN;
+    if (have_guess) {
+        if ((rc = check_vec_finite(c, mu_guess, 3 * (size_t)c->n, "mu_guess")))
+            return rc;
+        launch_gather_vec(c, mu_guess, c->v_mu);
+    }
+    launch_zero_acc(c);
+    int st = pcg_solve(c, tol_debye, max_iter, have_guess);
+    if (st < 0)
+        return st;
+    launch_scatter(c, c->v_mu, mu_out);
+    double ep = compute_epol(c);
+    if (e_pol_out)
+        *e_pol_out = ep;
+    if (iters_out)
+        *iters_out = c->last_iters;
+    if ((rc = hip_check(c, hipStreamSynchronize(c->stream), "amoeba_polarize")))
+        return rc;
+    if (st == AMOEBA_NOT_CONVERGED)
+        set_error(c, AMOEBA_NOT_CONVERGED, "PCG did not reach the tolerance within max_iter");
+    return st;
+}
+
+int amoeba_get_info(const amoeba_ctx* c, amoeba_info* out)
+{
+    if (!c || !out)
+        return AMOEBA_E_INVALID;
+    out->n_atoms = c->n;
+    out->n_blocks = c->nb;
+    out->n_tiles = c->ntiles;
+    out->precision = c->prm.precision;
+    out->n_pairs = c->n_pairs;
+    out->workspace_bytes = c->ws_bytes;
+    out->last_iterations = c->last_iters;
+    out->last_rms_debye = c->last_rms;
+    return AMOEBA_OK;
+}
+
+}  // extern "C"

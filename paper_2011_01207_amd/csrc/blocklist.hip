@@ -1,0 +1,530 @@
+// Blocked neighbour list of the real-space pair kernels (paper: "Neighbor list", "Box
+// partitioning", "List filtering").
+//
+// Build (once per list):
+//   1. atoms get a key along a column-serpentine cell order: the box is cut into ny x nz
+//      columns along x whose cross-section holds about one block's worth of atoms per block
+//      length, odd columns / odd z-slabs run backwards, so consecutive atoms stay spatially
+//      adjacent across column ends; keys (with the atom index as tie-break) are sorted by a
+//      bitonic network, giving a deterministic order;
+//   2. the sorted order is cut into 64-atom blocks (one block = one wave64); the last block is
+//      padded with phantom atoms;
+//   3. every block gets a bounding box; block pairs J > I whose boxes come within
+//      cutoff + buffer are candidates (the adjacency of the paper's block matrix, symmetric
+//      half kept);
+//   4. list filtering: the atoms of candidate blocks that lie within cutoff + buffer of ANY
+//      atom of block I are kept, in (J, slot) order, and packed into 64-atom tiles; each block
+//      also owns its diagonal tile (I, I).
+// Per configuration (every call that takes positions):
+//   5. positions are gathered into slot order, checked for NaN and for list staleness, each
+//      block gets an FP64 origin and FP32/FP64 offsets, and every tile gets its in-cutoff
+//      bitmasks (bit k of row i: |r_i - r_jk| < rc) and the j positions relative to the
+//      i-block origin, computed in FP64.
+#include "common.h"
+
+namespace amoeba {
+
+__device__ __forceinline__ double mimg(double d, double L) { return d - L * rint(d / L); }
+
+__device__ __forceinline__ double wrap_box(double x, double L)
+{
+    double y = x - L * floor(x / L);
+    return (y >= L) ? y - L : y;
+}
+
+__global__ void k_sort_keys(int n, int npow2, const double* __restrict__ pos, double3 box, int ny,
+                            int nz, unsigned long long* __restrict__ keys)
+{
+    int a = blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= npow2)
+        return;
+    if (a >= n) {
+        keys[a] = ~0ull;
+        return;
+    }
+    double x = wrap_box(pos[3 * a], box.x), y = wrap_box(pos[3 * a + 1], box.y),
+           z = wrap_box(pos[3 * a + 2], box.z);
+    if (!(x == x) || !(y == y) || !(z == z)) {  // NaN keys sort last; caught by the gather check
+        keys[a] = (~0ull << 32) | (unsigned)a;
+        return;
+    }
+    int cy = min(ny - 1, (int)(y / box.y * ny));
+    int cz = min(nz - 1, (int)(z / box.z * nz));
+    int cys = (cz & 1) ? ny - 1 - cy : cy;
+    unsigned col = (unsigned)(cz * ny + cys);
+    unsigned xq = min(65535u, (unsigned)(x / box.x * 65536.0));
+    if (col & 1u)
+        xq = 65535u - xq;
+    keys[a] = ((unsigned long long)((col << 16) | xq) << 32) | (unsigned)a;
+}
+
+__global__ void k_bitonic(unsigned long long* __restrict__ keys, int npow2, int j, int k)
+{
+    unsigned i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (unsigned)npow2)
+        return;
+    unsigned ixj = i ^ (unsigned)j;
+    if (ixj > i) {
+        unsigned long long a = keys[i], b = keys[ixj];
+        bool up = (i & (unsigned)k) == 0;
+        if ((a > b) == up) {
+            keys[i] = b;
+            keys[ixj] = a;
+        }
+    }
+}
+
+__global__ void k_perm(int n, int npad, const unsigned long long* __restrict__ keys, int* __restrict__ perm,
+                       int* __restrict__ slot)
+{
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= npad)
+        return;
+    if (s < n) {
+        int a = (int)(keys[s] & 0xffffffffull);
+        perm[s] = a;
+        slot[a] = s;
+    } else {
+        perm[s] = -1;
+    }
+}
+
+__global__ void k_params(int npad, const int* __restrict__ perm, const double* __restrict__ alpha,
+                         const double* __restrict__ thole, double4* __restrict__ pd, float4* __restrict__ pf)
+{
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= npad)
+        return;
+    int a = perm[s];
+    double al = a >= 0 ? alpha[a] : 1.0;
+    double th = a >= 0 ? thole[a] : 0.0;
+    double dinv = pow(al, -1.0 / 6.0);
+    pd[s] = make_double4(al, 1.0 / al, dinv, th);
+    pf[s] = make_float4((float)al, (float)(1.0 / al), (float)dinv, (float)th);
+}
+
+// Single-workgroup exclusive scan: out[i] = sum_{k<i} in[i], out[n] = total.
+__global__ __launch_bounds__(1024) void k_scan_excl(int n, const int* __restrict__ in, int* __restrict__ out)
+{
+    __shared__ int part[1024];
+    int t = threadIdx.x;
+    int chunk = (n + 1023) / 1024;
+    int b = t * chunk, e = min(n, b + chunk);
+    int s = 0;
+    for (int i = b; i < e; ++i)
+        s += in[i];
+    part[t] = s;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        int v = t >= off ? part[t - off] : 0;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    int run = t ? part[t - 1] : 0;
+    for (int i = b; i < e; ++i) {
+        out[i] = run;
+        run += in[i];
+    }
+    if (t == 1023)
+        out[n] = part[1023];
+}
+
+__global__ void k_csr_counts(int npad, const int* __restrict__ perm, const int* __restrict__ ptr_in,
+                             int* __restrict__ cnt)
+{
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= npad)
+        return;
+    int a = perm[s];
+    cnt[s] = a >= 0 ? ptr_in[a + 1] - ptr_in[a] : 0;
+}
+
+__global__ void k_csr_fill(int npad, const int* __restrict__ perm, const int* __restrict__ slot,
+                           const int* __restrict__ ptr_in, const int* __restrict__ j_in,
+                           const double* __restrict__ s_in, const int* __restrict__ ptr_out,
+                           int* __restrict__ j_out, double* __restrict__ s_out)
+{
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= npad)
+        return;
+    int a = perm[s];
+    if (a < 0)
+        return;
+    int o = ptr_out[s];
+    for (int k = ptr_in[a]; k < ptr_in[a + 1]; ++k, ++o) {
+        j_out[o] = slot[j_in[k]];
+        s_out[o] = s_in[k];
+    }
+}
+
+// Gather caller positions into slot order, wrap into the box, flag NaN/Inf and (if a reference
+// exists) atoms that moved more than buffer/2 since the list build.
+__global__ void k_gather_pos(int npad, const int* __restrict__ perm, const double* __restrict__ pos,
+                             double3 box, double4* __restrict__ pos_s, const double4* __restrict__ ref,
+                             double half_buf2, int* __restrict__ flags)
+{
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= npad)
+        return;
+    int a = perm[s];
+    if (a < 0) {
+        pos_s[s] = make_double4(0.0, 0.0, 0.0, 0.0);
+        return;
+    }
+    double x = pos[3 * a], y = pos[3 * a + 1], z = pos[3 * a + 2];
+    if (!isfinite(x) || !isfinite(y) || !isfinite(z)) {
+        atomicOr(flags, kFlagNonFinite);
+        x = y = z = 0.0;
+    }
+    x = wrap_box(x, box.x);
+    y = wrap_box(y, box.y);
+    z = wrap_box(z, box.z);
+    pos_s[s] = make_double4(x, y, z, 0.0);
+    if (ref) {
+        double4 r0 = ref[s];
+        double dx = mimg(x - r0.x, box.x), dy = mimg(y - r0.y, box.y), dz = mimg(z - r0.z, box.z);
+        if (dx * dx + dy * dy + dz * dz > half_buf2)
+            atomicOr(flags, kFlagStale);
+    }
+}
+
+// Block origin = FP64 position of the block's first atom; per-atom minimum-image offsets.
+__global__ void k_block_frame(int npad, const int* __restrict__ perm, const double4* __restrict__ pos_s,
+                              double3 box, double4* __restrict__ org, double4* __restrict__ off_d,
+                              float4* __restrict__ off_f)
+{
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= npad)
+        return;
+    int I = s / kBlock;
+    double4 o = pos_s[I * kBlock];
+    if ((s & (kBlock - 1)) == 0)
+        org[I] = o;
+    double4 p = pos_s[s];
+    double dx = 0.0, dy = 0.0, dz = 0.0;
+    if (perm[s] >= 0) {
+        dx = mimg(p.x - o.x, box.x);
+        dy = mimg(p.y - o.y, box.y);
+        dz = mimg(p.z - o.z, box.z);
+    }
+    off_d[s] = make_double4(dx, dy, dz, 0.0);
+    off_f[s] = make_float4((float)dx, (float)dy, (float)dz, 0.0f);
+}
+
+// Bounding box of each block in coordinates unwrapped around its first atom.
+__global__ __launch_bounds__(64) void k_bbox(int nb, const int* __restrict__ perm,
+                                             const double4* __restrict__ pos_s, double3 box,
+                                             double4* __restrict__ bc, double4* __restrict__ bh)
+{
+    int I = blockIdx.x, lane = threadIdx.x;
+    int s = I * kBlock + lane;
+    double4 o = pos_s[I * kBlock];
+    double rx = 0.0, ry = 0.0, rz = 0.0;
+    if (perm[s] >= 0) {
+        double4 p = pos_s[s];
+        rx = mimg(p.x - o.x, box.x);
+        ry = mimg(p.y - o.y, box.y);
+        rz = mimg(p.z - o.z, box.z);
+    }
+    double mnx = rx, mny = ry, mnz = rz, mxx = rx, mxy = ry, mxz = rz;
+    for (int off = 32; off > 0; off >>= 1) {
+        mnx = fmin(mnx, __shfl_xor(mnx, off));
+        mny = fmin(mny, __shfl_xor(mny, off));
+        mnz = fmin(mnz, __shfl_xor(mnz, off));
+        mxx = fmax(mxx, __shfl_xor(mxx, off));
+        mxy = fmax(mxy, __shfl_xor(mxy, off));
+        mxz = fmax(mxz, __shfl_xor(mxz, off));
+    }
+    if (lane == 0) {
+        bc[I] = make_double4(o.x + 0.5 * (mnx + mxx), o.y + 0.5 * (mny + mxy), o.z + 0.5 * (mnz + mxz), 0.0);
+        bh[I] = make_double4(0.5 * (mxx - mnx), 0.5 * (mxy - mny), 0.5 * (mxz - mnz), 0.0);
+    }
+}
+
+// List filtering: for block I, the atoms of blocks J > I within rcb of any atom of I, in order.
+__global__ __launch_bounds__(64) void k_filter(int nb, const int* __restrict__ perm,
+                                               const double4* __restrict__ pos_s,
+                                               const double4* __restrict__ bc, const double4* __restrict__ bh,
+                                               double3 box, double rcb, int* __restrict__ row_count,
+                                               int* __restrict__ row_j, int* __restrict__ flags)
+{
+    __shared__ double sx[kBlock], sy[kBlock], sz[kBlock];
+    __shared__ int sv[kBlock];
+    int I = blockIdx.x, lane = threadIdx.x;
+    int si = I * kBlock + lane;
+    double4 pi = pos_s[si];
+    sx[lane] = pi.x;
+    sy[lane] = pi.y;
+    sz[lane] = pi.z;
+    sv[lane] = perm[si] >= 0;
+    __syncthreads();
+    double rcb2 = rcb * rcb;
+    double4 ci = bc[I], hi = bh[I];
+    int count = 0;
+    for (int J0 = I + 1; J0 < nb; J0 += kBlock) {
+        int J = J0 + lane;
+        bool cand = false;
+        if (J < nb) {
+            double4 cj = bc[J], hj = bh[J];
+            double dx = fabs(mimg(ci.x - cj.x, box.x)) - hi.x - hj.x;
+            double dy = fabs(mimg(ci.y - cj.y, box.y)) - hi.y - hj.y;
+            double dz = fabs(mimg(ci.z - cj.z, box.z)) - hi.z - hj.z;
+            dx = fmax(dx, 0.0);
+            dy = fmax(dy, 0.0);
+            dz = fmax(dz, 0.0);
+            cand = dx * dx + dy * dy + dz * dz < rcb2;
+        }
+        unsigned long long cm = __ballot(cand);
+        while (cm) {
+            int k = __ffsll((long long)cm) - 1;
+            cm &= cm - 1;
+            int sj = (J0 + k) * kBlock + lane;
+            bool keep = false;
+            if (perm[sj] >= 0) {
+                double4 pj = pos_s[sj];
+                for (int i = 0; i < kBlock; ++i) {
+                    if (!sv[i])
+                        continue;
+                    double dx = mimg(sx[i] - pj.x, box.x);
+                    double dy = mimg(sy[i] - pj.y, box.y);
+                    double dz = mimg(sz[i] - pj.z, box.z);
+                    if (dx * dx + dy * dy + dz * dz < rcb2) {
+                        keep = true;
+                        break;
+                    }
+                }
+            }
+            unsigned long long km = __ballot(keep);
+            int before = __popcll(km & ((1ull << lane) - 1ull));
+            if (keep && count + before < kMaxFiltered)
+                row_j[(size_t)I * kMaxFiltered + count + before] = sj;
+            count += __popcll(km);
+        }
+    }
+    if (lane == 0) {
+        row_count[I] = min(count, kMaxFiltered);
+        if (count > kMaxFiltered)
+            atomicOr(flags, kFlagFilterOverflow);
+    }
+}
+
+__global__ void k_tiles_per_block(int nb, const int* __restrict__ row_count, int* __restrict__ tpb)
+{
+    int I = blockIdx.x * blockDim.x + threadIdx.x;
+    if (I < nb)
+        tpb[I] = 1 + (row_count[I] + kBlock - 1) / kBlock;
+}
+
+__global__ __launch_bounds__(64) void k_fill_tiles(int nb, const int* __restrict__ tile0,
+                                                   const int* __restrict__ row_count,
+                                                   const int* __restrict__ row_j, int* __restrict__ tile_blk,
+                                                   int* __restrict__ tile_j)
+{
+    int I = blockIdx.x, lane = threadIdx.x;
+    int t0 = tile0[I], nt = tile0[I + 1] - t0, cnt = row_count[I];
+    if (lane == 0)
+        for (int t = 0; t < nt; ++t)
+            tile_blk[t0 + t] = I;
+    tile_j[(size_t)t0 * kBlock + lane] = I * kBlock + lane;  // diagonal tile
+    for (int t = 1; t < nt; ++t) {
+        int idx = (t - 1) * kBlock + lane;
+        tile_j[(size_t)(t0 + t) * kBlock + lane] = idx < cnt ? row_j[(size_t)I * kMaxFiltered + idx] : -1;
+    }
+}
+
+// Per configuration: in-cutoff bitmasks (FP64 distances, strict r < rc) and j positions
+// relative to the i-block origin.  The diagonal tile keeps only k > i.
+__global__ __launch_bounds__(256) void k_tile_refresh(int ntiles, const int* __restrict__ tile_blk,
+                                                      const int* __restrict__ tile_j,
+                                                      const int* __restrict__ perm,
+                                                      const double4* __restrict__ pos_s,
+                                                      const double4* __restrict__ org, double3 box,
+                                                      double rc2, unsigned long long* __restrict__ mask,
+                                                      double4* __restrict__ jrel_d, float4* __restrict__ jrel_f,
+                                                      unsigned long long* __restrict__ pair_count)
+{
+    int gt = blockIdx.x * blockDim.x + threadIdx.x;
+    int t = gt >> 6, lane = threadIdx.x & 63;
+    if (t >= ntiles)
+        return;
+    int I = tile_blk[t];
+    int si = I * kBlock + lane;
+    bool ivalid = perm[si] >= 0;
+    double4 pi = pos_s[si];
+    int sj = tile_j[(size_t)t * kBlock + lane];
+    double4 pj = sj >= 0 ? pos_s[sj] : pi;
+    double4 o = org[I];
+    double jx = mimg(pj.x - o.x, box.x), jy = mimg(pj.y - o.y, box.y), jz = mimg(pj.z - o.z, box.z);
+    jrel_d[(size_t)t * kBlock + lane] = make_double4(jx, jy, jz, 0.0);
+    jrel_f[(size_t)t * kBlock + lane] = make_float4((float)jx, (float)jy, (float)jz, 0.0f);
+    bool jvalid = sj >= 0 && perm[sj] >= 0;
+    bool diag = tile_j[(size_t)t * kBlock] == I * kBlock;
+    unsigned long long m = 0;
+    for (int k = 0; k < kBlock; ++k) {
+        double xk = __shfl(pj.x, k), yk = __shfl(pj.y, k), zk = __shfl(pj.z, k);
+        int vk = __shfl((int)jvalid, k);
+        if (!vk || !ivalid || (diag && k <= lane))
+            continue;
+        double dx = mimg(pi.x - xk, box.x), dy = mimg(pi.y - yk, box.y), dz = mimg(pi.z - zk, box.z);
+        if (dx * dx + dy * dy + dz * dz < rc2)
+            m |= 1ull << k;
+    }
+    mask[(size_t)t * kBlock + lane] = m;
+    unsigned long long cnt = (unsigned long long)__popcll(m);
+    for (int off = 32; off > 0; off >>= 1)
+        cnt += __shfl_xor(cnt, off);
+    if (lane == 0 && cnt)
+        atomicAdd(pair_count, cnt);
+}
+
+static inline int nblk(long n, int b) { return (int)((n + b - 1) / b); }
+
+int sort_params(amoeba_ctx* c)
+{
+    hipStream_t st = c->stream;
+    hipLaunchKernelGGL(k_params, dim3(nblk(c->npad, 256)), dim3(256), 0, st, c->npad, c->perm, c->alpha_in,
+                       c->thole_in, c->par_d, c->par_f);
+    // scaled-pair CSR in slot order
+    int* cnt = nullptr;
+    if (hip_check(c, hipMalloc(&cnt, sizeof(int) * (c->npad + 1)), "hipMalloc"))
+        return AMOEBA_E_NOMEM;
+    hipLaunchKernelGGL(k_csr_counts, dim3(nblk(c->npad, 256)), dim3(256), 0, st, c->npad, c->perm, c->sc_ptr_in,
+                       cnt);
+    hipLaunchKernelGGL(k_scan_excl, dim3(1), dim3(1024), 0, st, c->npad, cnt, c->sc_ptr);
+    if (c->n_scaled > 0)
+        hipLaunchKernelGGL(k_csr_fill, dim3(nblk(c->npad, 256)), dim3(256), 0, st, c->npad, c->perm, c->slot,
+                           c->sc_ptr_in, c->sc_j_in, c->sc_s_in, c->sc_ptr, c->sc_j, c->sc_s);
+    int rc = hip_check(c, hipStreamSynchronize(st), "sort_params");
+    hipFree(cnt);
+    return rc;
+}
+
+void pme_bin_atoms(amoeba_ctx* c);
+
+static int refresh_tiles(amoeba_ctx* c)
+{
+    hipStream_t st = c->stream;
+    double3 box = make_double3(c->prm.box[0], c->prm.box[1], c->prm.box[2]);
+    hipLaunchKernelGGL(k_block_frame, dim3(nblk(c->npad, 256)), dim3(256), 0, st, c->npad, c->perm, c->pos_s, box,
+                       c->blk_org, c->off_d, c->off_f);
+    hipMemsetAsync(c->counter, 0, sizeof(unsigned long long), st);
+    hipLaunchKernelGGL(k_tile_refresh, dim3(nblk((long)c->ntiles * kBlock, 256)), dim3(256), 0, st, c->ntiles,
+                       c->tile_blk, c->tile_j, c->perm, c->pos_s, c->blk_org, box, c->prm.cutoff * c->prm.cutoff,
+                       c->tile_mask, c->jrel_d, c->jrel_f, c->counter);
+    pme_bin_atoms(c);
+    return AMOEBA_OK;
+}
+
+int build_blocklist(amoeba_ctx* c, const double* pos)
+{
+    hipStream_t st = c->stream;
+    const int n = c->n, nb = c->nb, npad = c->npad;
+    double3 box = make_double3(c->prm.box[0], c->prm.box[1], c->prm.box[2]);
+    // column cross-section: about one block per (edge x edge x edge) at the mean density
+    double vol = box.x * box.y * box.z;
+    double edge = cbrt(kBlock * vol / n);
+    int ny = (int)fmin(255.0, fmax(1.0, floor(box.y / edge + 0.5)));
+    int nz = (int)fmin(255.0, fmax(1.0, floor(box.z / edge + 0.5)));
+    int npow2 = 1;
+    while (npow2 < n)
+        npow2 <<= 1;
+
+    unsigned long long* keys = nullptr;
+    double4 *bc = nullptr, *bh = nullptr;
+    int *row_count = nullptr, *row_j = nullptr, *tpb = nullptr, *t0 = nullptr;
+    int rc = AMOEBA_OK;
+    auto fail = [&](int code) {
+        hipFree(keys); hipFree(bc); hipFree(bh); hipFree(row_count); hipFree(row_j); hipFree(tpb);
+        return code;
+    };
+    if (hipMalloc(&keys, sizeof(unsigned long long) * npow2) != hipSuccess ||
+        hipMalloc(&bc, sizeof(double4) * nb) != hipSuccess || hipMalloc(&bh, sizeof(double4) * nb) != hipSuccess ||
+        hipMalloc(&row_count, sizeof(int) * nb) != hipSuccess ||
+        hipMalloc(&row_j, sizeof(int) * (size_t)nb * kMaxFiltered) != hipSuccess ||
+        hipMalloc(&tpb, sizeof(int) * (nb + 1)) != hipSuccess) {
+        set_error(c, AMOEBA_E_NOMEM, "build_blocklist: temporary allocation failed");
+        return fail(AMOEBA_E_NOMEM);
+    }
+    t0 = c->blk_tile0;
+
+    hipLaunchKernelGGL(k_sort_keys, dim3(nblk(npow2, 256)), dim3(256), 0, st, n, npow2, pos, box, ny, nz, keys);
+    for (int k = 2; k <= npow2; k <<= 1)
+        for (int j = k >> 1; j > 0; j >>= 1)
+            hipLaunchKernelGGL(k_bitonic, dim3(nblk(npow2, 256)), dim3(256), 0, st, keys, npow2, j, k);
+    hipLaunchKernelGGL(k_perm, dim3(nblk(npad, 256)), dim3(256), 0, st, n, npad, keys, c->perm, c->slot);
+    if (c->atoms_set && (rc = sort_params(c)) != AMOEBA_OK)
+        return fail(rc);
+
+    hipMemsetAsync(c->flags, 0, sizeof(int), st);
+    hipLaunchKernelGGL(k_gather_pos, dim3(nblk(npad, 256)), dim3(256), 0, st, npad, c->perm, pos, box, c->pos_s,
+                       (const double4*)nullptr, 0.0, c->flags);
+    hipMemcpyAsync(c->pos_ref, c->pos_s, sizeof(double4) * npad, hipMemcpyDeviceToDevice, st);
+    hipLaunchKernelGGL(k_bbox, dim3(nb), dim3(64), 0, st, nb, c->perm, c->pos_s, box, bc, bh);
+    hipLaunchKernelGGL(k_filter, dim3(nb), dim3(64), 0, st, nb, c->perm, c->pos_s, bc, bh, box,
+                       c->prm.cutoff + c->prm.buffer, row_count, row_j, c->flags);
+    hipLaunchKernelGGL(k_tiles_per_block, dim3(nblk(nb, 256)), dim3(256), 0, st, nb, row_count, tpb);
+    hipLaunchKernelGGL(k_scan_excl, dim3(1), dim3(1024), 0, st, nb, tpb, t0);
+    int total = 0;
+    hipMemcpyAsync(&total, t0 + nb, sizeof(int), hipMemcpyDeviceToHost, st);
+    hipMemcpyAsync(c->flags_host, c->flags, sizeof(int), hipMemcpyDeviceToHost, st);
+    if ((rc = hip_check(c, hipStreamSynchronize(st), "build_blocklist")))
+        return fail(rc);
+    if (*c->flags_host & kFlagNonFinite) {
+        set_error(c, AMOEBA_E_NUMERIC, "build_blocklist: non-finite position");
+        return fail(AMOEBA_E_NUMERIC);
+    }
+    if (*c->flags_host & kFlagFilterOverflow) {
+        set_error(c, AMOEBA_E_INVALID, "build_blocklist: more than 2048 atoms within cutoff+buffer of a block "
+                                       "(density too high for the list capacity)");
+        return fail(AMOEBA_E_INVALID);
+    }
+    if (total > c->tile_cap) {
+        // grow the tile arrays (not counted against earlier allocations: freed on destroy)
+        size_t tb = (size_t)total * kBlock;
+        if ((rc = ctx_alloc(c, (void**)&c->tile_blk, sizeof(int) * total)) ||
+            (rc = ctx_alloc(c, (void**)&c->tile_j, sizeof(int) * tb)) ||
+            (rc = ctx_alloc(c, (void**)&c->tile_mask, sizeof(unsigned long long) * tb)) ||
+            (rc = ctx_alloc(c, (void**)&c->jrel_f, sizeof(float4) * tb)) ||
+            (!c->mixed && (rc = ctx_alloc(c, (void**)&c->jrel_d, sizeof(double4) * tb))))
+            return fail(rc);
+        if (c->mixed && !c->jrel_d && (rc = ctx_alloc(c, (void**)&c->jrel_d, sizeof(double4) * tb)))
+            return fail(rc);
+        c->tile_cap = total;
+    }
+    c->ntiles = total;
+    hipLaunchKernelGGL(k_fill_tiles, dim3(nb), dim3(64), 0, st, nb, t0, row_count, row_j, c->tile_blk, c->tile_j);
+    refresh_tiles(c);
+    hipMemcpyAsync(c->flags_host + 2, c->counter, sizeof(unsigned long long), hipMemcpyDeviceToHost, st);
+    if ((rc = hip_check(c, hipStreamSynchronize(st), "build_blocklist tiles")))
+        return fail(rc);
+    c->n_pairs = (int64_t) * (unsigned long long*)(c->flags_host + 2);
+    c->list_built = true;
+    fail(AMOEBA_OK);
+    return AMOEBA_OK;
+}
+
+int prepare_config(amoeba_ctx* c, const double* pos)
+{
+    hipStream_t st = c->stream;
+    double3 box = make_double3(c->prm.box[0], c->prm.box[1], c->prm.box[2]);
+    double hb = 0.5 * c->prm.buffer;
+    hipMemsetAsync(c->flags, 0, sizeof(int), st);
+    hipLaunchKernelGGL(k_gather_pos, dim3(nblk(c->npad, 256)), dim3(256), 0, st, c->npad, c->perm, pos, box,
+                       c->pos_s, (const double4*)c->pos_ref, hb * hb, c->flags);
+    refresh_tiles(c);
+    hipMemcpyAsync(c->flags_host, c->flags, sizeof(int), hipMemcpyDeviceToHost, st);
+    hipMemcpyAsync(c->flags_host + 2, c->counter, sizeof(unsigned long long), hipMemcpyDeviceToHost, st);
+    int rc = hip_check(c, hipStreamSynchronize(st), "prepare_config");
+    if (rc)
+        return rc;
+    if (*c->flags_host & kFlagNonFinite)
+        return set_error(c, AMOEBA_E_NUMERIC, "non-finite position");
+    if (*c->flags_host & kFlagStale)
+        return set_error(c, AMOEBA_E_LIST, "block list is stale: an atom moved more than buffer/2 since "
+                                           "amoeba_build_blocklist");
+    c->n_pairs = (int64_t) * (unsigned long long*)(c->flags_host + 2);
+    return AMOEBA_OK;
+}
+
+}  // namespace amoeba

@@ -1,0 +1,190 @@
+// Internal declarations shared by the HIP sources of the induced-dipole library.
+// Not part of the public ABI (see include/amoeba.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <rocfft/rocfft.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "amoeba.h"
+
+namespace amoeba {
+
+constexpr int kBlock = 64;                       // atoms per block = lanes per wave
+constexpr double kFixScale = 1099511627776.0;    // 2^40: fixed-point fraction bits of fields
+constexpr double kFixInv = 1.0 / 1099511627776.0;
+constexpr double kCoulomb = 332.0637133;         // kcal*A/(mol e^2)
+constexpr double kDebye = 4.80320;               // D per e*A
+constexpr int kBrick = 8;                        // PME spread brick edge (grid points)
+constexpr int kMaxFiltered = 2048;               // filtered j-atoms per block (list build)
+constexpr int kRedBlocks = 256;                  // workgroups of the deterministic reductions
+constexpr double kPi = 3.14159265358979323846;
+
+// Device flags written by validation / preparation kernels.
+enum : int {
+    kFlagNonFinite = 1,
+    kFlagStale = 2,
+    kFlagOverflow = 4,
+    kFlagBadAlpha = 8,
+    kFlagBadThole = 16,
+    kFlagBadCsr = 32,
+    kFlagFilterOverflow = 64,
+    kFlagBreakdown = 128,
+};
+
+// PCG scalars kept on the device (one struct, FP64).
+struct PcgScalars {
+    double rz;        // r.z of the current iterate
+    double pq;        // p.(A p)
+    double gamma;     // step length
+    double rz_new;
+    double zz;        // z.z -> rms
+    double rms;       // rms of z in Debye
+    double tol;       // tolerance in Debye
+    double epol_acc;  // sum mu.E
+    double beta;      // rz_new / rz of the last update
+    int32_t done;     // converged (or broken down): later kernels of the loop skip
+    int32_t iters;    // iterations completed
+    int32_t status;   // 0 running, 1 converged, 2 breakdown
+    int32_t pad;
+};
+
+// Deterministic two-level reduction scratch: per-workgroup partials + a completion ticket.
+struct RedScratch {
+    double* part;       // [kRedBlocks * 4]
+    unsigned int* ticket;
+};
+
+struct DeviceBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+};
+
+}  // namespace amoeba
+
+struct amoeba_ctx {
+    amoeba_params prm{};
+    hipStream_t stream = nullptr;
+    int device = 0;
+    std::string err;
+    int n = 0, nb = 0, npad = 0;
+    bool mixed = false;
+    bool atoms_set = false;
+    bool list_built = false;
+    int64_t n_scaled = 0;
+    int ntiles = 0, tile_cap = 0;
+    int64_t n_pairs = 0;
+    int last_iters = 0;
+    double last_rms = 0.0;
+    int64_t ws_bytes = 0;
+
+    // allocation registry (freed on destroy)
+    std::vector<void*> allocs;
+
+    // sorted-order atom data
+    int32_t* perm = nullptr;       // [npad] slot -> original atom (-1 phantom)
+    int32_t* slot = nullptr;       // [n] original atom -> slot
+    double4* par_d = nullptr;      // [npad] (alpha, 1/alpha, alpha^-1/6, thole)
+    float4* par_f = nullptr;       // same in FP32
+    int32_t* sc_ptr = nullptr;     // [npad+1] CSR of scaled pairs in slot order
+    int32_t* sc_j = nullptr;       // [n_scaled] partner slot
+    double* sc_s = nullptr;        // [n_scaled]
+    int32_t* sc_ptr_in = nullptr;  // caller-order CSR copy (validation / re-sorting)
+    int32_t* sc_j_in = nullptr;
+    double* sc_s_in = nullptr;
+    double* alpha_in = nullptr;    // caller-order parameters
+    double* thole_in = nullptr;
+
+    // per-configuration geometry (slot order)
+    double4* pos_s = nullptr;      // [npad] wrapped FP64 positions
+    double4* pos_ref = nullptr;    // [npad] positions at the last list build
+    double4* blk_org = nullptr;    // [nb] block origin (first atom of the block)
+    double4* off_d = nullptr;      // [npad] minimum-image offset from the block origin
+    float4* off_f = nullptr;
+
+    // tiles
+    int32_t* tile_blk = nullptr;   // [ntiles]
+    int32_t* tile_j = nullptr;     // [ntiles*64] j slot or -1
+    unsigned long long* tile_mask = nullptr; // [ntiles*64] bit k of row i: pair (i, j_k) within rc
+    double4* jrel_d = nullptr;     // [ntiles*64] j position relative to the i-block origin
+    float4* jrel_f = nullptr;
+    int32_t* blk_tile0 = nullptr;  // [nb+1] first tile of each block row
+
+    // PME
+    int K[3] = {0, 0, 0};
+    int nbr[3] = {0, 0, 0};        // bricks per dimension
+    int nbricks = 0;
+    size_t ngrid = 0, ncgrid = 0;
+    void* grid_r = nullptr;        // real grid (float or double) [K0][K1][K2]
+    void* grid_c = nullptr;        // complex half grid [K0][K1][K2/2+1]
+    void* theta = nullptr;         // influence function on the half grid (float or double)
+    int32_t* bin_start = nullptr;  // [nbricks+1] atoms binned by the brick of their base point
+    int32_t* bin_atoms = nullptr;  // [npad]
+    int32_t* bin_count = nullptr;  // [nbricks]
+    int32_t* atom_bin = nullptr;   // [npad]
+    rocfft_plan plan_fwd = nullptr, plan_bwd = nullptr;
+    rocfft_execution_info exec_fwd = nullptr, exec_bwd = nullptr;
+    void* fft_work = nullptr;
+    size_t fft_work_bytes = 0;
+
+    // field accumulators and vectors (slot order, FP64 N x 3 unless noted)
+    unsigned long long* acc_fx = nullptr;  // [npad*3] fixed-point real-space field (mixed)
+    double* acc_d = nullptr;               // [npad*3] FP64 real-space field (FP64 mode)
+    double* erec = nullptr;                // [npad*3] reciprocal field scratch
+    double* v_mu = nullptr;
+    double* v_r = nullptr;
+    double* v_z = nullptr;
+    double* v_p = nullptr;
+    double* v_q = nullptr;
+    double* v_e = nullptr;                 // E_perm in slot order
+    double4* pv_d = nullptr;               // [npad] pair-kernel copy of the direction (FP64)
+    float4* pv_f = nullptr;                // [npad] (FP32)
+    double4* mp_d = nullptr;               // [npad*3] (q,dx,dy,dz),(Txx,Txy,Txz,Tyy),(Tyz,Tzz,0,0)
+    float4* mp_f = nullptr;                // same in FP32 (mixed mode)
+
+    amoeba::PcgScalars* sc = nullptr;      // device scalars
+    amoeba::PcgScalars* sc_host = nullptr; // pinned mirror
+    amoeba::RedScratch red{};
+    int* flags = nullptr;                  // device error flags
+    int* flags_host = nullptr;             // pinned
+    unsigned long long* counter = nullptr; // device counters (pairs)
+    hipEvent_t ev[2] = {nullptr, nullptr};
+};
+
+namespace amoeba {
+
+// allocation helpers (api.hip)
+int ctx_alloc(amoeba_ctx* c, void** p, size_t bytes);
+int set_error(amoeba_ctx* c, int code, const std::string& msg);
+int hip_check(amoeba_ctx* c, hipError_t e, const char* what);
+
+// blocklist.hip
+int build_blocklist(amoeba_ctx* c, const double* pos);
+int prepare_config(amoeba_ctx* c, const double* pos);
+
+// realspace.hip
+void launch_mutual_tiles(amoeba_ctx* c, bool use_done);
+void launch_perm_tiles(amoeba_ctx* c);
+void launch_zero_acc(amoeba_ctx* c);
+void launch_perm_assemble(amoeba_ctx* c, double* out_slot);
+
+// pme.hip
+int pme_setup(amoeba_ctx* c);
+void pme_bin_atoms(amoeba_ctx* c);
+int pme_dipole_field(amoeba_ctx* c, bool use_done);   // spread p -> FFT -> convolve -> FFT
+int pme_perm_potential(amoeba_ctx* c);                // spread multipoles -> ... -> potential grid
+void launch_gather(amoeba_ctx* c, double* out);       // E_rec at atoms from the potential grid
+
+// pcg.hip
+void launch_gather_vec(amoeba_ctx* c, const double* src_caller, double* dst_slot);
+void launch_scatter(amoeba_ctx* c, const double* v_slot, double* out_caller);
+void launch_matvec_combine(amoeba_ctx* c, bool use_done, bool dot_pq);
+void launch_set_direction(amoeba_ctx* c, const double* src);
+int pcg_solve(amoeba_ctx* c, double tol, int max_iter, bool have_guess);
+double compute_epol(amoeba_ctx* c);
+int matvec_slot(amoeba_ctx* c, bool use_done, bool dot);
+
+}  // namespace amoeba

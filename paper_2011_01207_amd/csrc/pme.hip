@@ -1,0 +1,693 @@
+// Smooth PME reciprocal part (paper, "Reciprocal space scheme": B-spline spread of the
+// multipolar density, forward FFT, scalar product with the influence function, backward FFT,
+// interpolation of the field with the spline derivatives; Essmann et al. 1995).
+//
+// Spread is owner-computes over 8x8x8 grid bricks: atoms are binned once per configuration by
+// the brick holding their highest support point, a workgroup owns one brick, accumulates the
+// contributions of the atoms in its own and the seven following bins in LDS (64-bit fixed
+// point in mixed precision: order-free and deterministic; FP64 LDS atomics otherwise) and
+// writes each grid point exactly once.  No global atomics, no grid clearing pass.
+//
+// B-spline weights come from the standard order-raising recurrence
+//   M_k(w + t) = ((w + t) M_{k-1}(w + t) + (k - w - t) M_{k-1}(w + t - 1)) / (k - 1),
+// started from M_2 and evaluated for all t at once; derivatives are differences of the lower
+// orders.  Grid line for weight t is floor(u) - t (mod K), u = K x / L.
+#include "common.h"
+#include "reduce.h"
+
+namespace amoeba {
+
+template <typename R> struct V4p;
+template <> struct V4p<float> { using T = float4; using C = float2; };
+template <> struct V4p<double> { using T = double4; using C = double2; };
+
+// Order-5 weights m0[t] = M5(w+t), first derivatives m1 and (optionally) second derivatives m2.
+template <typename R, bool SECOND>
+__device__ __forceinline__ void spline5(R w, R* m0, R* m1, R* m2)
+{
+    R a[5] = {w, (R)1 - w, 0, 0, 0};
+    R a3[5], a4[5];
+#pragma unroll
+    for (int k = 3; k <= 5; ++k) {
+        if (k == 4)
+#pragma unroll
+            for (int t = 0; t < 5; ++t)
+                a3[t] = a[t];
+        if (k == 5)
+#pragma unroll
+            for (int t = 0; t < 5; ++t)
+                a4[t] = a[t];
+        const R inv = (R)1 / (R)(k - 1);
+#pragma unroll
+        for (int t = k - 1; t >= 1; --t)
+            a[t] = ((w + (R)t) * a[t] + ((R)k - w - (R)t) * a[t - 1]) * inv;
+        a[0] = w * a[0] * inv;
+    }
+#pragma unroll
+    for (int t = 0; t < 5; ++t) {
+        m0[t] = a[t];
+        m1[t] = a4[t] - (t > 0 ? a4[t - 1] : (R)0);
+        if (SECOND)
+            m2[t] = a3[t] - (t > 0 ? (R)2 * a3[t - 1] : (R)0) + (t > 1 ? a3[t - 2] : (R)0);
+    }
+}
+
+// fractional grid coordinate of a wrapped position: integer base and spline argument
+__device__ __forceinline__ void grid_coord(double x, double kl, int K, int& fl, double& w)
+{
+    double u = x * kl;
+    double f = floor(u);
+    fl = (int)f;
+    w = u - f;
+    if (fl >= K) {  // x rounded up to L
+        fl -= K;
+    }
+    if (fl < 0)
+        fl += K;
+}
+
+// ------------------------------------------------------------------------------------------
+// setup: B-spline moduli and influence function theta(m) = B(m) C(m) on the half grid
+// ------------------------------------------------------------------------------------------
+__device__ double bsmod_raw(int m, int K)
+{
+    double a0[5], a1[5], a2[5];
+    spline5<double, false>(0.0, a0, a1, a2);
+    double re = 0.0, im = 0.0;
+    for (int k = 0; k < 4; ++k) {
+        double ang = 2.0 * kPi * (double)m * k / K;
+        re += a0[k + 1] * cos(ang);
+        im += a0[k + 1] * sin(ang);
+    }
+    return re * re + im * im;
+}
+
+__global__ void k_bsmod(int K, double* __restrict__ mod)
+{
+    int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= K)
+        return;
+    double v = bsmod_raw(m, K);
+    if (v < 1e-14)  // order 5 vanishes at m = K/2: mean of the two neighbours
+        v = 0.5 * (bsmod_raw((m + K - 1) % K, K) + bsmod_raw((m + 1) % K, K));
+    mod[m] = v;
+}
+
+template <typename R>
+__global__ void k_theta(int3 K, double3 box, double beta, const double* __restrict__ mx,
+                        const double* __restrict__ my, const double* __restrict__ mz, R* __restrict__ theta)
+{
+    int kh = K.z / 2 + 1;
+    size_t n = (size_t)K.x * K.y * kh;
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n)
+        return;
+    int i2 = (int)(i % kh);
+    int i1 = (int)((i / kh) % K.y);
+    int i0 = (int)(i / ((size_t)kh * K.y));
+    double m0 = (i0 <= K.x / 2 ? i0 : i0 - K.x) / box.x;
+    double m1 = (i1 <= K.y / 2 ? i1 : i1 - K.y) / box.y;
+    double m2 = i2 / box.z;
+    double msq = m0 * m0 + m1 * m1 + m2 * m2;
+    double vol = box.x * box.y * box.z;
+    double v = 0.0;
+    if (i != 0)
+        v = exp(-kPi * kPi * msq / (beta * beta)) / (kPi * vol * msq) / (mx[i0] * my[i1] * mz[i2]);
+    theta[i] = (R)v;
+}
+
+// ------------------------------------------------------------------------------------------
+// per configuration: bin atoms by the brick of their base grid point
+// ------------------------------------------------------------------------------------------
+__global__ void k_bin_count(int npad, const int* __restrict__ perm, const double4* __restrict__ pos_s, double3 kl,
+                            int3 K, int3 nbr, int* __restrict__ bin_count, int* __restrict__ atom_bin)
+{
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= npad)
+        return;
+    if (perm[s] < 0) {
+        atom_bin[s] = -1;
+        return;
+    }
+    double4 p = pos_s[s];
+    int fx, fy, fz;
+    double w;
+    grid_coord(p.x, kl.x, K.x, fx, w);
+    grid_coord(p.y, kl.y, K.y, fy, w);
+    grid_coord(p.z, kl.z, K.z, fz, w);
+    int b = ((fx / kBrick) * nbr.y + fy / kBrick) * nbr.z + fz / kBrick;
+    atom_bin[s] = b;
+    atomicAdd(&bin_count[b], 1);
+}
+
+__global__ void k_bin_fill(int npad, const int* __restrict__ atom_bin, const int* __restrict__ bin_start,
+                           int* __restrict__ cursor, int* __restrict__ bin_atoms)
+{
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= npad)
+        return;
+    int b = atom_bin[s];
+    if (b < 0)
+        return;
+    int k = atomicAdd(&cursor[b], 1);
+    bin_atoms[bin_start[b] + k] = s;
+}
+
+// order within a bin by slot (deterministic accumulation order for the FP64 path)
+__global__ void k_bin_sort(int nbins, const int* __restrict__ bin_start, int* __restrict__ bin_atoms)
+{
+    int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nbins)
+        return;
+    int lo = bin_start[b], hi = bin_start[b + 1];
+    for (int i = lo + 1; i < hi; ++i) {
+        int v = bin_atoms[i];
+        int j = i - 1;
+        while (j >= lo && bin_atoms[j] > v) {
+            bin_atoms[j + 1] = bin_atoms[j];
+            --j;
+        }
+        bin_atoms[j + 1] = v;
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// spread (dipoles, or charges + dipoles + quadrupoles when PERM)
+// ------------------------------------------------------------------------------------------
+template <bool FIX> struct LdsAcc;
+template <> struct LdsAcc<true> {
+    using T = unsigned long long;
+    __device__ static void add(T* p, float v) { atomicAdd(p, (T)(long long)llrint((double)v * kFixScale)); }
+    __device__ static float get(const T* p) { return (float)((double)(long long)(*p) * kFixInv); }
+};
+template <> struct LdsAcc<false> {
+    using T = double;
+    __device__ static void add(T* p, double v) { atomicAdd(p, v); }
+    __device__ static double get(const T* p) { return *p; }
+};
+
+template <typename R, bool FIX, bool PERM>
+__global__ __launch_bounds__(256) void k_spread(int3 K, int3 nbr, const int* __restrict__ bin_start,
+                                                const int* __restrict__ bin_atoms,
+                                                const double4* __restrict__ pos_s, double3 kl,
+                                                const typename V4p<R>::T* __restrict__ src, R* __restrict__ grid,
+                                                const PcgScalars* __restrict__ sc, int use_done)
+{
+    using R4 = typename V4p<R>::T;
+    using AT = typename LdsAcc<FIX>::T;
+    __shared__ AT acc[kBrick * kBrick * kBrick];
+    __shared__ int bl[3][3], bnum[3];
+    __shared__ int rs[27], rn[27], pre[28];
+    if (use_done && sc->done)
+        return;
+    const int tid = threadIdx.x;
+    const int b = blockIdx.x;
+    const int bz = b % nbr.z, by = (b / nbr.z) % nbr.y, bx = b / (nbr.z * nbr.y);
+    const int lox = bx * kBrick, loy = by * kBrick, loz = bz * kBrick;
+    const int ex = min(kBrick, K.x - lox), ey = min(kBrick, K.y - loy), ez = min(kBrick, K.z - loz);
+    for (int p = tid; p < kBrick * kBrick * kBrick; p += 256)
+        acc[p] = (AT)0;
+    // Bins whose atoms can reach this brick: an atom's support is [base-4, base], so the brick
+    // [lo, hi] needs bases in [lo, hi+4] (cyclic): its own bin, the next one, and the one after
+    // that when the next bin is narrower than 4 points (ragged last bin).  Duplicates removed.
+    if (tid < 3) {
+        const int nb = tid == 0 ? nbr.x : (tid == 1 ? nbr.y : nbr.z);
+        const int kk = tid == 0 ? K.x : (tid == 1 ? K.y : K.z);
+        const int b0 = tid == 0 ? bx : (tid == 1 ? by : bz);
+        int cnt = 0;
+        int c0 = b0, c1 = (b0 + 1) % nb, c2 = (b0 + 2) % nb;
+        bl[tid][cnt++] = c0;
+        if (c1 != c0)
+            bl[tid][cnt++] = c1;
+        if (min(kBrick, kk - c1 * kBrick) < 4 && c2 != c0 && c2 != c1)
+            bl[tid][cnt++] = c2;
+        bnum[tid] = cnt;
+    }
+    __syncthreads();
+    const int nr = bnum[0] * bnum[1] * bnum[2];
+    if (tid < nr) {
+        int qz = tid % bnum[2], qy = (tid / bnum[2]) % bnum[1], qx = tid / (bnum[2] * bnum[1]);
+        int nbin = (bl[0][qx] * nbr.y + bl[1][qy]) * nbr.z + bl[2][qz];
+        rs[tid] = bin_start[nbin];
+        rn[tid] = bin_start[nbin + 1] - bin_start[nbin];
+    }
+    __syncthreads();
+    if (tid == 0) {
+        pre[0] = 0;
+        for (int q = 0; q < nr; ++q)
+            pre[q + 1] = pre[q] + rn[q];
+    }
+    __syncthreads();
+    const R klx = (R)kl.x, kly = (R)kl.y, klz = (R)kl.z;
+    const int ntot = pre[nr];
+    for (int item = tid; item < ntot; item += 256) {
+        int q = 0;
+        while (item >= pre[q + 1])
+            ++q;
+        const int s = bin_atoms[rs[q] + item - pre[q]];
+        const double4 p = pos_s[s];
+        int fx, fy, fz;
+        double wx, wy, wz;
+        grid_coord(p.x, kl.x, K.x, fx, wx);
+        grid_coord(p.y, kl.y, K.y, fy, wy);
+        grid_coord(p.z, kl.z, K.z, fz, wz);
+        int ix[5], iy[5], iz[5];
+        bool anyx = false, anyy = false, anyz = false;
+#pragma unroll
+        for (int t = 0; t < 5; ++t) {
+            int g = fx - t;
+            g += g < 0 ? K.x : 0;
+            int l = g - lox;
+            ix[t] = (l >= 0 && l < ex) ? l : -1;
+            anyx |= ix[t] >= 0;
+            g = fy - t;
+            g += g < 0 ? K.y : 0;
+            l = g - loy;
+            iy[t] = (l >= 0 && l < ey) ? l : -1;
+            anyy |= iy[t] >= 0;
+            g = fz - t;
+            g += g < 0 ? K.z : 0;
+            l = g - loz;
+            iz[t] = (l >= 0 && l < ez) ? l : -1;
+            anyz |= iz[t] >= 0;
+        }
+        if (!(anyx && anyy && anyz))
+            continue;
+        R x0[5], x1[5], x2[5], y0[5], y1[5], y2[5], z0[5], z1[5], z2[5];
+        spline5<R, PERM>((R)wx, x0, x1, x2);
+        spline5<R, PERM>((R)wy, y0, y1, y2);
+        spline5<R, PERM>((R)wz, z0, z1, z2);
+#pragma unroll
+        for (int t = 0; t < 5; ++t) {
+            x1[t] *= klx;
+            y1[t] *= kly;
+            z1[t] *= klz;
+            if (PERM) {
+                x2[t] *= klx * klx;
+                y2[t] *= kly * kly;
+                z2[t] *= klz * klz;
+            }
+        }
+        if (!PERM) {
+            const R4 mu = src[s];
+            for (int tx = 0; tx < 5; ++tx) {
+                if (ix[tx] < 0)
+                    continue;
+                for (int ty = 0; ty < 5; ++ty) {
+                    if (iy[ty] < 0)
+                        continue;
+                    const R c0 = mu.x * x1[tx] * y0[ty] + mu.y * x0[tx] * y1[ty];  // times z0
+                    const R c1 = mu.z * x0[tx] * y0[ty];                            // times z1
+                    const int base = (ix[tx] * kBrick + iy[ty]) * kBrick;
+                    for (int tz = 0; tz < 5; ++tz) {
+                        if (iz[tz] < 0)
+                            continue;
+                        LdsAcc<FIX>::add(&acc[base + iz[tz]], c0 * z0[tz] + c1 * z1[tz]);
+                    }
+                }
+            }
+        } else {
+            const R4 m0 = src[3 * (size_t)s], m1 = src[3 * (size_t)s + 1], m2 = src[3 * (size_t)s + 2];
+            const R q = m0.x, dx = m0.y, dy = m0.z, dz = m0.w;
+            const R txx = m1.x, txy = m1.y, txz = m1.z, tyy = m1.w, tyz = m2.x, tzz = m2.y;
+            const R third = (R)1 / (R)3;
+            for (int tx = 0; tx < 5; ++tx) {
+                if (ix[tx] < 0)
+                    continue;
+                for (int ty = 0; ty < 5; ++ty) {
+                    if (iy[ty] < 0)
+                        continue;
+                    const R c0 = q * x0[tx] * y0[ty] + dx * x1[tx] * y0[ty] + dy * x0[tx] * y1[ty] +
+                                 third * (txx * x2[tx] * y0[ty] + tyy * x0[tx] * y2[ty] +
+                                          (R)2 * txy * x1[tx] * y1[ty]);
+                    const R c1 = dz * x0[tx] * y0[ty] + (R)2 * third * (txz * x1[tx] * y0[ty] + tyz * x0[tx] * y1[ty]);
+                    const R c2 = third * tzz * x0[tx] * y0[ty];
+                    const int base = (ix[tx] * kBrick + iy[ty]) * kBrick;
+                    for (int tz = 0; tz < 5; ++tz) {
+                        if (iz[tz] < 0)
+                            continue;
+                        LdsAcc<FIX>::add(&acc[base + iz[tz]], c0 * z0[tz] + c1 * z1[tz] + c2 * z2[tz]);
+                    }
+                }
+            }
+        }
+    }
+    __syncthreads();
+    for (int p = tid; p < kBrick * kBrick * kBrick; p += 256) {
+        int lx = p / (kBrick * kBrick), ly = (p / kBrick) % kBrick, lz = p % kBrick;
+        if (lx < ex && ly < ey && lz < ez)
+            grid[((size_t)(lox + lx) * K.y + (loy + ly)) * K.z + (loz + lz)] = (R)LdsAcc<FIX>::get(&acc[p]);
+    }
+}
+
+template <typename R>
+__global__ void k_convolve(size_t n, typename V4p<R>::C* __restrict__ g, const R* __restrict__ theta,
+                           const PcgScalars* __restrict__ sc, int use_done)
+{
+    if (use_done && sc->done)
+        return;
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n)
+        return;
+    R th = theta[i];
+    typename V4p<R>::C v = g[i];
+    v.x *= th;
+    v.y *= th;
+    g[i] = v;
+}
+
+// ------------------------------------------------------------------------------------------
+// gather: E_i = - sum_k grad W_i(k) psi(k)
+// ------------------------------------------------------------------------------------------
+template <typename R>
+__device__ __forceinline__ void gather_field(const double4 p, double3 kl, int3 K, const R* __restrict__ psi, R& ex,
+                                             R& ey, R& ez)
+{
+    int fx, fy, fz;
+    double wx, wy, wz;
+    grid_coord(p.x, kl.x, K.x, fx, wx);
+    grid_coord(p.y, kl.y, K.y, fy, wy);
+    grid_coord(p.z, kl.z, K.z, fz, wz);
+    R x0[5], x1[5], y0[5], y1[5], z0[5], z1[5], dum[5];
+    spline5<R, false>((R)wx, x0, x1, dum);
+    spline5<R, false>((R)wy, y0, y1, dum);
+    spline5<R, false>((R)wz, z0, z1, dum);
+    int gz[5];
+#pragma unroll
+    for (int t = 0; t < 5; ++t) {
+        int g = fz - t;
+        gz[t] = g < 0 ? g + K.z : g;
+    }
+    R sx = 0, sy = 0, sz = 0;
+    for (int tx = 0; tx < 5; ++tx) {
+        int gx = fx - tx;
+        gx += gx < 0 ? K.x : 0;
+        for (int ty = 0; ty < 5; ++ty) {
+            int gy = fy - ty;
+            gy += gy < 0 ? K.y : 0;
+            const R* row = psi + ((size_t)gx * K.y + gy) * K.z;
+            R s0 = 0, s1 = 0;
+#pragma unroll
+            for (int tz = 0; tz < 5; ++tz) {
+                R v = row[gz[tz]];
+                s0 += z0[tz] * v;
+                s1 += z1[tz] * v;
+            }
+            sx += x1[tx] * y0[ty] * s0;
+            sy += x0[tx] * y1[ty] * s0;
+            sz += x0[tx] * y0[ty] * s1;
+        }
+    }
+    ex = -sx * (R)kl.x;
+    ey = -sy * (R)kl.y;
+    ez = -sz * (R)kl.z;
+}
+
+template <typename R>
+__global__ void k_gather_out(int npad, const int* __restrict__ perm, const double4* __restrict__ pos_s, double3 kl,
+                             int3 K, const R* __restrict__ psi, double* __restrict__ out)
+{
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= npad)
+        return;
+    R ex = 0, ey = 0, ez = 0;
+    if (perm[s] >= 0)
+        gather_field<R>(pos_s[s], kl, K, psi, ex, ey, ez);
+    out[3 * (size_t)s] = (double)ex;
+    out[3 * (size_t)s + 1] = (double)ey;
+    out[3 * (size_t)s + 2] = (double)ez;
+}
+
+// PCG matrix-vector product, last stage:  q = p / alpha - (E_real + E_rec + self * p);
+// clears the real-space accumulator for the next product; optionally p.q -> gamma = rz / pq.
+template <typename R, bool FIX>
+__global__ __launch_bounds__(256) void k_gather_combine(int npad, const int* __restrict__ perm,
+                                                        const double4* __restrict__ pos_s, double3 kl, int3 K,
+                                                        const R* __restrict__ psi, const double4* __restrict__ par,
+                                                        const double* __restrict__ p, double self,
+                                                        unsigned long long* __restrict__ acc_fx,
+                                                        double* __restrict__ acc_d, double* __restrict__ q,
+                                                        PcgScalars* __restrict__ sc, double* part,
+                                                        unsigned int* ticket, int use_done, int dot)
+{
+    if (use_done && sc->done)
+        return;
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    double pq = 0.0;
+    if (s < npad) {
+        double e[3] = {0.0, 0.0, 0.0};
+        if (perm[s] >= 0) {
+            R ex, ey, ez;
+            gather_field<R>(pos_s[s], kl, K, psi, ex, ey, ez);
+            e[0] = ex;
+            e[1] = ey;
+            e[2] = ez;
+        }
+        double ainv = par[s].y;
+        for (int a = 0; a < 3; ++a) {
+            size_t i = 3 * (size_t)s + a;
+            double er;
+            if (FIX) {
+                er = (double)(long long)acc_fx[i] * kFixInv;
+                acc_fx[i] = 0ull;
+            } else {
+                er = acc_d[i];
+                acc_d[i] = 0.0;
+            }
+            double pa = p[i];
+            double qa = perm[s] >= 0 ? pa * ainv - (er + e[a] + self * pa) : 0.0;
+            q[i] = qa;
+            pq += pa * qa;
+        }
+    }
+    if (!dot)
+        return;
+    double v[1] = {pq};
+    grid_reduce<1>(v, part, ticket, [sc](const double* tot) {
+        sc->pq = tot[0];
+        if (!(tot[0] > 0.0) || !isfinite(tot[0])) {
+            sc->done = 1;
+            sc->status = 2;
+            sc->gamma = 0.0;
+        } else {
+            sc->gamma = sc->rz / tot[0];
+        }
+    });
+}
+
+static inline int nblk(size_t n, int b) { return (int)((n + b - 1) / b); }
+
+// ------------------------------------------------------------------------------------------
+// host side
+// ------------------------------------------------------------------------------------------
+int pme_setup(amoeba_ctx* c)
+{
+    for (int a = 0; a < 3; ++a) {
+        c->K[a] = c->prm.grid[a];
+        c->nbr[a] = (c->K[a] + kBrick - 1) / kBrick;
+    }
+    c->nbricks = c->nbr[0] * c->nbr[1] * c->nbr[2];
+    c->ngrid = (size_t)c->K[0] * c->K[1] * c->K[2];
+    c->ncgrid = (size_t)c->K[0] * c->K[1] * (c->K[2] / 2 + 1);
+    size_t rs = c->mixed ? sizeof(float) : sizeof(double);
+    int rc;
+    if ((rc = ctx_alloc(c, &c->grid_r, rs * c->ngrid)) || (rc = ctx_alloc(c, &c->grid_c, 2 * rs * c->ncgrid)) ||
+        (rc = ctx_alloc(c, &c->theta, rs * c->ncgrid)) ||
+        (rc = ctx_alloc(c, (void**)&c->bin_start, sizeof(int) * (c->nbricks + 1))) ||
+        (rc = ctx_alloc(c, (void**)&c->bin_count, sizeof(int) * (c->nbricks + 1))) ||
+        (rc = ctx_alloc(c, (void**)&c->bin_atoms, sizeof(int) * c->npad)) ||
+        (rc = ctx_alloc(c, (void**)&c->atom_bin, sizeof(int) * c->npad)))
+        return rc;
+
+    // B-spline moduli and influence function
+    double* mods = nullptr;
+    if (hipMalloc(&mods, sizeof(double) * (c->K[0] + c->K[1] + c->K[2])) != hipSuccess)
+        return set_error(c, AMOEBA_E_NOMEM, "pme_setup: moduli");
+    double* md[3] = {mods, mods + c->K[0], mods + c->K[0] + c->K[1]};
+    for (int a = 0; a < 3; ++a)
+        hipLaunchKernelGGL(k_bsmod, dim3(nblk(c->K[a], 64)), dim3(64), 0, c->stream, c->K[a], md[a]);
+    int3 K = make_int3(c->K[0], c->K[1], c->K[2]);
+    double3 box = make_double3(c->prm.box[0], c->prm.box[1], c->prm.box[2]);
+    if (c->mixed)
+        hipLaunchKernelGGL(k_theta<float>, dim3(nblk(c->ncgrid, 256)), dim3(256), 0, c->stream, K, box,
+                           c->prm.ewald_alpha, md[0], md[1], md[2], (float*)c->theta);
+    else
+        hipLaunchKernelGGL(k_theta<double>, dim3(nblk(c->ncgrid, 256)), dim3(256), 0, c->stream, K, box,
+                           c->prm.ewald_alpha, md[0], md[1], md[2], (double*)c->theta);
+    rc = hip_check(c, hipStreamSynchronize(c->stream), "pme_setup theta");
+    hipFree(mods);
+    if (rc)
+        return rc;
+
+    // rocFFT plans: 3-D real <-> half-complex, out of place, lengths fastest-first
+    static bool fft_ready = false;
+    if (!fft_ready) {
+        if (rocfft_setup() != rocfft_status_success)
+            return set_error(c, AMOEBA_E_DEVICE, "rocfft_setup failed");
+        fft_ready = true;
+    }
+    size_t len[3] = {(size_t)c->K[2], (size_t)c->K[1], (size_t)c->K[0]};
+    rocfft_precision prec = c->mixed ? rocfft_precision_single : rocfft_precision_double;
+    if (rocfft_plan_create(&c->plan_fwd, rocfft_placement_notinplace, rocfft_transform_type_real_forward, prec, 3,
+                           len, 1, nullptr) != rocfft_status_success ||
+        rocfft_plan_create(&c->plan_bwd, rocfft_placement_notinplace, rocfft_transform_type_real_inverse, prec, 3,
+                           len, 1, nullptr) != rocfft_status_success)
+        return set_error(c, AMOEBA_E_DEVICE, "rocfft_plan_create failed");
+    size_t w1 = 0, w2 = 0;
+    rocfft_plan_get_work_buffer_size(c->plan_fwd, &w1);
+    rocfft_plan_get_work_buffer_size(c->plan_bwd, &w2);
+    c->fft_work_bytes = w1 > w2 ? w1 : w2;
+    if (c->fft_work_bytes && (rc = ctx_alloc(c, &c->fft_work, c->fft_work_bytes)))
+        return rc;
+    if (rocfft_execution_info_create(&c->exec_fwd) != rocfft_status_success ||
+        rocfft_execution_info_create(&c->exec_bwd) != rocfft_status_success)
+        return set_error(c, AMOEBA_E_DEVICE, "rocfft_execution_info_create failed");
+    rocfft_execution_info_set_stream(c->exec_fwd, c->stream);
+    rocfft_execution_info_set_stream(c->exec_bwd, c->stream);
+    if (c->fft_work_bytes) {
+        rocfft_execution_info_set_work_buffer(c->exec_fwd, c->fft_work, c->fft_work_bytes);
+        rocfft_execution_info_set_work_buffer(c->exec_bwd, c->fft_work, c->fft_work_bytes);
+    }
+    return AMOEBA_OK;
+}
+
+__global__ void k_scan_excl_pme(int n, const int* __restrict__ in, int* __restrict__ out);
+
+void pme_bin_atoms(amoeba_ctx* c)
+{
+    hipStream_t st = c->stream;
+    int3 K = make_int3(c->K[0], c->K[1], c->K[2]);
+    int3 nbr = make_int3(c->nbr[0], c->nbr[1], c->nbr[2]);
+    double3 kl = make_double3(c->K[0] / c->prm.box[0], c->K[1] / c->prm.box[1], c->K[2] / c->prm.box[2]);
+    hipMemsetAsync(c->bin_count, 0, sizeof(int) * (c->nbricks + 1), st);
+    hipLaunchKernelGGL(k_bin_count, dim3(nblk(c->npad, 256)), dim3(256), 0, st, c->npad, c->perm, c->pos_s, kl, K,
+                       nbr, c->bin_count, c->atom_bin);
+    hipLaunchKernelGGL(k_scan_excl_pme, dim3(1), dim3(1024), 0, st, c->nbricks, c->bin_count, c->bin_start);
+    hipMemsetAsync(c->bin_count, 0, sizeof(int) * (c->nbricks + 1), st);
+    hipLaunchKernelGGL(k_bin_fill, dim3(nblk(c->npad, 256)), dim3(256), 0, st, c->npad, c->atom_bin, c->bin_start,
+                       c->bin_count, c->bin_atoms);
+    hipLaunchKernelGGL(k_bin_sort, dim3(nblk(c->nbricks, 64)), dim3(64), 0, st, c->nbricks, c->bin_start,
+                       c->bin_atoms);
+}
+
+__global__ __launch_bounds__(1024) void k_scan_excl_pme(int n, const int* __restrict__ in, int* __restrict__ out)
+{
+    __shared__ int part[1024];
+    int t = threadIdx.x;
+    int chunk = (n + 1023) / 1024;
+    int b = t * chunk, e = min(n, b + chunk);
+    int s = 0;
+    for (int i = b; i < e; ++i)
+        s += in[i];
+    part[t] = s;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        int v = t >= off ? part[t - off] : 0;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    int run = t ? part[t - 1] : 0;
+    for (int i = b; i < e; ++i) {
+        out[i] = run;
+        run += in[i];
+    }
+    if (t == 1023)
+        out[n] = part[1023];
+}
+
+static int run_fft(amoeba_ctx* c, const void* grid_src, bool use_done)
+{
+    (void)grid_src;
+    (void)use_done;
+    void* in_f[1] = {c->grid_r};
+    void* out_f[1] = {c->grid_c};
+    if (rocfft_execute(c->plan_fwd, in_f, out_f, c->exec_fwd) != rocfft_status_success)
+        return set_error(c, AMOEBA_E_DEVICE, "rocfft_execute (forward) failed");
+    return AMOEBA_OK;
+}
+
+static int convolve_and_back(amoeba_ctx* c, bool use_done)
+{
+    if (c->mixed)
+        hipLaunchKernelGGL(k_convolve<float>, dim3(nblk(c->ncgrid, 256)), dim3(256), 0, c->stream, c->ncgrid,
+                           (float2*)c->grid_c, (const float*)c->theta, c->sc, (int)use_done);
+    else
+        hipLaunchKernelGGL(k_convolve<double>, dim3(nblk(c->ncgrid, 256)), dim3(256), 0, c->stream, c->ncgrid,
+                           (double2*)c->grid_c, (const double*)c->theta, c->sc, (int)use_done);
+    void* in_b[1] = {c->grid_c};
+    void* out_b[1] = {c->grid_r};
+    if (rocfft_execute(c->plan_bwd, in_b, out_b, c->exec_bwd) != rocfft_status_success)
+        return set_error(c, AMOEBA_E_DEVICE, "rocfft_execute (backward) failed");
+    return AMOEBA_OK;
+}
+
+int pme_dipole_field(amoeba_ctx* c, bool use_done)
+{
+    int3 K = make_int3(c->K[0], c->K[1], c->K[2]);
+    int3 nbr = make_int3(c->nbr[0], c->nbr[1], c->nbr[2]);
+    double3 kl = make_double3(c->K[0] / c->prm.box[0], c->K[1] / c->prm.box[1], c->K[2] / c->prm.box[2]);
+    if (c->mixed)
+        hipLaunchKernelGGL((k_spread<float, true, false>), dim3(c->nbricks), dim3(256), 0, c->stream, K, nbr,
+                           c->bin_start, c->bin_atoms, c->pos_s, kl, c->pv_f, (float*)c->grid_r, c->sc,
+                           (int)use_done);
+    else
+        hipLaunchKernelGGL((k_spread<double, false, false>), dim3(c->nbricks), dim3(256), 0, c->stream, K, nbr,
+                           c->bin_start, c->bin_atoms, c->pos_s, kl, c->pv_d, (double*)c->grid_r, c->sc,
+                           (int)use_done);
+    int rc = run_fft(c, nullptr, use_done);
+    if (rc)
+        return rc;
+    return convolve_and_back(c, use_done);
+}
+
+int pme_perm_potential(amoeba_ctx* c)
+{
+    int3 K = make_int3(c->K[0], c->K[1], c->K[2]);
+    int3 nbr = make_int3(c->nbr[0], c->nbr[1], c->nbr[2]);
+    double3 kl = make_double3(c->K[0] / c->prm.box[0], c->K[1] / c->prm.box[1], c->K[2] / c->prm.box[2]);
+    if (c->mixed)
+        hipLaunchKernelGGL((k_spread<float, true, true>), dim3(c->nbricks), dim3(256), 0, c->stream, K, nbr,
+                           c->bin_start, c->bin_atoms, c->pos_s, kl, (const float4*)c->mp_f, (float*)c->grid_r,
+                           c->sc, 0);
+    else
+        hipLaunchKernelGGL((k_spread<double, false, true>), dim3(c->nbricks), dim3(256), 0, c->stream, K, nbr,
+                           c->bin_start, c->bin_atoms, c->pos_s, kl, (const double4*)c->mp_d, (double*)c->grid_r,
+                           c->sc, 0);
+    int rc = run_fft(c, nullptr, false);
+    if (rc)
+        return rc;
+    return convolve_and_back(c, false);
+}
+
+void launch_gather(amoeba_ctx* c, double* out)
+{
+    int3 K = make_int3(c->K[0], c->K[1], c->K[2]);
+    double3 kl = make_double3(c->K[0] / c->prm.box[0], c->K[1] / c->prm.box[1], c->K[2] / c->prm.box[2]);
+    if (c->mixed)
+        hipLaunchKernelGGL(k_gather_out<float>, dim3(nblk(c->npad, 256)), dim3(256), 0, c->stream, c->npad, c->perm,
+                           c->pos_s, kl, K, (const float*)c->grid_r, out);
+    else
+        hipLaunchKernelGGL(k_gather_out<double>, dim3(nblk(c->npad, 256)), dim3(256), 0, c->stream, c->npad,
+                           c->perm, c->pos_s, kl, K, (const double*)c->grid_r, out);
+}
+
+void launch_matvec_combine(amoeba_ctx* c, bool use_done, bool dot_pq)
+{
+    int3 K = make_int3(c->K[0], c->K[1], c->K[2]);
+    double3 kl = make_double3(c->K[0] / c->prm.box[0], c->K[1] / c->prm.box[1], c->K[2] / c->prm.box[2]);
+    double b = c->prm.ewald_alpha;
+    double self = 4.0 * b * b * b / (3.0 * sqrt(kPi));
+    if (c->mixed)
+        hipLaunchKernelGGL((k_gather_combine<float, true>), dim3(nblk(c->npad, 256)), dim3(256), 0, c->stream,
+                           c->npad, c->perm, c->pos_s, kl, K, (const float*)c->grid_r, c->par_d, c->v_p, self,
+                           c->acc_fx, (double*)nullptr, c->v_q, c->sc, c->red.part, c->red.ticket, (int)use_done,
+                           (int)dot_pq);
+    else
+        hipLaunchKernelGGL((k_gather_combine<double, false>), dim3(nblk(c->npad, 256)), dim3(256), 0, c->stream,
+                           c->npad, c->perm, c->pos_s, kl, K, (const double*)c->grid_r, c->par_d, c->v_p, self,
+                           (unsigned long long*)nullptr, c->acc_d, c->v_q, c->sc, c->red.part, c->red.ticket,
+                           (int)use_done, (int)dot_pq);
+}
+
+}  // namespace amoeba

@@ -1,0 +1,199 @@
+"""GPU parity of every kernel stage against the FP64 oracle, through the C ABI.
+
+FP64 mode must agree with the oracle's smooth-PME evaluation (same grid, order, beta, cutoff)
+to rounding; mixed precision (FP32 pair/PME math, fixed-point accumulation, FP64 PCG) to the
+stated bounds.  Discretization error of PME against the exact Ewald k-sum is measured by the
+oracle tests, not here."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2011_01207_amd import amoeba, synth
+
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+DEV = "cuda:0"
+
+
+def rel_rms(a, b):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    return float(np.sqrt(np.mean((a - b) ** 2)) / np.sqrt(np.mean(b ** 2)))
+
+
+def tiny_water(n_w, L, K, seed, rc=None):
+    s = synth.water_box(n_w, L, K, seed, f"water_{3 * n_w}")
+    if rc is not None:
+        s.cutoff = rc
+    return s
+
+
+@pytest.fixture(scope="module")
+def c1():
+    return synth.water648()
+
+
+@pytest.fixture(scope="module")
+def c1_ref(c1):
+    rng = np.random.default_rng(42)
+    mu = rng.standard_normal((c1.n, 3)) * 0.05
+    return {
+        "mu": mu,
+        "real": O.real_mutual(c1, mu),
+        "recip": O.spme_field(c1, dip=mu),
+        "matvec": O.matvec(c1, mu, "spme"),
+        "perm": O.perm_field(c1, "spme"),
+    }
+
+
+@pytest.fixture(scope="module", params=["fp64", "mixed"])
+def c1_ctx(request, c1):
+    print(f"[gpu] c1 context {request.param}", flush=True)
+    ctx, t = amoeba.context_for(c1, precision=request.param, device=DEV)
+    yield request.param, ctx, t
+    ctx.close()
+
+
+TOL = {"fp64": {"real": 1e-12, "recip": 1e-11, "matvec": 1e-12, "perm": 1e-11},
+       "mixed": {"real": 2e-6, "recip": 2e-5, "matvec": 2e-6, "perm": 2e-5}}
+
+
+def test_pair_count_equals_oracle(c1, c1_ctx):
+    prec, ctx, t = c1_ctx
+    assert ctx.info()["n_pairs"] == O.count_pairs(c1)
+
+
+def test_real_and_recip_fields(c1, c1_ref, c1_ctx):
+    prec, ctx, t = c1_ctx
+    mu = torch.tensor(c1_ref["mu"], device=DEV)
+    er, ek = ctx.dipole_field_parts(t["pos"], mu)
+    assert rel_rms(er.cpu().numpy(), c1_ref["real"]) < TOL[prec]["real"]
+    assert rel_rms(ek.cpu().numpy(), c1_ref["recip"]) < TOL[prec]["recip"]
+
+
+def test_matvec(c1, c1_ref, c1_ctx):
+    prec, ctx, t = c1_ctx
+    mu = torch.tensor(c1_ref["mu"], device=DEV)
+    out = ctx.dipole_matvec(t["pos"], mu).cpu().numpy()
+    assert rel_rms(out, c1_ref["matvec"]) < TOL[prec]["matvec"]
+
+
+def test_perm_field(c1, c1_ref, c1_ctx):
+    prec, ctx, t = c1_ctx
+    e = ctx.perm_field(t["pos"], t["q"], t["dip"], t["quad"]).cpu().numpy()
+    assert rel_rms(e, c1_ref["perm"]) < TOL[prec]["perm"]
+
+
+def test_polarize_c1(c1, c1_ref, c1_ctx):
+    prec, ctx, t = c1_ctx
+    e_ref = c1_ref["perm"]
+    mu_ref, it_ref, _ = O.pcg(c1, e_ref, "spme", tol_debye=1e-10)
+    e_gpu = torch.tensor(e_ref, device=DEV)
+    mu, ep, it, st = ctx.polarize(t["pos"], e_gpu, tol_debye=1e-7, max_iter=200)
+    assert st == amoeba.AMOEBA_OK
+    err = O.rms_debye(mu.cpu().numpy() - mu_ref)
+    ep_ref = O.e_pol(mu_ref, e_ref)
+    if prec == "fp64":
+        assert err < 2e-7
+        assert abs(ep - ep_ref) < 1e-8 * abs(ep_ref)
+        # same iteration count as the oracle's PCG at the configuration's own tolerance
+        _, it_o, _ = O.pcg(c1, e_ref, "spme", tol_debye=1e-6)
+        _, _, it_g, _ = ctx.polarize(t["pos"], e_gpu, tol_debye=1e-6, max_iter=200)
+        assert abs(it_g - it_o) <= 1
+    else:
+        assert err < 1e-5
+        assert abs(ep - ep_ref) < 1e-5 * abs(ep_ref)
+
+
+def test_mixed_solve_is_bitwise_deterministic(c1):
+    ctx, t = amoeba.context_for(c1, precision="mixed", device=DEV)
+    e = ctx.perm_field(t["pos"], t["q"], t["dip"], t["quad"])
+    a, ea, ia, _ = ctx.polarize(t["pos"], e, tol_debye=1e-6)
+    b, eb, ib, _ = ctx.polarize(t["pos"], e, tol_debye=1e-6)
+    assert torch.equal(a, b) and ea == eb and ia == ib
+    # a fresh context (fresh list build) gives the same bits
+    ctx2, t2 = amoeba.context_for(c1, precision="mixed", device=DEV)
+    e2 = ctx2.perm_field(t2["pos"], t2["q"], t2["dip"], t2["quad"])
+    assert torch.equal(e, e2)
+    c, ec, ic, _ = ctx2.polarize(t2["pos"], e2, tol_debye=1e-6)
+    assert torch.equal(a, c)
+    ctx.close()
+    ctx2.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_solvated_chain_perm_and_matvec(prec):
+    """23,558 atoms with 1-2/1-3 exclusions and 1-4 half scaling; compared at sampled atoms."""
+    s = synth.solvated_chain()
+    print(f"[gpu] solvated chain {prec}", flush=True)
+    ctx, t = amoeba.context_for(s, precision=prec, device=DEV)
+    rng = np.random.default_rng(7)
+    idx = np.sort(rng.choice(s.n, 300, replace=False))
+    idx = np.unique(np.concatenate([idx, np.arange(0, 40)]))   # include chain atoms with 1-4 pairs
+    e_ref = O.perm_field(s, "spme", idx=idx)
+    e = ctx.perm_field(t["pos"], t["q"], t["dip"], t["quad"]).cpu().numpy()[idx]
+    tol = 1e-11 if prec == "fp64" else 3e-5
+    assert rel_rms(e, e_ref) < tol
+    mu = rng.standard_normal((s.n, 3)) * 0.05
+    q_ref = O.matvec(s, mu, "spme", idx=idx)
+    q = ctx.dipole_matvec(t["pos"], torch.tensor(mu, device=DEV)).cpu().numpy()[idx]
+    assert rel_rms(q, q_ref) < (1e-12 if prec == "fp64" else 3e-6)
+    ctx.close()
+
+
+def test_ragged_single_block_and_no_scaled_pairs():
+    """Fewer atoms than one block (phantom padding), no scaled pairs, non-cubic box."""
+    s = synth.tiny_cell(37, 16.0, 5, min_dist=1.2)
+    s.box = np.array([16.0, 17.0, 18.5])
+    s.pos = np.mod(s.pos, s.box)
+    s.cutoff, s.ewald_alpha, s.grid = 6.0, 0.6, (20, 18, 25)
+    ctx, t = amoeba.context_for(s, precision="fp64", device=DEV)
+    assert ctx.info()["n_pairs"] == O.count_pairs(s)
+    e = ctx.perm_field(t["pos"], t["q"], t["dip"], t["quad"]).cpu().numpy()
+    assert rel_rms(e, O.perm_field(s, "spme")) < 1e-11
+    mu_ref, _, _ = O.pcg(s, O.perm_field(s, "spme"), "spme", tol_debye=1e-10)
+    mu, _, _, st = ctx.polarize(t["pos"], torch.tensor(e, device=DEV), tol_debye=1e-9)
+    assert st == amoeba.AMOEBA_OK and O.rms_debye(mu.cpu().numpy() - mu_ref) < 1e-8
+    ctx.close()
+
+
+def test_error_paths(c1):
+    p = amoeba.Context(c1.n, c1.box, grid=c1.grid)
+    pos = torch.tensor(c1.pos, device=DEV)
+    with pytest.raises(amoeba.AmoebaError) as ei:
+        p.build_blocklist(pos)  # parameters not set yet is allowed; perm field is not
+        p.dipole_matvec(pos, torch.zeros_like(pos))
+    assert ei.value.status == amoeba.AMOEBA_E_STATE
+    p.close()
+    ctx, t = amoeba.context_for(c1, precision="fp64", device=DEV)
+    # stale list: buffer 0, any motion invalidates it
+    moved = t["pos"] + 0.01
+    with pytest.raises(amoeba.AmoebaError) as ei:
+        ctx.dipole_matvec(moved, torch.zeros_like(moved))
+    assert ei.value.status == amoeba.AMOEBA_E_LIST
+    # NaN in a dipole
+    bad = torch.zeros_like(t["pos"])
+    bad[5, 1] = float("nan")
+    with pytest.raises(amoeba.AmoebaError) as ei:
+        ctx.dipole_matvec(t["pos"], bad)
+    assert ei.value.status == amoeba.AMOEBA_E_NUMERIC
+    # non-convergence returns the last iterate
+    e = ctx.perm_field(t["pos"], t["q"], t["dip"], t["quad"])
+    mu, ep, it, st = ctx.polarize(t["pos"], e, tol_debye=1e-12, max_iter=3)
+    assert st == amoeba.AMOEBA_NOT_CONVERGED and it == 3 and torch.isfinite(mu).all()
+    # invalid CSR: one direction missing
+    sc_j = t["sc_j"].clone()
+    sc_j[0] = (sc_j[0] + 7) % c1.n
+    with pytest.raises(amoeba.AmoebaError) as ei:
+        ctx.set_atoms(t["alpha"], t["thole"], t["sc_ptr"], sc_j, t["sc_s"])
+    assert ei.value.status == amoeba.AMOEBA_E_INVALID
+    neg = t["alpha"].clone()
+    neg[3] = -1.0
+    with pytest.raises(amoeba.AmoebaError) as ei:
+        ctx.set_atoms(neg, t["thole"], t["sc_ptr"], t["sc_j"], t["sc_s"])
+    assert ei.value.status == amoeba.AMOEBA_E_INVALID
+    ctx.close()
