@@ -164,6 +164,33 @@ int amoeba_polarize(amoeba_ctx* ctx, const double* pos, const double* e_perm,
 /* Sizes and counters of the context (host struct). */
 int amoeba_get_info(const amoeba_ctx* ctx, amoeba_info* out);
 
+/* Kernel-time accounting (diagnostic; used by the benchmark for its roofline figures).
+ * When enabled, every launch of the listed stages is bracketed by HIP events on the context's
+ * stream; amoeba_get_timing synchronises the stream and returns the accumulated milliseconds
+ * and launch counts per stage since the last amoeba_set_timing.  Launches that return early
+ * because the solve already converged are included (as a profiler would count them);
+ * `matvecs` counts the matrix-vector products that did work. */
+typedef enum amoeba_stage {
+    AMOEBA_T_LIST = 0,     /* list build and per-configuration mask refresh                 */
+    AMOEBA_T_PERM = 1,     /* permanent-field tiles and assembly                            */
+    AMOEBA_T_REAL = 2,     /* real-space dipole tiles (one per matrix-vector product)       */
+    AMOEBA_T_SPREAD = 3,   /* PME spread                                                    */
+    AMOEBA_T_FFT = 4,      /* forward FFT + influence product + backward FFT                */
+    AMOEBA_T_GATHER = 5,   /* PME gather fused with the operator assembly and p.Ap          */
+    AMOEBA_T_PCG = 6,      /* PCG vector updates and reductions                             */
+    AMOEBA_T_COUNT = 7
+} amoeba_stage;
+
+typedef struct amoeba_timing {
+    double ms[AMOEBA_T_COUNT];
+    int64_t launches[AMOEBA_T_COUNT];
+    int64_t matvecs;
+} amoeba_timing;
+
+/* enable != 0 turns accounting on, 0 off; both reset the counters. */
+int amoeba_set_timing(amoeba_ctx* ctx, int enable);
+int amoeba_get_timing(amoeba_ctx* ctx, amoeba_timing* out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -47,6 +47,10 @@ class amoeba_info(ctypes.Structure):
                 ("last_iterations", ctypes.c_int32), ("last_rms_debye", ctypes.c_double)]
 
 
+class amoeba_timing(ctypes.Structure):
+    _fields_ = [("ms", ctypes.c_double * 7), ("launches", ctypes.c_int64 * 7), ("matvecs", ctypes.c_int64)]
+
+
 class AmoebaError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
@@ -79,6 +83,8 @@ def lib() -> ctypes.CDLL:
         L.amoeba_polarize.argtypes = [_P, _P, _P, _P, ctypes.c_int32, ctypes.c_double, ctypes.c_int32, _P,
                                       ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32)]
         L.amoeba_get_info.argtypes = [_P, ctypes.POINTER(amoeba_info)]
+        L.amoeba_set_timing.argtypes = [_P, ctypes.c_int]
+        L.amoeba_get_timing.argtypes = [_P, ctypes.POINTER(amoeba_timing)]
         _lib = L
     return _lib
 

@@ -25,6 +25,28 @@ int hip_check(amoeba_ctx* c, hipError_t e, const char* what)
     return set_error(c, e == hipErrorOutOfMemory ? AMOEBA_E_NOMEM : AMOEBA_E_DEVICE, m);
 }
 
+StageTimer::StageTimer(amoeba_ctx* ctx, int stage) : c(ctx)
+{
+    if (!c->timing)
+        return;
+    size_t need = c->trec.size() * 2 + 2;
+    while (c->tev.size() < need) {
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess)
+            return;
+        c->tev.push_back(e);
+    }
+    idx = (int)c->trec.size() * 2;
+    c->trec.push_back({stage, idx});
+    hipEventRecord(c->tev[idx], c->stream);
+}
+
+StageTimer::~StageTimer()
+{
+    if (idx >= 0)
+        hipEventRecord(c->tev[idx + 1], c->stream);
+}
+
 int ctx_alloc(amoeba_ctx* c, void** p, size_t bytes)
 {
     if (bytes == 0)
@@ -350,6 +372,8 @@ int amoeba_destroy(amoeba_ctx* c)
     for (auto& e : c->ev)
         if (e)
             hipEventDestroy(e);
+    for (auto& e : c->tev)
+        hipEventDestroy(e);
     delete c;
     return AMOEBA_OK;
 }
@@ -489,6 +513,7 @@ int amoeba_dipole_matvec(amoeba_ctx* c, const double* pos, const double* mu, dou
     launch_zero_acc(c);
     if ((rc = matvec_slot(c, false, false)))
         return rc;
+    c->matvecs += 1;
     if ((rc = check_overflow(c, c->v_q)))
         return rc;
     launch_scatter(c, c->v_q, out);
@@ -518,6 +543,7 @@ int amoeba_dipole_field_parts(amoeba_ctx* c, const double* pos, const double* mu
     if ((rc = pme_dipole_field(c, false)))
         return rc;
     launch_gather(c, c->erec);
+    c->matvecs += 1;
     if (e_recip)
         launch_scatter(c, c->erec, e_recip);
     return hip_check(c, hipStreamSynchronize(c->stream), "amoeba_dipole_field_parts");
@@ -569,6 +595,36 @@ int amoeba_polarize(amoeba_ctx* c, const double* pos, const double* e_perm, cons
     if (st == AMOEBA_NOT_CONVERGED)
         set_error(c, AMOEBA_NOT_CONVERGED, "PCG did not reach the tolerance within max_iter");
     return st;
+}
+
+int amoeba_set_timing(amoeba_ctx* c, int enable)
+{
+    if (!c)
+        return AMOEBA_E_INVALID;
+    hipStreamSynchronize(c->stream);
+    c->timing = enable != 0;
+    c->trec.clear();
+    c->matvecs = 0;
+    return AMOEBA_OK;
+}
+
+int amoeba_get_timing(amoeba_ctx* c, amoeba_timing* out)
+{
+    if (!c || !out)
+        return AMOEBA_E_INVALID;
+    int rc = hip_check(c, hipStreamSynchronize(c->stream), "amoeba_get_timing");
+    if (rc)
+        return rc;
+    std::memset(out, 0, sizeof(*out));
+    for (auto& r : c->trec) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, c->tev[r.second], c->tev[r.second + 1]) != hipSuccess)
+            return set_error(c, AMOEBA_E_DEVICE, "hipEventElapsedTime failed");
+        out->ms[r.first] += ms;
+        out->launches[r.first] += 1;
+    }
+    out->matvecs = c->matvecs;
+    return AMOEBA_OK;
 }
 
 int amoeba_get_info(const amoeba_ctx* c, amoeba_info* out)

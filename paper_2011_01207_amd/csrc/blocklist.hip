@@ -404,6 +404,7 @@ void pme_bin_atoms(amoeba_ctx* c);
 
 static int refresh_tiles(amoeba_ctx* c)
 {
+    StageTimer tm(c, AMOEBA_T_LIST);
     hipStream_t st = c->stream;
     double3 box = make_double3(c->prm.box[0], c->prm.box[1], c->prm.box[2]);
     hipLaunchKernelGGL(k_block_frame, dim3(nblk(c->npad, 256)), dim3(256), 0, st, c->npad, c->perm, c->pos_s, box,

@@ -152,6 +152,12 @@ struct amoeba_ctx {
     int* flags_host = nullptr;             // pinned
     unsigned long long* counter = nullptr; // device counters (pairs)
     hipEvent_t ev[2] = {nullptr, nullptr};
+
+    // stage timing (diagnostic)
+    bool timing = false;
+    std::vector<hipEvent_t> tev;                 // event pool
+    std::vector<std::pair<int, int>> trec;       // (stage, index of start event in the pool)
+    int64_t matvecs = 0;
 };
 
 namespace amoeba {
@@ -160,6 +166,14 @@ namespace amoeba {
 int ctx_alloc(amoeba_ctx* c, void** p, size_t bytes);
 int set_error(amoeba_ctx* c, int code, const std::string& msg);
 int hip_check(amoeba_ctx* c, hipError_t e, const char* what);
+
+// RAII stage timer: records a start/stop event pair on the context stream when timing is on.
+struct StageTimer {
+    amoeba_ctx* c;
+    int idx = -1;
+    StageTimer(amoeba_ctx* ctx, int stage);
+    ~StageTimer();
+};
 
 // blocklist.hip
 int build_blocklist(amoeba_ctx* c, const double* pos);

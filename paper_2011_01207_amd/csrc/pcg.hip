@@ -215,6 +215,7 @@ int matvec_slot(amoeba_ctx* c, bool use_done, bool dot)
 
 static void launch_init_residual(amoeba_ctx* c, const double* q)
 {
+    StageTimer tm(c, AMOEBA_T_PCG);
     if (c->mixed)
         hipLaunchKernelGGL(k_init_residual<float4>, dim3(nblk(c->npad, 256)), dim3(256), 0, c->stream, c->npad, c->n,
                            c->par_d, c->v_e, q, c->v_r, c->v_z, c->v_p, c->pv_f, c->sc, c->red.part, c->red.ticket);
@@ -297,6 +298,7 @@ int pcg_solve(amoeba_ctx* c, double tol, int max_iter, bool have_guess)
     if ((rc = read_scalars(c, &s)))
         return rc;
     int used = 0;
+    int extra_matvecs = 0;
     bool checked_true = !c->mixed;
     while (true) {
         if (!s.done && used < max_iter) {
@@ -313,6 +315,7 @@ int pcg_solve(amoeba_ctx* c, double tol, int max_iter, bool have_guess)
         // Mixed precision: confirm convergence on the true residual e - A mu (FP64 vectors); if it
         // fails, PCG restarts from the true residual with the remaining iteration budget.
         checked_true = true;
+        ++extra_matvecs;
         launch_set_direction(c, c->v_mu);
         if ((rc = matvec_slot(c, false, false)))
             return rc;
@@ -335,6 +338,7 @@ int pcg_solve(amoeba_ctx* c, double tol, int max_iter, bool have_guess)
     }
     c->last_iters = s.iters;
     c->last_rms = s.rms;
+    c->matvecs += s.iters + (have_guess ? 1 : 0) + extra_matvecs;
     return s.status == 1 ? AMOEBA_OK : AMOEBA_NOT_CONVERGED;
 }
 

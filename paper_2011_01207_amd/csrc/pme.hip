@@ -627,6 +627,8 @@ int pme_dipole_field(amoeba_ctx* c, bool use_done)
     int3 K = make_int3(c->K[0], c->K[1], c->K[2]);
     int3 nbr = make_int3(c->nbr[0], c->nbr[1], c->nbr[2]);
     double3 kl = make_double3(c->K[0] / c->prm.box[0], c->K[1] / c->prm.box[1], c->K[2] / c->prm.box[2]);
+    {
+    StageTimer tm(c, AMOEBA_T_SPREAD);
     if (c->mixed)
         hipLaunchKernelGGL((k_spread<float, true, false>), dim3(c->nbricks), dim3(256), 0, c->stream, K, nbr,
                            c->bin_start, c->bin_atoms, c->pos_s, kl, c->pv_f, (float*)c->grid_r, c->sc,
@@ -635,6 +637,8 @@ int pme_dipole_field(amoeba_ctx* c, bool use_done)
         hipLaunchKernelGGL((k_spread<double, false, false>), dim3(c->nbricks), dim3(256), 0, c->stream, K, nbr,
                            c->bin_start, c->bin_atoms, c->pos_s, kl, c->pv_d, (double*)c->grid_r, c->sc,
                            (int)use_done);
+    }
+    StageTimer tm(c, AMOEBA_T_FFT);
     int rc = run_fft(c, nullptr, use_done);
     if (rc)
         return rc;
@@ -643,6 +647,7 @@ int pme_dipole_field(amoeba_ctx* c, bool use_done)
 
 int pme_perm_potential(amoeba_ctx* c)
 {
+    StageTimer tm(c, AMOEBA_T_PERM);
     int3 K = make_int3(c->K[0], c->K[1], c->K[2]);
     int3 nbr = make_int3(c->nbr[0], c->nbr[1], c->nbr[2]);
     double3 kl = make_double3(c->K[0] / c->prm.box[0], c->K[1] / c->prm.box[1], c->K[2] / c->prm.box[2]);
@@ -662,6 +667,7 @@ int pme_perm_potential(amoeba_ctx* c)
 
 void launch_gather(amoeba_ctx* c, double* out)
 {
+    StageTimer tm(c, AMOEBA_T_GATHER);
     int3 K = make_int3(c->K[0], c->K[1], c->K[2]);
     double3 kl = make_double3(c->K[0] / c->prm.box[0], c->K[1] / c->prm.box[1], c->K[2] / c->prm.box[2]);
     if (c->mixed)
@@ -674,6 +680,7 @@ void launch_gather(amoeba_ctx* c, double* out)
 
 void launch_matvec_combine(amoeba_ctx* c, bool use_done, bool dot_pq)
 {
+    StageTimer tm(c, AMOEBA_T_GATHER);
     int3 K = make_int3(c->K[0], c->K[1], c->K[2]);
     double3 kl = make_double3(c->K[0] / c->prm.box[0], c->K[1] / c->prm.box[1], c->K[2] / c->prm.box[2]);
     double b = c->prm.ewald_alpha;

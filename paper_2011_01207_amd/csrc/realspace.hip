@@ -305,6 +305,7 @@ void launch_mutual_tiles(amoeba_ctx* c, bool use_done)
 {
     if (c->ntiles == 0)
         return;
+    StageTimer tm(c, AMOEBA_T_REAL);
     if (c->mixed)
         hipLaunchKernelGGL((k_mutual_tiles<float, true>), dim3(nwg(c->ntiles)), dim3(256), 0, c->stream, c->ntiles,
                            c->tile_blk, c->tile_j, c->tile_mask, c->jrel_f, c->off_f, c->par_f, c->pv_f,
@@ -319,6 +320,7 @@ void launch_perm_tiles(amoeba_ctx* c)
 {
     if (c->ntiles == 0)
         return;
+    StageTimer tm(c, AMOEBA_T_PERM);
     if (c->mixed)
         hipLaunchKernelGGL((k_perm_tiles<float, true>), dim3(nwg(c->ntiles)), dim3(256), 0, c->stream, c->ntiles,
                            c->tile_blk, c->tile_j, c->tile_mask, c->jrel_f, c->off_f, c->par_f,
@@ -401,6 +403,7 @@ __global__ void k_perm_assemble(int npad, const int* __restrict__ perm, const do
 
 void launch_perm_assemble(amoeba_ctx* c, double* out_slot)
 {
+    StageTimer tm(c, AMOEBA_T_PERM);
     double3 box = make_double3(c->prm.box[0], c->prm.box[1], c->prm.box[2]);
     double b = c->prm.ewald_alpha;
     double self = 4.0 * b * b * b / (3.0 * sqrt(kPi));
