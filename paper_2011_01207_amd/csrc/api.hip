@@ -162,15 +162,6 @@ __global__ void k_gather_mpole(int npad, const int* __restrict__ perm, const dou
     }
 }
 
-__global__ void k_acc_to_vec(size_t n3, const unsigned long long* __restrict__ fx, const double* __restrict__ d,
-                             double* __restrict__ out)
-{
-    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n3)
-        return;
-    out[i] = fx ? (double)(long long)fx[i] * kFixInv : d[i];
-}
-
 static inline int nblk(size_t n, int b) { return (int)((n + b - 1) / b); }
 
 int sort_params(amoeba_ctx* c);
@@ -288,7 +279,12 @@ int amoeba_create(const amoeba_params* p, void* hip_stream, amoeba_ctx** out)
     c->mixed = p->precision == AMOEBA_MIXED;
     int rc = AMOEBA_OK;
     size_t np = c->npad, n3 = 3 * np;
-    size_t part_n = (size_t)std::max(nblk(np, 256), kRedBlocks) * 4;
+    // partials of the grid reductions: up to one per 256-thread workgroup over 3 npad threads
+    // (vector kernels) or one per PME brick, 4 values each
+    size_t nbricks = 1;
+    for (int a = 0; a < 3; ++a)
+        nbricks *= (size_t)((p->grid[a] + kBrick - 1) / kBrick);
+    size_t part_n = (std::max((size_t)nblk(3 * np, 256), nbricks) + (size_t)kRedBlocks) * 4;
     do {
         if ((rc = ctx_alloc(c, (void**)&c->perm, sizeof(int) * np)) ||
             (rc = ctx_alloc(c, (void**)&c->slot, sizeof(int) * c->n)) ||
@@ -313,17 +309,20 @@ int amoeba_create(const amoeba_params* p, void* hip_stream, amoeba_ctx** out)
             (rc = ctx_alloc(c, (void**)&c->v_e, sizeof(double) * n3)) ||
             (rc = ctx_alloc(c, (void**)&c->sc, sizeof(PcgScalars))) ||
             (rc = ctx_alloc(c, (void**)&c->red.part, sizeof(double) * part_n)) ||
-            (rc = ctx_alloc(c, (void**)&c->red.ticket, sizeof(unsigned int) * 4)) ||
             (rc = ctx_alloc(c, (void**)&c->flags, sizeof(int) * 4)) ||
-            (rc = ctx_alloc(c, (void**)&c->counter, sizeof(unsigned long long) * 2)))
+            (rc = ctx_alloc(c, (void**)&c->counter, sizeof(unsigned long long) * 2)) ||
+            (rc = ctx_alloc(c, (void**)&c->b_cnt, sizeof(int) * (np + 1))) ||
+            (rc = ctx_alloc(c, (void**)&c->b_scan, sizeof(int) * 2 * (np / 1024 + 2))))
+            break;
+        if ((rc = ctx_alloc(c, (void**)&c->eipart, sizeof(double) * n3)) ||
+            (rc = ctx_alloc(c, (void**)&c->ereal, sizeof(double) * n3)) ||
+            (rc = ctx_alloc(c, (void**)&c->rev_ptr, sizeof(int) * (np + 1))))
             break;
         if (c->mixed) {
-            if ((rc = ctx_alloc(c, (void**)&c->acc_fx, sizeof(unsigned long long) * n3)) ||
-                (rc = ctx_alloc(c, (void**)&c->pv_f, sizeof(float4) * np)))
+            if ((rc = ctx_alloc(c, (void**)&c->pv_f, sizeof(float4) * np)))
                 break;
         } else {
-            if ((rc = ctx_alloc(c, (void**)&c->acc_d, sizeof(double) * n3)) ||
-                (rc = ctx_alloc(c, (void**)&c->pv_d, sizeof(double4) * np)))
+            if ((rc = ctx_alloc(c, (void**)&c->pv_d, sizeof(double4) * np)))
                 break;
         }
         if (hipHostMalloc((void**)&c->sc_host, sizeof(PcgScalars) * 2, hipHostMallocDefault) != hipSuccess ||
@@ -482,14 +481,12 @@ int amoeba_perm_field(amoeba_ctx* c, const double* pos, const double* q, const d
         return set_error(c, AMOEBA_E_NUMERIC, "amoeba_perm_field: non-finite multipole");
     if (f & kFlagBadCsr)
         return set_error(c, AMOEBA_E_INVALID, "amoeba_perm_field: quadrupole not traceless (|tr| > 1e-10)");
-    launch_zero_acc(c);
     launch_perm_tiles(c);
     if ((rc = pme_perm_potential(c)))
         return rc;
     launch_gather(c, c->erec);
     hipMemsetAsync(c->flags, 0, sizeof(int), st);
     launch_perm_assemble(c, c->v_q);
-    launch_zero_acc(c);
     if ((rc = check_overflow(c, c->v_q)))
         return rc;
     launch_scatter(c, c->v_q, e_perm);
@@ -510,7 +507,6 @@ int amoeba_dipole_matvec(amoeba_ctx* c, const double* pos, const double* mu, dou
         return rc;
     launch_gather_vec(c, mu, c->v_mu);
     launch_set_direction(c, c->v_mu);
-    launch_zero_acc(c);
     if ((rc = matvec_slot(c, false, false)))
         return rc;
     c->matvecs += 1;
@@ -532,14 +528,10 @@ int amoeba_dipole_field_parts(amoeba_ctx* c, const double* pos, const double* mu
         return rc;
     launch_gather_vec(c, mu, c->v_mu);
     launch_set_direction(c, c->v_mu);
-    launch_zero_acc(c);
     launch_mutual_tiles(c, false);
-    size_t n3 = 3 * (size_t)c->npad;
-    hipLaunchKernelGGL(k_acc_to_vec, dim3(nblk(n3, 256)), dim3(256), 0, c->stream, n3, c->mixed ? c->acc_fx : nullptr,
-                       c->mixed ? nullptr : c->acc_d, c->v_q);
-    launch_zero_acc(c);
+    launch_real_reduce(c, c->ereal);
     if (e_real)
-        launch_scatter(c, c->v_q, e_real);
+        launch_scatter(c, c->ereal, e_real);
     if ((rc = pme_dipole_field(c, false)))
         return rc;
     launch_gather(c, c->erec);
@@ -580,7 +572,6 @@ int amoeba_polarize(amoeba_ctx* c, const double* pos, const double* e_perm, cons
             return rc;
         launch_gather_vec(c, mu_guess, c->v_mu);
     }
-    launch_zero_acc(c);
     int st = pcg_solve(c, tol_debye, max_iter, have_guess);
     if (st < 0)
         return st;

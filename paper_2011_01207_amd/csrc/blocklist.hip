@@ -24,7 +24,7 @@
 
 namespace amoeba {
 
-__device__ __forceinline__ double mimg(double d, double L) { return d - L * rint(d / L); }
+__device__ __forceinline__ double mimg(double d, double L) { return mimg_fp64(d, L, 1.0 / L); }
 
 __device__ __forceinline__ double wrap_box(double x, double L)
 {
@@ -72,6 +72,92 @@ __global__ void k_bitonic(unsigned long long* __restrict__ keys, int npow2, int 
             keys[ixj] = a;
         }
     }
+}
+
+// Bitonic stages whose partner distance j stays inside a 1024-element block, done in LDS:
+// for k = k_lo .. k_hi (doubling) and j = min(k/2, j_hi) .. 1.  Direction from the global index.
+__global__ __launch_bounds__(512) void k_bitonic_lds(unsigned long long* __restrict__ keys, int npow2, int k_lo,
+                                                     int k_hi, int j_hi)
+{
+    __shared__ unsigned long long s[1024];
+    const int bs = min(npow2, 1024), half = bs >> 1;
+    const unsigned base = blockIdx.x * bs;
+    const int t = threadIdx.x;
+    if (t < half) {
+        s[t] = keys[base + t];
+        s[t + half] = keys[base + t + half];
+    }
+    __syncthreads();
+    for (int k = k_lo; k <= k_hi; k <<= 1)
+        for (int j = min(k >> 1, j_hi); j > 0; j >>= 1) {
+            if (t < half) {
+                unsigned i = 2u * t - (t & (j - 1));
+                unsigned ixj = i + j;
+                bool up = ((base + i) & (unsigned)k) == 0;
+                unsigned long long a = s[i], b = s[ixj];
+                if ((a > b) == up) {
+                    s[i] = b;
+                    s[ixj] = a;
+                }
+            }
+            __syncthreads();
+        }
+    if (t < half) {
+        keys[base + t] = s[t];
+        keys[base + t + half] = s[t + half];
+    }
+}
+
+// Three-phase exclusive scan for long arrays: block sums (1024 per workgroup), scan of the
+// sums, then block-local scans offset by the scanned sums.
+__global__ __launch_bounds__(256) void k_scan_blocksum(int n, const int* __restrict__ in, int* __restrict__ bsum)
+{
+    __shared__ int sh[256];
+    int base = blockIdx.x * 1024, t = threadIdx.x;
+    int s = 0;
+    for (int u = 0; u < 4; ++u) {
+        int i = base + t * 4 + u;
+        s += i < n ? in[i] : 0;
+    }
+    sh[t] = s;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (t < off)
+            sh[t] += sh[t + off];
+        __syncthreads();
+    }
+    if (t == 0)
+        bsum[blockIdx.x] = sh[0];
+}
+
+__global__ __launch_bounds__(256) void k_scan_apply(int n, const int* __restrict__ in, const int* __restrict__ boff,
+                                                    int* __restrict__ out)
+{
+    __shared__ int sh[256];
+    int base = blockIdx.x * 1024, t = threadIdx.x;
+    int v[4], s = 0;
+    for (int u = 0; u < 4; ++u) {
+        int i = base + t * 4 + u;
+        v[u] = i < n ? in[i] : 0;
+        s += v[u];
+    }
+    sh[t] = s;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+        int y = t >= off ? sh[t - off] : 0;
+        __syncthreads();
+        sh[t] += y;
+        __syncthreads();
+    }
+    int run = boff[blockIdx.x] + sh[t] - s;
+    for (int u = 0; u < 4; ++u) {
+        int i = base + t * 4 + u;
+        if (i < n)
+            out[i] = run;
+        run += v[u];
+    }
+    if (blockIdx.x == gridDim.x - 1 && t == 255)
+        out[n] = run;
 }
 
 __global__ void k_perm(int n, int npad, const unsigned long long* __restrict__ keys, int* __restrict__ perm,
@@ -180,6 +266,9 @@ __global__ void k_gather_pos(int npad, const int* __restrict__ perm, const doubl
     x = wrap_box(x, box.x);
     y = wrap_box(y, box.y);
     z = wrap_box(z, box.z);
+    double4 old = pos_s[s];
+    if (old.x != x || old.y != y || old.z != z)
+        atomicOr(flags, kFlagChanged);
     pos_s[s] = make_double4(x, y, z, 0.0);
     if (ref) {
         double4 r0 = ref[s];
@@ -246,7 +335,7 @@ __global__ __launch_bounds__(64) void k_bbox(int nb, const int* __restrict__ per
 __global__ __launch_bounds__(64) void k_filter(int nb, const int* __restrict__ perm,
                                                const double4* __restrict__ pos_s,
                                                const double4* __restrict__ bc, const double4* __restrict__ bh,
-                                               double3 box, double rcb, int* __restrict__ row_count,
+                                               double3 box, double3 binv, double rcb, int* __restrict__ row_count,
                                                int* __restrict__ row_j, int* __restrict__ flags)
 {
     __shared__ double sx[kBlock], sy[kBlock], sz[kBlock];
@@ -267,9 +356,9 @@ __global__ __launch_bounds__(64) void k_filter(int nb, const int* __restrict__ p
         bool cand = false;
         if (J < nb) {
             double4 cj = bc[J], hj = bh[J];
-            double dx = fabs(mimg(ci.x - cj.x, box.x)) - hi.x - hj.x;
-            double dy = fabs(mimg(ci.y - cj.y, box.y)) - hi.y - hj.y;
-            double dz = fabs(mimg(ci.z - cj.z, box.z)) - hi.z - hj.z;
+            double dx = fabs(mimg_fp64(ci.x - cj.x, box.x, binv.x)) - hi.x - hj.x;
+            double dy = fabs(mimg_fp64(ci.y - cj.y, box.y, binv.y)) - hi.y - hj.y;
+            double dz = fabs(mimg_fp64(ci.z - cj.z, box.z, binv.z)) - hi.z - hj.z;
             dx = fmax(dx, 0.0);
             dy = fmax(dy, 0.0);
             dz = fmax(dz, 0.0);
@@ -286,9 +375,9 @@ __global__ __launch_bounds__(64) void k_filter(int nb, const int* __restrict__ p
                 for (int i = 0; i < kBlock; ++i) {
                     if (!sv[i])
                         continue;
-                    double dx = mimg(sx[i] - pj.x, box.x);
-                    double dy = mimg(sy[i] - pj.y, box.y);
-                    double dz = mimg(sz[i] - pj.z, box.z);
+                    double dx = mimg_fp64(sx[i] - pj.x, box.x, binv.x);
+                    double dy = mimg_fp64(sy[i] - pj.y, box.y, binv.y);
+                    double dz = mimg_fp64(sz[i] - pj.z, box.z, binv.z);
                     if (dx * dx + dy * dy + dz * dz < rcb2) {
                         keep = true;
                         break;
@@ -333,42 +422,91 @@ __global__ __launch_bounds__(64) void k_fill_tiles(int nb, const int* __restrict
     }
 }
 
+// Reverse index of the off-diagonal tiles: for every slot, the (tile, lane) entries where it
+// is a j-atom, sorted, so that its j-field contributions are summed in a fixed order.
+__global__ void k_rev_count(int ntiles, const int* __restrict__ tile_blk, const int* __restrict__ tile0,
+                            const int* __restrict__ tile_j, int* __restrict__ cnt)
+{
+    long g = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    int t = (int)(g >> 6), k = (int)(g & 63);
+    if (t >= ntiles || t == tile0[tile_blk[t]])
+        return;
+    int sj = tile_j[(size_t)t * kBlock + k];
+    if (sj >= 0)
+        atomicAdd(&cnt[sj], 1);
+}
+
+__global__ void k_rev_fill(int ntiles, const int* __restrict__ tile_blk, const int* __restrict__ tile0,
+                           const int* __restrict__ tile_j, const int* __restrict__ rev_ptr, int* __restrict__ cursor,
+                           int* __restrict__ rev_idx)
+{
+    long g = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    int t = (int)(g >> 6), k = (int)(g & 63);
+    if (t >= ntiles || t == tile0[tile_blk[t]])
+        return;
+    int sj = tile_j[(size_t)t * kBlock + k];
+    if (sj >= 0)
+        rev_idx[rev_ptr[sj] + atomicAdd(&cursor[sj], 1)] = t * kBlock + k;
+}
+
+__global__ void k_rev_sort(int npad, const int* __restrict__ rev_ptr, int* __restrict__ rev_idx)
+{
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= npad)
+        return;
+    int lo = rev_ptr[s], hi = rev_ptr[s + 1];
+    for (int i = lo + 1; i < hi; ++i) {
+        int v = rev_idx[i];
+        int j = i - 1;
+        while (j >= lo && rev_idx[j] > v) {
+            rev_idx[j + 1] = rev_idx[j];
+            --j;
+        }
+        rev_idx[j + 1] = v;
+    }
+}
+
 // Per configuration: in-cutoff bitmasks (FP64 distances, strict r < rc) and j positions
 // relative to the i-block origin.  The diagonal tile keeps only k > i.
 __global__ __launch_bounds__(256) void k_tile_refresh(int ntiles, const int* __restrict__ tile_blk,
                                                       const int* __restrict__ tile_j,
                                                       const int* __restrict__ perm,
                                                       const double4* __restrict__ pos_s,
-                                                      const double4* __restrict__ org, double3 box,
+                                                      const double4* __restrict__ org, double3 box, double3 binv,
                                                       double rc2, unsigned long long* __restrict__ mask,
                                                       double4* __restrict__ jrel_d, float4* __restrict__ jrel_f,
                                                       unsigned long long* __restrict__ pair_count)
 {
+    __shared__ double4 s_j[4][kBlock];
     int gt = blockIdx.x * blockDim.x + threadIdx.x;
-    int t = gt >> 6, lane = threadIdx.x & 63;
-    if (t >= ntiles)
-        return;
-    int I = tile_blk[t];
+    int t = gt >> 6, lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    bool act = t < ntiles;
+    int I = act ? tile_blk[t] : 0;
     int si = I * kBlock + lane;
-    bool ivalid = perm[si] >= 0;
+    bool ivalid = act && perm[si] >= 0;
     double4 pi = pos_s[si];
-    int sj = tile_j[(size_t)t * kBlock + lane];
+    int sj = act ? tile_j[(size_t)t * kBlock + lane] : -1;
     double4 pj = sj >= 0 ? pos_s[sj] : pi;
+    bool jvalid = sj >= 0 && perm[sj] >= 0;
+    s_j[w][lane] = make_double4(pj.x, pj.y, pj.z, jvalid ? 1.0 : 0.0);
+    __syncthreads();
+    if (!act)
+        return;
     double4 o = org[I];
-    double jx = mimg(pj.x - o.x, box.x), jy = mimg(pj.y - o.y, box.y), jz = mimg(pj.z - o.z, box.z);
+    double jx = mimg_fp64(pj.x - o.x, box.x, binv.x), jy = mimg_fp64(pj.y - o.y, box.y, binv.y),
+           jz = mimg_fp64(pj.z - o.z, box.z, binv.z);
     jrel_d[(size_t)t * kBlock + lane] = make_double4(jx, jy, jz, 0.0);
     jrel_f[(size_t)t * kBlock + lane] = make_float4((float)jx, (float)jy, (float)jz, 0.0f);
-    bool jvalid = sj >= 0 && perm[sj] >= 0;
     bool diag = tile_j[(size_t)t * kBlock] == I * kBlock;
     unsigned long long m = 0;
-    for (int k = 0; k < kBlock; ++k) {
-        double xk = __shfl(pj.x, k), yk = __shfl(pj.y, k), zk = __shfl(pj.z, k);
-        int vk = __shfl((int)jvalid, k);
-        if (!vk || !ivalid || (diag && k <= lane))
-            continue;
-        double dx = mimg(pi.x - xk, box.x), dy = mimg(pi.y - yk, box.y), dz = mimg(pi.z - zk, box.z);
-        if (dx * dx + dy * dy + dz * dz < rc2)
-            m |= 1ull << k;
+    if (ivalid) {
+        for (int k = diag ? lane + 1 : 0; k < kBlock; ++k) {
+            double4 q = s_j[w][k];
+            double dx = mimg_fp64(pi.x - q.x, box.x, binv.x), dy = mimg_fp64(pi.y - q.y, box.y, binv.y),
+                   dz = mimg_fp64(pi.z - q.z, box.z, binv.z);
+            if (q.w != 0.0 && dx * dx + dy * dy + dz * dz < rc2)
+                m |= 1ull << k;
+        }
     }
     mask[(size_t)t * kBlock + lane] = m;
     unsigned long long cnt = (unsigned long long)__popcll(m);
@@ -380,24 +518,41 @@ __global__ __launch_bounds__(256) void k_tile_refresh(int ntiles, const int* __r
 
 static inline int nblk(long n, int b) { return (int)((n + b - 1) / b); }
 
+int device_scan(amoeba_ctx* c, int n, const int* in, int* out)
+{
+    hipStream_t st = c->stream;
+    if (n <= 65536) {
+        hipLaunchKernelGGL(k_scan_excl, dim3(1), dim3(1024), 0, st, n, in, out);
+        return AMOEBA_OK;
+    }
+    const int cap = c->npad / 1024 + 2;
+    int nbk = nblk(n, 1024);
+    if (nbk + 1 > cap)
+        return set_error(c, AMOEBA_E_INVALID, "device_scan: scratch too small");
+    int* bsum = c->b_scan;
+    int* boff = c->b_scan + cap;
+    hipLaunchKernelGGL(k_scan_blocksum, dim3(nbk), dim3(256), 0, st, n, in, bsum);
+    hipLaunchKernelGGL(k_scan_excl, dim3(1), dim3(1024), 0, st, nbk, bsum, boff);
+    hipLaunchKernelGGL(k_scan_apply, dim3(nbk), dim3(256), 0, st, n, in, boff, out);
+    return AMOEBA_OK;
+}
+
 int sort_params(amoeba_ctx* c)
 {
     hipStream_t st = c->stream;
     hipLaunchKernelGGL(k_params, dim3(nblk(c->npad, 256)), dim3(256), 0, st, c->npad, c->perm, c->alpha_in,
                        c->thole_in, c->par_d, c->par_f);
     // scaled-pair CSR in slot order
-    int* cnt = nullptr;
-    if (hip_check(c, hipMalloc(&cnt, sizeof(int) * (c->npad + 1)), "hipMalloc"))
-        return AMOEBA_E_NOMEM;
+    int* cnt = c->b_cnt;
     hipLaunchKernelGGL(k_csr_counts, dim3(nblk(c->npad, 256)), dim3(256), 0, st, c->npad, c->perm, c->sc_ptr_in,
                        cnt);
-    hipLaunchKernelGGL(k_scan_excl, dim3(1), dim3(1024), 0, st, c->npad, cnt, c->sc_ptr);
+    int rcs = device_scan(c, c->npad, cnt, c->sc_ptr);
+    if (rcs)
+        return rcs;
     if (c->n_scaled > 0)
         hipLaunchKernelGGL(k_csr_fill, dim3(nblk(c->npad, 256)), dim3(256), 0, st, c->npad, c->perm, c->slot,
                            c->sc_ptr_in, c->sc_j_in, c->sc_s_in, c->sc_ptr, c->sc_j, c->sc_s);
-    int rc = hip_check(c, hipStreamSynchronize(st), "sort_params");
-    hipFree(cnt);
-    return rc;
+    return hip_check(c, hipStreamSynchronize(st), "sort_params");
 }
 
 void pme_bin_atoms(amoeba_ctx* c);
@@ -410,9 +565,10 @@ static int refresh_tiles(amoeba_ctx* c)
     hipLaunchKernelGGL(k_block_frame, dim3(nblk(c->npad, 256)), dim3(256), 0, st, c->npad, c->perm, c->pos_s, box,
                        c->blk_org, c->off_d, c->off_f);
     hipMemsetAsync(c->counter, 0, sizeof(unsigned long long), st);
+    double3 binv = make_double3(1.0 / box.x, 1.0 / box.y, 1.0 / box.z);
     hipLaunchKernelGGL(k_tile_refresh, dim3(nblk((long)c->ntiles * kBlock, 256)), dim3(256), 0, st, c->ntiles,
-                       c->tile_blk, c->tile_j, c->perm, c->pos_s, c->blk_org, box, c->prm.cutoff * c->prm.cutoff,
-                       c->tile_mask, c->jrel_d, c->jrel_f, c->counter);
+                       c->tile_blk, c->tile_j, c->perm, c->pos_s, c->blk_org, box, binv,
+                       c->prm.cutoff * c->prm.cutoff, c->tile_mask, c->jrel_d, c->jrel_f, c->counter);
     pme_bin_atoms(c);
     return AMOEBA_OK;
 }
@@ -431,28 +587,34 @@ int build_blocklist(amoeba_ctx* c, const double* pos)
     while (npow2 < n)
         npow2 <<= 1;
 
-    unsigned long long* keys = nullptr;
-    double4 *bc = nullptr, *bh = nullptr;
-    int *row_count = nullptr, *row_j = nullptr, *tpb = nullptr, *t0 = nullptr;
     int rc = AMOEBA_OK;
-    auto fail = [&](int code) {
-        hipFree(keys); hipFree(bc); hipFree(bh); hipFree(row_count); hipFree(row_j); hipFree(tpb);
-        return code;
-    };
-    if (hipMalloc(&keys, sizeof(unsigned long long) * npow2) != hipSuccess ||
-        hipMalloc(&bc, sizeof(double4) * nb) != hipSuccess || hipMalloc(&bh, sizeof(double4) * nb) != hipSuccess ||
-        hipMalloc(&row_count, sizeof(int) * nb) != hipSuccess ||
-        hipMalloc(&row_j, sizeof(int) * (size_t)nb * kMaxFiltered) != hipSuccess ||
-        hipMalloc(&tpb, sizeof(int) * (nb + 1)) != hipSuccess) {
-        set_error(c, AMOEBA_E_NOMEM, "build_blocklist: temporary allocation failed");
-        return fail(AMOEBA_E_NOMEM);
+    if (!c->b_keys) {
+        if ((rc = ctx_alloc(c, (void**)&c->b_keys, sizeof(unsigned long long) * npow2)) ||
+            (rc = ctx_alloc(c, (void**)&c->b_bc, sizeof(double4) * nb)) ||
+            (rc = ctx_alloc(c, (void**)&c->b_bh, sizeof(double4) * nb)) ||
+            (rc = ctx_alloc(c, (void**)&c->b_rowc, sizeof(int) * nb)) ||
+            (rc = ctx_alloc(c, (void**)&c->b_rowj, sizeof(int) * (size_t)nb * kMaxFiltered)) ||
+            (rc = ctx_alloc(c, (void**)&c->b_tpb, sizeof(int) * (nb + 1))))
+            return rc;
+        c->b_npow2 = npow2;
     }
-    t0 = c->blk_tile0;
-
+    unsigned long long* keys = c->b_keys;
+    double4 *bc = c->b_bc, *bh = c->b_bh;
+    int *row_count = c->b_rowc, *row_j = c->b_rowj, *tpb = c->b_tpb, *t0 = c->blk_tile0;
+    auto fail = [&](int code) { return code; };
     hipLaunchKernelGGL(k_sort_keys, dim3(nblk(npow2, 256)), dim3(256), 0, st, n, npow2, pos, box, ny, nz, keys);
-    for (int k = 2; k <= npow2; k <<= 1)
-        for (int j = k >> 1; j > 0; j >>= 1)
-            hipLaunchKernelGGL(k_bitonic, dim3(nblk(npow2, 256)), dim3(256), 0, st, keys, npow2, j, k);
+    {
+        // bitonic network: stages with partner distance < 1024 run in LDS, longer ones in global memory
+        const int bs = npow2 < 1024 ? npow2 : 1024;
+        const int nwg_l = npow2 / bs;
+        if (npow2 >= 2)
+            hipLaunchKernelGGL(k_bitonic_lds, dim3(nwg_l), dim3(512), 0, st, keys, npow2, 2, bs, 512);
+        for (int k = 2 * bs; k <= npow2; k <<= 1) {
+            for (int j = k >> 1; j >= bs; j >>= 1)
+                hipLaunchKernelGGL(k_bitonic, dim3(nblk(npow2, 256)), dim3(256), 0, st, keys, npow2, j, k);
+            hipLaunchKernelGGL(k_bitonic_lds, dim3(nwg_l), dim3(512), 0, st, keys, npow2, k, k, 512);
+        }
+    }
     hipLaunchKernelGGL(k_perm, dim3(nblk(npad, 256)), dim3(256), 0, st, n, npad, keys, c->perm, c->slot);
     if (c->atoms_set && (rc = sort_params(c)) != AMOEBA_OK)
         return fail(rc);
@@ -462,10 +624,12 @@ int build_blocklist(amoeba_ctx* c, const double* pos)
                        (const double4*)nullptr, 0.0, c->flags);
     hipMemcpyAsync(c->pos_ref, c->pos_s, sizeof(double4) * npad, hipMemcpyDeviceToDevice, st);
     hipLaunchKernelGGL(k_bbox, dim3(nb), dim3(64), 0, st, nb, c->perm, c->pos_s, box, bc, bh);
-    hipLaunchKernelGGL(k_filter, dim3(nb), dim3(64), 0, st, nb, c->perm, c->pos_s, bc, bh, box,
+    double3 binv = make_double3(1.0 / box.x, 1.0 / box.y, 1.0 / box.z);
+    hipLaunchKernelGGL(k_filter, dim3(nb), dim3(64), 0, st, nb, c->perm, c->pos_s, bc, bh, box, binv,
                        c->prm.cutoff + c->prm.buffer, row_count, row_j, c->flags);
     hipLaunchKernelGGL(k_tiles_per_block, dim3(nblk(nb, 256)), dim3(256), 0, st, nb, row_count, tpb);
-    hipLaunchKernelGGL(k_scan_excl, dim3(1), dim3(1024), 0, st, nb, tpb, t0);
+    if ((rc = device_scan(c, nb, tpb, t0)))
+        return rc;
     int total = 0;
     hipMemcpyAsync(&total, t0 + nb, sizeof(int), hipMemcpyDeviceToHost, st);
     hipMemcpyAsync(c->flags_host, c->flags, sizeof(int), hipMemcpyDeviceToHost, st);
@@ -481,27 +645,41 @@ int build_blocklist(amoeba_ctx* c, const double* pos)
         return fail(AMOEBA_E_INVALID);
     }
     if (total > c->tile_cap) {
-        // grow the tile arrays (not counted against earlier allocations: freed on destroy)
+        // grow the tile arrays (earlier, smaller ones stay allocated until destroy)
         size_t tb = (size_t)total * kBlock;
+        size_t rs = c->mixed ? sizeof(float) : sizeof(double);
         if ((rc = ctx_alloc(c, (void**)&c->tile_blk, sizeof(int) * total)) ||
             (rc = ctx_alloc(c, (void**)&c->tile_j, sizeof(int) * tb)) ||
             (rc = ctx_alloc(c, (void**)&c->tile_mask, sizeof(unsigned long long) * tb)) ||
             (rc = ctx_alloc(c, (void**)&c->jrel_f, sizeof(float4) * tb)) ||
-            (!c->mixed && (rc = ctx_alloc(c, (void**)&c->jrel_d, sizeof(double4) * tb))))
-            return fail(rc);
-        if (c->mixed && !c->jrel_d && (rc = ctx_alloc(c, (void**)&c->jrel_d, sizeof(double4) * tb)))
+            (rc = ctx_alloc(c, (void**)&c->jrel_d, sizeof(double4) * tb)) ||
+            (rc = ctx_alloc(c, &c->jbuf, rs * 3 * tb)) ||
+            (rc = ctx_alloc(c, (void**)&c->rev_idx, sizeof(int) * tb)))
             return fail(rc);
         c->tile_cap = total;
+        c->rev_cap = (int64_t)tb;
     }
     c->ntiles = total;
     hipLaunchKernelGGL(k_fill_tiles, dim3(nb), dim3(64), 0, st, nb, t0, row_count, row_j, c->tile_blk, c->tile_j);
+    {
+        const long nthr = (long)total * kBlock;
+        hipMemsetAsync(c->b_cnt, 0, sizeof(int) * (npad + 1), st);
+        hipLaunchKernelGGL(k_rev_count, dim3(nblk(nthr, 256)), dim3(256), 0, st, total, c->tile_blk, t0, c->tile_j,
+                           c->b_cnt);
+        if ((rc = device_scan(c, npad, c->b_cnt, c->rev_ptr)))
+            return rc;
+        hipMemsetAsync(c->b_cnt, 0, sizeof(int) * (npad + 1), st);
+        hipLaunchKernelGGL(k_rev_fill, dim3(nblk(nthr, 256)), dim3(256), 0, st, total, c->tile_blk, t0, c->tile_j,
+                           c->rev_ptr, c->b_cnt, c->rev_idx);
+        hipLaunchKernelGGL(k_rev_sort, dim3(nblk(npad, 256)), dim3(256), 0, st, npad, c->rev_ptr, c->rev_idx);
+    }
     refresh_tiles(c);
     hipMemcpyAsync(c->flags_host + 2, c->counter, sizeof(unsigned long long), hipMemcpyDeviceToHost, st);
     if ((rc = hip_check(c, hipStreamSynchronize(st), "build_blocklist tiles")))
         return fail(rc);
     c->n_pairs = (int64_t) * (unsigned long long*)(c->flags_host + 2);
     c->list_built = true;
-    fail(AMOEBA_OK);
+    c->cfg_valid = true;
     return AMOEBA_OK;
 }
 
@@ -513,18 +691,28 @@ int prepare_config(amoeba_ctx* c, const double* pos)
     hipMemsetAsync(c->flags, 0, sizeof(int), st);
     hipLaunchKernelGGL(k_gather_pos, dim3(nblk(c->npad, 256)), dim3(256), 0, st, c->npad, c->perm, pos, box,
                        c->pos_s, (const double4*)c->pos_ref, hb * hb, c->flags);
-    refresh_tiles(c);
     hipMemcpyAsync(c->flags_host, c->flags, sizeof(int), hipMemcpyDeviceToHost, st);
-    hipMemcpyAsync(c->flags_host + 2, c->counter, sizeof(unsigned long long), hipMemcpyDeviceToHost, st);
     int rc = hip_check(c, hipStreamSynchronize(st), "prepare_config");
     if (rc)
         return rc;
-    if (*c->flags_host & kFlagNonFinite)
+    int f = c->flags_host[0];
+    if (f & kFlagNonFinite) {
+        c->cfg_valid = false;
         return set_error(c, AMOEBA_E_NUMERIC, "non-finite position");
-    if (*c->flags_host & kFlagStale)
+    }
+    if (f & kFlagStale) {
+        c->cfg_valid = false;
         return set_error(c, AMOEBA_E_LIST, "block list is stale: an atom moved more than buffer/2 since "
                                            "amoeba_build_blocklist");
+    }
+    if (c->cfg_valid && !(f & kFlagChanged))
+        return AMOEBA_OK;  // same configuration as the last refresh: masks, frames and bins are current
+    refresh_tiles(c);
+    hipMemcpyAsync(c->flags_host + 2, c->counter, sizeof(unsigned long long), hipMemcpyDeviceToHost, st);
+    if ((rc = hip_check(c, hipStreamSynchronize(st), "prepare_config refresh")))
+        return rc;
     c->n_pairs = (int64_t) * (unsigned long long*)(c->flags_host + 2);
+    c->cfg_valid = true;
     return AMOEBA_OK;
 }
 

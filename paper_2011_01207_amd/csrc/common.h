@@ -33,11 +33,30 @@ enum : int {
     kFlagBadCsr = 32,
     kFlagFilterOverflow = 64,
     kFlagBreakdown = 128,
+    kFlagChanged = 256,
 };
+
+// FP32 value -> 64-bit fixed point with 40 fraction bits, rounded to nearest even (|v| < 2^23).
+// a = |rint(v * 2^40)| has at most 24 significant bits, so hi = floor(a / 2^32) and
+// lo = a - hi * 2^32 in [0, 2^32) are exact floats; (hi, lo) are the two 32-bit halves of a,
+// and the sign is applied to the 64-bit integer.
+__device__ __forceinline__ unsigned long long fix40(float v)
+{
+    const float s = rintf(v * 1099511627776.0f);
+    const float a = fabsf(s);
+    const float hi = floorf(a * 2.3283064365386963e-10f);
+    const float lo = fmaf(hi, -4294967296.0f, a);
+    const unsigned long long u = ((unsigned long long)(unsigned)hi << 32) | (unsigned long long)(unsigned)lo;
+    return s < 0.0f ? 0ull - u : u;
+}
+
+// Minimum image used by every FP64 distance decision of the library (list build, in-cutoff
+// masks, scaled-pair correction), so that all of them agree bit for bit.
+__device__ __forceinline__ double mimg_fp64(double d, double L, double Linv) { return d - L * rint(d * Linv); }
 
 // PCG scalars kept on the device (one struct, FP64).
 struct PcgScalars {
-    double rz;        // r.z of the current iterate
+    double rzb[2];    // r.z at the start of iteration it, kept in rzb[it & 1]
     double pq;        // p.(A p)
     double gamma;     // step length
     double rz_new;
@@ -52,10 +71,9 @@ struct PcgScalars {
     int32_t pad;
 };
 
-// Deterministic two-level reduction scratch: per-workgroup partials + a completion ticket.
+// Reduction partials (see reduce.h).
 struct RedScratch {
-    double* part;       // [kRedBlocks * 4]
-    unsigned int* ticket;
+    double* part;
 };
 
 struct DeviceBuf {
@@ -74,6 +92,7 @@ struct amoeba_ctx {
     bool mixed = false;
     bool atoms_set = false;
     bool list_built = false;
+    bool cfg_valid = false;        // masks / frames / bins match pos_s
     int64_t n_scaled = 0;
     int ntiles = 0, tile_cap = 0;
     int64_t n_pairs = 0;
@@ -130,9 +149,13 @@ struct amoeba_ctx {
     void* fft_work = nullptr;
     size_t fft_work_bytes = 0;
 
-    // field accumulators and vectors (slot order, FP64 N x 3 unless noted)
-    unsigned long long* acc_fx = nullptr;  // [npad*3] fixed-point real-space field (mixed)
-    double* acc_d = nullptr;               // [npad*3] FP64 real-space field (FP64 mode)
+    // real-space field pieces and vectors (slot order, FP64 N x 3 unless noted)
+    double* eipart = nullptr;              // [npad*3] field at i summed over its own block's tiles
+    void* jbuf = nullptr;                  // [tile_cap*3*64] (R) j-field of every off-diagonal tile
+    int32_t* rev_ptr = nullptr;            // [npad+1] reverse index: jbuf slots where an atom is j
+    int32_t* rev_idx = nullptr;            // [rev_cap] entries tile*64 + lane
+    int64_t rev_cap = 0;
+    double* ereal = nullptr;               // [npad*3] reduced real-space field
     double* erec = nullptr;                // [npad*3] reciprocal field scratch
     double* v_mu = nullptr;
     double* v_r = nullptr;
@@ -152,6 +175,17 @@ struct amoeba_ctx {
     int* flags_host = nullptr;             // pinned
     unsigned long long* counter = nullptr; // device counters (pairs)
     hipEvent_t ev[2] = {nullptr, nullptr};
+
+    // list-build scratch, kept between builds
+    unsigned long long* b_keys = nullptr;  // [npow2]
+    int b_npow2 = 0;
+    double4* b_bc = nullptr;               // [nb] block box centres
+    double4* b_bh = nullptr;               // [nb] block box half-extents
+    int* b_rowc = nullptr;                 // [nb] filtered j count per block
+    int* b_rowj = nullptr;                 // [nb * kMaxFiltered]
+    int* b_tpb = nullptr;                  // [nb + 1] tiles per block
+    int* b_cnt = nullptr;                  // [npad + 1] per-slot counts
+    int* b_scan = nullptr;                 // [npad / 1024 + 2] scan block sums / offsets
 
     // stage timing (diagnostic)
     bool timing = false;
@@ -176,13 +210,14 @@ struct StageTimer {
 };
 
 // blocklist.hip
+int device_scan(amoeba_ctx* c, int n, const int* in, int* out);  // exclusive, out[n] = total
 int build_blocklist(amoeba_ctx* c, const double* pos);
 int prepare_config(amoeba_ctx* c, const double* pos);
 
 // realspace.hip
 void launch_mutual_tiles(amoeba_ctx* c, bool use_done);
+void launch_real_reduce(amoeba_ctx* c, double* ereal);
 void launch_perm_tiles(amoeba_ctx* c);
-void launch_zero_acc(amoeba_ctx* c);
 void launch_perm_assemble(amoeba_ctx* c, double* out_slot);
 
 // pme.hip

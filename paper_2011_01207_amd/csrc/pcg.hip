@@ -61,35 +61,54 @@ __global__ void k_set_dir(int npad, const double* __restrict__ src, double* __re
     pv[s] = Cast4<R4T>::make(x, y, z);
 }
 
-// r = e - q (q may be NULL: zero guess), z = alpha r, p = z; rz = r.z, rms(z) -> done?
+// The vector kernels below use a fixed grid of kRedBlocks workgroups striding over the
+// 3 npad components (component i belongs to slot i / 3); pv, the pair kernels' copy of p, is
+// written component-wise.  Scalars are reduced per workgroup into partials; the next kernel
+// sums the partials (see reduce.h).  Iteration `it` keeps r.z in sc->rzb[it & 1].
+template <typename R4T> struct Comp;
+template <> struct Comp<float4> {
+    __device__ static void set(float4* v, size_t i, double x) { reinterpret_cast<float*>(v)[(i / 3) * 4 + i % 3] = (float)x; }
+};
+template <> struct Comp<double4> {
+    __device__ static void set(double4* v, size_t i, double x) { reinterpret_cast<double*>(v)[(i / 3) * 4 + i % 3] = x; }
+};
+
+// r = e - q (q may be NULL: zero guess), z = alpha r, p = z; partials of r.z and z.z
 template <typename R4T>
-__global__ __launch_bounds__(256) void k_init_residual(int npad, int n, const double4* __restrict__ par,
+__global__ __launch_bounds__(256) void k_init_residual(int npad, const double4* __restrict__ par,
                                                        const double* __restrict__ e, const double* __restrict__ q,
                                                        double* __restrict__ r, double* __restrict__ z,
                                                        double* __restrict__ p, R4T* __restrict__ pv,
-                                                       PcgScalars* __restrict__ sc, double* part,
-                                                       unsigned int* ticket)
+                                                       double* __restrict__ part)
 {
-    int s = blockIdx.x * blockDim.x + threadIdx.x;
-    double rz = 0.0, zz = 0.0;
-    if (s < npad) {
-        double al = par[s].x;
-        double zv[3];
-        for (int c = 0; c < 3; ++c) {
-            size_t i = 3 * (size_t)s + c;
-            double rv = e[i] - (q ? q[i] : 0.0);
-            zv[c] = al * rv;
-            r[i] = rv;
-            z[i] = zv[c];
-            p[i] = zv[c];
-            rz += rv * zv[c];
-            zz += zv[c] * zv[c];
-        }
-        pv[s] = Cast4<R4T>::make(zv[0], zv[1], zv[2]);
+    double acc[2] = {0.0, 0.0};
+    const size_t n3 = 3 * (size_t)npad;
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n3; i += (size_t)gridDim.x * 256) {
+        double al = par[i / 3].x;
+        double rv = e[i] - (q ? q[i] : 0.0);
+        double zv = al * rv;
+        r[i] = rv;
+        z[i] = zv;
+        p[i] = zv;
+        Comp<R4T>::set(pv, i, zv);
+        acc[0] += rv * zv;
+        acc[1] += zv * zv;
     }
-    double v[2] = {rz, zz};
-    grid_reduce<2>(v, part, ticket, [sc, n](const double* tot) {
-        sc->rz = tot[0];
+    block_sum<2>(acc);
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = acc[0];
+        part[2 * blockIdx.x + 1] = acc[1];
+    }
+}
+
+// initial scalars of iteration `it`: r.z, rms of z, converged?
+__global__ __launch_bounds__(256) void k_init_finalize(int nparts, const double* __restrict__ part, int n, int it,
+                                                       PcgScalars* __restrict__ sc)
+{
+    double tot[2];
+    sum_partials<2>(part, nparts, tot);
+    if (threadIdx.x == 0) {
+        sc->rzb[it & 1] = tot[0];
         sc->zz = tot[1];
         sc->rms = kDebye * sqrt(tot[1] / n);
         bool conv = sc->rms < sc->tol;
@@ -99,82 +118,112 @@ __global__ __launch_bounds__(256) void k_init_residual(int npad, int n, const do
             sc->done = 1;
             sc->status = 2;
         }
-    });
+    }
 }
 
-// mu += gamma p, r -= gamma q, z = alpha r; rz_new = r.z, rms(z); convergence; beta
-__global__ __launch_bounds__(256) void k_update(int npad, int n, const double4* __restrict__ par,
+// gamma = r.z / p.Ap (p.Ap from the gather's per-brick partials); mu += gamma p, r -= gamma Ap,
+// z = alpha r; partials of the new r.z and z.z
+__global__ __launch_bounds__(256) void k_update(int npad, int it, const double4* __restrict__ par,
                                                 const double* __restrict__ p, const double* __restrict__ q,
                                                 double* __restrict__ mu, double* __restrict__ r,
-                                                double* __restrict__ z, PcgScalars* __restrict__ sc, double* part,
-                                                unsigned int* ticket)
+                                                double* __restrict__ z, PcgScalars* __restrict__ sc,
+                                                const double* __restrict__ part_pq, int n_pq,
+                                                double* __restrict__ part)
 {
     if (sc->done)
         return;
-    const double g = sc->gamma;
-    int s = blockIdx.x * blockDim.x + threadIdx.x;
-    double rz = 0.0, zz = 0.0;
-    if (s < npad) {
-        double al = par[s].x;
-        for (int c = 0; c < 3; ++c) {
-            size_t i = 3 * (size_t)s + c;
-            mu[i] += g * p[i];
-            double rv = r[i] - g * q[i];
-            double zv = al * rv;
-            r[i] = rv;
-            z[i] = zv;
-            rz += rv * zv;
-            zz += zv * zv;
-        }
-    }
-    double v[2] = {rz, zz};
-    grid_reduce<2>(v, part, ticket, [sc, n](const double* tot) {
-        sc->rz_new = tot[0];
-        sc->zz = tot[1];
-        sc->rms = kDebye * sqrt(tot[1] / n);
-        sc->iters += 1;
-        sc->beta = tot[0] / sc->rz;
-        sc->rz = tot[0];
-        if (sc->rms < sc->tol) {
-            sc->done = 1;
-            sc->status = 1;
-        } else if (!isfinite(tot[0])) {
+    double pq[1];
+    sum_partials<1>(part_pq, n_pq, pq);
+    if (!(pq[0] > 0.0) || !isfinite(pq[0])) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            sc->pq = pq[0];
             sc->done = 1;
             sc->status = 2;
         }
-    });
+        return;
+    }
+    const double g = sc->rzb[it & 1] / pq[0];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        sc->pq = pq[0];
+        sc->gamma = g;
+    }
+    double acc[2] = {0.0, 0.0};
+    const size_t n3 = 3 * (size_t)npad;
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n3; i += (size_t)gridDim.x * 256) {
+        double al = par[i / 3].x;
+        mu[i] += g * p[i];
+        double rv = r[i] - g * q[i];
+        double zv = al * rv;
+        r[i] = rv;
+        z[i] = zv;
+        acc[0] += rv * zv;
+        acc[1] += zv * zv;
+    }
+    block_sum<2>(acc);
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = acc[0];
+        part[2 * blockIdx.x + 1] = acc[1];
+    }
 }
 
-// p = z + beta p
+// convergence test on rms(z); unless converged: beta = r.z(new) / r.z(old), p = z + beta p
 template <typename R4T>
-__global__ void k_direction(int npad, const double* __restrict__ z, double* __restrict__ p, R4T* __restrict__ pv,
-                            const PcgScalars* __restrict__ sc)
+__global__ __launch_bounds__(256) void k_direction(int npad, int n, int it, const double* __restrict__ z,
+                                                   double* __restrict__ p, R4T* __restrict__ pv,
+                                                   PcgScalars* __restrict__ sc, const double* __restrict__ part)
 {
     if (sc->done)
         return;
-    int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= npad)
-        return;
-    const double b = sc->beta;
-    double v[3];
-    for (int c = 0; c < 3; ++c) {
-        size_t i = 3 * (size_t)s + c;
-        v[c] = z[i] + b * p[i];
-        p[i] = v[c];
+    double tot[2];
+    sum_partials<2>(part, gridDim.x, tot);
+    const double rms = kDebye * sqrt(tot[1] / n);
+    const bool conv = rms < sc->tol;
+    const bool bad = !isfinite(tot[0]);
+    const double beta = tot[0] / sc->rzb[it & 1];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        sc->rms = rms;
+        sc->zz = tot[1];
+        sc->iters = it + 1;
+        if (conv) {
+            sc->done = 1;
+            sc->status = 1;
+        } else if (bad) {
+            sc->done = 1;
+            sc->status = 2;
+        } else {
+            sc->rzb[(it + 1) & 1] = tot[0];
+            sc->beta = beta;
+        }
     }
-    pv[s] = Cast4<R4T>::make(v[0], v[1], v[2]);
+    if (conv || bad)
+        return;
+    const size_t n3 = 3 * (size_t)npad;
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n3; i += (size_t)gridDim.x * 256) {
+        double v = z[i] + beta * p[i];
+        p[i] = v;
+        Comp<R4T>::set(pv, i, v);
+    }
 }
 
 __global__ __launch_bounds__(256) void k_epol(int npad, const double* __restrict__ mu, const double* __restrict__ e,
-                                              PcgScalars* __restrict__ sc, double* part, unsigned int* ticket)
+                                              double* __restrict__ part)
 {
-    int s = blockIdx.x * blockDim.x + threadIdx.x;
-    double acc = 0.0;
-    if (s < npad)
-        for (int c = 0; c < 3; ++c)
-            acc += mu[3 * (size_t)s + c] * e[3 * (size_t)s + c];
-    double v[1] = {acc};
-    grid_reduce<1>(v, part, ticket, [sc](const double* tot) { sc->epol_acc = tot[0]; });
+    double acc[1] = {0.0};
+    const size_t n3 = 3 * (size_t)npad;
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n3; i += (size_t)gridDim.x * 256)
+        acc[0] += mu[i] * e[i];
+    block_sum<1>(acc);
+    if (threadIdx.x == 0)
+        part[blockIdx.x] = acc[0];
+}
+
+__global__ __launch_bounds__(256) void k_epol_finalize(int nparts, const double* __restrict__ part,
+                                                       PcgScalars* __restrict__ sc)
+{
+    double tot[1];
+    sum_partials<1>(part, nparts, tot);
+    if (threadIdx.x == 0)
+        sc->epol_acc = tot[0];
 }
 
 static inline int nblk(size_t n, int b) { return (int)((n + b - 1) / b); }
@@ -201,8 +250,11 @@ void launch_set_direction(amoeba_ctx* c, const double* src)
                            c->v_p, c->pv_d);
 }
 
-// q = A p for the current direction p (pv already set); acc must be clear on entry and is clear
-// on exit.
+// Partial buffers: the gather's per-brick p.Ap partials first, then the vector kernels' [G][2].
+static double* part_pq(amoeba_ctx* c) { return c->red.part; }
+static double* part_vec(amoeba_ctx* c) { return c->red.part + ((size_t)c->nbricks + 1) / 2 * 2; }
+
+// q = A p for the current direction p (pv already set).
 int matvec_slot(amoeba_ctx* c, bool use_done, bool dot)
 {
     launch_mutual_tiles(c, use_done);
@@ -213,43 +265,45 @@ int matvec_slot(amoeba_ctx* c, bool use_done, bool dot)
     return AMOEBA_OK;
 }
 
-static void launch_init_residual(amoeba_ctx* c, const double* q)
+// r = e - q, z = alpha r, p = z and the scalars of iteration `it`
+static void launch_init_residual(amoeba_ctx* c, const double* q, int it)
 {
     StageTimer tm(c, AMOEBA_T_PCG);
     if (c->mixed)
-        hipLaunchKernelGGL(k_init_residual<float4>, dim3(nblk(c->npad, 256)), dim3(256), 0, c->stream, c->npad, c->n,
-                           c->par_d, c->v_e, q, c->v_r, c->v_z, c->v_p, c->pv_f, c->sc, c->red.part, c->red.ticket);
+        hipLaunchKernelGGL(k_init_residual<float4>, dim3(kRedBlocks), dim3(256), 0, c->stream, c->npad, c->par_d,
+                           c->v_e, q, c->v_r, c->v_z, c->v_p, c->pv_f, part_vec(c));
     else
-        hipLaunchKernelGGL(k_init_residual<double4>, dim3(nblk(c->npad, 256)), dim3(256), 0, c->stream, c->npad,
-                           c->n, c->par_d, c->v_e, q, c->v_r, c->v_z, c->v_p, c->pv_d, c->sc, c->red.part,
-                           c->red.ticket);
+        hipLaunchKernelGGL(k_init_residual<double4>, dim3(kRedBlocks), dim3(256), 0, c->stream, c->npad, c->par_d,
+                           c->v_e, q, c->v_r, c->v_z, c->v_p, c->pv_d, part_vec(c));
+    hipLaunchKernelGGL(k_init_finalize, dim3(1), dim3(256), 0, c->stream, kRedBlocks, part_vec(c), c->n, it, c->sc);
 }
 
-static int enqueue_iteration(amoeba_ctx* c)
+static int enqueue_iteration(amoeba_ctx* c, int it)
 {
     int rc = matvec_slot(c, true, true);
     if (rc)
         return rc;
-    hipLaunchKernelGGL(k_update, dim3(nblk(c->npad, 256)), dim3(256), 0, c->stream, c->npad, c->n, c->par_d, c->v_p,
-                       c->v_q, c->v_mu, c->v_r, c->v_z, c->sc, c->red.part, c->red.ticket);
+    StageTimer tm(c, AMOEBA_T_PCG);
+    hipLaunchKernelGGL(k_update, dim3(kRedBlocks), dim3(256), 0, c->stream, c->npad, it, c->par_d, c->v_p, c->v_q,
+                       c->v_mu, c->v_r, c->v_z, c->sc, part_pq(c), c->nbricks, part_vec(c));
     if (c->mixed)
-        hipLaunchKernelGGL(k_direction<float4>, dim3(nblk(c->npad, 256)), dim3(256), 0, c->stream, c->npad, c->v_z,
-                           c->v_p, c->pv_f, c->sc);
+        hipLaunchKernelGGL(k_direction<float4>, dim3(kRedBlocks), dim3(256), 0, c->stream, c->npad, c->n, it, c->v_z,
+                           c->v_p, c->pv_f, c->sc, part_vec(c));
     else
-        hipLaunchKernelGGL(k_direction<double4>, dim3(nblk(c->npad, 256)), dim3(256), 0, c->stream, c->npad, c->v_z,
-                           c->v_p, c->pv_d, c->sc);
+        hipLaunchKernelGGL(k_direction<double4>, dim3(kRedBlocks), dim3(256), 0, c->stream, c->npad, c->n, it,
+                           c->v_z, c->v_p, c->pv_d, c->sc, part_vec(c));
     return AMOEBA_OK;
 }
 
-// Iterate until the device flag says done or `budget` more iterations ran.  Host reads lag the
-// device by one queued iteration.  Returns a HIP/rocFFT error code or AMOEBA_OK.
-static int run_iterations(amoeba_ctx* c, int budget)
+// Iterations first..first+budget-1 until the device flag says done.  Host reads lag the device
+// by one queued iteration.  Returns a HIP/rocFFT error code or AMOEBA_OK.
+static int run_iterations(amoeba_ctx* c, int first, int budget)
 {
     hipStream_t st = c->stream;
     int enq = 0, chk = 0, rc;
     while (true) {
         if (enq < budget) {
-            if ((rc = enqueue_iteration(c)))
+            if ((rc = enqueue_iteration(c, first + enq)))
                 return rc;
             ++enq;
             hipMemcpyAsync(&c->sc_host[enq & 1], c->sc, sizeof(PcgScalars), hipMemcpyDeviceToHost, st);
@@ -289,10 +343,10 @@ int pcg_solve(amoeba_ctx* c, double tol, int max_iter, bool have_guess)
         launch_set_direction(c, c->v_mu);
         if ((rc = matvec_slot(c, false, false)))
             return rc;
-        launch_init_residual(c, c->v_q);
+        launch_init_residual(c, c->v_q, 0);
     } else {
         hipMemsetAsync(c->v_mu, 0, sizeof(double) * 3 * (size_t)c->npad, st);
-        launch_init_residual(c, nullptr);
+        launch_init_residual(c, nullptr, 0);
     }
     PcgScalars s;
     if ((rc = read_scalars(c, &s)))
@@ -302,7 +356,7 @@ int pcg_solve(amoeba_ctx* c, double tol, int max_iter, bool have_guess)
     bool checked_true = !c->mixed;
     while (true) {
         if (!s.done && used < max_iter) {
-            if ((rc = run_iterations(c, max_iter - used)))
+            if ((rc = run_iterations(c, used, max_iter - used)))
                 return rc;
             if ((rc = read_scalars(c, &s)))
                 return rc;
@@ -319,33 +373,26 @@ int pcg_solve(amoeba_ctx* c, double tol, int max_iter, bool have_guess)
         launch_set_direction(c, c->v_mu);
         if ((rc = matvec_slot(c, false, false)))
             return rc;
-        launch_init_residual(c, c->v_q);
-        PcgScalars t;
-        if ((rc = read_scalars(c, &t)))
+        launch_init_residual(c, c->v_q, used);
+        if ((rc = read_scalars(c, &s)))
             return rc;
-        t.iters = s.iters;
-        s = t;
+        s.iters = used;
         if (s.done)
             break;
         checked_true = false;
-        // restore the iteration count lost by the re-initialisation
-        c->sc_host[1] = s;
-        hipMemcpyAsync(c->sc, &c->sc_host[1], sizeof(PcgScalars), hipMemcpyHostToDevice, st);
-        if ((rc = hip_check(c, hipStreamSynchronize(st), "pcg restart")))
-            return rc;
         if (used >= max_iter)
             break;
     }
-    c->last_iters = s.iters;
+    c->last_iters = used;
     c->last_rms = s.rms;
-    c->matvecs += s.iters + (have_guess ? 1 : 0) + extra_matvecs;
+    c->matvecs += used + (have_guess ? 1 : 0) + extra_matvecs;
     return s.status == 1 ? AMOEBA_OK : AMOEBA_NOT_CONVERGED;
 }
 
 double compute_epol(amoeba_ctx* c)
 {
-    hipLaunchKernelGGL(k_epol, dim3(nblk(c->npad, 256)), dim3(256), 0, c->stream, c->npad, c->v_mu, c->v_e, c->sc,
-                       c->red.part, c->red.ticket);
+    hipLaunchKernelGGL(k_epol, dim3(kRedBlocks), dim3(256), 0, c->stream, c->npad, c->v_mu, c->v_e, part_vec(c));
+    hipLaunchKernelGGL(k_epol_finalize, dim3(1), dim3(256), 0, c->stream, kRedBlocks, part_vec(c), c->sc);
     PcgScalars s;
     if (read_scalars(c, &s))
         return 0.0;

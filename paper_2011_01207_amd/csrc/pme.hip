@@ -153,22 +153,34 @@ __global__ void k_bin_fill(int npad, const int* __restrict__ atom_bin, const int
     bin_atoms[bin_start[b] + k] = s;
 }
 
-// order within a bin by slot (deterministic accumulation order for the FP64 path)
-__global__ void k_bin_sort(int nbins, const int* __restrict__ bin_start, int* __restrict__ bin_atoms)
+// Order the atoms of each bin by slot (one workgroup per bin, rank sort in LDS), so that the
+// gather assigns atoms to lanes, and sums per-brick partials, in a reproducible order.
+constexpr int kBinCap = 2048;
+
+// (A bin holding more than kBinCap atoms, far above any liquid density, keeps its fill order:
+// results stay correct, only their last bits may then vary between list builds.)
+__global__ __launch_bounds__(256) void k_bin_sort(const int* __restrict__ bin_start, int* __restrict__ bin_atoms)
 {
-    int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= nbins)
+    __shared__ int s_v[kBinCap];
+    const int b = blockIdx.x;
+    const int lo = bin_start[b], n = bin_start[b + 1] - lo;
+    if (n > kBinCap)
         return;
-    int lo = bin_start[b], hi = bin_start[b + 1];
-    for (int i = lo + 1; i < hi; ++i) {
-        int v = bin_atoms[i];
-        int j = i - 1;
-        while (j >= lo && bin_atoms[j] > v) {
-            bin_atoms[j + 1] = bin_atoms[j];
-            --j;
-        }
-        bin_atoms[j + 1] = v;
+    for (int i = threadIdx.x; i < n; i += 256)
+        s_v[i] = bin_atoms[lo + i];
+    __syncthreads();
+    int rank[kBinCap / 256], val[kBinCap / 256];
+    int m = 0;
+    for (int i = threadIdx.x; i < n; i += 256, ++m) {
+        const int v = s_v[i];
+        int r = 0;
+        for (int k = 0; k < n; ++k)
+            r += s_v[k] < v;
+        rank[m] = r;
+        val[m] = v;
     }
+    for (int q = 0; q < m; ++q)
+        bin_atoms[lo + rank[q]] = val[q];
 }
 
 // ------------------------------------------------------------------------------------------
@@ -177,7 +189,7 @@ __global__ void k_bin_sort(int nbins, const int* __restrict__ bin_start, int* __
 template <bool FIX> struct LdsAcc;
 template <> struct LdsAcc<true> {
     using T = unsigned long long;
-    __device__ static void add(T* p, float v) { atomicAdd(p, (T)(long long)llrint((double)v * kFixScale)); }
+    __device__ static void add(T* p, float v) { atomicAdd(p, fix40(v)); }
     __device__ static float get(const T* p) { return (float)((double)(long long)(*p) * kFixInv); }
 };
 template <> struct LdsAcc<false> {
@@ -403,76 +415,321 @@ __device__ __forceinline__ void gather_field(const double4 p, double3 kl, int3 K
     ez = -sz * (R)kl.z;
 }
 
-template <typename R>
-__global__ void k_gather_out(int npad, const int* __restrict__ perm, const double4* __restrict__ pos_s, double3 kl,
-                             int3 K, const R* __restrict__ psi, double* __restrict__ out)
-{
-    int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= npad)
-        return;
-    R ex = 0, ey = 0, ez = 0;
-    if (perm[s] >= 0)
-        gather_field<R>(pos_s[s], kl, K, psi, ex, ey, ez);
-    out[3 * (size_t)s] = (double)ex;
-    out[3 * (size_t)s + 1] = (double)ey;
-    out[3 * (size_t)s + 2] = (double)ez;
-}
-
-// PCG matrix-vector product, last stage:  q = p / alpha - (E_real + E_rec + self * p);
-// clears the real-space accumulator for the next product; optionally p.q -> gamma = rz / pq.
+// ------------------------------------------------------------------------------------------
+// Dipole spread, two phases per brick (the per-iteration spread of the PCG).
+// Phase 1: one thread per candidate atom computes its splines once and, if its support meets
+// the brick, stores the inside spline values (compacted per dimension) and the brick-local
+// grid lines in LDS.  Phase 2: the (atom, x-line, y-line) rows that lie inside the brick are
+// enumerated exactly (prefix sum over atoms) and shared evenly by the threads; each row adds
+// its inside z-points to the LDS brick.
+// ------------------------------------------------------------------------------------------
 template <typename R, bool FIX>
-__global__ __launch_bounds__(256) void k_gather_combine(int npad, const int* __restrict__ perm,
-                                                        const double4* __restrict__ pos_s, double3 kl, int3 K,
-                                                        const R* __restrict__ psi, const double4* __restrict__ par,
-                                                        const double* __restrict__ p, double self,
-                                                        unsigned long long* __restrict__ acc_fx,
-                                                        double* __restrict__ acc_d, double* __restrict__ q,
-                                                        PcgScalars* __restrict__ sc, double* part,
-                                                        unsigned int* ticket, int use_done, int dot)
+__global__ __launch_bounds__(256) void k_spread_dip(int3 K, int3 nbr, const int* __restrict__ bin_start,
+                                                    const int* __restrict__ bin_atoms,
+                                                    const double4* __restrict__ pos_s, double3 kl,
+                                                    const typename V4p<R>::T* __restrict__ src, R* __restrict__ grid,
+                                                    const PcgScalars* __restrict__ sc, int use_done)
 {
+    using R4 = typename V4p<R>::T;
+    using AT = typename LdsAcc<FIX>::T;
+    constexpr int CH = sizeof(R) == 4 ? 256 : 128;  // candidate atoms per chunk
+    __shared__ AT acc[kBrick * kBrick * kBrick];
+    __shared__ R e_sp[6][5][CH];                      // x0 x1 y0 y1 z0 z1, compacted to the inside lines
+    __shared__ R e_mu[3][CH];
+    __shared__ int e_loc[3][CH];                      // per dim: count (3 bits) + 5 x 3-bit brick-local lines
+    __shared__ int e_pre[CH + 1];
+    __shared__ int bl[3][3], bnum[3];
+    __shared__ int rs[27], rn[27], pre[28];
+    __shared__ int n_e;
     if (use_done && sc->done)
         return;
-    int s = blockIdx.x * blockDim.x + threadIdx.x;
-    double pq = 0.0;
-    if (s < npad) {
-        double e[3] = {0.0, 0.0, 0.0};
-        if (perm[s] >= 0) {
-            R ex, ey, ez;
-            gather_field<R>(pos_s[s], kl, K, psi, ex, ey, ez);
-            e[0] = ex;
-            e[1] = ey;
-            e[2] = ez;
-        }
-        double ainv = par[s].y;
-        for (int a = 0; a < 3; ++a) {
-            size_t i = 3 * (size_t)s + a;
-            double er;
-            if (FIX) {
-                er = (double)(long long)acc_fx[i] * kFixInv;
-                acc_fx[i] = 0ull;
-            } else {
-                er = acc_d[i];
-                acc_d[i] = 0.0;
+    const int tid = threadIdx.x;
+    const int b = blockIdx.x;
+    const int bz = b % nbr.z, by = (b / nbr.z) % nbr.y, bx = b / (nbr.z * nbr.y);
+    const int lo[3] = {bx * kBrick, by * kBrick, bz * kBrick};
+    const int kk[3] = {K.x, K.y, K.z};
+    const int ext[3] = {min(kBrick, K.x - lo[0]), min(kBrick, K.y - lo[1]), min(kBrick, K.z - lo[2])};
+    for (int q = tid; q < kBrick * kBrick * kBrick; q += 256)
+        acc[q] = (AT)0;
+    if (tid < 3) {
+        const int nb = tid == 0 ? nbr.x : (tid == 1 ? nbr.y : nbr.z);
+        const int b0 = tid == 0 ? bx : (tid == 1 ? by : bz);
+        int cnt = 0;
+        int c0 = b0, c1 = (b0 + 1) % nb, c2 = (b0 + 2) % nb;
+        bl[tid][cnt++] = c0;
+        if (c1 != c0)
+            bl[tid][cnt++] = c1;
+        if (min(kBrick, kk[tid] - c1 * kBrick) < 4 && c2 != c0 && c2 != c1)
+            bl[tid][cnt++] = c2;
+        bnum[tid] = cnt;
+    }
+    __syncthreads();
+    const int nr = bnum[0] * bnum[1] * bnum[2];
+    if (tid < nr) {
+        int qz = tid % bnum[2], qy = (tid / bnum[2]) % bnum[1], qx = tid / (bnum[2] * bnum[1]);
+        int nbin = (bl[0][qx] * nbr.y + bl[1][qy]) * nbr.z + bl[2][qz];
+        rs[tid] = bin_start[nbin];
+        rn[tid] = bin_start[nbin + 1] - bin_start[nbin];
+    }
+    __syncthreads();
+    if (tid == 0) {
+        pre[0] = 0;
+        for (int q = 0; q < nr; ++q)
+            pre[q + 1] = pre[q] + rn[q];
+    }
+    __syncthreads();
+    const int ntot = pre[nr];
+    const double klv[3] = {kl.x, kl.y, kl.z};
+    for (int c0 = 0; c0 < ntot; c0 += CH) {
+        if (tid == 0)
+            n_e = 0;
+        __syncthreads();
+        // phase 1
+        for (int item = c0 + tid; item < min(c0 + CH, ntot); item += 256) {
+            int q = 0;
+            while (item >= pre[q + 1])
+                ++q;
+            const int s = bin_atoms[rs[q] + item - pre[q]];
+            const double4 pp = pos_s[s];
+            const double xyz[3] = {pp.x, pp.y, pp.z};
+            int fl[3], loc[3] = {0, 0, 0}, cnt[3] = {0, 0, 0};
+            double wv[3];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                grid_coord(xyz[d], klv[d], kk[d], fl[d], wv[d]);
+#pragma unroll
+                for (int tt = 0; tt < 5; ++tt) {
+                    int g = fl[d] - tt;
+                    g += g < 0 ? kk[d] : 0;
+                    int l = g - lo[d];
+                    if (l >= 0 && l < ext[d]) {
+                        loc[d] |= l << (3 + 3 * cnt[d]);
+                        ++cnt[d];
+                    }
+                }
             }
-            double pa = p[i];
-            double qa = perm[s] >= 0 ? pa * ainv - (er + e[a] + self * pa) : 0.0;
-            q[i] = qa;
-            pq += pa * qa;
+            if (cnt[0] == 0 || cnt[1] == 0 || cnt[2] == 0)
+                continue;
+            const int e = atomicAdd(&n_e, 1);
+            const R4 mu = src[s];
+            e_mu[0][e] = mu.x;
+            e_mu[1][e] = mu.y;
+            e_mu[2][e] = mu.z;
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                R m0[5], m1[5], m2[5];
+                spline5<R, false>((R)wv[d], m0, m1, m2);
+                int j = 0;
+#pragma unroll
+                for (int tt = 0; tt < 5; ++tt) {
+                    int g = fl[d] - tt;
+                    g += g < 0 ? kk[d] : 0;
+                    int l = g - lo[d];
+                    if (l >= 0 && l < ext[d]) {
+                        e_sp[2 * d][j][e] = m0[tt];
+                        e_sp[2 * d + 1][j][e] = m1[tt] * (R)klv[d];
+                        ++j;
+                    }
+                }
+                e_loc[d][e] = loc[d] | cnt[d];
+            }
+        }
+        __syncthreads();
+        // rows per entry and their prefix sum (wave 0, 4 entries per lane)
+        const int ne = n_e;
+        if (tid < 64) {
+            int v[4], sum = 0;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                int e = tid * 4 + u;
+                v[u] = e < ne ? (e_loc[0][e] & 7) * (e_loc[1][e] & 7) : 0;
+                sum += v[u];
+            }
+            int incl = sum;
+#pragma unroll
+            for (int d = 1; d < 64; d <<= 1) {
+                int y = __shfl_up(incl, d);
+                if (tid >= d)
+                    incl += y;
+            }
+            int run = incl - sum;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                int e = tid * 4 + u;
+                if (e < CH + 1)
+                    e_pre[e] = run;
+                run += v[u];
+            }
+            if (tid == 63)
+                e_pre[CH] = run;  // total (entries >= n_e count zero rows)
+        }
+        __syncthreads();
+        // phase 2
+        const int rows = e_pre[ne];
+        for (int item = tid; item < rows; item += 256) {
+            int lo_e = 0, hi_e = ne - 1;
+            while (lo_e < hi_e) {
+                int mid = (lo_e + hi_e + 1) >> 1;
+                if (e_pre[mid] <= item)
+                    lo_e = mid;
+                else
+                    hi_e = mid - 1;
+            }
+            const int e = lo_e;
+            const int r = item - e_pre[e];
+            const int lx = e_loc[0][e], ly = e_loc[1][e], lz = e_loc[2][e];
+            const int cy = ly & 7, cz = lz & 7;
+            const int ix = r / cy, iy = r - ix * cy;
+            const int gx = (lx >> (3 + 3 * ix)) & 7, gy = (ly >> (3 + 3 * iy)) & 7;
+            const R x0 = e_sp[0][ix][e], x1 = e_sp[1][ix][e], y0 = e_sp[2][iy][e], y1 = e_sp[3][iy][e];
+            const R cz0 = e_mu[0][e] * x1 * y0 + e_mu[1][e] * x0 * y1;
+            const R cz1 = e_mu[2][e] * x0 * y0;
+            const int base = (gx * kBrick + gy) * kBrick;
+            for (int iz = 0; iz < cz; ++iz) {
+                const int gz = (lz >> (3 + 3 * iz)) & 7;
+                LdsAcc<FIX>::add(&acc[base + gz], cz0 * e_sp[4][iz][e] + cz1 * e_sp[5][iz][e]);
+            }
+        }
+        __syncthreads();
+    }
+    for (int q = tid; q < kBrick * kBrick * kBrick; q += 256) {
+        int lx = q / (kBrick * kBrick), ly = (q / kBrick) % kBrick, lz = q % kBrick;
+        if (lx < ext[0] && ly < ext[1] && lz < ext[2])
+            grid[((size_t)(lo[0] + lx) * K.y + (lo[1] + ly)) * K.z + (lo[2] + lz)] = (R)LdsAcc<FIX>::get(&acc[q]);
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// Gather, LDS-tiled per brick: the 12^3 potential points that the atoms binned in a brick can
+// touch are loaded once into LDS; eight lanes serve one atom: five of them one x-line of the
+// 5x5x5 stencil each, combined with shuffles.
+// MODE 0: write E_rec.
+// MODE 1: PCG operator assembly q = p/alpha - (E_real + E_rec + self p); the other three lanes
+//         of the atom's group sum its real-space field (its block's i-field plus the tile j-fields
+//         listed in the reverse index, in fixed order); optionally the workgroup's p.q partial.
+// ------------------------------------------------------------------------------------------
+constexpr int kReg = kBrick + 4;
+
+template <typename R, int MODE>
+__global__ __launch_bounds__(256) void k_gather_brick(int3 K, int3 nbr, const int* __restrict__ bin_start,
+                                                      const int* __restrict__ bin_atoms,
+                                                      const double4* __restrict__ pos_s, double3 kl,
+                                                      const R* __restrict__ psi, const double4* __restrict__ par,
+                                                      const double* __restrict__ p, double self,
+                                                      const double* __restrict__ eipart, const R* __restrict__ jbuf,
+                                                      const int* __restrict__ rev_ptr, const int* __restrict__ rev_idx,
+                                                      double* __restrict__ out, const PcgScalars* __restrict__ sc,
+                                                      double* __restrict__ part, int use_done, int dot)
+{
+    __shared__ R s_g[kReg * kReg * kReg];
+    if (use_done && sc->done)
+        return;
+    const int tid = threadIdx.x;
+    const int b = blockIdx.x;
+    const int bz = b % nbr.z, by = (b / nbr.z) % nbr.y, bx = b / (nbr.z * nbr.y);
+    const int ox = bx * kBrick - 4, oy = by * kBrick - 4, oz = bz * kBrick - 4;  // region origin
+    for (int idx = tid; idx < kReg * kReg * kReg; idx += 256) {
+        int lz = idx % kReg, ly = (idx / kReg) % kReg, lx = idx / (kReg * kReg);
+        // region coordinates lie in [-4, K + 7]: one conditional wrap per dimension (K >= 10)
+        int gx = ox + lx, gy = oy + ly, gz = oz + lz;
+        gx += gx < 0 ? K.x : 0;
+        gx -= gx >= K.x ? K.x : 0;
+        gy += gy < 0 ? K.y : 0;
+        gy -= gy >= K.y ? K.y : 0;
+        gz += gz < 0 ? K.z : 0;
+        gz -= gz >= K.z ? K.z : 0;
+        s_g[idx] = psi[((size_t)gx * K.y + gy) * K.z + gz];
+    }
+    __syncthreads();
+    const int a0 = bin_start[b], na = bin_start[b + 1] - a0;
+    const int sub = tid & 7, grp = tid >> 3, gl = (tid & 63) & ~7;  // gl: group's first lane in the wave
+    double pq[1] = {0.0};
+    for (int base = 0; base < na; base += 32) {
+        const int ai = base + grp;
+        R sx = 0, sy = 0, sz = 0;
+        double er = 0.0;
+        int s = -1;
+        if (ai < na) {
+            s = bin_atoms[a0 + ai];
+            if (sub < 5) {
+                const double4 pp = pos_s[s];
+                int fx, fy, fz;
+                double wx, wy, wz;
+                grid_coord(pp.x, kl.x, K.x, fx, wx);
+                grid_coord(pp.y, kl.y, K.y, fy, wy);
+                grid_coord(pp.z, kl.z, K.z, fz, wz);
+                R x0[5], x1[5], y0[5], y1[5], z0[5], z1[5], dum[5];
+                spline5<R, false>((R)wx, x0, x1, dum);
+                spline5<R, false>((R)wy, y0, y1, dum);
+                spline5<R, false>((R)wz, z0, z1, dum);
+                const int lx = fx - sub - ox;  // in [0, 11]: fx lies in this brick
+                const int lyb = fy - oy, lzb = fz - oz;
+                const R* plane = s_g + lx * kReg * kReg;
+                R ax = 0, ay = 0, az = 0;
+#pragma unroll
+                for (int ty = 0; ty < 5; ++ty) {
+                    const R* row = plane + (lyb - ty) * kReg;
+                    R s0 = 0, s1 = 0;
+#pragma unroll
+                    for (int tz = 0; tz < 5; ++tz) {
+                        R v = row[lzb - tz];
+                        s0 += z0[tz] * v;
+                        s1 += z1[tz] * v;
+                    }
+                    ax += y0[ty] * s0;
+                    ay += y1[ty] * s0;
+                    az += y0[ty] * s1;
+                }
+                sx = x1[sub] * ax;
+                sy = x0[sub] * ay;
+                sz = x0[sub] * az;
+            } else if (MODE == 1) {
+                const int c = sub - 5;
+                er = eipart[3 * (size_t)s + c];
+                for (int k = rev_ptr[s]; k < rev_ptr[s + 1]; ++k) {
+                    const int e = rev_idx[k];
+                    er += (double)jbuf[((size_t)(e >> 6) * 3 + c) * kBlock + (e & 63)];
+                }
+            }
+        }
+        sx += __shfl_xor(sx, 4);
+        sy += __shfl_xor(sy, 4);
+        sz += __shfl_xor(sz, 4);
+        sx += __shfl_xor(sx, 2);
+        sy += __shfl_xor(sy, 2);
+        sz += __shfl_xor(sz, 2);
+        sx += __shfl_xor(sx, 1);
+        sy += __shfl_xor(sy, 1);
+        sz += __shfl_xor(sz, 1);
+        double erx = 0.0, ery = 0.0, erz = 0.0;
+        if (MODE == 1) {
+            erx = __shfl(er, gl + 5);
+            ery = __shfl(er, gl + 6);
+            erz = __shfl(er, gl + 7);
+        }
+        if (sub == 0 && s >= 0) {
+            const double e[3] = {-(double)sx * kl.x, -(double)sy * kl.y, -(double)sz * kl.z};
+            if (MODE == 0) {
+                for (int a = 0; a < 3; ++a)
+                    out[3 * (size_t)s + a] = e[a];
+            } else {
+                const double ereal[3] = {erx, ery, erz};
+                const double ainv = par[s].y;
+                for (int a = 0; a < 3; ++a) {
+                    const size_t i = 3 * (size_t)s + a;
+                    const double pa = p[i];
+                    const double qa = pa * ainv - (ereal[a] + e[a] + self * pa);
+                    out[i] = qa;
+                    pq[0] += pa * qa;
+                }
+            }
         }
     }
-    if (!dot)
+    if (MODE == 0 || !dot)
         return;
-    double v[1] = {pq};
-    grid_reduce<1>(v, part, ticket, [sc](const double* tot) {
-        sc->pq = tot[0];
-        if (!(tot[0] > 0.0) || !isfinite(tot[0])) {
-            sc->done = 1;
-            sc->status = 2;
-            sc->gamma = 0.0;
-        } else {
-            sc->gamma = sc->rz / tot[0];
-        }
-    });
+    block_sum<1>(pq);
+    if (tid == 0)
+        part[b] = pq[0];
 }
 
 static inline int nblk(size_t n, int b) { return (int)((n + b - 1) / b); }
@@ -566,8 +823,7 @@ void pme_bin_atoms(amoeba_ctx* c)
     hipMemsetAsync(c->bin_count, 0, sizeof(int) * (c->nbricks + 1), st);
     hipLaunchKernelGGL(k_bin_fill, dim3(nblk(c->npad, 256)), dim3(256), 0, st, c->npad, c->atom_bin, c->bin_start,
                        c->bin_count, c->bin_atoms);
-    hipLaunchKernelGGL(k_bin_sort, dim3(nblk(c->nbricks, 64)), dim3(64), 0, st, c->nbricks, c->bin_start,
-                       c->bin_atoms);
+    hipLaunchKernelGGL(k_bin_sort, dim3(c->nbricks), dim3(256), 0, st, c->bin_start, c->bin_atoms);
 }
 
 __global__ __launch_bounds__(1024) void k_scan_excl_pme(int n, const int* __restrict__ in, int* __restrict__ out)
@@ -630,11 +886,11 @@ int pme_dipole_field(amoeba_ctx* c, bool use_done)
     {
     StageTimer tm(c, AMOEBA_T_SPREAD);
     if (c->mixed)
-        hipLaunchKernelGGL((k_spread<float, true, false>), dim3(c->nbricks), dim3(256), 0, c->stream, K, nbr,
+        hipLaunchKernelGGL((k_spread_dip<float, true>), dim3(c->nbricks), dim3(256), 0, c->stream, K, nbr,
                            c->bin_start, c->bin_atoms, c->pos_s, kl, c->pv_f, (float*)c->grid_r, c->sc,
                            (int)use_done);
     else
-        hipLaunchKernelGGL((k_spread<double, false, false>), dim3(c->nbricks), dim3(256), 0, c->stream, K, nbr,
+        hipLaunchKernelGGL((k_spread_dip<double, false>), dim3(c->nbricks), dim3(256), 0, c->stream, K, nbr,
                            c->bin_start, c->bin_atoms, c->pos_s, kl, c->pv_d, (double*)c->grid_r, c->sc,
                            (int)use_done);
     }
@@ -669,32 +925,38 @@ void launch_gather(amoeba_ctx* c, double* out)
 {
     StageTimer tm(c, AMOEBA_T_GATHER);
     int3 K = make_int3(c->K[0], c->K[1], c->K[2]);
+    int3 nbr = make_int3(c->nbr[0], c->nbr[1], c->nbr[2]);
     double3 kl = make_double3(c->K[0] / c->prm.box[0], c->K[1] / c->prm.box[1], c->K[2] / c->prm.box[2]);
     if (c->mixed)
-        hipLaunchKernelGGL(k_gather_out<float>, dim3(nblk(c->npad, 256)), dim3(256), 0, c->stream, c->npad, c->perm,
-                           c->pos_s, kl, K, (const float*)c->grid_r, out);
+        hipLaunchKernelGGL((k_gather_brick<float, 0>), dim3(c->nbricks), dim3(256), 0, c->stream, K, nbr,
+                           c->bin_start, c->bin_atoms, c->pos_s, kl, (const float*)c->grid_r, c->par_d,
+                           (const double*)nullptr, 0.0, (const double*)nullptr, (const float*)nullptr,
+                           (const int*)nullptr, (const int*)nullptr, out, c->sc, c->red.part, 0, 0);
     else
-        hipLaunchKernelGGL(k_gather_out<double>, dim3(nblk(c->npad, 256)), dim3(256), 0, c->stream, c->npad,
-                           c->perm, c->pos_s, kl, K, (const double*)c->grid_r, out);
+        hipLaunchKernelGGL((k_gather_brick<double, 0>), dim3(c->nbricks), dim3(256), 0, c->stream, K, nbr,
+                           c->bin_start, c->bin_atoms, c->pos_s, kl, (const double*)c->grid_r, c->par_d,
+                           (const double*)nullptr, 0.0, (const double*)nullptr, (const double*)nullptr,
+                           (const int*)nullptr, (const int*)nullptr, out, c->sc, c->red.part, 0, 0);
 }
 
 void launch_matvec_combine(amoeba_ctx* c, bool use_done, bool dot_pq)
 {
     StageTimer tm(c, AMOEBA_T_GATHER);
     int3 K = make_int3(c->K[0], c->K[1], c->K[2]);
+    int3 nbr = make_int3(c->nbr[0], c->nbr[1], c->nbr[2]);
     double3 kl = make_double3(c->K[0] / c->prm.box[0], c->K[1] / c->prm.box[1], c->K[2] / c->prm.box[2]);
     double b = c->prm.ewald_alpha;
     double self = 4.0 * b * b * b / (3.0 * sqrt(kPi));
     if (c->mixed)
-        hipLaunchKernelGGL((k_gather_combine<float, true>), dim3(nblk(c->npad, 256)), dim3(256), 0, c->stream,
-                           c->npad, c->perm, c->pos_s, kl, K, (const float*)c->grid_r, c->par_d, c->v_p, self,
-                           c->acc_fx, (double*)nullptr, c->v_q, c->sc, c->red.part, c->red.ticket, (int)use_done,
-                           (int)dot_pq);
-    else
-        hipLaunchKernelGGL((k_gather_combine<double, false>), dim3(nblk(c->npad, 256)), dim3(256), 0, c->stream,
-                           c->npad, c->perm, c->pos_s, kl, K, (const double*)c->grid_r, c->par_d, c->v_p, self,
-                           (unsigned long long*)nullptr, c->acc_d, c->v_q, c->sc, c->red.part, c->red.ticket,
+        hipLaunchKernelGGL((k_gather_brick<float, 1>), dim3(c->nbricks), dim3(256), 0, c->stream, K, nbr,
+                           c->bin_start, c->bin_atoms, c->pos_s, kl, (const float*)c->grid_r, c->par_d, c->v_p, self,
+                           c->eipart, (const float*)c->jbuf, c->rev_ptr, c->rev_idx, c->v_q, c->sc, c->red.part,
                            (int)use_done, (int)dot_pq);
+    else
+        hipLaunchKernelGGL((k_gather_brick<double, 1>), dim3(c->nbricks), dim3(256), 0, c->stream, K, nbr,
+                           c->bin_start, c->bin_atoms, c->pos_s, kl, (const double*)c->grid_r, c->par_d, c->v_p,
+                           self, c->eipart, (const double*)c->jbuf, c->rev_ptr, c->rev_idx, c->v_q, c->sc,
+                           c->red.part, (int)use_done, (int)dot_pq);
 }
 
 }  // namespace amoeba

@@ -1,17 +1,23 @@
 // Real-space pair kernels over 64 x 64 block tiles (paper: "Neighbor list" block-matrix
-// interaction, "List filtering" group-atom tiles, and the real-space scheme with atomic
-// accumulation).
+// interaction, "List filtering" group-atom tiles, and the real-space scheme; the scaled pairs
+// are corrected in a separate pass as in the paper's final real-space scheme).
 //
-// One wave64 per tile: lane i holds i-atom i of the block in registers; the tile's 64 j-atoms
-// (positions relative to the i-block origin, dipoles / multipoles and damping parameters) are
-// staged in LDS.  The wave walks the 64 diagonals of the tile: at step s lane i pairs with
-// j-atom (i + s) mod 64, so within a step every lane touches a different j and the j-field
-// accumulators in LDS are updated without atomics, in a fixed order.  A step is evaluated only
-// where the tile's in-cutoff bitmask has the bit (the wave skips steps with no bit set).  Both
-// directions of every pair are computed once (Newton's third law): the field at i stays in
-// registers, the field at j in LDS; both are flushed with one global atomic per atom and
-// component per tile — 64-bit fixed point in mixed precision (deterministic, order-free
-// integer sums), FP64 atomics in FP64 mode.
+// One workgroup (4 waves) per 64-atom i-block; the waves take the block's tiles in turn.  The
+// block's i-atoms are staged in LDS once; each wave stages its tile's 64 j-atoms (positions
+// relative to the i-block origin, dipoles or multipoles, damping parameters) and the tile's
+// in-cutoff bitmasks.  An exclusive wave scan of the row popcounts numbers the in-cutoff pairs,
+// and every lane evaluates an equal contiguous share of them by walking the set bits of the
+// masks, so masked-out pair slots cost nothing.  Each pair is evaluated once (Newton's third
+// law): the field at i accumulates in registers while the lane stays on a row and is then added
+// to the block's LDS accumulator, which collects all tiles of the block; the field at j is added
+// to the tile's LDS accumulator.  In mixed precision every LDS addition is a 64-bit fixed-point
+// integer (40 fraction bits), so the sums do not depend on the order of the lanes' atomics and
+// the product is bitwise reproducible; FP64 mode accumulates in FP64.
+//
+// No global atomics: a block writes its i-field once (eipart) and each off-diagonal tile writes
+// its 64 j-fields to its own slot of jbuf; the diagonal tile's j-field goes straight into the
+// block's accumulator.  Every atom's real-space field is then the sum of its eipart and of the
+// jbuf slots listed for it in the reverse index built with the list (fixed order).
 //
 // Pair math (Ewald real space, Thole damping of Ren & Ponder as used by AMOEBA):
 //   B0 = erfc(beta r)/r,  B_n = ((2n-1) B_{n-1} + (2 beta^2)^n e^{-beta^2 r^2} / (beta sqrt(pi))) / r^2
@@ -50,255 +56,353 @@ template <typename R> EwaldArgs<R> make_ewald(const amoeba_ctx* c)
     return e;
 }
 
-__device__ __forceinline__ float d_erfc(float x) { return erfcf(x); }
-__device__ __forceinline__ double d_erfc(double x) { return erfc(x); }
-__device__ __forceinline__ float d_exp(float x) { return expf(x); }
+// exp and erfc of the pair kernels.  FP64 uses the math library.  FP32 uses the hardware
+// exponential and erfc(x) = P(t) exp(-x^2), t = 1 / (1 + x/2), with P the degree-9 polynomial
+// fitted to erfc(x) exp(x^2) on [0, 4.5] by fit_erfc.py (relative error 2e-8 in exact
+// arithmetic, 4e-7 evaluated in FP32); exp(-x^2) is the Ewald Gaussian the pair needs anyway.
+__device__ __forceinline__ float d_exp(float x) { return __expf(x); }
 __device__ __forceinline__ double d_exp(double x) { return exp(x); }
+__device__ __forceinline__ float d_erfc_g(float x, float gauss)
+{
+    const float t = __frcp_rn(1.0f + 0.5f * x);
+    float p = -2.195935133e-02f;
+    p = fmaf(p, t, 7.868809266e-02f);
+    p = fmaf(p, t, 9.712290818e-03f);
+    p = fmaf(p, t, -4.060558973e-01f);
+    p = fmaf(p, t, 5.650127558e-01f);
+    p = fmaf(p, t, -1.304386780e-01f);
+    p = fmaf(p, t, 3.651958400e-01f);
+    p = fmaf(p, t, 2.542852723e-01f);
+    p = fmaf(p, t, 2.857695362e-01f);
+    p = fmaf(p, t, -2.098618019e-04f);
+    return p * gauss;
+}
+__device__ __forceinline__ double d_erfc_g(double x, double) { return erfc(x); }
 __device__ __forceinline__ float d_rsqrt(float x) { return rsqrtf(x); }
 __device__ __forceinline__ double d_rsqrt(double x) { return 1.0 / sqrt(x); }
 __device__ __forceinline__ float d_rint(float x) { return rintf(x); }
 __device__ __forceinline__ double d_rint(double x) { return rint(x); }
 
-template <bool FIX> struct Acc;
-template <> struct Acc<true> {
-    using T = unsigned long long;
-    __device__ static void add(T* p, float v)
-    {
-        if (v != 0.0f)
-            atomicAdd(p, (T)(long long)llrint((double)v * kFixScale));
-    }
-};
-template <> struct Acc<false> {
-    using T = double;
-    __device__ static void add(T* p, double v)
-    {
-        if (v != 0.0)
-            atomicAdd(p, v);
-    }
-};
-
 constexpr int kWavesPerWG = 4;
 
+// LDS field accumulators: 64-bit fixed point (mixed) or FP64.
+template <bool FIX> struct LdsField;
+template <> struct LdsField<true> {
+    using T = unsigned long long;
+    __device__ static void add(T* p, float v) { atomicAdd(p, fix40(v)); }
+    __device__ static void add_raw(T* p, T v) { atomicAdd(p, v); }
+    __device__ static double value(T v) { return (double)(long long)v * kFixInv; }
+};
+template <> struct LdsField<false> {
+    using T = double;
+    __device__ static void add(T* p, double v) { atomicAdd(p, v); }
+    __device__ static void add_raw(T* p, T v) { atomicAdd(p, v); }
+    __device__ static double value(T v) { return v; }
+};
+
+__device__ __forceinline__ int wave_excl_scan(int x, int lane, int& total)
+{
+    int incl = x;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        int y = __shfl_up(incl, d);
+        if (lane >= d)
+            incl += y;
+    }
+    total = __shfl(incl, 63);
+    return incl - x;
+}
+
+// first pair of a lane's range: row i (largest with off[i] <= p0) and its mask with the first
+// (p0 - off[i]) set bits cleared
+__device__ __forceinline__ void walk_start(const int* s_off, const unsigned long long* s_mask, int p0, int& i,
+                                           unsigned long long& rem)
+{
+    int lo = 0, hi = 63;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (s_off[mid] <= p0)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    i = lo;
+    rem = s_mask[i];
+    for (int r = p0 - s_off[i]; r > 0; --r)
+        rem &= rem - 1ull;
+}
+
+// Radial functions of a pair: B1', B2' (and B3' when THIRD), minimum-image displacement.
+template <typename R, bool THIRD> struct PairGeom {
+    R dx, dy, dz, b1p, b2p, b3p;
+    __device__ __forceinline__ PairGeom(const typename V4<R>::T& ip, const typename V4<R>::T& jp, R ai, R aj,
+                                        const EwaldArgs<R>& ew)
+    {
+        dx = ip.x - jp.x;
+        dy = ip.y - jp.y;
+        dz = ip.z - jp.z;
+        dx -= ew.L[0] * d_rint(dx * ew.Linv[0]);
+        dy -= ew.L[1] * d_rint(dy * ew.Linv[1]);
+        dz -= ew.L[2] * d_rint(dz * ew.Linv[2]);
+        const R r2 = dx * dx + dy * dy + dz * dz;
+        const R rinv = d_rsqrt(r2);
+        const R r = r2 * rinv;
+        const R rinv2 = rinv * rinv;
+        const R gauss = d_exp(-ew.beta2 * r2);
+        const R gb = ew.g * gauss;
+        const R b0 = d_erfc_g(ew.beta * r, gauss) * rinv;
+        const R b1 = (b0 + gb) * rinv2;
+        const R b2 = ((R)3 * b1 + ew.t * gb) * rinv2;
+        const R a = ai < aj ? ai : aj;
+        const R u = r * ip.w * jp.w;
+        const R eps = a * u * u * u;
+        const R ex = d_exp(-eps);
+        const R rinv3 = rinv * rinv2, rinv5 = rinv3 * rinv2;
+        b1p = b1 - ex * rinv3;
+        b2p = b2 - (R)3 * ((R)1 + eps) * ex * rinv5;
+        if (THIRD) {
+            const R b3 = ((R)5 * b2 + ew.t2 * gb) * rinv2;
+            b3p = b3 - (R)15 * ((R)1 + eps + (R)0.6 * eps * eps) * ex * rinv5 * rinv2;
+        } else {
+            b3p = 0;
+        }
+    }
+};
+
+// Induced-dipole interaction.  Per atom: d[0] = (mu_x, mu_y, mu_z, Thole a).
+template <typename R> struct DipoleKind {
+    using R4 = typename V4<R>::T;
+    static constexpr int NV = 1;
+    __device__ static void load(const R4* src, size_t s, R a, R4* d)
+    {
+        R4 m = src[s];
+        d[0] = R4{m.x, m.y, m.z, a};
+    }
+    __device__ static void pair(const R4& ip, const R4* di, const R4& jp, const R4* dj, const EwaldArgs<R>& ew,
+                                R* ei, R* ej)
+    {
+        PairGeom<R, false> g(ip, jp, di[0].w, dj[0].w, ew);
+        const R mjd = dj[0].x * g.dx + dj[0].y * g.dy + dj[0].z * g.dz;
+        const R mid = di[0].x * g.dx + di[0].y * g.dy + di[0].z * g.dz;
+        ei[0] = -g.b1p * dj[0].x + g.b2p * mjd * g.dx;
+        ei[1] = -g.b1p * dj[0].y + g.b2p * mjd * g.dy;
+        ei[2] = -g.b1p * dj[0].z + g.b2p * mjd * g.dz;
+        ej[0] = -g.b1p * di[0].x + g.b2p * mid * g.dx;
+        ej[1] = -g.b1p * di[0].y + g.b2p * mid * g.dy;
+        ej[2] = -g.b1p * di[0].z + g.b2p * mid * g.dz;
+    }
+};
+
+// Permanent multipoles.  Per atom: d[0] = (q, dx, dy, dz), d[1] = (Txx, Txy, Txz, Tyy),
+// d[2] = (Tyz, Tzz, Thole a, 0).
+template <typename R> struct MultipoleKind {
+    using R4 = typename V4<R>::T;
+    static constexpr int NV = 3;
+    __device__ static void load(const R4* src, size_t s, R a, R4* d)
+    {
+        d[0] = src[3 * s];
+        d[1] = src[3 * s + 1];
+        R4 m2 = src[3 * s + 2];
+        d[2] = R4{m2.x, m2.y, a, 0};
+    }
+    __device__ static void pair(const R4& ip, const R4* di, const R4& jp, const R4* dj, const EwaldArgs<R>& ew,
+                                R* ei, R* ej)
+    {
+        PairGeom<R, true> g(ip, jp, di[2].z, dj[2].z, ew);
+        const R third = (R)1 / (R)3;
+        const R c2 = g.b2p * ((R)2 / (R)3);
+        {  // field at i from j
+            const R tdx = dj[1].x * g.dx + dj[1].y * g.dy + dj[1].z * g.dz;
+            const R tdy = dj[1].y * g.dx + dj[1].w * g.dy + dj[2].x * g.dz;
+            const R tdz = dj[1].z * g.dx + dj[2].x * g.dy + dj[2].y * g.dz;
+            const R tdd = tdx * g.dx + tdy * g.dy + tdz * g.dz;
+            const R dd = dj[0].y * g.dx + dj[0].z * g.dy + dj[0].w * g.dz;
+            const R rad = dj[0].x * g.b1p + g.b2p * dd + g.b3p * tdd * third;
+            ei[0] = rad * g.dx - g.b1p * dj[0].y - c2 * tdx;
+            ei[1] = rad * g.dy - g.b1p * dj[0].z - c2 * tdy;
+            ei[2] = rad * g.dz - g.b1p * dj[0].w - c2 * tdz;
+        }
+        {  // field at j from i (r -> -r)
+            const R tdx = di[1].x * g.dx + di[1].y * g.dy + di[1].z * g.dz;
+            const R tdy = di[1].y * g.dx + di[1].w * g.dy + di[2].x * g.dz;
+            const R tdz = di[1].z * g.dx + di[2].x * g.dy + di[2].y * g.dz;
+            const R tdd = tdx * g.dx + tdy * g.dy + tdz * g.dz;
+            const R dd = di[0].y * g.dx + di[0].z * g.dy + di[0].w * g.dz;
+            const R rad = -di[0].x * g.b1p + g.b2p * dd - g.b3p * tdd * third;
+            ej[0] = rad * g.dx - g.b1p * di[0].y + c2 * tdx;
+            ej[1] = rad * g.dy - g.b1p * di[0].z + c2 * tdy;
+            ej[2] = rad * g.dz - g.b1p * di[0].w + c2 * tdz;
+        }
+    }
+};
+
 // ------------------------------------------------------------------------------------------
-// K3: induced-dipole field tiles (the PCG matrix-vector product, real-space part)
+// K3 / K3p: one workgroup per i-block over all the block's tiles.
+// jbuf layout: [tile][component][lane] (R);  eipart: [slot][3] (FP64).
 // ------------------------------------------------------------------------------------------
-template <typename R, bool FIX>
-__global__ __launch_bounds__(256) void k_mutual_tiles(int ntiles, const int* __restrict__ tile_blk,
-                                                      const int* __restrict__ tile_j,
-                                                      const unsigned long long* __restrict__ tile_mask,
-                                                      const typename V4<R>::T* __restrict__ jrel,
-                                                      const typename V4<R>::T* __restrict__ off,
-                                                      const typename V4<R>::T* __restrict__ par,
-                                                      const typename V4<R>::T* __restrict__ pv, EwaldArgs<R> ew,
-                                                      typename Acc<FIX>::T* __restrict__ acc,
-                                                      const PcgScalars* __restrict__ sc, int use_done)
+template <typename R, bool FIX, class K>
+__global__ __launch_bounds__(256) void k_block_tiles(int nb, const int* __restrict__ blk_tile0,
+                                                     const int* __restrict__ tile_j,
+                                                     const unsigned long long* __restrict__ tile_mask,
+                                                     const typename V4<R>::T* __restrict__ jrel,
+                                                     const typename V4<R>::T* __restrict__ off,
+                                                     const typename V4<R>::T* __restrict__ par,
+                                                     const typename V4<R>::T* __restrict__ src, EwaldArgs<R> ew,
+                                                     double* __restrict__ eipart, R* __restrict__ jbuf,
+                                                     const PcgScalars* __restrict__ sc, int use_done)
 {
     using R4 = typename V4<R>::T;
-    __shared__ R4 s_pos[kWavesPerWG][kBlock];  // j offset from the i-block origin, w = alpha_j^-1/6
-    __shared__ R4 s_mu[kWavesPerWG][kBlock];   // j dipole, w = Thole a_j
-    __shared__ R s_e[kWavesPerWG][3][kBlock];  // field at j
+    using LT = typename LdsField<FIX>::T;
+    constexpr int NV = K::NV;
+    __shared__ R4 s_ip[kBlock];                      // i offset from the block origin, w = alpha^-1/6
+    __shared__ R4 s_id[NV][kBlock];                  // i source data
+    __shared__ R4 s_jp[kWavesPerWG][kBlock];         // j offset from the i-block origin, w = alpha^-1/6
+    __shared__ R4 s_jd[kWavesPerWG][NV][kBlock];
+    __shared__ LT s_ei[3][kBlock];                   // block i-field over all tiles
+    __shared__ LT s_ej[kWavesPerWG][3][kBlock];      // tile j-field
+    __shared__ unsigned long long s_mask[kWavesPerWG][kBlock];
+    __shared__ int s_off[kWavesPerWG][kBlock];
     if (use_done && sc->done)
         return;
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int t = blockIdx.x * kWavesPerWG + w;
-    const bool act = t < ntiles;
-    const int I = act ? tile_blk[t] : 0;
-    const int si = I * kBlock + lane;
-    R4 oi = off[si], pi = par[si], mi = pv[si];
-    int sj = act ? tile_j[(size_t)t * kBlock + lane] : -1;
-    R4 jr = act ? jrel[(size_t)t * kBlock + lane] : R4{0, 0, 0, 0};
-    R4 mj{0, 0, 0, 0};
-    R dj = 0, aj = 0;
-    if (sj >= 0) {
-        mj = pv[sj];
-        R4 pj = par[sj];
-        dj = pj.z;
-        aj = pj.w;
+    const int I = blockIdx.x;
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+    const int t0 = blk_tile0[I], nt = blk_tile0[I + 1] - t0;
+    if (tid < kBlock) {
+        const int si = I * kBlock + tid;
+        const R4 oi = off[si], pi = par[si];
+        s_ip[tid] = R4{oi.x, oi.y, oi.z, pi.z};
+        R4 d[NV];
+        K::load(src, si, pi.w, d);
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+            s_id[v][tid] = d[v];
     }
-    s_pos[w][lane] = R4{jr.x, jr.y, jr.z, dj};
-    s_mu[w][lane] = R4{mj.x, mj.y, mj.z, aj};
-    s_e[w][0][lane] = 0;
-    s_e[w][1][lane] = 0;
-    s_e[w][2][lane] = 0;
-    const unsigned long long m = act ? tile_mask[(size_t)t * kBlock + lane] : 0ull;
-    __syncthreads();
-    R eix = 0, eiy = 0, eiz = 0;
-    const R di = pi.z, ai = pi.w;
-    for (int s = 0; s < kBlock; ++s) {
-        const int k = (lane + s) & 63;
-        if ((m >> k) & 1ull) {
-            R4 pj = s_pos[w][k];
-            R4 uj = s_mu[w][k];
-            R dx = oi.x - pj.x, dy = oi.y - pj.y, dz = oi.z - pj.z;
-            dx -= ew.L[0] * d_rint(dx * ew.Linv[0]);
-            dy -= ew.L[1] * d_rint(dy * ew.Linv[1]);
-            dz -= ew.L[2] * d_rint(dz * ew.Linv[2]);
-            R r2 = dx * dx + dy * dy + dz * dz;
-            R rinv = d_rsqrt(r2);
-            R r = r2 * rinv;
-            R rinv2 = rinv * rinv;
-            R gb = ew.g * d_exp(-ew.beta2 * r2);
-            R b0 = d_erfc(ew.beta * r) * rinv;
-            R b1 = (b0 + gb) * rinv2;
-            R b2 = ((R)3 * b1 + ew.t * gb) * rinv2;
-            R a = ai < uj.w ? ai : uj.w;
-            R u = r * di * pj.w;
-            R eps = a * u * u * u;
-            R ex = d_exp(-eps);
-            R rinv3 = rinv * rinv2;
-            R b1p = b1 - ex * rinv3;
-            R b2p = b2 - (R)3 * ((R)1 + eps) * ex * rinv3 * rinv2;
-            R mjd = uj.x * dx + uj.y * dy + uj.z * dz;
-            R mid = mi.x * dx + mi.y * dy + mi.z * dz;
-            eix += -b1p * uj.x + b2p * mjd * dx;
-            eiy += -b1p * uj.y + b2p * mjd * dy;
-            eiz += -b1p * uj.z + b2p * mjd * dz;
-            s_e[w][0][k] += -b1p * mi.x + b2p * mid * dx;
-            s_e[w][1][k] += -b1p * mi.y + b2p * mid * dy;
-            s_e[w][2][k] += -b1p * mi.z + b2p * mid * dz;
+    if (tid < 3 * kBlock)
+        s_ei[tid / kBlock][tid % kBlock] = (LT)0;
+    __syncthreads();  // block i data and accumulators ready
+    // Each wave walks its own share of the block's tiles (tt = w, w + 4, ...); its tile
+    // buffers are private, so only wave-level ordering is needed between staging and use (LDS
+    // operations of a wave complete in order; the wave barrier keeps the compiler from moving
+    // them across).
+    for (int tt = w; tt < nt; tt += kWavesPerWG) {
+        const int t = t0 + tt;
+        const int sj = tile_j[(size_t)t * kBlock + lane];
+        {
+            const R4 jr = jrel[(size_t)t * kBlock + lane];
+            R dj = 0, aj = 0;
+            R4 d[NV];
+#pragma unroll
+            for (int v = 0; v < NV; ++v)
+                d[v] = R4{0, 0, 0, 0};
+            if (sj >= 0) {
+                const R4 pj = par[sj];
+                dj = pj.z;
+                aj = pj.w;
+                K::load(src, sj, aj, d);
+            }
+            s_jp[w][lane] = R4{jr.x, jr.y, jr.z, dj};
+#pragma unroll
+            for (int v = 0; v < NV; ++v)
+                s_jd[w][v][lane] = d[v];
         }
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            s_ej[w][c][lane] = (LT)0;
+        const unsigned long long m = tile_mask[(size_t)t * kBlock + lane];
+        s_mask[w][lane] = m;
+        int P;
+        s_off[w][lane] = wave_excl_scan(__popcll(m), lane, P);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const int B = (P + 63) >> 6;
+        const int p0 = lane * B, p1 = min(p0 + B, P);
+        if (p0 < p1) {
+            int i;
+            unsigned long long rem;
+            walk_start(s_off[w], s_mask[w], p0, i, rem);
+            int cur = -1;
+            R4 ip{0, 0, 0, 0};
+            R4 di[NV];
+            R ea[3] = {0, 0, 0};
+            for (int p = p0; p < p1; ++p) {
+                while (rem == 0ull)
+                    rem = s_mask[w][++i];
+                const int k = __ffsll((long long)rem) - 1;
+                rem &= rem - 1ull;
+                if (i != cur) {
+                    if (cur >= 0)
+#pragma unroll
+                        for (int c = 0; c < 3; ++c)
+                            LdsField<FIX>::add(&s_ei[c][cur], ea[c]);
+                    cur = i;
+                    ip = s_ip[i];
+#pragma unroll
+                    for (int v = 0; v < NV; ++v)
+                        di[v] = s_id[v][i];
+                    ea[0] = ea[1] = ea[2] = 0;
+                }
+                R4 dj[NV];
+#pragma unroll
+                for (int v = 0; v < NV; ++v)
+                    dj[v] = s_jd[w][v][k];
+                R ei[3], ej[3];
+                K::pair(ip, di, s_jp[w][k], dj, ew, ei, ej);
+                ea[0] += ei[0];
+                ea[1] += ei[1];
+                ea[2] += ei[2];
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+                    LdsField<FIX>::add(&s_ej[w][c][k], ej[c]);
+            }
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                LdsField<FIX>::add(&s_ei[c][cur], ea[c]);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (tt == 0) {
+            // diagonal tile: its j-atoms are the block's own atoms
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                LdsField<FIX>::add_raw(&s_ei[c][lane], s_ej[w][c][lane]);
+        } else {
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                jbuf[((size_t)t * 3 + c) * kBlock + lane] = (R)LdsField<FIX>::value(s_ej[w][c][lane]);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
     __syncthreads();
-    if (!act)
-        return;
-    Acc<FIX>::add(&acc[3 * (size_t)si + 0], eix);
-    Acc<FIX>::add(&acc[3 * (size_t)si + 1], eiy);
-    Acc<FIX>::add(&acc[3 * (size_t)si + 2], eiz);
-    if (sj >= 0) {
-        Acc<FIX>::add(&acc[3 * (size_t)sj + 0], s_e[w][0][lane]);
-        Acc<FIX>::add(&acc[3 * (size_t)sj + 1], s_e[w][1][lane]);
-        Acc<FIX>::add(&acc[3 * (size_t)sj + 2], s_e[w][2][lane]);
+    if (tid < 3 * kBlock) {
+        const int c = tid / kBlock, l = tid % kBlock;
+        eipart[3 * ((size_t)I * kBlock + l) + c] = LdsField<FIX>::value(s_ei[c][l]);
     }
 }
 
-// ------------------------------------------------------------------------------------------
-// K3p: permanent multipole field tiles (once per configuration)
-// mp layout per slot: [3*s+0] = (q, dx, dy, dz), [3*s+1] = (Txx, Txy, Txz, Tyy), [3*s+2] = (Tyz, Tzz, 0, 0)
-// ------------------------------------------------------------------------------------------
-template <typename R, bool FIX>
-__global__ __launch_bounds__(256) void k_perm_tiles(int ntiles, const int* __restrict__ tile_blk,
-                                                    const int* __restrict__ tile_j,
-                                                    const unsigned long long* __restrict__ tile_mask,
-                                                    const typename V4<R>::T* __restrict__ jrel,
-                                                    const typename V4<R>::T* __restrict__ off,
-                                                    const typename V4<R>::T* __restrict__ par,
-                                                    const typename V4<R>::T* __restrict__ mp, EwaldArgs<R> ew,
-                                                    typename Acc<FIX>::T* __restrict__ acc)
+// E_real[s] = eipart[s] + sum of the jbuf slots of s in the reverse index (fixed order).
+template <typename R>
+__global__ void k_real_reduce(int npad, const double* __restrict__ eipart, const R* __restrict__ jbuf,
+                              const int* __restrict__ rev_ptr, const int* __restrict__ rev_idx,
+                              double* __restrict__ ereal)
 {
-    using R4 = typename V4<R>::T;
-    __shared__ R4 s_pos[kWavesPerWG][kBlock];
-    __shared__ R4 s_m0[kWavesPerWG][kBlock];
-    __shared__ R4 s_m1[kWavesPerWG][kBlock];
-    __shared__ R4 s_m2[kWavesPerWG][kBlock];
-    __shared__ R s_e[kWavesPerWG][3][kBlock];
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int t = blockIdx.x * kWavesPerWG + w;
-    const bool act = t < ntiles;
-    const int I = act ? tile_blk[t] : 0;
-    const int si = I * kBlock + lane;
-    const R4 oi = off[si], pi = par[si];
-    const R4 i0 = mp[3 * (size_t)si], i1 = mp[3 * (size_t)si + 1], i2 = mp[3 * (size_t)si + 2];
-    int sj = act ? tile_j[(size_t)t * kBlock + lane] : -1;
-    R4 jr = act ? jrel[(size_t)t * kBlock + lane] : R4{0, 0, 0, 0};
-    R4 j0{0, 0, 0, 0}, j1{0, 0, 0, 0}, j2{0, 0, 0, 0};
-    R dj = 0, aj = 0;
-    if (sj >= 0) {
-        j0 = mp[3 * (size_t)sj];
-        j1 = mp[3 * (size_t)sj + 1];
-        j2 = mp[3 * (size_t)sj + 2];
-        R4 pj = par[sj];
-        dj = pj.z;
-        aj = pj.w;
-    }
-    s_pos[w][lane] = R4{jr.x, jr.y, jr.z, dj};
-    s_m0[w][lane] = j0;
-    s_m1[w][lane] = j1;
-    s_m2[w][lane] = R4{j2.x, j2.y, aj, 0};
-    s_e[w][0][lane] = 0;
-    s_e[w][1][lane] = 0;
-    s_e[w][2][lane] = 0;
-    const unsigned long long m = act ? tile_mask[(size_t)t * kBlock + lane] : 0ull;
-    __syncthreads();
-    R eix = 0, eiy = 0, eiz = 0;
-    const R di = pi.z, ai = pi.w;
-    // i multipoles
-    const R qi = i0.x, dix = i0.y, diy = i0.z, diz = i0.w;
-    const R ixx = i1.x, ixy = i1.y, ixz = i1.z, iyy = i1.w, iyz = i2.x, izz = i2.y;
-    for (int s = 0; s < kBlock; ++s) {
-        const int k = (lane + s) & 63;
-        if ((m >> k) & 1ull) {
-            R4 pj = s_pos[w][k];
-            R4 a0 = s_m0[w][k], a1 = s_m1[w][k], a2 = s_m2[w][k];
-            R dx = oi.x - pj.x, dy = oi.y - pj.y, dz = oi.z - pj.z;
-            dx -= ew.L[0] * d_rint(dx * ew.Linv[0]);
-            dy -= ew.L[1] * d_rint(dy * ew.Linv[1]);
-            dz -= ew.L[2] * d_rint(dz * ew.Linv[2]);
-            R r2 = dx * dx + dy * dy + dz * dz;
-            R rinv = d_rsqrt(r2);
-            R r = r2 * rinv;
-            R rinv2 = rinv * rinv;
-            R gb = ew.g * d_exp(-ew.beta2 * r2);
-            R b0 = d_erfc(ew.beta * r) * rinv;
-            R b1 = (b0 + gb) * rinv2;
-            R b2 = ((R)3 * b1 + ew.t * gb) * rinv2;
-            R b3 = ((R)5 * b2 + ew.t2 * gb) * rinv2;
-            R a = ai < a2.z ? ai : a2.z;
-            R u = r * di * pj.w;
-            R eps = a * u * u * u;
-            R ex = d_exp(-eps);
-            R rinv3 = rinv * rinv2, rinv5 = rinv3 * rinv2, rinv7 = rinv5 * rinv2;
-            R b1p = b1 - ex * rinv3;
-            R b2p = b2 - (R)3 * ((R)1 + eps) * ex * rinv5;
-            R b3p = b3 - (R)15 * ((R)1 + eps + (R)0.6 * eps * eps) * ex * rinv7;
-            // field at i from j
-            {
-                R q = a0.x, ddx = a0.y, ddy = a0.z, ddz = a0.w;
-                R txx = a1.x, txy = a1.y, txz = a1.z, tyy = a1.w, tyz = a2.x, tzz = a2.y;
-                R tdx = txx * dx + txy * dy + txz * dz;
-                R tdy = txy * dx + tyy * dy + tyz * dz;
-                R tdz = txz * dx + tyz * dy + tzz * dz;
-                R tdd = tdx * dx + tdy * dy + tdz * dz;
-                R dd = ddx * dx + ddy * dy + ddz * dz;
-                R rad = q * b1p + b2p * dd + b3p * tdd * ((R)1 / (R)3);
-                R c2 = b2p * ((R)2 / (R)3);
-                eix += rad * dx - b1p * ddx - c2 * tdx;
-                eiy += rad * dy - b1p * ddy - c2 * tdy;
-                eiz += rad * dz - b1p * ddz - c2 * tdz;
-            }
-            // field at j from i (r -> -r)
-            {
-                R tdx = ixx * dx + ixy * dy + ixz * dz;
-                R tdy = ixy * dx + iyy * dy + iyz * dz;
-                R tdz = ixz * dx + iyz * dy + izz * dz;
-                R tdd = tdx * dx + tdy * dy + tdz * dz;
-                R dd = dix * dx + diy * dy + diz * dz;
-                R rad = -qi * b1p + b2p * dd - b3p * tdd * ((R)1 / (R)3);
-                R c2 = b2p * ((R)2 / (R)3);
-                s_e[w][0][k] += rad * dx - b1p * dix + c2 * tdx;
-                s_e[w][1][k] += rad * dy - b1p * diy + c2 * tdy;
-                s_e[w][2][k] += rad * dz - b1p * diz + c2 * tdz;
-            }
-        }
-    }
-    __syncthreads();
-    if (!act)
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= npad)
         return;
-    Acc<FIX>::add(&acc[3 * (size_t)si + 0], eix);
-    Acc<FIX>::add(&acc[3 * (size_t)si + 1], eiy);
-    Acc<FIX>::add(&acc[3 * (size_t)si + 2], eiz);
-    if (sj >= 0) {
-        Acc<FIX>::add(&acc[3 * (size_t)sj + 0], s_e[w][0][lane]);
-        Acc<FIX>::add(&acc[3 * (size_t)sj + 1], s_e[w][1][lane]);
-        Acc<FIX>::add(&acc[3 * (size_t)sj + 2], s_e[w][2][lane]);
+    double e0 = eipart[3 * (size_t)s], e1 = eipart[3 * (size_t)s + 1], e2 = eipart[3 * (size_t)s + 2];
+    for (int k = rev_ptr[s]; k < rev_ptr[s + 1]; ++k) {
+        const int e = rev_idx[k];
+        const size_t base = (size_t)(e >> 6) * 3 * kBlock + (e & 63);
+        e0 += (double)jbuf[base];
+        e1 += (double)jbuf[base + kBlock];
+        e2 += (double)jbuf[base + 2 * kBlock];
     }
-}
-
-static inline int nwg(long tiles) { return (int)((tiles + kWavesPerWG - 1) / kWavesPerWG); }
-
-void launch_zero_acc(amoeba_ctx* c)
-{
-    size_t bytes = sizeof(double) * 3 * (size_t)c->npad;  // same size for int64 and double
-    hipMemsetAsync(c->mixed ? (void*)c->acc_fx : (void*)c->acc_d, 0, bytes, c->stream);
+    ereal[3 * (size_t)s] = e0;
+    ereal[3 * (size_t)s + 1] = e1;
+    ereal[3 * (size_t)s + 2] = e2;
 }
 
 void launch_mutual_tiles(amoeba_ctx* c, bool use_done)
@@ -307,13 +411,23 @@ void launch_mutual_tiles(amoeba_ctx* c, bool use_done)
         return;
     StageTimer tm(c, AMOEBA_T_REAL);
     if (c->mixed)
-        hipLaunchKernelGGL((k_mutual_tiles<float, true>), dim3(nwg(c->ntiles)), dim3(256), 0, c->stream, c->ntiles,
-                           c->tile_blk, c->tile_j, c->tile_mask, c->jrel_f, c->off_f, c->par_f, c->pv_f,
-                           make_ewald<float>(c), c->acc_fx, c->sc, (int)use_done);
+        hipLaunchKernelGGL((k_block_tiles<float, true, DipoleKind<float>>), dim3(c->nb), dim3(256), 0, c->stream,
+                           c->nb, c->blk_tile0, c->tile_j, c->tile_mask, c->jrel_f, c->off_f, c->par_f, c->pv_f,
+                           make_ewald<float>(c), c->eipart, (float*)c->jbuf, c->sc, (int)use_done);
     else
-        hipLaunchKernelGGL((k_mutual_tiles<double, false>), dim3(nwg(c->ntiles)), dim3(256), 0, c->stream,
-                           c->ntiles, c->tile_blk, c->tile_j, c->tile_mask, c->jrel_d, c->off_d, c->par_d,
-                           c->pv_d, make_ewald<double>(c), c->acc_d, c->sc, (int)use_done);
+        hipLaunchKernelGGL((k_block_tiles<double, false, DipoleKind<double>>), dim3(c->nb), dim3(256), 0, c->stream,
+                           c->nb, c->blk_tile0, c->tile_j, c->tile_mask, c->jrel_d, c->off_d, c->par_d, c->pv_d,
+                           make_ewald<double>(c), c->eipart, (double*)c->jbuf, c->sc, (int)use_done);
+}
+
+void launch_real_reduce(amoeba_ctx* c, double* ereal)
+{
+    if (c->mixed)
+        hipLaunchKernelGGL(k_real_reduce<float>, dim3((c->npad + 255) / 256), dim3(256), 0, c->stream, c->npad,
+                           c->eipart, (const float*)c->jbuf, c->rev_ptr, c->rev_idx, ereal);
+    else
+        hipLaunchKernelGGL(k_real_reduce<double>, dim3((c->npad + 255) / 256), dim3(256), 0, c->stream, c->npad,
+                           c->eipart, (const double*)c->jbuf, c->rev_ptr, c->rev_idx, ereal);
 }
 
 void launch_perm_tiles(amoeba_ctx* c)
@@ -322,29 +436,28 @@ void launch_perm_tiles(amoeba_ctx* c)
         return;
     StageTimer tm(c, AMOEBA_T_PERM);
     if (c->mixed)
-        hipLaunchKernelGGL((k_perm_tiles<float, true>), dim3(nwg(c->ntiles)), dim3(256), 0, c->stream, c->ntiles,
-                           c->tile_blk, c->tile_j, c->tile_mask, c->jrel_f, c->off_f, c->par_f,
-                           (const float4*)c->mp_f, make_ewald<float>(c), c->acc_fx);
+        hipLaunchKernelGGL((k_block_tiles<float, true, MultipoleKind<float>>), dim3(c->nb), dim3(256), 0,
+                           c->stream, c->nb, c->blk_tile0, c->tile_j, c->tile_mask, c->jrel_f, c->off_f, c->par_f,
+                           (const float4*)c->mp_f, make_ewald<float>(c), c->eipart, (float*)c->jbuf, c->sc, 0);
     else
-        hipLaunchKernelGGL((k_perm_tiles<double, false>), dim3(nwg(c->ntiles)), dim3(256), 0, c->stream, c->ntiles,
-                           c->tile_blk, c->tile_j, c->tile_mask, c->jrel_d, c->off_d, c->par_d,
-                           (const double4*)c->mp_d, make_ewald<double>(c), c->acc_d);
+        hipLaunchKernelGGL((k_block_tiles<double, false, MultipoleKind<double>>), dim3(c->nb), dim3(256), 0,
+                           c->stream, c->nb, c->blk_tile0, c->tile_j, c->tile_mask, c->jrel_d, c->off_d, c->par_d,
+                           (const double4*)c->mp_d, make_ewald<double>(c), c->eipart, (double*)c->jbuf, c->sc, 0);
+    launch_real_reduce(c, c->ereal);
 }
 
 // ------------------------------------------------------------------------------------------
-// K4 + final assembly of E_perm (FP64): real-space accumulator + reciprocal field + dipole self
+// K4 + final assembly of E_perm (FP64): real-space field + reciprocal field + dipole self
 // field + the scaled-pair correction of every listed pair (at any separation):
 //   inside rc:  delta B_n = -c_n (1 - s) lambda_{2n+1} / r^{2n+1}   (tiles used s = 1)
 //   beyond rc:  delta B_n = -c_n (1 - s lambda_{2n+1}) / r^{2n+1}   (tiles skipped the pair)
 // ------------------------------------------------------------------------------------------
-__device__ __forceinline__ double mimg_d(double d, double L) { return d - L * rint(d / L); }
-
 __global__ void k_perm_assemble(int npad, const int* __restrict__ perm, const double4* __restrict__ pos_s,
                                 const double4* __restrict__ par, const double4* __restrict__ mp,
                                 const int* __restrict__ sc_ptr, const int* __restrict__ sc_j,
-                                const double* __restrict__ sc_s, const unsigned long long* __restrict__ acc_fx,
-                                const double* __restrict__ acc_d, const double* __restrict__ erec, double3 box,
-                                double rc2, double self, double* __restrict__ out, int* __restrict__ flags)
+                                const double* __restrict__ sc_s, const double* __restrict__ ereal,
+                                const double* __restrict__ erec, double3 box, double3 binv, double rc2, double self,
+                                double* __restrict__ out, int* __restrict__ flags)
 {
     int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= npad)
@@ -354,10 +467,8 @@ __global__ void k_perm_assemble(int npad, const int* __restrict__ perm, const do
         return;
     }
     double e[3];
-    for (int a = 0; a < 3; ++a) {
-        double ra = acc_fx ? (double)(long long)acc_fx[3 * (size_t)s + a] * kFixInv : acc_d[3 * (size_t)s + a];
-        e[a] = ra + erec[3 * (size_t)s + a];
-    }
+    for (int a = 0; a < 3; ++a)
+        e[a] = ereal[3 * (size_t)s + a] + erec[3 * (size_t)s + a];
     double4 m0 = mp[3 * (size_t)s];
     e[0] += self * m0.y;
     e[1] += self * m0.z;
@@ -367,7 +478,8 @@ __global__ void k_perm_assemble(int npad, const int* __restrict__ perm, const do
         int j = sc_j[k];
         double sf = sc_s[k];
         double4 pj = pos_s[j], parj = par[j];
-        double dx = mimg_d(pi.x - pj.x, box.x), dy = mimg_d(pi.y - pj.y, box.y), dz = mimg_d(pi.z - pj.z, box.z);
+        double dx = mimg_fp64(pi.x - pj.x, box.x, binv.x), dy = mimg_fp64(pi.y - pj.y, box.y, binv.y),
+               dz = mimg_fp64(pi.z - pj.z, box.z, binv.z);
         double r2 = dx * dx + dy * dy + dz * dz;
         bool in = r2 < rc2;
         double r = sqrt(r2);
@@ -408,9 +520,9 @@ void launch_perm_assemble(amoeba_ctx* c, double* out_slot)
     double b = c->prm.ewald_alpha;
     double self = 4.0 * b * b * b / (3.0 * sqrt(kPi));
     hipLaunchKernelGGL(k_perm_assemble, dim3((c->npad + 255) / 256), dim3(256), 0, c->stream, c->npad, c->perm,
-                       c->pos_s, c->par_d, (const double4*)c->mp_d, c->sc_ptr, c->sc_j, c->sc_s,
-                       c->mixed ? c->acc_fx : nullptr, c->mixed ? nullptr : c->acc_d, c->erec, box,
-                       c->prm.cutoff * c->prm.cutoff, self, out_slot, c->flags);
+                       c->pos_s, c->par_d, (const double4*)c->mp_d, c->sc_ptr, c->sc_j, c->sc_s, c->ereal, c->erec,
+                       box, make_double3(1.0 / box.x, 1.0 / box.y, 1.0 / box.z), c->prm.cutoff * c->prm.cutoff, self,
+                       out_slot, c->flags);
 }
 
 }  // namespace amoeba

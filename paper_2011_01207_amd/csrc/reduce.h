@@ -1,19 +1,22 @@
-// Deterministic grid-wide reductions in FP64 (paper, "Precision study and Validation": tree
-// reductions keep the rounding error logarithmic).  Each 256-thread workgroup reduces its
-// values in a fixed tree order and stores a partial; the workgroup that finishes last sums the
-// partials in index order and runs a finishing step on thread 0.  The result does not depend
-// on scheduling.
+// Deterministic FP64 reductions without device-wide fences or atomics (paper, "Precision study
+// and Validation": tree reductions keep the rounding error logarithmic).  A kernel reduces its
+// values per 256-thread workgroup in a fixed tree order and writes one partial per workgroup;
+// the next kernel of the stream sums the partials in index order (redundantly in every
+// workgroup that needs the total), so the result does not depend on scheduling and no
+// workgroup waits on another.
 #pragma once
 #include "common.h"
 
 namespace amoeba {
 
-template <int NV, typename Fin>
-__device__ __forceinline__ void grid_reduce(const double (&v)[NV], double* part, unsigned int* ticket, Fin fin)
+// Sum of NV values over the 256 threads of a workgroup, fixed tree order; every thread gets
+// the totals.  Must be reached by all threads of the workgroup.
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV])
 {
     __shared__ double sh[NV][256];
-    __shared__ int last;
     const int tid = threadIdx.x;
+    __syncthreads();
     for (int k = 0; k < NV; ++k)
         sh[k][tid] = v[k];
     __syncthreads();
@@ -23,39 +26,22 @@ __device__ __forceinline__ void grid_reduce(const double (&v)[NV], double* part,
                 sh[k][tid] += sh[k][tid + off];
         __syncthreads();
     }
-    if (tid == 0) {
-        for (int k = 0; k < NV; ++k)
-            part[(size_t)blockIdx.x * NV + k] = sh[k][0];
-        __threadfence();
-        unsigned int t = atomicAdd(ticket, 1u);
-        last = (t == gridDim.x - 1);
-    }
-    __syncthreads();
-    if (!last)
-        return;
-    __threadfence();
-    double acc[NV];
     for (int k = 0; k < NV; ++k)
-        acc[k] = 0.0;
-    for (unsigned b = tid; b < gridDim.x; b += 256)
-        for (int k = 0; k < NV; ++k)
-            acc[k] += ((volatile double*)part)[(size_t)b * NV + k];
-    for (int k = 0; k < NV; ++k)
-        sh[k][tid] = acc[k];
+        v[k] = sh[k][0];
     __syncthreads();
-    for (int off = 128; off > 0; off >>= 1) {
-        if (tid < off)
-            for (int k = 0; k < NV; ++k)
-                sh[k][tid] += sh[k][tid + off];
-        __syncthreads();
-    }
-    if (tid == 0) {
-        double tot[NV];
+}
+
+// Total of n partials of NV values each (layout [n][NV]), in a fixed order; every thread of
+// the workgroup gets the totals.
+template <int NV>
+__device__ __forceinline__ void sum_partials(const double* __restrict__ part, int n, double (&tot)[NV])
+{
+    for (int k = 0; k < NV; ++k)
+        tot[k] = 0.0;
+    for (int b = threadIdx.x; b < n; b += 256)
         for (int k = 0; k < NV; ++k)
-            tot[k] = sh[k][0];
-        fin(tot);
-        *ticket = 0u;
-    }
+            tot[k] += part[(size_t)b * NV + k];
+    block_sum<NV>(tot);
 }
 
 }  // namespace amoeba
