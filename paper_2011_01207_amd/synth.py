@@ -308,6 +308,20 @@ def trajectory(base: System, n_frames: int, step_sigma: float = 0.02, seed: int 
         yield np.mod(cur, base.box)
 
 
+def guess_init_model(seed: int = 7, n_feat: int = 11, hidden: int = 64, n_basis: int = 3) -> np.ndarray:
+    """Starting weights of the learned-guess network as one float32 model vector (layout
+    W1[hidden][n_feat], b1, W2[hidden][hidden], b2, W3[n_basis][hidden], b3, mean[n_feat],
+    inv_std[n_feat]): W1 and W2 drawn from N(0, 1/fan_in), every other entry zero, so the
+    untrained network returns the plain sum of its bases.  The normalisation entries are
+    filled by the feature-statistics fit before training."""
+    rng = _rng(seed)
+    w1 = rng.standard_normal((hidden, n_feat)) / np.sqrt(n_feat)
+    w2 = rng.standard_normal((hidden, hidden)) / np.sqrt(hidden)
+    parts = [w1.ravel(), np.zeros(hidden), w2.ravel(), np.zeros(hidden), np.zeros(n_basis * hidden),
+             np.zeros(n_basis), np.zeros(n_feat), np.ones(n_feat)]
+    return np.concatenate(parts).astype(np.float32)
+
+
 def tiny_cell(n_atoms: int, box_len: float, seed: int, min_dist: float = 0.0,
               with_multipoles: bool = True) -> System:
     """A few atoms at random positions in a small cubic box (rejection keeps them min_dist
