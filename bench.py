@@ -28,7 +28,7 @@ PEAK_HBM = 8000.0          # GB/s
 # Algorithmic FLOPs per in-cutoff pair of the real-space dipole kernel (FMA counted as 2; the
 # four transcendental calls rsqrt, exp, exp, erfc counted as one FLOP each).  See the design doc.
 FLOPS_PER_PAIR = 80
-STAGES = ["list", "perm", "real", "spread", "fft", "gather", "pcg"]
+STAGES = ["list", "perm", "real", "spread", "fft", "gather", "pcg", "guess"]
 
 
 def log(msg):
@@ -43,6 +43,7 @@ def parse():
     ap.add_argument("--tol", type=float, default=1e-5)
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle timing leg")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison leg")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-guess trajectory leg")
     return ap.parse_args()
 
 
@@ -53,8 +54,8 @@ def timing_dict(ctx):
     st = amoeba.lib().amoeba_get_timing(ctx.h, ctypes.byref(t))
     if st != 0:
         raise RuntimeError("amoeba_get_timing failed")
-    return {"ms": {STAGES[i]: t.ms[i] for i in range(7)},
-            "launches": {STAGES[i]: int(t.launches[i]) for i in range(7)}, "matvecs": int(t.matvecs)}
+    return {"ms": {STAGES[i]: t.ms[i] for i in range(len(STAGES))},
+            "launches": {STAGES[i]: int(t.launches[i]) for i in range(len(STAGES))}, "matvecs": int(t.matvecs)}
 
 
 def run_variant(s, t, precision, steps, warmup, tol, timing=True):
@@ -77,15 +78,20 @@ def run_variant(s, t, precision, steps, warmup, tol, timing=True):
     for _ in range(warmup):
         step()
     torch.cuda.synchronize()
-    amoeba.lib().amoeba_set_timing(ctx.h, 1 if timing else 0)
-    torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
         ep, it = step()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    tim = timing_dict(ctx) if timing else None
-    amoeba.lib().amoeba_set_timing(ctx.h, 0)
+    tim = None
+    if timing:
+        # a second pass of the same steps with every launch bracketed by HIP events on the
+        # library's stream (the per-stage kernel times of the roofline); not part of `value`
+        amoeba.lib().amoeba_set_timing(ctx.h, 1)
+        for _ in range(steps):
+            step()
+        tim = timing_dict(ctx)
+        amoeba.lib().amoeba_set_timing(ctx.h, 0)
     # solve-only rate (list and E_perm given), untimed by the stage timers
     torch.cuda.synchronize()
     u0 = time.perf_counter()
@@ -97,6 +103,93 @@ def run_variant(s, t, precision, steps, warmup, tol, timing=True):
     out = {"step_ms": 1e3 * (t1 - t0) / steps, "solve_only_ms": 1e3 * (u1 - u0) / steps, "iterations": it,
            "e_pol_kcal": ep, "n_pairs": info["n_pairs"], "n_tiles": info["n_tiles"], "n_blocks": info["n_blocks"],
            "timing": tim, "mu": mu.clone(), "e_perm": e_perm.clone()}
+    ctx.close()
+    return out
+
+
+def learned_leg(s, t, steps, tol, n_train=8, n_eval=4, train_steps=600, batch=16384):
+    """Mixed precision on a 0.02 A-step trajectory of the same box: the network is trained on
+    the solver's own converged dipoles of the first n_train configurations (GPU kernels), then
+    the next n_eval configurations are solved from the zero, previous-step, learned and judged
+    (learned vs previous-step) starts.  One step = list + E_perm + solve, as in the main leg."""
+    import numpy as np
+    import torch
+    from paper_2011_01207_amd import amoeba, synth
+    frames = list(synth.trajectory(s, n_train + n_eval + 1, 0.02, seed=204))
+    ctx = amoeba.Context(s.n, s.box, cutoff=s.cutoff, buffer=s.buffer, ewald_alpha=s.ewald_alpha, grid=s.grid,
+                         order=s.order, precision="mixed")
+    ctx.set_atoms(t["alpha"], t["thole"], t["sc_ptr"], t["sc_j"], t["sc_s"])
+    data = []
+    t0 = time.perf_counter()
+    for p in frames:
+        pos = torch.tensor(p, device=t["pos"].device)
+        ctx.build_blocklist(pos)
+        e = ctx.perm_field(pos, t["q"], t["dip"], t["quad"])
+        mu, _, _, st = ctx.polarize(pos, e, tol_debye=1e-6, max_iter=1000)
+        if st != amoeba.AMOEBA_OK:
+            raise RuntimeError("reference solve did not converge")
+        feat, basis = ctx.guess_features(pos, e)
+        data.append({"pos": pos, "e": e, "mu": mu.clone(), "feat": feat, "basis": basis})
+    torch.cuda.synchronize()
+    t_data = time.perf_counter() - t0
+    tr = data[1:n_train + 1]
+    feat = torch.cat([d["feat"] for d in tr])
+    basis = torch.cat([d["basis"] for d in tr])
+    target = torch.cat([d["mu"] for d in tr]).float()
+    ctx.guess_set_model(synth.guess_init_model(seed=7))
+    ctx.guess_fit_norm(feat)
+    rng = np.random.default_rng(5)
+    t0 = time.perf_counter()
+    losses = []
+    for k in range(train_steps):
+        idx = torch.tensor(rng.integers(0, feat.shape[0], batch).astype(np.int32), device=feat.device)
+        losses.append(ctx.guess_train_step(feat, basis, target, 2e-3, idx=idx))
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    ev = data[n_train + 1:]
+    prevs = [data[n_train + k]["mu"] for k in range(n_eval)]
+    out = {"train_configs": n_train, "eval_configs": n_eval, "train_samples": int(feat.shape[0]),
+           "train_steps": train_steps, "batch": batch, "loss_first_d2": float(np.mean(losses[:20])),
+           "loss_last_d2": float(np.mean(losses[-20:])), "reference_solves_s": t_data, "train_s": t_train,
+           "guess_rms_err_debye": float(np.mean([
+               4.80320 * float(torch.sqrt(torch.sum((ctx.guess_forward(d["feat"], d["basis"]).double() - d["mu"]) ** 2)
+                                          / s.n)) for d in ev])),
+           "prev_rms_err_debye": float(np.mean([
+               4.80320 * float(torch.sqrt(torch.sum((prevs[k] - ev[k]["mu"]) ** 2) / s.n)) for k in range(n_eval)])),
+           "modes": {}}
+    mu = torch.empty_like(t["pos"])
+    e_buf = torch.empty_like(t["pos"])
+    for mode in ("zero", "given", "learned", "best"):
+        def step(k):
+            d = ev[k % n_eval]
+            ctx.build_blocklist(d["pos"])
+            ctx.perm_field(d["pos"], t["q"], t["dip"], t["quad"], out=e_buf)
+            g = prevs[k % n_eval] if mode in ("given", "best") else None
+            _, _, it, st = ctx.polarize(d["pos"], e_buf, mu_guess=g, guess_mode=mode, tol_debye=tol, max_iter=1000,
+                                        out=mu)
+            if st != amoeba.AMOEBA_OK:
+                raise RuntimeError(f"{mode} solve did not converge")
+            return it
+        for k in range(2):
+            step(k)
+        torch.cuda.synchronize()
+        its, picks = [], []
+        t0 = time.perf_counter()
+        for k in range(steps):
+            its.append(step(k))
+            picks.append(ctx.info()["last_guess"])
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0) / steps
+        amoeba.lib().amoeba_set_timing(ctx.h, 1)
+        for k in range(steps):
+            step(k)
+        tim = timing_dict(ctx)
+        amoeba.lib().amoeba_set_timing(ctx.h, 0)
+        name = {"given": "previous_step"}.get(mode, mode)
+        out["modes"][name] = {"step_ms": ms, "solves_per_s": 1e3 / ms, "mean_iterations": float(np.mean(its)),
+                              "learned_picked": int(sum(1 for p in picks if p == amoeba.AMOEBA_GUESS_LEARNED)),
+                              "kernel_ms_per_step": {k: v / steps for k, v in tim["ms"].items()},
+                              "matvecs_per_step": tim["matvecs"] / steps}
     ctx.close()
     return out
 
@@ -246,6 +339,15 @@ def main():
             "e_pol_abs_kcal": abs(mixed["e_pol_kcal"] - fp64["e_pol_kcal"]),
             "e_pol_rel": abs(mixed["e_pol_kcal"] - fp64["e_pol_kcal"]) / abs(fp64["e_pol_kcal"]),
         }
+    if not a.no_learned:
+        log("learned-guess leg (trajectory, training on the GPU)")
+        lg = learned_leg(s, t, a.steps, a.tol)
+        if fp64 is not None:
+            for v in lg["modes"].values():
+                v["speedup_vs_fp64_zero_guess"] = fp64["step_ms"] / v["step_ms"]
+        res["learned_guess"] = lg
+        log("learned: " + ", ".join(f"{k} {v['step_ms']:.3f} ms {v['mean_iterations']:.1f} it"
+                                    for k, v in lg["modes"].items()))
     if not a.no_cpu_baseline:
         log("cpu baseline (oracle)")
         res["cpu_baseline"] = cpu_baseline(s, fp64["iterations"] if fp64 else mixed["iterations"])

@@ -95,6 +95,11 @@ typedef struct amoeba_info {
     int64_t workspace_bytes;   /* device memory held by the context                             */
     int32_t last_iterations;   /* PCG iterations of the last amoeba_polarize                    */
     double last_rms_debye;     /* final preconditioned-residual rms of the last solve (D)      */
+    int32_t last_guess;        /* starting point the last solve used: an amoeba_guess_mode
+                                  (ZERO, GIVEN or LEARNED; BEST resolves to one of them)        */
+    int32_t guess_loaded;      /* 1 once amoeba_guess_set_model has been called                 */
+    double last_guess_rms_debye[2]; /* AMOEBA_GUESS_BEST: rms of alpha r0 (D) of the fallback
+                                  (zero or given) [0] and of the learned guess [1]; else 0    */
 } amoeba_info;
 
 /* Create a context for one system size and one parameter set on the current HIP device,
@@ -161,6 +166,79 @@ int amoeba_polarize(amoeba_ctx* ctx, const double* pos, const double* e_perm,
                     const double* mu_guess, int32_t guess_mode, double tol_debye, int32_t max_iter,
                     double* mu_out, double* e_pol_out, int32_t* iters_out);
 
+/* ------------------------------------------------------------------------------------------
+ * Learned initial guess (an addition to the paper's method: the paper starts PCG from a plain
+ * guess).  A small per-atom network over neighbour-list environment features predicts the
+ * induced dipoles; amoeba_polarize can start from its prediction (AMOEBA_GUESS_LEARNED) or from
+ * whichever of the prediction and the zero / given guess has the smaller preconditioned
+ * initial residual (AMOEBA_GUESS_BEST).  PCG always converges to the same tolerance, so the
+ * guess changes the iteration count, never the accepted accuracy.
+ *
+ * Bases (e*A, per atom), with R the real-space Thole-damped Ewald dipole field over the
+ * in-cutoff pairs (the real-space part of T) and c = 4 beta^3 / (3 sqrt(pi)):
+ *     v0 = alpha E_perm,  v1 = alpha (R[v0] + c v0),  v2 = alpha (R[v1] + c v1)
+ * (the first terms of the Neumann series of (alpha^-1 - T)^-1 E_perm without the reciprocal
+ * part).  Invariant features x[AMOEBA_GUESS_NFEAT]:
+ *     alpha, Thole a, D|v0|, D|v1|, D|v2| (D = 4.80320 Debye per e*A),
+ *     cos(v0,v1), cos(v0,v2), cos(v1,v2) with cos(a,b) = a.b / sqrt(|a|^2 |b|^2 + 1e-20),
+ *     sum over in-cutoff neighbours of exp(-((r - c_k) / 0.6 A)^2) for c_k = 1, 2, 3 A.
+ * Network (FP32): xh = (x - mean) * inv_std; h1 = silu(W1 xh + b1); h2 = silu(W2 h1 + b2);
+ * y = W3 h2 + b3; mu0 = sum_k (1 + y_k) v_k.  Loss of a batch of n samples:
+ * L = D^2 / n * sum_i |mu0_i - target_i|^2 (Debye^2).  Optimiser: Adam (beta1 0.9, beta2 0.999,
+ * eps 1e-8, bias-corrected).
+ *
+ * Model vector (FP32, AMOEBA_GUESS_NMODEL floats, row-major): W1[64][11], b1[64], W2[64][64],
+ * b2[64], W3[3][64], b3[3], mean[11], inv_std[11].  The first AMOEBA_GUESS_NPARAM entries are
+ * trained; the last 2*NFEAT are set by amoeba_guess_fit_norm.
+ *
+ * Training-set arrays are caller-owned device memory in sample order: feat[n][NFEAT] FP32,
+ * basis[n][NBASIS][3] FP32 (e*A), target[n][3] FP32 (e*A).  Batches are either the first n_batch
+ * rows (idx NULL) or the rows idx[0..n_batch) (int32 device array; every entry must lie in
+ * [0, n_rows), else AMOEBA_E_INVALID).  Sums over samples run in a fixed order, so every call
+ * is bitwise reproducible.
+ * ---------------------------------------------------------------------------------------- */
+#define AMOEBA_GUESS_NFEAT 11
+#define AMOEBA_GUESS_NBASIS 3
+#define AMOEBA_GUESS_HIDDEN 64
+#define AMOEBA_GUESS_NPARAM 5123   /* 64*11 + 64 + 64*64 + 64 + 3*64 + 3 */
+#define AMOEBA_GUESS_NMODEL 5145   /* NPARAM + 2*NFEAT                   */
+
+/* Load a model (host array of n_floats == AMOEBA_GUESS_NMODEL floats); resets the Adam
+ * moments and step count.  The first call allocates the guess workspace. */
+int amoeba_guess_set_model(amoeba_ctx* ctx, const float* model, int64_t n_floats);
+
+/* Copy the current model to a host array of n_floats == AMOEBA_GUESS_NMODEL floats. */
+int amoeba_guess_get_model(amoeba_ctx* ctx, float* model, int64_t n_floats);
+
+/* Bases and features of one configuration (positions pos, permanent field e_perm, the list
+ * built): feat_out[N][NFEAT] and basis_out[N][NBASIS][3] (device FP32, caller atom order). */
+int amoeba_guess_features(amoeba_ctx* ctx, const double* pos, const double* e_perm,
+                          float* feat_out, float* basis_out);
+
+/* Set the model's mean and inv_std from the first n_rows rows of feat (population standard
+ * deviation; inv_std = 0 where it is <= 1e-6).  Needs a loaded model. */
+int amoeba_guess_fit_norm(amoeba_ctx* ctx, const float* feat, int64_t n_rows);
+
+/* mu_out[n][3] (device FP32, e*A) = the network's prediction for the n rows of feat/basis. */
+int amoeba_guess_forward(amoeba_ctx* ctx, const float* feat, const float* basis, int64_t n,
+                         float* mu_out);
+
+/* Loss and gradient of a batch without changing the model: grad_out[NPARAM] (device FP32),
+ * *loss_out (host, Debye^2). */
+int amoeba_guess_gradient(amoeba_ctx* ctx, const float* feat, const float* basis,
+                          const float* target, int64_t n_rows, const int32_t* idx, int64_t n_batch,
+                          float* grad_out, double* loss_out);
+
+/* One Adam step with learning rate lr on a batch; *loss_out (host, may be NULL) is the batch
+ * loss before the step. */
+int amoeba_guess_train_step(amoeba_ctx* ctx, const float* feat, const float* basis,
+                            const float* target, int64_t n_rows, const int32_t* idx,
+                            int64_t n_batch, float lr, double* loss_out);
+
+/* The learned guess for one configuration: mu0_out[N][3] (device FP64, caller order), the
+ * starting point amoeba_polarize uses with AMOEBA_GUESS_LEARNED. */
+int amoeba_guess_predict(amoeba_ctx* ctx, const double* pos, const double* e_perm, double* mu0_out);
+
 /* Sizes and counters of the context (host struct). */
 int amoeba_get_info(const amoeba_ctx* ctx, amoeba_info* out);
 
@@ -178,7 +256,9 @@ typedef enum amoeba_stage {
     AMOEBA_T_FFT = 4,      /* forward FFT + influence product + backward FFT                */
     AMOEBA_T_GATHER = 5,   /* PME gather fused with the operator assembly and p.Ap          */
     AMOEBA_T_PCG = 6,      /* PCG vector updates and reductions                             */
-    AMOEBA_T_COUNT = 7
+    AMOEBA_T_GUESS = 7,    /* learned guess: features, network, training kernels (the
+                              real-space products of its bases count under AMOEBA_T_REAL)     */
+    AMOEBA_T_COUNT = 8
 } amoeba_stage;
 
 typedef struct amoeba_timing {

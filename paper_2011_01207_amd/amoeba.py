@@ -33,6 +33,14 @@ AMOEBA_GUESS_ZERO = 0
 AMOEBA_GUESS_GIVEN = 1
 AMOEBA_GUESS_LEARNED = 2
 AMOEBA_GUESS_BEST = 3
+GUESS_NAMES = {0: "zero", 1: "given", 2: "learned", 3: "best"}
+
+GUESS_NFEAT = 11
+GUESS_NBASIS = 3
+GUESS_HIDDEN = 64
+GUESS_NPARAM = 5123
+GUESS_NMODEL = 5145
+N_STAGES = 8
 
 
 class amoeba_params(ctypes.Structure):
@@ -44,11 +52,14 @@ class amoeba_params(ctypes.Structure):
 class amoeba_info(ctypes.Structure):
     _fields_ = [("n_atoms", ctypes.c_int32), ("n_blocks", ctypes.c_int32), ("n_tiles", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("n_pairs", ctypes.c_int64), ("workspace_bytes", ctypes.c_int64),
-                ("last_iterations", ctypes.c_int32), ("last_rms_debye", ctypes.c_double)]
+                ("last_iterations", ctypes.c_int32), ("last_rms_debye", ctypes.c_double),
+                ("last_guess", ctypes.c_int32), ("guess_loaded", ctypes.c_int32),
+                ("last_guess_rms_debye", ctypes.c_double * 2)]
 
 
 class amoeba_timing(ctypes.Structure):
-    _fields_ = [("ms", ctypes.c_double * 7), ("launches", ctypes.c_int64 * 7), ("matvecs", ctypes.c_int64)]
+    _fields_ = [("ms", ctypes.c_double * N_STAGES), ("launches", ctypes.c_int64 * N_STAGES),
+                ("matvecs", ctypes.c_int64)]
 
 
 class AmoebaError(RuntimeError):
@@ -83,6 +94,17 @@ def lib() -> ctypes.CDLL:
         L.amoeba_polarize.argtypes = [_P, _P, _P, _P, ctypes.c_int32, ctypes.c_double, ctypes.c_int32, _P,
                                       ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32)]
         L.amoeba_get_info.argtypes = [_P, ctypes.POINTER(amoeba_info)]
+        _fp = ctypes.POINTER(ctypes.c_float)
+        L.amoeba_guess_set_model.argtypes = [_P, _fp, ctypes.c_int64]
+        L.amoeba_guess_get_model.argtypes = [_P, _fp, ctypes.c_int64]
+        L.amoeba_guess_features.argtypes = [_P, _P, _P, _P, _P]
+        L.amoeba_guess_fit_norm.argtypes = [_P, _P, ctypes.c_int64]
+        L.amoeba_guess_forward.argtypes = [_P, _P, _P, ctypes.c_int64, _P]
+        L.amoeba_guess_gradient.argtypes = [_P, _P, _P, _P, ctypes.c_int64, _P, ctypes.c_int64, _P,
+                                            ctypes.POINTER(ctypes.c_double)]
+        L.amoeba_guess_train_step.argtypes = [_P, _P, _P, _P, ctypes.c_int64, _P, ctypes.c_int64, ctypes.c_float,
+                                              ctypes.POINTER(ctypes.c_double)]
+        L.amoeba_guess_predict.argtypes = [_P, _P, _P, _P]
         L.amoeba_set_timing.argtypes = [_P, ctypes.c_int]
         L.amoeba_get_timing.argtypes = [_P, ctypes.POINTER(amoeba_timing)]
         _lib = L
@@ -186,8 +208,12 @@ class Context:
         return er, ek
 
     def polarize(self, pos, e_perm, mu_guess=None, guess_mode=None, tol_debye=1e-5, max_iter=500, out=None):
-        """Returns (mu, e_pol kcal/mol, iterations, status); status is OK or NOT_CONVERGED."""
+        """Returns (mu, e_pol kcal/mol, iterations, status); status is OK or NOT_CONVERGED.
+        guess_mode: None (zero, or given when mu_guess is passed), an AMOEBA_GUESS_* value or one
+        of "zero", "given", "learned", "best"."""
         n = self.n
+        if isinstance(guess_mode, str):
+            guess_mode = {v: k for k, v in GUESS_NAMES.items()}[guess_mode]
         if guess_mode is None:
             guess_mode = AMOEBA_GUESS_ZERO if mu_guess is None else AMOEBA_GUESS_GIVEN
         out = torch.empty((n, 3), dtype=torch.float64, device=pos.device) if out is None else out
@@ -203,7 +229,83 @@ class Context:
     def info(self) -> dict:
         inf = amoeba_info()
         self._check(lib().amoeba_get_info(self.h, ctypes.byref(inf)))
-        return {k: getattr(inf, k) for k, _ in amoeba_info._fields_}
+        out = {k: getattr(inf, k) for k, _ in amoeba_info._fields_}
+        out["last_guess_rms_debye"] = tuple(out["last_guess_rms_debye"])
+        return out
+
+    # learned initial guess ------------------------------------------------------------------
+    def guess_set_model(self, model):
+        """model: host float32 array-like of GUESS_NMODEL entries."""
+        import numpy as np
+        m = np.ascontiguousarray(np.asarray(model, dtype=np.float32).ravel())
+        return self._check(lib().amoeba_guess_set_model(
+            self.h, m.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), m.size))
+
+    def guess_get_model(self):
+        import numpy as np
+        m = np.empty(GUESS_NMODEL, dtype=np.float32)
+        self._check(lib().amoeba_guess_get_model(self.h, m.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), m.size))
+        return m
+
+    def guess_features(self, pos, e_perm, feat=None, basis=None):
+        """(feat [N][NFEAT], basis [N][NBASIS][3]) FP32 on the device, caller order."""
+        n = self.n
+        feat = torch.empty((n, GUESS_NFEAT), dtype=torch.float32, device=pos.device) if feat is None else feat
+        basis = torch.empty((n, GUESS_NBASIS, 3), dtype=torch.float32, device=pos.device) if basis is None else basis
+        self._check(lib().amoeba_guess_features(
+            self.h, _ptr(pos, torch.float64, (n, 3), "pos"), _ptr(e_perm, torch.float64, (n, 3), "e_perm"),
+            _ptr(feat, torch.float32, (n, GUESS_NFEAT), "feat"),
+            _ptr(basis, torch.float32, (n, GUESS_NBASIS, 3), "basis")))
+        return feat, basis
+
+    def guess_fit_norm(self, feat):
+        rows = int(feat.shape[0])
+        return self._check(lib().amoeba_guess_fit_norm(
+            self.h, _ptr(feat, torch.float32, (rows, GUESS_NFEAT), "feat"), rows))
+
+    def guess_forward(self, feat, basis, out=None):
+        rows = int(feat.shape[0])
+        out = torch.empty((rows, 3), dtype=torch.float32, device=feat.device) if out is None else out
+        self._check(lib().amoeba_guess_forward(
+            self.h, _ptr(feat, torch.float32, (rows, GUESS_NFEAT), "feat"),
+            _ptr(basis, torch.float32, (rows, GUESS_NBASIS, 3), "basis"), rows,
+            _ptr(out, torch.float32, (rows, 3), "mu_out")))
+        return out
+
+    def _batch_args(self, feat, basis, target, idx, n_batch):
+        rows = int(feat.shape[0])
+        if idx is not None:
+            n_batch = int(idx.numel())
+            ip = _ptr(idx, torch.int32, (n_batch,), "idx")
+        else:
+            n_batch = rows if n_batch is None else int(n_batch)
+            ip = None
+        return (_ptr(feat, torch.float32, (rows, GUESS_NFEAT), "feat"),
+                _ptr(basis, torch.float32, (rows, GUESS_NBASIS, 3), "basis"),
+                _ptr(target, torch.float32, (rows, 3), "target"), rows, ip, n_batch)
+
+    def guess_gradient(self, feat, basis, target, idx=None, n_batch=None):
+        """(loss in D^2, gradient [NPARAM] FP32 on the device) of a batch; the model is unchanged."""
+        g = torch.empty(GUESS_NPARAM, dtype=torch.float32, device=feat.device)
+        loss = ctypes.c_double(0.0)
+        self._check(lib().amoeba_guess_gradient(self.h, *self._batch_args(feat, basis, target, idx, n_batch),
+                                                g.data_ptr(), ctypes.byref(loss)))
+        return loss.value, g
+
+    def guess_train_step(self, feat, basis, target, lr, idx=None, n_batch=None):
+        """One Adam step; returns the batch loss (D^2) before the step."""
+        loss = ctypes.c_double(0.0)
+        self._check(lib().amoeba_guess_train_step(self.h, *self._batch_args(feat, basis, target, idx, n_batch),
+                                                  float(lr), ctypes.byref(loss)))
+        return loss.value
+
+    def guess_predict(self, pos, e_perm, out=None):
+        n = self.n
+        out = torch.empty((n, 3), dtype=torch.float64, device=pos.device) if out is None else out
+        self._check(lib().amoeba_guess_predict(self.h, _ptr(pos, torch.float64, (n, 3), "pos"),
+                                               _ptr(e_perm, torch.float64, (n, 3), "e_perm"),
+                                               _ptr(out, torch.float64, (n, 3), "mu0_out")))
+        return out
 
 
 def context_for(system, precision="fp64", device="cuda", **kw):

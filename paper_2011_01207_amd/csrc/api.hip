@@ -166,7 +166,7 @@ static inline int nblk(size_t n, int b) { return (int)((n + b - 1) / b); }
 
 int sort_params(amoeba_ctx* c);
 
-static int read_flags(amoeba_ctx* c, int* out)
+int read_flags(amoeba_ctx* c, int* out)
 {
     hipMemcpyAsync(c->flags_host, c->flags, sizeof(int), hipMemcpyDeviceToHost, c->stream);
     int rc = hip_check(c, hipStreamSynchronize(c->stream), "flags");
@@ -174,7 +174,7 @@ static int read_flags(amoeba_ctx* c, int* out)
     return rc;
 }
 
-static int check_vec_finite(amoeba_ctx* c, const double* v, size_t n, const char* what)
+int check_vec_finite(amoeba_ctx* c, const double* v, size_t n, const char* what)
 {
     hipMemsetAsync(c->flags, 0, sizeof(int), c->stream);
     hipLaunchKernelGGL(k_check_finite, dim3(nblk(n, 256)), dim3(256), 0, c->stream, n, v, c->flags);
@@ -210,6 +210,16 @@ static int check_overflow(amoeba_ctx* c, const double* v_slot)
     if (f & kFlagOverflow)
         return set_error(c, AMOEBA_E_OVERFLOW, "field outside the fixed-point range (|E| >= 4e6 e/A^2)");
     return AMOEBA_OK;
+}
+
+int begin_config(amoeba_ctx* c, const double* pos, const char* who)
+{
+    int rc = ready(c, who);
+    if (rc)
+        return rc;
+    if (!pos)
+        return set_error(c, AMOEBA_E_INVALID, std::string(who) + ": NULL pos");
+    return prepare_config(c, pos);
 }
 
 }  // namespace amoeba
@@ -368,6 +378,8 @@ int amoeba_destroy(amoeba_ctx* c)
         hipHostFree(c->sc_host);
     if (c->flags_host)
         hipHostFree(c->flags_host);
+    if (c->g_scal_host)
+        hipHostFree(c->g_scal_host);
     for (auto& e : c->ev)
         if (e)
             hipEventDestroy(e);
@@ -441,16 +453,6 @@ int amoeba_build_blocklist(amoeba_ctx* c, const double* pos)
     if (rc)
         c->list_built = false;
     return rc;
-}
-
-static int begin_config(amoeba_ctx* c, const double* pos, const char* who)
-{
-    int rc = ready(c, who);
-    if (rc)
-        return rc;
-    if (!pos)
-        return set_error(c, AMOEBA_E_INVALID, std::string(who) + ": NULL pos");
-    return prepare_config(c, pos);
 }
 
 int amoeba_perm_field(amoeba_ctx* c, const double* pos, const double* q, const double* dip, const double* quad,
@@ -558,21 +560,67 @@ int amoeba_polarize(amoeba_ctx* c, const double* pos, const double* e_perm, cons
         return set_error(c, AMOEBA_E_INVALID, "amoeba_polarize: unknown guess_mode");
     if (guess_mode == AMOEBA_GUESS_GIVEN && !mu_guess)
         return set_error(c, AMOEBA_E_INVALID, "amoeba_polarize: AMOEBA_GUESS_GIVEN needs mu_guess");
-    if (guess_mode == AMOEBA_GUESS_LEARNED || guess_mode == AMOEBA_GUESS_BEST)
-        return set_error(c, AMOEBA_E_STATE, "amoeba_polarize: no learned guess model loaded");
+    if ((guess_mode == AMOEBA_GUESS_LEARNED || guess_mode == AMOEBA_GUESS_BEST) && !c->guess_loaded)
+        return set_error(c, AMOEBA_E_STATE,
+                         "amoeba_polarize: no learned guess model loaded (amoeba_guess_set_model)");
     int rc = begin_config(c, pos, "amoeba_polarize");
     if (rc)
         return rc;
     if ((rc = check_vec_finite(c, e_perm, 3 * (size_t)c->n, "e_perm")))
         return rc;
     launch_gather_vec(c, e_perm, c->v_e);
-    bool have_guess = guess_mode == AMOEBA_GUESS_GIVEN;
-    if (have_guess) {
-        if ((rc = check_vec_finite(c, mu_guess, 3 * (size_t)c->n, "mu_guess")))
+    const bool given = mu_guess != nullptr && (guess_mode == AMOEBA_GUESS_GIVEN || guess_mode == AMOEBA_GUESS_BEST);
+    if (given && (rc = check_vec_finite(c, mu_guess, 3 * (size_t)c->n, "mu_guess")))
+        return rc;
+    c->last_guess_rms[0] = c->last_guess_rms[1] = 0.0;
+    int st;
+    if (guess_mode == AMOEBA_GUESS_ZERO || guess_mode == AMOEBA_GUESS_GIVEN) {
+        if (given)
+            launch_gather_vec(c, mu_guess, c->v_mu);
+        st = pcg_solve(c, tol_debye, max_iter, given);
+        c->last_guess = given ? AMOEBA_GUESS_GIVEN : AMOEBA_GUESS_ZERO;
+    } else if (guess_mode == AMOEBA_GUESS_LEARNED) {
+        if ((rc = guess_compute(c)))
             return rc;
-        launch_gather_vec(c, mu_guess, c->v_mu);
+        guess_forward_slot(c, c->v_mu);
+        st = pcg_solve(c, tol_debye, max_iter, true);
+        c->last_guess = AMOEBA_GUESS_LEARNED;
+    } else {
+        // The judge: the preconditioned initial residual of the fallback (zero or given) and of
+        // the learned guess; PCG starts from the smaller.  The fallback state is kept while
+        // the learned one is evaluated.
+        if ((rc = guess_compute(c)) || (rc = pcg_begin(c, tol_debye)))
+            return rc;
+        const size_t bytes = sizeof(double) * 3 * (size_t)c->npad;
+        double rms_f = 0.0, rms_l = 0.0;
+        if (given) {
+            launch_gather_vec(c, mu_guess, c->v_mu);
+            if ((rc = pcg_start(c, true, &rms_f)))
+                return rc;
+            hipMemcpyAsync(c->g_save_mu, c->v_mu, bytes, hipMemcpyDeviceToDevice, c->stream);
+            hipMemcpyAsync(c->g_save_q, c->v_q, bytes, hipMemcpyDeviceToDevice, c->stream);
+        } else if ((rc = pcg_start(c, false, &rms_f))) {
+            return rc;
+        }
+        guess_forward_slot(c, c->v_mu);
+        if ((rc = pcg_start(c, true, &rms_l)))
+            return rc;
+        const bool learned = rms_l < rms_f;
+        if (!learned) {
+            if (given) {
+                hipMemcpyAsync(c->v_mu, c->g_save_mu, bytes, hipMemcpyDeviceToDevice, c->stream);
+                rc = pcg_start_from(c, c->g_save_q, nullptr);
+            } else {
+                rc = pcg_start(c, false, nullptr);
+            }
+            if (rc)
+                return rc;
+        }
+        st = pcg_run(c, max_iter, given ? 2 : 1);
+        c->last_guess = learned ? AMOEBA_GUESS_LEARNED : (given ? AMOEBA_GUESS_GIVEN : AMOEBA_GUESS_ZERO);
+        c->last_guess_rms[0] = rms_f;
+        c->last_guess_rms[1] = rms_l;
     }
-    int st = pcg_solve(c, tol_debye, max_iter, have_guess);
     if (st < 0)
         return st;
     launch_scatter(c, c->v_mu, mu_out);
@@ -630,6 +678,10 @@ int amoeba_get_info(const amoeba_ctx* c, amoeba_info* out)
     out->workspace_bytes = c->ws_bytes;
     out->last_iterations = c->last_iters;
     out->last_rms_debye = c->last_rms;
+    out->last_guess = c->last_guess;
+    out->guess_loaded = c->guess_loaded ? 1 : 0;
+    out->last_guess_rms_debye[0] = c->last_guess_rms[0];
+    out->last_guess_rms_debye[1] = c->last_guess_rms[1];
     return AMOEBA_OK;
 }
 

@@ -34,6 +34,7 @@ enum : int {
     kFlagFilterOverflow = 64,
     kFlagBreakdown = 128,
     kFlagChanged = 256,
+    kFlagBadIndex = 512,
 };
 
 // FP32 value -> 64-bit fixed point with 40 fraction bits, rounded to nearest even (|v| < 2^23).
@@ -187,6 +188,27 @@ struct amoeba_ctx {
     int* b_cnt = nullptr;                  // [npad + 1] per-slot counts
     int* b_scan = nullptr;                 // [npad / 1024 + 2] scan block sums / offsets
 
+    // learned initial guess (guess.hip); allocated by the first amoeba_guess_set_model
+    bool guess_loaded = false;
+    float* g_model = nullptr;              // [NMODEL] parameters + mean + inv_std
+    float* g_adam_m = nullptr;             // [NPARAM] Adam first moment
+    float* g_adam_v = nullptr;             // [NPARAM] Adam second moment
+    int64_t g_step = 0;                    // Adam steps taken since the model was set
+    float* g_part = nullptr;               // [kGuessWG][NPARAM] per-workgroup gradient partials
+    double* g_lossp = nullptr;             // [kGuessWG] per-workgroup loss partials
+    double* g_scal = nullptr;              // [4] device scalars (loss)
+    double* g_scal_host = nullptr;         // pinned mirror
+    double* g_npart = nullptr;             // [kRedBlocks][NFEAT] normalisation partials
+    double* g_nmean = nullptr;             // [NFEAT]
+    double* g_v = nullptr;                 // [3][npad*3] bases v0, v1, v2 (slot order, FP64)
+    double* g_radial = nullptr;            // [npad*3] radial neighbour sums
+    float* g_feat = nullptr;               // [npad][NFEAT]
+    float* g_basis = nullptr;              // [npad][NBASIS*3]
+    double* g_save_mu = nullptr;           // [npad*3] fallback guess kept while the judge runs
+    double* g_save_q = nullptr;            // [npad*3] its A mu0
+    int last_guess = 0;
+    double last_guess_rms[2] = {0.0, 0.0};
+
     // stage timing (diagnostic)
     bool timing = false;
     std::vector<hipEvent_t> tev;                 // event pool
@@ -227,12 +249,25 @@ int pme_dipole_field(amoeba_ctx* c, bool use_done);   // spread p -> FFT -> conv
 int pme_perm_potential(amoeba_ctx* c);                // spread multipoles -> ... -> potential grid
 void launch_gather(amoeba_ctx* c, double* out);       // E_rec at atoms from the potential grid
 
+// api.hip
+int read_flags(amoeba_ctx* c, int* out);
+int check_vec_finite(amoeba_ctx* c, const double* v, size_t n, const char* what);
+int begin_config(amoeba_ctx* c, const double* pos, const char* who);
+
+// guess.hip
+int guess_compute(amoeba_ctx* c);                     // bases + features of v_e (slot order)
+void guess_forward_slot(amoeba_ctx* c, double* mu_slot);
+
 // pcg.hip
 void launch_gather_vec(amoeba_ctx* c, const double* src_caller, double* dst_slot);
 void launch_scatter(amoeba_ctx* c, const double* v_slot, double* out_caller);
 void launch_matvec_combine(amoeba_ctx* c, bool use_done, bool dot_pq);
 void launch_set_direction(amoeba_ctx* c, const double* src);
 int pcg_solve(amoeba_ctx* c, double tol, int max_iter, bool have_guess);
+int pcg_begin(amoeba_ctx* c, double tol);                          // initial device scalars
+int pcg_start(amoeba_ctx* c, bool have_guess, double* rms_debye);   // r0, z0, p0 from v_mu
+int pcg_start_from(amoeba_ctx* c, const double* q0, double* rms_debye); // same, A mu0 given
+int pcg_run(amoeba_ctx* c, int max_iter, int start_matvecs);        // iterate from r0, z0, p0
 double compute_epol(amoeba_ctx* c);
 int matvec_slot(amoeba_ctx* c, bool use_done, bool dot);
 

@@ -1,0 +1,859 @@
+// Learned initial guess of the induced dipoles: bases, features, the per-atom network and its
+// training (forward, backward, Adam).  This is an addition to the paper's method, which starts
+// its PCG from a plain guess; PCG still converges to the same tolerance from any start.
+//
+// Bases (slot order, FP64): v0 = alpha E_perm, v_{k+1} = alpha (R[v_k] + c v_k), with R the
+// real-space dipole field of the pair kernel (the same tiles and precision as a PCG product)
+// and c the Ewald self coefficient.  Invariant features: alpha, Thole a, |v_k| in Debye, the
+// three cosines between the bases, and three Gaussian-weighted neighbour counts over the
+// in-cutoff pairs of the tile list.  Network: SiLU MLP NFEAT -> 64 -> 64 -> NBASIS on the
+// vector ALU in FP32, mu0 = sum_k (1 + y_k) v_k.
+//
+// Weights are read at addresses that are the same for every lane, so they come through the
+// scalar unit and stay in the scalar cache; activations live in vector registers.  Training
+// sums every gradient over a fixed grid of one-wave workgroups in a fixed order and then over
+// the workgroups in index order, so gradients, losses and updates are bitwise reproducible.
+#include <algorithm>
+#include <cmath>
+
+#include "common.h"
+#include "reduce.h"
+
+namespace amoeba {
+
+template <typename R> struct V4R;
+template <> struct V4R<float> { using T = float4; };
+template <> struct V4R<double> { using T = double4; };
+template <typename R4T> struct Cast4G;
+template <> struct Cast4G<float4> {
+    __device__ static float4 make(double x, double y, double z) { return make_float4((float)x, (float)y, (float)z, 0.f); }
+};
+template <> struct Cast4G<double4> {
+    __device__ static double4 make(double x, double y, double z) { return make_double4(x, y, z, 0.0); }
+};
+
+constexpr int kNF = AMOEBA_GUESS_NFEAT;
+constexpr int kNB = AMOEBA_GUESS_NBASIS;
+constexpr int kH = AMOEBA_GUESS_HIDDEN;
+constexpr int kNP = AMOEBA_GUESS_NPARAM;
+constexpr int kNM = AMOEBA_GUESS_NMODEL;
+constexpr int kOffB1 = kH * kNF;
+constexpr int kOffW2 = kOffB1 + kH;
+constexpr int kOffB2 = kOffW2 + kH * kH;
+constexpr int kOffW3 = kOffB2 + kH;
+constexpr int kOffB3 = kOffW3 + kNB * kH;
+constexpr int kOffMean = kNP;
+constexpr int kOffInv = kNP + kNF;
+static_assert(kOffB3 + kNB == kNP, "parameter layout");
+static_assert(kNP + 2 * kNF == kNM, "model layout");
+constexpr int kGuessWG = 512;          // workgroups of the gradient kernel (at most)
+constexpr float kRadialC[3] = {1.0f, 2.0f, 3.0f};
+constexpr float kRadialInvW = 1.0f / 0.6f;
+
+__device__ __forceinline__ float sigm(float a) { return 1.0f / (1.0f + __expf(-a)); }
+
+static inline int nblk64(int64_t n, int b) { return (int)((n + b - 1) / b); }
+
+// ------------------------------------------------------------------------------------------
+// Radial neighbour sums over the tile list, one wave per i-block.  Lane l sums its row of
+// every tile of the block (pairs (l, k) with bit k set) and the tile's column l (pairs (i, l)
+// with bit l of row i set): rows accumulate in registers, columns of off-diagonal tiles go to
+// the tile's jbuf slot and are added to their atom by the reverse-index reduction, the
+// diagonal tile's column belongs to the block's own atom l.
+// ------------------------------------------------------------------------------------------
+template <typename R>
+__global__ __launch_bounds__(64) void k_guess_radial(const int* __restrict__ blk_tile0,
+                                                     const unsigned long long* __restrict__ tile_mask,
+                                                     const typename V4R<R>::T* __restrict__ jrel,
+                                                     const typename V4R<R>::T* __restrict__ off, R L0, R L1, R L2,
+                                                     R Li0, R Li1, R Li2, double* __restrict__ eipart,
+                                                     R* __restrict__ jbuf)
+{
+    using R4 = typename V4R<R>::T;
+    __shared__ R4 s_i[kBlock];
+    __shared__ R4 s_j[kBlock];
+    __shared__ unsigned long long s_m[kBlock];
+    const int I = blockIdx.x, lane = threadIdx.x;
+    const int si = I * kBlock + lane;
+    const R4 oi = off[si];
+    s_i[lane] = oi;
+    const int t0 = blk_tile0[I], t1 = blk_tile0[I + 1];
+    R row[3] = {0, 0, 0};
+    for (int t = t0; t < t1; ++t) {
+        __syncthreads();
+        s_j[lane] = jrel[(size_t)t * kBlock + lane];
+        s_m[lane] = tile_mask[(size_t)t * kBlock + lane];
+        __syncthreads();
+        unsigned long long m = s_m[lane];
+        while (m) {
+            const int k = __ffsll((long long)m) - 1;
+            m &= m - 1ull;
+            const R4 q = s_j[k];
+            R dx = oi.x - q.x, dy = oi.y - q.y, dz = oi.z - q.z;
+            dx -= L0 * rint(dx * Li0);
+            dy -= L1 * rint(dy * Li1);
+            dz -= L2 * rint(dz * Li2);
+            const R r = sqrt(dx * dx + dy * dy + dz * dz);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const R u = (r - (R)kRadialC[c]) * (R)kRadialInvW;
+                row[c] += exp(-u * u);
+            }
+        }
+        R col[3] = {0, 0, 0};
+        const R4 q = s_j[lane];
+        for (int i = 0; i < kBlock; ++i) {
+            if ((s_m[i] >> lane) & 1ull) {
+                const R4 p = s_i[i];
+                R dx = p.x - q.x, dy = p.y - q.y, dz = p.z - q.z;
+                dx -= L0 * rint(dx * Li0);
+                dy -= L1 * rint(dy * Li1);
+                dz -= L2 * rint(dz * Li2);
+                const R r = sqrt(dx * dx + dy * dy + dz * dz);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const R u = (r - (R)kRadialC[c]) * (R)kRadialInvW;
+                    col[c] += exp(-u * u);
+                }
+            }
+        }
+        if (t == t0) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                row[c] += col[c];
+        } else {
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                jbuf[((size_t)t * 3 + c) * kBlock + lane] = col[c];
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+        eipart[3 * (size_t)si + c] = (double)row[c];
+}
+
+// next basis vector: v = alpha (ereal + cself vprev), or v0 = alpha e when ereal is NULL; the
+// pair kernel's copy of it is written to pv for the following real-space product
+template <typename R4T>
+__global__ void k_guess_basis(int npad, const double4* __restrict__ par, const double* __restrict__ ereal,
+                              const double* __restrict__ vprev, double cself, double* __restrict__ vnext,
+                              R4T* __restrict__ pv)
+{
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= npad)
+        return;
+    const double al = par[s].x;
+    double v[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const double x = vprev[3 * (size_t)s + c];
+        v[c] = ereal ? al * (ereal[3 * (size_t)s + c] + cself * x) : al * x;
+        vnext[3 * (size_t)s + c] = v[c];
+    }
+    pv[s] = Cast4G<R4T>::make(v[0], v[1], v[2]);
+}
+
+// features and FP32 bases of every real atom, written at its slot (perm_out NULL) or at its
+// caller index (perm_out = perm); phantom slots get zeros in slot order
+__global__ void k_guess_features(int npad, const int* __restrict__ perm, const double4* __restrict__ par,
+                                 const double* __restrict__ v, const double* __restrict__ radial, int caller_order,
+                                 float* __restrict__ feat, float* __restrict__ basis)
+{
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= npad)
+        return;
+    const int a = perm[s];
+    if (a < 0) {
+        if (!caller_order) {
+            for (int f = 0; f < kNF; ++f)
+                feat[(size_t)s * kNF + f] = 0.0f;
+            for (int f = 0; f < kNB * 3; ++f)
+                basis[(size_t)s * kNB * 3 + f] = 0.0f;
+        }
+        return;
+    }
+    const size_t d = caller_order ? (size_t)a : (size_t)s;
+    const size_t n3 = 3 * (size_t)npad;
+    double b[kNB][3], nn[kNB];
+#pragma unroll
+    for (int k = 0; k < kNB; ++k) {
+        nn[k] = 0.0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            b[k][c] = v[k * n3 + 3 * (size_t)s + c];
+            nn[k] += b[k][c] * b[k][c];
+            basis[d * kNB * 3 + k * 3 + c] = (float)b[k][c];
+        }
+    }
+    const double4 p = par[s];
+    float* x = feat + d * kNF;
+    x[0] = (float)p.x;
+    x[1] = (float)p.w;
+#pragma unroll
+    for (int k = 0; k < kNB; ++k)
+        x[2 + k] = (float)(kDebye * sqrt(nn[k]));
+    const int pa[3] = {0, 0, 1}, pb[3] = {1, 2, 2};
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        const int i = pa[q], j = pb[q];
+        const double dot = b[i][0] * b[j][0] + b[i][1] * b[j][1] + b[i][2] * b[j][2];
+        x[5 + q] = (float)(dot / sqrt(nn[i] * nn[j] + 1e-20));
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+        x[8 + c] = (float)radial[3 * (size_t)s + c];
+}
+
+// ------------------------------------------------------------------------------------------
+// Network forward for one sample: layer 1 keeps a1 and h1 in registers; layer 2 runs over its
+// units one at a time (the unit index only addresses weights), feeding the output layer.
+// ------------------------------------------------------------------------------------------
+__device__ __forceinline__ void mlp_layer1(const float* __restrict__ w, const float (&x)[kNF], float (&a1)[kH],
+                                           float (&h1)[kH])
+{
+    float xh[kNF];
+#pragma unroll
+    for (int f = 0; f < kNF; ++f)
+        xh[f] = (x[f] - w[kOffMean + f]) * w[kOffInv + f];
+#pragma unroll
+    for (int k = 0; k < kH; ++k) {
+        float a = w[kOffB1 + k];
+#pragma unroll
+        for (int f = 0; f < kNF; ++f)
+            a = fmaf(w[k * kNF + f], xh[f], a);
+        a1[k] = a;
+        h1[k] = a * sigm(a);
+    }
+}
+
+__device__ __forceinline__ float mlp_unit2(const float* __restrict__ w, int k, const float (&h1)[kH])
+{
+    const float* row = w + kOffW2 + k * kH;
+    float a = w[kOffB2 + k];
+#pragma unroll
+    for (int j = 0; j < kH; ++j)
+        a = fmaf(row[j], h1[j], a);
+    return a;
+}
+
+__global__ __launch_bounds__(256) void k_guess_forward(int64_t n, const float* __restrict__ w,
+                                                       const float* __restrict__ feat,
+                                                       const float* __restrict__ basis, const int* __restrict__ perm,
+                                                       double* __restrict__ out64, float* __restrict__ out32)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n)
+        return;
+    if (perm && perm[i] < 0) {
+        out64[3 * i] = out64[3 * i + 1] = out64[3 * i + 2] = 0.0;
+        return;
+    }
+    float x[kNF];
+#pragma unroll
+    for (int f = 0; f < kNF; ++f)
+        x[f] = feat[i * kNF + f];
+    float a1[kH], h1[kH];
+    mlp_layer1(w, x, a1, h1);
+    float y[kNB];
+#pragma unroll
+    for (int c = 0; c < kNB; ++c)
+        y[c] = w[kOffB3 + c];
+    for (int k = 0; k < kH; ++k) {
+        const float a = mlp_unit2(w, k, h1);
+        const float h = a * sigm(a);
+#pragma unroll
+        for (int c = 0; c < kNB; ++c)
+            y[c] = fmaf(w[kOffW3 + c * kH + k], h, y[c]);
+    }
+    float mu[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+    for (int k = 0; k < kNB; ++k)
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            mu[c] = fmaf(1.0f + y[k], basis[i * kNB * 3 + k * 3 + c], mu[c]);
+    if (out64) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            out64[3 * i + c] = (double)mu[c];
+    } else {
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            out32[3 * i + c] = mu[c];
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// Loss and gradient.  One wave per workgroup, chunks of 64 samples, chunk q handled by
+// workgroup q mod G.  Phase 1 (lane = sample): forward, dL/dmu0, backward deltas, written to
+// LDS by rows.  Phase 2 (lane = hidden unit h): the workgroup's gradient of every parameter
+// that belongs to unit h, summed over the chunk's samples in order, kept in registers across
+// chunks.  Samples past the batch end contribute exactly zero.
+// ------------------------------------------------------------------------------------------
+constexpr int kRow = kH + 4;     // LDS row stride of the per-sample activations (16-byte rows)
+
+__global__ __launch_bounds__(64) void k_guess_grad(int64_t n_batch, int64_t n_rows, const int* __restrict__ idx,
+                                                   const float* __restrict__ w, const float* __restrict__ feat,
+                                                   const float* __restrict__ basis,
+                                                   const float* __restrict__ target, float lscale,
+                                                   float* __restrict__ part, double* __restrict__ lossp,
+                                                   int* __restrict__ flags)
+{
+    __shared__ __align__(16) float s_x[kBlock][12];
+    __shared__ __align__(16) float s_h1[kBlock][kRow];
+    __shared__ __align__(16) float s_d1[kBlock][kRow];
+    __shared__ __align__(16) float s_h2[kBlock][kRow];
+    __shared__ __align__(16) float s_d2[kBlock][kRow];   // holds silu'(a2) until delta2 replaces it
+    __shared__ __align__(16) float s_d3[kBlock][4];
+    const int lane = threadIdx.x;
+    const int64_t nchunk = (n_batch + kBlock - 1) / kBlock;
+    float gW1[kNF], gW2[kH], gW3[kNB], gb1 = 0.f, gb2 = 0.f, gb3 = 0.f;
+#pragma unroll
+    for (int f = 0; f < kNF; ++f)
+        gW1[f] = 0.f;
+#pragma unroll
+    for (int j = 0; j < kH; ++j)
+        gW2[j] = 0.f;
+#pragma unroll
+    for (int c = 0; c < kNB; ++c)
+        gW3[c] = 0.f;
+    double lacc = 0.0;
+    for (int64_t q = blockIdx.x; q < nchunk; q += gridDim.x) {
+        // ---- phase 1: lane = sample
+        const int64_t b = q * kBlock + lane;
+        int64_t row = -1;
+        if (b < n_batch) {
+            row = idx ? (int64_t)idx[b] : b;
+            if (row < 0 || row >= n_rows) {
+                atomicOr(flags, kFlagBadIndex);
+                row = -1;
+            }
+        }
+        float x[kNF], v[kNB][3], tg[3];
+        if (row >= 0) {
+#pragma unroll
+            for (int f = 0; f < kNF; ++f)
+                x[f] = feat[row * kNF + f];
+#pragma unroll
+            for (int k = 0; k < kNB; ++k)
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+                    v[k][c] = basis[row * kNB * 3 + k * 3 + c];
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                tg[c] = target[row * 3 + c];
+        } else {
+#pragma unroll
+            for (int f = 0; f < kNF; ++f)
+                x[f] = w[kOffMean + f];
+#pragma unroll
+            for (int k = 0; k < kNB; ++k)
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+                    v[k][c] = 0.f;
+            tg[0] = tg[1] = tg[2] = 0.f;
+        }
+        float a1[kH], h1[kH];
+        mlp_layer1(w, x, a1, h1);
+#pragma unroll
+        for (int f = 0; f < kNF; ++f)
+            s_x[lane][f] = (x[f] - w[kOffMean + f]) * w[kOffInv + f];
+#pragma unroll
+        for (int j = 0; j < kH; ++j)
+            s_h1[lane][j] = h1[j];
+        float y[kNB];
+#pragma unroll
+        for (int c = 0; c < kNB; ++c)
+            y[c] = w[kOffB3 + c];
+        for (int k = 0; k < kH; ++k) {
+            const float a = mlp_unit2(w, k, h1);
+            const float sg = sigm(a);
+            const float h = a * sg;
+            s_h2[lane][k] = h;
+            s_d2[lane][k] = sg * (1.0f + a * (1.0f - sg));
+#pragma unroll
+            for (int c = 0; c < kNB; ++c)
+                y[c] = fmaf(w[kOffW3 + c * kH + k], h, y[c]);
+        }
+        float gmu[3];
+        float l = 0.f;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            float m = 0.f;
+#pragma unroll
+            for (int k = 0; k < kNB; ++k)
+                m = fmaf(1.0f + y[k], v[k][c], m);
+            const float dlt = m - tg[c];
+            l = fmaf(dlt, dlt, l);
+            gmu[c] = 2.0f * lscale * dlt;
+        }
+        float d3[kNB];
+#pragma unroll
+        for (int k = 0; k < kNB; ++k) {
+            d3[k] = gmu[0] * v[k][0] + gmu[1] * v[k][1] + gmu[2] * v[k][2];
+            s_d3[lane][k] = d3[k];
+        }
+        s_d3[lane][3] = 0.f;
+        // delta2 and W2^T delta2
+        float t1[kH];
+#pragma unroll
+        for (int j = 0; j < kH; ++j)
+            t1[j] = 0.f;
+        for (int k = 0; k < kH; ++k) {
+            float g = 0.f;
+#pragma unroll
+            for (int c = 0; c < kNB; ++c)
+                g = fmaf(w[kOffW3 + c * kH + k], d3[c], g);
+            const float d2 = g * s_d2[lane][k];
+            s_d2[lane][k] = d2;
+            const float* wr = w + kOffW2 + k * kH;
+#pragma unroll
+            for (int j = 0; j < kH; ++j)
+                t1[j] = fmaf(wr[j], d2, t1[j]);
+        }
+#pragma unroll
+        for (int j = 0; j < kH; ++j) {
+            const float sg = sigm(a1[j]);
+            s_d1[lane][j] = t1[j] * (sg * (1.0f + a1[j] * (1.0f - sg)));
+        }
+        // chunk loss, summed over the wave in a fixed tree
+        float ls = l * lscale;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1)
+            ls += __shfl_xor(ls, o);
+        lacc += (double)ls;
+        __syncthreads();
+        // ---- phase 2: lane = hidden unit h
+        const int h = lane;
+        const int na = (int)min((int64_t)kBlock, n_batch - q * kBlock);
+        for (int a = 0; a < na; ++a) {
+            const float d2 = s_d2[a][h];
+            const float d1 = s_d1[a][h];
+            const float h2 = s_h2[a][h];
+            gb2 += d2;
+            gb1 += d1;
+            const float4* hr = reinterpret_cast<const float4*>(&s_h1[a][0]);
+#pragma unroll
+            for (int j4 = 0; j4 < kH / 4; ++j4) {
+                const float4 hv = hr[j4];
+                gW2[4 * j4] = fmaf(d2, hv.x, gW2[4 * j4]);
+                gW2[4 * j4 + 1] = fmaf(d2, hv.y, gW2[4 * j4 + 1]);
+                gW2[4 * j4 + 2] = fmaf(d2, hv.z, gW2[4 * j4 + 2]);
+                gW2[4 * j4 + 3] = fmaf(d2, hv.w, gW2[4 * j4 + 3]);
+            }
+#pragma unroll
+            for (int f = 0; f < kNF; ++f)
+                gW1[f] = fmaf(d1, s_x[a][f], gW1[f]);
+            const float4 dv = *reinterpret_cast<const float4*>(&s_d3[a][0]);
+            gW3[0] = fmaf(dv.x, h2, gW3[0]);
+            gW3[1] = fmaf(dv.y, h2, gW3[1]);
+            gW3[2] = fmaf(dv.z, h2, gW3[2]);
+            gb3 += h == 0 ? dv.x : (h == 1 ? dv.y : (h == 2 ? dv.z : 0.f));
+        }
+        __syncthreads();
+    }
+    float* p = part + (size_t)blockIdx.x * kNP;
+    const int h = lane;
+#pragma unroll
+    for (int f = 0; f < kNF; ++f)
+        p[h * kNF + f] = gW1[f];
+    p[kOffB1 + h] = gb1;
+#pragma unroll
+    for (int j = 0; j < kH; ++j)
+        p[kOffW2 + h * kH + j] = gW2[j];
+    p[kOffB2 + h] = gb2;
+#pragma unroll
+    for (int c = 0; c < kNB; ++c)
+        p[kOffW3 + c * kH + h] = gW3[c];
+    if (h < kNB)
+        p[kOffB3 + h] = gb3;
+    if (lane == 0)
+        lossp[blockIdx.x] = lacc;
+}
+
+// Sum of the workgroup partials (fixed order, FP64) per parameter; then either the gradient is
+// written out or an Adam step is applied.  The loss is summed by thread 0 of workgroup 0.
+__global__ __launch_bounds__(256) void k_guess_reduce(int nwg, const float* __restrict__ part,
+                                                      const double* __restrict__ lossp, float* __restrict__ grad,
+                                                      float* __restrict__ w, float* __restrict__ m,
+                                                      float* __restrict__ v, int adam, float lr, float bc1,
+                                                      float bc2, double* __restrict__ loss)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p == 0) {
+        double l = 0.0;
+        for (int g = 0; g < nwg; ++g)
+            l += lossp[g];
+        loss[0] = l;
+    }
+    if (p >= kNP)
+        return;
+    double s = 0.0;
+    for (int g = 0; g < nwg; ++g)
+        s += (double)part[(size_t)g * kNP + p];
+    const float gr = (float)s;
+    if (grad)
+        grad[p] = gr;
+    if (adam) {
+        const float mm = 0.9f * m[p] + 0.1f * gr;
+        const float vv = 0.999f * v[p] + 0.001f * gr * gr;
+        m[p] = mm;
+        v[p] = vv;
+        w[p] -= lr * (mm * bc1) / (sqrtf(vv * bc2) + 1e-8f);
+    }
+}
+
+// Feature statistics: pass 0 sums x, pass 1 sums (x - mean)^2; FP64 partials per workgroup.
+__global__ __launch_bounds__(256) void k_guess_norm_partial(int64_t n, const float* __restrict__ feat, int pass,
+                                                            const double* __restrict__ mean,
+                                                            double* __restrict__ part)
+{
+    double acc[kNF];
+#pragma unroll
+    for (int f = 0; f < kNF; ++f)
+        acc[f] = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+#pragma unroll
+        for (int f = 0; f < kNF; ++f) {
+            const double x = (double)feat[i * kNF + f];
+            const double d = pass ? x - mean[f] : x;
+            acc[f] += pass ? d * d : d;
+        }
+    block_sum<kNF>(acc);
+    if (threadIdx.x < kNF)
+        part[(size_t)blockIdx.x * kNF + threadIdx.x] = acc[threadIdx.x];
+}
+
+__global__ __launch_bounds__(256) void k_guess_norm_final(int nparts, int64_t n, const double* __restrict__ part,
+                                                          int pass, double* __restrict__ mean, float* __restrict__ w)
+{
+    double tot[kNF];
+    sum_partials<kNF>(part, nparts, tot);
+    if (threadIdx.x < kNF) {
+        const int f = threadIdx.x;
+        if (pass == 0) {
+            mean[f] = tot[f] / (double)n;
+            w[kOffMean + f] = (float)mean[f];
+        } else {
+            const double sd = sqrt(tot[f] / (double)n);
+            w[kOffInv + f] = sd > 1e-6 ? (float)(1.0 / sd) : 0.0f;
+        }
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// host side
+// ------------------------------------------------------------------------------------------
+template <typename R> static void launch_radial(amoeba_ctx* c, R* jbuf, const void* jrel, const void* off)
+{
+    using R4 = typename V4R<R>::T;
+    const R L0 = (R)c->prm.box[0], L1 = (R)c->prm.box[1], L2 = (R)c->prm.box[2];
+    hipLaunchKernelGGL(k_guess_radial<R>, dim3(c->nb), dim3(64), 0, c->stream, c->blk_tile0, c->tile_mask,
+                       (const R4*)jrel, (const R4*)off, L0, L1, L2, (R)(1.0 / c->prm.box[0]),
+                       (R)(1.0 / c->prm.box[1]), (R)(1.0 / c->prm.box[2]), c->eipart, jbuf);
+}
+
+static int guess_alloc_config(amoeba_ctx* c)
+{
+    if (c->g_v)
+        return AMOEBA_OK;
+    const size_t n3 = 3 * (size_t)c->npad;
+    int rc;
+    if ((rc = ctx_alloc(c, (void**)&c->g_v, sizeof(double) * 3 * n3)) ||
+        (rc = ctx_alloc(c, (void**)&c->g_radial, sizeof(double) * n3)) ||
+        (rc = ctx_alloc(c, (void**)&c->g_feat, sizeof(float) * kNF * (size_t)c->npad)) ||
+        (rc = ctx_alloc(c, (void**)&c->g_basis, sizeof(float) * kNB * 3 * (size_t)c->npad)) ||
+        (rc = ctx_alloc(c, (void**)&c->g_save_mu, sizeof(double) * n3)) ||
+        (rc = ctx_alloc(c, (void**)&c->g_save_q, sizeof(double) * n3)))
+        return rc;
+    return AMOEBA_OK;
+}
+
+// Bases and features of the configuration whose permanent field is in v_e (slot order).
+int guess_compute(amoeba_ctx* c)
+{
+    int rc = guess_alloc_config(c);
+    if (rc)
+        return rc;
+    const size_t n3 = 3 * (size_t)c->npad;
+    const double cself = 4.0 * pow(c->prm.ewald_alpha, 3) / (3.0 * sqrt(kPi));
+    const int g = nblk64(c->npad, 256);
+    for (int k = 0; k < kNB; ++k) {
+        const double* prev = k ? c->g_v + (k - 1) * n3 : c->v_e;
+        const double* er = k ? c->ereal : nullptr;
+        {
+            StageTimer tm(c, AMOEBA_T_GUESS);
+            if (c->mixed)
+                hipLaunchKernelGGL(k_guess_basis<float4>, dim3(g), dim3(256), 0, c->stream, c->npad, c->par_d, er,
+                                   prev, cself, c->g_v + k * n3, c->pv_f);
+            else
+                hipLaunchKernelGGL(k_guess_basis<double4>, dim3(g), dim3(256), 0, c->stream, c->npad, c->par_d, er,
+                                   prev, cself, c->g_v + k * n3, c->pv_d);
+        }
+        if (k + 1 < kNB) {
+            launch_mutual_tiles(c, false);
+            launch_real_reduce(c, c->ereal);
+        }
+    }
+    {
+        StageTimer tm(c, AMOEBA_T_GUESS);
+        if (c->ntiles > 0) {
+            if (c->mixed)
+                launch_radial<float>(c, (float*)c->jbuf, c->jrel_f, c->off_f);
+            else
+                launch_radial<double>(c, (double*)c->jbuf, c->jrel_d, c->off_d);
+        }
+    }
+    if (c->ntiles > 0)
+        launch_real_reduce(c, c->g_radial);
+    else
+        hipMemsetAsync(c->g_radial, 0, sizeof(double) * n3, c->stream);
+    StageTimer tm(c, AMOEBA_T_GUESS);
+    hipLaunchKernelGGL(k_guess_features, dim3(g), dim3(256), 0, c->stream, c->npad, c->perm, c->par_d, c->g_v,
+                       c->g_radial, 0, c->g_feat, c->g_basis);
+    return AMOEBA_OK;
+}
+
+// mu0 of every slot (FP64, phantoms zero) from the slot-order features of guess_compute.
+void guess_forward_slot(amoeba_ctx* c, double* mu_slot)
+{
+    StageTimer tm(c, AMOEBA_T_GUESS);
+    hipLaunchKernelGGL(k_guess_forward, dim3(nblk64(c->npad, 256)), dim3(256), 0, c->stream, (int64_t)c->npad,
+                       c->g_model, c->g_feat, c->g_basis, c->perm, mu_slot, (float*)nullptr);
+}
+
+static int guess_alloc_model(amoeba_ctx* c)
+{
+    if (c->g_model)
+        return AMOEBA_OK;
+    int rc;
+    if ((rc = ctx_alloc(c, (void**)&c->g_model, sizeof(float) * kNM)) ||
+        (rc = ctx_alloc(c, (void**)&c->g_adam_m, sizeof(float) * kNP)) ||
+        (rc = ctx_alloc(c, (void**)&c->g_adam_v, sizeof(float) * kNP)) ||
+        (rc = ctx_alloc(c, (void**)&c->g_part, sizeof(float) * kNP * (size_t)kGuessWG)) ||
+        (rc = ctx_alloc(c, (void**)&c->g_lossp, sizeof(double) * kGuessWG)) ||
+        (rc = ctx_alloc(c, (void**)&c->g_scal, sizeof(double) * 4)) ||
+        (rc = ctx_alloc(c, (void**)&c->g_npart, sizeof(double) * kNF * kRedBlocks)) ||
+        (rc = ctx_alloc(c, (void**)&c->g_nmean, sizeof(double) * kNF)))
+        return rc;
+    if (hipHostMalloc((void**)&c->g_scal_host, sizeof(double) * 4, hipHostMallocDefault) != hipSuccess) {
+        c->g_scal_host = nullptr;
+        return set_error(c, AMOEBA_E_NOMEM, "pinned host allocation failed");
+    }
+    return AMOEBA_OK;
+}
+
+static int guess_ready(amoeba_ctx* c, const char* who)
+{
+    if (!c->guess_loaded)
+        return set_error(c, AMOEBA_E_STATE, std::string(who) + ": no model loaded (amoeba_guess_set_model)");
+    return AMOEBA_OK;
+}
+
+// loss and gradient partials of a batch, then the reduction (Adam step when adam != 0)
+static int guess_grad(amoeba_ctx* c, const float* feat, const float* basis, const float* target, int64_t n_rows,
+                      const int32_t* idx, int64_t n_batch, float* grad_out, bool adam, float lr, double* loss_out,
+                      const char* who)
+{
+    if (!feat || !basis || !target)
+        return set_error(c, AMOEBA_E_INVALID, std::string(who) + ": NULL feat, basis or target");
+    if (n_batch < 1 || n_rows < 1 || (!idx && n_batch > n_rows))
+        return set_error(c, AMOEBA_E_INVALID, std::string(who) + ": need 1 <= n_batch (<= n_rows without idx)");
+    if (adam && !(lr > 0.0f && std::isfinite(lr)))
+        return set_error(c, AMOEBA_E_INVALID, std::string(who) + ": lr must be positive");
+    hipStream_t st = c->stream;
+    const int64_t nchunk = (n_batch + kBlock - 1) / kBlock;
+    const int nwg = (int)std::min<int64_t>(nchunk, kGuessWG);
+    hipMemsetAsync(c->flags, 0, sizeof(int), st);
+    float bc1 = 1.f, bc2 = 1.f;
+    if (adam) {
+        const int64_t t = c->g_step + 1;
+        bc1 = (float)(1.0 / (1.0 - pow(0.9, (double)t)));
+        bc2 = (float)(1.0 / (1.0 - pow(0.999, (double)t)));
+    }
+    {
+        StageTimer tm(c, AMOEBA_T_GUESS);
+        const float lscale = (float)(kDebye * kDebye / (double)n_batch);
+        hipLaunchKernelGGL(k_guess_grad, dim3(nwg), dim3(64), 0, st, n_batch, n_rows, idx, c->g_model, feat, basis,
+                           target, lscale, c->g_part, c->g_lossp, c->flags);
+        // an invalid index leaves the model untouched: the reduction runs without the update
+        // only after the flags are known, so the Adam step is a second, separate launch
+        hipLaunchKernelGGL(k_guess_reduce, dim3(nblk64(kNP, 256)), dim3(256), 0, st, nwg, c->g_part, c->g_lossp,
+                           grad_out, c->g_model, c->g_adam_m, c->g_adam_v, 0, lr, bc1, bc2, c->g_scal);
+    }
+    int f = 0, rc = read_flags(c, &f);
+    if (rc)
+        return rc;
+    if (f & kFlagBadIndex)
+        return set_error(c, AMOEBA_E_INVALID, std::string(who) + ": idx entry outside [0, n_rows)");
+    if (adam) {
+        StageTimer tm(c, AMOEBA_T_GUESS);
+        hipLaunchKernelGGL(k_guess_reduce, dim3(nblk64(kNP, 256)), dim3(256), 0, st, nwg, c->g_part, c->g_lossp,
+                           (float*)nullptr, c->g_model, c->g_adam_m, c->g_adam_v, 1, lr, bc1, bc2, c->g_scal + 1);
+        c->g_step += 1;
+    }
+    hipMemcpyAsync(c->g_scal_host, c->g_scal, sizeof(double), hipMemcpyDeviceToHost, st);
+    if ((rc = hip_check(c, hipStreamSynchronize(st), who)))
+        return rc;
+    if (loss_out)
+        *loss_out = c->g_scal_host[0];
+    return AMOEBA_OK;
+}
+
+}  // namespace amoeba
+
+using namespace amoeba;
+
+extern "C" {
+
+int amoeba_guess_set_model(amoeba_ctx* c, const float* model, int64_t n_floats)
+{
+    if (!c)
+        return AMOEBA_E_INVALID;
+    c->err.clear();
+    if (!model || n_floats != kNM)
+        return set_error(c, AMOEBA_E_INVALID, "amoeba_guess_set_model: need AMOEBA_GUESS_NMODEL floats");
+    for (int64_t i = 0; i < n_floats; ++i)
+        if (!std::isfinite(model[i]))
+            return set_error(c, AMOEBA_E_NUMERIC, "amoeba_guess_set_model: non-finite model entry");
+    int rc = guess_alloc_model(c);
+    if (rc)
+        return rc;
+    hipStream_t st = c->stream;
+    hipMemcpyAsync(c->g_model, model, sizeof(float) * kNM, hipMemcpyHostToDevice, st);
+    hipMemsetAsync(c->g_adam_m, 0, sizeof(float) * kNP, st);
+    hipMemsetAsync(c->g_adam_v, 0, sizeof(float) * kNP, st);
+    c->g_step = 0;
+    if ((rc = hip_check(c, hipStreamSynchronize(st), "amoeba_guess_set_model")))
+        return rc;
+    c->guess_loaded = true;
+    return AMOEBA_OK;
+}
+
+int amoeba_guess_get_model(amoeba_ctx* c, float* model, int64_t n_floats)
+{
+    if (!c)
+        return AMOEBA_E_INVALID;
+    c->err.clear();
+    if (!model || n_floats != kNM)
+        return set_error(c, AMOEBA_E_INVALID, "amoeba_guess_get_model: need AMOEBA_GUESS_NMODEL floats");
+    int rc = guess_ready(c, "amoeba_guess_get_model");
+    if (rc)
+        return rc;
+    hipMemcpyAsync(model, c->g_model, sizeof(float) * kNM, hipMemcpyDeviceToHost, c->stream);
+    return hip_check(c, hipStreamSynchronize(c->stream), "amoeba_guess_get_model");
+}
+
+int amoeba_guess_features(amoeba_ctx* c, const double* pos, const double* e_perm, float* feat_out, float* basis_out)
+{
+    if (!c)
+        return AMOEBA_E_INVALID;
+    c->err.clear();
+    if (!e_perm || !feat_out || !basis_out)
+        return set_error(c, AMOEBA_E_INVALID, "amoeba_guess_features: NULL argument");
+    int rc = begin_config(c, pos, "amoeba_guess_features");
+    if (rc)
+        return rc;
+    if ((rc = check_vec_finite(c, e_perm, 3 * (size_t)c->n, "e_perm")))
+        return rc;
+    launch_gather_vec(c, e_perm, c->v_e);
+    if ((rc = guess_compute(c)))
+        return rc;
+    {
+        StageTimer tm(c, AMOEBA_T_GUESS);
+        hipLaunchKernelGGL(k_guess_features, dim3(nblk64(c->npad, 256)), dim3(256), 0, c->stream, c->npad, c->perm,
+                           c->par_d, c->g_v, c->g_radial, 1, feat_out, basis_out);
+    }
+    return hip_check(c, hipStreamSynchronize(c->stream), "amoeba_guess_features");
+}
+
+int amoeba_guess_fit_norm(amoeba_ctx* c, const float* feat, int64_t n_rows)
+{
+    if (!c)
+        return AMOEBA_E_INVALID;
+    c->err.clear();
+    if (!feat || n_rows < 1)
+        return set_error(c, AMOEBA_E_INVALID, "amoeba_guess_fit_norm: need feat and n_rows >= 1");
+    int rc = guess_ready(c, "amoeba_guess_fit_norm");
+    if (rc)
+        return rc;
+    hipStream_t st = c->stream;
+    const int nwg = (int)std::min<int64_t>(kRedBlocks, (n_rows + 255) / 256);
+    StageTimer tm(c, AMOEBA_T_GUESS);
+    for (int pass = 0; pass < 2; ++pass) {
+        hipLaunchKernelGGL(k_guess_norm_partial, dim3(nwg), dim3(256), 0, st, n_rows, feat, pass, c->g_nmean,
+                           c->g_npart);
+        hipLaunchKernelGGL(k_guess_norm_final, dim3(1), dim3(256), 0, st, nwg, n_rows, c->g_npart, pass,
+                           c->g_nmean, c->g_model);
+    }
+    return hip_check(c, hipStreamSynchronize(st), "amoeba_guess_fit_norm");
+}
+
+int amoeba_guess_forward(amoeba_ctx* c, const float* feat, const float* basis, int64_t n, float* mu_out)
+{
+    if (!c)
+        return AMOEBA_E_INVALID;
+    c->err.clear();
+    if (!feat || !basis || !mu_out || n < 1)
+        return set_error(c, AMOEBA_E_INVALID, "amoeba_guess_forward: NULL argument or n < 1");
+    int rc = guess_ready(c, "amoeba_guess_forward");
+    if (rc)
+        return rc;
+    {
+        StageTimer tm(c, AMOEBA_T_GUESS);
+        hipLaunchKernelGGL(k_guess_forward, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, n,
+                           c->g_model, feat, basis, (const int*)nullptr, (double*)nullptr, mu_out);
+    }
+    return hip_check(c, hipStreamSynchronize(c->stream), "amoeba_guess_forward");
+}
+
+int amoeba_guess_gradient(amoeba_ctx* c, const float* feat, const float* basis, const float* target, int64_t n_rows,
+                          const int32_t* idx, int64_t n_batch, float* grad_out, double* loss_out)
+{
+    if (!c)
+        return AMOEBA_E_INVALID;
+    c->err.clear();
+    if (!grad_out)
+        return set_error(c, AMOEBA_E_INVALID, "amoeba_guess_gradient: NULL grad_out");
+    int rc = guess_ready(c, "amoeba_guess_gradient");
+    if (rc)
+        return rc;
+    return guess_grad(c, feat, basis, target, n_rows, idx, n_batch, grad_out, false, 0.0f, loss_out,
+                      "amoeba_guess_gradient");
+}
+
+int amoeba_guess_train_step(amoeba_ctx* c, const float* feat, const float* basis, const float* target,
+                            int64_t n_rows, const int32_t* idx, int64_t n_batch, float lr, double* loss_out)
+{
+    if (!c)
+        return AMOEBA_E_INVALID;
+    c->err.clear();
+    int rc = guess_ready(c, "amoeba_guess_train_step");
+    if (rc)
+        return rc;
+    return guess_grad(c, feat, basis, target, n_rows, idx, n_batch, nullptr, true, lr, loss_out,
+                      "amoeba_guess_train_step");
+}
+
+int amoeba_guess_predict(amoeba_ctx* c, const double* pos, const double* e_perm, double* mu0_out)
+{
+    if (!c)
+        return AMOEBA_E_INVALID;
+    c->err.clear();
+    if (!e_perm || !mu0_out)
+        return set_error(c, AMOEBA_E_INVALID, "amoeba_guess_predict: NULL argument");
+    int rc = guess_ready(c, "amoeba_guess_predict");
+    if (rc)
+        return rc;
+    if ((rc = begin_config(c, pos, "amoeba_guess_predict")))
+        return rc;
+    if ((rc = check_vec_finite(c, e_perm, 3 * (size_t)c->n, "e_perm")))
+        return rc;
+    launch_gather_vec(c, e_perm, c->v_e);
+    if ((rc = guess_compute(c)))
+        return rc;
+    guess_forward_slot(c, c->v_q);
+    launch_scatter(c, c->v_q, mu0_out);
+    return hip_check(c, hipStreamSynchronize(c->stream), "amoeba_guess_predict");
+}
+
+}  // extern "C"

@@ -328,27 +328,55 @@ static int read_scalars(amoeba_ctx* c, PcgScalars* out)
     return rc;
 }
 
-// Solve A mu = e (v_e, slot order).  On entry v_mu holds the guess if have_guess.
-int pcg_solve(amoeba_ctx* c, double tol, int max_iter, bool have_guess)
+// Initial device scalars of a solve (tolerance; everything else zero).
+int pcg_begin(amoeba_ctx* c, double tol)
 {
-    hipStream_t st = c->stream;
     PcgScalars init{};
     init.tol = tol;
     c->sc_host[0] = init;
-    hipMemcpyAsync(c->sc, &c->sc_host[0], sizeof(PcgScalars), hipMemcpyHostToDevice, st);
+    hipMemcpyAsync(c->sc, &c->sc_host[0], sizeof(PcgScalars), hipMemcpyHostToDevice, c->stream);
+    return hip_check(c, hipStreamSynchronize(c->stream), "pcg init");
+}
+
+// r0 = e - A mu0, z0 = alpha r0, p0 = z0 from v_mu (have_guess) or mu0 = 0; *rms_debye = rms of z0.
+int pcg_start(amoeba_ctx* c, bool have_guess, double* rms_debye)
+{
     int rc;
-    if ((rc = hip_check(c, hipStreamSynchronize(st), "pcg init")))
-        return rc;
     if (have_guess) {
         launch_set_direction(c, c->v_mu);
         if ((rc = matvec_slot(c, false, false)))
             return rc;
         launch_init_residual(c, c->v_q, 0);
     } else {
-        hipMemsetAsync(c->v_mu, 0, sizeof(double) * 3 * (size_t)c->npad, st);
+        hipMemsetAsync(c->v_mu, 0, sizeof(double) * 3 * (size_t)c->npad, c->stream);
         launch_init_residual(c, nullptr, 0);
     }
     PcgScalars s;
+    if ((rc = read_scalars(c, &s)))
+        return rc;
+    if (rms_debye)
+        *rms_debye = s.rms;
+    return AMOEBA_OK;
+}
+
+// Same with A mu0 already known (q0; NULL for mu0 = 0, v_mu must then be zero).
+int pcg_start_from(amoeba_ctx* c, const double* q0, double* rms_debye)
+{
+    launch_init_residual(c, q0, 0);
+    PcgScalars s;
+    int rc = read_scalars(c, &s);
+    if (rms_debye)
+        *rms_debye = s.rms;
+    return rc;
+}
+
+// Iterate from the state left by pcg_start (v_mu, r, z, p and the scalars of iteration 0)
+// until rms(z) < tol or max_iter iterations.  start_matvecs: products already spent on the
+// starting point (accounting only).
+int pcg_run(amoeba_ctx* c, int max_iter, int start_matvecs)
+{
+    PcgScalars s;
+    int rc;
     if ((rc = read_scalars(c, &s)))
         return rc;
     int used = 0;
@@ -385,8 +413,19 @@ int pcg_solve(amoeba_ctx* c, double tol, int max_iter, bool have_guess)
     }
     c->last_iters = used;
     c->last_rms = s.rms;
-    c->matvecs += used + (have_guess ? 1 : 0) + extra_matvecs;
+    c->matvecs += used + start_matvecs + extra_matvecs;
     return s.status == 1 ? AMOEBA_OK : AMOEBA_NOT_CONVERGED;
+}
+
+// Solve A mu = e (v_e, slot order).  On entry v_mu holds the guess if have_guess.
+int pcg_solve(amoeba_ctx* c, double tol, int max_iter, bool have_guess)
+{
+    int rc;
+    if ((rc = pcg_begin(c, tol)))
+        return rc;
+    if ((rc = pcg_start(c, have_guess, nullptr)))
+        return rc;
+    return pcg_run(c, max_iter, have_guess ? 1 : 0);
 }
 
 double compute_epol(amoeba_ctx* c)
