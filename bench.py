@@ -23,10 +23,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "induced-dipole solves/s to 1e-5 D rms (FP64 vs mixed vs learned guess)"
-PEAK_FP32_VALU = 157.3     # TFLOP/s, MI355X published FP32 vector peak
+PEAK_FP32_VALU = 157.3     # TFLOP/s, MI355X published FP32 vector peak (packed FMA)
+PEAK_FP32_NONPACKED = 78.6 # TFLOP/s: 256 CUs x 64 lanes x 2 FLOP x 2.4 GHz (packed FP32 is disabled)
 PEAK_HBM = 8000.0          # GB/s
-# Algorithmic FLOPs per in-cutoff pair of the real-space dipole kernel (FMA counted as 2; the
-# four transcendental calls rsqrt, exp, exp, erfc counted as one FLOP each).  See the design doc.
+# Algorithmic FLOPs per in-cutoff pair of the real-space dipole kernel: FMA counted as 2, each
+# of the four hardware transcendentals (rsq, rcp, exp2, exp2) as 1; fixed-point conversion,
+# loop control and masked slots not counted.
 FLOPS_PER_PAIR = 80
 STAGES = ["list", "perm", "real", "spread", "fft", "gather", "pcg", "guess"]
 
@@ -44,6 +46,12 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle timing leg")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison leg")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-guess trajectory leg")
+    ap.add_argument("--trajectory-288k", action="store_true",
+                    help="add the 288,000-atom trajectory leg: 200 configurations, train on 150, "
+                         "evaluate the learned and previous-step guesses on the last 50")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="end with three plain 256 MiB device-to-device copies (the reference dispatch that "
+                         "scales the FETCH_SIZE / WRITE_SIZE counters of a profiling run)")
     return ap.parse_args()
 
 
@@ -107,15 +115,16 @@ def run_variant(s, t, precision, steps, warmup, tol, timing=True):
     return out
 
 
-def learned_leg(s, t, steps, tol, n_train=8, n_eval=4, train_steps=600, batch=16384):
+def learned_leg(s, t, steps, tol, n_train=8, n_eval=4, train_steps=600, batch=16384, seed=204):
     """Mixed precision on a 0.02 A-step trajectory of the same box: the network is trained on
     the solver's own converged dipoles of the first n_train configurations (GPU kernels), then
     the next n_eval configurations are solved from the zero, previous-step, learned and judged
-    (learned vs previous-step) starts.  One step = list + E_perm + solve, as in the main leg."""
+    (learned vs previous-step) starts, `steps` solves per start cycling over them.  One step =
+    list + E_perm + solve, as in the main leg."""
     import numpy as np
     import torch
     from paper_2011_01207_amd import amoeba, synth
-    frames = list(synth.trajectory(s, n_train + n_eval + 1, 0.02, seed=204))
+    frames = list(synth.trajectory(s, n_train + n_eval + 1, 0.02, seed=seed))
     ctx = amoeba.Context(s.n, s.box, cutoff=s.cutoff, buffer=s.buffer, ewald_alpha=s.ewald_alpha, grid=s.grid,
                          order=s.order, precision="mixed")
     ctx.set_atoms(t["alpha"], t["thole"], t["sc_ptr"], t["sc_j"], t["sc_s"])
@@ -206,20 +215,23 @@ def roofline(s, res, K):
     flops = FLOPS_PER_PAIR * res["n_pairs"] * mv
     stages["real"] = {"bound": "alu", "achieved": flops / (ms * 1e-3) / 1e12, "peak": PEAK_FP32_VALU,
                       "unit": "TFLOP/s", "ms_total": ms, "launches": tim["launches"]["real"],
-                      "kernel": "k_mutual_tiles<float,true>", "algorithmic_per_launch": FLOPS_PER_PAIR * res["n_pairs"]}
+                      "kernel": "k_block_tiles<float, true, DipoleKind<float>, *>",
+                      "algorithmic_per_launch": FLOPS_PER_PAIR * res["n_pairs"],
+                      "peak_nonpacked": PEAK_FP32_NONPACKED,
+                      "frac_nonpacked": flops / (ms * 1e-3) / 1e12 / PEAK_FP32_NONPACKED}
     # PME spread: position (12 B) + dipole (12 B) per atom read, FP32 grid written once
     b_spread = n * 24 + k3 * 4
     ms = tim["ms"]["spread"]
     stages["spread"] = {"bound": "hbm", "achieved": b_spread * mv / (ms * 1e-3) / 1e9, "peak": PEAK_HBM,
                         "unit": "GB/s", "ms_total": ms, "launches": tim["launches"]["spread"],
-                        "kernel": "k_spread<float,true,false>", "algorithmic_per_launch": b_spread}
+                        "kernel": "k_spread_dip<float, true>", "algorithmic_per_launch": b_spread}
     # gather + operator assembly: grid read once; per atom position 12, real-space field 24,
     # direction 24, 1/alpha 8 read and A p 24 written (FP64 vectors)
     b_gather = k3 * 4 + n * (12 + 24 + 24 + 8 + 24)
     ms = tim["ms"]["gather"]
     stages["gather"] = {"bound": "hbm", "achieved": b_gather * mv / (ms * 1e-3) / 1e9, "peak": PEAK_HBM,
                         "unit": "GB/s", "ms_total": ms, "launches": tim["launches"]["gather"],
-                        "kernel": "k_gather_combine<float,true>", "algorithmic_per_launch": b_gather}
+                        "kernel": "k_gather_brick<float, 1>", "algorithmic_per_launch": b_gather}
     # FFT pair + influence product: each 3-D FFT reads and writes the grid once (real K^3 x 4 B,
     # half-complex K^3 x 4 B); the product reads/writes the half grid and reads theta
     b_fft = 2 * (k3 * 4 + k3 * 4) + (k3 * 4 * 2 + k3 * 2)
@@ -235,6 +247,9 @@ def roofline(s, res, K):
            "frac": d["frac"], "traffic": None, "kernel": d["kernel"], "stage": dom,
            "avg_launch_us": 1e3 * d["ms_total"] / max(1, d["launches"]),
            "productive_launches": mv, "launches": d["launches"]}
+    for k in ("peak_nonpacked", "frac_nonpacked"):
+        if k in d:
+            top[k] = d[k]
     return top, stages
 
 
@@ -348,9 +363,30 @@ def main():
         res["learned_guess"] = lg
         log("learned: " + ", ".join(f"{k} {v['step_ms']:.3f} ms {v['mean_iterations']:.1f} it"
                                     for k, v in lg["modes"].items()))
+    if a.trajectory_288k:
+        log("288,000-atom trajectory leg")
+        s4 = synth.water288k()
+        t4 = {k: torch.tensor(getattr(s4, k), device=dev) for k in ("pos", "q", "dip", "quad", "alpha", "thole",
+                                                                    "sc_s")}
+        t4["sc_ptr"] = torch.tensor(s4.sc_ptr, dtype=torch.int32, device=dev)
+        t4["sc_j"] = torch.tensor(s4.sc_j, dtype=torch.int32, device=dev)
+        lg4 = learned_leg(s4, t4, 50, a.tol, n_train=150, n_eval=50, train_steps=2000, batch=65536, seed=304)
+        lg4["workload"] = ("water_288000: 96,000 waters, 142.3 A box, PME 144^3; 200 configurations of "
+                           "cumulative 0.02 A per-atom steps; train on 1-150, evaluate 151-200 once per start")
+        res["trajectory_288000"] = lg4
+        log("288k: " + ", ".join(f"{k} {v['step_ms']:.3f} ms {v['mean_iterations']:.1f} it"
+                                 for k, v in lg4["modes"].items()))
+        del t4
     if not a.no_cpu_baseline:
         log("cpu baseline (oracle)")
         res["cpu_baseline"] = cpu_baseline(s, fp64["iterations"] if fp64 else mixed["iterations"])
+    if a.copy_calibration:
+        src = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy calibration: 3 x 256 MiB device-to-device copies")
     print(json.dumps(res), flush=True)
 
 

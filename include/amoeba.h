@@ -33,8 +33,10 @@
  *    returns after its outputs are complete.  A context is not thread-safe: use
  *    one context per host thread.
  *  - Errors: every call returns an amoeba_status; negative values are errors
- *    with a message in amoeba_last_error().  Arguments are validated before
- *    any output is written; on an error the outputs are unspecified.
+ *    with a message in amoeba_last_error().  Host-side argument checks run
+ *    before any work is queued; checks that need the data (NaN/Inf, traceless
+ *    quadrupoles, list staleness, field range) run on the device and are
+ *    reported when the call returns.  On an error the outputs are unspecified.
  */
 #ifndef AMOEBA_H
 #define AMOEBA_H
@@ -54,7 +56,7 @@ typedef enum amoeba_status {
     AMOEBA_E_NOMEM = -2,       /* device allocation failed or max_workspace_bytes exceeded      */
     AMOEBA_E_DEVICE = -3,      /* no usable gfx950 device, or a HIP / rocFFT call failed        */
     AMOEBA_E_LIST = -4,        /* block list missing or stale (an atom moved > buffer/2)        */
-    AMOEBA_E_OVERFLOW = -5,    /* a fixed-point field accumulator left its range                */
+    AMOEBA_E_OVERFLOW = -5,    /* a field beyond the exact fixed-point range (|E| >= 8192 e/A^2) */
     AMOEBA_E_NUMERIC = -6,     /* NaN/Inf in an input, or a PCG breakdown                       */
     AMOEBA_E_STATE = -7        /* call order violated (e.g. no amoeba_set_atoms yet)             */
 } amoeba_status;
@@ -80,7 +82,8 @@ typedef struct amoeba_params {
     double buffer;         /* neighbour-list buffer (A) >= 0; list is valid while every atom
                               stays within buffer/2 of its position at the last build        */
     double ewald_alpha;    /* Ewald splitting beta (1/A) > 0                                  */
-    int32_t grid[3];       /* PME grid points per edge, each >= 2*order and 2,3,5,7-smooth    */
+    int32_t grid[3];       /* PME grid points per edge, 2*order <= K <= 2048 (FFT sizes of      
+                              2, 3, 5, 7 factors are the fast ones)                           */
     int32_t order;         /* B-spline order; must be 5                                      */
     int32_t precision;     /* amoeba_precision                                                */
     int64_t max_workspace_bytes; /* cap on device memory the context may allocate; 0 = none  */
@@ -100,6 +103,10 @@ typedef struct amoeba_info {
     int32_t guess_loaded;      /* 1 once amoeba_guess_set_model has been called                 */
     double last_guess_rms_debye[2]; /* AMOEBA_GUESS_BEST: rms of alpha r0 (D) of the fallback
                                   (zero or given) [0] and of the learned guess [1]; else 0    */
+    int32_t pair_min_image;    /* 1 if the pair kernels apply the minimum image per pair; 0 when
+                                  the list build proved block-relative offsets already give it
+                                  (cutoff + 3 buffer + 4 x largest block half-extent < box/2) */
+    int32_t reserved;
 } amoeba_info;
 
 /* Create a context for one system size and one parameter set on the current HIP device,

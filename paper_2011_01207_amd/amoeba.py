@@ -54,7 +54,8 @@ class amoeba_info(ctypes.Structure):
                 ("precision", ctypes.c_int32), ("n_pairs", ctypes.c_int64), ("workspace_bytes", ctypes.c_int64),
                 ("last_iterations", ctypes.c_int32), ("last_rms_debye", ctypes.c_double),
                 ("last_guess", ctypes.c_int32), ("guess_loaded", ctypes.c_int32),
-                ("last_guess_rms_debye", ctypes.c_double * 2)]
+                ("last_guess_rms_debye", ctypes.c_double * 2), ("pair_min_image", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class amoeba_timing(ctypes.Structure):

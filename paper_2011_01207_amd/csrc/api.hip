@@ -201,14 +201,15 @@ static int check_overflow(amoeba_ctx* c, const double* v_slot)
         return AMOEBA_OK;
     size_t n3 = 3 * (size_t)c->npad;
     hipMemsetAsync(c->flags, 0, sizeof(int), c->stream);
-    hipLaunchKernelGGL(k_check_overflow, dim3(nblk(n3, 256)), dim3(256), 0, c->stream, n3, v_slot, 4.0e6, c->flags);
+    hipLaunchKernelGGL(k_check_overflow, dim3(nblk(n3, 256)), dim3(256), 0, c->stream, n3, v_slot, kFixRange,
+                       c->flags);
     int f = 0, rc = read_flags(c, &f);
     if (rc)
         return rc;
     if (f & kFlagNonFinite)
         return set_error(c, AMOEBA_E_NUMERIC, "non-finite field");
     if (f & kFlagOverflow)
-        return set_error(c, AMOEBA_E_OVERFLOW, "field outside the fixed-point range (|E| >= 4e6 e/A^2)");
+        return set_error(c, AMOEBA_E_OVERFLOW, "field outside the exact fixed-point range (|E| >= 8192 e/A^2)");
     return AMOEBA_OK;
 }
 
@@ -364,6 +365,10 @@ int amoeba_destroy(amoeba_ctx* c)
         return AMOEBA_OK;
     if (c->stream || true)
         hipStreamSynchronize(c->stream);
+    for (void* p : c->allocs)
+        hipFree(p);
+    if (c->sc_host)
+        hipHostFree(c->sc_host);
     if (c->plan_fwd)
         rocfft_plan_destroy(c->plan_fwd);
     if (c->plan_bwd)
@@ -372,10 +377,6 @@ int amoeba_destroy(amoeba_ctx* c)
         rocfft_execution_info_destroy(c->exec_fwd);
     if (c->exec_bwd)
         rocfft_execution_info_destroy(c->exec_bwd);
-    for (void* p : c->allocs)
-        hipFree(p);
-    if (c->sc_host)
-        hipHostFree(c->sc_host);
     if (c->flags_host)
         hipHostFree(c->flags_host);
     if (c->g_scal_host)
@@ -472,27 +473,32 @@ int amoeba_perm_field(amoeba_ctx* c, const double* pos, const double* q, const d
         if (c->mixed && (rc = ctx_alloc(c, (void**)&c->mp_f, sizeof(float4) * 3 * c->npad)))
             return rc;
     }
+    // The multipole checks (finite, traceless) and the range check of the result are flags
+    // written on the device and read once at the end; on an error e_perm is unspecified.
     hipStream_t st = c->stream;
     hipMemsetAsync(c->flags, 0, sizeof(int), st);
     hipLaunchKernelGGL(k_gather_mpole, dim3(nblk(c->npad, 256)), dim3(256), 0, st, c->npad, c->perm, q, dip, quad,
                        c->mp_d, c->mixed ? c->mp_f : nullptr, c->flags);
-    int f = 0;
-    if ((rc = read_flags(c, &f)))
-        return rc;
-    if (f & kFlagNonFinite)
-        return set_error(c, AMOEBA_E_NUMERIC, "amoeba_perm_field: non-finite multipole");
-    if (f & kFlagBadCsr)
-        return set_error(c, AMOEBA_E_INVALID, "amoeba_perm_field: quadrupole not traceless (|tr| > 1e-10)");
     launch_perm_tiles(c);
     if ((rc = pme_perm_potential(c)))
         return rc;
     launch_gather(c, c->erec);
-    hipMemsetAsync(c->flags, 0, sizeof(int), st);
     launch_perm_assemble(c, c->v_q);
-    if ((rc = check_overflow(c, c->v_q)))
-        return rc;
+    if (c->mixed)
+        hipLaunchKernelGGL(k_check_overflow, dim3(nblk(3 * (size_t)c->npad, 256)), dim3(256), 0, st,
+                           3 * (size_t)c->npad, c->v_q, kFixRange, c->flags);
     launch_scatter(c, c->v_q, e_perm);
-    return hip_check(c, hipStreamSynchronize(st), "amoeba_perm_field");
+    int f = 0;
+    if ((rc = read_flags(c, &f)))
+        return rc;
+    if (f & kFlagBadCsr)
+        return set_error(c, AMOEBA_E_INVALID, "amoeba_perm_field: quadrupole not traceless (|tr| > 1e-10)");
+    if (f & kFlagNonFinite)
+        return set_error(c, AMOEBA_E_NUMERIC, "amoeba_perm_field: non-finite multipole or field");
+    if (f & kFlagOverflow)
+        return set_error(c, AMOEBA_E_OVERFLOW,
+                         "amoeba_perm_field: field outside the exact fixed-point range (|E| >= 8192 e/A^2)");
+    return AMOEBA_OK;
 }
 
 int amoeba_dipole_matvec(amoeba_ctx* c, const double* pos, const double* mu, double* out)
@@ -566,35 +572,36 @@ int amoeba_polarize(amoeba_ctx* c, const double* pos, const double* e_perm, cons
     int rc = begin_config(c, pos, "amoeba_polarize");
     if (rc)
         return rc;
-    if ((rc = check_vec_finite(c, e_perm, 3 * (size_t)c->n, "e_perm")))
-        return rc;
-    launch_gather_vec(c, e_perm, c->v_e);
+    // the inputs are checked for NaN/Inf by the gathers; the flag is read with the solve's
+    // first host wait (AMOEBA_E_NUMERIC, outputs unspecified)
+    hipMemsetAsync(c->flags, 0, sizeof(int), c->stream);
+    launch_gather_vec_checked(c, e_perm, c->v_e);
     const bool given = mu_guess != nullptr && (guess_mode == AMOEBA_GUESS_GIVEN || guess_mode == AMOEBA_GUESS_BEST);
-    if (given && (rc = check_vec_finite(c, mu_guess, 3 * (size_t)c->n, "mu_guess")))
-        return rc;
     c->last_guess_rms[0] = c->last_guess_rms[1] = 0.0;
+    double ep = 0.0;
     int st;
     if (guess_mode == AMOEBA_GUESS_ZERO || guess_mode == AMOEBA_GUESS_GIVEN) {
         if (given)
-            launch_gather_vec(c, mu_guess, c->v_mu);
-        st = pcg_solve(c, tol_debye, max_iter, given);
+            launch_gather_vec_checked(c, mu_guess, c->v_mu);
+        st = pcg_solve(c, tol_debye, max_iter, given, mu_out, &ep);
         c->last_guess = given ? AMOEBA_GUESS_GIVEN : AMOEBA_GUESS_ZERO;
     } else if (guess_mode == AMOEBA_GUESS_LEARNED) {
         if ((rc = guess_compute(c)))
             return rc;
         guess_forward_slot(c, c->v_mu);
-        st = pcg_solve(c, tol_debye, max_iter, true);
+        st = pcg_solve(c, tol_debye, max_iter, true, mu_out, &ep);
         c->last_guess = AMOEBA_GUESS_LEARNED;
     } else {
         // The judge: the preconditioned initial residual of the fallback (zero or given) and of
         // the learned guess; PCG starts from the smaller.  The fallback state is kept while
         // the learned one is evaluated.
-        if ((rc = guess_compute(c)) || (rc = pcg_begin(c, tol_debye)))
+        if ((rc = guess_compute(c)))
             return rc;
+        pcg_begin(c, tol_debye);
         const size_t bytes = sizeof(double) * 3 * (size_t)c->npad;
         double rms_f = 0.0, rms_l = 0.0;
         if (given) {
-            launch_gather_vec(c, mu_guess, c->v_mu);
+            launch_gather_vec_checked(c, mu_guess, c->v_mu);
             if ((rc = pcg_start(c, true, &rms_f)))
                 return rc;
             hipMemcpyAsync(c->g_save_mu, c->v_mu, bytes, hipMemcpyDeviceToDevice, c->stream);
@@ -609,28 +616,24 @@ int amoeba_polarize(amoeba_ctx* c, const double* pos, const double* e_perm, cons
         if (!learned) {
             if (given) {
                 hipMemcpyAsync(c->v_mu, c->g_save_mu, bytes, hipMemcpyDeviceToDevice, c->stream);
-                rc = pcg_start_from(c, c->g_save_q, nullptr);
+                rc = pcg_start_from(c, c->g_save_q);
             } else {
                 rc = pcg_start(c, false, nullptr);
             }
             if (rc)
                 return rc;
         }
-        st = pcg_run(c, max_iter, given ? 2 : 1);
+        st = pcg_run(c, max_iter, given ? 2 : 1, mu_out, &ep);
         c->last_guess = learned ? AMOEBA_GUESS_LEARNED : (given ? AMOEBA_GUESS_GIVEN : AMOEBA_GUESS_ZERO);
         c->last_guess_rms[0] = rms_f;
         c->last_guess_rms[1] = rms_l;
     }
     if (st < 0)
         return st;
-    launch_scatter(c, c->v_mu, mu_out);
-    double ep = compute_epol(c);
     if (e_pol_out)
         *e_pol_out = ep;
     if (iters_out)
         *iters_out = c->last_iters;
-    if ((rc = hip_check(c, hipStreamSynchronize(c->stream), "amoeba_polarize")))
-        return rc;
     if (st == AMOEBA_NOT_CONVERGED)
         set_error(c, AMOEBA_NOT_CONVERGED, "PCG did not reach the tolerance within max_iter");
     return st;
@@ -682,6 +685,8 @@ int amoeba_get_info(const amoeba_ctx* c, amoeba_info* out)
     out->guess_loaded = c->guess_loaded ? 1 : 0;
     out->last_guess_rms_debye[0] = c->last_guess_rms[0];
     out->last_guess_rms_debye[1] = c->last_guess_rms[1];
+    out->pair_min_image = c->skip_mimg ? 0 : 1;
+    out->reserved = 0;
     return AMOEBA_OK;
 }
 

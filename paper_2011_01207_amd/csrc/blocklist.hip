@@ -20,6 +20,8 @@
 //      block gets an FP64 origin and FP32/FP64 offsets, and every tile gets its in-cutoff
 //      bitmasks (bit k of row i: |r_i - r_jk| < rc) and the j positions relative to the
 //      i-block origin, computed in FP64.
+#include <cmath>
+
 #include "common.h"
 
 namespace amoeba {
@@ -331,67 +333,147 @@ __global__ __launch_bounds__(64) void k_bbox(int nb, const int* __restrict__ per
     }
 }
 
-// List filtering: for block I, the atoms of blocks J > I within rcb of any atom of I, in order.
-__global__ __launch_bounds__(64) void k_filter(int nb, const int* __restrict__ perm,
-                                               const double4* __restrict__ pos_s,
-                                               const double4* __restrict__ bc, const double4* __restrict__ bh,
-                                               double3 box, double3 binv, double rcb, int* __restrict__ row_count,
-                                               int* __restrict__ row_j, int* __restrict__ flags)
+// Largest block half-extent per axis (one workgroup; max is order-independent).
+__global__ __launch_bounds__(256) void k_extent_max(int nb, const double4* __restrict__ bh, double* __restrict__ out)
 {
-    __shared__ double sx[kBlock], sy[kBlock], sz[kBlock];
-    __shared__ int sv[kBlock];
-    int I = blockIdx.x, lane = threadIdx.x;
-    int si = I * kBlock + lane;
-    double4 pi = pos_s[si];
-    sx[lane] = pi.x;
-    sy[lane] = pi.y;
-    sz[lane] = pi.z;
-    sv[lane] = perm[si] >= 0;
+    __shared__ double sh[3][256];
+    double m0 = 0.0, m1 = 0.0, m2 = 0.0;
+    for (int I = threadIdx.x; I < nb; I += 256) {
+        const double4 h = bh[I];
+        m0 = fmax(m0, h.x);
+        m1 = fmax(m1, h.y);
+        m2 = fmax(m2, h.z);
+    }
+    sh[0][threadIdx.x] = m0;
+    sh[1][threadIdx.x] = m1;
+    sh[2][threadIdx.x] = m2;
     __syncthreads();
-    double rcb2 = rcb * rcb;
-    double4 ci = bc[I], hi = bh[I];
+    for (int off = 128; off > 0; off >>= 1) {
+        if (threadIdx.x < off)
+            for (int a = 0; a < 3; ++a)
+                sh[a][threadIdx.x] = fmax(sh[a][threadIdx.x], sh[a][threadIdx.x + off]);
+        __syncthreads();
+    }
+    if (threadIdx.x < 3)
+        out[threadIdx.x] = sh[threadIdx.x][0];
+}
+
+__device__ __forceinline__ int wave_excl_scan_i(int x, int lane, int& total)
+{
+    int incl = x;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        int y = __shfl_up(incl, d);
+        if (lane >= d)
+            incl += y;
+    }
+    total = __shfl(incl, 63);
+    return incl - x;
+}
+
+// List filtering: for block I, the atoms of blocks J > I within rcb of any atom of I, in (J,
+// slot) order.  Four waves per block: wave 0 finds the candidate blocks of a chunk of 64 block
+// ids by their bounding boxes, the waves test the candidates' atoms against the block's atoms
+// (FP32 distances with a 1e-3 A margin: the filter only has to keep a superset, the masks of
+// every configuration decide at rc in FP64), and the kept atoms are written at offsets from an
+// ordered scan, so the list does not depend on scheduling.
+__global__ __launch_bounds__(256) void k_filter(int nb, const int* __restrict__ perm,
+                                                const double4* __restrict__ pos_s,
+                                                const double4* __restrict__ bc, const double4* __restrict__ bh,
+                                                double3 box, double3 binv, double rcb, int* __restrict__ row_count,
+                                                int* __restrict__ row_j, int* __restrict__ flags)
+{
+    __shared__ float4 s_i[kBlock];                 // i atoms relative to the block centre, w = real atom
+    __shared__ unsigned long long s_keep[kBlock];  // kept atoms of each candidate of the chunk
+    __shared__ int s_cand[kBlock];
+    __shared__ int s_off[kBlock + 1];
+    __shared__ int s_ncand;
+    const int I = blockIdx.x, tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+    const double4 ci = bc[I], hi = bh[I];
+    if (tid < kBlock) {
+        const int si = I * kBlock + tid;
+        const double4 pi = pos_s[si];
+        s_i[tid] = make_float4((float)mimg_fp64(pi.x - ci.x, box.x, binv.x), (float)mimg_fp64(pi.y - ci.y, box.y, binv.y),
+                               (float)mimg_fp64(pi.z - ci.z, box.z, binv.z), perm[si] >= 0 ? 1.0f : 0.0f);
+    }
+    const double rcb2 = rcb * rcb;
+    const float rf2 = (float)((rcb + 1e-3) * (rcb + 1e-3));
+    const float hxf = (float)hi.x + 1e-3f, hyf = (float)hi.y + 1e-3f, hzf = (float)hi.z + 1e-3f;
+    const float Lx = (float)box.x, Ly = (float)box.y, Lz = (float)box.z;
+    const float Lix = (float)binv.x, Liy = (float)binv.y, Liz = (float)binv.z;
     int count = 0;
     for (int J0 = I + 1; J0 < nb; J0 += kBlock) {
-        int J = J0 + lane;
-        bool cand = false;
-        if (J < nb) {
-            double4 cj = bc[J], hj = bh[J];
-            double dx = fabs(mimg_fp64(ci.x - cj.x, box.x, binv.x)) - hi.x - hj.x;
-            double dy = fabs(mimg_fp64(ci.y - cj.y, box.y, binv.y)) - hi.y - hj.y;
-            double dz = fabs(mimg_fp64(ci.z - cj.z, box.z, binv.z)) - hi.z - hj.z;
-            dx = fmax(dx, 0.0);
-            dy = fmax(dy, 0.0);
-            dz = fmax(dz, 0.0);
-            cand = dx * dx + dy * dy + dz * dz < rcb2;
+        __syncthreads();
+        if (w == 0) {
+            const int J = J0 + lane;
+            bool cand = false;
+            if (J < nb) {
+                const double4 cj = bc[J], hj = bh[J];
+                double dx = fabs(mimg_fp64(ci.x - cj.x, box.x, binv.x)) - hi.x - hj.x;
+                double dy = fabs(mimg_fp64(ci.y - cj.y, box.y, binv.y)) - hi.y - hj.y;
+                double dz = fabs(mimg_fp64(ci.z - cj.z, box.z, binv.z)) - hi.z - hj.z;
+                dx = fmax(dx, 0.0);
+                dy = fmax(dy, 0.0);
+                dz = fmax(dz, 0.0);
+                cand = dx * dx + dy * dy + dz * dz < rcb2;
+            }
+            const unsigned long long cm = __ballot(cand);
+            if (cand)
+                s_cand[__popcll(cm & ((1ull << lane) - 1ull))] = J;
+            if (lane == 0)
+                s_ncand = __popcll(cm);
         }
-        unsigned long long cm = __ballot(cand);
-        while (cm) {
-            int k = __ffsll((long long)cm) - 1;
-            cm &= cm - 1;
-            int sj = (J0 + k) * kBlock + lane;
+        __syncthreads();
+        const int nc = s_ncand;
+        for (int k = w; k < nc; k += 4) {
+            const int sj = s_cand[k] * kBlock + lane;
             bool keep = false;
             if (perm[sj] >= 0) {
-                double4 pj = pos_s[sj];
-                for (int i = 0; i < kBlock; ++i) {
-                    if (!sv[i])
-                        continue;
-                    double dx = mimg_fp64(sx[i] - pj.x, box.x, binv.x);
-                    double dy = mimg_fp64(sy[i] - pj.y, box.y, binv.y);
-                    double dz = mimg_fp64(sz[i] - pj.z, box.z, binv.z);
-                    if (dx * dx + dy * dy + dz * dz < rcb2) {
-                        keep = true;
-                        break;
+                const double4 pj = pos_s[sj];
+                const float jx = (float)mimg_fp64(pj.x - ci.x, box.x, binv.x);
+                const float jy = (float)mimg_fp64(pj.y - ci.y, box.y, binv.y);
+                const float jz = (float)mimg_fp64(pj.z - ci.z, box.z, binv.z);
+                // outside rcb of the block's box: outside rcb of every atom in it
+                const float bx = fmaxf(fabsf(jx) - hxf, 0.0f), by = fmaxf(fabsf(jy) - hyf, 0.0f),
+                            bz = fmaxf(fabsf(jz) - hzf, 0.0f);
+                if (bx * bx + by * by + bz * bz < rf2) {
+                    for (int i0 = 0; i0 < kBlock && !keep; i0 += 8) {
+#pragma unroll
+                        for (int u = 0; u < 8; ++u) {
+                            const float4 q = s_i[i0 + u];
+                            float dx = q.x - jx, dy = q.y - jy, dz = q.z - jz;
+                            dx -= Lx * rintf(dx * Lix);
+                            dy -= Ly * rintf(dy * Liy);
+                            dz -= Lz * rintf(dz * Liz);
+                            keep = keep || (q.w != 0.0f && dx * dx + dy * dy + dz * dz < rf2);
+                        }
                     }
                 }
             }
-            unsigned long long km = __ballot(keep);
-            int before = __popcll(km & ((1ull << lane) - 1ull));
-            if (keep && count + before < kMaxFiltered)
-                row_j[(size_t)I * kMaxFiltered + count + before] = sj;
-            count += __popcll(km);
+            const unsigned long long km = __ballot(keep);
+            if (lane == 0)
+                s_keep[k] = km;
         }
+        __syncthreads();
+        if (w == 0) {
+            int tot;
+            const int ex = wave_excl_scan_i(lane < nc ? __popcll(s_keep[lane]) : 0, lane, tot);
+            s_off[lane] = ex;
+            if (lane == 0)
+                s_off[kBlock] = tot;
+        }
+        __syncthreads();
+        for (int k = w; k < nc; k += 4) {
+            const unsigned long long km = s_keep[k];
+            if ((km >> lane) & 1ull) {
+                const int pos = count + s_off[k] + __popcll(km & ((1ull << lane) - 1ull));
+                if (pos < kMaxFiltered)
+                    row_j[(size_t)I * kMaxFiltered + pos] = s_cand[k] * kBlock + lane;
+            }
+        }
+        count += s_off[kBlock];
     }
-    if (lane == 0) {
+    if (tid == 0) {
         row_count[I] = min(count, kMaxFiltered);
         if (count > kMaxFiltered)
             atomicOr(flags, kFlagFilterOverflow);
@@ -466,18 +548,22 @@ __global__ void k_rev_sort(int npad, const int* __restrict__ rev_ptr, int* __res
     }
 }
 
-// Per configuration: in-cutoff bitmasks (FP64 distances, strict r < rc) and j positions
-// relative to the i-block origin.  The diagonal tile keeps only k > i.
+// Per configuration: in-cutoff bitmasks (strict r < rc, decided as in FP64) and j positions
+// relative to the i-block origin.  The diagonal tile keeps only k > i.  Each pair is first
+// classified from FP32 offsets; only pairs within a relative 1e-5 of rc^2 (far above the FP32
+// error of the offsets) are decided by the FP64 distance, so every bit equals the FP64 test.
 __global__ __launch_bounds__(256) void k_tile_refresh(int ntiles, const int* __restrict__ tile_blk,
                                                       const int* __restrict__ tile_j,
                                                       const int* __restrict__ perm,
                                                       const double4* __restrict__ pos_s,
-                                                      const double4* __restrict__ org, double3 box, double3 binv,
+                                                      const double4* __restrict__ org,
+                                                      const float4* __restrict__ off_f, double3 box, double3 binv,
                                                       double rc2, unsigned long long* __restrict__ mask,
                                                       double4* __restrict__ jrel_d, float4* __restrict__ jrel_f,
                                                       unsigned long long* __restrict__ pair_count)
 {
-    __shared__ double4 s_j[4][kBlock];
+    __shared__ double4 s_jd[4][kBlock];
+    __shared__ float4 s_jf[4][kBlock];
     int gt = blockIdx.x * blockDim.x + threadIdx.x;
     int t = gt >> 6, lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     bool act = t < ntiles;
@@ -485,27 +571,44 @@ __global__ __launch_bounds__(256) void k_tile_refresh(int ntiles, const int* __r
     int si = I * kBlock + lane;
     bool ivalid = act && perm[si] >= 0;
     double4 pi = pos_s[si];
+    float4 oi = off_f[si];
     int sj = act ? tile_j[(size_t)t * kBlock + lane] : -1;
     double4 pj = sj >= 0 ? pos_s[sj] : pi;
     bool jvalid = sj >= 0 && perm[sj] >= 0;
-    s_j[w][lane] = make_double4(pj.x, pj.y, pj.z, jvalid ? 1.0 : 0.0);
-    __syncthreads();
-    if (!act)
-        return;
     double4 o = org[I];
     double jx = mimg_fp64(pj.x - o.x, box.x, binv.x), jy = mimg_fp64(pj.y - o.y, box.y, binv.y),
            jz = mimg_fp64(pj.z - o.z, box.z, binv.z);
+    s_jd[w][lane] = make_double4(pj.x, pj.y, pj.z, 0.0);
+    s_jf[w][lane] = make_float4((float)jx, (float)jy, (float)jz, jvalid ? 1.0f : 0.0f);
+    __syncthreads();
+    if (!act)
+        return;
     jrel_d[(size_t)t * kBlock + lane] = make_double4(jx, jy, jz, 0.0);
     jrel_f[(size_t)t * kBlock + lane] = make_float4((float)jx, (float)jy, (float)jz, 0.0f);
     bool diag = tile_j[(size_t)t * kBlock] == I * kBlock;
+    const float lo2 = (float)(rc2 * (1.0 - 1e-5)), hi2 = (float)(rc2 * (1.0 + 1e-5));
+    const float Lx = (float)box.x, Ly = (float)box.y, Lz = (float)box.z;
+    const float Lix = (float)binv.x, Liy = (float)binv.y, Liz = (float)binv.z;
     unsigned long long m = 0;
     if (ivalid) {
-        for (int k = diag ? lane + 1 : 0; k < kBlock; ++k) {
-            double4 q = s_j[w][k];
-            double dx = mimg_fp64(pi.x - q.x, box.x, binv.x), dy = mimg_fp64(pi.y - q.y, box.y, binv.y),
-                   dz = mimg_fp64(pi.z - q.z, box.z, binv.z);
-            if (q.w != 0.0 && dx * dx + dy * dy + dz * dz < rc2)
-                m |= 1ull << k;
+        const int k0 = diag ? lane + 1 : 0;
+#pragma unroll 8
+        for (int k = 0; k < kBlock; ++k) {
+            const float4 q = s_jf[w][k];
+            float dx = oi.x - q.x, dy = oi.y - q.y, dz = oi.z - q.z;
+            dx -= Lx * rintf(dx * Lix);
+            dy -= Ly * rintf(dy * Liy);
+            dz -= Lz * rintf(dz * Liz);
+            const float r2 = dx * dx + dy * dy + dz * dz;
+            const bool use = k >= k0 && q.w != 0.0f;
+            bool in = use && r2 < lo2;
+            if (use && !(r2 < lo2) && r2 < hi2) {
+                const double4 p = s_jd[w][k];
+                const double ex = mimg_fp64(pi.x - p.x, box.x, binv.x), ey = mimg_fp64(pi.y - p.y, box.y, binv.y),
+                             ez = mimg_fp64(pi.z - p.z, box.z, binv.z);
+                in = ex * ex + ey * ey + ez * ez < rc2;
+            }
+            m |= (unsigned long long)in << k;
         }
     }
     mask[(size_t)t * kBlock + lane] = m;
@@ -567,7 +670,7 @@ static int refresh_tiles(amoeba_ctx* c)
     hipMemsetAsync(c->counter, 0, sizeof(unsigned long long), st);
     double3 binv = make_double3(1.0 / box.x, 1.0 / box.y, 1.0 / box.z);
     hipLaunchKernelGGL(k_tile_refresh, dim3(nblk((long)c->ntiles * kBlock, 256)), dim3(256), 0, st, c->ntiles,
-                       c->tile_blk, c->tile_j, c->perm, c->pos_s, c->blk_org, box, binv,
+                       c->tile_blk, c->tile_j, c->perm, c->pos_s, c->blk_org, c->off_f, box, binv,
                        c->prm.cutoff * c->prm.cutoff, c->tile_mask, c->jrel_d, c->jrel_f, c->counter);
     pme_bin_atoms(c);
     return AMOEBA_OK;
@@ -594,7 +697,8 @@ int build_blocklist(amoeba_ctx* c, const double* pos)
             (rc = ctx_alloc(c, (void**)&c->b_bh, sizeof(double4) * nb)) ||
             (rc = ctx_alloc(c, (void**)&c->b_rowc, sizeof(int) * nb)) ||
             (rc = ctx_alloc(c, (void**)&c->b_rowj, sizeof(int) * (size_t)nb * kMaxFiltered)) ||
-            (rc = ctx_alloc(c, (void**)&c->b_tpb, sizeof(int) * (nb + 1))))
+            (rc = ctx_alloc(c, (void**)&c->b_tpb, sizeof(int) * (nb + 1))) ||
+            (rc = ctx_alloc(c, (void**)&c->b_extent, sizeof(double) * 4)))
             return rc;
         c->b_npow2 = npow2;
     }
@@ -624,8 +728,9 @@ int build_blocklist(amoeba_ctx* c, const double* pos)
                        (const double4*)nullptr, 0.0, c->flags);
     hipMemcpyAsync(c->pos_ref, c->pos_s, sizeof(double4) * npad, hipMemcpyDeviceToDevice, st);
     hipLaunchKernelGGL(k_bbox, dim3(nb), dim3(64), 0, st, nb, c->perm, c->pos_s, box, bc, bh);
+    hipLaunchKernelGGL(k_extent_max, dim3(1), dim3(256), 0, st, nb, bh, c->b_extent);
     double3 binv = make_double3(1.0 / box.x, 1.0 / box.y, 1.0 / box.z);
-    hipLaunchKernelGGL(k_filter, dim3(nb), dim3(64), 0, st, nb, c->perm, c->pos_s, bc, bh, box, binv,
+    hipLaunchKernelGGL(k_filter, dim3(nb), dim3(256), 0, st, nb, c->perm, c->pos_s, bc, bh, box, binv,
                        c->prm.cutoff + c->prm.buffer, row_count, row_j, c->flags);
     hipLaunchKernelGGL(k_tiles_per_block, dim3(nblk(nb, 256)), dim3(256), 0, st, nb, row_count, tpb);
     if ((rc = device_scan(c, nb, tpb, t0)))
@@ -633,8 +738,23 @@ int build_blocklist(amoeba_ctx* c, const double* pos)
     int total = 0;
     hipMemcpyAsync(&total, t0 + nb, sizeof(int), hipMemcpyDeviceToHost, st);
     hipMemcpyAsync(c->flags_host, c->flags, sizeof(int), hipMemcpyDeviceToHost, st);
+    hipMemcpyAsync(c->flags_host + 4, c->b_extent, 3 * sizeof(double), hipMemcpyDeviceToHost, st);
     if ((rc = hip_check(c, hipStreamSynchronize(st), "build_blocklist")))
         return fail(rc);
+    {
+        // Every j-atom of a tile lies within cutoff + buffer of an atom of the i-block at the
+        // build, and atoms move at most buffer/2 before the list goes stale, so a tile
+        // displacement component is at most rc + 3 buffer + 4 h (h the largest block
+        // half-extent on that axis).  Below half the box edge the block-relative offsets
+        // already give the minimum image and the pair kernels skip it.
+        const double* ext = (const double*)(c->flags_host + 4);
+        bool ok = true;
+        for (int a = 0; a < 3; ++a) {
+            const double bound = c->prm.cutoff + 3.0 * c->prm.buffer + 4.0 * ext[a];
+            ok = ok && std::isfinite(ext[a]) && bound < 0.5 * c->prm.box[a] * (1.0 - 1e-3);
+        }
+        c->skip_mimg = ok;
+    }
     if (*c->flags_host & kFlagNonFinite) {
         set_error(c, AMOEBA_E_NUMERIC, "build_blocklist: non-finite position");
         return fail(AMOEBA_E_NUMERIC);

@@ -37,19 +37,14 @@ enum : int {
     kFlagBadIndex = 512,
 };
 
-// FP32 value -> 64-bit fixed point with 40 fraction bits, rounded to nearest even (|v| < 2^23).
-// a = |rint(v * 2^40)| has at most 24 significant bits, so hi = floor(a / 2^32) and
-// lo = a - hi * 2^32 in [0, 2^32) are exact floats; (hi, lo) are the two 32-bit halves of a,
-// and the sign is applied to the 64-bit integer.
-__device__ __forceinline__ unsigned long long fix40(float v)
-{
-    const float s = rintf(v * 1099511627776.0f);
-    const float a = fabsf(s);
-    const float hi = floorf(a * 2.3283064365386963e-10f);
-    const float lo = fmaf(hi, -4294967296.0f, a);
-    const unsigned long long u = ((unsigned long long)(unsigned)hi << 32) | (unsigned long long)(unsigned)lo;
-    return s < 0.0f ? 0ull - u : u;
-}
+// Fixed-point accumulation in FP64 registers and LDS: a contribution v is rounded to the
+// nearest multiple of 2^-40 (ties to even) and kept as the integer rint(v * 2^40) in a double.
+// Sums of such integers are exact, so they do not depend on the order of the additions
+// (FP64 LDS atomics give bitwise-reproducible fixed-point sums), as long as every partial sum
+// stays below 2^53 in magnitude, i.e. fields below kFixRange = 2^13 e/A^2; the value is the
+// sum times 2^-40.
+constexpr double kFixRange = 8192.0;
+__device__ __forceinline__ double fixd(float v) { return rint((double)v * 1099511627776.0); }
 
 // Minimum image used by every FP64 distance decision of the library (list build, in-cutoff
 // masks, scaled-pair correction), so that all of them agree bit for bit.
@@ -96,6 +91,8 @@ struct amoeba_ctx {
     bool cfg_valid = false;        // masks / frames / bins match pos_s
     int64_t n_scaled = 0;
     int ntiles = 0, tile_cap = 0;
+    bool skip_mimg = false;        // pair kernels may skip the minimum image (set per list build)
+    double* b_extent = nullptr;    // [4] device: largest block half-extent per axis (list build)
     int64_t n_pairs = 0;
     int last_iters = 0;
     double last_rms = 0.0;
@@ -145,6 +142,8 @@ struct amoeba_ctx {
     int32_t* bin_atoms = nullptr;  // [npad]
     int32_t* bin_count = nullptr;  // [nbricks]
     int32_t* atom_bin = nullptr;   // [npad]
+    int4* sp_base = nullptr;       // [npad] base grid point of each atom (x, y, z, real atom)
+    void* sp_w = nullptr;          // [npad][32] (R) B-spline weights m0, m1 per dimension
     rocfft_plan plan_fwd = nullptr, plan_bwd = nullptr;
     rocfft_execution_info exec_fwd = nullptr, exec_bwd = nullptr;
     void* fft_work = nullptr;
@@ -263,12 +262,12 @@ void launch_gather_vec(amoeba_ctx* c, const double* src_caller, double* dst_slot
 void launch_scatter(amoeba_ctx* c, const double* v_slot, double* out_caller);
 void launch_matvec_combine(amoeba_ctx* c, bool use_done, bool dot_pq);
 void launch_set_direction(amoeba_ctx* c, const double* src);
-int pcg_solve(amoeba_ctx* c, double tol, int max_iter, bool have_guess);
-int pcg_begin(amoeba_ctx* c, double tol);                          // initial device scalars
+void launch_gather_vec_checked(amoeba_ctx* c, const double* src_caller, double* dst_slot); // + NaN flag
+int pcg_solve(amoeba_ctx* c, double tol, int max_iter, bool have_guess, double* mu_out, double* e_pol);
+void pcg_begin(amoeba_ctx* c, double tol);                         // initial device scalars
 int pcg_start(amoeba_ctx* c, bool have_guess, double* rms_debye);   // r0, z0, p0 from v_mu
-int pcg_start_from(amoeba_ctx* c, const double* q0, double* rms_debye); // same, A mu0 given
-int pcg_run(amoeba_ctx* c, int max_iter, int start_matvecs);        // iterate from r0, z0, p0
-double compute_epol(amoeba_ctx* c);
+int pcg_start_from(amoeba_ctx* c, const double* q0);                // same, A mu0 given
+int pcg_run(amoeba_ctx* c, int max_iter, int start_matvecs, double* mu_out, double* e_pol);
 int matvec_slot(amoeba_ctx* c, bool use_done, bool dot);
 
 }  // namespace amoeba

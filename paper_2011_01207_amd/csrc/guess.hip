@@ -55,69 +55,78 @@ __device__ __forceinline__ float sigm(float a) { return 1.0f / (1.0f + __expf(-a
 static inline int nblk64(int64_t n, int b) { return (int)((n + b - 1) / b); }
 
 // ------------------------------------------------------------------------------------------
-// Radial neighbour sums over the tile list, one wave per i-block.  Lane l sums its row of
-// every tile of the block (pairs (l, k) with bit k set) and the tile's column l (pairs (i, l)
-// with bit l of row i set): rows accumulate in registers, columns of off-diagonal tiles go to
-// the tile's jbuf slot and are added to their atom by the reverse-index reduction, the
-// diagonal tile's column belongs to the block's own atom l.
+// Radial neighbour sums over the tile list: one workgroup (4 waves) per i-block, wave w takes
+// the block's tiles w, w+4, ...  Lane l sums its row of a tile (pairs (l, k) with bit k set)
+// and the tile's column l (pairs (i, l) with bit l of row i set).  Rows accumulate in
+// registers per wave and are summed over the waves in a fixed order at the end; columns of
+// off-diagonal tiles go to the tile's jbuf slot and are added to their atom by the
+// reverse-index reduction; the diagonal tile's column belongs to the block's own atom l.
 // ------------------------------------------------------------------------------------------
+__device__ __forceinline__ float rad_exp(float x) { return __expf(x); }
+__device__ __forceinline__ double rad_exp(double x) { return exp(x); }
+__device__ __forceinline__ float rad_len(float r2) { return r2 * __builtin_amdgcn_rsqf(r2); }
+__device__ __forceinline__ double rad_len(double r2) { return sqrt(r2); }
+
 template <typename R>
-__global__ __launch_bounds__(64) void k_guess_radial(const int* __restrict__ blk_tile0,
-                                                     const unsigned long long* __restrict__ tile_mask,
-                                                     const typename V4R<R>::T* __restrict__ jrel,
-                                                     const typename V4R<R>::T* __restrict__ off, R L0, R L1, R L2,
-                                                     R Li0, R Li1, R Li2, double* __restrict__ eipart,
-                                                     R* __restrict__ jbuf)
+__device__ __forceinline__ void radial_add(R dx, R dy, R dz, R L0, R L1, R L2, R Li0, R Li1, R Li2, R (&acc)[3])
+{
+    dx -= L0 * rint(dx * Li0);
+    dy -= L1 * rint(dy * Li1);
+    dz -= L2 * rint(dz * Li2);
+    const R r = rad_len(dx * dx + dy * dy + dz * dz);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const R u = (r - (R)kRadialC[c]) * (R)kRadialInvW;
+        acc[c] += rad_exp(-u * u);
+    }
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_guess_radial(const int* __restrict__ blk_tile0,
+                                                      const unsigned long long* __restrict__ tile_mask,
+                                                      const typename V4R<R>::T* __restrict__ jrel,
+                                                      const typename V4R<R>::T* __restrict__ off, R L0, R L1, R L2,
+                                                      R Li0, R Li1, R Li2, double* __restrict__ eipart,
+                                                      R* __restrict__ jbuf)
 {
     using R4 = typename V4R<R>::T;
     __shared__ R4 s_i[kBlock];
-    __shared__ R4 s_j[kBlock];
-    __shared__ unsigned long long s_m[kBlock];
-    const int I = blockIdx.x, lane = threadIdx.x;
+    __shared__ R4 s_j[4][kBlock];
+    __shared__ unsigned long long s_m[4][kBlock];
+    __shared__ R s_row[4][3][kBlock];
+    const int I = blockIdx.x, tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
     const int si = I * kBlock + lane;
-    const R4 oi = off[si];
-    s_i[lane] = oi;
-    const int t0 = blk_tile0[I], t1 = blk_tile0[I + 1];
+    if (tid < kBlock)
+        s_i[tid] = off[I * kBlock + tid];
+    __syncthreads();
+    const R4 oi = s_i[lane];
+    const int t0 = blk_tile0[I], nt = blk_tile0[I + 1] - t0;
     R row[3] = {0, 0, 0};
-    for (int t = t0; t < t1; ++t) {
-        __syncthreads();
-        s_j[lane] = jrel[(size_t)t * kBlock + lane];
-        s_m[lane] = tile_mask[(size_t)t * kBlock + lane];
-        __syncthreads();
-        unsigned long long m = s_m[lane];
+    for (int tt = w; tt < nt; tt += 4) {
+        const int t = t0 + tt;
+        s_j[w][lane] = jrel[(size_t)t * kBlock + lane];
+        s_m[w][lane] = tile_mask[(size_t)t * kBlock + lane];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        unsigned long long m = s_m[w][lane];
         while (m) {
             const int k = __ffsll((long long)m) - 1;
             m &= m - 1ull;
-            const R4 q = s_j[k];
-            R dx = oi.x - q.x, dy = oi.y - q.y, dz = oi.z - q.z;
-            dx -= L0 * rint(dx * Li0);
-            dy -= L1 * rint(dy * Li1);
-            dz -= L2 * rint(dz * Li2);
-            const R r = sqrt(dx * dx + dy * dy + dz * dz);
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                const R u = (r - (R)kRadialC[c]) * (R)kRadialInvW;
-                row[c] += exp(-u * u);
-            }
+            const R4 q = s_j[w][k];
+            radial_add(oi.x - q.x, oi.y - q.y, oi.z - q.z, L0, L1, L2, Li0, Li1, Li2, row);
         }
         R col[3] = {0, 0, 0};
-        const R4 q = s_j[lane];
+        const R4 q = s_j[w][lane];
+#pragma unroll 8
         for (int i = 0; i < kBlock; ++i) {
-            if ((s_m[i] >> lane) & 1ull) {
+            const bool set = (s_m[w][i] >> lane) & 1ull;
+            if (set) {
                 const R4 p = s_i[i];
-                R dx = p.x - q.x, dy = p.y - q.y, dz = p.z - q.z;
-                dx -= L0 * rint(dx * Li0);
-                dy -= L1 * rint(dy * Li1);
-                dz -= L2 * rint(dz * Li2);
-                const R r = sqrt(dx * dx + dy * dy + dz * dz);
-#pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    const R u = (r - (R)kRadialC[c]) * (R)kRadialInvW;
-                    col[c] += exp(-u * u);
-                }
+                radial_add(p.x - q.x, p.y - q.y, p.z - q.z, L0, L1, L2, Li0, Li1, Li2, col);
             }
         }
-        if (t == t0) {
+        if (tt == 0) {
 #pragma unroll
             for (int c = 0; c < 3; ++c)
                 row[c] += col[c];
@@ -126,10 +135,21 @@ __global__ __launch_bounds__(64) void k_guess_radial(const int* __restrict__ blk
             for (int c = 0; c < 3; ++c)
                 jbuf[((size_t)t * 3 + c) * kBlock + lane] = col[c];
         }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
 #pragma unroll
     for (int c = 0; c < 3; ++c)
-        eipart[3 * (size_t)si + c] = (double)row[c];
+        s_row[w][c][lane] = row[c];
+    __syncthreads();
+    if (tid < 3 * kBlock) {
+        const int c = tid / kBlock, l = tid % kBlock;
+        const double v = (double)s_row[0][c][l] + (double)s_row[1][c][l] + (double)s_row[2][c][l] +
+                         (double)s_row[3][c][l];
+        eipart[3 * ((size_t)I * kBlock + l) + c] = v;
+    }
+    (void)si;
 }
 
 // next basis vector: v = alpha (ereal + cself vprev), or v0 = alpha e when ereal is NULL; the
@@ -470,30 +490,39 @@ __global__ __launch_bounds__(64) void k_guess_grad(int64_t n_batch, int64_t n_ro
         lossp[blockIdx.x] = lacc;
 }
 
-// Sum of the workgroup partials (fixed order, FP64) per parameter; then either the gradient is
-// written out or an Adam step is applied.  The loss is summed by thread 0 of workgroup 0.
+// Sum of the workgroup partials per parameter in FP64, in a fixed order: 64 parameters per
+// workgroup, four groups of partials per parameter (g, g+4, ...) combined in LDS in group
+// order.  Then the gradient is written out and/or an Adam step is applied -- skipped when the
+// gradient kernel flagged an index outside the data, so a rejected step changes nothing.  The
+// loss is summed by thread 0 of workgroup 0.
 __global__ __launch_bounds__(256) void k_guess_reduce(int nwg, const float* __restrict__ part,
                                                       const double* __restrict__ lossp, float* __restrict__ grad,
                                                       float* __restrict__ w, float* __restrict__ m,
                                                       float* __restrict__ v, int adam, float lr, float bc1,
-                                                      float bc2, double* __restrict__ loss)
+                                                      float bc2, double* __restrict__ loss,
+                                                      const int* __restrict__ flags)
 {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p == 0) {
+    __shared__ double s_sum[4][64];
+    const int tid = threadIdx.x, g = tid >> 6, pl = tid & 63;
+    const int p = blockIdx.x * 64 + pl;
+    if (blockIdx.x == 0 && tid == 0) {
         double l = 0.0;
-        for (int g = 0; g < nwg; ++g)
-            l += lossp[g];
+        for (int q = 0; q < nwg; ++q)
+            l += lossp[q];
         loss[0] = l;
     }
-    if (p >= kNP)
+    double acc = 0.0;
+    if (p < kNP)
+        for (int q = g; q < nwg; q += 4)
+            acc += (double)part[(size_t)q * kNP + p];
+    s_sum[g][pl] = acc;
+    __syncthreads();
+    if (g != 0 || p >= kNP)
         return;
-    double s = 0.0;
-    for (int g = 0; g < nwg; ++g)
-        s += (double)part[(size_t)g * kNP + p];
-    const float gr = (float)s;
+    const float gr = (float)(((s_sum[0][pl] + s_sum[1][pl]) + s_sum[2][pl]) + s_sum[3][pl]);
     if (grad)
         grad[p] = gr;
-    if (adam) {
+    if (adam && !(flags[0] & kFlagBadIndex)) {
         const float mm = 0.9f * m[p] + 0.1f * gr;
         const float vv = 0.999f * v[p] + 0.001f * gr * gr;
         m[p] = mm;
@@ -547,7 +576,7 @@ template <typename R> static void launch_radial(amoeba_ctx* c, R* jbuf, const vo
 {
     using R4 = typename V4R<R>::T;
     const R L0 = (R)c->prm.box[0], L1 = (R)c->prm.box[1], L2 = (R)c->prm.box[2];
-    hipLaunchKernelGGL(k_guess_radial<R>, dim3(c->nb), dim3(64), 0, c->stream, c->blk_tile0, c->tile_mask,
+    hipLaunchKernelGGL(k_guess_radial<R>, dim3(c->nb), dim3(256), 0, c->stream, c->blk_tile0, c->tile_mask,
                        (const R4*)jrel, (const R4*)off, L0, L1, L2, (R)(1.0 / c->prm.box[0]),
                        (R)(1.0 / c->prm.box[1]), (R)(1.0 / c->prm.box[2]), c->eipart, jbuf);
 }
@@ -675,25 +704,19 @@ static int guess_grad(amoeba_ctx* c, const float* feat, const float* basis, cons
         const float lscale = (float)(kDebye * kDebye / (double)n_batch);
         hipLaunchKernelGGL(k_guess_grad, dim3(nwg), dim3(64), 0, st, n_batch, n_rows, idx, c->g_model, feat, basis,
                            target, lscale, c->g_part, c->g_lossp, c->flags);
-        // an invalid index leaves the model untouched: the reduction runs without the update
-        // only after the flags are known, so the Adam step is a second, separate launch
-        hipLaunchKernelGGL(k_guess_reduce, dim3(nblk64(kNP, 256)), dim3(256), 0, st, nwg, c->g_part, c->g_lossp,
-                           grad_out, c->g_model, c->g_adam_m, c->g_adam_v, 0, lr, bc1, bc2, c->g_scal);
+        hipLaunchKernelGGL(k_guess_reduce, dim3((kNP + 63) / 64), dim3(256), 0, st, nwg, c->g_part, c->g_lossp,
+                           grad_out, c->g_model, c->g_adam_m, c->g_adam_v, adam ? 1 : 0, lr, bc1, bc2, c->g_scal,
+                           c->flags);
     }
-    int f = 0, rc = read_flags(c, &f);
+    hipMemcpyAsync(c->flags_host, c->flags, sizeof(int), hipMemcpyDeviceToHost, st);
+    hipMemcpyAsync(c->g_scal_host, c->g_scal, sizeof(double), hipMemcpyDeviceToHost, st);
+    int rc = hip_check(c, hipStreamSynchronize(st), who);
     if (rc)
         return rc;
-    if (f & kFlagBadIndex)
+    if (c->flags_host[0] & kFlagBadIndex)
         return set_error(c, AMOEBA_E_INVALID, std::string(who) + ": idx entry outside [0, n_rows)");
-    if (adam) {
-        StageTimer tm(c, AMOEBA_T_GUESS);
-        hipLaunchKernelGGL(k_guess_reduce, dim3(nblk64(kNP, 256)), dim3(256), 0, st, nwg, c->g_part, c->g_lossp,
-                           (float*)nullptr, c->g_model, c->g_adam_m, c->g_adam_v, 1, lr, bc1, bc2, c->g_scal + 1);
+    if (adam)
         c->g_step += 1;
-    }
-    hipMemcpyAsync(c->g_scal_host, c->g_scal, sizeof(double), hipMemcpyDeviceToHost, st);
-    if ((rc = hip_check(c, hipStreamSynchronize(st), who)))
-        return rc;
     if (loss_out)
         *loss_out = c->g_scal_host[0];
     return AMOEBA_OK;

@@ -4,10 +4,12 @@
 //
 // All vectors are FP64 in slot order (npad x 3), as are every dot product and the convergence
 // test, whatever the precision of the matrix-vector product.  Scalars live on the device
-// (PcgScalars): gamma and beta are computed by the last workgroup of the reductions, so an
-// iteration needs no host round trip.  Once converged, a device flag makes the remaining
-// queued kernels return at entry; the host reads the scalars of iteration k through an event
-// while iteration k+1 is already queued.
+// (PcgScalars): every workgroup of the kernel that needs gamma or beta sums the previous
+// kernel's partials itself, so an iteration needs no host round trip.  Once converged, a
+// device flag makes the remaining queued kernels return at entry; the host reads the scalars
+// of iteration k through an event while iteration k+1 is already queued.  A solve waits on the
+// host only for these per-iteration events and once at the end, where the outputs (E_pol, mu
+// in caller order) and, in mixed precision, the true-residual check are queued together.
 #include "common.h"
 #include "reduce.h"
 
@@ -30,6 +32,31 @@ __global__ void k_gather_vec(int npad, const int* __restrict__ perm, const doubl
     int a = perm[s];
     for (int c = 0; c < 3; ++c)
         dst[3 * (size_t)s + c] = a >= 0 ? src[3 * (size_t)a + c] : 0.0;
+}
+
+// gather that also flags a non-finite input value (checked once, at the end of the call)
+__global__ void k_gather_vec_checked(int npad, const int* __restrict__ perm, const double* __restrict__ src,
+                                     double* __restrict__ dst, int* __restrict__ flags)
+{
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= npad)
+        return;
+    int a = perm[s];
+    bool bad = false;
+    for (int c = 0; c < 3; ++c) {
+        const double v = a >= 0 ? src[3 * (size_t)a + c] : 0.0;
+        bad = bad || !isfinite(v);
+        dst[3 * (size_t)s + c] = v;
+    }
+    if (bad)
+        atomicOr(flags, kFlagNonFinite);
+}
+
+__global__ void k_pcg_begin(PcgScalars* __restrict__ sc, double tol)
+{
+    PcgScalars init{};
+    init.tol = tol;
+    *sc = init;
 }
 
 __global__ void k_scatter_vec(int npad, const int* __restrict__ perm, const double* __restrict__ src,
@@ -234,6 +261,12 @@ void launch_gather_vec(amoeba_ctx* c, const double* src_caller, double* dst_slot
                        dst_slot);
 }
 
+void launch_gather_vec_checked(amoeba_ctx* c, const double* src_caller, double* dst_slot)
+{
+    hipLaunchKernelGGL(k_gather_vec_checked, dim3(nblk(c->npad, 256)), dim3(256), 0, c->stream, c->npad, c->perm,
+                       src_caller, dst_slot, c->flags);
+}
+
 void launch_scatter(amoeba_ctx* c, const double* v_slot, double* out_caller)
 {
     hipLaunchKernelGGL(k_scatter_vec, dim3(nblk(c->npad, 256)), dim3(256), 0, c->stream, c->npad, c->perm, v_slot,
@@ -296,8 +329,9 @@ static int enqueue_iteration(amoeba_ctx* c, int it)
 }
 
 // Iterations first..first+budget-1 until the device flag says done.  Host reads lag the device
-// by one queued iteration.  Returns a HIP/rocFFT error code or AMOEBA_OK.
-static int run_iterations(amoeba_ctx* c, int first, int budget)
+// by one queued iteration; *last receives the scalars after the last iteration the host saw
+// (later queued iterations return at entry).  Returns a HIP/rocFFT error code or AMOEBA_OK.
+static int run_iterations(amoeba_ctx* c, int first, int budget, PcgScalars* last)
 {
     hipStream_t st = c->stream;
     int enq = 0, chk = 0, rc;
@@ -313,32 +347,49 @@ static int run_iterations(amoeba_ctx* c, int first, int budget)
             ++chk;
             if ((rc = hip_check(c, hipEventSynchronize(c->ev[chk & 1]), "pcg iteration")))
                 return rc;
-            if (c->sc_host[chk & 1].done || chk >= budget)
-                break;
+            if (c->sc_host[chk & 1].done || chk >= budget) {
+                *last = c->sc_host[chk & 1];
+                return AMOEBA_OK;
+            }
         }
     }
-    return hip_check(c, hipStreamSynchronize(st), "pcg loop");
+}
+
+// scalars and error flags in one round trip
+static int read_state(amoeba_ctx* c, PcgScalars* out, int* flags)
+{
+    hipMemcpyAsync(&c->sc_host[0], c->sc, sizeof(PcgScalars), hipMemcpyDeviceToHost, c->stream);
+    hipMemcpyAsync(c->flags_host, c->flags, sizeof(int), hipMemcpyDeviceToHost, c->stream);
+    int rc = hip_check(c, hipStreamSynchronize(c->stream), "read scalars");
+    *out = c->sc_host[0];
+    *flags = c->flags_host[0];
+    return rc;
 }
 
 static int read_scalars(amoeba_ctx* c, PcgScalars* out)
 {
-    hipMemcpyAsync(&c->sc_host[0], c->sc, sizeof(PcgScalars), hipMemcpyDeviceToHost, c->stream);
-    int rc = hip_check(c, hipStreamSynchronize(c->stream), "read scalars");
-    *out = c->sc_host[0];
+    int f = 0;
+    int rc = read_state(c, out, &f);
+    if (!rc && (f & kFlagNonFinite))
+        return set_error(c, AMOEBA_E_NUMERIC, "non-finite value in e_perm or mu_guess");
     return rc;
 }
 
-// Initial device scalars of a solve (tolerance; everything else zero).
-int pcg_begin(amoeba_ctx* c, double tol)
+static void launch_epol(amoeba_ctx* c)
 {
-    PcgScalars init{};
-    init.tol = tol;
-    c->sc_host[0] = init;
-    hipMemcpyAsync(c->sc, &c->sc_host[0], sizeof(PcgScalars), hipMemcpyHostToDevice, c->stream);
-    return hip_check(c, hipStreamSynchronize(c->stream), "pcg init");
+    StageTimer tm(c, AMOEBA_T_PCG);
+    hipLaunchKernelGGL(k_epol, dim3(kRedBlocks), dim3(256), 0, c->stream, c->npad, c->v_mu, c->v_e, part_vec(c));
+    hipLaunchKernelGGL(k_epol_finalize, dim3(1), dim3(256), 0, c->stream, kRedBlocks, part_vec(c), c->sc);
 }
 
-// r0 = e - A mu0, z0 = alpha r0, p0 = z0 from v_mu (have_guess) or mu0 = 0; *rms_debye = rms of z0.
+// Initial device scalars of a solve (tolerance; everything else zero); no host wait.
+void pcg_begin(amoeba_ctx* c, double tol)
+{
+    hipLaunchKernelGGL(k_pcg_begin, dim3(1), dim3(1), 0, c->stream, c->sc, tol);
+}
+
+// r0 = e - A mu0, z0 = alpha r0, p0 = z0 from v_mu (have_guess) or mu0 = 0.  With rms_debye
+// non-NULL the host waits for the rms of z0 (and the input checks).
 int pcg_start(amoeba_ctx* c, bool have_guess, double* rms_debye)
 {
     int rc;
@@ -351,91 +402,101 @@ int pcg_start(amoeba_ctx* c, bool have_guess, double* rms_debye)
         hipMemsetAsync(c->v_mu, 0, sizeof(double) * 3 * (size_t)c->npad, c->stream);
         launch_init_residual(c, nullptr, 0);
     }
+    if (!rms_debye)
+        return AMOEBA_OK;
     PcgScalars s;
     if ((rc = read_scalars(c, &s)))
         return rc;
-    if (rms_debye)
-        *rms_debye = s.rms;
+    *rms_debye = s.rms;
     return AMOEBA_OK;
 }
 
 // Same with A mu0 already known (q0; NULL for mu0 = 0, v_mu must then be zero).
-int pcg_start_from(amoeba_ctx* c, const double* q0, double* rms_debye)
+int pcg_start_from(amoeba_ctx* c, const double* q0)
 {
     launch_init_residual(c, q0, 0);
-    PcgScalars s;
-    int rc = read_scalars(c, &s);
-    if (rms_debye)
-        *rms_debye = s.rms;
-    return rc;
+    return AMOEBA_OK;
 }
 
 // Iterate from the state left by pcg_start (v_mu, r, z, p and the scalars of iteration 0)
-// until rms(z) < tol or max_iter iterations.  start_matvecs: products already spent on the
-// starting point (accounting only).
-int pcg_run(amoeba_ctx* c, int max_iter, int start_matvecs)
+// until rms(z) < tol or max_iter iterations, then write mu (caller order) and E_pol.
+// start_matvecs: products already spent on the starting point (accounting only).
+int pcg_run(amoeba_ctx* c, int max_iter, int start_matvecs, double* mu_out, double* e_pol)
 {
-    PcgScalars s;
-    int rc;
-    if ((rc = read_scalars(c, &s)))
-        return rc;
+    PcgScalars s{};
+    int rc, f = 0;
     int used = 0;
     int extra_matvecs = 0;
     bool checked_true = !c->mixed;
+    bool first = true;
     while (true) {
-        if (!s.done && used < max_iter) {
-            if ((rc = run_iterations(c, used, max_iter - used)))
+        if (first || (!s.done && used < max_iter)) {
+            // the first round always runs: the host has not seen the starting scalars yet (a
+            // start that is already converged makes the queued kernels return at entry)
+            first = false;
+            if (max_iter > used) {
+                if ((rc = run_iterations(c, used, max_iter - used, &s)))
+                    return rc;
+                used = s.iters;
+            } else if ((rc = read_scalars(c, &s))) {
                 return rc;
-            if ((rc = read_scalars(c, &s)))
-                return rc;
-            used = s.iters;
+            }
         }
         if (s.status == 2)
-            return set_error(c, AMOEBA_E_NUMERIC, "PCG breakdown (non-positive curvature or non-finite residual)");
-        if (s.status != 1 || checked_true)
-            break;
+            break;   // breakdown (or a non-finite input), told apart below
         // Mixed precision: confirm convergence on the true residual e - A mu (FP64 vectors); if it
-        // fails, PCG restarts from the true residual with the remaining iteration budget.
-        checked_true = true;
-        ++extra_matvecs;
-        launch_set_direction(c, c->v_mu);
-        if ((rc = matvec_slot(c, false, false)))
+        // fails, PCG restarts from the true residual with the remaining iteration budget.  The
+        // outputs are queued behind it and kept when the check passes.
+        const bool check = s.status == 1 && !checked_true;
+        if (check) {
+            checked_true = true;
+            ++extra_matvecs;
+            launch_set_direction(c, c->v_mu);
+            if ((rc = matvec_slot(c, false, false)))
+                return rc;
+            launch_init_residual(c, c->v_q, used);
+        }
+        launch_epol(c);
+        launch_scatter(c, c->v_mu, mu_out);
+        if ((rc = read_state(c, &s, &f)))
             return rc;
-        launch_init_residual(c, c->v_q, used);
-        if ((rc = read_scalars(c, &s)))
+        if (f & kFlagNonFinite)
+            return set_error(c, AMOEBA_E_NUMERIC, "non-finite value in e_perm or mu_guess");
+        if (check) {
+            s.iters = used;
+            if (!s.done) {
+                checked_true = false;
+                if (used < max_iter)
+                    continue;
+            }
+        }
+        break;
+    }
+    if (s.status == 2) {
+        int fl = 0;
+        if ((rc = read_state(c, &s, &fl)))
             return rc;
-        s.iters = used;
-        if (s.done)
-            break;
-        checked_true = false;
-        if (used >= max_iter)
-            break;
+        if (fl & kFlagNonFinite)
+            return set_error(c, AMOEBA_E_NUMERIC, "non-finite value in e_perm or mu_guess");
+        return set_error(c, AMOEBA_E_NUMERIC, "PCG breakdown (non-positive curvature or non-finite residual)");
     }
     c->last_iters = used;
     c->last_rms = s.rms;
     c->matvecs += used + start_matvecs + extra_matvecs;
+    if (e_pol)
+        *e_pol = -0.5 * kCoulomb * s.epol_acc;
     return s.status == 1 ? AMOEBA_OK : AMOEBA_NOT_CONVERGED;
 }
 
-// Solve A mu = e (v_e, slot order).  On entry v_mu holds the guess if have_guess.
-int pcg_solve(amoeba_ctx* c, double tol, int max_iter, bool have_guess)
+// Solve A mu = e (v_e, slot order); on entry v_mu holds the guess if have_guess.
+int pcg_solve(amoeba_ctx* c, double tol, int max_iter, bool have_guess, double* mu_out, double* e_pol)
 {
-    int rc;
-    if ((rc = pcg_begin(c, tol)))
+    pcg_begin(c, tol);
+    int rc = pcg_start(c, have_guess, nullptr);
+    if (rc)
         return rc;
-    if ((rc = pcg_start(c, have_guess, nullptr)))
-        return rc;
-    return pcg_run(c, max_iter, have_guess ? 1 : 0);
+    return pcg_run(c, max_iter, have_guess ? 1 : 0, mu_out, e_pol);
 }
 
-double compute_epol(amoeba_ctx* c)
-{
-    hipLaunchKernelGGL(k_epol, dim3(kRedBlocks), dim3(256), 0, c->stream, c->npad, c->v_mu, c->v_e, part_vec(c));
-    hipLaunchKernelGGL(k_epol_finalize, dim3(1), dim3(256), 0, c->stream, kRedBlocks, part_vec(c), c->sc);
-    PcgScalars s;
-    if (read_scalars(c, &s))
-        return 0.0;
-    return -0.5 * kCoulomb * s.epol_acc;
-}
 
 }  // namespace amoeba

@@ -66,6 +66,46 @@ __device__ __forceinline__ void grid_coord(double x, double kl, int K, int& fl, 
         fl += K;
 }
 
+// Per configuration: each atom's base grid point and its order-5 weights and first derivatives
+// per dimension (the positions do not change during a solve, so the spread and the gather of
+// every matrix-vector product read them instead of recomputing them).  Layout per slot:
+// w[32 s + 10 d + t] = M5(w_d + t), w[32 s + 10 d + 5 + t] = M5'(w_d + t).
+constexpr int kSpStride = 32;
+
+template <typename R>
+__global__ void k_spline_table(int npad, const int* __restrict__ perm, const double4* __restrict__ pos_s,
+                               double3 kl, int3 K, int4* __restrict__ base, R* __restrict__ w)
+{
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= npad)
+        return;
+    if (perm[s] < 0) {
+        base[s] = make_int4(0, 0, 0, 0);
+        for (int q = 0; q < kSpStride; ++q)
+            w[(size_t)s * kSpStride + q] = (R)0;
+        return;
+    }
+    const double4 p = pos_s[s];
+    int f[3];
+    double u[3];
+    grid_coord(p.x, kl.x, K.x, f[0], u[0]);
+    grid_coord(p.y, kl.y, K.y, f[1], u[1]);
+    grid_coord(p.z, kl.z, K.z, f[2], u[2]);
+    base[s] = make_int4(f[0], f[1], f[2], 1);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        R m0[5], m1[5], m2[5];
+        spline5<R, false>((R)u[d], m0, m1, m2);
+#pragma unroll
+        for (int t = 0; t < 5; ++t) {
+            w[(size_t)s * kSpStride + 10 * d + t] = m0[t];
+            w[(size_t)s * kSpStride + 10 * d + 5 + t] = m1[t];
+        }
+    }
+    w[(size_t)s * kSpStride + 30] = (R)0;
+    w[(size_t)s * kSpStride + 31] = (R)0;
+}
+
 // ------------------------------------------------------------------------------------------
 // setup: B-spline moduli and influence function theta(m) = B(m) C(m) on the half grid
 // ------------------------------------------------------------------------------------------
@@ -188,9 +228,9 @@ __global__ __launch_bounds__(256) void k_bin_sort(const int* __restrict__ bin_st
 // ------------------------------------------------------------------------------------------
 template <bool FIX> struct LdsAcc;
 template <> struct LdsAcc<true> {
-    using T = unsigned long long;
-    __device__ static void add(T* p, float v) { atomicAdd(p, fix40(v)); }
-    __device__ static float get(const T* p) { return (float)((double)(long long)(*p) * kFixInv); }
+    using T = double;   // fixed point, integer-valued FP64 (see fixd)
+    __device__ static void add(T* p, float v) { atomicAdd(p, fixd(v)); }
+    __device__ static float get(const T* p) { return (float)(*p * kFixInv); }
 };
 template <> struct LdsAcc<false> {
     using T = double;
@@ -352,21 +392,6 @@ __global__ __launch_bounds__(256) void k_spread(int3 K, int3 nbr, const int* __r
     }
 }
 
-template <typename R>
-__global__ void k_convolve(size_t n, typename V4p<R>::C* __restrict__ g, const R* __restrict__ theta,
-                           const PcgScalars* __restrict__ sc, int use_done)
-{
-    if (use_done && sc->done)
-        return;
-    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n)
-        return;
-    R th = theta[i];
-    typename V4p<R>::C v = g[i];
-    v.x *= th;
-    v.y *= th;
-    g[i] = v;
-}
 
 // ------------------------------------------------------------------------------------------
 // gather: E_i = - sum_k grad W_i(k) psi(k)
@@ -426,18 +451,20 @@ __device__ __forceinline__ void gather_field(const double4 p, double3 kl, int3 K
 template <typename R, bool FIX>
 __global__ __launch_bounds__(256) void k_spread_dip(int3 K, int3 nbr, const int* __restrict__ bin_start,
                                                     const int* __restrict__ bin_atoms,
-                                                    const double4* __restrict__ pos_s, double3 kl,
-                                                    const typename V4p<R>::T* __restrict__ src, R* __restrict__ grid,
-                                                    const PcgScalars* __restrict__ sc, int use_done)
+                                                    const int4* __restrict__ sp_base, const R* __restrict__ sp_w,
+                                                    double3 kl, const typename V4p<R>::T* __restrict__ src,
+                                                    R* __restrict__ grid, const PcgScalars* __restrict__ sc,
+                                                    int use_done)
 {
     using R4 = typename V4p<R>::T;
     using AT = typename LdsAcc<FIX>::T;
-    constexpr int CH = sizeof(R) == 4 ? 256 : 128;  // candidate atoms per chunk
+    constexpr int CH = 128;                           // candidate atoms per chunk
     __shared__ AT acc[kBrick * kBrick * kBrick];
     __shared__ R e_sp[6][5][CH];                      // x0 x1 y0 y1 z0 z1, compacted to the inside lines
     __shared__ R e_mu[3][CH];
     __shared__ int e_loc[3][CH];                      // per dim: count (3 bits) + 5 x 3-bit brick-local lines
     __shared__ int e_pre[CH + 1];
+    __shared__ unsigned short rowmap[CH * 25];       // (entry << 5) | row of every (entry, x, y) row
     __shared__ int bl[3][3], bnum[3];
     __shared__ int rs[27], rn[27], pre[28];
     __shared__ int n_e;
@@ -490,13 +517,11 @@ __global__ __launch_bounds__(256) void k_spread_dip(int3 K, int3 nbr, const int*
             while (item >= pre[q + 1])
                 ++q;
             const int s = bin_atoms[rs[q] + item - pre[q]];
-            const double4 pp = pos_s[s];
-            const double xyz[3] = {pp.x, pp.y, pp.z};
-            int fl[3], loc[3] = {0, 0, 0}, cnt[3] = {0, 0, 0};
-            double wv[3];
+            const int4 fb = sp_base[s];
+            const int fl[3] = {fb.x, fb.y, fb.z};
+            int loc[3] = {0, 0, 0}, cnt[3] = {0, 0, 0};
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
-                grid_coord(xyz[d], klv[d], kk[d], fl[d], wv[d]);
 #pragma unroll
                 for (int tt = 0; tt < 5; ++tt) {
                     int g = fl[d] - tt;
@@ -515,10 +540,21 @@ __global__ __launch_bounds__(256) void k_spread_dip(int3 K, int3 nbr, const int*
             e_mu[0][e] = mu.x;
             e_mu[1][e] = mu.y;
             e_mu[2][e] = mu.z;
+            // the atom's table record (32 values, 16-byte aligned) in eight vector loads
+            R ws[kSpStride];
+            {
+                const R4* rec = reinterpret_cast<const R4*>(sp_w + (size_t)s * kSpStride);
+#pragma unroll
+                for (int q = 0; q < kSpStride / 4; ++q) {
+                    const R4 v = rec[q];
+                    ws[4 * q] = v.x;
+                    ws[4 * q + 1] = v.y;
+                    ws[4 * q + 2] = v.z;
+                    ws[4 * q + 3] = v.w;
+                }
+            }
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
-                R m0[5], m1[5], m2[5];
-                spline5<R, false>((R)wv[d], m0, m1, m2);
                 int j = 0;
 #pragma unroll
                 for (int tt = 0; tt < 5; ++tt) {
@@ -526,8 +562,8 @@ __global__ __launch_bounds__(256) void k_spread_dip(int3 K, int3 nbr, const int*
                     g += g < 0 ? kk[d] : 0;
                     int l = g - lo[d];
                     if (l >= 0 && l < ext[d]) {
-                        e_sp[2 * d][j][e] = m0[tt];
-                        e_sp[2 * d + 1][j][e] = m1[tt] * (R)klv[d];
+                        e_sp[2 * d][j][e] = ws[10 * d + tt];
+                        e_sp[2 * d + 1][j][e] = ws[10 * d + 5 + tt] * (R)klv[d];
                         ++j;
                     }
                 }
@@ -564,19 +600,19 @@ __global__ __launch_bounds__(256) void k_spread_dip(int3 K, int3 nbr, const int*
                 e_pre[CH] = run;  // total (entries >= n_e count zero rows)
         }
         __syncthreads();
+        // row map: every (entry, x line, y line) row of the chunk, numbered by the prefix sums
+        for (int e = tid; e < ne; e += 256) {
+            const int o = e_pre[e], n = e_pre[e + 1] - o;
+            for (int r = 0; r < n; ++r)
+                rowmap[o + r] = (unsigned short)((e << 5) | r);
+        }
+        __syncthreads();
         // phase 2
         const int rows = e_pre[ne];
         for (int item = tid; item < rows; item += 256) {
-            int lo_e = 0, hi_e = ne - 1;
-            while (lo_e < hi_e) {
-                int mid = (lo_e + hi_e + 1) >> 1;
-                if (e_pre[mid] <= item)
-                    lo_e = mid;
-                else
-                    hi_e = mid - 1;
-            }
-            const int e = lo_e;
-            const int r = item - e_pre[e];
+            const int rm = rowmap[item];
+            const int e = rm >> 5;
+            const int r = rm & 31;
             const int lx = e_loc[0][e], ly = e_loc[1][e], lz = e_loc[2][e];
             const int cy = ly & 7, cz = lz & 7;
             const int ix = r / cy, iy = r - ix * cy;
@@ -613,7 +649,8 @@ constexpr int kReg = kBrick + 4;
 template <typename R, int MODE>
 __global__ __launch_bounds__(256) void k_gather_brick(int3 K, int3 nbr, const int* __restrict__ bin_start,
                                                       const int* __restrict__ bin_atoms,
-                                                      const double4* __restrict__ pos_s, double3 kl,
+                                                      const int4* __restrict__ sp_base, const R* __restrict__ sp_w,
+                                                      double3 kl,
                                                       const R* __restrict__ psi, const double4* __restrict__ par,
                                                       const double* __restrict__ p, double self,
                                                       const double* __restrict__ eipart, const R* __restrict__ jbuf,
@@ -652,16 +689,19 @@ __global__ __launch_bounds__(256) void k_gather_brick(int3 K, int3 nbr, const in
         if (ai < na) {
             s = bin_atoms[a0 + ai];
             if (sub < 5) {
-                const double4 pp = pos_s[s];
-                int fx, fy, fz;
-                double wx, wy, wz;
-                grid_coord(pp.x, kl.x, K.x, fx, wx);
-                grid_coord(pp.y, kl.y, K.y, fy, wy);
-                grid_coord(pp.z, kl.z, K.z, fz, wz);
-                R x0[5], x1[5], y0[5], y1[5], z0[5], z1[5], dum[5];
-                spline5<R, false>((R)wx, x0, x1, dum);
-                spline5<R, false>((R)wy, y0, y1, dum);
-                spline5<R, false>((R)wz, z0, z1, dum);
+                const int4 fb = sp_base[s];
+                const int fx = fb.x, fy = fb.y, fz = fb.z;
+                const R* ws = sp_w + (size_t)s * kSpStride;
+                R x0[5], x1[5], y0[5], y1[5], z0[5], z1[5];
+#pragma unroll
+                for (int t = 0; t < 5; ++t) {
+                    x0[t] = ws[t];
+                    x1[t] = ws[5 + t];
+                    y0[t] = ws[10 + t];
+                    y1[t] = ws[15 + t];
+                    z0[t] = ws[20 + t];
+                    z1[t] = ws[25 + t];
+                }
                 const int lx = fx - sub - ox;  // in [0, 11]: fx lies in this brick
                 const int lyb = fy - oy, lzb = fz - oz;
                 const R* plane = s_g + lx * kReg * kReg;
@@ -732,6 +772,22 @@ __global__ __launch_bounds__(256) void k_gather_brick(int3 K, int3 nbr, const in
         part[b] = pq[0];
 }
 
+template <typename R>
+__global__ void k_convolve(size_t n, typename V4p<R>::C* __restrict__ g, const R* __restrict__ theta,
+                           const PcgScalars* __restrict__ sc, int use_done)
+{
+    if (use_done && sc->done)
+        return;
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n)
+        return;
+    R th = theta[i];
+    typename V4p<R>::C v = g[i];
+    v.x *= th;
+    v.y *= th;
+    g[i] = v;
+}
+
 static inline int nblk(size_t n, int b) { return (int)((n + b - 1) / b); }
 
 // ------------------------------------------------------------------------------------------
@@ -750,6 +806,8 @@ int pme_setup(amoeba_ctx* c)
     int rc;
     if ((rc = ctx_alloc(c, &c->grid_r, rs * c->ngrid)) || (rc = ctx_alloc(c, &c->grid_c, 2 * rs * c->ncgrid)) ||
         (rc = ctx_alloc(c, &c->theta, rs * c->ncgrid)) ||
+        (rc = ctx_alloc(c, (void**)&c->sp_base, sizeof(int4) * c->npad)) ||
+        (rc = ctx_alloc(c, &c->sp_w, rs * kSpStride * c->npad)) ||
         (rc = ctx_alloc(c, (void**)&c->bin_start, sizeof(int) * (c->nbricks + 1))) ||
         (rc = ctx_alloc(c, (void**)&c->bin_count, sizeof(int) * (c->nbricks + 1))) ||
         (rc = ctx_alloc(c, (void**)&c->bin_atoms, sizeof(int) * c->npad)) ||
@@ -824,6 +882,12 @@ void pme_bin_atoms(amoeba_ctx* c)
     hipLaunchKernelGGL(k_bin_fill, dim3(nblk(c->npad, 256)), dim3(256), 0, st, c->npad, c->atom_bin, c->bin_start,
                        c->bin_count, c->bin_atoms);
     hipLaunchKernelGGL(k_bin_sort, dim3(c->nbricks), dim3(256), 0, st, c->bin_start, c->bin_atoms);
+    if (c->mixed)
+        hipLaunchKernelGGL(k_spline_table<float>, dim3(nblk(c->npad, 256)), dim3(256), 0, st, c->npad, c->perm,
+                           c->pos_s, kl, K, c->sp_base, (float*)c->sp_w);
+    else
+        hipLaunchKernelGGL(k_spline_table<double>, dim3(nblk(c->npad, 256)), dim3(256), 0, st, c->npad, c->perm,
+                           c->pos_s, kl, K, c->sp_base, (double*)c->sp_w);
 }
 
 __global__ __launch_bounds__(1024) void k_scan_excl_pme(int n, const int* __restrict__ in, int* __restrict__ out)
@@ -887,11 +951,13 @@ int pme_dipole_field(amoeba_ctx* c, bool use_done)
     StageTimer tm(c, AMOEBA_T_SPREAD);
     if (c->mixed)
         hipLaunchKernelGGL((k_spread_dip<float, true>), dim3(c->nbricks), dim3(256), 0, c->stream, K, nbr,
-                           c->bin_start, c->bin_atoms, c->pos_s, kl, c->pv_f, (float*)c->grid_r, c->sc,
+                           c->bin_start, c->bin_atoms, c->sp_base, (const float*)c->sp_w, kl, c->pv_f,
+                           (float*)c->grid_r, c->sc,
                            (int)use_done);
     else
         hipLaunchKernelGGL((k_spread_dip<double, false>), dim3(c->nbricks), dim3(256), 0, c->stream, K, nbr,
-                           c->bin_start, c->bin_atoms, c->pos_s, kl, c->pv_d, (double*)c->grid_r, c->sc,
+                           c->bin_start, c->bin_atoms, c->sp_base, (const double*)c->sp_w, kl, c->pv_d,
+                           (double*)c->grid_r, c->sc,
                            (int)use_done);
     }
     StageTimer tm(c, AMOEBA_T_FFT);
@@ -929,12 +995,14 @@ void launch_gather(amoeba_ctx* c, double* out)
     double3 kl = make_double3(c->K[0] / c->prm.box[0], c->K[1] / c->prm.box[1], c->K[2] / c->prm.box[2]);
     if (c->mixed)
         hipLaunchKernelGGL((k_gather_brick<float, 0>), dim3(c->nbricks), dim3(256), 0, c->stream, K, nbr,
-                           c->bin_start, c->bin_atoms, c->pos_s, kl, (const float*)c->grid_r, c->par_d,
+                           c->bin_start, c->bin_atoms, c->sp_base, (const float*)c->sp_w, kl,
+                           (const float*)c->grid_r, c->par_d,
                            (const double*)nullptr, 0.0, (const double*)nullptr, (const float*)nullptr,
                            (const int*)nullptr, (const int*)nullptr, out, c->sc, c->red.part, 0, 0);
     else
         hipLaunchKernelGGL((k_gather_brick<double, 0>), dim3(c->nbricks), dim3(256), 0, c->stream, K, nbr,
-                           c->bin_start, c->bin_atoms, c->pos_s, kl, (const double*)c->grid_r, c->par_d,
+                           c->bin_start, c->bin_atoms, c->sp_base, (const double*)c->sp_w, kl,
+                           (const double*)c->grid_r, c->par_d,
                            (const double*)nullptr, 0.0, (const double*)nullptr, (const double*)nullptr,
                            (const int*)nullptr, (const int*)nullptr, out, c->sc, c->red.part, 0, 0);
 }
@@ -949,12 +1017,14 @@ void launch_matvec_combine(amoeba_ctx* c, bool use_done, bool dot_pq)
     double self = 4.0 * b * b * b / (3.0 * sqrt(kPi));
     if (c->mixed)
         hipLaunchKernelGGL((k_gather_brick<float, 1>), dim3(c->nbricks), dim3(256), 0, c->stream, K, nbr,
-                           c->bin_start, c->bin_atoms, c->pos_s, kl, (const float*)c->grid_r, c->par_d, c->v_p, self,
+                           c->bin_start, c->bin_atoms, c->sp_base, (const float*)c->sp_w, kl,
+                           (const float*)c->grid_r, c->par_d, c->v_p, self,
                            c->eipart, (const float*)c->jbuf, c->rev_ptr, c->rev_idx, c->v_q, c->sc, c->red.part,
                            (int)use_done, (int)dot_pq);
     else
         hipLaunchKernelGGL((k_gather_brick<double, 1>), dim3(c->nbricks), dim3(256), 0, c->stream, K, nbr,
-                           c->bin_start, c->bin_atoms, c->pos_s, kl, (const double*)c->grid_r, c->par_d, c->v_p,
+                           c->bin_start, c->bin_atoms, c->sp_base, (const double*)c->sp_w, kl,
+                           (const double*)c->grid_r, c->par_d, c->v_p,
                            self, c->eipart, (const double*)c->jbuf, c->rev_ptr, c->rev_idx, c->v_q, c->sc,
                            c->red.part, (int)use_done, (int)dot_pq);
 }

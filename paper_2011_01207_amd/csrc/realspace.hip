@@ -10,9 +10,9 @@
 // masks, so masked-out pair slots cost nothing.  Each pair is evaluated once (Newton's third
 // law): the field at i accumulates in registers while the lane stays on a row and is then added
 // to the block's LDS accumulator, which collects all tiles of the block; the field at j is added
-// to the tile's LDS accumulator.  In mixed precision every LDS addition is a 64-bit fixed-point
-// integer (40 fraction bits), so the sums do not depend on the order of the lanes' atomics and
-// the product is bitwise reproducible; FP64 mode accumulates in FP64.
+// to the tile's LDS accumulator.  In mixed precision every LDS addition is a fixed-point integer
+// (40 fraction bits) held exactly in FP64, so the sums do not depend on the order of the lanes'
+// atomics and the product is bitwise reproducible; FP64 mode accumulates in FP64.
 //
 // No global atomics: a block writes its i-field once (eipart) and each off-diagonal tile writes
 // its 64 j-fields to its own slot of jbuf; the diagonal tile's j-field goes straight into the
@@ -37,6 +37,7 @@ template <> struct V4<double> { using T = double4; };
 
 template <typename R> struct EwaldArgs {
     R beta, beta2, g, t, t2;  // beta, beta^2, 2 beta/sqrt(pi), 2 beta^2, (2 beta^2)^2
+    R nb2l;                   // -beta^2 log2(e): exp(-beta^2 r^2) = 2^(nb2l r^2)
     R L[3], Linv[3];
 };
 
@@ -49,6 +50,7 @@ template <typename R> EwaldArgs<R> make_ewald(const amoeba_ctx* c)
     e.g = (R)(2.0 * b / sqrt(kPi));
     e.t = (R)(2.0 * b * b);
     e.t2 = (R)(4.0 * b * b * b * b);
+    e.nb2l = (R)(-b * b * 1.4426950408889634);
     for (int a = 0; a < 3; ++a) {
         e.L[a] = (R)c->prm.box[a];
         e.Linv[a] = (R)(1.0 / c->prm.box[a]);
@@ -59,12 +61,16 @@ template <typename R> EwaldArgs<R> make_ewald(const amoeba_ctx* c)
 // exp and erfc of the pair kernels.  FP64 uses the math library.  FP32 uses the hardware
 // exponential and erfc(x) = P(t) exp(-x^2), t = 1 / (1 + x/2), with P the degree-9 polynomial
 // fitted to erfc(x) exp(x^2) on [0, 4.5] by fit_erfc.py (relative error 2e-8 in exact
-// arithmetic, 4e-7 evaluated in FP32); exp(-x^2) is the Ewald Gaussian the pair needs anyway.
+// arithmetic, below 6e-7 evaluated in FP32 with the 1-ulp hardware reciprocal for t);
+// exp(-x^2) is the Ewald Gaussian the pair needs anyway.
 __device__ __forceinline__ float d_exp(float x) { return __expf(x); }
 __device__ __forceinline__ double d_exp(double x) { return exp(x); }
+// 2^x: the hardware base-2 exponential in FP32
+__device__ __forceinline__ float d_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
+__device__ __forceinline__ double d_exp2(double x) { return exp2(x); }
 __device__ __forceinline__ float d_erfc_g(float x, float gauss)
 {
-    const float t = __frcp_rn(1.0f + 0.5f * x);
+    const float t = __builtin_amdgcn_rcpf(1.0f + 0.5f * x);   // hardware reciprocal, 1 ulp
     float p = -2.195935133e-02f;
     p = fmaf(p, t, 7.868809266e-02f);
     p = fmaf(p, t, 9.712290818e-03f);
@@ -78,20 +84,22 @@ __device__ __forceinline__ float d_erfc_g(float x, float gauss)
     return p * gauss;
 }
 __device__ __forceinline__ double d_erfc_g(double x, double) { return erfc(x); }
-__device__ __forceinline__ float d_rsqrt(float x) { return rsqrtf(x); }
+// hardware reciprocal square root (1 ulp); pair distances are far above the FP32 denormal range
+__device__ __forceinline__ float d_rsqrt(float x) { return __builtin_amdgcn_rsqf(x); }
 __device__ __forceinline__ double d_rsqrt(double x) { return 1.0 / sqrt(x); }
 __device__ __forceinline__ float d_rint(float x) { return rintf(x); }
 __device__ __forceinline__ double d_rint(double x) { return rint(x); }
 
 constexpr int kWavesPerWG = 4;
 
-// LDS field accumulators: 64-bit fixed point (mixed) or FP64.
+// LDS field accumulators: fixed point with 40 fraction bits held as integer-valued FP64
+// (mixed; see fixd) or plain FP64.
 template <bool FIX> struct LdsField;
 template <> struct LdsField<true> {
-    using T = unsigned long long;
-    __device__ static void add(T* p, float v) { atomicAdd(p, fix40(v)); }
+    using T = double;
+    __device__ static void add(T* p, float v) { atomicAdd(p, fixd(v)); }
     __device__ static void add_raw(T* p, T v) { atomicAdd(p, v); }
-    __device__ static double value(T v) { return (double)(long long)v * kFixInv; }
+    __device__ static double value(T v) { return v * kFixInv; }
 };
 template <> struct LdsField<false> {
     using T = double;
@@ -113,6 +121,30 @@ __device__ __forceinline__ int wave_excl_scan(int x, int lane, int& total)
     return incl - x;
 }
 
+// Position of set bit number n (0-based) of m, n < popcount(m): a binary search on the
+// popcounts of halves, quarters, ...
+__device__ __forceinline__ int nth_set_bit(unsigned long long m, int n)
+{
+    unsigned w = (unsigned)m;
+    int base = 0;
+    int c = __popc(w);
+    if (n >= c) {
+        n -= c;
+        w = (unsigned)(m >> 32);
+        base = 32;
+    }
+#pragma unroll
+    for (int half = 16; half >= 1; half >>= 1) {
+        c = __popc(w & ((1u << half) - 1u));
+        if (n >= c) {
+            n -= c;
+            w >>= half;
+            base += half;
+        }
+    }
+    return base;
+}
+
 // first pair of a lane's range: row i (largest with off[i] <= p0) and its mask with the first
 // (p0 - off[i]) set bits cleared
 __device__ __forceinline__ void walk_start(const int* s_off, const unsigned long long* s_mask, int p0, int& i,
@@ -127,13 +159,15 @@ __device__ __forceinline__ void walk_start(const int* s_off, const unsigned long
             hi = mid - 1;
     }
     i = lo;
-    rem = s_mask[i];
-    for (int r = p0 - s_off[i]; r > 0; --r)
-        rem &= rem - 1ull;
+    const unsigned long long m = s_mask[i];
+    rem = m & (~0ull << nth_set_bit(m, p0 - s_off[i]));
 }
 
 // Radial functions of a pair: B1', B2' (and B3' when THIRD), minimum-image displacement.
-template <typename R, bool THIRD> struct PairGeom {
+// MI = false skips the minimum image: the host enables that only when block extents, cutoff
+// and buffer bound every tile displacement below half the box, so that the difference of the
+// two block-relative offsets already is the minimum image.
+template <typename R, bool THIRD, bool MI> struct PairGeom {
     R dx, dy, dz, b1p, b2p, b3p;
     __device__ __forceinline__ PairGeom(const typename V4<R>::T& ip, const typename V4<R>::T& jp, R ai, R aj,
                                         const EwaldArgs<R>& ew)
@@ -141,14 +175,16 @@ template <typename R, bool THIRD> struct PairGeom {
         dx = ip.x - jp.x;
         dy = ip.y - jp.y;
         dz = ip.z - jp.z;
-        dx -= ew.L[0] * d_rint(dx * ew.Linv[0]);
-        dy -= ew.L[1] * d_rint(dy * ew.Linv[1]);
-        dz -= ew.L[2] * d_rint(dz * ew.Linv[2]);
+        if (MI) {
+            dx -= ew.L[0] * d_rint(dx * ew.Linv[0]);
+            dy -= ew.L[1] * d_rint(dy * ew.Linv[1]);
+            dz -= ew.L[2] * d_rint(dz * ew.Linv[2]);
+        }
         const R r2 = dx * dx + dy * dy + dz * dz;
         const R rinv = d_rsqrt(r2);
         const R r = r2 * rinv;
         const R rinv2 = rinv * rinv;
-        const R gauss = d_exp(-ew.beta2 * r2);
+        const R gauss = d_exp2(ew.nb2l * r2);
         const R gb = ew.g * gauss;
         const R b0 = d_erfc_g(ew.beta * r, gauss) * rinv;
         const R b1 = (b0 + gb) * rinv2;
@@ -156,7 +192,7 @@ template <typename R, bool THIRD> struct PairGeom {
         const R a = ai < aj ? ai : aj;
         const R u = r * ip.w * jp.w;
         const R eps = a * u * u * u;
-        const R ex = d_exp(-eps);
+        const R ex = d_exp2(eps * (R)-1.4426950408889634);
         const R rinv3 = rinv * rinv2, rinv5 = rinv3 * rinv2;
         b1p = b1 - ex * rinv3;
         b2p = b2 - (R)3 * ((R)1 + eps) * ex * rinv5;
@@ -169,6 +205,11 @@ template <typename R, bool THIRD> struct PairGeom {
     }
 };
 
+__device__ __forceinline__ float fma_r(float a, float b, float c) { return fmaf(a, b, c); }
+__device__ __forceinline__ double fma_r(double a, double b, double c) { return fma(a, b, c); }
+
+// Pair kinds: pair() adds the field at i from j to ei (the caller's running sum over the row)
+// and returns the field at j from i in ej.
 // Induced-dipole interaction.  Per atom: d[0] = (mu_x, mu_y, mu_z, Thole a).
 template <typename R> struct DipoleKind {
     using R4 = typename V4<R>::T;
@@ -178,15 +219,17 @@ template <typename R> struct DipoleKind {
         R4 m = src[s];
         d[0] = R4{m.x, m.y, m.z, a};
     }
+    template <bool MI>
     __device__ static void pair(const R4& ip, const R4* di, const R4& jp, const R4* dj, const EwaldArgs<R>& ew,
                                 R* ei, R* ej)
     {
-        PairGeom<R, false> g(ip, jp, di[0].w, dj[0].w, ew);
+        PairGeom<R, false, MI> g(ip, jp, di[0].w, dj[0].w, ew);
         const R mjd = dj[0].x * g.dx + dj[0].y * g.dy + dj[0].z * g.dz;
         const R mid = di[0].x * g.dx + di[0].y * g.dy + di[0].z * g.dz;
-        ei[0] = -g.b1p * dj[0].x + g.b2p * mjd * g.dx;
-        ei[1] = -g.b1p * dj[0].y + g.b2p * mjd * g.dy;
-        ei[2] = -g.b1p * dj[0].z + g.b2p * mjd * g.dz;
+        const R tj = g.b2p * mjd;
+        ei[0] = fma_r(tj, g.dx, fma_r(-g.b1p, dj[0].x, ei[0]));
+        ei[1] = fma_r(tj, g.dy, fma_r(-g.b1p, dj[0].y, ei[1]));
+        ei[2] = fma_r(tj, g.dz, fma_r(-g.b1p, dj[0].z, ei[2]));
         ej[0] = -g.b1p * di[0].x + g.b2p * mid * g.dx;
         ej[1] = -g.b1p * di[0].y + g.b2p * mid * g.dy;
         ej[2] = -g.b1p * di[0].z + g.b2p * mid * g.dz;
@@ -205,10 +248,11 @@ template <typename R> struct MultipoleKind {
         R4 m2 = src[3 * s + 2];
         d[2] = R4{m2.x, m2.y, a, 0};
     }
+    template <bool MI>
     __device__ static void pair(const R4& ip, const R4* di, const R4& jp, const R4* dj, const EwaldArgs<R>& ew,
                                 R* ei, R* ej)
     {
-        PairGeom<R, true> g(ip, jp, di[2].z, dj[2].z, ew);
+        PairGeom<R, true, MI> g(ip, jp, di[2].z, dj[2].z, ew);
         const R third = (R)1 / (R)3;
         const R c2 = g.b2p * ((R)2 / (R)3);
         {  // field at i from j
@@ -218,9 +262,9 @@ template <typename R> struct MultipoleKind {
             const R tdd = tdx * g.dx + tdy * g.dy + tdz * g.dz;
             const R dd = dj[0].y * g.dx + dj[0].z * g.dy + dj[0].w * g.dz;
             const R rad = dj[0].x * g.b1p + g.b2p * dd + g.b3p * tdd * third;
-            ei[0] = rad * g.dx - g.b1p * dj[0].y - c2 * tdx;
-            ei[1] = rad * g.dy - g.b1p * dj[0].z - c2 * tdy;
-            ei[2] = rad * g.dz - g.b1p * dj[0].w - c2 * tdz;
+            ei[0] += rad * g.dx - g.b1p * dj[0].y - c2 * tdx;
+            ei[1] += rad * g.dy - g.b1p * dj[0].z - c2 * tdy;
+            ei[2] += rad * g.dz - g.b1p * dj[0].w - c2 * tdz;
         }
         {  // field at j from i (r -> -r)
             const R tdx = di[1].x * g.dx + di[1].y * g.dy + di[1].z * g.dz;
@@ -240,7 +284,7 @@ template <typename R> struct MultipoleKind {
 // K3 / K3p: one workgroup per i-block over all the block's tiles.
 // jbuf layout: [tile][component][lane] (R);  eipart: [slot][3] (FP64).
 // ------------------------------------------------------------------------------------------
-template <typename R, bool FIX, class K>
+template <typename R, bool FIX, class K, bool MI>
 __global__ __launch_bounds__(256) void k_block_tiles(int nb, const int* __restrict__ blk_tile0,
                                                      const int* __restrict__ tile_j,
                                                      const unsigned long long* __restrict__ tile_mask,
@@ -346,11 +390,8 @@ __global__ __launch_bounds__(256) void k_block_tiles(int nb, const int* __restri
 #pragma unroll
                 for (int v = 0; v < NV; ++v)
                     dj[v] = s_jd[w][v][k];
-                R ei[3], ej[3];
-                K::pair(ip, di, s_jp[w][k], dj, ew, ei, ej);
-                ea[0] += ei[0];
-                ea[1] += ei[1];
-                ea[2] += ei[2];
+                R ej[3];
+                K::template pair<MI>(ip, di, s_jp[w][k], dj, ew, ea, ej);
 #pragma unroll
                 for (int c = 0; c < 3; ++c)
                     LdsField<FIX>::add(&s_ej[w][c][k], ej[c]);
@@ -405,19 +446,27 @@ __global__ void k_real_reduce(int npad, const double* __restrict__ eipart, const
     ereal[3 * (size_t)s + 2] = e2;
 }
 
-void launch_mutual_tiles(amoeba_ctx* c, bool use_done)
+template <bool MI> static void mutual_tiles(amoeba_ctx* c, bool use_done)
 {
     if (c->ntiles == 0)
         return;
     StageTimer tm(c, AMOEBA_T_REAL);
     if (c->mixed)
-        hipLaunchKernelGGL((k_block_tiles<float, true, DipoleKind<float>>), dim3(c->nb), dim3(256), 0, c->stream,
+        hipLaunchKernelGGL((k_block_tiles<float, true, DipoleKind<float>, MI>), dim3(c->nb), dim3(256), 0, c->stream,
                            c->nb, c->blk_tile0, c->tile_j, c->tile_mask, c->jrel_f, c->off_f, c->par_f, c->pv_f,
                            make_ewald<float>(c), c->eipart, (float*)c->jbuf, c->sc, (int)use_done);
     else
-        hipLaunchKernelGGL((k_block_tiles<double, false, DipoleKind<double>>), dim3(c->nb), dim3(256), 0, c->stream,
+        hipLaunchKernelGGL((k_block_tiles<double, false, DipoleKind<double>, MI>), dim3(c->nb), dim3(256), 0, c->stream,
                            c->nb, c->blk_tile0, c->tile_j, c->tile_mask, c->jrel_d, c->off_d, c->par_d, c->pv_d,
                            make_ewald<double>(c), c->eipart, (double*)c->jbuf, c->sc, (int)use_done);
+}
+
+void launch_mutual_tiles(amoeba_ctx* c, bool use_done)
+{
+    if (c->skip_mimg)
+        mutual_tiles<false>(c, use_done);
+    else
+        mutual_tiles<true>(c, use_done);
 }
 
 void launch_real_reduce(amoeba_ctx* c, double* ereal)
@@ -430,19 +479,29 @@ void launch_real_reduce(amoeba_ctx* c, double* ereal)
                            c->eipart, (const double*)c->jbuf, c->rev_ptr, c->rev_idx, ereal);
 }
 
-void launch_perm_tiles(amoeba_ctx* c)
+template <bool MI> static void perm_tiles(amoeba_ctx* c)
 {
     if (c->ntiles == 0)
         return;
     StageTimer tm(c, AMOEBA_T_PERM);
     if (c->mixed)
-        hipLaunchKernelGGL((k_block_tiles<float, true, MultipoleKind<float>>), dim3(c->nb), dim3(256), 0,
+        hipLaunchKernelGGL((k_block_tiles<float, true, MultipoleKind<float>, MI>), dim3(c->nb), dim3(256), 0,
                            c->stream, c->nb, c->blk_tile0, c->tile_j, c->tile_mask, c->jrel_f, c->off_f, c->par_f,
                            (const float4*)c->mp_f, make_ewald<float>(c), c->eipart, (float*)c->jbuf, c->sc, 0);
     else
-        hipLaunchKernelGGL((k_block_tiles<double, false, MultipoleKind<double>>), dim3(c->nb), dim3(256), 0,
+        hipLaunchKernelGGL((k_block_tiles<double, false, MultipoleKind<double>, MI>), dim3(c->nb), dim3(256), 0,
                            c->stream, c->nb, c->blk_tile0, c->tile_j, c->tile_mask, c->jrel_d, c->off_d, c->par_d,
                            (const double4*)c->mp_d, make_ewald<double>(c), c->eipart, (double*)c->jbuf, c->sc, 0);
+}
+
+void launch_perm_tiles(amoeba_ctx* c)
+{
+    if (c->ntiles == 0)
+        return;
+    if (c->skip_mimg)
+        perm_tiles<false>(c);
+    else
+        perm_tiles<true>(c);
     launch_real_reduce(c, c->ereal);
 }
 

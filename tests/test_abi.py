@@ -48,6 +48,7 @@ def _params(**kw):
     ({"beta": 0.0}, "ewald_alpha"),
     ({"order": 4}, "order 5"),
     ({"grid": 8}, "grid"),
+    ({"grid": 4096}, "grid"),
     ({"precision": 7}, "precision"),
     ({"cap": -5}, "max_workspace_bytes"),
 ])

@@ -68,3 +68,33 @@ def test_water96k_mixed_matches_fp64_and_pair_count(c2):
     assert O.rms_debye(res["mixed"][0] - res["fp64"][0]) < 1e-5
     assert abs(res["mixed"][1] - res["fp64"][1]) < 1e-5 * abs(res["fp64"][1])
     assert res["mixed"][2] == res["fp64"][2] == O.count_pairs(s)
+
+
+@pytest.fixture(scope="module")
+def subcell864():
+    """The periodic subcell of the 864,000-atom box (whole waters in 11 lattice spacings, grid
+    36^3): small enough for the oracle's full SPME solve."""
+    s = synth.subcell(synth.water864k())
+    print(f"[gpu] oracle solve of the {s.n}-atom subcell", flush=True)
+    e = O.perm_field(s, "spme")
+    mu, _, _ = O.pcg(s, e, "spme", tol_debye=1e-10)
+    return s, e, mu
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_subcell_of_864k_box_dipoles_and_energy(subcell864, prec):
+    """E_perm, mu and E_pol of the GPU solver against the oracle's exact SPME solution."""
+    s, e_ref, mu_ref = subcell864
+    ctx, t = amoeba.context_for(s, precision=prec, device=DEV)
+    e = ctx.perm_field(t["pos"], t["q"], t["dip"], t["quad"])
+    assert rel_rms(e.cpu().numpy(), e_ref) < (1e-11 if prec == "fp64" else 3e-5)
+    tol = 1e-9 if prec == "fp64" else 1e-6
+    mu, ep, it, st = ctx.polarize(t["pos"], e, tol_debye=tol)
+    assert st == amoeba.AMOEBA_OK
+    err = O.rms_debye(mu.cpu().numpy() - mu_ref)
+    ep_ref = O.e_pol(mu_ref, e_ref)
+    print(f"[gpu] subcell {prec}: {it} it, mu rms err {err:.2e} D, E_pol rel err {abs(ep - ep_ref) / abs(ep_ref):.2e}",
+          flush=True)
+    assert err < (5e-9 if prec == "fp64" else 5e-6)
+    assert abs(ep - ep_ref) < (1e-9 if prec == "fp64" else 1e-6) * abs(ep_ref)
+    ctx.close()

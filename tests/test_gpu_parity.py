@@ -185,6 +185,29 @@ def test_error_paths(c1):
     e = ctx.perm_field(t["pos"], t["q"], t["dip"], t["quad"])
     mu, ep, it, st = ctx.polarize(t["pos"], e, tol_debye=1e-12, max_iter=3)
     assert st == amoeba.AMOEBA_NOT_CONVERGED and it == 3 and torch.isfinite(mu).all()
+    mu0, _, it0, st0 = ctx.polarize(t["pos"], e, tol_debye=1e-5, max_iter=0)
+    assert st0 == amoeba.AMOEBA_NOT_CONVERGED and it0 == 0 and torch.count_nonzero(mu0) == 0
+    # NaN in the permanent field or in a given guess: reported, and the next solve is unaffected
+    ebad = e.clone()
+    ebad[7, 2] = float("inf")
+    with pytest.raises(amoeba.AmoebaError) as ei:
+        ctx.polarize(t["pos"], ebad, tol_debye=1e-5)
+    assert ei.value.status == amoeba.AMOEBA_E_NUMERIC
+    with pytest.raises(amoeba.AmoebaError) as ei:
+        ctx.polarize(t["pos"], e, mu_guess=bad, tol_debye=1e-5)
+    assert ei.value.status == amoeba.AMOEBA_E_NUMERIC
+    mu_a, ep_a, it_a, st_a = ctx.polarize(t["pos"], e, tol_debye=1e-8)
+    mu_b, ep_b, it_b, st_b = ctx.polarize(t["pos"], e, mu_guess=mu_a, tol_debye=1e-7)
+    assert st_a == st_b == amoeba.AMOEBA_OK and it_b == 0 and ep_b == ep_a
+    assert torch.equal(mu_a, mu_b)
+    # a quadrupole with a trace is rejected
+    qbad = t["quad"].clone()
+    qbad[4, 0] += 1e-6
+    with pytest.raises(amoeba.AmoebaError) as ei:
+        ctx.perm_field(t["pos"], t["q"], t["dip"], qbad)
+    assert ei.value.status == amoeba.AMOEBA_E_INVALID
+    # FP64 mode sums with FP64 atomics (order-dependent rounding): equal to rounding, not bitwise
+    assert torch.allclose(ctx.perm_field(t["pos"], t["q"], t["dip"], t["quad"]), e, rtol=1e-13, atol=1e-16)
     # invalid CSR: one direction missing
     sc_j = t["sc_j"].clone()
     sc_j[0] = (sc_j[0] + 7) % c1.n
