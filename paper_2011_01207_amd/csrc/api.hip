@@ -669,10 +669,20 @@ int amoeba_get_timing(amoeba_ctx* c, amoeba_timing* out)
     return AMOEBA_OK;
 }
 
-int amoeba_get_info(const amoeba_ctx* c, amoeba_info* out)
+int amoeba_get_info(const amoeba_ctx* cc, amoeba_info* out)
 {
-    if (!c || !out)
+    if (!cc || !out)
         return AMOEBA_E_INVALID;
+    amoeba_ctx* c = const_cast<amoeba_ctx*>(cc);  // the pair count of the last refresh is read lazily
+    if (c->pairs_pending) {
+        unsigned long long np = 0;
+        hipMemcpyAsync(c->flags_host + 2, c->counter, sizeof(unsigned long long), hipMemcpyDeviceToHost, c->stream);
+        if (hipStreamSynchronize(c->stream) != hipSuccess)
+            return AMOEBA_E_DEVICE;
+        np = *(unsigned long long*)(c->flags_host + 2);
+        c->n_pairs = (int64_t)np;
+        c->pairs_pending = false;
+    }
     out->n_atoms = c->n;
     out->n_blocks = c->nb;
     out->n_tiles = c->ntiles;

@@ -560,10 +560,11 @@ __global__ __launch_bounds__(256) void k_tile_refresh(int ntiles, const int* __r
                                                       const float4* __restrict__ off_f, double3 box, double3 binv,
                                                       double rc2, unsigned long long* __restrict__ mask,
                                                       double4* __restrict__ jrel_d, float4* __restrict__ jrel_f,
-                                                      unsigned long long* __restrict__ pair_count)
+                                                      unsigned long long* __restrict__ pair_part)
 {
     __shared__ double4 s_jd[4][kBlock];
     __shared__ float4 s_jf[4][kBlock];
+    __shared__ unsigned long long s_cnt[4];
     int gt = blockIdx.x * blockDim.x + threadIdx.x;
     int t = gt >> 6, lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     bool act = t < ntiles;
@@ -581,42 +582,65 @@ __global__ __launch_bounds__(256) void k_tile_refresh(int ntiles, const int* __r
     s_jd[w][lane] = make_double4(pj.x, pj.y, pj.z, 0.0);
     s_jf[w][lane] = make_float4((float)jx, (float)jy, (float)jz, jvalid ? 1.0f : 0.0f);
     __syncthreads();
-    if (!act)
-        return;
-    jrel_d[(size_t)t * kBlock + lane] = make_double4(jx, jy, jz, 0.0);
-    jrel_f[(size_t)t * kBlock + lane] = make_float4((float)jx, (float)jy, (float)jz, 0.0f);
-    bool diag = tile_j[(size_t)t * kBlock] == I * kBlock;
-    const float lo2 = (float)(rc2 * (1.0 - 1e-5)), hi2 = (float)(rc2 * (1.0 + 1e-5));
-    const float Lx = (float)box.x, Ly = (float)box.y, Lz = (float)box.z;
-    const float Lix = (float)binv.x, Liy = (float)binv.y, Liz = (float)binv.z;
     unsigned long long m = 0;
-    if (ivalid) {
-        const int k0 = diag ? lane + 1 : 0;
+    if (act) {
+        jrel_d[(size_t)t * kBlock + lane] = make_double4(jx, jy, jz, 0.0);
+        jrel_f[(size_t)t * kBlock + lane] = make_float4((float)jx, (float)jy, (float)jz, 0.0f);
+        bool diag = tile_j[(size_t)t * kBlock] == I * kBlock;
+        const float lo2 = (float)(rc2 * (1.0 - 1e-5)), hi2 = (float)(rc2 * (1.0 + 1e-5));
+        const float Lx = (float)box.x, Ly = (float)box.y, Lz = (float)box.z;
+        const float Lix = (float)binv.x, Liy = (float)binv.y, Liz = (float)binv.z;
+        if (ivalid) {
+            const int k0 = diag ? lane + 1 : 0;
 #pragma unroll 8
-        for (int k = 0; k < kBlock; ++k) {
-            const float4 q = s_jf[w][k];
-            float dx = oi.x - q.x, dy = oi.y - q.y, dz = oi.z - q.z;
-            dx -= Lx * rintf(dx * Lix);
-            dy -= Ly * rintf(dy * Liy);
-            dz -= Lz * rintf(dz * Liz);
-            const float r2 = dx * dx + dy * dy + dz * dz;
-            const bool use = k >= k0 && q.w != 0.0f;
-            bool in = use && r2 < lo2;
-            if (use && !(r2 < lo2) && r2 < hi2) {
-                const double4 p = s_jd[w][k];
-                const double ex = mimg_fp64(pi.x - p.x, box.x, binv.x), ey = mimg_fp64(pi.y - p.y, box.y, binv.y),
-                             ez = mimg_fp64(pi.z - p.z, box.z, binv.z);
-                in = ex * ex + ey * ey + ez * ez < rc2;
+            for (int k = 0; k < kBlock; ++k) {
+                const float4 q = s_jf[w][k];
+                float dx = oi.x - q.x, dy = oi.y - q.y, dz = oi.z - q.z;
+                dx -= Lx * rintf(dx * Lix);
+                dy -= Ly * rintf(dy * Liy);
+                dz -= Lz * rintf(dz * Liz);
+                const float r2 = dx * dx + dy * dy + dz * dz;
+                const bool use = k >= k0 && q.w != 0.0f;
+                bool in = use && r2 < lo2;
+                if (use && !(r2 < lo2) && r2 < hi2) {
+                    const double4 p = s_jd[w][k];
+                    const double ex = mimg_fp64(pi.x - p.x, box.x, binv.x), ey = mimg_fp64(pi.y - p.y, box.y, binv.y),
+                                 ez = mimg_fp64(pi.z - p.z, box.z, binv.z);
+                    in = ex * ex + ey * ey + ez * ez < rc2;
+                }
+                m |= (unsigned long long)in << k;
             }
-            m |= (unsigned long long)in << k;
         }
+        mask[(size_t)t * kBlock + lane] = m;
     }
-    mask[(size_t)t * kBlock + lane] = m;
+    // pairs of the workgroup's tiles: one partial per workgroup, summed in order by
+    // k_sum_pairs (no global atomics)
     unsigned long long cnt = (unsigned long long)__popcll(m);
     for (int off = 32; off > 0; off >>= 1)
         cnt += __shfl_xor(cnt, off);
-    if (lane == 0 && cnt)
-        atomicAdd(pair_count, cnt);
+    if (lane == 0)
+        s_cnt[w] = cnt;
+    __syncthreads();
+    if (threadIdx.x == 0)
+        pair_part[blockIdx.x] = s_cnt[0] + s_cnt[1] + s_cnt[2] + s_cnt[3];
+}
+
+__global__ __launch_bounds__(256) void k_sum_pairs(int n, const unsigned long long* __restrict__ part,
+                                                   unsigned long long* __restrict__ total)
+{
+    __shared__ unsigned long long sh[256];
+    unsigned long long s = 0;
+    for (int i = threadIdx.x; i < n; i += 256)
+        s += part[i];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (threadIdx.x < off)
+            sh[threadIdx.x] += sh[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        total[0] = sh[0];
 }
 
 static inline int nblk(long n, int b) { return (int)((n + b - 1) / b); }
@@ -667,11 +691,13 @@ static int refresh_tiles(amoeba_ctx* c)
     double3 box = make_double3(c->prm.box[0], c->prm.box[1], c->prm.box[2]);
     hipLaunchKernelGGL(k_block_frame, dim3(nblk(c->npad, 256)), dim3(256), 0, st, c->npad, c->perm, c->pos_s, box,
                        c->blk_org, c->off_d, c->off_f);
-    hipMemsetAsync(c->counter, 0, sizeof(unsigned long long), st);
     double3 binv = make_double3(1.0 / box.x, 1.0 / box.y, 1.0 / box.z);
-    hipLaunchKernelGGL(k_tile_refresh, dim3(nblk((long)c->ntiles * kBlock, 256)), dim3(256), 0, st, c->ntiles,
-                       c->tile_blk, c->tile_j, c->perm, c->pos_s, c->blk_org, c->off_f, box, binv,
-                       c->prm.cutoff * c->prm.cutoff, c->tile_mask, c->jrel_d, c->jrel_f, c->counter);
+    const int nwg = nblk((long)c->ntiles * kBlock, 256);
+    hipLaunchKernelGGL(k_tile_refresh, dim3(nwg), dim3(256), 0, st, c->ntiles, c->tile_blk, c->tile_j, c->perm,
+                       c->pos_s, c->blk_org, c->off_f, box, binv, c->prm.cutoff * c->prm.cutoff, c->tile_mask,
+                       c->jrel_d, c->jrel_f, c->pair_part);
+    hipLaunchKernelGGL(k_sum_pairs, dim3(1), dim3(256), 0, st, nwg, c->pair_part, c->counter);
+    c->pairs_pending = true;
     pme_bin_atoms(c);
     return AMOEBA_OK;
 }
@@ -774,7 +800,8 @@ int build_blocklist(amoeba_ctx* c, const double* pos)
             (rc = ctx_alloc(c, (void**)&c->jrel_f, sizeof(float4) * tb)) ||
             (rc = ctx_alloc(c, (void**)&c->jrel_d, sizeof(double4) * tb)) ||
             (rc = ctx_alloc(c, &c->jbuf, rs * 3 * tb)) ||
-            (rc = ctx_alloc(c, (void**)&c->rev_idx, sizeof(int) * tb)))
+            (rc = ctx_alloc(c, (void**)&c->rev_idx, sizeof(int) * tb)) ||
+            (rc = ctx_alloc(c, (void**)&c->pair_part, sizeof(unsigned long long) * ((size_t)total / 4 + 1))))
             return fail(rc);
         c->tile_cap = total;
         c->rev_cap = (int64_t)tb;
@@ -798,6 +825,7 @@ int build_blocklist(amoeba_ctx* c, const double* pos)
     if ((rc = hip_check(c, hipStreamSynchronize(st), "build_blocklist tiles")))
         return fail(rc);
     c->n_pairs = (int64_t) * (unsigned long long*)(c->flags_host + 2);
+    c->pairs_pending = false;
     c->list_built = true;
     c->cfg_valid = true;
     return AMOEBA_OK;
@@ -827,11 +855,7 @@ int prepare_config(amoeba_ctx* c, const double* pos)
     }
     if (c->cfg_valid && !(f & kFlagChanged))
         return AMOEBA_OK;  // same configuration as the last refresh: masks, frames and bins are current
-    refresh_tiles(c);
-    hipMemcpyAsync(c->flags_host + 2, c->counter, sizeof(unsigned long long), hipMemcpyDeviceToHost, st);
-    if ((rc = hip_check(c, hipStreamSynchronize(st), "prepare_config refresh")))
-        return rc;
-    c->n_pairs = (int64_t) * (unsigned long long*)(c->flags_host + 2);
+    refresh_tiles(c);  // the pair count is read when amoeba_get_info asks for it
     c->cfg_valid = true;
     return AMOEBA_OK;
 }

@@ -174,6 +174,8 @@ struct amoeba_ctx {
     int* flags = nullptr;                  // device error flags
     int* flags_host = nullptr;             // pinned
     unsigned long long* counter = nullptr; // device counters (pairs)
+    unsigned long long* pair_part = nullptr; // per-workgroup pair counts of the mask refresh
+    bool pairs_pending = false;            // counter holds a pair count not yet read to n_pairs
     hipEvent_t ev[2] = {nullptr, nullptr};
 
     // list-build scratch, kept between builds

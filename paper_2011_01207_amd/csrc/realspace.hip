@@ -163,6 +163,83 @@ __device__ __forceinline__ void walk_start(const int* s_off, const unsigned long
     rem = m & (~0ull << nth_set_bit(m, p0 - s_off[i]));
 }
 
+// Very close pairs: B_n ~ (2n-1)!!/r^(2n+1) and its Thole term cancel to an O(1) B_n', which the
+// direct formula cannot resolve once the rounding of the two terms exceeds the result (in FP32
+// near r = 0.5 A for B2; FP64 keeps B1', B2' to 2e-4 even at 0.005 A and uses the direct
+// formula).  In FP32, below kCloseR the functions are summed from
+// well-conditioned pieces, with x = beta r, A = a (alpha_i alpha_j)^(-1/2), eps = A r^3:
+//   B1' = beta^3 d1(x^2) + A phi3(eps),  B2' = beta^5 d2(x^2) + 3 A^2 r phi5(eps),
+//   B3' = beta^7 d3(x^2) + 15 A^2 psi7(eps) / r,
+// d_n = (B_n - (2n-1)!!/r^(2n+1)) / beta^(2n+1) as power series in x^2, phi3 = lambda3/eps,
+// phi5 = lambda5/eps^2, psi7 = lambda7/eps^2 as power series in eps (coefficients written by
+// close_series.py; eps beyond the series range uses the exponential directly, which no longer
+// cancels there).  Physical configurations have no such pairs; random-walk test trajectories do.
+constexpr float kCloseR2 = 0.25f;  // (0.5 A)^2
+constexpr double kD1[9] = {
+    -7.52252778063674965e-01, 4.51351666838205046e-01, -1.61197023870787493e-01,
+    4.17918210035374965e-02, -8.54832702345085377e-03, 1.44663995781475979e-03,
+    -2.08959105017687488e-04, 2.63393829854227941e-05, -2.94585204442228630e-06};
+constexpr double kD2[9] = {
+    -9.02703333676410091e-01, 6.44788095483149970e-01, -2.50750926021225007e-01,
+    6.83866161876068301e-02, -1.44663995781475971e-02, 2.50750926021224996e-03,
+    -3.68751361795919132e-04, 4.71336327107565808e-05, -5.33058941371651774e-06};
+constexpr double kD3[9] = {
+    -1.28957619096629994e+00, 1.00300370408490003e+00, -4.10319697125640925e-01,
+    1.15731196625180777e-01, -2.50750926021225014e-02, 4.42501634155103001e-03,
+    -6.59870857950592199e-04, 8.52894306194642839e-05, -9.73411979896059946e-06};
+constexpr double kPhi3[12] = {
+    1.00000000000000000e+00, -5.00000000000000000e-01, 1.66666666666666657e-01,
+    -4.16666666666666644e-02, 8.33333333333333322e-03, -1.38888888888888894e-03,
+    1.98412698412698413e-04, -2.48015873015873016e-05, 2.75573192239858925e-06,
+    -2.75573192239858883e-07, 2.50521083854417202e-08, -2.08767569878681002e-09};
+constexpr double kPhi5[12] = {
+    5.00000000000000000e-01, -3.33333333333333315e-01, 1.25000000000000000e-01,
+    -3.33333333333333329e-02, 6.94444444444444406e-03, -1.19047619047619058e-03,
+    1.73611111111111118e-04, -2.20458553791887140e-05, 2.48015873015873016e-06,
+    -2.50521083854417176e-07, 2.29644326866549102e-08, -1.92708526041859370e-09};
+constexpr double kPsi7[12] = {
+    -1.00000000000000006e-01, 2.66666666666666663e-01, -1.74999999999999989e-01,
+    6.66666666666666657e-02, -1.80555555555555539e-02, 3.80952380952380952e-03,
+    -6.59722222222222242e-04, 9.70017636684303335e-05, -1.24007936507936508e-05,
+    1.40291806958473623e-06, -1.42379482657260439e-07, 1.31041797708464367e-08};
+
+template <int N, typename R> __device__ __forceinline__ R horner(const double (&c)[N], R t)
+{
+    R p = (R)c[N - 1];
+#pragma unroll
+    for (int k = N - 2; k >= 0; --k)
+        p = p * t + (R)c[k];
+    return p;
+}
+
+template <typename R, bool THIRD>
+__device__ __forceinline__ void close_pair_series(R r2, R r, R rinv, R a, R w, const EwaldArgs<R>& ew, R& b1p, R& b2p,
+                                                  R& b3p)
+{
+    const R x2 = ew.beta2 * r2;
+    const R be3 = ew.beta2 * ew.beta, be5 = be3 * ew.beta2;
+    const R A = a * w * w * w;
+    const R eps = A * r2 * r;
+    R ph3, ph5, ps7 = 0;
+    if (eps < (R)1) {
+        ph3 = horner(kPhi3, eps);
+        ph5 = horner(kPhi5, eps);
+        if (THIRD)
+            ps7 = horner(kPsi7, eps);
+    } else {
+        const R ex = d_exp(-eps);
+        const R ie = (R)1 / eps;
+        ph3 = ((R)1 - ex) * ie;
+        ph5 = ((R)1 - ((R)1 + eps) * ex) * ie * ie;
+        if (THIRD)
+            ps7 = ((R)1 - ((R)1 + eps + (R)0.6 * eps * eps) * ex) * ie * ie;
+    }
+    b1p = be3 * horner(kD1, x2) + A * ph3;
+    b2p = be5 * horner(kD2, x2) + (R)3 * A * A * r * ph5;
+    if (THIRD)
+        b3p = be5 * ew.beta2 * horner(kD3, x2) + (R)15 * A * A * ps7 * rinv;
+}
+
 // Radial functions of a pair: B1', B2' (and B3' when THIRD), minimum-image displacement.
 // MI = false skips the minimum image: the host enables that only when block extents, cutoff
 // and buffer bound every tile displacement below half the box, so that the difference of the
@@ -201,6 +278,10 @@ template <typename R, bool THIRD, bool MI> struct PairGeom {
             b3p = b3 - (R)15 * ((R)1 + eps + (R)0.6 * eps * eps) * ex * rinv5 * rinv2;
         } else {
             b3p = 0;
+        }
+        if constexpr (sizeof(R) == 4) {
+            if (r2 < kCloseR2)
+                close_pair_series<R, THIRD>(r2, r, rinv, a, ip.w * jp.w, ew, b1p, b2p, b3p);
         }
     }
 };

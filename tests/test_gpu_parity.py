@@ -161,6 +161,43 @@ def test_ragged_single_block_and_no_scaled_pairs():
     ctx.close()
 
 
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_near_coincident_atoms(prec):
+    """Pairs at 0.02, 0.1, 0.3 and 0.45 A (the short-range series of the FP32 kernels) and
+    their multipoles: real-space field, matvec, permanent field and a converged solve against
+    the oracle."""
+    import dataclasses
+    s = synth.tiny_cell(40, 16.0, seed=140, min_dist=1.2)
+    pos = s.pos.copy()
+    for (i, j), d in zip(((0, 1), (2, 3), (4, 5), (6, 7)), (0.02, 0.1, 0.3, 0.45)):
+        v = np.array([0.6, -0.48, 0.64])
+        pos[j] = np.mod(pos[i] + d * v, 16.0)
+    s = dataclasses.replace(s, pos=pos, grid=(20, 20, 20))
+    rng = np.random.default_rng(141)
+    mu = rng.standard_normal((s.n, 3)) * 0.05
+    print(f"[gpu] near-coincident atoms {prec}", flush=True)
+    ctx, t = amoeba.context_for(s, precision=prec, device=DEV)
+    mt = torch.tensor(mu, device=DEV)
+    # FP64: the direct formulas of both sides cancel at 0.02 A (B2 ~ 3/r^5 ~ 1e9), ~1e-10 relative
+    tf = 1e-9 if prec == "fp64" else 2e-6
+    er, _ = ctx.dipole_field_parts(t["pos"], mt)
+    err = rel_rms(er.cpu().numpy(), O.real_mutual(s, mu))
+    assert err < tf, err
+    err = rel_rms(ctx.dipole_matvec(t["pos"], mt).cpu().numpy(), O.matvec(s, mu, "spme"))
+    assert err < tf, err
+    e_ref = O.perm_field(s, "spme")
+    e = ctx.perm_field(t["pos"], t["q"], t["dip"], t["quad"])
+    err = rel_rms(e.cpu().numpy(), e_ref)
+    # FP64 permanent field: B3 ~ 15/r^7 ~ 1e13 at 0.02 A cancels in both direct formulas
+    assert err < (1e-7 if prec == "fp64" else 2e-5), err
+    mu_ref, _, _ = O.pcg(s, e_ref, "spme", tol_debye=1e-10)
+    m, ep, it, st = ctx.polarize(t["pos"], e, tol_debye=1e-7 if prec == "fp64" else 1e-6)
+    assert st == amoeba.AMOEBA_OK
+    err = O.rms_debye(m.cpu().numpy() - mu_ref)
+    assert err < (3e-7 if prec == "fp64" else 5e-6), err
+    ctx.close()
+
+
 def test_error_paths(c1):
     p = amoeba.Context(c1.n, c1.box, grid=c1.grid)
     pos = torch.tensor(c1.pos, device=DEV)
