@@ -75,6 +75,18 @@ typedef enum amoeba_guess_mode {
                                   mu_guess is NULL)                                           */
 } amoeba_guess_mode;
 
+/* How the reciprocal dipole field of the PCG product is computed (paper, "Reciprocal space
+ * scheme"; the permanent-multipole field always uses the brick path).  Both give the same
+ * field up to rounding. */
+typedef enum amoeba_pme_path {
+    AMOEBA_PME_AUTO = 0,    /* planes when the grid fits, else bricks                          */
+    AMOEBA_PME_PLANES = 1,  /* x-planes held in LDS: spread and y-z FFT fused, x-line FFT with
+                               the influence function, inverse y-z FFT and interpolation fused;
+                               needs every K a product of 2, 3, 5, 7 and a plane of
+                               ceil(K1/2) x 2(K2/2+1) complex FP64 values within 150 KB       */
+    AMOEBA_PME_BRICKS = 2   /* 8^3-point brick spread and gather around rocFFT r2c / c2r      */
+} amoeba_pme_path;
+
 typedef struct amoeba_params {
     int32_t n_atoms;       /* N >= 1                                                          */
     double box[3];         /* orthorhombic box edges (A)                                      */
@@ -106,7 +118,7 @@ typedef struct amoeba_info {
     int32_t pair_min_image;    /* 1 if the pair kernels apply the minimum image per pair; 0 when
                                   the list build proved block-relative offsets already give it
                                   (cutoff + 3 buffer + 4 x largest block half-extent < box/2) */
-    int32_t reserved;
+    int32_t pme_planes;        /* 1 if the PCG products use the plane path (amoeba_pme_path)  */
 } amoeba_info;
 
 /* Create a context for one system size and one parameter set on the current HIP device,
@@ -245,6 +257,11 @@ int amoeba_guess_train_step(amoeba_ctx* ctx, const float* feat, const float* bas
 /* The learned guess for one configuration: mu0_out[N][3] (device FP64, caller order), the
  * starting point amoeba_polarize uses with AMOEBA_GUESS_LEARNED. */
 int amoeba_guess_predict(amoeba_ctx* ctx, const double* pos, const double* e_perm, double* mu0_out);
+
+/* Select the reciprocal dipole-field path (amoeba_pme_path) for later products.
+ * AMOEBA_PME_PLANES on a grid that does not fit: AMOEBA_E_INVALID, the setting is unchanged.
+ * The default is AMOEBA_PME_AUTO. */
+int amoeba_set_pme_path(amoeba_ctx* ctx, int32_t path);
 
 /* Sizes and counters of the context (host struct). */
 int amoeba_get_info(const amoeba_ctx* ctx, amoeba_info* out);

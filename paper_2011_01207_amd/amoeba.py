@@ -34,6 +34,10 @@ AMOEBA_GUESS_GIVEN = 1
 AMOEBA_GUESS_LEARNED = 2
 AMOEBA_GUESS_BEST = 3
 GUESS_NAMES = {0: "zero", 1: "given", 2: "learned", 3: "best"}
+AMOEBA_PME_AUTO = 0
+AMOEBA_PME_PLANES = 1
+AMOEBA_PME_BRICKS = 2
+PME_PATHS = {"auto": 0, "planes": 1, "bricks": 2}
 
 GUESS_NFEAT = 11
 GUESS_NBASIS = 3
@@ -55,7 +59,7 @@ class amoeba_info(ctypes.Structure):
                 ("last_iterations", ctypes.c_int32), ("last_rms_debye", ctypes.c_double),
                 ("last_guess", ctypes.c_int32), ("guess_loaded", ctypes.c_int32),
                 ("last_guess_rms_debye", ctypes.c_double * 2), ("pair_min_image", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("pme_planes", ctypes.c_int32)]
 
 
 class amoeba_timing(ctypes.Structure):
@@ -106,6 +110,7 @@ def lib() -> ctypes.CDLL:
         L.amoeba_guess_train_step.argtypes = [_P, _P, _P, _P, ctypes.c_int64, _P, ctypes.c_int64, ctypes.c_float,
                                               ctypes.POINTER(ctypes.c_double)]
         L.amoeba_guess_predict.argtypes = [_P, _P, _P, _P]
+        L.amoeba_set_pme_path.argtypes = [_P, ctypes.c_int32]
         L.amoeba_set_timing.argtypes = [_P, ctypes.c_int]
         L.amoeba_get_timing.argtypes = [_P, ctypes.POINTER(amoeba_timing)]
         _lib = L
@@ -226,6 +231,10 @@ class Context:
             _ptr(out, torch.float64, (n, 3), "mu_out"), ctypes.byref(ep), ctypes.byref(it)),
             ok=(AMOEBA_OK, AMOEBA_NOT_CONVERGED))
         return out, ep.value, it.value, st
+
+    def set_pme_path(self, path):
+        """path: "auto", "planes" or "bricks" (or the AMOEBA_PME_* value)."""
+        self._check(lib().amoeba_set_pme_path(self.h, PME_PATHS[path] if isinstance(path, str) else int(path)))
 
     def info(self) -> dict:
         inf = amoeba_info()

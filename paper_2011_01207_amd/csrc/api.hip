@@ -669,6 +669,19 @@ int amoeba_get_timing(amoeba_ctx* c, amoeba_timing* out)
     return AMOEBA_OK;
 }
 
+int amoeba_set_pme_path(amoeba_ctx* c, int32_t path)
+{
+    if (!c)
+        return AMOEBA_E_INVALID;
+    if (path != AMOEBA_PME_AUTO && path != AMOEBA_PME_PLANES && path != AMOEBA_PME_BRICKS)
+        return set_error(c, AMOEBA_E_INVALID, "amoeba_set_pme_path: unknown path");
+    if (path == AMOEBA_PME_PLANES && !c->plane_ok)
+        return set_error(c, AMOEBA_E_INVALID, "amoeba_set_pme_path: the PME grid does not fit the plane path "
+                                              "(K not a product of 2, 3, 5, 7, or the plane exceeds 150 KB)");
+    c->pme_path = path;
+    return AMOEBA_OK;
+}
+
 int amoeba_get_info(const amoeba_ctx* cc, amoeba_info* out)
 {
     if (!cc || !out)
@@ -696,7 +709,7 @@ int amoeba_get_info(const amoeba_ctx* cc, amoeba_info* out)
     out->last_guess_rms_debye[0] = c->last_guess_rms[0];
     out->last_guess_rms_debye[1] = c->last_guess_rms[1];
     out->pair_min_image = c->skip_mimg ? 0 : 1;
-    out->reserved = 0;
+    out->pme_planes = c->plane_ok && c->pme_path != AMOEBA_PME_BRICKS ? 1 : 0;
     return AMOEBA_OK;
 }
 

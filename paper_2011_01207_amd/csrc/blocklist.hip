@@ -584,8 +584,11 @@ __global__ __launch_bounds__(256) void k_tile_refresh(int ntiles, const int* __r
     __syncthreads();
     unsigned long long m = 0;
     if (act) {
-        jrel_d[(size_t)t * kBlock + lane] = make_double4(jx, jy, jz, 0.0);
-        jrel_f[(size_t)t * kBlock + lane] = make_float4((float)jx, (float)jy, (float)jz, 0.0f);
+        // the pair kernels of the context's precision read one of the two
+        if (jrel_d)
+            jrel_d[(size_t)t * kBlock + lane] = make_double4(jx, jy, jz, 0.0);
+        if (jrel_f)
+            jrel_f[(size_t)t * kBlock + lane] = make_float4((float)jx, (float)jy, (float)jz, 0.0f);
         bool diag = tile_j[(size_t)t * kBlock] == I * kBlock;
         const float lo2 = (float)(rc2 * (1.0 - 1e-5)), hi2 = (float)(rc2 * (1.0 + 1e-5));
         const float Lx = (float)box.x, Ly = (float)box.y, Lz = (float)box.z;
@@ -797,9 +800,9 @@ int build_blocklist(amoeba_ctx* c, const double* pos)
         if ((rc = ctx_alloc(c, (void**)&c->tile_blk, sizeof(int) * total)) ||
             (rc = ctx_alloc(c, (void**)&c->tile_j, sizeof(int) * tb)) ||
             (rc = ctx_alloc(c, (void**)&c->tile_mask, sizeof(unsigned long long) * tb)) ||
-            (rc = ctx_alloc(c, (void**)&c->jrel_f, sizeof(float4) * tb)) ||
-            (rc = ctx_alloc(c, (void**)&c->jrel_d, sizeof(double4) * tb)) ||
-            (rc = ctx_alloc(c, &c->jbuf, rs * 3 * tb)) ||
+            (c->mixed && (rc = ctx_alloc(c, (void**)&c->jrel_f, sizeof(float4) * tb))) ||
+            (!c->mixed && (rc = ctx_alloc(c, (void**)&c->jrel_d, sizeof(double4) * tb))) ||
+            (rc = ctx_alloc(c, &c->jbuf, rs * 4 * tb)) ||
             (rc = ctx_alloc(c, (void**)&c->rev_idx, sizeof(int) * tb)) ||
             (rc = ctx_alloc(c, (void**)&c->pair_part, sizeof(unsigned long long) * ((size_t)total / 4 + 1))))
             return fail(rc);

@@ -46,6 +46,16 @@ enum : int {
 constexpr double kFixRange = 8192.0;
 __device__ __forceinline__ double fixd(float v) { return rint((double)v * 1099511627776.0); }
 
+// Workgroups are dispatched round-robin over the eight XCDs (workgroup b runs on XCD b mod 8),
+// each with its own L2.  This maps the hardware index to a work item so that every XCD gets a
+// contiguous range of items; consecutive items (neighbouring blocks or bricks, which read the
+// same atoms and grid points) then share one L2.  A bijection of [0, n).
+__device__ __forceinline__ int xcd_remap(int b, int n)
+{
+    const int q = n >> 3, r = n & 7, x = b & 7, i = b >> 3;
+    return x * q + (x < r ? x : r) + i;
+}
+
 // Minimum image used by every FP64 distance decision of the library (list build, in-cutoff
 // masks, scaled-pair correction), so that all of them agree bit for bit.
 __device__ __forceinline__ double mimg_fp64(double d, double L, double Linv) { return d - L * rint(d * Linv); }
@@ -144,6 +154,18 @@ struct amoeba_ctx {
     int32_t* atom_bin = nullptr;   // [npad]
     int4* sp_base = nullptr;       // [npad] base grid point of each atom (x, y, z, real atom)
     void* sp_w = nullptr;          // [npad][32] (R) B-spline weights m0, m1 per dimension
+    // dipole reciprocal field by x-planes (plane.hip), used when the grid fits (plane_ok)
+    bool plane_ok = false;
+    int pme_path = 0;              // amoeba_pme_path requested by the caller
+    bool rec_plane = false;        // the last reciprocal dipole field came from the plane path
+    int32_t* xb_start = nullptr;   // [K0+1] atoms binned by the x line of their base point
+    int32_t* xb_count = nullptr;   // [K0+1]
+    int4* xb_rec = nullptr;        // [npad] per binned atom: (slot, fx, fy, fz)
+    void* xb_w = nullptr;          // [npad] (R4) spline arguments (wx, wy, wz, 0)
+    void* rec_part = nullptr;      // [npad][5] (R4) field share of each of an atom's five x-planes
+    void* pl_roots[3] = {nullptr, nullptr, nullptr};  // roots of unity exp(-2 pi i m / K) (R complex)
+    int npq = 0;                   // p.q partials written by the last PCG product
+    int npq_cap = 0;               // room for them at the start of red.part
     rocfft_plan plan_fwd = nullptr, plan_bwd = nullptr;
     rocfft_execution_info exec_fwd = nullptr, exec_bwd = nullptr;
     void* fft_work = nullptr;
@@ -151,7 +173,7 @@ struct amoeba_ctx {
 
     // real-space field pieces and vectors (slot order, FP64 N x 3 unless noted)
     double* eipart = nullptr;              // [npad*3] field at i summed over its own block's tiles
-    void* jbuf = nullptr;                  // [tile_cap*3*64] (R) j-field of every off-diagonal tile
+    void* jbuf = nullptr;                  // [tile_cap*64][4] (R) j-field (x, y, z, 0) of every off-diagonal tile slot
     int32_t* rev_ptr = nullptr;            // [npad+1] reverse index: jbuf slots where an atom is j
     int32_t* rev_idx = nullptr;            // [rev_cap] entries tile*64 + lane
     int64_t rev_cap = 0;
@@ -248,6 +270,15 @@ int pme_setup(amoeba_ctx* c);
 void pme_bin_atoms(amoeba_ctx* c);
 int pme_dipole_field(amoeba_ctx* c, bool use_done);   // spread p -> FFT -> convolve -> FFT
 int pme_perm_potential(amoeba_ctx* c);                // spread multipoles -> ... -> potential grid
+void pme_scan_excl(amoeba_ctx* c, int n, const int* in, int* out);
+
+// plane.hip
+bool plane_eligible(const amoeba_ctx* c);
+int plane_setup(amoeba_ctx* c);
+void plane_bin_atoms(amoeba_ctx* c);
+void plane_dipole_field(amoeba_ctx* c, bool use_done);  // passes A, B, C: per-atom plane shares
+void plane_gather(amoeba_ctx* c, double* out);          // E_rec from the plane shares
+int plane_combine(amoeba_ctx* c, bool use_done, bool dot_pq);  // PCG product; returns its partial count
 void launch_gather(amoeba_ctx* c, double* out);       // E_rec at atoms from the potential grid
 
 // api.hip

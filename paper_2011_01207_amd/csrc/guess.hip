@@ -131,9 +131,7 @@ __global__ __launch_bounds__(256) void k_guess_radial(const int* __restrict__ bl
             for (int c = 0; c < 3; ++c)
                 row[c] += col[c];
         } else {
-#pragma unroll
-            for (int c = 0; c < 3; ++c)
-                jbuf[((size_t)t * 3 + c) * kBlock + lane] = col[c];
+            reinterpret_cast<R4*>(jbuf)[(size_t)t * kBlock + lane] = R4{col[0], col[1], col[2], (R)0};
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();

@@ -283,9 +283,10 @@ void launch_set_direction(amoeba_ctx* c, const double* src)
                            c->v_p, c->pv_d);
 }
 
-// Partial buffers: the gather's per-brick p.Ap partials first, then the vector kernels' [G][2].
+// Partial buffers: the p.Ap partials of the operator product first (one per PME brick or per
+// 256 atoms), then the vector kernels' [G][2].
 static double* part_pq(amoeba_ctx* c) { return c->red.part; }
-static double* part_vec(amoeba_ctx* c) { return c->red.part + ((size_t)c->nbricks + 1) / 2 * 2; }
+static double* part_vec(amoeba_ctx* c) { return c->red.part + ((size_t)c->npq_cap + 1) / 2 * 2; }
 
 // q = A p for the current direction p (pv already set).
 int matvec_slot(amoeba_ctx* c, bool use_done, bool dot)
@@ -318,7 +319,7 @@ static int enqueue_iteration(amoeba_ctx* c, int it)
         return rc;
     StageTimer tm(c, AMOEBA_T_PCG);
     hipLaunchKernelGGL(k_update, dim3(kRedBlocks), dim3(256), 0, c->stream, c->npad, it, c->par_d, c->v_p, c->v_q,
-                       c->v_mu, c->v_r, c->v_z, c->sc, part_pq(c), c->nbricks, part_vec(c));
+                       c->v_mu, c->v_r, c->v_z, c->sc, part_pq(c), c->npq, part_vec(c));
     if (c->mixed)
         hipLaunchKernelGGL(k_direction<float4>, dim3(kRedBlocks), dim3(256), 0, c->stream, c->npad, c->n, it, c->v_z,
                            c->v_p, c->pv_f, c->sc, part_vec(c));

@@ -12,59 +12,17 @@
 //   M_k(w + t) = ((w + t) M_{k-1}(w + t) + (k - w - t) M_{k-1}(w + t - 1)) / (k - 1),
 // started from M_2 and evaluated for all t at once; derivatives are differences of the lower
 // orders.  Grid line for weight t is floor(u) - t (mod K), u = K x / L.
+#include <algorithm>
+
 #include "common.h"
 #include "reduce.h"
+#include "spline.h"
 
 namespace amoeba {
 
 template <typename R> struct V4p;
 template <> struct V4p<float> { using T = float4; using C = float2; };
 template <> struct V4p<double> { using T = double4; using C = double2; };
-
-// Order-5 weights m0[t] = M5(w+t), first derivatives m1 and (optionally) second derivatives m2.
-template <typename R, bool SECOND>
-__device__ __forceinline__ void spline5(R w, R* m0, R* m1, R* m2)
-{
-    R a[5] = {w, (R)1 - w, 0, 0, 0};
-    R a3[5], a4[5];
-#pragma unroll
-    for (int k = 3; k <= 5; ++k) {
-        if (k == 4)
-#pragma unroll
-            for (int t = 0; t < 5; ++t)
-                a3[t] = a[t];
-        if (k == 5)
-#pragma unroll
-            for (int t = 0; t < 5; ++t)
-                a4[t] = a[t];
-        const R inv = (R)1 / (R)(k - 1);
-#pragma unroll
-        for (int t = k - 1; t >= 1; --t)
-            a[t] = ((w + (R)t) * a[t] + ((R)k - w - (R)t) * a[t - 1]) * inv;
-        a[0] = w * a[0] * inv;
-    }
-#pragma unroll
-    for (int t = 0; t < 5; ++t) {
-        m0[t] = a[t];
-        m1[t] = a4[t] - (t > 0 ? a4[t - 1] : (R)0);
-        if (SECOND)
-            m2[t] = a3[t] - (t > 0 ? (R)2 * a3[t - 1] : (R)0) + (t > 1 ? a3[t - 2] : (R)0);
-    }
-}
-
-// fractional grid coordinate of a wrapped position: integer base and spline argument
-__device__ __forceinline__ void grid_coord(double x, double kl, int K, int& fl, double& w)
-{
-    double u = x * kl;
-    double f = floor(u);
-    fl = (int)f;
-    w = u - f;
-    if (fl >= K) {  // x rounded up to L
-        fl -= K;
-    }
-    if (fl < 0)
-        fl += K;
-}
 
 // Per configuration: each atom's base grid point and its order-5 weights and first derivatives
 // per dimension (the positions do not change during a solve, so the spread and the gather of
@@ -662,7 +620,7 @@ __global__ __launch_bounds__(256) void k_gather_brick(int3 K, int3 nbr, const in
     if (use_done && sc->done)
         return;
     const int tid = threadIdx.x;
-    const int b = blockIdx.x;
+    const int b = xcd_remap(blockIdx.x, gridDim.x);
     const int bz = b % nbr.z, by = (b / nbr.z) % nbr.y, bx = b / (nbr.z * nbr.y);
     const int ox = bx * kBrick - 4, oy = by * kBrick - 4, oz = bz * kBrick - 4;  // region origin
     for (int idx = tid; idx < kReg * kReg * kReg; idx += 256) {
@@ -728,7 +686,7 @@ __global__ __launch_bounds__(256) void k_gather_brick(int3 K, int3 nbr, const in
                 er = eipart[3 * (size_t)s + c];
                 for (int k = rev_ptr[s]; k < rev_ptr[s + 1]; ++k) {
                     const int e = rev_idx[k];
-                    er += (double)jbuf[((size_t)(e >> 6) * 3 + c) * kBlock + (e & 63)];
+                    er += (double)jbuf[4 * (size_t)e + c];
                 }
             }
         }
@@ -863,7 +821,9 @@ int pme_setup(amoeba_ctx* c)
         rocfft_execution_info_set_work_buffer(c->exec_fwd, c->fft_work, c->fft_work_bytes);
         rocfft_execution_info_set_work_buffer(c->exec_bwd, c->fft_work, c->fft_work_bytes);
     }
-    return AMOEBA_OK;
+    c->npq_cap = std::max(c->nbricks, nblk(c->npad, 256));
+    c->npq = c->nbricks;
+    return plane_setup(c);
 }
 
 __global__ void k_scan_excl_pme(int n, const int* __restrict__ in, int* __restrict__ out);
@@ -888,6 +848,7 @@ void pme_bin_atoms(amoeba_ctx* c)
     else
         hipLaunchKernelGGL(k_spline_table<double>, dim3(nblk(c->npad, 256)), dim3(256), 0, st, c->npad, c->perm,
                            c->pos_s, kl, K, c->sp_base, (double*)c->sp_w);
+    plane_bin_atoms(c);
 }
 
 __global__ __launch_bounds__(1024) void k_scan_excl_pme(int n, const int* __restrict__ in, int* __restrict__ out)
@@ -916,6 +877,11 @@ __global__ __launch_bounds__(1024) void k_scan_excl_pme(int n, const int* __rest
         out[n] = part[1023];
 }
 
+void pme_scan_excl(amoeba_ctx* c, int n, const int* in, int* out)
+{
+    hipLaunchKernelGGL(k_scan_excl_pme, dim3(1), dim3(1024), 0, c->stream, n, in, out);
+}
+
 static int run_fft(amoeba_ctx* c, const void* grid_src, bool use_done)
 {
     (void)grid_src;
@@ -942,8 +908,15 @@ static int convolve_and_back(amoeba_ctx* c, bool use_done)
     return AMOEBA_OK;
 }
 
+static bool use_planes(const amoeba_ctx* c) { return c->plane_ok && c->pme_path != AMOEBA_PME_BRICKS; }
+
 int pme_dipole_field(amoeba_ctx* c, bool use_done)
 {
+    c->rec_plane = use_planes(c);
+    if (c->rec_plane) {
+        plane_dipole_field(c, use_done);
+        return AMOEBA_OK;
+    }
     int3 K = make_int3(c->K[0], c->K[1], c->K[2]);
     int3 nbr = make_int3(c->nbr[0], c->nbr[1], c->nbr[2]);
     double3 kl = make_double3(c->K[0] / c->prm.box[0], c->K[1] / c->prm.box[1], c->K[2] / c->prm.box[2]);
@@ -970,6 +943,7 @@ int pme_dipole_field(amoeba_ctx* c, bool use_done)
 int pme_perm_potential(amoeba_ctx* c)
 {
     StageTimer tm(c, AMOEBA_T_PERM);
+    c->rec_plane = false;
     int3 K = make_int3(c->K[0], c->K[1], c->K[2]);
     int3 nbr = make_int3(c->nbr[0], c->nbr[1], c->nbr[2]);
     double3 kl = make_double3(c->K[0] / c->prm.box[0], c->K[1] / c->prm.box[1], c->K[2] / c->prm.box[2]);
@@ -989,6 +963,10 @@ int pme_perm_potential(amoeba_ctx* c)
 
 void launch_gather(amoeba_ctx* c, double* out)
 {
+    if (c->rec_plane) {
+        plane_gather(c, out);
+        return;
+    }
     StageTimer tm(c, AMOEBA_T_GATHER);
     int3 K = make_int3(c->K[0], c->K[1], c->K[2]);
     int3 nbr = make_int3(c->nbr[0], c->nbr[1], c->nbr[2]);
@@ -1009,6 +987,11 @@ void launch_gather(amoeba_ctx* c, double* out)
 
 void launch_matvec_combine(amoeba_ctx* c, bool use_done, bool dot_pq)
 {
+    if (c->rec_plane) {
+        c->npq = plane_combine(c, use_done, dot_pq);
+        return;
+    }
+    c->npq = c->nbricks;
     StageTimer tm(c, AMOEBA_T_GATHER);
     int3 K = make_int3(c->K[0], c->K[1], c->K[2]);
     int3 nbr = make_int3(c->nbr[0], c->nbr[1], c->nbr[2]);

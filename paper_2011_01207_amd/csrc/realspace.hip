@@ -363,7 +363,7 @@ template <typename R> struct MultipoleKind {
 
 // ------------------------------------------------------------------------------------------
 // K3 / K3p: one workgroup per i-block over all the block's tiles.
-// jbuf layout: [tile][component][lane] (R);  eipart: [slot][3] (FP64).
+// jbuf layout: [tile * 64 + lane] (x, y, z, 0) (R);  eipart: [slot][3] (FP64).
 // ------------------------------------------------------------------------------------------
 template <typename R, bool FIX, class K, bool MI>
 __global__ __launch_bounds__(256) void k_block_tiles(int nb, const int* __restrict__ blk_tile0,
@@ -490,9 +490,9 @@ __global__ __launch_bounds__(256) void k_block_tiles(int nb, const int* __restri
             for (int c = 0; c < 3; ++c)
                 LdsField<FIX>::add_raw(&s_ei[c][lane], s_ej[w][c][lane]);
         } else {
-#pragma unroll
-            for (int c = 0; c < 3; ++c)
-                jbuf[((size_t)t * 3 + c) * kBlock + lane] = (R)LdsField<FIX>::value(s_ej[w][c][lane]);
+            reinterpret_cast<R4*>(jbuf)[(size_t)t * kBlock + lane] =
+                R4{(R)LdsField<FIX>::value(s_ej[w][0][lane]), (R)LdsField<FIX>::value(s_ej[w][1][lane]),
+                   (R)LdsField<FIX>::value(s_ej[w][2][lane]), (R)0};
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
@@ -516,11 +516,10 @@ __global__ void k_real_reduce(int npad, const double* __restrict__ eipart, const
         return;
     double e0 = eipart[3 * (size_t)s], e1 = eipart[3 * (size_t)s + 1], e2 = eipart[3 * (size_t)s + 2];
     for (int k = rev_ptr[s]; k < rev_ptr[s + 1]; ++k) {
-        const int e = rev_idx[k];
-        const size_t base = (size_t)(e >> 6) * 3 * kBlock + (e & 63);
-        e0 += (double)jbuf[base];
-        e1 += (double)jbuf[base + kBlock];
-        e2 += (double)jbuf[base + 2 * kBlock];
+        const typename V4<R>::T v = reinterpret_cast<const typename V4<R>::T*>(jbuf)[rev_idx[k]];
+        e0 += (double)v.x;
+        e1 += (double)v.y;
+        e2 += (double)v.z;
     }
     ereal[3 * (size_t)s] = e0;
     ereal[3 * (size_t)s + 1] = e1;

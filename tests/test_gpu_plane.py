@@ -1,0 +1,116 @@
+"""GPU parity of the plane path of the reciprocal dipole field (x-planes of the PME grid in LDS:
+fused spread and y-z FFT, x-line FFT with the influence function, fused inverse y-z FFT and
+interpolation) against the FP64 oracle's smooth PME and against the brick / rocFFT path of
+the same context, on grids with odd edges, radices 2 to 7 and non-cubic shapes."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2011_01207_amd import amoeba, synth
+
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+DEV = "cuda:0"
+TOL = {"fp64": 1e-11, "mixed": 2e-5}
+# both paths on one context: same arithmetic up to summation order and FFT algorithm
+TOL_PATHS = {"fp64": 1e-12, "mixed": 5e-6}
+
+
+def rel_rms(a, b):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    return float(np.sqrt(np.mean((a - b) ** 2)) / np.sqrt(np.mean(b ** 2)))
+
+
+def system(grid, seed=3):
+    s = synth.water_box(216, 18.63, 24, seed, "water_648")
+    s.grid = tuple(grid)
+    return s
+
+
+GRIDS = [(24, 24, 24), (20, 21, 28), (30, 25, 18), (28, 15, 35), (10, 12, 14)]
+
+
+@pytest.mark.parametrize("grid", GRIDS, ids=lambda g: "x".join(map(str, g)))
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_plane_field_matches_oracle_and_bricks(grid, prec):
+    print(f"[gpu] plane field grid={grid} {prec}", flush=True)
+    s = system(grid)
+    rng = np.random.default_rng(11)
+    mu = rng.standard_normal((s.n, 3)) * 0.05
+    ref_rec = O.spme_field(s, dip=mu)
+    ref_mv = O.matvec(s, mu, "spme")
+    ctx, t = amoeba.context_for(s, precision=prec, device=DEV)
+    try:
+        assert ctx.info()["pme_planes"] == 1
+        mu_d = torch.tensor(mu, device=DEV)
+        _, ek = ctx.dipole_field_parts(t["pos"], mu_d)
+        ek = ek.cpu().numpy()
+        q = ctx.dipole_matvec(t["pos"], mu_d).cpu().numpy()
+        err_rec = rel_rms(ek, ref_rec)
+        err_mv = rel_rms(q, ref_mv)
+        ctx.set_pme_path("bricks")
+        assert ctx.info()["pme_planes"] == 0
+        _, ek_b = ctx.dipole_field_parts(t["pos"], mu_d)
+        q_b = ctx.dipole_matvec(t["pos"], mu_d).cpu().numpy()
+        err_paths = rel_rms(ek, ek_b.cpu().numpy())
+        err_paths_mv = rel_rms(q, q_b)
+    finally:
+        ctx.close()
+    assert err_rec < TOL[prec], err_rec
+    assert err_mv < (1e-12 if prec == "fp64" else 2e-6), err_mv
+    assert err_paths < TOL_PATHS[prec], err_paths
+    assert err_paths_mv < TOL_PATHS[prec], err_paths_mv
+
+
+def test_plane_mixed_is_bitwise_reproducible():
+    s = system((20, 21, 28))
+    rng = np.random.default_rng(5)
+    mu = torch.tensor(rng.standard_normal((s.n, 3)) * 0.05, device=DEV)
+    ctx, t = amoeba.context_for(s, precision="mixed", device=DEV)
+    try:
+        a = ctx.dipole_field_parts(t["pos"], mu)[1].clone()
+        # a different list build of the same configuration refills the x-bins in another order
+        ctx.build_blocklist(t["pos"])
+        b = ctx.dipole_field_parts(t["pos"], mu)[1].clone()
+    finally:
+        ctx.close()
+    assert torch.equal(a, b)
+
+
+def test_plane_solve_matches_oracle():
+    s = system((20, 21, 28))
+    e_ref = O.perm_field(s, "spme")
+    mu_ref, _, _ = O.pcg(s, e_ref, "spme", tol_debye=1e-10)
+    e_gpu = torch.tensor(e_ref, device=DEV)
+    for prec in ("fp64", "mixed"):
+        ctx, t = amoeba.context_for(s, precision=prec, device=DEV)
+        try:
+            assert ctx.info()["pme_planes"] == 1
+            mu, ep, it, st = ctx.polarize(t["pos"], e_gpu, tol_debye=1e-7, max_iter=200)
+        finally:
+            ctx.close()
+        assert st == amoeba.AMOEBA_OK
+        err = O.rms_debye(mu.cpu().numpy() - mu_ref)
+        assert err < (2e-7 if prec == "fp64" else 1e-5), (prec, err)
+
+
+def test_grid_outside_plane_path_falls_back_to_bricks():
+    s = system((22, 24, 24))   # 22 = 2 x 11: no radix for 11
+    rng = np.random.default_rng(2)
+    mu = rng.standard_normal((s.n, 3)) * 0.05
+    ref = O.spme_field(s, dip=mu)
+    ctx, t = amoeba.context_for(s, precision="fp64", device=DEV)
+    try:
+        assert ctx.info()["pme_planes"] == 0
+        with pytest.raises(amoeba.AmoebaError):
+            ctx.set_pme_path("planes")
+        ctx.set_pme_path("auto")
+        _, ek = ctx.dipole_field_parts(t["pos"], torch.tensor(mu, device=DEV))
+    finally:
+        ctx.close()
+    assert rel_rms(ek.cpu().numpy(), ref) < TOL["fp64"]
