@@ -110,6 +110,7 @@ def run_variant(s, t, precision, steps, warmup, tol, timing=True):
     info = ctx.info()
     out = {"step_ms": 1e3 * (t1 - t0) / steps, "solve_only_ms": 1e3 * (u1 - u0) / steps, "iterations": it,
            "e_pol_kcal": ep, "n_pairs": info["n_pairs"], "n_tiles": info["n_tiles"], "n_blocks": info["n_blocks"],
+           "pme_planes": info["pme_planes"],
            "timing": tim, "mu": mu.clone(), "e_perm": e_perm.clone()}
     ctx.close()
     return out
@@ -219,26 +220,46 @@ def roofline(s, res, K):
                       "algorithmic_per_launch": FLOPS_PER_PAIR * res["n_pairs"],
                       "peak_nonpacked": PEAK_FP32_NONPACKED,
                       "frac_nonpacked": flops / (ms * 1e-3) / 1e12 / PEAK_FP32_NONPACKED}
-    # PME spread: position (12 B) + dipole (12 B) per atom read, FP32 grid written once
-    b_spread = n * 24 + k3 * 4
+    kh = K[2] // 2 + 1
+    nc = K[0] * K[1] * kh
+    if res.get("pme_planes"):
+        # plane path.  spread stage = k_plane_fwd: per atom its binned record (16 B) and spline
+        # arguments (16 B) and its FP32 dipole (16 B) read once, the half-complex y-z spectrum
+        # (8 B per point) written once
+        b_spread = n * 48 + nc * 8
+        k_spread = "k_plane_fwd<float, true>"
+        # fft stage = k_plane_xconv: half grid read and written, influence function read
+        b_fft = nc * (8 + 8 + 4)
+        k_fft = "k_plane_xconv<float>"
+        # gather stage = k_plane_bwd + k_plane_combine: half grid read once, atom records read,
+        # five field shares written and read (16 B each); combine: i-field 24 B, direction 24 B,
+        # 1/alpha 8 B read and A p 24 B written per atom, every tile j-field slot (16 B) read
+        b_gather = nc * 8 + n * (32 + 2 * 80 + 24 + 24 + 8 + 24) + res["n_tiles"] * 64 * 16
+        k_gather = "k_plane_bwd<float> + k_plane_combine<float, 1>"
+    else:
+        # PME spread: position (12 B) + dipole (12 B) per atom read, FP32 grid written once
+        b_spread = n * 24 + k3 * 4
+        k_spread = "k_spread_dip<float, true>"
+        # FFT pair + influence product: each 3-D FFT reads and writes the grid once (real K^3 x
+        # 4 B, half-complex K^3 x 4 B); the product reads/writes the half grid and reads theta
+        b_fft = 2 * (k3 * 4 + k3 * 4) + (k3 * 4 * 2 + k3 * 2)
+        k_fft = "rocFFT r2c + k_convolve + rocFFT c2r"
+        # gather + operator assembly: grid read once; per atom position 12, real-space field 24,
+        # direction 24, 1/alpha 8 read and A p 24 written (FP64 vectors)
+        b_gather = k3 * 4 + n * (12 + 24 + 24 + 8 + 24)
+        k_gather = "k_gather_brick<float, 1>"
     ms = tim["ms"]["spread"]
     stages["spread"] = {"bound": "hbm", "achieved": b_spread * mv / (ms * 1e-3) / 1e9, "peak": PEAK_HBM,
                         "unit": "GB/s", "ms_total": ms, "launches": tim["launches"]["spread"],
-                        "kernel": "k_spread_dip<float, true>", "algorithmic_per_launch": b_spread}
-    # gather + operator assembly: grid read once; per atom position 12, real-space field 24,
-    # direction 24, 1/alpha 8 read and A p 24 written (FP64 vectors)
-    b_gather = k3 * 4 + n * (12 + 24 + 24 + 8 + 24)
+                        "kernel": k_spread, "algorithmic_per_launch": b_spread}
     ms = tim["ms"]["gather"]
     stages["gather"] = {"bound": "hbm", "achieved": b_gather * mv / (ms * 1e-3) / 1e9, "peak": PEAK_HBM,
                         "unit": "GB/s", "ms_total": ms, "launches": tim["launches"]["gather"],
-                        "kernel": "k_gather_brick<float, 1>", "algorithmic_per_launch": b_gather}
-    # FFT pair + influence product: each 3-D FFT reads and writes the grid once (real K^3 x 4 B,
-    # half-complex K^3 x 4 B); the product reads/writes the half grid and reads theta
-    b_fft = 2 * (k3 * 4 + k3 * 4) + (k3 * 4 * 2 + k3 * 2)
+                        "kernel": k_gather, "algorithmic_per_launch": b_gather}
     ms = tim["ms"]["fft"]
     stages["fft"] = {"bound": "hbm", "achieved": b_fft * mv / (ms * 1e-3) / 1e9, "peak": PEAK_HBM,
                      "unit": "GB/s", "ms_total": ms, "launches": tim["launches"]["fft"],
-                     "kernel": "rocFFT r2c + k_convolve + rocFFT c2r", "algorithmic_per_launch": b_fft}
+                     "kernel": k_fft, "algorithmic_per_launch": b_fft}
     for v in stages.values():
         v["frac"] = v["achieved"] / v["peak"]
     dom = max(["real", "spread", "gather", "fft"], key=lambda k: stages[k]["ms_total"])

@@ -337,12 +337,16 @@ int amoeba_create(const amoeba_params* p, void* hip_stream, amoeba_ctx** out)
                 break;
         }
         if (hipHostMalloc((void**)&c->sc_host, sizeof(PcgScalars) * 2, hipHostMallocDefault) != hipSuccess ||
+            hipHostGetDevicePointer((void**)&c->sc_host_dev, c->sc_host, 0) != hipSuccess ||
             hipHostMalloc((void**)&c->flags_host, 64, hipHostMallocDefault) != hipSuccess) {
             rc = set_error(c, AMOEBA_E_NOMEM, "pinned host allocation failed");
             break;
         }
         if (hipEventCreateWithFlags(&c->ev[0], hipEventDisableTiming) != hipSuccess ||
-            hipEventCreateWithFlags(&c->ev[1], hipEventDisableTiming) != hipSuccess) {
+            hipEventCreateWithFlags(&c->ev[1], hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess ||
+            hipStreamCreateWithFlags(&c->stream2, hipStreamNonBlocking) != hipSuccess) {
             rc = set_error(c, AMOEBA_E_DEVICE, "hipEventCreate failed");
             break;
         }
@@ -363,8 +367,11 @@ int amoeba_destroy(amoeba_ctx* c)
 {
     if (!c)
         return AMOEBA_OK;
-    if (c->stream || true)
-        hipStreamSynchronize(c->stream);
+    hipStreamSynchronize(c->stream);
+    if (c->stream2) {
+        hipStreamSynchronize(c->stream2);
+        hipStreamDestroy(c->stream2);
+    }
     for (void* p : c->allocs)
         hipFree(p);
     if (c->sc_host)
@@ -384,6 +391,10 @@ int amoeba_destroy(amoeba_ctx* c)
     for (auto& e : c->ev)
         if (e)
             hipEventDestroy(e);
+    if (c->ev_fork)
+        hipEventDestroy(c->ev_fork);
+    if (c->ev_join)
+        hipEventDestroy(c->ev_join);
     for (auto& e : c->tev)
         hipEventDestroy(e);
     delete c;

@@ -191,7 +191,8 @@ struct amoeba_ctx {
     float4* mp_f = nullptr;                // same in FP32 (mixed mode)
 
     amoeba::PcgScalars* sc = nullptr;      // device scalars
-    amoeba::PcgScalars* sc_host = nullptr; // pinned mirror
+    amoeba::PcgScalars* sc_host = nullptr; // pinned mirror [2] (one per in-flight PCG iteration)
+    amoeba::PcgScalars* sc_host_dev = nullptr; // its device-side address
     amoeba::RedScratch red{};
     int* flags = nullptr;                  // device error flags
     int* flags_host = nullptr;             // pinned
@@ -199,6 +200,10 @@ struct amoeba_ctx {
     unsigned long long* pair_part = nullptr; // per-workgroup pair counts of the mask refresh
     bool pairs_pending = false;            // counter holds a pair count not yet read to n_pairs
     hipEvent_t ev[2] = {nullptr, nullptr};
+    // the real-space tiles of a PCG product run on a second stream (default priority), beside
+    // the reciprocal passes on the context stream: forked and joined with events
+    hipStream_t stream2 = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 
     // list-build scratch, kept between builds
     unsigned long long* b_keys = nullptr;  // [npow2]
@@ -260,7 +265,7 @@ int build_blocklist(amoeba_ctx* c, const double* pos);
 int prepare_config(amoeba_ctx* c, const double* pos);
 
 // realspace.hip
-void launch_mutual_tiles(amoeba_ctx* c, bool use_done);
+void launch_mutual_tiles(amoeba_ctx* c, bool use_done, hipStream_t st = nullptr);  // null: context stream
 void launch_real_reduce(amoeba_ctx* c, double* ereal);
 void launch_perm_tiles(amoeba_ctx* c);
 void launch_perm_assemble(amoeba_ctx* c, double* out_slot);
@@ -275,10 +280,11 @@ void pme_scan_excl(amoeba_ctx* c, int n, const int* in, int* out);
 // plane.hip
 bool plane_eligible(const amoeba_ctx* c);
 int plane_setup(amoeba_ctx* c);
-void plane_bin_atoms(amoeba_ctx* c);
-void plane_dipole_field(amoeba_ctx* c, bool use_done);  // passes A, B, C: per-atom plane shares
+int plane_bin_atoms(amoeba_ctx* c);
+void plane_dipole_field(amoeba_ctx* c, bool use_done, int parts);  // 1 spread, 2 the rest, 3 all
 void plane_gather(amoeba_ctx* c, double* out);          // E_rec from the plane shares
 int plane_combine(amoeba_ctx* c, bool use_done, bool dot_pq);  // PCG product; returns its partial count
+bool pme_use_planes(const amoeba_ctx* c);
 void launch_gather(amoeba_ctx* c, double* out);       // E_rec at atoms from the potential grid
 
 // api.hip
@@ -301,6 +307,6 @@ void pcg_begin(amoeba_ctx* c, double tol);                         // initial de
 int pcg_start(amoeba_ctx* c, bool have_guess, double* rms_debye);   // r0, z0, p0 from v_mu
 int pcg_start_from(amoeba_ctx* c, const double* q0);                // same, A mu0 given
 int pcg_run(amoeba_ctx* c, int max_iter, int start_matvecs, double* mu_out, double* e_pol);
-int matvec_slot(amoeba_ctx* c, bool use_done, bool dot);
+int matvec_slot(amoeba_ctx* c, bool use_done, bool dot, hipEvent_t fork_ev = nullptr);  // q = A p
 
 }  // namespace amoeba

@@ -197,10 +197,16 @@ __global__ __launch_bounds__(256) void k_update(int npad, int it, const double4*
 template <typename R4T>
 __global__ __launch_bounds__(256) void k_direction(int npad, int n, int it, const double* __restrict__ z,
                                                    double* __restrict__ p, R4T* __restrict__ pv,
-                                                   PcgScalars* __restrict__ sc, const double* __restrict__ part)
+                                                   PcgScalars* __restrict__ sc, const double* __restrict__ part,
+                                                   PcgScalars* __restrict__ pub)
 {
-    if (sc->done)
+    // pub: pinned host copy of the scalars after this iteration, written by one thread (no
+    // separate device-to-host copy per iteration)
+    if (sc->done) {
+        if (blockIdx.x == 0 && threadIdx.x == 0 && pub)
+            *pub = *sc;
         return;
+    }
     double tot[2];
     sum_partials<2>(part, gridDim.x, tot);
     const double rms = kDebye * sqrt(tot[1] / n);
@@ -221,6 +227,8 @@ __global__ __launch_bounds__(256) void k_direction(int npad, int n, int it, cons
             sc->rzb[(it + 1) & 1] = tot[0];
             sc->beta = beta;
         }
+        if (pub)
+            *pub = *sc;
     }
     if (conv || bad)
         return;
@@ -288,13 +296,33 @@ void launch_set_direction(amoeba_ctx* c, const double* src)
 static double* part_pq(amoeba_ctx* c) { return c->red.part; }
 static double* part_vec(amoeba_ctx* c) { return c->red.part + ((size_t)c->npq_cap + 1) / 2 * 2; }
 
-// q = A p for the current direction p (pv already set).
-int matvec_slot(amoeba_ctx* c, bool use_done, bool dot)
+// q = A p for the current direction p (pv already set).  With the plane path the spread pass
+// runs first on the whole GPU; then the real-space tiles (VALU bound) run on the second stream
+// while the reciprocal transforms and the interpolation (latency bound) run on the context
+// stream, so that the two share the CUs; the combine waits for both.  Stage timing keeps
+// everything on the context stream so that each stage is timed alone.
+// fork_ev: an event already recorded at the current end of the context stream (the PCG loop's
+// per-iteration event), used as the fork point instead of recording another one.
+int matvec_slot(amoeba_ctx* c, bool use_done, bool dot, hipEvent_t fork_ev)
 {
-    launch_mutual_tiles(c, use_done);
-    int rc = pme_dipole_field(c, use_done);
-    if (rc)
-        return rc;
+    if (pme_use_planes(c) && !c->timing) {
+        c->rec_plane = true;
+        if (!fork_ev) {
+            hipEventRecord(c->ev_fork, c->stream);
+            fork_ev = c->ev_fork;
+        }
+        plane_dipole_field(c, use_done, 1);
+        hipStreamWaitEvent(c->stream2, fork_ev, 0);
+        launch_mutual_tiles(c, use_done, c->stream2);
+        hipEventRecord(c->ev_join, c->stream2);
+        plane_dipole_field(c, use_done, 2);
+        hipStreamWaitEvent(c->stream, c->ev_join, 0);
+    } else {
+        launch_mutual_tiles(c, use_done, c->stream);
+        int rc = pme_dipole_field(c, use_done);
+        if (rc)
+            return rc;
+    }
     launch_matvec_combine(c, use_done, dot);
     return AMOEBA_OK;
 }
@@ -312,9 +340,9 @@ static void launch_init_residual(amoeba_ctx* c, const double* q, int it)
     hipLaunchKernelGGL(k_init_finalize, dim3(1), dim3(256), 0, c->stream, kRedBlocks, part_vec(c), c->n, it, c->sc);
 }
 
-static int enqueue_iteration(amoeba_ctx* c, int it)
+static int enqueue_iteration(amoeba_ctx* c, int it, PcgScalars* pub, hipEvent_t fork_ev)
 {
-    int rc = matvec_slot(c, true, true);
+    int rc = matvec_slot(c, true, true, fork_ev);
     if (rc)
         return rc;
     StageTimer tm(c, AMOEBA_T_PCG);
@@ -322,10 +350,10 @@ static int enqueue_iteration(amoeba_ctx* c, int it)
                        c->v_mu, c->v_r, c->v_z, c->sc, part_pq(c), c->npq, part_vec(c));
     if (c->mixed)
         hipLaunchKernelGGL(k_direction<float4>, dim3(kRedBlocks), dim3(256), 0, c->stream, c->npad, c->n, it, c->v_z,
-                           c->v_p, c->pv_f, c->sc, part_vec(c));
+                           c->v_p, c->pv_f, c->sc, part_vec(c), pub);
     else
         hipLaunchKernelGGL(k_direction<double4>, dim3(kRedBlocks), dim3(256), 0, c->stream, c->npad, c->n, it,
-                           c->v_z, c->v_p, c->pv_d, c->sc, part_vec(c));
+                           c->v_z, c->v_p, c->pv_d, c->sc, part_vec(c), pub);
     return AMOEBA_OK;
 }
 
@@ -338,10 +366,11 @@ static int run_iterations(amoeba_ctx* c, int first, int budget, PcgScalars* last
     int enq = 0, chk = 0, rc;
     while (true) {
         if (enq < budget) {
-            if ((rc = enqueue_iteration(c, first + enq)))
+            // the previous iteration's event marks the end of the stream at this point
+            if ((rc = enqueue_iteration(c, first + enq, c->sc_host_dev + ((enq + 1) & 1),
+                                        enq > 0 ? c->ev[enq & 1] : nullptr)))
                 return rc;
             ++enq;
-            hipMemcpyAsync(&c->sc_host[enq & 1], c->sc, sizeof(PcgScalars), hipMemcpyDeviceToHost, st);
             hipEventRecord(c->ev[enq & 1], st);
         }
         if (enq >= chk + 2 || enq == budget) {

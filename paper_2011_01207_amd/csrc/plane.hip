@@ -1,33 +1,32 @@
-// Reciprocal dipole field of the smooth PME by planes of the grid (paper, "Reciprocal space
-// scheme": spread of the dipoles with B-spline derivatives, forward FFT, scalar product with
-// the influence function, backward FFT, interpolation of the field; Essmann et al. 1995).
+// Reciprocal dipole field of the smooth PME in five passes over the grid (paper, "Reciprocal
+// space scheme": spread of the dipoles with B-spline derivatives, forward FFT, scalar product
+// with the influence function, backward FFT, interpolation of the field; Essmann et al. 1995).
 //
-// The grid is [K0][K1][K2] with z fastest.  Three kernels per product, each plane of constant
-// x held whole in LDS:
+// The grid is [K0][K1][K2] with z fastest; G is the half-complex grid [K0][K1][K2/2 + 1].
 //
-//   A (one workgroup per x-plane): every atom whose x-support contains the plane adds its 25
-//     (y, z) contributions to the plane in LDS, then the plane is transformed in y and z
-//     (real-to-half-complex in z) and written to the half-complex grid G[x][ky][kz].
-//   B (one workgroup per ky): FFT of the x-lines, product with the influence function,
-//     inverse FFT of the x-lines, in place in G.
-//   C (one workgroup per x-plane): inverse transform of the plane in y and z back to the real
-//     potential in LDS, then every atom whose x-support contains the plane interpolates its
-//     share of the field from it (its x-weight for this plane times the y-z sums) and writes
-//     it to its slot for that plane offset.
+//   1 (row chunk, plane x): the atoms whose support meets the chunk's rows of plane x spread
+//     into them in LDS; each row is transformed along z (real to half-complex) into G[x][y].
+//   2 (plane x, kz chunk):  FFT of the y-lines of G.
+//   3 (ky, kz chunk):       FFT of the x-lines, product with the influence function, inverse.
+//   4 (plane x, kz chunk):  inverse FFT of the y-lines.
+//   5 (row chunk, plane x): the chunk's rows and the four below it are transformed back along
+//     z into the potential in LDS; every atom whose top y line lies in the chunk interpolates
+//     its share of the field from plane x and writes it to its slot for that plane offset.
 //
 // A per-atom combine sums the five plane shares in a fixed order (plus, in the PCG product,
-// the real-space pieces and the operator assembly).  There are no grid-size global atomics and
-// no grid clearing pass; in mixed precision the spread sums are 64-bit fixed point (exact, so
-// the result does not depend on the order of the additions) and every later step is a fixed
+// the real-space pieces and the operator assembly).  Every pass has a few hundred small
+// workgroups, so all CUs share the work.  There are no grid-size global atomics and no grid
+// clearing pass; in mixed precision the spread sums are 64-bit fixed point (exact, so the
+// result does not depend on the order of the additions) and every later step is a fixed
 // sequence of operations, which makes the reciprocal field bitwise reproducible.
 //
-// Plane layout in LDS: rows y = 2p and 2p+1 share complex line p (real and imaginary part),
-// line stride S = 2 (K2/2 + 1) complex values.  A complex FFT of line p along z gives the
-// spectra of both rows, separated by X_2p[k] = (Z[k] + conj Z[K2-k]) / 2 and
-// X_2p+1[k] = (Z[k] - conj Z[K2-k]) / 2i, stored at line offsets [0, kh) and [kh, 2 kh); the
-// inverse runs the same steps backwards.  The one-dimensional transforms are self-sorting
+// Rows y = 2p and 2p+1 share one complex line (real and imaginary part) of stride
+// S = 2 (K2/2 + 1).  A complex FFT of the line along z gives the spectra of both rows,
+// separated by X_2p[k] = (Z[k] + conj Z[K2-k]) / 2 and X_2p+1[k] = (Z[k] - conj Z[K2-k]) / 2i;
+// the inverse runs the same steps backwards.  The one-dimensional transforms are self-sorting
 // (Stockham) mixed-radix FFTs (radices 2 to 7) done in place through registers, with the
 // roots of unity in LDS (computed in FP64).
+#include <algorithm>
 #include <type_traits>
 
 #include "common.h"
@@ -40,11 +39,12 @@ template <typename R> struct PlT;
 template <> struct PlT<float> { using C = float2; using R4 = float4; };
 template <> struct PlT<double> { using C = double2; using R4 = double4; };
 
-constexpr int kPlThreads = 1024;        // threads per plane workgroup
+constexpr int kPlThreads = 256;         // threads per workgroup of every pass
 constexpr int kPlMaxB = 1;              // butterflies per thread in one FFT round
-constexpr int kPlConv = 12;             // fixed-point values per thread in the conversion
-constexpr int kPlSplit = 4;             // split / combine items per thread in one round
-constexpr size_t kPlLdsMax = 150 * 1024;
+constexpr int kPlConv = 32;             // fixed-point values per thread in the conversion
+constexpr int kPlSplit = 8;             // split / combine items per thread in one round
+constexpr size_t kPlLdsMax = 64 * 1024; // LDS of one workgroup
+constexpr int kPlTargetWG = 432;        // workgroups per pass the chunking aims at
 
 // Factorisation of a transform length into radices 2..7 (host-computed).
 struct PlaneDim {
@@ -233,12 +233,17 @@ __device__ __forceinline__ void fft_lines(C* buf, int nl, const PlaneDim& d, con
     }
 }
 
-// Geometry shared by the plane kernels.
+
+// Geometry and chunking shared by the passes.  Rows y = 2p and 2p + 1 form row pair p; the
+// spread and the interpolation work on chunks of Pc consecutive pairs, the y and x transforms
+// on chunks of kc consecutive kz columns.
 struct PlaneGeom {
     int K0, K1, K2;
-    int P;        // complex lines of a plane: ceil(K1 / 2)
-    int S;        // line stride (complex values): 2 kh
     int kh;       // K2 / 2 + 1
+    int S;        // line stride of a pair (complex values): 2 kh
+    int P;        // row pairs: ceil(K1 / 2)
+    int Pc, nyc;  // pairs per row chunk, row chunks
+    int kc, nkc;  // columns per column chunk, column chunks
     double klx, kly, klz;
 };
 
@@ -255,48 +260,69 @@ template <typename R> __device__ __forceinline__ R pick5(const R (&a)[5], int t)
     return v;
 }
 
-// The atoms whose x-support contains plane x are those with base line fx in x..x+4 (mod K0)
-// (grid line of weight t is fx - t): five consecutive x-bins.  Entry i of that list, counted
-// bin by bin, is returned with its weight index t; -1 past the end.
-struct PlaneAtoms {
-    int lo[5], pre[6];
-    __device__ void init(const int* __restrict__ xb_start, int x, int K0)
-    {
-        pre[0] = 0;
-#pragma unroll
-        for (int t = 0; t < 5; ++t) {
-            int b = x + t;
-            b -= b >= K0 ? K0 : 0;
-            lo[t] = xb_start[b];
-            pre[t + 1] = pre[t] + xb_start[b + 1] - lo[t];
-        }
-    }
+// NR ranges of the (x, y)-binned atom entries; entry i of their concatenation and the x-weight
+// index t of its range (selects, so that the arrays stay in registers).
+template <int NR> struct BinRanges {
+    int lo[NR], pre[NR + 1], tq[NR];
+    __device__ __forceinline__ int total() const { return pre[NR]; }
     __device__ __forceinline__ int entry(int i, int& t) const
     {
-        // selects, not indexing, so that the arrays stay in registers
-        t = 0;
+        t = tq[0];
         int e = lo[0] + i;
 #pragma unroll
-        for (int q = 1; q < 5; ++q) {
+        for (int q = 1; q < NR; ++q) {
             const bool in = i >= pre[q];
-            t += in ? 1 : 0;
+            t = in ? tq[q] : t;
             e = in ? lo[q] + i - pre[q] : e;
         }
         return e;
     }
 };
 
-// Pass A: spread of the direction p (dipoles) into plane x, then forward y-z transform.
+// Row chunk c of the grid: pairs [p0, p0 + np), rows [ya, yb).
+struct RowChunk {
+    int np, ya, yb;
+    __device__ __forceinline__ RowChunk(const PlaneGeom& g, int c)
+    {
+        const int p0 = c * g.Pc;
+        np = min(g.Pc, g.P - p0);
+        ya = 2 * p0;
+        yb = min(g.K1, 2 * (p0 + np));
+    }
+};
+
+// the spline weights of an atom entry (arguments w) and its z grid lines, doubled for the pair
+// layout
+template <typename R>
+__device__ __forceinline__ void entry_splines(const typename PlT<R>::R4& w, int fz, int K2, R (&x0)[5], R (&x1)[5],
+                                              R (&y0)[5], R (&y1)[5], R (&z0)[5], R (&z1)[5], int (&zi)[5])
+{
+    R dum[5];
+    spline5<R, false>(w.x, x0, x1, dum);
+    spline5<R, false>(w.y, y0, y1, dum);
+    spline5<R, false>(w.z, z0, z1, dum);
+#pragma unroll
+    for (int tz = 0; tz < 5; ++tz) {
+        int zz = fz - tz;
+        zz += zz < 0 ? K2 : 0;
+        zi[tz] = 2 * zz;
+    }
+}
+
+// Pass 1 (spread, z transform): workgroup (row chunk c, plane x).  The atoms whose support
+// meets the chunk's rows of plane x have fx in x..x+4 and fy in [ya, yb + 4) (mod K); they add
+// p_x M' M M + p_y M M' M + p_z M M M' (derivatives scaled by K/L) at their in-chunk points.
+// Then every row pair is transformed along z, separated into the two rows' half spectra, and
+// the rows are written to G[x][y][0, kh).
 template <typename R, bool FIX>
-__global__ __launch_bounds__(kPlThreads) void k_plane_fwd(PlaneGeom g, PlaneDim dy, PlaneDim dz,
-                                                          const int* __restrict__ xb_start,
-                                                          const int4* __restrict__ xb_rec,
-                                                          const typename PlT<R>::R4* __restrict__ xb_w,
-                                                          const typename PlT<R>::R4* __restrict__ src,
-                                                          const typename PlT<R>::C* __restrict__ roots_y,
-                                                          const typename PlT<R>::C* __restrict__ roots_z,
-                                                          typename PlT<R>::C* __restrict__ gout,
-                                                          const PcgScalars* __restrict__ sc, int use_done)
+__global__ __launch_bounds__(kPlThreads) void k_pme_spread_z(PlaneGeom g, PlaneDim dz,
+                                                             const int* __restrict__ xy_start,
+                                                             const int4* __restrict__ xb_rec,
+                                                             const typename PlT<R>::R4* __restrict__ xb_w,
+                                                             const typename PlT<R>::R4* __restrict__ src,
+                                                             const typename PlT<R>::C* __restrict__ roots_z,
+                                                             typename PlT<R>::C* __restrict__ gout,
+                                                             const PcgScalars* __restrict__ sc, int use_done)
 {
     using C = typename PlT<R>::C;
     using R4 = typename PlT<R>::R4;
@@ -304,51 +330,61 @@ __global__ __launch_bounds__(kPlThreads) void k_plane_fwd(PlaneGeom g, PlaneDim 
     if (use_done && sc->done)
         return;
     const int tid = threadIdx.x;
-    const int x = xcd_remap(blockIdx.x, gridDim.x);
-    const int n2 = 2 * g.P * g.S;                       // doubles of the accumulation plane
+    const int item = xcd_remap(blockIdx.x, gridDim.x);
+    const int c = item / g.K0, x = item - c * g.K0;
+    const RowChunk rc(g, c);
+    const int n2 = 2 * rc.np * g.S;                    // doubles of the chunk's accumulation
     double* acc = pl_smem;
-    C* tw_y = reinterpret_cast<C*>(pl_smem + n2);
-    C* tw_z = tw_y + g.K1;
+    C* tw_z = reinterpret_cast<C*>(pl_smem + 2 * g.Pc * g.S);
     for (int i = tid; i < n2; i += kPlThreads)
         acc[i] = 0.0;
-    for (int i = tid; i < g.K1; i += kPlThreads)
-        tw_y[i] = roots_y[i];
     for (int i = tid; i < g.K2; i += kPlThreads)
         tw_z[i] = roots_z[i];
-    PlaneAtoms pa;
-    pa.init(xb_start, x, g.K0);
+    BinRanges<10> br;
+    {
+        const int L = min(g.K1, rc.yb - rc.ya + 4), f1 = rc.ya + L;
+        br.pre[0] = 0;
+#pragma unroll
+        for (int t = 0; t < 5; ++t) {
+            int bx = x + t;
+            bx -= bx >= g.K0 ? g.K0 : 0;
+            const int* st = xy_start + (size_t)bx * g.K1;
+            const int a0 = st[rc.ya], a1 = st[min(f1, g.K1)];
+            br.lo[2 * t] = a0;
+            br.tq[2 * t] = t;
+            br.pre[2 * t + 1] = br.pre[2 * t] + a1 - a0;
+            const int b1 = f1 > g.K1 ? st[f1 - g.K1] : st[0];
+            br.lo[2 * t + 1] = st[0];
+            br.tq[2 * t + 1] = t;
+            br.pre[2 * t + 2] = br.pre[2 * t + 1] + b1 - st[0];
+        }
+    }
     __syncthreads();
-
-    // spread: 25 (y, z) points per atom, p_x M' M M + p_y M M' M + p_z M M M' (derivatives
-    // scaled by K/L)
     const R klx = (R)g.klx, kly = (R)g.kly, klz = (R)g.klz;
-    for (int i = tid; i < pa.pre[5]; i += kPlThreads) {
+    const int nyr = rc.yb - rc.ya;
+    for (int i = tid; i < br.total(); i += kPlThreads) {
         int t;
-        const int e = pa.entry(i, t);
+        const int e = br.entry(i, t);
         const int4 rec = xb_rec[e];
-        const R4 w = xb_w[e];
         const R4 mu = src[rec.x];
-        R x0[5], x1[5], y0[5], y1[5], z0[5], z1[5], dum[5];
-        spline5<R, false>(w.x, x0, x1, dum);
-        spline5<R, false>(w.y, y0, y1, dum);
-        spline5<R, false>(w.z, z0, z1, dum);
+        R x0[5], x1[5], y0[5], y1[5], z0[5], z1[5];
+        int zi[5];
+        entry_splines<R>(xb_w[e], rec.w, g.K2, x0, x1, y0, y1, z0, z1, zi);
         const R tx0 = pick5(x0, t), tx1 = pick5(x1, t) * klx;
         const R ax = mu.x * tx1, bx = mu.y * tx0, cx = mu.z * tx0;
-        int zi[5];
 #pragma unroll
-        for (int tz = 0; tz < 5; ++tz) {
-            int zz = rec.w - tz;
-            zz += zz < 0 ? g.K2 : 0;
-            zi[tz] = 2 * zz;
+        for (int tz = 0; tz < 5; ++tz)
             z1[tz] *= klz;
-        }
 #pragma unroll
         for (int ty = 0; ty < 5; ++ty) {
             int yy = rec.z - ty;
             yy += yy < 0 ? g.K1 : 0;
+            const int yl = yy - rc.ya;
+            if (yl < 0 || yl >= nyr)
+                continue;
             const R cz0 = ax * y0[ty] + bx * (y1[ty] * kly);
             const R cz1 = cx * y0[ty];
-            double* row = acc + 2 * (yy >> 1) * g.S + (yy & 1);
+            double* row = acc + 2 * (yl >> 1) * g.S + (yl & 1);
 #pragma unroll
             for (int tz = 0; tz < 5; ++tz) {
                 const R v = cz0 * z0[tz] + cz1 * z1[tz];
@@ -362,7 +398,7 @@ __global__ __launch_bounds__(kPlThreads) void k_plane_fwd(PlaneGeom g, PlaneDim 
     __syncthreads();
     C* pl = reinterpret_cast<C*>(pl_smem);
     if (FIX) {
-        // fixed point -> FP32 in place (value k of the plane keeps its index)
+        // fixed point -> FP32 in place (value k keeps its index)
         float f[kPlConv];
 #pragma unroll
         for (int m = 0; m < kPlConv; ++m) {
@@ -379,15 +415,13 @@ __global__ __launch_bounds__(kPlThreads) void k_plane_fwd(PlaneGeom g, PlaneDim 
         }
         __syncthreads();
     }
-
-    // z: complex FFT of the P row pairs
-    fft_lines<-1>(pl, g.P, dz, tw_z, LineMap{g.S, 2, 1});
+    fft_lines<-1>(pl, rc.np, dz, tw_z, LineMap{g.S, 2, 1});
     // separate the two rows of every pair into half spectra at [0, kh) and [kh, 2 kh)
     {
         const int lpr = max(1, kPlThreads * kPlSplit / g.kh);
         const SmallDiv dkh(g.kh);
-        for (int p0 = 0; p0 < g.P; p0 += lpr) {
-            const int cnt = min(lpr, g.P - p0) * g.kh;
+        for (int p0 = 0; p0 < rc.np; p0 += lpr) {
+            const int cnt = min(lpr, rc.np - p0) * g.kh;
             C a[kPlSplit], b[kPlSplit];
 #pragma unroll
             for (int m = 0; m < kPlSplit; ++m) {
@@ -395,8 +429,7 @@ __global__ __launch_bounds__(kPlThreads) void k_plane_fwd(PlaneGeom g, PlaneDim 
                 if (it < cnt) {
                     const int pq = dkh.quot(it), p = p0 + pq, k = it - pq * g.kh;
                     const C z = pl[p * g.S + k];
-                    const int kr = k == 0 ? 0 : g.K2 - k;
-                    const C zr = pl[p * g.S + kr];
+                    const C zr = pl[p * g.S + (k == 0 ? 0 : g.K2 - k)];
                     // (z + conj zr) / 2 and (z - conj zr) / 2i
                     a[m] = C{(R)0.5 * (z.x + zr.x), (R)0.5 * (z.y - zr.y)};
                     b[m] = C{(R)0.5 * (z.y + zr.y), (R)0.5 * (zr.x - z.x)};
@@ -415,74 +448,112 @@ __global__ __launch_bounds__(kPlThreads) void k_plane_fwd(PlaneGeom g, PlaneDim 
             __syncthreads();
         }
     }
-    // y: complex FFT of the kh columns
-    fft_lines<-1>(pl, g.kh, dy, tw_y, LineMap{1, g.S, g.kh});
-    C* out = gout + (size_t)x * g.K1 * g.kh;
+    C* out = gout + ((size_t)x * g.K1 + rc.ya) * g.kh;
     const SmallDiv dkh(g.kh);
-    for (int i = tid; i < g.K1 * g.kh; i += kPlThreads) {
-        const int ky = dkh.quot(i), kz = i - ky * g.kh;
-        out[i] = pl[(ky >> 1) * g.S + (ky & 1) * g.kh + kz];
+    for (int i = tid; i < nyr * g.kh; i += kPlThreads) {
+        const int yl = dkh.quot(i), k = i - yl * g.kh;
+        out[i] = pl[(yl >> 1) * g.S + (yl & 1) * g.kh + k];
     }
 }
 
-// Pass B: x-lines of G for one ky (kz in [kz0, kz0 + cw)): FFT, product with the influence
-// function theta[kx][ky][kz], inverse FFT.
-template <typename R>
-__global__ __launch_bounds__(kPlThreads) void k_plane_xconv(PlaneGeom g, PlaneDim dx, int cw, int nch,
-                                                            typename PlT<R>::C* __restrict__ gc,
-                                                            const R* __restrict__ theta,
-                                                            const typename PlT<R>::C* __restrict__ roots_x,
-                                                            const PcgScalars* __restrict__ sc, int use_done)
+// Passes 2 and 4 (y transform, SIGN -1 forward, +1 inverse): workgroup (plane x, column chunk):
+// the y-lines G[x][.][kz] for kz in the chunk, in place.
+template <typename R, int SIGN>
+__global__ __launch_bounds__(kPlThreads) void k_pme_ylines(PlaneGeom g, PlaneDim dy,
+                                                           typename PlT<R>::C* __restrict__ gc,
+                                                           const typename PlT<R>::C* __restrict__ roots_y,
+                                                           const PcgScalars* __restrict__ sc, int use_done)
 {
     using C = typename PlT<R>::C;
     extern __shared__ __align__(16) double pl_smem[];
     if (use_done && sc->done)
         return;
     const int tid = threadIdx.x;
-    const int ky = blockIdx.x / nch, kz0 = (blockIdx.x - ky * nch) * cw;
-    const int ncol = min(cw, g.kh - kz0);
+    const int item = blockIdx.x;
+    const int x = item / g.nkc, kz0 = (item - x * g.nkc) * g.kc;
+    const int ncol = min(g.kc, g.kh - kz0);
     const SmallDiv dnc(ncol);
     C* buf = reinterpret_cast<C*>(pl_smem);
-    C* tw = buf + g.K0 * cw;
-    for (int i = tid; i < g.K0; i += kPlThreads)
-        tw[i] = roots_x[i];
-    for (int i = tid; i < g.K0 * ncol; i += kPlThreads) {
-        const int xx = dnc.quot(i), cc = i - xx * ncol;
-        buf[xx * cw + cc] = gc[((size_t)xx * g.K1 + ky) * g.kh + kz0 + cc];
+    C* tw = buf + g.K1 * g.kc;
+    for (int i = tid; i < g.K1; i += kPlThreads)
+        tw[i] = roots_y[i];
+    C* base = gc + (size_t)x * g.K1 * g.kh + kz0;
+    for (int i = tid; i < g.K1 * ncol; i += kPlThreads) {
+        const int y = dnc.quot(i), cc = i - y * ncol;
+        buf[y * g.kc + cc] = base[(size_t)y * g.kh + cc];
     }
     __syncthreads();
-    const LineMap am{1, 2 * cw, cw};
+    fft_lines<SIGN>(buf, ncol, dy, tw, LineMap{1, 2 * g.kc, g.kc});
+    for (int i = tid; i < g.K1 * ncol; i += kPlThreads) {
+        const int y = dnc.quot(i), cc = i - y * ncol;
+        base[(size_t)y * g.kh + cc] = buf[y * g.kc + cc];
+    }
+}
+
+// Pass 3: workgroup (ky, column chunk): the x-lines of G for kz in the chunk: FFT, product with
+// the influence function theta[kx][ky][kz], inverse FFT, in place.
+template <typename R>
+__global__ __launch_bounds__(kPlThreads) void k_pme_xconv(PlaneGeom g, PlaneDim dx,
+                                                          typename PlT<R>::C* __restrict__ gc,
+                                                          const R* __restrict__ theta,
+                                                          const typename PlT<R>::C* __restrict__ roots_x,
+                                                          const PcgScalars* __restrict__ sc, int use_done)
+{
+    using C = typename PlT<R>::C;
+    extern __shared__ __align__(16) double pl_smem[];
+    if (use_done && sc->done)
+        return;
+    const int tid = threadIdx.x;
+    const int item = blockIdx.x;
+    const int ky = item / g.nkc, kz0 = (item - ky * g.nkc) * g.kc;
+    const int ncol = min(g.kc, g.kh - kz0);
+    const SmallDiv dnc(ncol);
+    C* buf = reinterpret_cast<C*>(pl_smem);
+    C* tw = buf + g.K0 * g.kc;
+    for (int i = tid; i < g.K0; i += kPlThreads)
+        tw[i] = roots_x[i];
+    const size_t xs = (size_t)g.K1 * g.kh;   // stride of x in G
+    const size_t off = (size_t)ky * g.kh + kz0;
+    for (int i = tid; i < g.K0 * ncol; i += kPlThreads) {
+        const int xx = dnc.quot(i), cc = i - xx * ncol;
+        buf[xx * g.kc + cc] = gc[xx * xs + off + cc];
+    }
+    __syncthreads();
+    const LineMap am{1, 2 * g.kc, g.kc};
     fft_lines<-1>(buf, ncol, dx, tw, am);
     for (int i = tid; i < g.K0 * ncol; i += kPlThreads) {
         const int kx = dnc.quot(i), cc = i - kx * ncol;
-        const R th = theta[((size_t)kx * g.K1 + ky) * g.kh + kz0 + cc];
-        C v = buf[kx * cw + cc];
+        const R th = theta[kx * xs + off + cc];
+        C v = buf[kx * g.kc + cc];
         v.x *= th;
         v.y *= th;
-        buf[kx * cw + cc] = v;
+        buf[kx * g.kc + cc] = v;
     }
     __syncthreads();
     fft_lines<+1>(buf, ncol, dx, tw, am);
     for (int i = tid; i < g.K0 * ncol; i += kPlThreads) {
         const int xx = dnc.quot(i), cc = i - xx * ncol;
-        gc[((size_t)xx * g.K1 + ky) * g.kh + kz0 + cc] = buf[xx * cw + cc];
+        gc[xx * xs + off + cc] = buf[xx * g.kc + cc];
     }
 }
 
-// Pass C: inverse y-z transform of plane x, then each atom's share of the field from it:
-// part[5 s + t] = (M'_x M_y M_z psi, M_x M'_y M_z psi, M_x M_y M'_z psi) summed over the
-// plane's 25 points, t the atom's weight index for this plane (the K/L factors and the sign
-// are applied by the combine).
+// Pass 5 (z transform back, interpolation): workgroup (row chunk c, plane x).  The potential
+// rows [ya - 4, yb) (mod K1) are rebuilt from their half spectra (two rows per complex line:
+// Z[k] = A[k] + i B[k] with the Hermitian extension A[k] = conj A[K2 - k] for k >= kh, the
+// imaginary parts of the real terms k = 0 and K2/2 dropped as a real inverse transform does)
+// and transformed back along z; then every atom with fx in x..x+4 and fy in [ya, yb) adds up its
+// share of the field from plane x: part[5 s + t] = (M'_x M_y M_z psi, M_x M'_y M_z psi,
+// M_x M_y M'_z psi) over its 25 (y, z) points, t its weight index for the plane (the K/L
+// factors and the sign are applied by the combine).
 template <typename R>
-__global__ __launch_bounds__(kPlThreads) void k_plane_bwd(PlaneGeom g, PlaneDim dy, PlaneDim dz,
-                                                          const typename PlT<R>::C* __restrict__ gc,
-                                                          const int* __restrict__ xb_start,
-                                                          const int4* __restrict__ xb_rec,
-                                                          const typename PlT<R>::R4* __restrict__ xb_w,
-                                                          const typename PlT<R>::C* __restrict__ roots_y,
-                                                          const typename PlT<R>::C* __restrict__ roots_z,
-                                                          typename PlT<R>::R4* __restrict__ part,
-                                                          const PcgScalars* __restrict__ sc, int use_done)
+__global__ __launch_bounds__(kPlThreads) void k_pme_z_gather(PlaneGeom g, PlaneDim dz,
+                                                             const typename PlT<R>::C* __restrict__ gc,
+                                                             const int* __restrict__ xy_start,
+                                                             const int4* __restrict__ xb_rec,
+                                                             const typename PlT<R>::R4* __restrict__ xb_w,
+                                                             const typename PlT<R>::C* __restrict__ roots_z,
+                                                             typename PlT<R>::R4* __restrict__ part,
+                                                             const PcgScalars* __restrict__ sc, int use_done)
 {
     using C = typename PlT<R>::C;
     using R4 = typename PlT<R>::R4;
@@ -490,33 +561,30 @@ __global__ __launch_bounds__(kPlThreads) void k_plane_bwd(PlaneGeom g, PlaneDim 
     if (use_done && sc->done)
         return;
     const int tid = threadIdx.x;
-    const int x = xcd_remap(blockIdx.x, gridDim.x);
+    const int item = xcd_remap(blockIdx.x, gridDim.x);
+    const int c = item / g.K0, x = item - c * g.K0;
+    const RowChunk rc(g, c);
+    const int nrows = rc.yb - rc.ya + 4, npl = (nrows + 1) / 2;
     C* pl = reinterpret_cast<C*>(pl_smem);
-    C* tw_y = pl + g.P * g.S;
-    C* tw_z = tw_y + g.K1;
-    for (int i = tid; i < g.K1; i += kPlThreads)
-        tw_y[i] = roots_y[i];
+    C* tw_z = pl + (g.Pc + 2) * g.S;
     for (int i = tid; i < g.K2; i += kPlThreads)
         tw_z[i] = roots_z[i];
-    const C* in = gc + (size_t)x * g.K1 * g.kh;
     const SmallDiv dkh(g.kh);
-    for (int i = tid; i < g.K1 * g.kh; i += kPlThreads) {
-        const int ky = dkh.quot(i), kz = i - ky * g.kh;
-        pl[(ky >> 1) * g.S + (ky & 1) * g.kh + kz] = in[i];
+    for (int i = tid; i < nrows * g.kh; i += kPlThreads) {
+        const int r = dkh.quot(i), k = i - r * g.kh;
+        int gy = rc.ya - 4 + r;
+        gy += gy < 0 ? g.K1 : 0;
+        pl[(r >> 1) * g.S + (r & 1) * g.kh + k] = gc[((size_t)x * g.K1 + gy) * g.kh + k];
     }
-    if (g.K1 & 1)  // odd K1: the last pair has no second row
-        for (int kz = tid; kz < g.kh; kz += kPlThreads)
-            pl[(g.P - 1) * g.S + g.kh + kz] = C{(R)0, (R)0};
+    if (nrows & 1)  // the last line holds one row only
+        for (int k = tid; k < g.kh; k += kPlThreads)
+            pl[(npl - 1) * g.S + g.kh + k] = C{(R)0, (R)0};
     __syncthreads();
-    fft_lines<+1>(pl, g.kh, dy, tw_y, LineMap{1, g.S, g.kh});
-    // rebuild the full z spectrum of every pair: Z[k] = A[k] + i B[k] with the Hermitian
-    // extension A[k] = conj A[K2 - k] for k >= kh (imaginary parts of the real terms k = 0 and
-    // k = K2/2 dropped, as a real inverse transform does)
     {
         const int lpr = max(1, kPlThreads * kPlSplit / g.K2);
         const SmallDiv dk2(g.K2);
-        for (int p0 = 0; p0 < g.P; p0 += lpr) {
-            const int cnt = min(lpr, g.P - p0) * g.K2;
+        for (int p0 = 0; p0 < npl; p0 += lpr) {
+            const int cnt = min(lpr, npl - p0) * g.K2;
             C zv[kPlSplit];
 #pragma unroll
             for (int m = 0; m < kPlSplit; ++m) {
@@ -549,33 +617,34 @@ __global__ __launch_bounds__(kPlThreads) void k_plane_bwd(PlaneGeom g, PlaneDim 
             __syncthreads();
         }
     }
-    fft_lines<+1>(pl, g.P, dz, tw_z, LineMap{g.S, 2, 1});
-    // potential psi(y, z) = component (y mod 2) of pl[(y div 2) S + z]
+    fft_lines<+1>(pl, npl, dz, tw_z, LineMap{g.S, 2, 1});
+    // potential of local row r (global row ya - 4 + r), point z: component r mod 2 of
+    // pl[(r div 2) S + z]
     const R* psi = reinterpret_cast<const R*>(pl_smem);
-    PlaneAtoms pa;
-    pa.init(xb_start, x, g.K0);
-    for (int i = tid; i < pa.pre[5]; i += kPlThreads) {
-        int t;
-        const int e = pa.entry(i, t);
-        const int4 rec = xb_rec[e];
-        const R4 w = xb_w[e];
-        R x0[5], x1[5], y0[5], y1[5], z0[5], z1[5], dum[5];
-        spline5<R, false>(w.x, x0, x1, dum);
-        spline5<R, false>(w.y, y0, y1, dum);
-        spline5<R, false>(w.z, z0, z1, dum);
-        int zi[5];
+    BinRanges<5> br;
+    br.pre[0] = 0;
 #pragma unroll
-        for (int tz = 0; tz < 5; ++tz) {
-            int zz = rec.w - tz;
-            zz += zz < 0 ? g.K2 : 0;
-            zi[tz] = 2 * zz;
-        }
+    for (int t = 0; t < 5; ++t) {
+        int bx = x + t;
+        bx -= bx >= g.K0 ? g.K0 : 0;
+        const int* st = xy_start + (size_t)bx * g.K1;
+        br.lo[t] = st[rc.ya];
+        br.tq[t] = t;
+        br.pre[t + 1] = br.pre[t] + st[rc.yb] - br.lo[t];
+    }
+    const int yorg = rc.ya - 4;
+    for (int i = tid; i < br.total(); i += kPlThreads) {
+        int t;
+        const int e = br.entry(i, t);
+        const int4 rec = xb_rec[e];
+        R x0[5], x1[5], y0[5], y1[5], z0[5], z1[5];
+        int zi[5];
+        entry_splines<R>(xb_w[e], rec.w, g.K2, x0, x1, y0, y1, z0, z1, zi);
         R ax = 0, ay = 0, az = 0;
 #pragma unroll
         for (int ty = 0; ty < 5; ++ty) {
-            int yy = rec.z - ty;
-            yy += yy < 0 ? g.K1 : 0;
-            const R* row = psi + 2 * (yy >> 1) * g.S + (yy & 1);
+            const int r = rec.z - ty - yorg;   // in [0, nrows): fy lies in [ya, yb)
+            const R* row = psi + 2 * (r >> 1) * g.S + (r & 1);
             R s0 = 0, s1 = 0;
 #pragma unroll
             for (int tz = 0; tz < 5; ++tz) {
@@ -634,7 +703,22 @@ __global__ __launch_bounds__(256) void k_plane_combine(int npad, double3 kl, con
                 out[3 * (size_t)s + a] = e[a];
         } else if (perm[s] >= 0) {
             double er[3] = {eipart[3 * (size_t)s], eipart[3 * (size_t)s + 1], eipart[3 * (size_t)s + 2]};
-            for (int k = rev_ptr[s]; k < rev_ptr[s + 1]; ++k) {
+            const int k1 = rev_ptr[s + 1];
+            int k = rev_ptr[s];
+            // four independent loads in flight, added in index order
+            for (; k + 4 <= k1; k += 4) {
+                R4 j[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    j[u] = jbuf[rev_idx[k + u]];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    er[0] += (double)j[u].x;
+                    er[1] += (double)j[u].y;
+                    er[2] += (double)j[u].z;
+                }
+            }
+            for (; k < k1; ++k) {
                 const R4 j = jbuf[rev_idx[k]];
                 er[0] += (double)j.x;
                 er[1] += (double)j.y;
@@ -661,62 +745,35 @@ __global__ __launch_bounds__(256) void k_plane_combine(int npad, double3 kl, con
 }
 
 // ------------------------------------------------------------------------------------------
-// per configuration: atoms in x-bins of their base line, with their spline arguments
+// per configuration: atoms binned by the (x, y) lines of their base point, with their spline
+// arguments; the order inside a bin is arbitrary (no result depends on it)
 // ------------------------------------------------------------------------------------------
-// Per-workgroup histogram in LDS, then one global atomic per nonempty bin (the bins are few:
-// global atomics per atom would all land on K0 addresses).
-constexpr int kXbinMax = 2048;
-
-__global__ __launch_bounds__(256) void k_xbin_count(int npad, int K0, const int* __restrict__ perm,
-                                                    const int4* __restrict__ sp_base, int* __restrict__ count)
+__global__ void k_xybin_count(int npad, int K1, const int* __restrict__ perm, const int4* __restrict__ sp_base,
+                              int* __restrict__ count)
 {
-    __shared__ int h[kXbinMax];
-    for (int b = threadIdx.x; b < K0; b += 256)
-        h[b] = 0;
-    __syncthreads();
-    const int s = blockIdx.x * 256 + threadIdx.x;
-    if (s < npad && perm[s] >= 0)
-        atomicAdd(&h[sp_base[s].x], 1);
-    __syncthreads();
-    for (int b = threadIdx.x; b < K0; b += 256)
-        if (h[b])
-            atomicAdd(&count[b], h[b]);
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= npad || perm[s] < 0)
+        return;
+    const int4 b = sp_base[s];
+    atomicAdd(&count[b.x * K1 + b.y], 1);
 }
 
-// Entry of each atom: its workgroup's block of the bin (one global atomic per bin) plus its rank
-// among the workgroup's atoms of that bin (LDS atomic).  The order inside a bin is arbitrary;
-// no result depends on it.
 template <typename R>
-__global__ __launch_bounds__(256) void k_xbin_fill(int npad, const int* __restrict__ perm,
-                                                   const double4* __restrict__ pos_s, double3 kl, int3 K,
-                                                   const int* __restrict__ start, int* __restrict__ cursor,
-                                                   int4* __restrict__ rec, typename PlT<R>::R4* __restrict__ wout)
+__global__ void k_xybin_fill(int npad, const int* __restrict__ perm, const double4* __restrict__ pos_s, double3 kl,
+                             int3 K, const int* __restrict__ start, int* __restrict__ cursor,
+                             int4* __restrict__ rec, typename PlT<R>::R4* __restrict__ wout)
 {
-    __shared__ int h[kXbinMax];
-    for (int b = threadIdx.x; b < K.x; b += 256)
-        h[b] = 0;
-    __syncthreads();
-    const int s = blockIdx.x * 256 + threadIdx.x;
-    const bool real = s < npad && perm[s] >= 0;
-    int f[3] = {0, 0, 0}, rank = 0;
-    double u[3] = {0.0, 0.0, 0.0};
-    if (real) {
-        const double4 p = pos_s[s];
-        grid_coord(p.x, kl.x, K.x, f[0], u[0]);
-        grid_coord(p.y, kl.y, K.y, f[1], u[1]);
-        grid_coord(p.z, kl.z, K.z, f[2], u[2]);
-        rank = atomicAdd(&h[f[0]], 1);
-    }
-    __syncthreads();
-    for (int b = threadIdx.x; b < K.x; b += 256) {
-        const int n = h[b];
-        if (n)
-            h[b] = start[b] + atomicAdd(&cursor[b], n);
-    }
-    __syncthreads();
-    if (!real)
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= npad || perm[s] < 0)
         return;
-    const int e = h[f[0]] + rank;
+    const double4 p = pos_s[s];
+    int f[3];
+    double u[3];
+    grid_coord(p.x, kl.x, K.x, f[0], u[0]);
+    grid_coord(p.y, kl.y, K.y, f[1], u[1]);
+    grid_coord(p.z, kl.z, K.z, f[2], u[2]);
+    const int b = f[0] * K.y + f[1];
+    const int e = start[b] + atomicAdd(&cursor[b], 1);
     rec[e] = make_int4(s, f[0], f[1], f[2]);
     wout[e] = typename PlT<R>::R4{(R)u[0], (R)u[1], (R)u[2], (R)0};
 }
@@ -736,7 +793,9 @@ __global__ void k_plane_roots(int n, typename PlT<R>::C* __restrict__ out)
 // host side
 // ------------------------------------------------------------------------------------------
 static inline int nblk(size_t n, int b) { return (int)((n + b - 1) / b); }
+static inline int cdiv(int a, int b) { return (a + b - 1) / b; }
 
+// radices 6, 4, 3, 5, 7, 2 in that order; every stage must fit one round of butterflies
 static bool plane_factor(int n, PlaneDim& d)
 {
     d.n = n;
@@ -746,11 +805,17 @@ static bool plane_factor(int n, PlaneDim& d)
         while (m % r == 0) {
             if (d.nr >= 12)
                 return false;
+            if (n / r > kPlThreads * kPlMaxB)
+                return false;
             d.rad[d.nr++] = r;
             m /= r;
         }
-    return m == 1 && n >= 2 && n <= 2 * kPlThreads * kPlMaxB;
+    return m == 1 && n >= 2;
 }
+
+static size_t lds_spread(const PlaneGeom& g, size_t cs) { return 16 * (size_t)g.Pc * g.S + cs * g.K2; }
+static size_t lds_gather(const PlaneGeom& g, size_t cs) { return cs * ((size_t)(g.Pc + 2) * g.S + g.K2); }
+static size_t lds_lines(int N, int kc, size_t cs) { return cs * ((size_t)N * kc + N); }
 
 static PlaneGeom plane_geom(const amoeba_ctx* c)
 {
@@ -758,19 +823,28 @@ static PlaneGeom plane_geom(const amoeba_ctx* c)
     g.K0 = c->K[0];
     g.K1 = c->K[1];
     g.K2 = c->K[2];
-    g.P = (g.K1 + 1) / 2;
     g.kh = g.K2 / 2 + 1;
     g.S = 2 * g.kh;
+    g.P = (g.K1 + 1) / 2;
+    const size_t cs = c->mixed ? sizeof(float2) : sizeof(double2);
+    // row chunks: about kPlTargetWG workgroups, within the LDS and conversion limits
+    g.nyc = std::min(g.P, std::max(1, cdiv(kPlTargetWG, g.K0)));
+    g.Pc = cdiv(g.P, g.nyc);
+    while (g.Pc > 1 && (lds_spread(g, cs) > kPlLdsMax || lds_gather(g, cs) > kPlLdsMax ||
+                        2 * g.Pc * g.S > kPlThreads * kPlConv))
+        g.Pc = cdiv(g.Pc, 2);
+    g.nyc = cdiv(g.P, g.Pc);
+    // column chunks likewise
+    g.nkc = std::min(g.kh, std::max(1, cdiv(kPlTargetWG, std::min(g.K0, g.K1))));
+    g.kc = cdiv(g.kh, g.nkc);
+    while (g.kc > 1 && (lds_lines(g.K0, g.kc, cs) > kPlLdsMax || lds_lines(g.K1, g.kc, cs) > kPlLdsMax))
+        g.kc = cdiv(g.kc, 2);
+    g.nkc = cdiv(g.kh, g.kc);
     g.klx = c->K[0] / c->prm.box[0];
     g.kly = c->K[1] / c->prm.box[1];
     g.klz = c->K[2] / c->prm.box[2];
     return g;
 }
-
-// LDS bytes of the three plane kernels
-static size_t lds_fwd(const PlaneGeom& g, size_t cs) { return 16 * (size_t)g.P * g.S + cs * (g.K1 + g.K2); }
-static size_t lds_bwd(const PlaneGeom& g, size_t cs) { return cs * ((size_t)g.P * g.S + g.K1 + g.K2); }
-static size_t lds_x(const PlaneGeom& g, size_t cs, int cw) { return cs * ((size_t)g.K0 * cw + g.K0); }
 
 bool plane_eligible(const amoeba_ctx* c)
 {
@@ -780,35 +854,22 @@ bool plane_eligible(const amoeba_ctx* c)
             return false;
     const PlaneGeom g = plane_geom(c);
     const size_t cs = c->mixed ? sizeof(float2) : sizeof(double2);
-    return lds_fwd(g, cs) <= kPlLdsMax && lds_bwd(g, cs) <= kPlLdsMax && lds_x(g, cs, g.kh) <= kPlLdsMax &&
-           2 * (size_t)g.P * g.S <= (size_t)kPlThreads * kPlConv && g.kh <= kPlThreads * kPlSplit &&
-           g.K2 <= kPlThreads * kPlSplit;
-}
-
-// Allow the plane kernels more than the default dynamic LDS; false if the runtime refuses.
-template <typename R> static bool set_lds_limits()
-{
-    const int lim = (int)kPlLdsMax;
-    const bool ok = hipFuncSetAttribute((const void*)k_plane_fwd<R, std::is_same<R, float>::value>,
-                                        hipFuncAttributeMaxDynamicSharedMemorySize, lim) == hipSuccess &&
-                    hipFuncSetAttribute((const void*)k_plane_xconv<R>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                        lim) == hipSuccess &&
-                    hipFuncSetAttribute((const void*)k_plane_bwd<R>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                        lim) == hipSuccess;
-    if (!ok)
-        (void)hipGetLastError();
-    return ok;
+    return lds_spread(g, cs) <= kPlLdsMax && lds_gather(g, cs) <= kPlLdsMax &&
+           lds_lines(g.K0, g.kc, cs) <= kPlLdsMax && lds_lines(g.K1, g.kc, cs) <= kPlLdsMax &&
+           2 * g.Pc * g.S <= kPlThreads * kPlConv && g.kh <= kPlThreads * kPlSplit &&
+           g.K2 <= kPlThreads * kPlSplit && (size_t)g.K0 * g.K1 <= 65536;
 }
 
 int plane_setup(amoeba_ctx* c)
 {
-    c->plane_ok = plane_eligible(c) && (c->mixed ? set_lds_limits<float>() : set_lds_limits<double>());
+    c->plane_ok = plane_eligible(c);
     if (!c->plane_ok)
         return AMOEBA_OK;
     const size_t rs = c->mixed ? sizeof(float) : sizeof(double);
+    const int nb2 = c->K[0] * c->K[1];
     int rc;
-    if ((rc = ctx_alloc(c, (void**)&c->xb_start, sizeof(int) * (c->K[0] + 1))) ||
-        (rc = ctx_alloc(c, (void**)&c->xb_count, sizeof(int) * (c->K[0] + 1))) ||
+    if ((rc = ctx_alloc(c, (void**)&c->xb_start, sizeof(int) * (nb2 + 1))) ||
+        (rc = ctx_alloc(c, (void**)&c->xb_count, sizeof(int) * (nb2 + 1))) ||
         (rc = ctx_alloc(c, (void**)&c->xb_rec, sizeof(int4) * c->npad)) ||
         (rc = ctx_alloc(c, &c->xb_w, 4 * rs * c->npad)) ||
         (rc = ctx_alloc(c, &c->rec_part, 4 * rs * 5 * (size_t)c->npad)))
@@ -826,28 +887,32 @@ int plane_setup(amoeba_ctx* c)
     return AMOEBA_OK;
 }
 
-void plane_bin_atoms(amoeba_ctx* c)
+int plane_bin_atoms(amoeba_ctx* c)
 {
     if (!c->plane_ok)
-        return;
+        return AMOEBA_OK;
     hipStream_t st = c->stream;
-    const int K0 = c->K[0];
+    const int nb2 = c->K[0] * c->K[1];
     int3 K = make_int3(c->K[0], c->K[1], c->K[2]);
     double3 kl = make_double3(c->K[0] / c->prm.box[0], c->K[1] / c->prm.box[1], c->K[2] / c->prm.box[2]);
-    hipMemsetAsync(c->xb_count, 0, sizeof(int) * (K0 + 1), st);
-    hipLaunchKernelGGL(k_xbin_count, dim3(nblk(c->npad, 256)), dim3(256), 0, st, c->npad, K0, c->perm,
+    hipMemsetAsync(c->xb_count, 0, sizeof(int) * (nb2 + 1), st);
+    hipLaunchKernelGGL(k_xybin_count, dim3(nblk(c->npad, 256)), dim3(256), 0, st, c->npad, c->K[1], c->perm,
                        c->sp_base, c->xb_count);
-    pme_scan_excl(c, K0, c->xb_count, c->xb_start);
-    hipMemsetAsync(c->xb_count, 0, sizeof(int) * (K0 + 1), st);
+    int rc = device_scan(c, nb2, c->xb_count, c->xb_start);
+    if (rc)
+        return rc;
+    hipMemsetAsync(c->xb_count, 0, sizeof(int) * (nb2 + 1), st);
     if (c->mixed)
-        hipLaunchKernelGGL(k_xbin_fill<float>, dim3(nblk(c->npad, 256)), dim3(256), 0, st, c->npad, c->perm,
+        hipLaunchKernelGGL(k_xybin_fill<float>, dim3(nblk(c->npad, 256)), dim3(256), 0, st, c->npad, c->perm,
                            c->pos_s, kl, K, c->xb_start, c->xb_count, c->xb_rec, (float4*)c->xb_w);
     else
-        hipLaunchKernelGGL(k_xbin_fill<double>, dim3(nblk(c->npad, 256)), dim3(256), 0, st, c->npad, c->perm,
+        hipLaunchKernelGGL(k_xybin_fill<double>, dim3(nblk(c->npad, 256)), dim3(256), 0, st, c->npad, c->perm,
                            c->pos_s, kl, K, c->xb_start, c->xb_count, c->xb_rec, (double4*)c->xb_w);
+    return AMOEBA_OK;
 }
 
-template <typename R> static void plane_field_t(amoeba_ctx* c, bool use_done)
+// part 1: the spread pass; part 2: the transforms and the interpolation; 3: both
+template <typename R> static void plane_field_t(amoeba_ctx* c, bool use_done, int parts)
 {
     using C = typename PlT<R>::C;
     using R4 = typename PlT<R>::R4;
@@ -859,33 +924,39 @@ template <typename R> static void plane_field_t(amoeba_ctx* c, bool use_done)
     hipStream_t st = c->stream;
     const int ud = use_done ? 1 : 0;
     const C* const* roots = (const C* const*)c->pl_roots;
-    {
+    C* gc = (C*)c->grid_c;
+    const dim3 nt(kPlThreads);
+    if (parts & 1) {
         StageTimer tm(c, AMOEBA_T_SPREAD);
         const R4* src = c->mixed ? (const R4*)c->pv_f : (const R4*)c->pv_d;
-        hipLaunchKernelGGL((k_plane_fwd<R, std::is_same<R, float>::value>), dim3(g.K0), dim3(kPlThreads),
-                           lds_fwd(g, cs), st, g, d[1], d[2], c->xb_start, c->xb_rec, (const R4*)c->xb_w, src,
-                           roots[1], roots[2], (C*)c->grid_c, c->sc, ud);
+        hipLaunchKernelGGL((k_pme_spread_z<R, std::is_same<R, float>::value>), dim3(g.K0 * g.nyc), nt,
+                           lds_spread(g, cs), st, g, d[2], c->xb_start, c->xb_rec, (const R4*)c->xb_w, src, roots[2],
+                           gc, c->sc, ud);
     }
+    if (!(parts & 2))
+        return;
     {
         StageTimer tm(c, AMOEBA_T_FFT);
-        const int cw = g.kh, nch = 1;
-        hipLaunchKernelGGL(k_plane_xconv<R>, dim3(g.K1 * nch), dim3(kPlThreads), lds_x(g, cs, cw), st, g, d[0], cw,
-                           nch, (C*)c->grid_c, (const R*)c->theta, roots[0], c->sc, ud);
+        hipLaunchKernelGGL((k_pme_ylines<R, -1>), dim3(g.K0 * g.nkc), nt, lds_lines(g.K1, g.kc, cs), st, g, d[1], gc,
+                           roots[1], c->sc, ud);
+        hipLaunchKernelGGL(k_pme_xconv<R>, dim3(g.K1 * g.nkc), nt, lds_lines(g.K0, g.kc, cs), st, g, d[0], gc,
+                           (const R*)c->theta, roots[0], c->sc, ud);
+        hipLaunchKernelGGL((k_pme_ylines<R, 1>), dim3(g.K0 * g.nkc), nt, lds_lines(g.K1, g.kc, cs), st, g, d[1], gc,
+                           roots[1], c->sc, ud);
     }
     {
         StageTimer tm(c, AMOEBA_T_GATHER);
-        hipLaunchKernelGGL(k_plane_bwd<R>, dim3(g.K0), dim3(kPlThreads), lds_bwd(g, cs), st, g, d[1], d[2],
-                           (const C*)c->grid_c, c->xb_start, c->xb_rec, (const R4*)c->xb_w, roots[1], roots[2],
-                           (R4*)c->rec_part, c->sc, ud);
+        hipLaunchKernelGGL(k_pme_z_gather<R>, dim3(g.K0 * g.nyc), nt, lds_gather(g, cs), st, g, d[2], (const C*)gc,
+                           c->xb_start, c->xb_rec, (const R4*)c->xb_w, roots[2], (R4*)c->rec_part, c->sc, ud);
     }
 }
 
-void plane_dipole_field(amoeba_ctx* c, bool use_done)
+void plane_dipole_field(amoeba_ctx* c, bool use_done, int parts)
 {
     if (c->mixed)
-        plane_field_t<float>(c, use_done);
+        plane_field_t<float>(c, use_done, parts);
     else
-        plane_field_t<double>(c, use_done);
+        plane_field_t<double>(c, use_done, parts);
 }
 
 void plane_gather(amoeba_ctx* c, double* out)

@@ -908,13 +908,13 @@ static int convolve_and_back(amoeba_ctx* c, bool use_done)
     return AMOEBA_OK;
 }
 
-static bool use_planes(const amoeba_ctx* c) { return c->plane_ok && c->pme_path != AMOEBA_PME_BRICKS; }
+bool pme_use_planes(const amoeba_ctx* c) { return c->plane_ok && c->pme_path != AMOEBA_PME_BRICKS; }
 
 int pme_dipole_field(amoeba_ctx* c, bool use_done)
 {
-    c->rec_plane = use_planes(c);
+    c->rec_plane = pme_use_planes(c);
     if (c->rec_plane) {
-        plane_dipole_field(c, use_done);
+        plane_dipole_field(c, use_done, 3);
         return AMOEBA_OK;
     }
     int3 K = make_int3(c->K[0], c->K[1], c->K[2]);

@@ -526,27 +526,29 @@ __global__ void k_real_reduce(int npad, const double* __restrict__ eipart, const
     ereal[3 * (size_t)s + 2] = e2;
 }
 
-template <bool MI> static void mutual_tiles(amoeba_ctx* c, bool use_done)
+template <bool MI> static void mutual_tiles(amoeba_ctx* c, bool use_done, hipStream_t st)
 {
     if (c->ntiles == 0)
         return;
     StageTimer tm(c, AMOEBA_T_REAL);
     if (c->mixed)
-        hipLaunchKernelGGL((k_block_tiles<float, true, DipoleKind<float>, MI>), dim3(c->nb), dim3(256), 0, c->stream,
+        hipLaunchKernelGGL((k_block_tiles<float, true, DipoleKind<float>, MI>), dim3(c->nb), dim3(256), 0, st,
                            c->nb, c->blk_tile0, c->tile_j, c->tile_mask, c->jrel_f, c->off_f, c->par_f, c->pv_f,
                            make_ewald<float>(c), c->eipart, (float*)c->jbuf, c->sc, (int)use_done);
     else
-        hipLaunchKernelGGL((k_block_tiles<double, false, DipoleKind<double>, MI>), dim3(c->nb), dim3(256), 0, c->stream,
+        hipLaunchKernelGGL((k_block_tiles<double, false, DipoleKind<double>, MI>), dim3(c->nb), dim3(256), 0, st,
                            c->nb, c->blk_tile0, c->tile_j, c->tile_mask, c->jrel_d, c->off_d, c->par_d, c->pv_d,
                            make_ewald<double>(c), c->eipart, (double*)c->jbuf, c->sc, (int)use_done);
 }
 
-void launch_mutual_tiles(amoeba_ctx* c, bool use_done)
+void launch_mutual_tiles(amoeba_ctx* c, bool use_done, hipStream_t st)
 {
+    if (!st)
+        st = c->stream;
     if (c->skip_mimg)
-        mutual_tiles<false>(c, use_done);
+        mutual_tiles<false>(c, use_done, st);
     else
-        mutual_tiles<true>(c, use_done);
+        mutual_tiles<true>(c, use_done, st);
 }
 
 void launch_real_reduce(amoeba_ctx* c, double* ereal)
