@@ -5,13 +5,13 @@
 //   1. atoms get a key along a column-serpentine cell order: the box is cut into ny x nz
 //      columns along x whose cross-section holds about one block's worth of atoms per block
 //      length, odd columns / odd z-slabs run backwards, so consecutive atoms stay spatially
-//      adjacent across column ends; keys (with the atom index as tie-break) are sorted by a
-//      bitonic network, giving a deterministic order;
+//      adjacent across column ends; keys (with the atom index as tie-break, so all distinct)
+//      are radix-sorted, giving a deterministic order;
 //   2. the sorted order is cut into 64-atom blocks (one block = one wave64); the last block is
 //      padded with phantom atoms;
-//   3. every block gets a bounding box; block pairs J > I whose boxes come within
-//      cutoff + buffer are candidates (the adjacency of the paper's block matrix, symmetric
-//      half kept);
+//   3. every block gets a bounding box; block pairs whose boxes come within cutoff + buffer
+//      are candidates (the adjacency of the paper's block matrix; each unordered pair once,
+//      block I taking J = I + 1 .. I + nb/2 circularly, so all blocks scan equally many);
 //   4. list filtering: the atoms of candidate blocks that lie within cutoff + buffer of ANY
 //      atom of block I are kept, in (J, slot) order, and packed into 64-atom tiles; each block
 //      also owns its diagonal tile (I, I).
@@ -21,6 +21,8 @@
 //      bitmasks (bit k of row i: |r_i - r_jk| < rc) and the j positions relative to the
 //      i-block origin, computed in FP64.
 #include <cmath>
+
+#include <rocprim/device/device_radix_sort.hpp>
 
 #include "common.h"
 
@@ -34,80 +36,33 @@ __device__ __forceinline__ double wrap_box(double x, double L)
     return (y >= L) ? y - L : y;
 }
 
-__global__ void k_sort_keys(int n, int npow2, const double* __restrict__ pos, double3 box, int ny,
-                            int nz, unsigned long long* __restrict__ keys)
+// Sort key of atom a: column (cz, cy) in a serpentine order, then x within the column (also
+// serpentine), then the atom index; packed as col | xq (16 bits) | a (ib bits) so that a radix
+// sort over the low ib + 16 + colbits bits orders it.  The largest column value is kept for
+// non-finite positions, which sort last (the gather check reports them).
+__global__ void k_sort_keys(int n, const double* __restrict__ pos, double3 box, int ny, int nz, int ib,
+                            int colbits, unsigned long long* __restrict__ keys)
 {
     int a = blockIdx.x * blockDim.x + threadIdx.x;
-    if (a >= npow2)
+    if (a >= n)
         return;
-    if (a >= n) {
-        keys[a] = ~0ull;
-        return;
-    }
     double x = wrap_box(pos[3 * a], box.x), y = wrap_box(pos[3 * a + 1], box.y),
            z = wrap_box(pos[3 * a + 2], box.z);
-    if (!(x == x) || !(y == y) || !(z == z)) {  // NaN keys sort last; caught by the gather check
-        keys[a] = (~0ull << 32) | (unsigned)a;
-        return;
+    unsigned long long col, xq;
+    if (!(x == x) || !(y == y) || !(z == z)) {
+        col = (1ull << colbits) - 1ull;
+        xq = 65535ull;
+    } else {
+        int cy = min(ny - 1, (int)(y / box.y * ny));
+        int cz = min(nz - 1, (int)(z / box.z * nz));
+        int cys = (cz & 1) ? ny - 1 - cy : cy;
+        col = (unsigned long long)(cz * ny + cys);
+        unsigned q = min(65535u, (unsigned)(x / box.x * 65536.0));
+        if (col & 1ull)
+            q = 65535u - q;
+        xq = q;
     }
-    int cy = min(ny - 1, (int)(y / box.y * ny));
-    int cz = min(nz - 1, (int)(z / box.z * nz));
-    int cys = (cz & 1) ? ny - 1 - cy : cy;
-    unsigned col = (unsigned)(cz * ny + cys);
-    unsigned xq = min(65535u, (unsigned)(x / box.x * 65536.0));
-    if (col & 1u)
-        xq = 65535u - xq;
-    keys[a] = ((unsigned long long)((col << 16) | xq) << 32) | (unsigned)a;
-}
-
-__global__ void k_bitonic(unsigned long long* __restrict__ keys, int npow2, int j, int k)
-{
-    unsigned i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= (unsigned)npow2)
-        return;
-    unsigned ixj = i ^ (unsigned)j;
-    if (ixj > i) {
-        unsigned long long a = keys[i], b = keys[ixj];
-        bool up = (i & (unsigned)k) == 0;
-        if ((a > b) == up) {
-            keys[i] = b;
-            keys[ixj] = a;
-        }
-    }
-}
-
-// Bitonic stages whose partner distance j stays inside a 1024-element block, done in LDS:
-// for k = k_lo .. k_hi (doubling) and j = min(k/2, j_hi) .. 1.  Direction from the global index.
-__global__ __launch_bounds__(512) void k_bitonic_lds(unsigned long long* __restrict__ keys, int npow2, int k_lo,
-                                                     int k_hi, int j_hi)
-{
-    __shared__ unsigned long long s[1024];
-    const int bs = min(npow2, 1024), half = bs >> 1;
-    const unsigned base = blockIdx.x * bs;
-    const int t = threadIdx.x;
-    if (t < half) {
-        s[t] = keys[base + t];
-        s[t + half] = keys[base + t + half];
-    }
-    __syncthreads();
-    for (int k = k_lo; k <= k_hi; k <<= 1)
-        for (int j = min(k >> 1, j_hi); j > 0; j >>= 1) {
-            if (t < half) {
-                unsigned i = 2u * t - (t & (j - 1));
-                unsigned ixj = i + j;
-                bool up = ((base + i) & (unsigned)k) == 0;
-                unsigned long long a = s[i], b = s[ixj];
-                if ((a > b) == up) {
-                    s[i] = b;
-                    s[ixj] = a;
-                }
-            }
-            __syncthreads();
-        }
-    if (t < half) {
-        keys[base + t] = s[t];
-        keys[base + t + half] = s[t + half];
-    }
+    keys[a] = (col << (16 + ib)) | (xq << ib) | (unsigned long long)a;
 }
 
 // Three-phase exclusive scan for long arrays: block sums (1024 per workgroup), scan of the
@@ -162,14 +117,15 @@ __global__ __launch_bounds__(256) void k_scan_apply(int n, const int* __restrict
         out[n] = run;
 }
 
-__global__ void k_perm(int n, int npad, const unsigned long long* __restrict__ keys, int* __restrict__ perm,
+
+__global__ void k_perm(int n, int npad, const unsigned long long* __restrict__ keys, int ib, int* __restrict__ perm,
                        int* __restrict__ slot)
 {
     int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= npad)
         return;
     if (s < n) {
-        int a = (int)(keys[s] & 0xffffffffull);
+        int a = (int)(keys[s] & ((1ull << ib) - 1ull));
         perm[s] = a;
         slot[a] = s;
     } else {
@@ -371,43 +327,113 @@ __device__ __forceinline__ int wave_excl_scan_i(int x, int lane, int& total)
     return incl - x;
 }
 
-// List filtering: for block I, the atoms of blocks J > I within rcb of any atom of I, in (J,
-// slot) order.  Four waves per block: wave 0 finds the candidate blocks of a chunk of 64 block
-// ids by their bounding boxes, the waves test the candidates' atoms against the block's atoms
-// (FP32 distances with a 1e-3 A margin: the filter only has to keep a superset, the masks of
-// every configuration decide at rc in FP64), and the kept atoms are written at offsets from an
-// ordered scan, so the list does not depend on scheduling.
+// Whether j (offset from the i-block centre, inside rcb of the block's box) lies within rf2 of an
+// atom of the block.  MI: apply the minimum image to every pair offset and test all atoms.
+// Without it the offsets are taken as they are, which is exact when twice the largest block
+// half-extent plus rcb stays below half the box edge (then no offset can exceed half the box);
+// the block's atoms (spatially sorted) then form eight groups of eight with their own boxes
+// (s_gc centre, s_gh half-extent, w < 0 for a group without real atoms), and a group is tested
+// atom by atom only when j comes within reach of its box (a box contains its atoms, so a group
+// it rules out holds no atom within reach).
+template <bool MI>
+__device__ __forceinline__ bool near_block(const float4* s_i, const float4* s_gc, const float4* s_gh, float jx,
+                                           float jy, float jz, float rf2, float Lx, float Ly, float Lz, float Lix,
+                                           float Liy, float Liz)
+{
+    bool keep = false;
+    for (int g = 0; g < 8 && !keep; ++g) {
+        if (!MI) {
+            const float4 c = s_gc[g], h = s_gh[g];
+            const float ex = fmaxf(fabsf(c.x - jx) - h.x, 0.0f);
+            const float ey = fmaxf(fabsf(c.y - jy) - h.y, 0.0f);
+            const float ez = fmaxf(fabsf(c.z - jz) - h.z, 0.0f);
+            if (h.w < 0.0f || ex * ex + ey * ey + ez * ez >= rf2)
+                continue;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const float4 q = s_i[8 * g + u];
+            float dx = q.x - jx, dy = q.y - jy, dz = q.z - jz;
+            if (MI) {
+                dx -= Lx * rintf(dx * Lix);
+                dy -= Ly * rintf(dy * Liy);
+                dz -= Lz * rintf(dz * Liz);
+            }
+            keep = keep || (q.w != 0.0f && dx * dx + dy * dy + dz * dz < rf2);
+        }
+    }
+    return keep;
+}
+
+// List filtering: for block I, the atoms of the blocks J = I + d (mod nb), d = 1 .. floor(nb/2)
+// (d = nb/2 only for I < nb/2), within rcb of any atom of I, in (d, slot) order.  Every
+// unordered block pair is examined exactly once and every block scans the same number of
+// candidates.  Chunks of 256 candidates: each thread tests one candidate's bounding box, the
+// waves test the candidates' atoms against the block's atoms (FP32 distances with a 1e-3 A
+// margin: the filter only has to keep a superset, the masks of every configuration decide at
+// rc in FP64), and the kept atoms are written at offsets from an ordered scan, so the list
+// does not depend on scheduling.
+constexpr int kFiltChunk = 256;
+
 __global__ __launch_bounds__(256) void k_filter(int nb, const int* __restrict__ perm,
                                                 const double4* __restrict__ pos_s,
                                                 const double4* __restrict__ bc, const double4* __restrict__ bh,
-                                                double3 box, double3 binv, double rcb, int* __restrict__ row_count,
-                                                int* __restrict__ row_j, int* __restrict__ flags)
+                                                const double* __restrict__ ext, double3 box, double3 binv,
+                                                double rcb, int* __restrict__ row_count, int* __restrict__ row_j,
+                                                int* __restrict__ flags)
 {
-    __shared__ float4 s_i[kBlock];                 // i atoms relative to the block centre, w = real atom
-    __shared__ unsigned long long s_keep[kBlock];  // kept atoms of each candidate of the chunk
-    __shared__ int s_cand[kBlock];
-    __shared__ int s_off[kBlock + 1];
-    __shared__ int s_ncand;
+    __shared__ float4 s_i[kBlock];                       // i atoms relative to the block centre, w = real atom
+    __shared__ unsigned long long s_keep[kFiltChunk];    // kept atoms of each candidate of the chunk
+    __shared__ int s_cand[kFiltChunk];
+    __shared__ int s_off[kFiltChunk + 1];
+    __shared__ int s_wn[4], s_wk[4];
+    __shared__ float4 s_gc[8], s_gh[8];                  // boxes of the eight 8-atom groups
     const int I = blockIdx.x, tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
     const double4 ci = bc[I], hi = bh[I];
     if (tid < kBlock) {
         const int si = I * kBlock + tid;
         const double4 pi = pos_s[si];
-        s_i[tid] = make_float4((float)mimg_fp64(pi.x - ci.x, box.x, binv.x), (float)mimg_fp64(pi.y - ci.y, box.y, binv.y),
-                               (float)mimg_fp64(pi.z - ci.z, box.z, binv.z), perm[si] >= 0 ? 1.0f : 0.0f);
+        const bool real = perm[si] >= 0;
+        const float4 q = make_float4((float)mimg_fp64(pi.x - ci.x, box.x, binv.x),
+                                     (float)mimg_fp64(pi.y - ci.y, box.y, binv.y),
+                                     (float)mimg_fp64(pi.z - ci.z, box.z, binv.z), real ? 1.0f : 0.0f);
+        s_i[tid] = q;
+        // group box over the real atoms of lanes 8g .. 8g+7 (xor-shuffles within the group)
+        float mn[3] = {real ? q.x : 3e38f, real ? q.y : 3e38f, real ? q.z : 3e38f};
+        float mx[3] = {real ? q.x : -3e38f, real ? q.y : -3e38f, real ? q.z : -3e38f};
+#pragma unroll
+        for (int off = 1; off < 8; off <<= 1)
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                mn[a] = fminf(mn[a], __shfl_xor(mn[a], off));
+                mx[a] = fmaxf(mx[a], __shfl_xor(mx[a], off));
+            }
+        if ((tid & 7) == 0) {
+            const bool any = mn[0] <= mx[0];
+            // half-extent rounded up by 1e-4 A so the box contains its atoms despite FP32 rounding
+            s_gc[tid >> 3] = make_float4(0.5f * (mn[0] + mx[0]), 0.5f * (mn[1] + mx[1]), 0.5f * (mn[2] + mx[2]), 0.0f);
+            s_gh[tid >> 3] = make_float4(0.5f * (mx[0] - mn[0]) + 1e-4f, 0.5f * (mx[1] - mn[1]) + 1e-4f,
+                                         0.5f * (mx[2] - mn[2]) + 1e-4f, any ? 1.0f : -1.0f);
+        }
     }
     const double rcb2 = rcb * rcb;
     const float rf2 = (float)((rcb + 1e-3) * (rcb + 1e-3));
     const float hxf = (float)hi.x + 1e-3f, hyf = (float)hi.y + 1e-3f, hzf = (float)hi.z + 1e-3f;
     const float Lx = (float)box.x, Ly = (float)box.y, Lz = (float)box.z;
     const float Lix = (float)binv.x, Liy = (float)binv.y, Liz = (float)binv.z;
+    // pair offsets |q - j| <= h_I + (h_I + rcb + margins) <= 2 h_max + rcb
+    const bool mi = !(2.0 * ext[0] + rcb + 0.01 < 0.5 * box.x && 2.0 * ext[1] + rcb + 0.01 < 0.5 * box.y &&
+                      2.0 * ext[2] + rcb + 0.01 < 0.5 * box.z);
+    const int dmax = (nb % 2 == 0 && I < nb / 2) ? nb / 2 : (nb - 1) / 2;
     int count = 0;
-    for (int J0 = I + 1; J0 < nb; J0 += kBlock) {
+    for (int d0 = 1; d0 <= dmax; d0 += kFiltChunk) {
         __syncthreads();
-        if (w == 0) {
-            const int J = J0 + lane;
+        {
+            const int d = d0 + tid;
+            int J = I + d;
+            J -= J >= nb ? nb : 0;
             bool cand = false;
-            if (J < nb) {
+            if (d <= dmax) {
                 const double4 cj = bc[J], hj = bh[J];
                 double dx = fabs(mimg_fp64(ci.x - cj.x, box.x, binv.x)) - hi.x - hj.x;
                 double dy = fabs(mimg_fp64(ci.y - cj.y, box.y, binv.y)) - hi.y - hj.y;
@@ -418,13 +444,15 @@ __global__ __launch_bounds__(256) void k_filter(int nb, const int* __restrict__ 
                 cand = dx * dx + dy * dy + dz * dz < rcb2;
             }
             const unsigned long long cm = __ballot(cand);
-            if (cand)
-                s_cand[__popcll(cm & ((1ull << lane) - 1ull))] = J;
             if (lane == 0)
-                s_ncand = __popcll(cm);
+                s_wn[w] = __popcll(cm);
+            __syncthreads();
+            const int wbase = (w > 0 ? s_wn[0] : 0) + (w > 1 ? s_wn[1] : 0) + (w > 2 ? s_wn[2] : 0);
+            if (cand)
+                s_cand[wbase + __popcll(cm & ((1ull << lane) - 1ull))] = J;
         }
+        const int nc = s_wn[0] + s_wn[1] + s_wn[2] + s_wn[3];
         __syncthreads();
-        const int nc = s_ncand;
         for (int k = w; k < nc; k += 4) {
             const int sj = s_cand[k] * kBlock + lane;
             bool keep = false;
@@ -436,31 +464,27 @@ __global__ __launch_bounds__(256) void k_filter(int nb, const int* __restrict__ 
                 // outside rcb of the block's box: outside rcb of every atom in it
                 const float bx = fmaxf(fabsf(jx) - hxf, 0.0f), by = fmaxf(fabsf(jy) - hyf, 0.0f),
                             bz = fmaxf(fabsf(jz) - hzf, 0.0f);
-                if (bx * bx + by * by + bz * bz < rf2) {
-                    for (int i0 = 0; i0 < kBlock && !keep; i0 += 8) {
-#pragma unroll
-                        for (int u = 0; u < 8; ++u) {
-                            const float4 q = s_i[i0 + u];
-                            float dx = q.x - jx, dy = q.y - jy, dz = q.z - jz;
-                            dx -= Lx * rintf(dx * Lix);
-                            dy -= Ly * rintf(dy * Liy);
-                            dz -= Lz * rintf(dz * Liz);
-                            keep = keep || (q.w != 0.0f && dx * dx + dy * dy + dz * dz < rf2);
-                        }
-                    }
-                }
+                if (bx * bx + by * by + bz * bz < rf2)
+                    keep = mi ? near_block<true>(s_i, s_gc, s_gh, jx, jy, jz, rf2, Lx, Ly, Lz, Lix, Liy, Liz)
+                              : near_block<false>(s_i, s_gc, s_gh, jx, jy, jz, rf2, Lx, Ly, Lz, Lix, Liy, Liz);
             }
             const unsigned long long km = __ballot(keep);
             if (lane == 0)
                 s_keep[k] = km;
         }
         __syncthreads();
-        if (w == 0) {
+        {
+            // ordered exclusive scan of the kept counts (wave w holds candidates 64w .. 64w+63)
+            const int k = tid;
             int tot;
-            const int ex = wave_excl_scan_i(lane < nc ? __popcll(s_keep[lane]) : 0, lane, tot);
-            s_off[lane] = ex;
+            const int ex = wave_excl_scan_i(k < nc ? __popcll(s_keep[k]) : 0, lane, tot);
             if (lane == 0)
-                s_off[kBlock] = tot;
+                s_wk[w] = tot;
+            __syncthreads();
+            const int wbase = (w > 0 ? s_wk[0] : 0) + (w > 1 ? s_wk[1] : 0) + (w > 2 ? s_wk[2] : 0);
+            s_off[k] = wbase + ex;
+            if (tid == 0)
+                s_off[kFiltChunk] = s_wk[0] + s_wk[1] + s_wk[2] + s_wk[3];
         }
         __syncthreads();
         for (int k = w; k < nc; k += 4) {
@@ -471,7 +495,7 @@ __global__ __launch_bounds__(256) void k_filter(int nb, const int* __restrict__ 
                     row_j[(size_t)I * kMaxFiltered + pos] = s_cand[k] * kBlock + lane;
             }
         }
-        count += s_off[kBlock];
+        count += s_off[kFiltChunk];
     }
     if (tid == 0) {
         row_count[I] = min(count, kMaxFiltered);
@@ -682,7 +706,7 @@ int sort_params(amoeba_ctx* c)
     if (c->n_scaled > 0)
         hipLaunchKernelGGL(k_csr_fill, dim3(nblk(c->npad, 256)), dim3(256), 0, st, c->npad, c->perm, c->slot,
                            c->sc_ptr_in, c->sc_j_in, c->sc_s_in, c->sc_ptr, c->sc_j, c->sc_s);
-    return hip_check(c, hipStreamSynchronize(st), "sort_params");
+    return AMOEBA_OK;
 }
 
 void pme_bin_atoms(amoeba_ctx* c);
@@ -715,13 +739,19 @@ int build_blocklist(amoeba_ctx* c, const double* pos)
     double edge = cbrt(kBlock * vol / n);
     int ny = (int)fmin(255.0, fmax(1.0, floor(box.y / edge + 0.5)));
     int nz = (int)fmin(255.0, fmax(1.0, floor(box.z / edge + 0.5)));
-    int npow2 = 1;
-    while (npow2 < n)
-        npow2 <<= 1;
+    auto bits_for = [](long long v) {  // bits of the values 0 .. v-1
+        int b = 1;
+        while ((1ll << b) < v)
+            ++b;
+        return b;
+    };
+    const int ib = bits_for(n), colbits = bits_for((long long)ny * nz) + 1;
+    const unsigned end_bit = (unsigned)(ib + 16 + colbits);
 
     int rc = AMOEBA_OK;
     if (!c->b_keys) {
-        if ((rc = ctx_alloc(c, (void**)&c->b_keys, sizeof(unsigned long long) * npow2)) ||
+        if ((rc = ctx_alloc(c, (void**)&c->b_keys, sizeof(unsigned long long) * n)) ||
+            (rc = ctx_alloc(c, (void**)&c->b_keys2, sizeof(unsigned long long) * n)) ||
             (rc = ctx_alloc(c, (void**)&c->b_bc, sizeof(double4) * nb)) ||
             (rc = ctx_alloc(c, (void**)&c->b_bh, sizeof(double4) * nb)) ||
             (rc = ctx_alloc(c, (void**)&c->b_rowc, sizeof(int) * nb)) ||
@@ -729,26 +759,24 @@ int build_blocklist(amoeba_ctx* c, const double* pos)
             (rc = ctx_alloc(c, (void**)&c->b_tpb, sizeof(int) * (nb + 1))) ||
             (rc = ctx_alloc(c, (void**)&c->b_extent, sizeof(double) * 4)))
             return rc;
-        c->b_npow2 = npow2;
+        size_t tb = 0;
+        if (rocprim::radix_sort_keys(nullptr, tb, c->b_keys, c->b_keys2, n, 0u, end_bit, st) != hipSuccess)
+            return set_error(c, AMOEBA_E_DEVICE, "build_blocklist: radix sort size query failed");
+        if ((rc = ctx_alloc(c, &c->b_sort_tmp, tb)))
+            return rc;
+        c->b_sort_bytes = tb;
     }
     unsigned long long* keys = c->b_keys;
     double4 *bc = c->b_bc, *bh = c->b_bh;
     int *row_count = c->b_rowc, *row_j = c->b_rowj, *tpb = c->b_tpb, *t0 = c->blk_tile0;
     auto fail = [&](int code) { return code; };
-    hipLaunchKernelGGL(k_sort_keys, dim3(nblk(npow2, 256)), dim3(256), 0, st, n, npow2, pos, box, ny, nz, keys);
+    hipLaunchKernelGGL(k_sort_keys, dim3(nblk(n, 256)), dim3(256), 0, st, n, pos, box, ny, nz, ib, colbits, keys);
     {
-        // bitonic network: stages with partner distance < 1024 run in LDS, longer ones in global memory
-        const int bs = npow2 < 1024 ? npow2 : 1024;
-        const int nwg_l = npow2 / bs;
-        if (npow2 >= 2)
-            hipLaunchKernelGGL(k_bitonic_lds, dim3(nwg_l), dim3(512), 0, st, keys, npow2, 2, bs, 512);
-        for (int k = 2 * bs; k <= npow2; k <<= 1) {
-            for (int j = k >> 1; j >= bs; j >>= 1)
-                hipLaunchKernelGGL(k_bitonic, dim3(nblk(npow2, 256)), dim3(256), 0, st, keys, npow2, j, k);
-            hipLaunchKernelGGL(k_bitonic_lds, dim3(nwg_l), dim3(512), 0, st, keys, npow2, k, k, 512);
-        }
+        size_t tb = c->b_sort_bytes;
+        if (rocprim::radix_sort_keys(c->b_sort_tmp, tb, keys, c->b_keys2, n, 0u, end_bit, st) != hipSuccess)
+            return set_error(c, AMOEBA_E_DEVICE, "build_blocklist: radix sort failed");
     }
-    hipLaunchKernelGGL(k_perm, dim3(nblk(npad, 256)), dim3(256), 0, st, n, npad, keys, c->perm, c->slot);
+    hipLaunchKernelGGL(k_perm, dim3(nblk(npad, 256)), dim3(256), 0, st, n, npad, c->b_keys2, ib, c->perm, c->slot);
     if (c->atoms_set && (rc = sort_params(c)) != AMOEBA_OK)
         return fail(rc);
 
@@ -759,7 +787,7 @@ int build_blocklist(amoeba_ctx* c, const double* pos)
     hipLaunchKernelGGL(k_bbox, dim3(nb), dim3(64), 0, st, nb, c->perm, c->pos_s, box, bc, bh);
     hipLaunchKernelGGL(k_extent_max, dim3(1), dim3(256), 0, st, nb, bh, c->b_extent);
     double3 binv = make_double3(1.0 / box.x, 1.0 / box.y, 1.0 / box.z);
-    hipLaunchKernelGGL(k_filter, dim3(nb), dim3(256), 0, st, nb, c->perm, c->pos_s, bc, bh, box, binv,
+    hipLaunchKernelGGL(k_filter, dim3(nb), dim3(256), 0, st, nb, c->perm, c->pos_s, bc, bh, c->b_extent, box, binv,
                        c->prm.cutoff + c->prm.buffer, row_count, row_j, c->flags);
     hipLaunchKernelGGL(k_tiles_per_block, dim3(nblk(nb, 256)), dim3(256), 0, st, nb, row_count, tpb);
     if ((rc = device_scan(c, nb, tpb, t0)))
@@ -823,12 +851,7 @@ int build_blocklist(amoeba_ctx* c, const double* pos)
                            c->rev_ptr, c->b_cnt, c->rev_idx);
         hipLaunchKernelGGL(k_rev_sort, dim3(nblk(npad, 256)), dim3(256), 0, st, npad, c->rev_ptr, c->rev_idx);
     }
-    refresh_tiles(c);
-    hipMemcpyAsync(c->flags_host + 2, c->counter, sizeof(unsigned long long), hipMemcpyDeviceToHost, st);
-    if ((rc = hip_check(c, hipStreamSynchronize(st), "build_blocklist tiles")))
-        return fail(rc);
-    c->n_pairs = (int64_t) * (unsigned long long*)(c->flags_host + 2);
-    c->pairs_pending = false;
+    refresh_tiles(c);   // the pair count is read when amoeba_get_info asks for it
     c->list_built = true;
     c->cfg_valid = true;
     return AMOEBA_OK;

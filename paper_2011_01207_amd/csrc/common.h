@@ -206,8 +206,10 @@ struct amoeba_ctx {
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 
     // list-build scratch, kept between builds
-    unsigned long long* b_keys = nullptr;  // [npow2]
-    int b_npow2 = 0;
+    unsigned long long* b_keys = nullptr;  // [n] sort keys
+    unsigned long long* b_keys2 = nullptr; // [n] sorted keys
+    void* b_sort_tmp = nullptr;            // radix sort scratch
+    size_t b_sort_bytes = 0;
     double4* b_bc = nullptr;               // [nb] block box centres
     double4* b_bh = nullptr;               // [nb] block box half-extents
     int* b_rowc = nullptr;                 // [nb] filtered j count per block

@@ -39,10 +39,10 @@ template <typename R> struct PlT;
 template <> struct PlT<float> { using C = float2; using R4 = float4; };
 template <> struct PlT<double> { using C = double2; using R4 = double4; };
 
-constexpr int kPlThreads = 256;         // threads per workgroup of every pass
+constexpr int kPlThreads = 512;         // threads per workgroup of every pass
 constexpr int kPlMaxB = 1;              // butterflies per thread in one FFT round
-constexpr int kPlConv = 32;             // fixed-point values per thread in the conversion
-constexpr int kPlSplit = 8;             // split / combine items per thread in one round
+constexpr int kPlConv = 16;             // fixed-point values per thread in the conversion
+constexpr int kPlSplit = 4;             // split / combine items per thread in one round
 constexpr size_t kPlLdsMax = 64 * 1024; // LDS of one workgroup
 constexpr int kPlTargetWG = 432;        // workgroups per pass the chunking aims at
 
@@ -362,36 +362,54 @@ __global__ __launch_bounds__(kPlThreads) void k_pme_spread_z(PlaneGeom g, PlaneD
     __syncthreads();
     const R klx = (R)g.klx, kly = (R)g.kly, klz = (R)g.klz;
     const int nyr = rc.yb - rc.ya;
-    for (int i = tid; i < br.total(); i += kPlThreads) {
-        int t;
-        const int e = br.entry(i, t);
-        const int4 rec = xb_rec[e];
-        const R4 mu = src[rec.x];
-        R x0[5], x1[5], y0[5], y1[5], z0[5], z1[5];
-        int zi[5];
-        entry_splines<R>(xb_w[e], rec.w, g.K2, x0, x1, y0, y1, z0, z1, zi);
-        const R tx0 = pick5(x0, t), tx1 = pick5(x1, t) * klx;
-        const R ax = mu.x * tx1, bx = mu.y * tx0, cx = mu.z * tx0;
+    // two atoms per thread and round, their loads issued together
+    for (int i0 = tid; i0 < br.total(); i0 += 2 * kPlThreads) {
+        int tq[2];
+        int4 rec[2];
+        R4 w[2], mu[2];
+        bool ok[2];
 #pragma unroll
-        for (int tz = 0; tz < 5; ++tz)
-            z1[tz] *= klz;
+        for (int u = 0; u < 2; ++u) {
+            const int i = i0 + u * kPlThreads;
+            ok[u] = i < br.total();
+            const int e = br.entry(ok[u] ? i : i0, tq[u]);
+            rec[u] = xb_rec[e];
+            w[u] = xb_w[e];
+        }
 #pragma unroll
-        for (int ty = 0; ty < 5; ++ty) {
-            int yy = rec.z - ty;
-            yy += yy < 0 ? g.K1 : 0;
-            const int yl = yy - rc.ya;
-            if (yl < 0 || yl >= nyr)
+        for (int u = 0; u < 2; ++u)
+            mu[u] = src[rec[u].x];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            if (!ok[u])
                 continue;
-            const R cz0 = ax * y0[ty] + bx * (y1[ty] * kly);
-            const R cz1 = cx * y0[ty];
-            double* row = acc + 2 * (yl >> 1) * g.S + (yl & 1);
+            const int t = tq[u];
+            R x0[5], x1[5], y0[5], y1[5], z0[5], z1[5];
+            int zi[5];
+            entry_splines<R>(w[u], rec[u].w, g.K2, x0, x1, y0, y1, z0, z1, zi);
+            const R tx0 = pick5(x0, t), tx1 = pick5(x1, t) * klx;
+            const R ax = mu[u].x * tx1, bx = mu[u].y * tx0, cx = mu[u].z * tx0;
 #pragma unroll
-            for (int tz = 0; tz < 5; ++tz) {
-                const R v = cz0 * z0[tz] + cz1 * z1[tz];
-                if (FIX)
-                    atomicAdd(row + zi[tz], fixd((float)v));
-                else
-                    atomicAdd(row + zi[tz], (double)v);
+            for (int tz = 0; tz < 5; ++tz)
+                z1[tz] *= klz;
+#pragma unroll
+            for (int ty = 0; ty < 5; ++ty) {
+                int yy = rec[u].z - ty;
+                yy += yy < 0 ? g.K1 : 0;
+                const int yl = yy - rc.ya;
+                if (yl < 0 || yl >= nyr)
+                    continue;
+                const R cz0 = ax * y0[ty] + bx * (y1[ty] * kly);
+                const R cz1 = cx * y0[ty];
+                double* row = acc + 2 * (yl >> 1) * g.S + (yl & 1);
+#pragma unroll
+                for (int tz = 0; tz < 5; ++tz) {
+                    const R v = cz0 * z0[tz] + cz1 * z1[tz];
+                    if (FIX)
+                        atomicAdd(row + zi[tz], fixd((float)v));
+                    else
+                        atomicAdd(row + zi[tz], (double)v);
+                }
             }
         }
     }
@@ -633,31 +651,46 @@ __global__ __launch_bounds__(kPlThreads) void k_pme_z_gather(PlaneGeom g, PlaneD
         br.pre[t + 1] = br.pre[t] + st[rc.yb] - br.lo[t];
     }
     const int yorg = rc.ya - 4;
-    for (int i = tid; i < br.total(); i += kPlThreads) {
-        int t;
-        const int e = br.entry(i, t);
-        const int4 rec = xb_rec[e];
-        R x0[5], x1[5], y0[5], y1[5], z0[5], z1[5];
-        int zi[5];
-        entry_splines<R>(xb_w[e], rec.w, g.K2, x0, x1, y0, y1, z0, z1, zi);
-        R ax = 0, ay = 0, az = 0;
+    // two atoms per thread and round, their loads issued together
+    for (int i0 = tid; i0 < br.total(); i0 += 2 * kPlThreads) {
+        int tq[2];
+        int4 rec[2];
+        R4 w[2];
+        bool ok[2];
 #pragma unroll
-        for (int ty = 0; ty < 5; ++ty) {
-            const int r = rec.z - ty - yorg;   // in [0, nrows): fy lies in [ya, yb)
-            const R* row = psi + 2 * (r >> 1) * g.S + (r & 1);
-            R s0 = 0, s1 = 0;
-#pragma unroll
-            for (int tz = 0; tz < 5; ++tz) {
-                const R v = row[zi[tz]];
-                s0 += z0[tz] * v;
-                s1 += z1[tz] * v;
-            }
-            ax += y0[ty] * s0;
-            ay += y1[ty] * s0;
-            az += y0[ty] * s1;
+        for (int u = 0; u < 2; ++u) {
+            const int i = i0 + u * kPlThreads;
+            ok[u] = i < br.total();
+            const int e = br.entry(ok[u] ? i : i0, tq[u]);
+            rec[u] = xb_rec[e];
+            w[u] = xb_w[e];
         }
-        const R tx0 = pick5(x0, t), tx1 = pick5(x1, t);
-        part[5 * (size_t)rec.x + t] = R4{tx1 * ax, tx0 * ay, tx0 * az, (R)0};
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            if (!ok[u])
+                continue;
+            R x0[5], x1[5], y0[5], y1[5], z0[5], z1[5];
+            int zi[5];
+            entry_splines<R>(w[u], rec[u].w, g.K2, x0, x1, y0, y1, z0, z1, zi);
+            R ax = 0, ay = 0, az = 0;
+#pragma unroll
+            for (int ty = 0; ty < 5; ++ty) {
+                const int r = rec[u].z - ty - yorg;   // in [0, nrows): fy lies in [ya, yb)
+                const R* row = psi + 2 * (r >> 1) * g.S + (r & 1);
+                R s0 = 0, s1 = 0;
+#pragma unroll
+                for (int tz = 0; tz < 5; ++tz) {
+                    const R v = row[zi[tz]];
+                    s0 += z0[tz] * v;
+                    s1 += z1[tz] * v;
+                }
+                ax += y0[ty] * s0;
+                ay += y1[ty] * s0;
+                az += y0[ty] * s1;
+            }
+            const R tx0 = pick5(x0, tq[u]), tx1 = pick5(x1, tq[u]);
+            part[5 * (size_t)rec[u].x + tq[u]] = R4{tx1 * ax, tx0 * ay, tx0 * az, (R)0};
+        }
     }
 }
 
