@@ -157,7 +157,8 @@ struct amoeba_ctx {
     // dipole reciprocal field by x-planes (plane.hip), used when the grid fits (plane_ok)
     bool plane_ok = false;
     int pme_path = 0;              // amoeba_pme_path requested by the caller
-    bool rec_plane = false;        // the last reciprocal dipole field came from the plane path
+    bool rec_plane = false;        // the last reciprocal field came from the plane path
+    bool brick_bins_stale = true;  // brick bins and spline table not built for the current positions
     int32_t* xb_start = nullptr;   // [K0+1] atoms binned by the x line of their base point
     int32_t* xb_count = nullptr;   // [K0+1]
     int4* xb_rec = nullptr;        // [npad] per binned atom: (slot, fx, fy, fz)
@@ -284,6 +285,7 @@ bool plane_eligible(const amoeba_ctx* c);
 int plane_setup(amoeba_ctx* c);
 int plane_bin_atoms(amoeba_ctx* c);
 void plane_dipole_field(amoeba_ctx* c, bool use_done, int parts);  // 1 spread, 2 the rest, 3 all
+void plane_perm_field(amoeba_ctx* c);                             // permanent multipoles, all passes
 void plane_gather(amoeba_ctx* c, double* out);          // E_rec from the plane shares
 int plane_combine(amoeba_ctx* c, bool use_done, bool dot_pq);  // PCG product; returns its partial count
 bool pme_use_planes(const amoeba_ctx* c);

@@ -291,16 +291,17 @@ struct RowChunk {
     }
 };
 
-// the spline weights of an atom entry (arguments w) and its z grid lines, doubled for the pair
-// layout
-template <typename R>
+// the spline weights of an atom entry (arguments w; second derivatives x2, y2, z2 when SECOND)
+// and its z grid lines, doubled for the pair layout
+template <typename R, bool SECOND = false>
 __device__ __forceinline__ void entry_splines(const typename PlT<R>::R4& w, int fz, int K2, R (&x0)[5], R (&x1)[5],
-                                              R (&y0)[5], R (&y1)[5], R (&z0)[5], R (&z1)[5], int (&zi)[5])
+                                              R (&y0)[5], R (&y1)[5], R (&z0)[5], R (&z1)[5], int (&zi)[5],
+                                              R* x2 = nullptr, R* y2 = nullptr, R* z2 = nullptr)
 {
-    R dum[5];
-    spline5<R, false>(w.x, x0, x1, dum);
-    spline5<R, false>(w.y, y0, y1, dum);
-    spline5<R, false>(w.z, z0, z1, dum);
+    R dum[3][5];
+    spline5<R, SECOND>(w.x, x0, x1, SECOND ? x2 : dum[0]);
+    spline5<R, SECOND>(w.y, y0, y1, SECOND ? y2 : dum[1]);
+    spline5<R, SECOND>(w.z, z0, z1, SECOND ? z2 : dum[2]);
 #pragma unroll
     for (int tz = 0; tz < 5; ++tz) {
         int zz = fz - tz;
@@ -311,10 +312,12 @@ __device__ __forceinline__ void entry_splines(const typename PlT<R>::R4& w, int 
 
 // Pass 1 (spread, z transform): workgroup (row chunk c, plane x).  The atoms whose support
 // meets the chunk's rows of plane x have fx in x..x+4 and fy in [ya, yb + 4) (mod K); they add
-// p_x M' M M + p_y M M' M + p_z M M M' (derivatives scaled by K/L) at their in-chunk points.
+// p_x M' M M + p_y M M' M + p_z M M M' (derivatives scaled by K/L) at their in-chunk points,
+// or with PERM their permanent multipoles, q M M M + d . grad(M M M) + Theta : grad grad (M M M) / 3
+// (src then holds three R4 per atom: (q, d), (Txx, Txy, Txz, Tyy), (Tyz, Tzz, 0, 0)).
 // Then every row pair is transformed along z, separated into the two rows' half spectra, and
 // the rows are written to G[x][y][0, kh).
-template <typename R, bool FIX>
+template <typename R, bool FIX, bool PERM>
 __global__ __launch_bounds__(kPlThreads) void k_pme_spread_z(PlaneGeom g, PlaneDim dz,
                                                              const int* __restrict__ xy_start,
                                                              const int4* __restrict__ xb_rec,
@@ -366,7 +369,7 @@ __global__ __launch_bounds__(kPlThreads) void k_pme_spread_z(PlaneGeom g, PlaneD
     for (int i0 = tid; i0 < br.total(); i0 += 2 * kPlThreads) {
         int tq[2];
         int4 rec[2];
-        R4 w[2], mu[2];
+        R4 w[2], m[2][PERM ? 3 : 1];
         bool ok[2];
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
@@ -378,20 +381,41 @@ __global__ __launch_bounds__(kPlThreads) void k_pme_spread_z(PlaneGeom g, PlaneD
         }
 #pragma unroll
         for (int u = 0; u < 2; ++u)
-            mu[u] = src[rec[u].x];
+#pragma unroll
+            for (int k = 0; k < (PERM ? 3 : 1); ++k)
+                m[u][k] = src[(PERM ? 3 : 1) * (size_t)rec[u].x + k];
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
             if (!ok[u])
                 continue;
             const int t = tq[u];
-            R x0[5], x1[5], y0[5], y1[5], z0[5], z1[5];
+            R x0[5], x1[5], y0[5], y1[5], z0[5], z1[5], x2[5], y2[5], z2[5];
             int zi[5];
-            entry_splines<R>(w[u], rec[u].w, g.K2, x0, x1, y0, y1, z0, z1, zi);
-            const R tx0 = pick5(x0, t), tx1 = pick5(x1, t) * klx;
-            const R ax = mu[u].x * tx1, bx = mu[u].y * tx0, cx = mu[u].z * tx0;
+            entry_splines<R, PERM>(w[u], rec[u].w, g.K2, x0, x1, y0, y1, z0, z1, zi, x2, y2, z2);
+            const R X0 = pick5(x0, t), X1 = pick5(x1, t) * klx;
 #pragma unroll
-            for (int tz = 0; tz < 5; ++tz)
+            for (int tz = 0; tz < 5; ++tz) {
                 z1[tz] *= klz;
+                if (PERM)
+                    z2[tz] *= klz * klz;
+            }
+            // per y weight: c0 (times M_z), c1 (times M'_z), c2 (times M''_z)
+            R a0 = 0, a1 = 0, a2 = 0, b0 = 0, b1 = 0, b2 = 0, e0 = 0;
+            if (PERM) {
+                const R X2 = pick5(x2, t) * klx * klx, third = (R)1 / (R)3;
+                const R4 m0 = m[u][0], m1 = m[u][1], m2 = m[u][PERM ? 2 : 0];
+                // c0 = a0 y0 + a1 y1 + a2 y2, c1 = b0 y0 + b1 y1, c2 = e0 y0
+                a0 = m0.x * X0 + m0.y * X1 + third * m1.x * X2;
+                a1 = m0.z * X0 + (R)2 * third * m1.y * X1;
+                a2 = third * m1.w * X0;
+                b0 = m0.w * X0 + (R)2 * third * m1.z * X1;
+                b1 = (R)2 * third * m2.x * X0;
+                e0 = third * m2.y * X0;
+            } else {
+                a0 = m[u][0].x * X1;
+                a1 = m[u][0].y * X0;
+                b0 = m[u][0].z * X0;
+            }
 #pragma unroll
             for (int ty = 0; ty < 5; ++ty) {
                 int yy = rec[u].z - ty;
@@ -399,12 +423,23 @@ __global__ __launch_bounds__(kPlThreads) void k_pme_spread_z(PlaneGeom g, PlaneD
                 const int yl = yy - rc.ya;
                 if (yl < 0 || yl >= nyr)
                     continue;
-                const R cz0 = ax * y0[ty] + bx * (y1[ty] * kly);
-                const R cz1 = cx * y0[ty];
+                const R yw1 = y1[ty] * kly;
+                R c0, c1, c2 = 0;
+                if (PERM) {
+                    const R yw2 = y2[ty] * kly * kly;
+                    c0 = a0 * y0[ty] + a1 * yw1 + a2 * yw2;
+                    c1 = b0 * y0[ty] + b1 * yw1;
+                    c2 = e0 * y0[ty];
+                } else {
+                    c0 = a0 * y0[ty] + a1 * yw1;
+                    c1 = b0 * y0[ty];
+                }
                 double* row = acc + 2 * (yl >> 1) * g.S + (yl & 1);
 #pragma unroll
                 for (int tz = 0; tz < 5; ++tz) {
-                    const R v = cz0 * z0[tz] + cz1 * z1[tz];
+                    R v = c0 * z0[tz] + c1 * z1[tz];
+                    if (PERM)
+                        v += c2 * z2[tz];
                     if (FIX)
                         atomicAdd(row + zi[tz], fixd((float)v));
                     else
@@ -781,14 +816,18 @@ __global__ __launch_bounds__(256) void k_plane_combine(int npad, double3 kl, con
 // per configuration: atoms binned by the (x, y) lines of their base point, with their spline
 // arguments; the order inside a bin is arbitrary (no result depends on it)
 // ------------------------------------------------------------------------------------------
-__global__ void k_xybin_count(int npad, int K1, const int* __restrict__ perm, const int4* __restrict__ sp_base,
-                              int* __restrict__ count)
+__global__ void k_xybin_count(int npad, const int* __restrict__ perm, const double4* __restrict__ pos_s, double3 kl,
+                              int3 K, int* __restrict__ count)
 {
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= npad || perm[s] < 0)
         return;
-    const int4 b = sp_base[s];
-    atomicAdd(&count[b.x * K1 + b.y], 1);
+    const double4 p = pos_s[s];
+    int fx, fy;
+    double u;
+    grid_coord(p.x, kl.x, K.x, fx, u);
+    grid_coord(p.y, kl.y, K.y, fy, u);
+    atomicAdd(&count[fx * K.y + fy], 1);
 }
 
 template <typename R>
@@ -929,8 +968,8 @@ int plane_bin_atoms(amoeba_ctx* c)
     int3 K = make_int3(c->K[0], c->K[1], c->K[2]);
     double3 kl = make_double3(c->K[0] / c->prm.box[0], c->K[1] / c->prm.box[1], c->K[2] / c->prm.box[2]);
     hipMemsetAsync(c->xb_count, 0, sizeof(int) * (nb2 + 1), st);
-    hipLaunchKernelGGL(k_xybin_count, dim3(nblk(c->npad, 256)), dim3(256), 0, st, c->npad, c->K[1], c->perm,
-                       c->sp_base, c->xb_count);
+    hipLaunchKernelGGL(k_xybin_count, dim3(nblk(c->npad, 256)), dim3(256), 0, st, c->npad, c->perm, c->pos_s, kl, K,
+                       c->xb_count);
     int rc = device_scan(c, nb2, c->xb_count, c->xb_start);
     if (rc)
         return rc;
@@ -944,8 +983,9 @@ int plane_bin_atoms(amoeba_ctx* c)
     return AMOEBA_OK;
 }
 
-// part 1: the spread pass; part 2: the transforms and the interpolation; 3: both
-template <typename R> static void plane_field_t(amoeba_ctx* c, bool use_done, int parts)
+// part 1: the spread pass; part 2: the transforms and the interpolation; 3: both.  perm: spread
+// the permanent multipoles (mp) instead of the direction, all stages timed as AMOEBA_T_PERM.
+template <typename R> static void plane_field_t(amoeba_ctx* c, bool use_done, int parts, bool perm)
 {
     using C = typename PlT<R>::C;
     using R4 = typename PlT<R>::R4;
@@ -959,17 +999,23 @@ template <typename R> static void plane_field_t(amoeba_ctx* c, bool use_done, in
     const C* const* roots = (const C* const*)c->pl_roots;
     C* gc = (C*)c->grid_c;
     const dim3 nt(kPlThreads);
+    constexpr bool FIX = std::is_same<R, float>::value;
     if (parts & 1) {
-        StageTimer tm(c, AMOEBA_T_SPREAD);
-        const R4* src = c->mixed ? (const R4*)c->pv_f : (const R4*)c->pv_d;
-        hipLaunchKernelGGL((k_pme_spread_z<R, std::is_same<R, float>::value>), dim3(g.K0 * g.nyc), nt,
-                           lds_spread(g, cs), st, g, d[2], c->xb_start, c->xb_rec, (const R4*)c->xb_w, src, roots[2],
-                           gc, c->sc, ud);
+        StageTimer tm(c, perm ? AMOEBA_T_PERM : AMOEBA_T_SPREAD);
+        if (perm) {
+            const R4* src = c->mixed ? (const R4*)c->mp_f : (const R4*)c->mp_d;
+            hipLaunchKernelGGL((k_pme_spread_z<R, FIX, true>), dim3(g.K0 * g.nyc), nt, lds_spread(g, cs), st, g, d[2],
+                               c->xb_start, c->xb_rec, (const R4*)c->xb_w, src, roots[2], gc, c->sc, 0);
+        } else {
+            const R4* src = c->mixed ? (const R4*)c->pv_f : (const R4*)c->pv_d;
+            hipLaunchKernelGGL((k_pme_spread_z<R, FIX, false>), dim3(g.K0 * g.nyc), nt, lds_spread(g, cs), st, g,
+                               d[2], c->xb_start, c->xb_rec, (const R4*)c->xb_w, src, roots[2], gc, c->sc, ud);
+        }
     }
     if (!(parts & 2))
         return;
     {
-        StageTimer tm(c, AMOEBA_T_FFT);
+        StageTimer tm(c, perm ? AMOEBA_T_PERM : AMOEBA_T_FFT);
         hipLaunchKernelGGL((k_pme_ylines<R, -1>), dim3(g.K0 * g.nkc), nt, lds_lines(g.K1, g.kc, cs), st, g, d[1], gc,
                            roots[1], c->sc, ud);
         hipLaunchKernelGGL(k_pme_xconv<R>, dim3(g.K1 * g.nkc), nt, lds_lines(g.K0, g.kc, cs), st, g, d[0], gc,
@@ -978,7 +1024,7 @@ template <typename R> static void plane_field_t(amoeba_ctx* c, bool use_done, in
                            roots[1], c->sc, ud);
     }
     {
-        StageTimer tm(c, AMOEBA_T_GATHER);
+        StageTimer tm(c, perm ? AMOEBA_T_PERM : AMOEBA_T_GATHER);
         hipLaunchKernelGGL(k_pme_z_gather<R>, dim3(g.K0 * g.nyc), nt, lds_gather(g, cs), st, g, d[2], (const C*)gc,
                            c->xb_start, c->xb_rec, (const R4*)c->xb_w, roots[2], (R4*)c->rec_part, c->sc, ud);
     }
@@ -987,9 +1033,17 @@ template <typename R> static void plane_field_t(amoeba_ctx* c, bool use_done, in
 void plane_dipole_field(amoeba_ctx* c, bool use_done, int parts)
 {
     if (c->mixed)
-        plane_field_t<float>(c, use_done, parts);
+        plane_field_t<float>(c, use_done, parts, false);
     else
-        plane_field_t<double>(c, use_done, parts);
+        plane_field_t<double>(c, use_done, parts, false);
+}
+
+void plane_perm_field(amoeba_ctx* c)
+{
+    if (c->mixed)
+        plane_field_t<float>(c, false, 3, true);
+    else
+        plane_field_t<double>(c, false, 3, true);
 }
 
 void plane_gather(amoeba_ctx* c, double* out)

@@ -828,7 +828,8 @@ int pme_setup(amoeba_ctx* c)
 
 __global__ void k_scan_excl_pme(int n, const int* __restrict__ in, int* __restrict__ out);
 
-void pme_bin_atoms(amoeba_ctx* c)
+// Brick bins and the spline table (the brick path); built on first use for a configuration.
+static void brick_bin_atoms(amoeba_ctx* c)
 {
     hipStream_t st = c->stream;
     int3 K = make_int3(c->K[0], c->K[1], c->K[2]);
@@ -848,7 +849,23 @@ void pme_bin_atoms(amoeba_ctx* c)
     else
         hipLaunchKernelGGL(k_spline_table<double>, dim3(nblk(c->npad, 256)), dim3(256), 0, st, c->npad, c->perm,
                            c->pos_s, kl, K, c->sp_base, (double*)c->sp_w);
+    c->brick_bins_stale = false;
+}
+
+static void ensure_brick_bins(amoeba_ctx* c)
+{
+    if (c->brick_bins_stale)
+        brick_bin_atoms(c);
+}
+
+// Per configuration: the bins of the path in use (the plane bins whenever the grid fits the
+// plane path; the brick bins then only when a brick-path product asks for them).
+void pme_bin_atoms(amoeba_ctx* c)
+{
+    c->brick_bins_stale = true;
     plane_bin_atoms(c);
+    if (!pme_use_planes(c))
+        brick_bin_atoms(c);
 }
 
 __global__ __launch_bounds__(1024) void k_scan_excl_pme(int n, const int* __restrict__ in, int* __restrict__ out)
@@ -917,6 +934,7 @@ int pme_dipole_field(amoeba_ctx* c, bool use_done)
         plane_dipole_field(c, use_done, 3);
         return AMOEBA_OK;
     }
+    ensure_brick_bins(c);
     int3 K = make_int3(c->K[0], c->K[1], c->K[2]);
     int3 nbr = make_int3(c->nbr[0], c->nbr[1], c->nbr[2]);
     double3 kl = make_double3(c->K[0] / c->prm.box[0], c->K[1] / c->prm.box[1], c->K[2] / c->prm.box[2]);
@@ -942,8 +960,13 @@ int pme_dipole_field(amoeba_ctx* c, bool use_done)
 
 int pme_perm_potential(amoeba_ctx* c)
 {
+    c->rec_plane = pme_use_planes(c);
+    if (c->rec_plane) {
+        plane_perm_field(c);
+        return AMOEBA_OK;
+    }
+    ensure_brick_bins(c);
     StageTimer tm(c, AMOEBA_T_PERM);
-    c->rec_plane = false;
     int3 K = make_int3(c->K[0], c->K[1], c->K[2]);
     int3 nbr = make_int3(c->nbr[0], c->nbr[1], c->nbr[2]);
     double3 kl = make_double3(c->K[0] / c->prm.box[0], c->K[1] / c->prm.box[1], c->K[2] / c->prm.box[2]);

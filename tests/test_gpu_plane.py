@@ -67,6 +67,24 @@ def test_plane_field_matches_oracle_and_bricks(grid, prec):
     assert err_paths_mv < TOL_PATHS[prec], err_paths_mv
 
 
+@pytest.mark.parametrize("grid", [(24, 24, 24), (20, 21, 28), (28, 15, 35)], ids=lambda g: "x".join(map(str, g)))
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_plane_perm_field_matches_oracle_and_bricks(grid, prec):
+    """Permanent multipoles (charges, dipoles, quadrupoles) spread on the plane path."""
+    print(f"[gpu] plane perm field grid={grid} {prec}", flush=True)
+    s = system(grid)
+    ref = O.perm_field(s, "spme")
+    ctx, t = amoeba.context_for(s, precision=prec, device=DEV)
+    try:
+        e = ctx.perm_field(t["pos"], t["q"], t["dip"], t["quad"]).cpu().numpy()
+        ctx.set_pme_path("bricks")
+        e_b = ctx.perm_field(t["pos"], t["q"], t["dip"], t["quad"]).cpu().numpy()
+    finally:
+        ctx.close()
+    assert rel_rms(e, ref) < (1e-11 if prec == "fp64" else 2e-5)
+    assert rel_rms(e, e_b) < TOL_PATHS[prec]
+
+
 def test_plane_mixed_is_bitwise_reproducible():
     s = system((20, 21, 28))
     rng = np.random.default_rng(5)
