@@ -110,7 +110,7 @@ def run_variant(s, t, precision, steps, warmup, tol, timing=True):
     info = ctx.info()
     out = {"step_ms": 1e3 * (t1 - t0) / steps, "solve_only_ms": 1e3 * (u1 - u0) / steps, "iterations": it,
            "e_pol_kcal": ep, "n_pairs": info["n_pairs"], "n_tiles": info["n_tiles"], "n_blocks": info["n_blocks"],
-           "pme_planes": info["pme_planes"],
+           "pme_planes": info["pme_planes"], "pair_min_image": info["pair_min_image"],
            "timing": tim, "mu": mu.clone(), "e_perm": e_perm.clone()}
     ctx.close()
     return out
@@ -214,28 +214,30 @@ def roofline(s, res, K):
     # real-space dipole tiles: FP32 VALU bound
     ms = tim["ms"]["real"]
     flops = FLOPS_PER_PAIR * res["n_pairs"] * mv
+    mi = "true" if res.get("pair_min_image") else "false"
     stages["real"] = {"bound": "alu", "achieved": flops / (ms * 1e-3) / 1e12, "peak": PEAK_FP32_VALU,
                       "unit": "TFLOP/s", "ms_total": ms, "launches": tim["launches"]["real"],
-                      "kernel": "k_block_tiles<float, true, DipoleKind<float>, *>",
+                      "kernel": f"k_block_tiles<float, true, DipoleKind<float>, {mi}>",
                       "algorithmic_per_launch": FLOPS_PER_PAIR * res["n_pairs"],
                       "peak_nonpacked": PEAK_FP32_NONPACKED,
                       "frac_nonpacked": flops / (ms * 1e-3) / 1e12 / PEAK_FP32_NONPACKED}
     kh = K[2] // 2 + 1
     nc = K[0] * K[1] * kh
     if res.get("pme_planes"):
-        # plane path.  spread stage = k_plane_fwd: per atom its binned record (16 B) and spline
-        # arguments (16 B) and its FP32 dipole (16 B) read once, the half-complex y-z spectrum
-        # (8 B per point) written once
+        # plane path.  spread stage = k_pme_spread_z: per atom its binned record (16 B), spline
+        # arguments (16 B) and FP32 dipole (16 B) read once, the z half spectra (8 B per point)
+        # written once
         b_spread = n * 48 + nc * 8
-        k_spread = "k_plane_fwd<float, true>"
-        # fft stage = k_plane_xconv: half grid read and written, influence function read
-        b_fft = nc * (8 + 8 + 4)
-        k_fft = "k_plane_xconv<float>"
-        # gather stage = k_plane_bwd + k_plane_combine: half grid read once, atom records read,
+        k_spread = "k_pme_spread_z<float, true, false>"
+        # fft stage = forward y-lines, x-lines with the influence function, inverse y-lines: the
+        # half grid read and written by each pass, the influence function read once
+        b_fft = 3 * nc * (8 + 8) + nc * 4
+        k_fft = "k_pme_ylines<float, -1> + k_pme_xconv<float> + k_pme_ylines<float, 1>"
+        # gather stage = k_pme_z_gather + k_plane_combine: half grid read once, atom records read,
         # five field shares written and read (16 B each); combine: i-field 24 B, direction 24 B,
         # 1/alpha 8 B read and A p 24 B written per atom, every tile j-field slot (16 B) read
         b_gather = nc * 8 + n * (32 + 2 * 80 + 24 + 24 + 8 + 24) + res["n_tiles"] * 64 * 16
-        k_gather = "k_plane_bwd<float> + k_plane_combine<float, 1>"
+        k_gather = "k_pme_z_gather<float> + k_plane_combine<float, 1>"
     else:
         # PME spread: position (12 B) + dipole (12 B) per atom read, FP32 grid written once
         b_spread = n * 24 + k3 * 4
@@ -264,10 +266,18 @@ def roofline(s, res, K):
         v["frac"] = v["achieved"] / v["peak"]
     dom = max(["real", "spread", "gather", "fft"], key=lambda k: stages[k]["ms_total"])
     d = stages[dom]
+    # HBM bytes per launch of the dominant kernel from the committed FETCH_SIZE / WRITE_SIZE
+    # summary (copy-calibrated), or None once the kernel's sources changed since it was taken
+    from paper_2011_01207_amd import profiling
+    traffic = profiling.traffic_lookup(os.path.join(ROOT, "profiles", "hbm_traffic_water_96000_mixed.md"),
+                                       d["kernel"])
+    avg_us = 1e3 * d["ms_total"] / max(1, d["launches"])
     top = {"bound": d["bound"], "achieved": d["achieved"], "peak": d["peak"], "unit": d["unit"],
-           "frac": d["frac"], "traffic": None, "kernel": d["kernel"], "stage": dom,
-           "avg_launch_us": 1e3 * d["ms_total"] / max(1, d["launches"]),
-           "productive_launches": mv, "launches": d["launches"]}
+           "frac": d["frac"], "traffic": traffic, "kernel": d["kernel"], "stage": dom,
+           "avg_launch_us": avg_us, "productive_launches": mv, "launches": d["launches"]}
+    if traffic is not None:
+        top["traffic_unit"] = "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)"
+        top["traffic_rate_gbs"] = traffic / (avg_us * 1e-6) / 1e9
     for k in ("peak_nonpacked", "frac_nonpacked"):
         if k in d:
             top[k] = d[k]
