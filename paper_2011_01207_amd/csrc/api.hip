@@ -490,10 +490,22 @@ int amoeba_perm_field(amoeba_ctx* c, const double* pos, const double* q, const d
     hipMemsetAsync(c->flags, 0, sizeof(int), st);
     hipLaunchKernelGGL(k_gather_mpole, dim3(nblk(c->npad, 256)), dim3(256), 0, st, c->npad, c->perm, q, dip, quad,
                        c->mp_d, c->mixed ? c->mp_f : nullptr, c->flags);
-    launch_perm_tiles(c);
-    if ((rc = pme_perm_potential(c)))
-        return rc;
-    launch_gather(c, c->erec);
+    if (pme_use_planes(c) && !c->timing) {
+        // the multipole tiles (VALU bound) on the second stream beside the reciprocal passes
+        hipEventRecord(c->ev_fork, st);
+        hipStreamWaitEvent(c->stream2, c->ev_fork, 0);
+        if ((rc = pme_perm_potential(c)))
+            return rc;
+        launch_perm_tiles(c, c->stream2);
+        hipEventRecord(c->ev_join, c->stream2);
+        launch_gather(c, c->erec);
+        hipStreamWaitEvent(st, c->ev_join, 0);
+    } else {
+        launch_perm_tiles(c);
+        if ((rc = pme_perm_potential(c)))
+            return rc;
+        launch_gather(c, c->erec);
+    }
     launch_perm_assemble(c, c->v_q);
     if (c->mixed)
         hipLaunchKernelGGL(k_check_overflow, dim3(nblk(3 * (size_t)c->npad, 256)), dim3(256), 0, st,

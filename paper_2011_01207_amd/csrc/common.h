@@ -269,8 +269,8 @@ int prepare_config(amoeba_ctx* c, const double* pos);
 
 // realspace.hip
 void launch_mutual_tiles(amoeba_ctx* c, bool use_done, hipStream_t st = nullptr);  // null: context stream
-void launch_real_reduce(amoeba_ctx* c, double* ereal);
-void launch_perm_tiles(amoeba_ctx* c);
+void launch_real_reduce(amoeba_ctx* c, double* ereal, hipStream_t st = nullptr);
+void launch_perm_tiles(amoeba_ctx* c, hipStream_t st = nullptr);
 void launch_perm_assemble(amoeba_ctx* c, double* out_slot);
 
 // pme.hip

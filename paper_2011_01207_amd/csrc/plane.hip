@@ -39,12 +39,14 @@ template <typename R> struct PlT;
 template <> struct PlT<float> { using C = float2; using R4 = float4; };
 template <> struct PlT<double> { using C = double2; using R4 = double4; };
 
-constexpr int kPlThreads = 512;         // threads per workgroup of every pass
+constexpr int kPlThreads = 512;         // threads per workgroup of the row-chunk passes (spread, gather)
+constexpr int kPlColThreads = 512;      // threads per workgroup of the column passes (y and x lines)
 constexpr int kPlMaxB = 1;              // butterflies per thread in one FFT round
 constexpr int kPlConv = 16;             // fixed-point values per thread in the conversion
 constexpr int kPlSplit = 4;             // split / combine items per thread in one round
 constexpr size_t kPlLdsMax = 64 * 1024; // LDS of one workgroup
-constexpr int kPlTargetWG = 432;        // workgroups per pass the chunking aims at
+constexpr int kPlTargetWG = 432;        // workgroups per row-chunk pass the chunking aims at
+constexpr int kPlColTargetWG = 432;     // workgroups per column pass
 
 // Factorisation of a transform length into radices 2..7 (host-computed).
 struct PlaneDim {
@@ -161,12 +163,12 @@ template <int RAD, int SIGN, typename C> __device__ __forceinline__ void dft(C (
 // (w = exp(SIGN 2 pi i / N), tw[m] = exp(-2 pi i m / N)), applies the RAD-point DFT and writes
 // output q to (j div Ns) Ns RAD + (j mod Ns) + q Ns.  Whole lines are processed per round, so
 // each round reads all its points into registers before the barrier and writes after it.
-template <int RAD, int SIGN, typename C>
+template <int RAD, int SIGN, int NT, typename C>
 __device__ __forceinline__ void fft_stage(C* buf, int nl, int N, int Ns, const C* tw, LineMap am)
 {
     const int nb = N / RAD;
     const int tstep = N / (Ns * RAD);
-    const int lpr = max(1, kPlThreads * kPlMaxB / nb);
+    const int lpr = max(1, NT * kPlMaxB / nb);
     const SmallDiv dnb(nb), dns(Ns);
     // an opaque copy of the thread index: keeps the compiler from hoisting every stage's index
     // arithmetic out of the stage loop (which would hold all of it in registers at once)
@@ -178,7 +180,7 @@ __device__ __forceinline__ void fft_stage(C* buf, int nl, int N, int Ns, const C
         int dst[kPlMaxB];
 #pragma unroll
         for (int m = 0; m < kPlMaxB; ++m) {
-            const int it = tid + m * kPlThreads;
+            const int it = tid + m * NT;
             dst[m] = -1;
             if (it < cnt) {
                 const int lq = dnb.quot(it), l = l0 + lq, j = it - lq * nb;
@@ -202,7 +204,7 @@ __device__ __forceinline__ void fft_stage(C* buf, int nl, int N, int Ns, const C
 #pragma unroll
         for (int m = 0; m < kPlMaxB; ++m) {
             if (dst[m] >= 0) {
-                const int it = tid + m * kPlThreads;
+                const int it = tid + m * NT;
                 const int lq = dnb.quot(it), l = l0 + lq, j = it - lq * nb, k = j - dns.quot(j) * Ns;
                 const int o = (j - k) * RAD + k;
 #pragma unroll
@@ -216,18 +218,18 @@ __device__ __forceinline__ void fft_stage(C* buf, int nl, int N, int Ns, const C
 
 // FFT (SIGN -1 forward, +1 unnormalised inverse) of nl lines of length d.n.  All threads of
 // the workgroup call it after a barrier; it ends with one.
-template <int SIGN, typename C>
+template <int SIGN, int NT = kPlThreads, typename C>
 __device__ __forceinline__ void fft_lines(C* buf, int nl, const PlaneDim& d, const C* tw, LineMap am)
 {
     int Ns = 1;
     for (int s = 0; s < d.nr; ++s) {
         switch (d.rad[s]) {
-        case 2: fft_stage<2, SIGN>(buf, nl, d.n, Ns, tw, am); break;
-        case 3: fft_stage<3, SIGN>(buf, nl, d.n, Ns, tw, am); break;
-        case 4: fft_stage<4, SIGN>(buf, nl, d.n, Ns, tw, am); break;
-        case 5: fft_stage<5, SIGN>(buf, nl, d.n, Ns, tw, am); break;
-        case 6: fft_stage<6, SIGN>(buf, nl, d.n, Ns, tw, am); break;
-        default: fft_stage<7, SIGN>(buf, nl, d.n, Ns, tw, am); break;
+        case 2: fft_stage<2, SIGN, NT>(buf, nl, d.n, Ns, tw, am); break;
+        case 3: fft_stage<3, SIGN, NT>(buf, nl, d.n, Ns, tw, am); break;
+        case 4: fft_stage<4, SIGN, NT>(buf, nl, d.n, Ns, tw, am); break;
+        case 5: fft_stage<5, SIGN, NT>(buf, nl, d.n, Ns, tw, am); break;
+        case 6: fft_stage<6, SIGN, NT>(buf, nl, d.n, Ns, tw, am); break;
+        default: fft_stage<7, SIGN, NT>(buf, nl, d.n, Ns, tw, am); break;
         }
         Ns *= d.rad[s];
     }
@@ -512,7 +514,7 @@ __global__ __launch_bounds__(kPlThreads) void k_pme_spread_z(PlaneGeom g, PlaneD
 // Passes 2 and 4 (y transform, SIGN -1 forward, +1 inverse): workgroup (plane x, column chunk):
 // the y-lines G[x][.][kz] for kz in the chunk, in place.
 template <typename R, int SIGN>
-__global__ __launch_bounds__(kPlThreads) void k_pme_ylines(PlaneGeom g, PlaneDim dy,
+__global__ __launch_bounds__(kPlColThreads) void k_pme_ylines(PlaneGeom g, PlaneDim dy,
                                                            typename PlT<R>::C* __restrict__ gc,
                                                            const typename PlT<R>::C* __restrict__ roots_y,
                                                            const PcgScalars* __restrict__ sc, int use_done)
@@ -528,16 +530,16 @@ __global__ __launch_bounds__(kPlThreads) void k_pme_ylines(PlaneGeom g, PlaneDim
     const SmallDiv dnc(ncol);
     C* buf = reinterpret_cast<C*>(pl_smem);
     C* tw = buf + g.K1 * g.kc;
-    for (int i = tid; i < g.K1; i += kPlThreads)
+    for (int i = tid; i < g.K1; i += kPlColThreads)
         tw[i] = roots_y[i];
     C* base = gc + (size_t)x * g.K1 * g.kh + kz0;
-    for (int i = tid; i < g.K1 * ncol; i += kPlThreads) {
+    for (int i = tid; i < g.K1 * ncol; i += kPlColThreads) {
         const int y = dnc.quot(i), cc = i - y * ncol;
         buf[y * g.kc + cc] = base[(size_t)y * g.kh + cc];
     }
     __syncthreads();
-    fft_lines<SIGN>(buf, ncol, dy, tw, LineMap{1, 2 * g.kc, g.kc});
-    for (int i = tid; i < g.K1 * ncol; i += kPlThreads) {
+    fft_lines<SIGN, kPlColThreads>(buf, ncol, dy, tw, LineMap{1, 2 * g.kc, g.kc});
+    for (int i = tid; i < g.K1 * ncol; i += kPlColThreads) {
         const int y = dnc.quot(i), cc = i - y * ncol;
         base[(size_t)y * g.kh + cc] = buf[y * g.kc + cc];
     }
@@ -546,7 +548,7 @@ __global__ __launch_bounds__(kPlThreads) void k_pme_ylines(PlaneGeom g, PlaneDim
 // Pass 3: workgroup (ky, column chunk): the x-lines of G for kz in the chunk: FFT, product with
 // the influence function theta[kx][ky][kz], inverse FFT, in place.
 template <typename R>
-__global__ __launch_bounds__(kPlThreads) void k_pme_xconv(PlaneGeom g, PlaneDim dx,
+__global__ __launch_bounds__(kPlColThreads) void k_pme_xconv(PlaneGeom g, PlaneDim dx,
                                                           typename PlT<R>::C* __restrict__ gc,
                                                           const R* __restrict__ theta,
                                                           const typename PlT<R>::C* __restrict__ roots_x,
@@ -563,18 +565,18 @@ __global__ __launch_bounds__(kPlThreads) void k_pme_xconv(PlaneGeom g, PlaneDim 
     const SmallDiv dnc(ncol);
     C* buf = reinterpret_cast<C*>(pl_smem);
     C* tw = buf + g.K0 * g.kc;
-    for (int i = tid; i < g.K0; i += kPlThreads)
+    for (int i = tid; i < g.K0; i += kPlColThreads)
         tw[i] = roots_x[i];
     const size_t xs = (size_t)g.K1 * g.kh;   // stride of x in G
     const size_t off = (size_t)ky * g.kh + kz0;
-    for (int i = tid; i < g.K0 * ncol; i += kPlThreads) {
+    for (int i = tid; i < g.K0 * ncol; i += kPlColThreads) {
         const int xx = dnc.quot(i), cc = i - xx * ncol;
         buf[xx * g.kc + cc] = gc[xx * xs + off + cc];
     }
     __syncthreads();
     const LineMap am{1, 2 * g.kc, g.kc};
-    fft_lines<-1>(buf, ncol, dx, tw, am);
-    for (int i = tid; i < g.K0 * ncol; i += kPlThreads) {
+    fft_lines<-1, kPlColThreads>(buf, ncol, dx, tw, am);
+    for (int i = tid; i < g.K0 * ncol; i += kPlColThreads) {
         const int kx = dnc.quot(i), cc = i - kx * ncol;
         const R th = theta[kx * xs + off + cc];
         C v = buf[kx * g.kc + cc];
@@ -583,8 +585,8 @@ __global__ __launch_bounds__(kPlThreads) void k_pme_xconv(PlaneGeom g, PlaneDim 
         buf[kx * g.kc + cc] = v;
     }
     __syncthreads();
-    fft_lines<+1>(buf, ncol, dx, tw, am);
-    for (int i = tid; i < g.K0 * ncol; i += kPlThreads) {
+    fft_lines<+1, kPlColThreads>(buf, ncol, dx, tw, am);
+    for (int i = tid; i < g.K0 * ncol; i += kPlColThreads) {
         const int xx = dnc.quot(i), cc = i - xx * ncol;
         gc[xx * xs + off + cc] = buf[xx * g.kc + cc];
     }
@@ -877,7 +879,7 @@ static bool plane_factor(int n, PlaneDim& d)
         while (m % r == 0) {
             if (d.nr >= 12)
                 return false;
-            if (n / r > kPlThreads * kPlMaxB)
+            if (n / r > kPlColThreads * kPlMaxB)
                 return false;
             d.rad[d.nr++] = r;
             m /= r;
@@ -907,7 +909,7 @@ static PlaneGeom plane_geom(const amoeba_ctx* c)
         g.Pc = cdiv(g.Pc, 2);
     g.nyc = cdiv(g.P, g.Pc);
     // column chunks likewise
-    g.nkc = std::min(g.kh, std::max(1, cdiv(kPlTargetWG, std::min(g.K0, g.K1))));
+    g.nkc = std::min(g.kh, std::max(1, cdiv(kPlColTargetWG, std::min(g.K0, g.K1))));
     g.kc = cdiv(g.kh, g.nkc);
     while (g.kc > 1 && (lds_lines(g.K0, g.kc, cs) > kPlLdsMax || lds_lines(g.K1, g.kc, cs) > kPlLdsMax))
         g.kc = cdiv(g.kc, 2);
@@ -998,7 +1000,7 @@ template <typename R> static void plane_field_t(amoeba_ctx* c, bool use_done, in
     const int ud = use_done ? 1 : 0;
     const C* const* roots = (const C* const*)c->pl_roots;
     C* gc = (C*)c->grid_c;
-    const dim3 nt(kPlThreads);
+    const dim3 nt(kPlThreads), ntc(kPlColThreads);
     constexpr bool FIX = std::is_same<R, float>::value;
     if (parts & 1) {
         StageTimer tm(c, perm ? AMOEBA_T_PERM : AMOEBA_T_SPREAD);
@@ -1016,11 +1018,11 @@ template <typename R> static void plane_field_t(amoeba_ctx* c, bool use_done, in
         return;
     {
         StageTimer tm(c, perm ? AMOEBA_T_PERM : AMOEBA_T_FFT);
-        hipLaunchKernelGGL((k_pme_ylines<R, -1>), dim3(g.K0 * g.nkc), nt, lds_lines(g.K1, g.kc, cs), st, g, d[1], gc,
+        hipLaunchKernelGGL((k_pme_ylines<R, -1>), dim3(g.K0 * g.nkc), ntc, lds_lines(g.K1, g.kc, cs), st, g, d[1], gc,
                            roots[1], c->sc, ud);
-        hipLaunchKernelGGL(k_pme_xconv<R>, dim3(g.K1 * g.nkc), nt, lds_lines(g.K0, g.kc, cs), st, g, d[0], gc,
+        hipLaunchKernelGGL(k_pme_xconv<R>, dim3(g.K1 * g.nkc), ntc, lds_lines(g.K0, g.kc, cs), st, g, d[0], gc,
                            (const R*)c->theta, roots[0], c->sc, ud);
-        hipLaunchKernelGGL((k_pme_ylines<R, 1>), dim3(g.K0 * g.nkc), nt, lds_lines(g.K1, g.kc, cs), st, g, d[1], gc,
+        hipLaunchKernelGGL((k_pme_ylines<R, 1>), dim3(g.K0 * g.nkc), ntc, lds_lines(g.K1, g.kc, cs), st, g, d[1], gc,
                            roots[1], c->sc, ud);
     }
     {

@@ -551,40 +551,44 @@ void launch_mutual_tiles(amoeba_ctx* c, bool use_done, hipStream_t st)
         mutual_tiles<true>(c, use_done, st);
 }
 
-void launch_real_reduce(amoeba_ctx* c, double* ereal)
+void launch_real_reduce(amoeba_ctx* c, double* ereal, hipStream_t st)
 {
+    if (!st)
+        st = c->stream;
     if (c->mixed)
-        hipLaunchKernelGGL(k_real_reduce<float>, dim3((c->npad + 255) / 256), dim3(256), 0, c->stream, c->npad,
+        hipLaunchKernelGGL(k_real_reduce<float>, dim3((c->npad + 255) / 256), dim3(256), 0, st, c->npad,
                            c->eipart, (const float*)c->jbuf, c->rev_ptr, c->rev_idx, ereal);
     else
-        hipLaunchKernelGGL(k_real_reduce<double>, dim3((c->npad + 255) / 256), dim3(256), 0, c->stream, c->npad,
+        hipLaunchKernelGGL(k_real_reduce<double>, dim3((c->npad + 255) / 256), dim3(256), 0, st, c->npad,
                            c->eipart, (const double*)c->jbuf, c->rev_ptr, c->rev_idx, ereal);
 }
 
-template <bool MI> static void perm_tiles(amoeba_ctx* c)
+template <bool MI> static void perm_tiles(amoeba_ctx* c, hipStream_t st)
 {
     if (c->ntiles == 0)
         return;
     StageTimer tm(c, AMOEBA_T_PERM);
     if (c->mixed)
         hipLaunchKernelGGL((k_block_tiles<float, true, MultipoleKind<float>, MI>), dim3(c->nb), dim3(256), 0,
-                           c->stream, c->nb, c->blk_tile0, c->tile_j, c->tile_mask, c->jrel_f, c->off_f, c->par_f,
+                           st, c->nb, c->blk_tile0, c->tile_j, c->tile_mask, c->jrel_f, c->off_f, c->par_f,
                            (const float4*)c->mp_f, make_ewald<float>(c), c->eipart, (float*)c->jbuf, c->sc, 0);
     else
         hipLaunchKernelGGL((k_block_tiles<double, false, MultipoleKind<double>, MI>), dim3(c->nb), dim3(256), 0,
-                           c->stream, c->nb, c->blk_tile0, c->tile_j, c->tile_mask, c->jrel_d, c->off_d, c->par_d,
+                           st, c->nb, c->blk_tile0, c->tile_j, c->tile_mask, c->jrel_d, c->off_d, c->par_d,
                            (const double4*)c->mp_d, make_ewald<double>(c), c->eipart, (double*)c->jbuf, c->sc, 0);
 }
 
-void launch_perm_tiles(amoeba_ctx* c)
+void launch_perm_tiles(amoeba_ctx* c, hipStream_t st)
 {
     if (c->ntiles == 0)
         return;
+    if (!st)
+        st = c->stream;
     if (c->skip_mimg)
-        perm_tiles<false>(c);
+        perm_tiles<false>(c, st);
     else
-        perm_tiles<true>(c);
-    launch_real_reduce(c, c->ereal);
+        perm_tiles<true>(c, st);
+    launch_real_reduce(c, c->ereal, st);
 }
 
 // ------------------------------------------------------------------------------------------
