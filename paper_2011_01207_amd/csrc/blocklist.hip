@@ -584,6 +584,7 @@ __global__ __launch_bounds__(256) void k_tile_refresh(int ntiles, const int* __r
                                                       const float4* __restrict__ off_f, double3 box, double3 binv,
                                                       double rc2, unsigned long long* __restrict__ mask,
                                                       double4* __restrict__ jrel_d, float4* __restrict__ jrel_f,
+                                                      int* __restrict__ tile_np,
                                                       unsigned long long* __restrict__ pair_part)
 {
     __shared__ double4 s_jd[4][kBlock];
@@ -645,8 +646,11 @@ __global__ __launch_bounds__(256) void k_tile_refresh(int ntiles, const int* __r
     unsigned long long cnt = (unsigned long long)__popcll(m);
     for (int off = 32; off > 0; off >>= 1)
         cnt += __shfl_xor(cnt, off);
-    if (lane == 0)
+    if (lane == 0) {
         s_cnt[w] = cnt;
+        if (act)
+            tile_np[t] = (int)cnt;  // the pair kernels balance their waves by it
+    }
     __syncthreads();
     if (threadIdx.x == 0)
         pair_part[blockIdx.x] = s_cnt[0] + s_cnt[1] + s_cnt[2] + s_cnt[3];
@@ -722,7 +726,7 @@ static int refresh_tiles(amoeba_ctx* c)
     const int nwg = nblk((long)c->ntiles * kBlock, 256);
     hipLaunchKernelGGL(k_tile_refresh, dim3(nwg), dim3(256), 0, st, c->ntiles, c->tile_blk, c->tile_j, c->perm,
                        c->pos_s, c->blk_org, c->off_f, box, binv, c->prm.cutoff * c->prm.cutoff, c->tile_mask,
-                       c->jrel_d, c->jrel_f, c->pair_part);
+                       c->jrel_d, c->jrel_f, c->tile_np, c->pair_part);
     hipLaunchKernelGGL(k_sum_pairs, dim3(1), dim3(256), 0, st, nwg, c->pair_part, c->counter);
     c->pairs_pending = true;
     pme_bin_atoms(c);
@@ -828,6 +832,7 @@ int build_blocklist(amoeba_ctx* c, const double* pos)
         if ((rc = ctx_alloc(c, (void**)&c->tile_blk, sizeof(int) * total)) ||
             (rc = ctx_alloc(c, (void**)&c->tile_j, sizeof(int) * tb)) ||
             (rc = ctx_alloc(c, (void**)&c->tile_mask, sizeof(unsigned long long) * tb)) ||
+            (rc = ctx_alloc(c, (void**)&c->tile_np, sizeof(int) * total)) ||
             (c->mixed && (rc = ctx_alloc(c, (void**)&c->jrel_f, sizeof(float4) * tb))) ||
             (!c->mixed && (rc = ctx_alloc(c, (void**)&c->jrel_d, sizeof(double4) * tb))) ||
             (rc = ctx_alloc(c, &c->jbuf, rs * 4 * tb)) ||

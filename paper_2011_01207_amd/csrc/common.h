@@ -136,6 +136,7 @@ struct amoeba_ctx {
     int32_t* tile_blk = nullptr;   // [ntiles]
     int32_t* tile_j = nullptr;     // [ntiles*64] j slot or -1
     unsigned long long* tile_mask = nullptr; // [ntiles*64] bit k of row i: pair (i, j_k) within rc
+    int32_t* tile_np = nullptr;    // [ntiles] in-cutoff pairs of each tile (per configuration)
     double4* jrel_d = nullptr;     // [ntiles*64] j position relative to the i-block origin
     float4* jrel_f = nullptr;
     int32_t* blk_tile0 = nullptr;  // [nb+1] first tile of each block row

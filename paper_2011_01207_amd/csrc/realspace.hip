@@ -91,6 +91,7 @@ __device__ __forceinline__ float d_rint(float x) { return rintf(x); }
 __device__ __forceinline__ double d_rint(double x) { return rint(x); }
 
 constexpr int kWavesPerWG = 4;
+constexpr int kTileCost = 128;  // per-tile cost of staging and scanning, in units of pairs
 
 // LDS field accumulators: fixed point with 40 fraction bits held as integer-valued FP64
 // (mixed; see fixd) or plain FP64.
@@ -367,6 +368,7 @@ template <typename R> struct MultipoleKind {
 // ------------------------------------------------------------------------------------------
 template <typename R, bool FIX, class K, bool MI>
 __global__ __launch_bounds__(256) void k_block_tiles(int nb, const int* __restrict__ blk_tile0,
+                                                     const int* __restrict__ tile_np,
                                                      const int* __restrict__ tile_j,
                                                      const unsigned long long* __restrict__ tile_mask,
                                                      const typename V4<R>::T* __restrict__ jrel,
@@ -405,12 +407,31 @@ __global__ __launch_bounds__(256) void k_block_tiles(int nb, const int* __restri
     if (tid < 3 * kBlock)
         s_ei[tid / kBlock][tid % kBlock] = (LT)0;
     __syncthreads();  // block i data and accumulators ready
-    // Each wave walks its own share of the block's tiles (tt = w, w + 4, ...); its tile
-    // buffers are private, so only wave-level ordering is needed between staging and use (LDS
-    // operations of a wave complete in order; the wave barrier keeps the compiler from moving
-    // them across).
-    for (int tt = w; tt < nt; tt += kWavesPerWG) {
+    // Each wave walks its own share of the block's tiles; its tile buffers are private, so only
+    // wave-level ordering is needed between staging and use (LDS operations of a wave complete
+    // in order; the wave barrier keeps the compiler from moving them across).  The share: in
+    // tile order, each tile goes to the wave with the least work so far (its pairs plus a fixed
+    // per-tile cost); every wave computes the same assignment.  The diagonal tile holds about
+    // three times the pairs of the others, so a plain round robin left one wave of every block
+    // with about twice the average work.
+    int load0 = 0, load1 = 0, load2 = 0, load3 = 0;
+    for (int tt = 0; tt < nt; ++tt) {
         const int t = t0 + tt;
+        {
+            const int cost = tile_np[t] + kTileCost;
+            int wm = 0, lm = load0;
+            wm = load1 < lm ? 1 : wm;
+            lm = min(lm, load1);
+            wm = load2 < lm ? 2 : wm;
+            lm = min(lm, load2);
+            wm = load3 < lm ? 3 : wm;
+            load0 += wm == 0 ? cost : 0;
+            load1 += wm == 1 ? cost : 0;
+            load2 += wm == 2 ? cost : 0;
+            load3 += wm == 3 ? cost : 0;
+            if (wm != w)
+                continue;
+        }
         const int sj = tile_j[(size_t)t * kBlock + lane];
         {
             const R4 jr = jrel[(size_t)t * kBlock + lane];
@@ -533,11 +554,11 @@ template <bool MI> static void mutual_tiles(amoeba_ctx* c, bool use_done, hipStr
     StageTimer tm(c, AMOEBA_T_REAL);
     if (c->mixed)
         hipLaunchKernelGGL((k_block_tiles<float, true, DipoleKind<float>, MI>), dim3(c->nb), dim3(256), 0, st,
-                           c->nb, c->blk_tile0, c->tile_j, c->tile_mask, c->jrel_f, c->off_f, c->par_f, c->pv_f,
+                           c->nb, c->blk_tile0, c->tile_np, c->tile_j, c->tile_mask, c->jrel_f, c->off_f, c->par_f, c->pv_f,
                            make_ewald<float>(c), c->eipart, (float*)c->jbuf, c->sc, (int)use_done);
     else
         hipLaunchKernelGGL((k_block_tiles<double, false, DipoleKind<double>, MI>), dim3(c->nb), dim3(256), 0, st,
-                           c->nb, c->blk_tile0, c->tile_j, c->tile_mask, c->jrel_d, c->off_d, c->par_d, c->pv_d,
+                           c->nb, c->blk_tile0, c->tile_np, c->tile_j, c->tile_mask, c->jrel_d, c->off_d, c->par_d, c->pv_d,
                            make_ewald<double>(c), c->eipart, (double*)c->jbuf, c->sc, (int)use_done);
 }
 
@@ -570,11 +591,11 @@ template <bool MI> static void perm_tiles(amoeba_ctx* c, hipStream_t st)
     StageTimer tm(c, AMOEBA_T_PERM);
     if (c->mixed)
         hipLaunchKernelGGL((k_block_tiles<float, true, MultipoleKind<float>, MI>), dim3(c->nb), dim3(256), 0,
-                           st, c->nb, c->blk_tile0, c->tile_j, c->tile_mask, c->jrel_f, c->off_f, c->par_f,
+                           st, c->nb, c->blk_tile0, c->tile_np, c->tile_j, c->tile_mask, c->jrel_f, c->off_f, c->par_f,
                            (const float4*)c->mp_f, make_ewald<float>(c), c->eipart, (float*)c->jbuf, c->sc, 0);
     else
         hipLaunchKernelGGL((k_block_tiles<double, false, MultipoleKind<double>, MI>), dim3(c->nb), dim3(256), 0,
-                           st, c->nb, c->blk_tile0, c->tile_j, c->tile_mask, c->jrel_d, c->off_d, c->par_d,
+                           st, c->nb, c->blk_tile0, c->tile_np, c->tile_j, c->tile_mask, c->jrel_d, c->off_d, c->par_d,
                            (const double4*)c->mp_d, make_ewald<double>(c), c->eipart, (double*)c->jbuf, c->sc, 0);
 }
 
