@@ -270,7 +270,7 @@ int prepare_config(amoeba_ctx* c, const double* pos);
 
 // realspace.hip
 void launch_mutual_tiles(amoeba_ctx* c, bool use_done, hipStream_t st = nullptr);  // null: context stream
-void launch_real_reduce(amoeba_ctx* c, double* ereal, hipStream_t st = nullptr);
+void launch_real_reduce(amoeba_ctx* c, double* ereal, hipStream_t st = nullptr, bool use_done = false);
 void launch_perm_tiles(amoeba_ctx* c, hipStream_t st = nullptr);
 void launch_perm_assemble(amoeba_ctx* c, double* out_slot);
 
@@ -288,7 +288,7 @@ int plane_bin_atoms(amoeba_ctx* c);
 void plane_dipole_field(amoeba_ctx* c, bool use_done, int parts);  // 1 spread, 2 the rest, 3 all
 void plane_perm_field(amoeba_ctx* c);                             // permanent multipoles, all passes
 void plane_gather(amoeba_ctx* c, double* out);          // E_rec from the plane shares
-int plane_combine(amoeba_ctx* c, bool use_done, bool dot_pq);  // PCG product; returns its partial count
+int plane_combine(amoeba_ctx* c, bool use_done, bool dot_pq, bool reduced);  // PCG product; returns its partial count
 bool pme_use_planes(const amoeba_ctx* c);
 void launch_gather(amoeba_ctx* c, double* out);       // E_rec at atoms from the potential grid
 
@@ -304,7 +304,7 @@ void guess_forward_slot(amoeba_ctx* c, double* mu_slot);
 // pcg.hip
 void launch_gather_vec(amoeba_ctx* c, const double* src_caller, double* dst_slot);
 void launch_scatter(amoeba_ctx* c, const double* v_slot, double* out_caller);
-void launch_matvec_combine(amoeba_ctx* c, bool use_done, bool dot_pq);
+void launch_matvec_combine(amoeba_ctx* c, bool use_done, bool dot_pq, bool reduced = false);  // reduced: E_real already in ereal
 void launch_set_direction(amoeba_ctx* c, const double* src);
 void launch_gather_vec_checked(amoeba_ctx* c, const double* src_caller, double* dst_slot); // + NaN flag
 int pcg_solve(amoeba_ctx* c, double tol, int max_iter, bool have_guess, double* mu_out, double* e_pol);

@@ -314,16 +314,18 @@ int matvec_slot(amoeba_ctx* c, bool use_done, bool dot, hipEvent_t fork_ev)
         plane_dipole_field(c, use_done, 1);
         hipStreamWaitEvent(c->stream2, fork_ev, 0);
         launch_mutual_tiles(c, use_done, c->stream2);
+        launch_real_reduce(c, c->ereal, c->stream2, use_done);   // E_real beside the reciprocal tail
         hipEventRecord(c->ev_join, c->stream2);
         plane_dipole_field(c, use_done, 2);
         hipStreamWaitEvent(c->stream, c->ev_join, 0);
-    } else {
-        launch_mutual_tiles(c, use_done, c->stream);
-        int rc = pme_dipole_field(c, use_done);
-        if (rc)
-            return rc;
+        launch_matvec_combine(c, use_done, dot, true);
+        return AMOEBA_OK;
     }
-    launch_matvec_combine(c, use_done, dot);
+    launch_mutual_tiles(c, use_done, c->stream);
+    int rc = pme_dipole_field(c, use_done);
+    if (rc)
+        return rc;
+    launch_matvec_combine(c, use_done, dot, false);
     return AMOEBA_OK;
 }
 

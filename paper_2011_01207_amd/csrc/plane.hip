@@ -40,7 +40,7 @@ template <> struct PlT<float> { using C = float2; using R4 = float4; };
 template <> struct PlT<double> { using C = double2; using R4 = double4; };
 
 constexpr int kPlThreads = 512;         // threads per workgroup of the row-chunk passes (spread, gather)
-constexpr int kPlColThreads = 512;      // threads per workgroup of the column passes (y and x lines)
+constexpr int kPlColThreads = 256;      // threads per workgroup of the column passes (y and x lines)
 constexpr int kPlMaxB = 1;              // butterflies per thread in one FFT round
 constexpr int kPlConv = 16;             // fixed-point values per thread in the conversion
 constexpr int kPlSplit = 4;             // split / combine items per thread in one round
@@ -734,8 +734,8 @@ __global__ __launch_bounds__(kPlThreads) void k_pme_z_gather(PlaneGeom g, PlaneD
 // Per-atom combine of the plane shares: E_rec = -(K/L) sum_t part[5 s + t] (fixed order).
 // MODE 0 writes E_rec (slot order, FP64).  MODE 1 assembles the PCG operator product
 // q = p / alpha - (E_real + E_rec + self p): the real-space field is the atom's block i-field
-// plus the tile j-fields listed in the reverse index, in index order; optionally the
-// workgroup's p.q partial.
+// plus the tile j-fields listed in the reverse index, in index order (or, MODE 2, the same sum
+// already in ereal); optionally the workgroup's p.q partial.
 template <typename R, int MODE>
 __global__ __launch_bounds__(256) void k_plane_combine(int npad, double3 kl, const int* __restrict__ perm,
                                                        const typename PlT<R>::R4* __restrict__ part,
@@ -744,7 +744,8 @@ __global__ __launch_bounds__(256) void k_plane_combine(int npad, double3 kl, con
                                                        const double* __restrict__ eipart,
                                                        const typename PlT<R>::R4* __restrict__ jbuf,
                                                        const int* __restrict__ rev_ptr,
-                                                       const int* __restrict__ rev_idx, double* __restrict__ out,
+                                                       const int* __restrict__ rev_idx,
+                                                       const double* __restrict__ ereal, double* __restrict__ out,
                                                        const PcgScalars* __restrict__ sc,
                                                        double* __restrict__ pq_part, int use_done, int dot)
 {
@@ -771,6 +772,15 @@ __global__ __launch_bounds__(256) void k_plane_combine(int npad, double3 kl, con
         if (MODE == 0) {
             for (int a = 0; a < 3; ++a)
                 out[3 * (size_t)s + a] = e[a];
+        } else if (perm[s] >= 0 && MODE == 2) {
+            const double ainv = par[s].y;
+            for (int a = 0; a < 3; ++a) {
+                const size_t i = 3 * (size_t)s + a;
+                const double pa = p[i];
+                const double qa = pa * ainv - (ereal[i] + e[a] + self * pa);
+                out[i] = qa;
+                pq[0] += pa * qa;
+            }
         } else if (perm[s] >= 0) {
             double er[3] = {eipart[3 * (size_t)s], eipart[3 * (size_t)s + 1], eipart[3 * (size_t)s + 2]};
             const int k1 = rev_ptr[s + 1];
@@ -1056,29 +1066,32 @@ void plane_gather(amoeba_ctx* c, double* out)
         hipLaunchKernelGGL((k_plane_combine<float, 0>), dim3(nblk(c->npad, 256)), dim3(256), 0, c->stream, c->npad,
                            kl, c->perm, (const float4*)c->rec_part, c->par_d, (const double*)nullptr, 0.0,
                            (const double*)nullptr, (const float4*)nullptr, (const int*)nullptr, (const int*)nullptr,
-                           out, c->sc, (double*)nullptr, 0, 0);
+                           (const double*)nullptr, out, c->sc, (double*)nullptr, 0, 0);
     else
         hipLaunchKernelGGL((k_plane_combine<double, 0>), dim3(nblk(c->npad, 256)), dim3(256), 0, c->stream,
                            c->npad, kl, c->perm, (const double4*)c->rec_part, c->par_d, (const double*)nullptr, 0.0,
                            (const double*)nullptr, (const double4*)nullptr, (const int*)nullptr,
-                           (const int*)nullptr, out, c->sc, (double*)nullptr, 0, 0);
+                           (const int*)nullptr, (const double*)nullptr, out, c->sc, (double*)nullptr, 0, 0);
 }
 
-int plane_combine(amoeba_ctx* c, bool use_done, bool dot_pq)
+int plane_combine(amoeba_ctx* c, bool use_done, bool dot_pq, bool reduced)
 {
     StageTimer tm(c, AMOEBA_T_GATHER);
     double3 kl = make_double3(c->K[0] / c->prm.box[0], c->K[1] / c->prm.box[1], c->K[2] / c->prm.box[2]);
     const double b = c->prm.ewald_alpha;
     const double self = 4.0 * b * b * b / (3.0 * sqrt(kPi));
     const int nwg = nblk(c->npad, 256);
-    if (c->mixed)
-        hipLaunchKernelGGL((k_plane_combine<float, 1>), dim3(nwg), dim3(256), 0, c->stream, c->npad, kl, c->perm,
-                           (const float4*)c->rec_part, c->par_d, c->v_p, self, c->eipart, (const float4*)c->jbuf,
-                           c->rev_ptr, c->rev_idx, c->v_q, c->sc, c->red.part, (int)use_done, (int)dot_pq);
-    else
-        hipLaunchKernelGGL((k_plane_combine<double, 1>), dim3(nwg), dim3(256), 0, c->stream, c->npad, kl, c->perm,
-                           (const double4*)c->rec_part, c->par_d, c->v_p, self, c->eipart, (const double4*)c->jbuf,
-                           c->rev_ptr, c->rev_idx, c->v_q, c->sc, c->red.part, (int)use_done, (int)dot_pq);
+    if (c->mixed) {
+        auto k = reduced ? k_plane_combine<float, 2> : k_plane_combine<float, 1>;
+        hipLaunchKernelGGL(k, dim3(nwg), dim3(256), 0, c->stream, c->npad, kl, c->perm, (const float4*)c->rec_part,
+                           c->par_d, c->v_p, self, c->eipart, (const float4*)c->jbuf, c->rev_ptr, c->rev_idx,
+                           c->ereal, c->v_q, c->sc, c->red.part, (int)use_done, (int)dot_pq);
+    } else {
+        auto k = reduced ? k_plane_combine<double, 2> : k_plane_combine<double, 1>;
+        hipLaunchKernelGGL(k, dim3(nwg), dim3(256), 0, c->stream, c->npad, kl, c->perm, (const double4*)c->rec_part,
+                           c->par_d, c->v_p, self, c->eipart, (const double4*)c->jbuf, c->rev_ptr, c->rev_idx,
+                           c->ereal, c->v_q, c->sc, c->red.part, (int)use_done, (int)dot_pq);
+    }
     return nwg;
 }
 

@@ -1008,10 +1008,10 @@ void launch_gather(amoeba_ctx* c, double* out)
                            (const int*)nullptr, (const int*)nullptr, out, c->sc, c->red.part, 0, 0);
 }
 
-void launch_matvec_combine(amoeba_ctx* c, bool use_done, bool dot_pq)
+void launch_matvec_combine(amoeba_ctx* c, bool use_done, bool dot_pq, bool reduced)
 {
     if (c->rec_plane) {
-        c->npq = plane_combine(c, use_done, dot_pq);
+        c->npq = plane_combine(c, use_done, dot_pq, reduced);
         return;
     }
     c->npq = c->nbricks;

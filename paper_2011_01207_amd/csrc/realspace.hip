@@ -526,18 +526,37 @@ __global__ __launch_bounds__(256) void k_block_tiles(int nb, const int* __restri
     }
 }
 
-// E_real[s] = eipart[s] + sum of the jbuf slots of s in the reverse index (fixed order).
+// E_real[s] = eipart[s] + sum of the jbuf slots of s in the reverse index (fixed order; four
+// loads in flight, added in index order).
 template <typename R>
 __global__ void k_real_reduce(int npad, const double* __restrict__ eipart, const R* __restrict__ jbuf,
                               const int* __restrict__ rev_ptr, const int* __restrict__ rev_idx,
-                              double* __restrict__ ereal)
+                              double* __restrict__ ereal, const PcgScalars* __restrict__ sc, int use_done)
 {
+    using R4 = typename V4<R>::T;
+    if (use_done && sc->done)
+        return;
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= npad)
         return;
     double e0 = eipart[3 * (size_t)s], e1 = eipart[3 * (size_t)s + 1], e2 = eipart[3 * (size_t)s + 2];
-    for (int k = rev_ptr[s]; k < rev_ptr[s + 1]; ++k) {
-        const typename V4<R>::T v = reinterpret_cast<const typename V4<R>::T*>(jbuf)[rev_idx[k]];
+    const R4* jb = reinterpret_cast<const R4*>(jbuf);
+    const int k1 = rev_ptr[s + 1];
+    int k = rev_ptr[s];
+    for (; k + 4 <= k1; k += 4) {
+        R4 v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            v[u] = jb[rev_idx[k + u]];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            e0 += (double)v[u].x;
+            e1 += (double)v[u].y;
+            e2 += (double)v[u].z;
+        }
+    }
+    for (; k < k1; ++k) {
+        const R4 v = jb[rev_idx[k]];
         e0 += (double)v.x;
         e1 += (double)v.y;
         e2 += (double)v.z;
@@ -572,16 +591,16 @@ void launch_mutual_tiles(amoeba_ctx* c, bool use_done, hipStream_t st)
         mutual_tiles<true>(c, use_done, st);
 }
 
-void launch_real_reduce(amoeba_ctx* c, double* ereal, hipStream_t st)
+void launch_real_reduce(amoeba_ctx* c, double* ereal, hipStream_t st, bool use_done)
 {
     if (!st)
         st = c->stream;
     if (c->mixed)
         hipLaunchKernelGGL(k_real_reduce<float>, dim3((c->npad + 255) / 256), dim3(256), 0, st, c->npad,
-                           c->eipart, (const float*)c->jbuf, c->rev_ptr, c->rev_idx, ereal);
+                           c->eipart, (const float*)c->jbuf, c->rev_ptr, c->rev_idx, ereal, c->sc, (int)use_done);
     else
         hipLaunchKernelGGL(k_real_reduce<double>, dim3((c->npad + 255) / 256), dim3(256), 0, st, c->npad,
-                           c->eipart, (const double*)c->jbuf, c->rev_ptr, c->rev_idx, ereal);
+                           c->eipart, (const double*)c->jbuf, c->rev_ptr, c->rev_idx, ereal, c->sc, (int)use_done);
 }
 
 template <bool MI> static void perm_tiles(amoeba_ctx* c, hipStream_t st)
