@@ -150,28 +150,58 @@ __global__ void k_params(int npad, const int* __restrict__ perm, const double* _
 // Single-workgroup exclusive scan: out[i] = sum_{k<i} in[i], out[n] = total.
 __global__ __launch_bounds__(1024) void k_scan_excl(int n, const int* __restrict__ in, int* __restrict__ out)
 {
-    __shared__ int part[1024];
-    int t = threadIdx.x;
-    int chunk = (n + 1023) / 1024;
-    int b = t * chunk, e = min(n, b + chunk);
-    int s = 0;
-    for (int i = b; i < e; ++i)
-        s += in[i];
-    part[t] = s;
-    __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-        int v = t >= off ? part[t - off] : 0;
+    // tiles of 4096: four consecutive values per thread (coalesced), a wave scan by shuffles,
+    // the sixteen wave totals scanned by wave 0, and the running total carried across tiles
+    __shared__ int wsum[16];
+    __shared__ int carry_s;
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    int carry = 0;
+    for (int base = 0; base < n; base += 4096) {
+        int v[4], s = 0;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int i = base + 4 * t + u;
+            v[u] = i < n ? in[i] : 0;
+            s += v[u];
+        }
+        int incl = s;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const int y = __shfl_up(incl, d);
+            if (lane >= d)
+                incl += y;
+        }
+        if (lane == 63)
+            wsum[w] = incl;
         __syncthreads();
-        part[t] += v;
+        if (w == 0) {
+            const int x = lane < 16 ? wsum[lane] : 0;
+            int wi = x;
+#pragma unroll
+            for (int d = 1; d < 16; d <<= 1) {
+                const int y = __shfl_up(wi, d);
+                if (lane >= d)
+                    wi += y;
+            }
+            if (lane < 16)
+                wsum[lane] = wi - x;   // exclusive over waves
+            if (lane == 15)
+                carry_s = wi;          // tile total
+        }
         __syncthreads();
+        int run = carry + wsum[w] + incl - s;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int i = base + 4 * t + u;
+            if (i < n)
+                out[i] = run;
+            run += v[u];
+        }
+        carry += carry_s;
+        __syncthreads();   // wsum and carry_s are rewritten by the next tile
     }
-    int run = t ? part[t - 1] : 0;
-    for (int i = b; i < e; ++i) {
-        out[i] = run;
-        run += in[i];
-    }
-    if (t == 1023)
-        out[n] = part[1023];
+    if (t == 0)
+        out[n] = carry;
 }
 
 __global__ void k_csr_counts(int npad, const int* __restrict__ perm, const int* __restrict__ ptr_in,
@@ -555,12 +585,33 @@ __global__ void k_rev_fill(int ntiles, const int* __restrict__ tile_blk, const i
         rev_idx[rev_ptr[sj] + atomicAdd(&cursor[sj], 1)] = t * kBlock + k;
 }
 
-__global__ void k_rev_sort(int npad, const int* __restrict__ rev_ptr, int* __restrict__ rev_idx)
+// Each slot's reverse entries in increasing order: up to kRevLds entries sorted in LDS (one
+// thread per slot, its own region), longer lists in place in global memory.
+constexpr int kRevLds = 32;
+
+__global__ __launch_bounds__(256) void k_rev_sort(int npad, const int* __restrict__ rev_ptr, int* __restrict__ rev_idx)
 {
-    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    __shared__ int buf[kRevLds][256];   // column per thread: conflict-free
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= npad)
         return;
-    int lo = rev_ptr[s], hi = rev_ptr[s + 1];
+    const int lo = rev_ptr[s], hi = rev_ptr[s + 1], m = hi - lo;
+    if (m <= kRevLds) {
+        for (int i = 0; i < m; ++i)
+            buf[i][threadIdx.x] = rev_idx[lo + i];
+        for (int i = 1; i < m; ++i) {
+            const int v = buf[i][threadIdx.x];
+            int j = i - 1;
+            while (j >= 0 && buf[j][threadIdx.x] > v) {
+                buf[j + 1][threadIdx.x] = buf[j][threadIdx.x];
+                --j;
+            }
+            buf[j + 1][threadIdx.x] = v;
+        }
+        for (int i = 0; i < m; ++i)
+            rev_idx[lo + i] = buf[i][threadIdx.x];
+        return;
+    }
     for (int i = lo + 1; i < hi; ++i) {
         int v = rev_idx[i];
         int j = i - 1;
