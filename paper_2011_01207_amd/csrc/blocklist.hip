@@ -627,6 +627,10 @@ __global__ __launch_bounds__(256) void k_rev_sort(int npad, const int* __restric
 // relative to the i-block origin.  The diagonal tile keeps only k > i.  Each pair is first
 // classified from FP32 offsets; only pairs within a relative 1e-5 of rc^2 (far above the FP32
 // error of the offsets) are decided by the FP64 distance, so every bit equals the FP64 test.
+// MI: minimum image per pair offset; without it the block-relative offsets are used as they are
+// (valid when the list build proved that no tile offset can reach half the box, as for the
+// pair kernels).
+template <bool MI>
 __global__ __launch_bounds__(256) void k_tile_refresh(int ntiles, const int* __restrict__ tile_blk,
                                                       const int* __restrict__ tile_j,
                                                       const int* __restrict__ perm,
@@ -675,9 +679,11 @@ __global__ __launch_bounds__(256) void k_tile_refresh(int ntiles, const int* __r
             for (int k = 0; k < kBlock; ++k) {
                 const float4 q = s_jf[w][k];
                 float dx = oi.x - q.x, dy = oi.y - q.y, dz = oi.z - q.z;
-                dx -= Lx * rintf(dx * Lix);
-                dy -= Ly * rintf(dy * Liy);
-                dz -= Lz * rintf(dz * Liz);
+                if (MI) {
+                    dx -= Lx * rintf(dx * Lix);
+                    dy -= Ly * rintf(dy * Liy);
+                    dz -= Lz * rintf(dz * Liz);
+                }
                 const float r2 = dx * dx + dy * dy + dz * dz;
                 const bool use = k >= k0 && q.w != 0.0f;
                 bool in = use && r2 < lo2;
@@ -775,7 +781,8 @@ static int refresh_tiles(amoeba_ctx* c)
                        c->blk_org, c->off_d, c->off_f);
     double3 binv = make_double3(1.0 / box.x, 1.0 / box.y, 1.0 / box.z);
     const int nwg = nblk((long)c->ntiles * kBlock, 256);
-    hipLaunchKernelGGL(k_tile_refresh, dim3(nwg), dim3(256), 0, st, c->ntiles, c->tile_blk, c->tile_j, c->perm,
+    hipLaunchKernelGGL(c->skip_mimg ? k_tile_refresh<false> : k_tile_refresh<true>, dim3(nwg), dim3(256), 0, st,
+                       c->ntiles, c->tile_blk, c->tile_j, c->perm,
                        c->pos_s, c->blk_org, c->off_f, box, binv, c->prm.cutoff * c->prm.cutoff, c->tile_mask,
                        c->jrel_d, c->jrel_f, c->tile_np, c->pair_part);
     hipLaunchKernelGGL(k_sum_pairs, dim3(1), dim3(256), 0, st, nwg, c->pair_part, c->counter);
