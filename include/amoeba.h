@@ -75,9 +75,9 @@ typedef enum amoeba_guess_mode {
                                   mu_guess is NULL)                                           */
 } amoeba_guess_mode;
 
-/* How the reciprocal dipole field of the PCG product is computed (paper, "Reciprocal space
- * scheme"; the permanent-multipole field always uses the brick path).  Both give the same
- * field up to rounding. */
+/* How the reciprocal field is computed (paper, "Reciprocal space scheme"), for the induced
+ * dipoles of the PCG product and for the permanent multipoles.  Both give the same field up to
+ * rounding. */
 typedef enum amoeba_pme_path {
     AMOEBA_PME_AUTO = 0,    /* planes when the grid fits, else bricks                          */
     AMOEBA_PME_PLANES = 1,  /* x-planes held in LDS: spread and y-z FFT fused, x-line FFT with
@@ -86,6 +86,26 @@ typedef enum amoeba_pme_path {
                                ceil(K1/2) x 2(K2/2+1) complex FP64 values within 150 KB       */
     AMOEBA_PME_BRICKS = 2   /* 8^3-point brick spread and gather around rocFFT r2c / c2r      */
 } amoeba_pme_path;
+
+/* How the real-space dipole product gets the radial coefficients B1', B2' of its in-cutoff
+ * pairs (paper, PCG section: the option of computing and storing the real-space matrix elements
+ * once before iterating).  The coefficients with the pair displacement give the interaction
+ * tensor, -B1' I + B2' r r^T.  Both use bitwise the same coefficients, so that mixed-precision
+ * products (exact fixed-point sums) are bitwise equal; FP64 products agree to the rounding of
+ * their FP64 sums. */
+typedef enum amoeba_pair_store {
+    AMOEBA_PAIRS_AUTO = 0,     /* STORED in FP64, where the pair functions cost more than reading
+                                  the coefficients back; COMPUTE in mixed precision, where the
+                                  FP32 tiles are bound by LDS traffic that the store leaves as
+                                  it is                                                         */
+    AMOEBA_PAIRS_COMPUTE = 1,  /* every product evaluates erfc, the Thole damping and the powers
+                                  of 1/r for every pair                                          */
+    AMOEBA_PAIRS_STORED = 2    /* the first product after a new configuration (or new atom
+                                  parameters) stores B1', B2' per pair (8 bytes per pair mixed, 16
+                                  FP64); later products read them back and rebuild only the
+                                  displacement.  Falls back to COMPUTE, per tile, where the store
+                                  does not fit the workspace cap                                */
+} amoeba_pair_store;
 
 typedef struct amoeba_params {
     int32_t n_atoms;       /* N >= 1                                                          */
@@ -119,6 +139,9 @@ typedef struct amoeba_info {
                                   the list build proved block-relative offsets already give it
                                   (cutoff + 3 buffer + 4 x largest block half-extent < box/2) */
     int32_t pme_planes;        /* 1 if the PCG products use the plane path (amoeba_pme_path)  */
+    int32_t pair_store;        /* 1 if the dipole products replay stored pair coefficients
+                                  (amoeba_pair_store)                                           */
+    int64_t pair_store_bytes;  /* device memory held by the stored coefficients                 */
 } amoeba_info;
 
 /* Create a context for one system size and one parameter set on the current HIP device,
@@ -262,6 +285,10 @@ int amoeba_guess_predict(amoeba_ctx* ctx, const double* pos, const double* e_per
  * AMOEBA_PME_PLANES on a grid that does not fit: AMOEBA_E_INVALID, the setting is unchanged.
  * The default is AMOEBA_PME_AUTO. */
 int amoeba_set_pme_path(amoeba_ctx* ctx, int32_t path);
+
+/* Select how the real-space dipole product gets its pair coefficients (amoeba_pair_store) for
+ * later products; an unknown value: AMOEBA_E_INVALID.  The default is AMOEBA_PAIRS_AUTO. */
+int amoeba_set_pair_store(amoeba_ctx* ctx, int32_t mode);
 
 /* Sizes and counters of the context (host struct). */
 int amoeba_get_info(const amoeba_ctx* ctx, amoeba_info* out);

@@ -38,6 +38,7 @@ AMOEBA_PME_AUTO = 0
 AMOEBA_PME_PLANES = 1
 AMOEBA_PME_BRICKS = 2
 PME_PATHS = {"auto": 0, "planes": 1, "bricks": 2}
+PAIR_STORE = {"auto": 0, "compute": 1, "stored": 2}
 
 GUESS_NFEAT = 11
 GUESS_NBASIS = 3
@@ -59,7 +60,9 @@ class amoeba_info(ctypes.Structure):
                 ("last_iterations", ctypes.c_int32), ("last_rms_debye", ctypes.c_double),
                 ("last_guess", ctypes.c_int32), ("guess_loaded", ctypes.c_int32),
                 ("last_guess_rms_debye", ctypes.c_double * 2), ("pair_min_image", ctypes.c_int32),
-                ("pme_planes", ctypes.c_int32)]
+                ("pme_planes", ctypes.c_int32),
+                ("pair_store", ctypes.c_int32),
+                ("pair_store_bytes", ctypes.c_int64)]
 
 
 class amoeba_timing(ctypes.Structure):
@@ -111,6 +114,7 @@ def lib() -> ctypes.CDLL:
                                               ctypes.POINTER(ctypes.c_double)]
         L.amoeba_guess_predict.argtypes = [_P, _P, _P, _P]
         L.amoeba_set_pme_path.argtypes = [_P, ctypes.c_int32]
+        L.amoeba_set_pair_store.argtypes = [_P, ctypes.c_int32]
         L.amoeba_set_timing.argtypes = [_P, ctypes.c_int]
         L.amoeba_get_timing.argtypes = [_P, ctypes.POINTER(amoeba_timing)]
         _lib = L
@@ -235,6 +239,10 @@ class Context:
     def set_pme_path(self, path):
         """path: "auto", "planes" or "bricks" (or the AMOEBA_PME_* value)."""
         self._check(lib().amoeba_set_pme_path(self.h, PME_PATHS[path] if isinstance(path, str) else int(path)))
+
+    def set_pair_store(self, mode):
+        """mode: "auto", "compute" or "stored" (or the AMOEBA_PAIRS_* value)."""
+        self._check(lib().amoeba_set_pair_store(self.h, PAIR_STORE[mode] if isinstance(mode, str) else int(mode)))
 
     def info(self) -> dict:
         inf = amoeba_info()

@@ -51,6 +51,9 @@ int ctx_alloc(amoeba_ctx* c, void** p, size_t bytes)
 {
     if (bytes == 0)
         bytes = 16;
+    // the stored pair coefficients are optional: they give way to any other allocation
+    if (c->prm.max_workspace_bytes > 0 && c->ws_bytes + (int64_t)bytes > c->prm.max_workspace_bytes && c->coef)
+        coef_release(c);
     if (c->prm.max_workspace_bytes > 0 && c->ws_bytes + (int64_t)bytes > c->prm.max_workspace_bytes)
         return set_error(c, AMOEBA_E_NOMEM, "device workspace would exceed max_workspace_bytes (" +
                                                 std::to_string(c->ws_bytes + (int64_t)bytes) + " > " +
@@ -386,6 +389,7 @@ int amoeba_destroy(amoeba_ctx* c)
         rocfft_execution_info_destroy(c->exec_bwd);
     if (c->flags_host)
         hipHostFree(c->flags_host);
+    coef_release(c);
     if (c->g_scal_host)
         hipHostFree(c->g_scal_host);
     for (auto& e : c->ev)
@@ -705,6 +709,16 @@ int amoeba_set_pme_path(amoeba_ctx* c, int32_t path)
     return AMOEBA_OK;
 }
 
+int amoeba_set_pair_store(amoeba_ctx* c, int32_t mode)
+{
+    if (!c)
+        return AMOEBA_E_INVALID;
+    if (mode != AMOEBA_PAIRS_AUTO && mode != AMOEBA_PAIRS_COMPUTE && mode != AMOEBA_PAIRS_STORED)
+        return set_error(c, AMOEBA_E_INVALID, "amoeba_set_pair_store: unknown mode");
+    c->pair_store = mode;
+    return AMOEBA_OK;
+}
+
 int amoeba_get_info(const amoeba_ctx* cc, amoeba_info* out)
 {
     if (!cc || !out)
@@ -733,6 +747,8 @@ int amoeba_get_info(const amoeba_ctx* cc, amoeba_info* out)
     out->last_guess_rms_debye[1] = c->last_guess_rms[1];
     out->pair_min_image = c->skip_mimg ? 0 : 1;
     out->pme_planes = c->plane_ok && c->pme_path != AMOEBA_PME_BRICKS ? 1 : 0;
+    out->pair_store = c->coef_last_stored ? 1 : 0;
+    out->pair_store_bytes = c->coef_bytes;
     return AMOEBA_OK;
 }
 

@@ -639,7 +639,7 @@ __global__ __launch_bounds__(256) void k_tile_refresh(int ntiles, const int* __r
                                                       const float4* __restrict__ off_f, double3 box, double3 binv,
                                                       double rc2, unsigned long long* __restrict__ mask,
                                                       double4* __restrict__ jrel_d, float4* __restrict__ jrel_f,
-                                                      int* __restrict__ tile_np,
+                                                      int* __restrict__ tile_np, int* __restrict__ tile_rows,
                                                       unsigned long long* __restrict__ pair_part)
 {
     __shared__ double4 s_jd[4][kBlock];
@@ -705,8 +705,10 @@ __global__ __launch_bounds__(256) void k_tile_refresh(int ntiles, const int* __r
         cnt += __shfl_xor(cnt, off);
     if (lane == 0) {
         s_cnt[w] = cnt;
-        if (act)
-            tile_np[t] = (int)cnt;  // the pair kernels balance their waves by it
+        if (act) {
+            tile_np[t] = (int)cnt;                 // the pair kernels balance their waves by it
+            tile_rows[t] = (int)((cnt + 63) >> 6);  // rows of the tile's stored coefficients
+        }
     }
     __syncthreads();
     if (threadIdx.x == 0)
@@ -755,6 +757,7 @@ int device_scan(amoeba_ctx* c, int n, const int* in, int* out)
 int sort_params(amoeba_ctx* c)
 {
     hipStream_t st = c->stream;
+    coef_invalidate(c);  // the coefficients depend on the polarizabilities and Thole factors
     hipLaunchKernelGGL(k_params, dim3(nblk(c->npad, 256)), dim3(256), 0, st, c->npad, c->perm, c->alpha_in,
                        c->thole_in, c->par_d, c->par_f);
     // scaled-pair CSR in slot order
@@ -784,9 +787,18 @@ static int refresh_tiles(amoeba_ctx* c)
     hipLaunchKernelGGL(c->skip_mimg ? k_tile_refresh<false> : k_tile_refresh<true>, dim3(nwg), dim3(256), 0, st,
                        c->ntiles, c->tile_blk, c->tile_j, c->perm,
                        c->pos_s, c->blk_org, c->off_f, box, binv, c->prm.cutoff * c->prm.cutoff, c->tile_mask,
-                       c->jrel_d, c->jrel_f, c->tile_np, c->pair_part);
+                       c->jrel_d, c->jrel_f, c->tile_np, c->tile_rows, c->pair_part);
     hipLaunchKernelGGL(k_sum_pairs, dim3(1), dim3(256), 0, st, nwg, c->pair_part, c->counter);
     c->pairs_pending = true;
+    // rows of the stored pair coefficients; their total reaches the host with its next wait
+    coef_invalidate(c);
+    c->coef_rows_ok = false;
+    const bool scan_fits = c->ntiles <= 65536 || nblk(c->ntiles, 1024) + 1 <= c->npad / 1024 + 2;
+    if (c->ntiles > 0 && scan_fits && device_scan(c, c->ntiles, c->tile_rows, c->coef_row0) == AMOEBA_OK) {
+        hipMemcpyAsync(c->flags_host + 10, c->coef_row0 + c->ntiles, sizeof(int), hipMemcpyDeviceToHost, st);
+        c->coef_rows_ok = true;
+        c->coef_rows_pending = true;
+    }
     pme_bin_atoms(c);
     return AMOEBA_OK;
 }
@@ -891,6 +903,8 @@ int build_blocklist(amoeba_ctx* c, const double* pos)
             (rc = ctx_alloc(c, (void**)&c->tile_j, sizeof(int) * tb)) ||
             (rc = ctx_alloc(c, (void**)&c->tile_mask, sizeof(unsigned long long) * tb)) ||
             (rc = ctx_alloc(c, (void**)&c->tile_np, sizeof(int) * total)) ||
+            (rc = ctx_alloc(c, (void**)&c->tile_rows, sizeof(int) * total)) ||
+            (rc = ctx_alloc(c, (void**)&c->coef_row0, sizeof(int) * (total + 1))) ||
             (c->mixed && (rc = ctx_alloc(c, (void**)&c->jrel_f, sizeof(float4) * tb))) ||
             (!c->mixed && (rc = ctx_alloc(c, (void**)&c->jrel_d, sizeof(double4) * tb))) ||
             (rc = ctx_alloc(c, &c->jbuf, rs * 4 * tb)) ||
@@ -932,6 +946,7 @@ int prepare_config(amoeba_ctx* c, const double* pos)
     int rc = hip_check(c, hipStreamSynchronize(st), "prepare_config");
     if (rc)
         return rc;
+    coef_reserve(c);
     int f = c->flags_host[0];
     if (f & kFlagNonFinite) {
         c->cfg_valid = false;

@@ -137,6 +137,8 @@ struct amoeba_ctx {
     int32_t* tile_j = nullptr;     // [ntiles*64] j slot or -1
     unsigned long long* tile_mask = nullptr; // [ntiles*64] bit k of row i: pair (i, j_k) within rc
     int32_t* tile_np = nullptr;    // [ntiles] in-cutoff pairs of each tile (per configuration)
+    int32_t* tile_rows = nullptr;  // [ntiles] ceil(tile_np / 64): rows of 64 stored pair coefficients
+    int32_t* coef_row0 = nullptr;  // [ntiles+1] first stored-coefficient row of each tile (exclusive scan)
     double4* jrel_d = nullptr;     // [ntiles*64] j position relative to the i-block origin
     float4* jrel_f = nullptr;
     int32_t* blk_tile0 = nullptr;  // [nb+1] first tile of each block row
@@ -175,6 +177,16 @@ struct amoeba_ctx {
 
     // real-space field pieces and vectors (slot order, FP64 N x 3 unless noted)
     double* eipart = nullptr;              // [npad*3] field at i summed over its own block's tiles
+    // stored radial coefficients (B1', B2') of every in-cutoff pair: recorded by the first dipole
+    // product of a configuration, replayed by the later ones; row r, lane l at r*64 + l (R2)
+    int pair_store = 0;                    // amoeba_pair_store requested by the caller
+    void* coef = nullptr;                  // [coef_cap_rows*64] (R2)
+    int64_t coef_cap_rows = 0;
+    int64_t coef_bytes = 0;
+    bool coef_ready = false;               // coef holds the current configuration's coefficients
+    bool coef_rows_ok = false;             // coef_row0 holds the current tiles' rows
+    bool coef_rows_pending = false;        // flags_host[10] receives the row total of the last refresh
+    bool coef_last_stored = false;         // the last dipole product stored or replayed every tile
     void* jbuf = nullptr;                  // [tile_cap*64][4] (R) j-field (x, y, z, 0) of every off-diagonal tile slot
     int32_t* rev_ptr = nullptr;            // [npad+1] reverse index: jbuf slots where an atom is j
     int32_t* rev_idx = nullptr;            // [rev_cap] entries tile*64 + lane
@@ -270,6 +282,10 @@ int prepare_config(amoeba_ctx* c, const double* pos);
 
 // realspace.hip
 void launch_mutual_tiles(amoeba_ctx* c, bool use_done, hipStream_t st = nullptr);  // null: context stream
+void coef_invalidate(amoeba_ctx* c);      // pair coefficients must be recorded again
+int coef_reserve(amoeba_ctx* c);          // size the coefficient store (host has synchronized)
+void coef_release(amoeba_ctx* c);         // free it (other allocations come first under the cap)
+bool coef_store_on(const amoeba_ctx* c);  // the requested mode uses the store
 void launch_real_reduce(amoeba_ctx* c, double* ereal, hipStream_t st = nullptr, bool use_done = false);
 void launch_perm_tiles(amoeba_ctx* c, hipStream_t st = nullptr);
 void launch_perm_assemble(amoeba_ctx* c, double* out_slot);

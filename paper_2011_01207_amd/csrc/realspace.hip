@@ -27,6 +27,8 @@
 //   dipole field at i from mu_j:  -B1' mu_j + B2' (mu_j.r) r           (r = r_i - r_j)
 //   multipole field at i from j:   q_j B1' r - B1' d_j + B2' (d_j.r) r
 //                                  + (1/3) B3' (Theta_j:rr) r - (2/3) B2' Theta_j r
+#include <algorithm>
+
 #include "common.h"
 
 namespace amoeba {
@@ -34,6 +36,9 @@ namespace amoeba {
 template <typename R> struct V4;
 template <> struct V4<float> { using T = float4; };
 template <> struct V4<double> { using T = double4; };
+template <typename R> struct V2;
+template <> struct V2<float> { using T = float2; };
+template <> struct V2<double> { using T = double2; };
 
 template <typename R> struct EwaldArgs {
     R beta, beta2, g, t, t2;  // beta, beta^2, 2 beta/sqrt(pi), 2 beta^2, (2 beta^2)^2
@@ -92,6 +97,11 @@ __device__ __forceinline__ double d_rint(double x) { return rint(x); }
 
 constexpr int kWavesPerWG = 4;
 constexpr int kTileCost = 128;  // per-tile cost of staging and scanning, in units of pairs
+
+// How a dipole tile gets the radial coefficients of its pairs (the paper's option of storing the
+// real-space matrix elements before the PCG iterations): evaluate them, evaluate and store them,
+// or read the stored ones back.
+enum CoefMode { kCoefCompute = 0, kCoefRecord = 1, kCoefReplay = 2 };
 
 // LDS field accumulators: fixed point with 40 fraction bits held as integer-valued FP64
 // (mixed; see fixd) or plain FP64.
@@ -241,6 +251,23 @@ __device__ __forceinline__ void close_pair_series(R r2, R r, R rinv, R a, R w, c
         b3p = be5 * ew.beta2 * horner(kD3, x2) + (R)15 * A * A * ps7 * rinv;
 }
 
+// Displacement r_i - r_j of a pair from the two block-relative offsets (minimum image when MI).
+// The stored-coefficient replay rebuilds it with this same code, so that it is bitwise the
+// displacement the coefficients were recorded with.
+template <typename R, bool MI>
+__device__ __forceinline__ void pair_disp(const typename V4<R>::T& ip, const typename V4<R>::T& jp,
+                                          const EwaldArgs<R>& ew, R& dx, R& dy, R& dz)
+{
+    dx = ip.x - jp.x;
+    dy = ip.y - jp.y;
+    dz = ip.z - jp.z;
+    if (MI) {
+        dx -= ew.L[0] * d_rint(dx * ew.Linv[0]);
+        dy -= ew.L[1] * d_rint(dy * ew.Linv[1]);
+        dz -= ew.L[2] * d_rint(dz * ew.Linv[2]);
+    }
+}
+
 // Radial functions of a pair: B1', B2' (and B3' when THIRD), minimum-image displacement.
 // MI = false skips the minimum image: the host enables that only when block extents, cutoff
 // and buffer bound every tile displacement below half the box, so that the difference of the
@@ -250,14 +277,7 @@ template <typename R, bool THIRD, bool MI> struct PairGeom {
     __device__ __forceinline__ PairGeom(const typename V4<R>::T& ip, const typename V4<R>::T& jp, R ai, R aj,
                                         const EwaldArgs<R>& ew)
     {
-        dx = ip.x - jp.x;
-        dy = ip.y - jp.y;
-        dz = ip.z - jp.z;
-        if (MI) {
-            dx -= ew.L[0] * d_rint(dx * ew.Linv[0]);
-            dy -= ew.L[1] * d_rint(dy * ew.Linv[1]);
-            dz -= ew.L[2] * d_rint(dz * ew.Linv[2]);
-        }
+        pair_disp<R, MI>(ip, jp, ew, dx, dy, dz);
         const R r2 = dx * dx + dy * dy + dz * dz;
         const R rinv = d_rsqrt(r2);
         const R r = r2 * rinv;
@@ -301,20 +321,45 @@ template <typename R> struct DipoleKind {
         R4 m = src[s];
         d[0] = R4{m.x, m.y, m.z, a};
     }
+    using C = typename V2<R>::T;  // stored radial coefficients (B1', B2')
+    // the field of the pair from its displacement and radial coefficients
+    __device__ static __forceinline__ void apply(R dx, R dy, R dz, R b1p, R b2p, const R4* di, const R4* dj, R* ei,
+                                                 R* ej)
+    {
+        const R mjd = dj[0].x * dx + dj[0].y * dy + dj[0].z * dz;
+        const R mid = di[0].x * dx + di[0].y * dy + di[0].z * dz;
+        const R tj = b2p * mjd;
+        ei[0] = fma_r(tj, dx, fma_r(-b1p, dj[0].x, ei[0]));
+        ei[1] = fma_r(tj, dy, fma_r(-b1p, dj[0].y, ei[1]));
+        ei[2] = fma_r(tj, dz, fma_r(-b1p, dj[0].z, ei[2]));
+        ej[0] = -b1p * di[0].x + b2p * mid * dx;
+        ej[1] = -b1p * di[0].y + b2p * mid * dy;
+        ej[2] = -b1p * di[0].z + b2p * mid * dz;
+    }
     template <bool MI>
     __device__ static void pair(const R4& ip, const R4* di, const R4& jp, const R4* dj, const EwaldArgs<R>& ew,
                                 R* ei, R* ej)
     {
         PairGeom<R, false, MI> g(ip, jp, di[0].w, dj[0].w, ew);
-        const R mjd = dj[0].x * g.dx + dj[0].y * g.dy + dj[0].z * g.dz;
-        const R mid = di[0].x * g.dx + di[0].y * g.dy + di[0].z * g.dz;
-        const R tj = g.b2p * mjd;
-        ei[0] = fma_r(tj, g.dx, fma_r(-g.b1p, dj[0].x, ei[0]));
-        ei[1] = fma_r(tj, g.dy, fma_r(-g.b1p, dj[0].y, ei[1]));
-        ei[2] = fma_r(tj, g.dz, fma_r(-g.b1p, dj[0].z, ei[2]));
-        ej[0] = -g.b1p * di[0].x + g.b2p * mid * g.dx;
-        ej[1] = -g.b1p * di[0].y + g.b2p * mid * g.dy;
-        ej[2] = -g.b1p * di[0].z + g.b2p * mid * g.dz;
+        apply(g.dx, g.dy, g.dz, g.b1p, g.b2p, di, dj, ei, ej);
+    }
+    // same, also returning the coefficients for the store
+    template <bool MI>
+    __device__ static void pair_record(const R4& ip, const R4* di, const R4& jp, const R4* dj,
+                                       const EwaldArgs<R>& ew, R* ei, R* ej, C& cf)
+    {
+        PairGeom<R, false, MI> g(ip, jp, di[0].w, dj[0].w, ew);
+        cf = C{g.b1p, g.b2p};
+        apply(g.dx, g.dy, g.dz, g.b1p, g.b2p, di, dj, ei, ej);
+    }
+    // same from stored coefficients: only the displacement is rebuilt
+    template <bool MI>
+    __device__ static void pair_stored(const R4& ip, const R4* di, const R4& jp, const R4* dj,
+                                       const EwaldArgs<R>& ew, const C& cf, R* ei, R* ej)
+    {
+        R dx, dy, dz;
+        pair_disp<R, MI>(ip, jp, ew, dx, dy, dz);
+        apply(dx, dy, dz, cf.x, cf.y, di, dj, ei, ej);
     }
 };
 
@@ -365,8 +410,13 @@ template <typename R> struct MultipoleKind {
 // ------------------------------------------------------------------------------------------
 // K3 / K3p: one workgroup per i-block over all the block's tiles.
 // jbuf layout: [tile * 64 + lane] (x, y, z, 0) (R);  eipart: [slot][3] (FP64).
+// Stored coefficients (CM != kCoefCompute, dipoles only): tile t owns rows coef_row0[t] ..
+// coef_row0[t+1]-1 of 64 (B1', B2') each, one row per step of the lanes' pair walk: the pair a
+// lane evaluates at step s of its share sits at (coef_row0[t] + s) * 64 + lane, so each step's
+// loads and stores are one contiguous row.  A tile whose rows end beyond coef_cap_rows is
+// evaluated as with kCoefCompute (the store did not fit); record and replay agree on which.
 // ------------------------------------------------------------------------------------------
-template <typename R, bool FIX, class K, bool MI>
+template <typename R, bool FIX, class K, bool MI, int CM = kCoefCompute>
 __global__ __launch_bounds__(256) void k_block_tiles(int nb, const int* __restrict__ blk_tile0,
                                                      const int* __restrict__ tile_np,
                                                      const int* __restrict__ tile_j,
@@ -376,9 +426,12 @@ __global__ __launch_bounds__(256) void k_block_tiles(int nb, const int* __restri
                                                      const typename V4<R>::T* __restrict__ par,
                                                      const typename V4<R>::T* __restrict__ src, EwaldArgs<R> ew,
                                                      double* __restrict__ eipart, R* __restrict__ jbuf,
-                                                     const PcgScalars* __restrict__ sc, int use_done)
+                                                     const PcgScalars* __restrict__ sc, int use_done,
+                                                     const int* __restrict__ coef_row0, long long coef_cap_rows,
+                                                     typename V2<R>::T* __restrict__ coef)
 {
     using R4 = typename V4<R>::T;
+    using R2 = typename V2<R>::T;
     using LT = typename LdsField<FIX>::T;
     constexpr int NV = K::NV;
     __shared__ R4 s_ip[kBlock];                      // i offset from the block origin, w = alpha^-1/6
@@ -432,6 +485,22 @@ __global__ __launch_bounds__(256) void k_block_tiles(int nb, const int* __restri
             if (wm != w)
                 continue;
         }
+        // stored coefficients of the tile: rows r0 .. r1-1; the first four steps' loads are
+        // issued before the staging so that they arrive with it
+        bool stored = false;  // wave-uniform
+        R2* cp = nullptr;     // this lane's slot of step 0
+        R2 ca[4] = {R2{0, 0}, R2{0, 0}, R2{0, 0}, R2{0, 0}};
+        if constexpr (CM != kCoefCompute) {
+            const int r0 = coef_row0[t], r1 = coef_row0[t + 1];
+            stored = (long long)r1 <= coef_cap_rows;
+            cp = coef + (size_t)r0 * kBlock + lane;
+            if (CM == kCoefReplay && stored) {
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    if (u < r1 - r0)
+                        ca[u] = cp[u * kBlock];
+            }
+        }
         const int sj = tile_j[(size_t)t * kBlock + lane];
         {
             const R4 jr = jrel[(size_t)t * kBlock + lane];
@@ -471,7 +540,9 @@ __global__ __launch_bounds__(256) void k_block_tiles(int nb, const int* __restri
             R4 ip{0, 0, 0, 0};
             R4 di[NV];
             R ea[3] = {0, 0, 0};
-            for (int p = p0; p < p1; ++p) {
+            // one pair of the walk: the next set bit (a new row first adds the finished row's
+            // i-field to the block accumulator), the pair's field from eval, the j-field added
+            auto visit = [&](auto&& eval) {
                 while (rem == 0ull)
                     rem = s_mask[w][++i];
                 const int k = __ffsll((long long)rem) - 1;
@@ -493,10 +564,45 @@ __global__ __launch_bounds__(256) void k_block_tiles(int nb, const int* __restri
                 for (int v = 0; v < NV; ++v)
                     dj[v] = s_jd[w][v][k];
                 R ej[3];
-                K::template pair<MI>(ip, di, s_jp[w][k], dj, ew, ea, ej);
+                eval(s_jp[w][k], dj, ej);
 #pragma unroll
                 for (int c = 0; c < 3; ++c)
                     LdsField<FIX>::add(&s_ej[w][c][k], ej[c]);
+            };
+            const int n = p1 - p0;
+            bool replayed = false;
+            if constexpr (CM == kCoefReplay) {
+                // the stored coefficients four steps at a time, the next four in flight while
+                // these are used
+                replayed = stored;
+                for (int s = 0; replayed && s < n; s += 4) {
+                    R2 cb[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+                        cb[u] = s + 4 + u < n ? cp[(s + 4 + u) * kBlock] : R2{0, 0};
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+                        if (s + u < n)
+                            visit([&](const R4& jp, const R4* dj, R* ej) {
+                                K::template pair_stored<MI>(ip, di, jp, dj, ew, ca[u], ea, ej);
+                            });
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+                        ca[u] = cb[u];
+                }
+            }
+            if (!replayed) {
+                for (int s = 0; s < n; ++s)
+                    visit([&](const R4& jp, const R4* dj, R* ej) {
+                        if constexpr (CM == kCoefCompute) {
+                            K::template pair<MI>(ip, di, jp, dj, ew, ea, ej);
+                        } else {
+                            R2 cf;
+                            K::template pair_record<MI>(ip, di, jp, dj, ew, ea, ej, cf);
+                            if (CM == kCoefRecord && stored)
+                                cp[s * kBlock] = cf;
+                        }
+                    });
             }
 #pragma unroll
             for (int c = 0; c < 3; ++c)
@@ -566,19 +672,111 @@ __global__ void k_real_reduce(int npad, const double* __restrict__ eipart, const
     ereal[3 * (size_t)s + 2] = e2;
 }
 
+template <typename R, bool FIX, bool MI, int CM>
+static void dipole_tiles(amoeba_ctx* c, bool use_done, hipStream_t st, const typename V4<R>::T* jrel,
+                         const typename V4<R>::T* off, const typename V4<R>::T* par, const typename V4<R>::T* pv)
+{
+    hipLaunchKernelGGL((k_block_tiles<R, FIX, DipoleKind<R>, MI, CM>), dim3(c->nb), dim3(256), 0, st, c->nb,
+                       c->blk_tile0, c->tile_np, c->tile_j, c->tile_mask, jrel, off, par, pv, make_ewald<R>(c),
+                       c->eipart, (R*)c->jbuf, c->sc, (int)use_done, c->coef_row0, (long long)c->coef_cap_rows,
+                       (typename V2<R>::T*)c->coef);
+}
+
+template <typename R, bool FIX, bool MI>
+static void dipole_tiles_cm(amoeba_ctx* c, int cm, bool use_done, hipStream_t st, const typename V4<R>::T* jrel,
+                            const typename V4<R>::T* off, const typename V4<R>::T* par,
+                            const typename V4<R>::T* pv)
+{
+    if (cm == kCoefReplay)
+        dipole_tiles<R, FIX, MI, kCoefReplay>(c, use_done, st, jrel, off, par, pv);
+    else if (cm == kCoefRecord)
+        dipole_tiles<R, FIX, MI, kCoefRecord>(c, use_done, st, jrel, off, par, pv);
+    else
+        dipole_tiles<R, FIX, MI, kCoefCompute>(c, use_done, st, jrel, off, par, pv);
+}
+
+// Whether the dipole products use the store.  AUTO: in FP64, where the pair functions cost far
+// more than reading 16 bytes per pair back; not in mixed precision, where the FP32 tiles are
+// bound by their LDS traffic (the field atomics and the j-data reads), which the store leaves as
+// it is, so that replay measured no faster than evaluation.
+bool coef_store_on(const amoeba_ctx* c)
+{
+    return c->pair_store == AMOEBA_PAIRS_STORED || (c->pair_store == AMOEBA_PAIRS_AUTO && !c->mixed);
+}
+
+// Coefficient mode of the next dipole product: the store needs the refresh's row scan and a
+// buffer; the first product of a configuration records, the later ones replay.
+static int next_coef_mode(const amoeba_ctx* c)
+{
+    if (!coef_store_on(c) || !c->coef_rows_ok || !c->coef)
+        return kCoefCompute;
+    return c->coef_ready ? kCoefReplay : kCoefRecord;
+}
+
 template <bool MI> static void mutual_tiles(amoeba_ctx* c, bool use_done, hipStream_t st)
 {
     if (c->ntiles == 0)
         return;
     StageTimer tm(c, AMOEBA_T_REAL);
+    const int cm = next_coef_mode(c);
+    // a recording product runs even when a converged PCG skips the rest of its iteration, so
+    // that the store is whole for the products that replay it
+    if (cm == kCoefRecord)
+        use_done = false;
     if (c->mixed)
-        hipLaunchKernelGGL((k_block_tiles<float, true, DipoleKind<float>, MI>), dim3(c->nb), dim3(256), 0, st,
-                           c->nb, c->blk_tile0, c->tile_np, c->tile_j, c->tile_mask, c->jrel_f, c->off_f, c->par_f, c->pv_f,
-                           make_ewald<float>(c), c->eipart, (float*)c->jbuf, c->sc, (int)use_done);
+        dipole_tiles_cm<float, true, MI>(c, cm, use_done, st, c->jrel_f, c->off_f, c->par_f, c->pv_f);
     else
-        hipLaunchKernelGGL((k_block_tiles<double, false, DipoleKind<double>, MI>), dim3(c->nb), dim3(256), 0, st,
-                           c->nb, c->blk_tile0, c->tile_np, c->tile_j, c->tile_mask, c->jrel_d, c->off_d, c->par_d, c->pv_d,
-                           make_ewald<double>(c), c->eipart, (double*)c->jbuf, c->sc, (int)use_done);
+        dipole_tiles_cm<double, false, MI>(c, cm, use_done, st, c->jrel_d, c->off_d, c->par_d, c->pv_d);
+    if (cm == kCoefRecord)
+        c->coef_ready = true;
+    c->coef_last_stored = cm != kCoefCompute;
+}
+
+void coef_invalidate(amoeba_ctx* c) { c->coef_ready = false; }
+
+// Frees the store (hipFree waits for the device, so no queued product still reads it).
+void coef_release(amoeba_ctx* c)
+{
+    if (!c->coef)
+        return;
+    hipFree(c->coef);
+    c->coef = nullptr;
+    c->ws_bytes -= c->coef_bytes;
+    c->coef_bytes = 0;
+    c->coef_cap_rows = 0;
+    coef_invalidate(c);
+}
+
+// Called with the context stream synchronized: grows the store to the rows of the last mask
+// refresh (read back with that synchronization) plus an eighth, or to what the workspace cap
+// leaves.  A store smaller than the rows is still used: the tiles beyond it evaluate their
+// coefficients.
+int coef_reserve(amoeba_ctx* c)
+{
+    if (!c->coef_rows_pending || !coef_store_on(c))
+        return AMOEBA_OK;
+    c->coef_rows_pending = false;
+    const int64_t rows = (int64_t)(unsigned)c->flags_host[10];
+    if (rows <= c->coef_cap_rows)
+        return AMOEBA_OK;
+    const int64_t row_bytes = (int64_t)kBlock * (c->mixed ? sizeof(float2) : sizeof(double2));
+    int64_t want = rows + rows / 8 + 64;
+    const int64_t others = c->ws_bytes - c->coef_bytes;
+    if (c->prm.max_workspace_bytes > 0)
+        want = std::min(want, (c->prm.max_workspace_bytes - others) / row_bytes);
+    if (want <= c->coef_cap_rows)
+        return AMOEBA_OK;  // the cap leaves no more room: keep the store it has
+    coef_release(c);
+    void* q = nullptr;
+    if (want < 64 || hipMalloc(&q, (size_t)(want * row_bytes)) != hipSuccess) {
+        (void)hipGetLastError();
+        return AMOEBA_OK;  // no store: the products evaluate the coefficients
+    }
+    c->coef = q;
+    c->coef_bytes = want * row_bytes;
+    c->ws_bytes += c->coef_bytes;
+    c->coef_cap_rows = want;
+    return AMOEBA_OK;
 }
 
 void launch_mutual_tiles(amoeba_ctx* c, bool use_done, hipStream_t st)
@@ -611,11 +809,13 @@ template <bool MI> static void perm_tiles(amoeba_ctx* c, hipStream_t st)
     if (c->mixed)
         hipLaunchKernelGGL((k_block_tiles<float, true, MultipoleKind<float>, MI>), dim3(c->nb), dim3(256), 0,
                            st, c->nb, c->blk_tile0, c->tile_np, c->tile_j, c->tile_mask, c->jrel_f, c->off_f, c->par_f,
-                           (const float4*)c->mp_f, make_ewald<float>(c), c->eipart, (float*)c->jbuf, c->sc, 0);
+                           (const float4*)c->mp_f, make_ewald<float>(c), c->eipart, (float*)c->jbuf, c->sc, 0,
+                           (const int*)nullptr, 0ll, (float2*)nullptr);
     else
         hipLaunchKernelGGL((k_block_tiles<double, false, MultipoleKind<double>, MI>), dim3(c->nb), dim3(256), 0,
                            st, c->nb, c->blk_tile0, c->tile_np, c->tile_j, c->tile_mask, c->jrel_d, c->off_d, c->par_d,
-                           (const double4*)c->mp_d, make_ewald<double>(c), c->eipart, (double*)c->jbuf, c->sc, 0);
+                           (const double4*)c->mp_d, make_ewald<double>(c), c->eipart, (double*)c->jbuf, c->sc, 0,
+                           (const int*)nullptr, 0ll, (double2*)nullptr);
 }
 
 void launch_perm_tiles(amoeba_ctx* c, hipStream_t st)
