@@ -286,6 +286,19 @@ int amoeba_guess_predict(amoeba_ctx* ctx, const double* pos, const double* e_per
  * The default is AMOEBA_PME_AUTO. */
 int amoeba_set_pme_path(amoeba_ctx* ctx, int32_t path);
 
+/* Run each PCG iteration (the dipole product on its two streams, the update and the direction
+ * kernels) as one captured HIP graph (enable != 0) or as individual launches (enable = 0, the
+ * default).  The paper observes that the small kernels of an iteration are launch bound; a graph
+ * replays them without per-kernel host launches.  Both give bitwise the same iterates: the graph
+ * holds the same kernels with the same arguments.  On MI355X the graph measured slower than the
+ * direct launches, which the host already queues two iterations ahead (water_96000 solve 1.49
+ * against 1.45 ms), hence the default.  The graph is used on the plane PME path without stage
+ * timers; it is captured at the first iteration that can use it and captured again when a
+ * launch parameter it holds changes (pair kernel variant, coefficient store).  Waits for the
+ * context stream.  A capture that fails turns graphs off for the context (the solve goes on with
+ * direct launches). */
+int amoeba_set_graphs(amoeba_ctx* ctx, int32_t enable);
+
 /* Select how the real-space dipole product gets its pair coefficients (amoeba_pair_store) for
  * later products; an unknown value: AMOEBA_E_INVALID.  The default is AMOEBA_PAIRS_AUTO. */
 int amoeba_set_pair_store(amoeba_ctx* ctx, int32_t mode);

@@ -115,6 +115,7 @@ def lib() -> ctypes.CDLL:
         L.amoeba_guess_predict.argtypes = [_P, _P, _P, _P]
         L.amoeba_set_pme_path.argtypes = [_P, ctypes.c_int32]
         L.amoeba_set_pair_store.argtypes = [_P, ctypes.c_int32]
+        L.amoeba_set_graphs.argtypes = [_P, ctypes.c_int32]
         L.amoeba_set_timing.argtypes = [_P, ctypes.c_int]
         L.amoeba_get_timing.argtypes = [_P, ctypes.POINTER(amoeba_timing)]
         _lib = L
@@ -243,6 +244,11 @@ class Context:
     def set_pair_store(self, mode):
         """mode: "auto", "compute" or "stored" (or the AMOEBA_PAIRS_* value)."""
         self._check(lib().amoeba_set_pair_store(self.h, PAIR_STORE[mode] if isinstance(mode, str) else int(mode)))
+
+    def set_graphs(self, enable):
+        """Run PCG iterations as one captured HIP graph each (True, the default) or as
+        individual kernel launches (False)."""
+        self._check(lib().amoeba_set_graphs(self.h, 1 if enable else 0))
 
     def info(self) -> dict:
         inf = amoeba_info()

@@ -349,7 +349,8 @@ int amoeba_create(const amoeba_params* p, void* hip_stream, amoeba_ctx** out)
             hipEventCreateWithFlags(&c->ev[1], hipEventDisableTiming) != hipSuccess ||
             hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
             hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess ||
-            hipStreamCreateWithFlags(&c->stream2, hipStreamNonBlocking) != hipSuccess) {
+            hipStreamCreateWithFlags(&c->stream2, hipStreamNonBlocking) != hipSuccess ||
+            hipStreamCreateWithFlags(&c->gstream, hipStreamNonBlocking) != hipSuccess) {
             rc = set_error(c, AMOEBA_E_DEVICE, "hipEventCreate failed");
             break;
         }
@@ -375,6 +376,9 @@ int amoeba_destroy(amoeba_ctx* c)
         hipStreamSynchronize(c->stream2);
         hipStreamDestroy(c->stream2);
     }
+    iteration_graph_release(c);
+    if (c->gstream)
+        hipStreamDestroy(c->gstream);
     for (void* p : c->allocs)
         hipFree(p);
     if (c->sc_host)
@@ -706,6 +710,17 @@ int amoeba_set_pme_path(amoeba_ctx* c, int32_t path)
         return set_error(c, AMOEBA_E_INVALID, "amoeba_set_pme_path: the PME grid does not fit the plane path "
                                               "(K not a product of 2, 3, 5, 7, or the plane exceeds 150 KB)");
     c->pme_path = path;
+    return AMOEBA_OK;
+}
+
+int amoeba_set_graphs(amoeba_ctx* c, int32_t enable)
+{
+    if (!c)
+        return AMOEBA_E_INVALID;
+    hipStreamSynchronize(c->stream);
+    c->use_graphs = enable != 0;
+    if (!c->use_graphs)
+        iteration_graph_release(c);
     return AMOEBA_OK;
 }
 

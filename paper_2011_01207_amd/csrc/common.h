@@ -74,7 +74,10 @@ struct PcgScalars {
     int32_t done;     // converged (or broken down): later kernels of the loop skip
     int32_t iters;    // iterations completed
     int32_t status;   // 0 running, 1 converged, 2 breakdown
-    int32_t pad;
+    int32_t seq;      // direction kernels run since the solve began (publication counter)
+    int32_t seq_cur;  // seq and iteration index for the running direction kernel, set by the
+    int32_t it_cur;   // update kernel before it (no kernel reads a field it writes)
+    int32_t pad[2];
 };
 
 // Reduction partials (see reduce.h).
@@ -218,6 +221,15 @@ struct amoeba_ctx {
     // the reciprocal passes on the context stream: forked and joined with events
     hipStream_t stream2 = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    // one PCG iteration (product on both streams, update, direction) as a HIP graph: captured on
+    // gstream, replayed on the context stream; recaptured when a launch parameter it bakes in
+    // changes (key).  Off unless the caller asks: measured slower than the direct launches.
+    bool use_graphs = false;
+    hipStream_t gstream = nullptr;
+    hipGraph_t it_graph = nullptr;
+    hipGraphExec_t it_exec = nullptr;
+    unsigned long long it_key = 0;
+    int pcg_seq = 0;                       // direction kernels enqueued since the solve began
 
     // list-build scratch, kept between builds
     unsigned long long* b_keys = nullptr;  // [n] sort keys
@@ -282,10 +294,12 @@ int prepare_config(amoeba_ctx* c, const double* pos);
 
 // realspace.hip
 void launch_mutual_tiles(amoeba_ctx* c, bool use_done, hipStream_t st = nullptr);  // null: context stream
+void iteration_graph_release(amoeba_ctx* c);  // drop the captured PCG iteration
 void coef_invalidate(amoeba_ctx* c);      // pair coefficients must be recorded again
 int coef_reserve(amoeba_ctx* c);          // size the coefficient store (host has synchronized)
 void coef_release(amoeba_ctx* c);         // free it (other allocations come first under the cap)
 bool coef_store_on(const amoeba_ctx* c);  // the requested mode uses the store
+int next_coef_mode(const amoeba_ctx* c);  // the next dipole product: 0 evaluates, 1 records, 2 replays
 void launch_real_reduce(amoeba_ctx* c, double* ereal, hipStream_t st = nullptr, bool use_done = false);
 void launch_perm_tiles(amoeba_ctx* c, hipStream_t st = nullptr);
 void launch_perm_assemble(amoeba_ctx* c, double* out_slot);

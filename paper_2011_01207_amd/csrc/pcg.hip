@@ -150,13 +150,20 @@ __global__ __launch_bounds__(256) void k_init_finalize(int nparts, const double*
 
 // gamma = r.z / p.Ap (p.Ap from the gather's per-brick partials); mu += gamma p, r -= gamma Ap,
 // z = alpha r; partials of the new r.z and z.z
-__global__ __launch_bounds__(256) void k_update(int npad, int it, const double4* __restrict__ par,
+// The iteration index is the device's count of completed iterations, so that the launches of
+// an iteration take no per-iteration argument (one captured iteration serves them all).
+__global__ __launch_bounds__(256) void k_update(int npad, const double4* __restrict__ par,
                                                 const double* __restrict__ p, const double* __restrict__ q,
                                                 double* __restrict__ mu, double* __restrict__ r,
                                                 double* __restrict__ z, PcgScalars* __restrict__ sc,
                                                 const double* __restrict__ part_pq, int n_pq,
                                                 double* __restrict__ part)
 {
+    const int it = sc->iters;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        sc->seq_cur = sc->seq;  // for the direction kernel that follows
+        sc->it_cur = it;
+    }
     if (sc->done)
         return;
     double pq[1];
@@ -195,16 +202,20 @@ __global__ __launch_bounds__(256) void k_update(int npad, int it, const double4*
 
 // convergence test on rms(z); unless converged: beta = r.z(new) / r.z(old), p = z + beta p
 template <typename R4T>
-__global__ __launch_bounds__(256) void k_direction(int npad, int n, int it, const double* __restrict__ z,
+__global__ __launch_bounds__(256) void k_direction(int npad, int n, const double* __restrict__ z,
                                                    double* __restrict__ p, R4T* __restrict__ pv,
                                                    PcgScalars* __restrict__ sc, const double* __restrict__ part,
                                                    PcgScalars* __restrict__ pub)
 {
-    // pub: pinned host copy of the scalars after this iteration, written by one thread (no
-    // separate device-to-host copy per iteration)
+    // pub[2]: pinned host copies of the scalars, written by one thread (no separate
+    // device-to-host copy per iteration); the k-th direction kernel of a solve writes pub[k & 1]
+    const int it = sc->it_cur, seq = sc->seq_cur;
     if (sc->done) {
-        if (blockIdx.x == 0 && threadIdx.x == 0 && pub)
-            *pub = *sc;
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            sc->seq = seq + 1;
+            if (pub)
+                pub[seq & 1] = *sc;
+        }
         return;
     }
     double tot[2];
@@ -227,8 +238,9 @@ __global__ __launch_bounds__(256) void k_direction(int npad, int n, int it, cons
             sc->rzb[(it + 1) & 1] = tot[0];
             sc->beta = beta;
         }
+        sc->seq = seq + 1;
         if (pub)
-            *pub = *sc;
+            pub[seq & 1] = *sc;
     }
     if (conv || bad)
         return;
@@ -342,21 +354,100 @@ static void launch_init_residual(amoeba_ctx* c, const double* q, int it)
     hipLaunchKernelGGL(k_init_finalize, dim3(1), dim3(256), 0, c->stream, kRedBlocks, part_vec(c), c->n, it, c->sc);
 }
 
-static int enqueue_iteration(amoeba_ctx* c, int it, PcgScalars* pub, hipEvent_t fork_ev)
+static int enqueue_iteration_direct(amoeba_ctx* c, hipEvent_t fork_ev)
 {
     int rc = matvec_slot(c, true, true, fork_ev);
     if (rc)
         return rc;
     StageTimer tm(c, AMOEBA_T_PCG);
-    hipLaunchKernelGGL(k_update, dim3(kRedBlocks), dim3(256), 0, c->stream, c->npad, it, c->par_d, c->v_p, c->v_q,
+    hipLaunchKernelGGL(k_update, dim3(kRedBlocks), dim3(256), 0, c->stream, c->npad, c->par_d, c->v_p, c->v_q,
                        c->v_mu, c->v_r, c->v_z, c->sc, part_pq(c), c->npq, part_vec(c));
     if (c->mixed)
-        hipLaunchKernelGGL(k_direction<float4>, dim3(kRedBlocks), dim3(256), 0, c->stream, c->npad, c->n, it, c->v_z,
-                           c->v_p, c->pv_f, c->sc, part_vec(c), pub);
+        hipLaunchKernelGGL(k_direction<float4>, dim3(kRedBlocks), dim3(256), 0, c->stream, c->npad, c->n, c->v_z,
+                           c->v_p, c->pv_f, c->sc, part_vec(c), c->sc_host_dev);
     else
-        hipLaunchKernelGGL(k_direction<double4>, dim3(kRedBlocks), dim3(256), 0, c->stream, c->npad, c->n, it,
-                           c->v_z, c->v_p, c->pv_d, c->sc, part_vec(c), pub);
+        hipLaunchKernelGGL(k_direction<double4>, dim3(kRedBlocks), dim3(256), 0, c->stream, c->npad, c->n, c->v_z,
+                           c->v_p, c->pv_d, c->sc, part_vec(c), c->sc_host_dev);
     return AMOEBA_OK;
+}
+
+void iteration_graph_release(amoeba_ctx* c)
+{
+    if (c->it_exec)
+        hipGraphExecDestroy(c->it_exec);
+    if (c->it_graph)
+        hipGraphDestroy(c->it_graph);
+    c->it_exec = nullptr;
+    c->it_graph = nullptr;
+    c->it_key = 0;
+}
+
+// What a captured iteration bakes in besides the context's fixed buffers: the pair kernel's
+// minimum-image variant and coefficient mode, the coefficient store, the p.q partial count.
+static unsigned long long iteration_key(const amoeba_ctx* c)
+{
+    unsigned long long k = 1469598103934665603ull;
+    auto mix = [&](unsigned long long v) { k = (k ^ v) * 1099511628211ull; };
+    mix(c->skip_mimg ? 1 : 2);
+    mix((unsigned long long)next_coef_mode(c) + 3);
+    mix((unsigned long long)(uintptr_t)c->coef);
+    mix((unsigned long long)c->coef_cap_rows);
+    mix((unsigned long long)c->npq_cap);
+    return k | 1ull;
+}
+
+// Capture one iteration on gstream (the context stream may be the legacy default stream, which
+// cannot be captured); the product forks to stream2 and joins back inside the capture.
+static int capture_iteration(amoeba_ctx* c)
+{
+    iteration_graph_release(c);
+    hipStream_t saved = c->stream;
+    if (hipStreamBeginCapture(c->gstream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        (void)hipGetLastError();
+        return AMOEBA_E_DEVICE;
+    }
+    c->stream = c->gstream;
+    int rc = enqueue_iteration_direct(c, nullptr);
+    c->stream = saved;
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(c->gstream, &g);
+    if (rc || e != hipSuccess || !g) {
+        (void)hipGetLastError();
+        if (g)
+            hipGraphDestroy(g);
+        return rc ? rc : AMOEBA_E_DEVICE;
+    }
+    hipGraphExec_t x = nullptr;
+    if (hipGraphInstantiate(&x, g, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        hipGraphDestroy(g);
+        return AMOEBA_E_DEVICE;
+    }
+    c->it_graph = g;
+    c->it_exec = x;
+    c->it_key = iteration_key(c);
+    return AMOEBA_OK;
+}
+
+// One PCG iteration: the captured graph when the overlapped plane path runs without stage timers
+// and the pair coefficients are not being recorded (that launch changes host state), else the
+// direct launches.  A capture that fails leaves the direct launches in use.
+static int enqueue_iteration(amoeba_ctx* c, hipEvent_t fork_ev)
+{
+    const bool graph = c->use_graphs && !c->timing && pme_use_planes(c) && next_coef_mode(c) != 1;
+    if (graph) {
+        if ((!c->it_exec || c->it_key != iteration_key(c)) && capture_iteration(c) != AMOEBA_OK)
+            c->use_graphs = false;
+        if (c->it_exec) {
+            c->rec_plane = true;  // c->npq keeps the plane path's count set during the capture
+            if (hipGraphLaunch(c->it_exec, c->stream) == hipSuccess)
+                return AMOEBA_OK;
+            (void)hipGetLastError();
+            iteration_graph_release(c);
+            c->use_graphs = false;
+        }
+    }
+    return enqueue_iteration_direct(c, fork_ev);
 }
 
 // Iterations first..first+budget-1 until the device flag says done.  Host reads lag the device
@@ -364,23 +455,26 @@ static int enqueue_iteration(amoeba_ctx* c, int it, PcgScalars* pub, hipEvent_t 
 // (later queued iterations return at entry).  Returns a HIP/rocFFT error code or AMOEBA_OK.
 static int run_iterations(amoeba_ctx* c, int first, int budget, PcgScalars* last)
 {
+    (void)first;
     hipStream_t st = c->stream;
+    const int seq0 = c->pcg_seq;  // the k-th iteration of this call publishes to slot (seq0 + k) & 1
     int enq = 0, chk = 0, rc;
     while (true) {
         if (enq < budget) {
             // the previous iteration's event marks the end of the stream at this point
-            if ((rc = enqueue_iteration(c, first + enq, c->sc_host_dev + ((enq + 1) & 1),
-                                        enq > 0 ? c->ev[enq & 1] : nullptr)))
+            if ((rc = enqueue_iteration(c, enq > 0 ? c->ev[enq & 1] : nullptr)))
                 return rc;
             ++enq;
+            ++c->pcg_seq;
             hipEventRecord(c->ev[enq & 1], st);
         }
         if (enq >= chk + 2 || enq == budget) {
             ++chk;
             if ((rc = hip_check(c, hipEventSynchronize(c->ev[chk & 1]), "pcg iteration")))
                 return rc;
-            if (c->sc_host[chk & 1].done || chk >= budget) {
-                *last = c->sc_host[chk & 1];
+            const PcgScalars& s = c->sc_host[(seq0 + chk - 1) & 1];
+            if (s.done || chk >= budget) {
+                *last = s;
                 return AMOEBA_OK;
             }
         }
@@ -417,6 +511,7 @@ static void launch_epol(amoeba_ctx* c)
 // Initial device scalars of a solve (tolerance; everything else zero); no host wait.
 void pcg_begin(amoeba_ctx* c, double tol)
 {
+    c->pcg_seq = 0;
     hipLaunchKernelGGL(k_pcg_begin, dim3(1), dim3(1), 0, c->stream, c->sc, tol);
 }
 

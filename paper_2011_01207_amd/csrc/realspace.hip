@@ -706,7 +706,7 @@ bool coef_store_on(const amoeba_ctx* c)
 
 // Coefficient mode of the next dipole product: the store needs the refresh's row scan and a
 // buffer; the first product of a configuration records, the later ones replay.
-static int next_coef_mode(const amoeba_ctx* c)
+int next_coef_mode(const amoeba_ctx* c)
 {
     if (!coef_store_on(c) || !c->coef_rows_ok || !c->coef)
         return kCoefCompute;

@@ -1,0 +1,81 @@
+"""GPU tests of the PCG iteration run as a captured HIP graph (the paper's observation that the
+iteration's small kernels are launch bound).  A solve replays the graph once per iteration, with
+host waits and other work between the replays; every solve is compared with the same solve
+launched kernel by kernel.  Mixed precision sums exactly in fixed point, so the iterates must be
+bitwise equal; FP64 products sum FP64 atomics in a varying order and agree to that rounding."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2011_01207_amd import amoeba, synth
+
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+DEV = "cuda:0"
+
+
+def system():
+    return synth.water_box(1000, 31.05, 32, 7, "water_3000", buffer=1.0)
+
+
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+def test_graph_solves_equal_launched_solves(prec):
+    print(f"[gpu] graph solve {prec}", flush=True)
+    s = system()
+    e_ref = O.perm_field(s, "spme")
+    mu_ref, _, _ = O.pcg(s, e_ref, "spme", tol_debye=1e-10)
+    rng = np.random.default_rng(8)
+    step = rng.standard_normal((s.n, 3))
+    step *= 0.2 / np.linalg.norm(step, axis=1, keepdims=True)
+    runs = {}
+    for graphs in (False, True):
+        ctx, t = amoeba.context_for(s, precision=prec, device=DEV)
+        try:
+            ctx.set_graphs(graphs)
+            out = []
+            # three solves: same configuration twice, then a moved one; eager work between
+            for k, pos in enumerate([t["pos"], t["pos"], t["pos"] + torch.tensor(step, device=DEV)]):
+                e = ctx.perm_field(pos, t["q"], t["dip"], t["quad"])
+                mu, ep, it, st = ctx.polarize(pos, e, tol_debye=1e-7, max_iter=200)
+                assert st == amoeba.AMOEBA_OK
+                torch.cuda.synchronize()
+                out.append((e.clone(), mu.clone(), ep, it))
+            runs[graphs] = out
+        finally:
+            ctx.close()
+    for (e0, m0, p0, i0), (e1, m1, p1, i1) in zip(runs[False], runs[True]):
+        if prec == "mixed":
+            assert torch.equal(e0, e1)
+            assert torch.equal(m0, m1) and p0 == p1 and i0 == i1
+        else:
+            assert abs(i0 - i1) <= 1
+            assert O.rms_debye(m1.cpu().numpy() - m0.cpu().numpy()) < 1e-8
+    mu_first = runs[True][0][1].cpu().numpy()
+    assert O.rms_debye(mu_first - mu_ref) < (2e-7 if prec == "fp64" else 1e-5)
+
+
+def test_graph_follows_a_change_of_pair_kernel_and_store():
+    """Switching the coefficient store on and off between solves recaptures the iteration."""
+    print("[gpu] graph recapture", flush=True)
+    s = system()
+    e_ref = O.perm_field(s, "spme")
+    e = torch.tensor(e_ref, device=DEV)
+    ctx, t = amoeba.context_for(s, precision="mixed", device=DEV)
+    try:
+        ctx.set_graphs(True)
+        res = []
+        for mode in ("compute", "stored", "stored", "compute"):
+            ctx.set_pair_store(mode)
+            mu, ep, it, st = ctx.polarize(t["pos"], e, tol_debye=1e-7, max_iter=200)
+            assert st == amoeba.AMOEBA_OK
+            res.append((mu.clone(), it))
+        ctx.set_graphs(False)
+        mu_l, _, it_l, _ = ctx.polarize(t["pos"], e, tol_debye=1e-7, max_iter=200)
+    finally:
+        ctx.close()
+    for mu, it in res:
+        assert torch.equal(mu, mu_l) and it == it_l
