@@ -323,11 +323,12 @@ int amoeba_create(const amoeba_params* p, void* hip_stream, amoeba_ctx** out)
             (rc = ctx_alloc(c, (void**)&c->v_e, sizeof(double) * n3)) ||
             (rc = ctx_alloc(c, (void**)&c->sc, sizeof(PcgScalars))) ||
             (rc = ctx_alloc(c, (void**)&c->red.part, sizeof(double) * part_n)) ||
-            (rc = ctx_alloc(c, (void**)&c->flags, sizeof(int) * 4)) ||
+            (rc = ctx_alloc(c, (void**)&c->flags, sizeof(int) * 16)) ||
             (rc = ctx_alloc(c, (void**)&c->counter, sizeof(unsigned long long) * 2)) ||
             (rc = ctx_alloc(c, (void**)&c->b_cnt, sizeof(int) * (np + 1))) ||
             (rc = ctx_alloc(c, (void**)&c->b_scan, sizeof(int) * 2 * (np / 1024 + 2))))
             break;
+        c->b_extent = (double*)(c->flags + 4);  // read back with the flags after a list build
         if ((rc = ctx_alloc(c, (void**)&c->eipart, sizeof(double) * n3)) ||
             (rc = ctx_alloc(c, (void**)&c->ereal, sizeof(double) * n3)) ||
             (rc = ctx_alloc(c, (void**)&c->rev_ptr, sizeof(int) * (np + 1))))
@@ -731,6 +732,8 @@ int amoeba_set_pair_store(amoeba_ctx* c, int32_t mode)
     if (mode != AMOEBA_PAIRS_AUTO && mode != AMOEBA_PAIRS_COMPUTE && mode != AMOEBA_PAIRS_STORED)
         return set_error(c, AMOEBA_E_INVALID, "amoeba_set_pair_store: unknown mode");
     c->pair_store = mode;
+    if (coef_store_on(c) && c->cfg_valid && !c->coef_rows_ok)
+        coef_scan_rows(c);  // the store's rows for the current masks (scanned at a refresh otherwise)
     return AMOEBA_OK;
 }
 
@@ -741,6 +744,7 @@ int amoeba_get_info(const amoeba_ctx* cc, amoeba_info* out)
     amoeba_ctx* c = const_cast<amoeba_ctx*>(cc);  // the pair count of the last refresh is read lazily
     if (c->pairs_pending) {
         unsigned long long np = 0;
+        launch_sum_pairs(c);
         hipMemcpyAsync(c->flags_host + 2, c->counter, sizeof(unsigned long long), hipMemcpyDeviceToHost, c->stream);
         if (hipStreamSynchronize(c->stream) != hipSuccess)
             return AMOEBA_E_DEVICE;

@@ -40,10 +40,17 @@ __device__ __forceinline__ double wrap_box(double x, double L)
 // serpentine), then the atom index; packed as col | xq (16 bits) | a (ib bits) so that a radix
 // sort over the low ib + 16 + colbits bits orders it.  The largest column value is kept for
 // non-finite positions, which sort last (the gather check reports them).
+// Also clears the build's status words (error flags, the block extent maxima of k_bbox).
 __global__ void k_sort_keys(int n, const double* __restrict__ pos, double3 box, int ny, int nz, int ib,
-                            int colbits, unsigned long long* __restrict__ keys)
+                            int colbits, unsigned long long* __restrict__ keys, int* __restrict__ flags,
+                            unsigned long long* __restrict__ extent_bits)
 {
     int a = blockIdx.x * blockDim.x + threadIdx.x;
+    if (a == 0) {
+        flags[0] = 0;
+        for (int d = 0; d < 3; ++d)
+            extent_bits[d] = 0ull;
+    }
     if (a >= n)
         return;
     double x = wrap_box(pos[3 * a], box.x), y = wrap_box(pos[3 * a + 1], box.y),
@@ -65,8 +72,8 @@ __global__ void k_sort_keys(int n, const double* __restrict__ pos, double3 box, 
     keys[a] = (col << (16 + ib)) | (xq << ib) | (unsigned long long)a;
 }
 
-// Three-phase exclusive scan for long arrays: block sums (1024 per workgroup), scan of the
-// sums, then block-local scans offset by the scanned sums.
+// Two-phase exclusive scan for long arrays: block sums (1024 per workgroup), then block-local
+// scans, each offset by the sum of the block sums before it.
 __global__ __launch_bounds__(256) void k_scan_blocksum(int n, const int* __restrict__ in, int* __restrict__ bsum)
 {
     __shared__ int sh[256];
@@ -87,11 +94,28 @@ __global__ __launch_bounds__(256) void k_scan_blocksum(int n, const int* __restr
         bsum[blockIdx.x] = sh[0];
 }
 
-__global__ __launch_bounds__(256) void k_scan_apply(int n, const int* __restrict__ in, const int* __restrict__ boff,
+__global__ __launch_bounds__(256) void k_scan_apply(int n, const int* __restrict__ in, const int* __restrict__ bsum,
                                                     int* __restrict__ out)
 {
     __shared__ int sh[256];
+    __shared__ int s_boff;
     int base = blockIdx.x * 1024, t = threadIdx.x;
+    {
+        // this workgroup's offset: the sum of the block sums before it (fixed order)
+        int b = 0;
+        for (int k = t; k < (int)blockIdx.x; k += 256)
+            b += bsum[k];
+        sh[t] = b;
+        __syncthreads();
+        for (int off = 128; off > 0; off >>= 1) {
+            if (t < off)
+                sh[t] += sh[t + off];
+            __syncthreads();
+        }
+        if (t == 0)
+            s_boff = sh[0];
+        __syncthreads();
+    }
     int v[4], s = 0;
     for (int u = 0; u < 4; ++u) {
         int i = base + t * 4 + u;
@@ -106,7 +130,7 @@ __global__ __launch_bounds__(256) void k_scan_apply(int n, const int* __restrict
         sh[t] += y;
         __syncthreads();
     }
-    int run = boff[blockIdx.x] + sh[t] - s;
+    int run = s_boff + sh[t] - s;
     for (int u = 0; u < 4; ++u) {
         int i = base + t * 4 + u;
         if (i < n)
@@ -133,13 +157,16 @@ __global__ void k_perm(int n, int npad, const unsigned long long* __restrict__ k
     }
 }
 
+// Per-slot parameters and the slot's count of scaled pairs (the CSR in slot order).
 __global__ void k_params(int npad, const int* __restrict__ perm, const double* __restrict__ alpha,
-                         const double* __restrict__ thole, double4* __restrict__ pd, float4* __restrict__ pf)
+                         const double* __restrict__ thole, double4* __restrict__ pd, float4* __restrict__ pf,
+                         const int* __restrict__ ptr_in, int* __restrict__ cnt)
 {
     int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= npad)
         return;
     int a = perm[s];
+    cnt[s] = a >= 0 ? ptr_in[a + 1] - ptr_in[a] : 0;
     double al = a >= 0 ? alpha[a] : 1.0;
     double th = a >= 0 ? thole[a] : 0.0;
     double dinv = pow(al, -1.0 / 6.0);
@@ -148,7 +175,10 @@ __global__ void k_params(int npad, const int* __restrict__ perm, const double* _
 }
 
 // Single-workgroup exclusive scan: out[i] = sum_{k<i} in[i], out[n] = total.
-__global__ __launch_bounds__(1024) void k_scan_excl(int n, const int* __restrict__ in, int* __restrict__ out)
+// Exclusive scan of n values in one workgroup, out[n] = total (also written to *total_copy when
+// given).
+__global__ __launch_bounds__(1024) void k_scan_excl(int n, const int* __restrict__ in, int* __restrict__ out,
+                                                    int* __restrict__ total_copy)
 {
     // tiles of 4096: four consecutive values per thread (coalesced), a wave scan by shuffles,
     // the sixteen wave totals scanned by wave 0, and the running total carried across tiles
@@ -200,18 +230,11 @@ __global__ __launch_bounds__(1024) void k_scan_excl(int n, const int* __restrict
         carry += carry_s;
         __syncthreads();   // wsum and carry_s are rewritten by the next tile
     }
-    if (t == 0)
+    if (t == 0) {
         out[n] = carry;
-}
-
-__global__ void k_csr_counts(int npad, const int* __restrict__ perm, const int* __restrict__ ptr_in,
-                             int* __restrict__ cnt)
-{
-    int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= npad)
-        return;
-    int a = perm[s];
-    cnt[s] = a >= 0 ? ptr_in[a + 1] - ptr_in[a] : 0;
+        if (total_copy)
+            *total_copy = carry;
+    }
 }
 
 __global__ void k_csr_fill(int npad, const int* __restrict__ perm, const int* __restrict__ slot,
@@ -234,9 +257,10 @@ __global__ void k_csr_fill(int npad, const int* __restrict__ perm, const int* __
 
 // Gather caller positions into slot order, wrap into the box, flag NaN/Inf and (if a reference
 // exists) atoms that moved more than buffer/2 since the list build.
+// ref_out (list build): also keep the positions as the reference of the staleness test.
 __global__ void k_gather_pos(int npad, const int* __restrict__ perm, const double* __restrict__ pos,
                              double3 box, double4* __restrict__ pos_s, const double4* __restrict__ ref,
-                             double half_buf2, int* __restrict__ flags)
+                             double half_buf2, int* __restrict__ flags, double4* __restrict__ ref_out)
 {
     int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= npad)
@@ -244,6 +268,8 @@ __global__ void k_gather_pos(int npad, const int* __restrict__ perm, const doubl
     int a = perm[s];
     if (a < 0) {
         pos_s[s] = make_double4(0.0, 0.0, 0.0, 0.0);
+        if (ref_out)
+            ref_out[s] = make_double4(0.0, 0.0, 0.0, 0.0);
         return;
     }
     double x = pos[3 * a], y = pos[3 * a + 1], z = pos[3 * a + 2];
@@ -258,6 +284,8 @@ __global__ void k_gather_pos(int npad, const int* __restrict__ perm, const doubl
     if (old.x != x || old.y != y || old.z != z)
         atomicOr(flags, kFlagChanged);
     pos_s[s] = make_double4(x, y, z, 0.0);
+    if (ref_out)
+        ref_out[s] = make_double4(x, y, z, 0.0);
     if (ref) {
         double4 r0 = ref[s];
         double dx = mimg(x - r0.x, box.x), dy = mimg(y - r0.y, box.y), dz = mimg(z - r0.z, box.z);
@@ -292,7 +320,8 @@ __global__ void k_block_frame(int npad, const int* __restrict__ perm, const doub
 // Bounding box of each block in coordinates unwrapped around its first atom.
 __global__ __launch_bounds__(64) void k_bbox(int nb, const int* __restrict__ perm,
                                              const double4* __restrict__ pos_s, double3 box,
-                                             double4* __restrict__ bc, double4* __restrict__ bh)
+                                             double4* __restrict__ bc, double4* __restrict__ bh,
+                                             unsigned long long* __restrict__ extent_bits)
 {
     int I = blockIdx.x, lane = threadIdx.x;
     int s = I * kBlock + lane;
@@ -314,35 +343,18 @@ __global__ __launch_bounds__(64) void k_bbox(int nb, const int* __restrict__ per
         mxz = fmax(mxz, __shfl_xor(mxz, off));
     }
     if (lane == 0) {
+        const double hx = 0.5 * (mxx - mnx), hy = 0.5 * (mxy - mny), hz = 0.5 * (mxz - mnz);
         bc[I] = make_double4(o.x + 0.5 * (mnx + mxx), o.y + 0.5 * (mny + mxy), o.z + 0.5 * (mnz + mxz), 0.0);
-        bh[I] = make_double4(0.5 * (mxx - mnx), 0.5 * (mxy - mny), 0.5 * (mxz - mnz), 0.0);
+        bh[I] = make_double4(hx, hy, hz, 0.0);
+        // largest half-extent per axis over all blocks: non-negative doubles order as their bit
+        // patterns, so an integer maximum is exact and order-independent (NaN, from non-finite
+        // positions, orders above every finite value)
+        atomicMax(&extent_bits[0], (unsigned long long)__double_as_longlong(hx));
+        atomicMax(&extent_bits[1], (unsigned long long)__double_as_longlong(hy));
+        atomicMax(&extent_bits[2], (unsigned long long)__double_as_longlong(hz));
     }
 }
 
-// Largest block half-extent per axis (one workgroup; max is order-independent).
-__global__ __launch_bounds__(256) void k_extent_max(int nb, const double4* __restrict__ bh, double* __restrict__ out)
-{
-    __shared__ double sh[3][256];
-    double m0 = 0.0, m1 = 0.0, m2 = 0.0;
-    for (int I = threadIdx.x; I < nb; I += 256) {
-        const double4 h = bh[I];
-        m0 = fmax(m0, h.x);
-        m1 = fmax(m1, h.y);
-        m2 = fmax(m2, h.z);
-    }
-    sh[0][threadIdx.x] = m0;
-    sh[1][threadIdx.x] = m1;
-    sh[2][threadIdx.x] = m2;
-    __syncthreads();
-    for (int off = 128; off > 0; off >>= 1) {
-        if (threadIdx.x < off)
-            for (int a = 0; a < 3; ++a)
-                sh[a][threadIdx.x] = fmax(sh[a][threadIdx.x], sh[a][threadIdx.x + off]);
-        __syncthreads();
-    }
-    if (threadIdx.x < 3)
-        out[threadIdx.x] = sh[threadIdx.x][0];
-}
 
 __device__ __forceinline__ int wave_excl_scan_i(int x, int lane, int& total)
 {
@@ -410,7 +422,7 @@ __global__ __launch_bounds__(256) void k_filter(int nb, const int* __restrict__ 
                                                 const double4* __restrict__ bc, const double4* __restrict__ bh,
                                                 const double* __restrict__ ext, double3 box, double3 binv,
                                                 double rcb, int* __restrict__ row_count, int* __restrict__ row_j,
-                                                int* __restrict__ flags)
+                                                int* __restrict__ tpb, int* __restrict__ flags)
 {
     __shared__ float4 s_i[kBlock];                       // i atoms relative to the block centre, w = real atom
     __shared__ unsigned long long s_keep[kFiltChunk];    // kept atoms of each candidate of the chunk
@@ -528,17 +540,12 @@ __global__ __launch_bounds__(256) void k_filter(int nb, const int* __restrict__ 
         count += s_off[kFiltChunk];
     }
     if (tid == 0) {
-        row_count[I] = min(count, kMaxFiltered);
+        const int kept = min(count, kMaxFiltered);
+        row_count[I] = kept;
+        tpb[I] = 1 + (kept + kBlock - 1) / kBlock;  // the diagonal tile and the filtered j-atoms
         if (count > kMaxFiltered)
             atomicOr(flags, kFlagFilterOverflow);
     }
-}
-
-__global__ void k_tiles_per_block(int nb, const int* __restrict__ row_count, int* __restrict__ tpb)
-{
-    int I = blockIdx.x * blockDim.x + threadIdx.x;
-    if (I < nb)
-        tpb[I] = 1 + (row_count[I] + kBlock - 1) / kBlock;
 }
 
 __global__ __launch_bounds__(64) void k_fill_tiles(int nb, const int* __restrict__ tile0,
@@ -581,8 +588,8 @@ __global__ void k_rev_fill(int ntiles, const int* __restrict__ tile_blk, const i
     if (t >= ntiles || t == tile0[tile_blk[t]])
         return;
     int sj = tile_j[(size_t)t * kBlock + k];
-    if (sj >= 0)
-        rev_idx[rev_ptr[sj] + atomicAdd(&cursor[sj], 1)] = t * kBlock + k;
+    if (sj >= 0)  // the cursor counts down from the slot's count: zero again afterwards
+        rev_idx[rev_ptr[sj] + atomicSub(&cursor[sj], 1) - 1] = t * kBlock + k;
 }
 
 // Each slot's reverse entries in increasing order: up to kRevLds entries sorted in LDS (one
@@ -735,22 +742,20 @@ __global__ __launch_bounds__(256) void k_sum_pairs(int n, const unsigned long lo
 
 static inline int nblk(long n, int b) { return (int)((n + b - 1) / b); }
 
-int device_scan(amoeba_ctx* c, int n, const int* in, int* out)
+int device_scan(amoeba_ctx* c, int n, const int* in, int* out, int* total_copy)
 {
     hipStream_t st = c->stream;
     if (n <= 65536) {
-        hipLaunchKernelGGL(k_scan_excl, dim3(1), dim3(1024), 0, st, n, in, out);
+        hipLaunchKernelGGL(k_scan_excl, dim3(1), dim3(1024), 0, st, n, in, out, total_copy);
         return AMOEBA_OK;
     }
     const int cap = c->npad / 1024 + 2;
     int nbk = nblk(n, 1024);
-    if (nbk + 1 > cap)
+    if (nbk + 1 > cap || total_copy)
         return set_error(c, AMOEBA_E_INVALID, "device_scan: scratch too small");
     int* bsum = c->b_scan;
-    int* boff = c->b_scan + cap;
     hipLaunchKernelGGL(k_scan_blocksum, dim3(nbk), dim3(256), 0, st, n, in, bsum);
-    hipLaunchKernelGGL(k_scan_excl, dim3(1), dim3(1024), 0, st, nbk, bsum, boff);
-    hipLaunchKernelGGL(k_scan_apply, dim3(nbk), dim3(256), 0, st, n, in, boff, out);
+    hipLaunchKernelGGL(k_scan_apply, dim3(nbk), dim3(256), 0, st, n, in, bsum, out);
     return AMOEBA_OK;
 }
 
@@ -758,12 +763,10 @@ int sort_params(amoeba_ctx* c)
 {
     hipStream_t st = c->stream;
     coef_invalidate(c);  // the coefficients depend on the polarizabilities and Thole factors
-    hipLaunchKernelGGL(k_params, dim3(nblk(c->npad, 256)), dim3(256), 0, st, c->npad, c->perm, c->alpha_in,
-                       c->thole_in, c->par_d, c->par_f);
-    // scaled-pair CSR in slot order
+    // parameters and the scaled-pair CSR in slot order
     int* cnt = c->b_cnt;
-    hipLaunchKernelGGL(k_csr_counts, dim3(nblk(c->npad, 256)), dim3(256), 0, st, c->npad, c->perm, c->sc_ptr_in,
-                       cnt);
+    hipLaunchKernelGGL(k_params, dim3(nblk(c->npad, 256)), dim3(256), 0, st, c->npad, c->perm, c->alpha_in,
+                       c->thole_in, c->par_d, c->par_f, c->sc_ptr_in, cnt);
     int rcs = device_scan(c, c->npad, cnt, c->sc_ptr);
     if (rcs)
         return rcs;
@@ -774,6 +777,24 @@ int sort_params(amoeba_ctx* c)
 }
 
 void pme_bin_atoms(amoeba_ctx* c);
+
+// Rows of the stored pair coefficients of the current masks; their total reaches the host with
+// its next wait.
+void coef_scan_rows(amoeba_ctx* c)
+{
+    const bool scan_fits = c->ntiles <= 65536 || nblk(c->ntiles, 1024) + 1 <= c->npad / 1024 + 2;
+    if (c->ntiles > 0 && scan_fits && device_scan(c, c->ntiles, c->tile_rows, c->coef_row0) == AMOEBA_OK) {
+        hipMemcpyAsync(c->flags_host + 10, c->coef_row0 + c->ntiles, sizeof(int), hipMemcpyDeviceToHost, c->stream);
+        c->coef_rows_ok = true;
+        c->coef_rows_pending = true;
+    }
+}
+
+// Sum of the mask refresh's per-workgroup pair counts into counter[0] (read by amoeba_get_info).
+void launch_sum_pairs(amoeba_ctx* c)
+{
+    hipLaunchKernelGGL(k_sum_pairs, dim3(1), dim3(256), 0, c->stream, c->pair_nwg, c->pair_part, c->counter);
+}
 
 static int refresh_tiles(amoeba_ctx* c)
 {
@@ -788,17 +809,12 @@ static int refresh_tiles(amoeba_ctx* c)
                        c->ntiles, c->tile_blk, c->tile_j, c->perm,
                        c->pos_s, c->blk_org, c->off_f, box, binv, c->prm.cutoff * c->prm.cutoff, c->tile_mask,
                        c->jrel_d, c->jrel_f, c->tile_np, c->tile_rows, c->pair_part);
-    hipLaunchKernelGGL(k_sum_pairs, dim3(1), dim3(256), 0, st, nwg, c->pair_part, c->counter);
-    c->pairs_pending = true;
-    // rows of the stored pair coefficients; their total reaches the host with its next wait
+    c->pair_nwg = nwg;
+    c->pairs_pending = true;  // summed (k_sum_pairs) when amoeba_get_info asks for the count
     coef_invalidate(c);
     c->coef_rows_ok = false;
-    const bool scan_fits = c->ntiles <= 65536 || nblk(c->ntiles, 1024) + 1 <= c->npad / 1024 + 2;
-    if (c->ntiles > 0 && scan_fits && device_scan(c, c->ntiles, c->tile_rows, c->coef_row0) == AMOEBA_OK) {
-        hipMemcpyAsync(c->flags_host + 10, c->coef_row0 + c->ntiles, sizeof(int), hipMemcpyDeviceToHost, st);
-        c->coef_rows_ok = true;
-        c->coef_rows_pending = true;
-    }
+    if (coef_store_on(c))
+        coef_scan_rows(c);
     pme_bin_atoms(c);
     return AMOEBA_OK;
 }
@@ -831,7 +847,7 @@ int build_blocklist(amoeba_ctx* c, const double* pos)
             (rc = ctx_alloc(c, (void**)&c->b_rowc, sizeof(int) * nb)) ||
             (rc = ctx_alloc(c, (void**)&c->b_rowj, sizeof(int) * (size_t)nb * kMaxFiltered)) ||
             (rc = ctx_alloc(c, (void**)&c->b_tpb, sizeof(int) * (nb + 1))) ||
-            (rc = ctx_alloc(c, (void**)&c->b_extent, sizeof(double) * 4)))
+            (rc = ctx_alloc(c, (void**)&c->rev_cnt, sizeof(int) * (npad + 1))))
             return rc;
         size_t tb = 0;
         if (rocprim::radix_sort_keys(nullptr, tb, c->b_keys, c->b_keys2, n, 0u, end_bit, st) != hipSuccess)
@@ -844,7 +860,10 @@ int build_blocklist(amoeba_ctx* c, const double* pos)
     double4 *bc = c->b_bc, *bh = c->b_bh;
     int *row_count = c->b_rowc, *row_j = c->b_rowj, *tpb = c->b_tpb, *t0 = c->blk_tile0;
     auto fail = [&](int code) { return code; };
-    hipLaunchKernelGGL(k_sort_keys, dim3(nblk(n, 256)), dim3(256), 0, st, n, pos, box, ny, nz, ib, colbits, keys);
+    // build status words, read back with one copy: flags[0] error flags, flags[1] the tile
+    // count, flags[4..9] the largest block half-extents (b_extent)
+    hipLaunchKernelGGL(k_sort_keys, dim3(nblk(n, 256)), dim3(256), 0, st, n, pos, box, ny, nz, ib, colbits, keys,
+                       c->flags, (unsigned long long*)c->b_extent);
     {
         size_t tb = c->b_sort_bytes;
         if (rocprim::radix_sort_keys(c->b_sort_tmp, tb, keys, c->b_keys2, n, 0u, end_bit, st) != hipSuccess)
@@ -854,24 +873,19 @@ int build_blocklist(amoeba_ctx* c, const double* pos)
     if (c->atoms_set && (rc = sort_params(c)) != AMOEBA_OK)
         return fail(rc);
 
-    hipMemsetAsync(c->flags, 0, sizeof(int), st);
     hipLaunchKernelGGL(k_gather_pos, dim3(nblk(npad, 256)), dim3(256), 0, st, npad, c->perm, pos, box, c->pos_s,
-                       (const double4*)nullptr, 0.0, c->flags);
-    hipMemcpyAsync(c->pos_ref, c->pos_s, sizeof(double4) * npad, hipMemcpyDeviceToDevice, st);
-    hipLaunchKernelGGL(k_bbox, dim3(nb), dim3(64), 0, st, nb, c->perm, c->pos_s, box, bc, bh);
-    hipLaunchKernelGGL(k_extent_max, dim3(1), dim3(256), 0, st, nb, bh, c->b_extent);
+                       (const double4*)nullptr, 0.0, c->flags, c->pos_ref);
+    hipLaunchKernelGGL(k_bbox, dim3(nb), dim3(64), 0, st, nb, c->perm, c->pos_s, box, bc, bh,
+                       (unsigned long long*)c->b_extent);
     double3 binv = make_double3(1.0 / box.x, 1.0 / box.y, 1.0 / box.z);
     hipLaunchKernelGGL(k_filter, dim3(nb), dim3(256), 0, st, nb, c->perm, c->pos_s, bc, bh, c->b_extent, box, binv,
-                       c->prm.cutoff + c->prm.buffer, row_count, row_j, c->flags);
-    hipLaunchKernelGGL(k_tiles_per_block, dim3(nblk(nb, 256)), dim3(256), 0, st, nb, row_count, tpb);
-    if ((rc = device_scan(c, nb, tpb, t0)))
+                       c->prm.cutoff + c->prm.buffer, row_count, row_j, tpb, c->flags);
+    if ((rc = device_scan(c, nb, tpb, t0, c->flags + 1)))
         return rc;
-    int total = 0;
-    hipMemcpyAsync(&total, t0 + nb, sizeof(int), hipMemcpyDeviceToHost, st);
-    hipMemcpyAsync(c->flags_host, c->flags, sizeof(int), hipMemcpyDeviceToHost, st);
-    hipMemcpyAsync(c->flags_host + 4, c->b_extent, 3 * sizeof(double), hipMemcpyDeviceToHost, st);
+    hipMemcpyAsync(c->flags_host, c->flags, 4 * sizeof(int) + 3 * sizeof(double), hipMemcpyDeviceToHost, st);
     if ((rc = hip_check(c, hipStreamSynchronize(st), "build_blocklist")))
         return fail(rc);
+    const int total = c->flags_host[1];
     {
         // Every j-atom of a tile lies within cutoff + buffer of an atom of the i-block at the
         // build, and atoms move at most buffer/2 before the list goes stale, so a tile
@@ -917,15 +931,16 @@ int build_blocklist(amoeba_ctx* c, const double* pos)
     c->ntiles = total;
     hipLaunchKernelGGL(k_fill_tiles, dim3(nb), dim3(64), 0, st, nb, t0, row_count, row_j, c->tile_blk, c->tile_j);
     {
+        // rev_cnt is zero between builds (zeroed at allocation; the fill counts it back down)
         const long nthr = (long)total * kBlock;
-        hipMemsetAsync(c->b_cnt, 0, sizeof(int) * (npad + 1), st);
         hipLaunchKernelGGL(k_rev_count, dim3(nblk(nthr, 256)), dim3(256), 0, st, total, c->tile_blk, t0, c->tile_j,
-                           c->b_cnt);
-        if ((rc = device_scan(c, npad, c->b_cnt, c->rev_ptr)))
+                           c->rev_cnt);
+        if ((rc = device_scan(c, npad, c->rev_cnt, c->rev_ptr))) {
+            hipMemsetAsync(c->rev_cnt, 0, sizeof(int) * (npad + 1), st);
             return rc;
-        hipMemsetAsync(c->b_cnt, 0, sizeof(int) * (npad + 1), st);
+        }
         hipLaunchKernelGGL(k_rev_fill, dim3(nblk(nthr, 256)), dim3(256), 0, st, total, c->tile_blk, t0, c->tile_j,
-                           c->rev_ptr, c->b_cnt, c->rev_idx);
+                           c->rev_ptr, c->rev_cnt, c->rev_idx);
         hipLaunchKernelGGL(k_rev_sort, dim3(nblk(npad, 256)), dim3(256), 0, st, npad, c->rev_ptr, c->rev_idx);
     }
     refresh_tiles(c);   // the pair count is read when amoeba_get_info asks for it
@@ -941,7 +956,7 @@ int prepare_config(amoeba_ctx* c, const double* pos)
     double hb = 0.5 * c->prm.buffer;
     hipMemsetAsync(c->flags, 0, sizeof(int), st);
     hipLaunchKernelGGL(k_gather_pos, dim3(nblk(c->npad, 256)), dim3(256), 0, st, c->npad, c->perm, pos, box,
-                       c->pos_s, (const double4*)c->pos_ref, hb * hb, c->flags);
+                       c->pos_s, (const double4*)c->pos_ref, hb * hb, c->flags, (double4*)nullptr);
     hipMemcpyAsync(c->flags_host, c->flags, sizeof(int), hipMemcpyDeviceToHost, st);
     int rc = hip_check(c, hipStreamSynchronize(st), "prepare_config");
     if (rc)

@@ -105,7 +105,7 @@ struct amoeba_ctx {
     int64_t n_scaled = 0;
     int ntiles = 0, tile_cap = 0;
     bool skip_mimg = false;        // pair kernels may skip the minimum image (set per list build)
-    double* b_extent = nullptr;    // [4] device: largest block half-extent per axis (list build)
+    double* b_extent = nullptr;    // [3] device, flags + 4: largest block half-extent per axis (list build)
     int64_t n_pairs = 0;
     int last_iters = 0;
     double last_rms = 0.0;
@@ -215,7 +215,8 @@ struct amoeba_ctx {
     int* flags_host = nullptr;             // pinned
     unsigned long long* counter = nullptr; // device counters (pairs)
     unsigned long long* pair_part = nullptr; // per-workgroup pair counts of the mask refresh
-    bool pairs_pending = false;            // counter holds a pair count not yet read to n_pairs
+    bool pairs_pending = false;            // pair_part holds a pair count not yet read to n_pairs
+    int pair_nwg = 0;                      // pair_part entries of the last mask refresh
     hipEvent_t ev[2] = {nullptr, nullptr};
     // the real-space tiles of a PCG product run on a second stream (default priority), beside
     // the reciprocal passes on the context stream: forked and joined with events
@@ -242,6 +243,7 @@ struct amoeba_ctx {
     int* b_rowj = nullptr;                 // [nb * kMaxFiltered]
     int* b_tpb = nullptr;                  // [nb + 1] tiles per block
     int* b_cnt = nullptr;                  // [npad + 1] per-slot counts
+    int* rev_cnt = nullptr;                // [npad + 1] reverse-index counters, zero between builds
     int* b_scan = nullptr;                 // [npad / 1024 + 2] scan block sums / offsets
 
     // learned initial guess (guess.hip); allocated by the first amoeba_guess_set_model
@@ -288,7 +290,10 @@ struct StageTimer {
 };
 
 // blocklist.hip
-int device_scan(amoeba_ctx* c, int n, const int* in, int* out);  // exclusive, out[n] = total
+// exclusive, out[n] = total; total_copy (n <= 65536 only): a second place for the total
+int device_scan(amoeba_ctx* c, int n, const int* in, int* out, int* total_copy = nullptr);
+void coef_scan_rows(amoeba_ctx* c);       // rows of the coefficient store for the current masks
+void launch_sum_pairs(amoeba_ctx* c);     // pair count of the last mask refresh into counter[0]
 int build_blocklist(amoeba_ctx* c, const double* pos);
 int prepare_config(amoeba_ctx* c, const double* pos);
 

@@ -857,7 +857,9 @@ __global__ void k_xybin_fill(int npad, const int* __restrict__ perm, const doubl
     grid_coord(p.y, kl.y, K.y, f[1], u[1]);
     grid_coord(p.z, kl.z, K.z, f[2], u[2]);
     const int b = f[0] * K.y + f[1];
-    const int e = start[b] + atomicAdd(&cursor[b], 1);
+    // the cursor starts at the bin's count and counts down to zero, which leaves the counters
+    // cleared for the next binning
+    const int e = start[b] + atomicSub(&cursor[b], 1) - 1;
     rec[e] = make_int4(s, f[0], f[1], f[2]);
     wout[e] = typename PlT<R>::R4{(R)u[0], (R)u[1], (R)u[2], (R)0};
 }
@@ -979,13 +981,14 @@ int plane_bin_atoms(amoeba_ctx* c)
     const int nb2 = c->K[0] * c->K[1];
     int3 K = make_int3(c->K[0], c->K[1], c->K[2]);
     double3 kl = make_double3(c->K[0] / c->prm.box[0], c->K[1] / c->prm.box[1], c->K[2] / c->prm.box[2]);
-    hipMemsetAsync(c->xb_count, 0, sizeof(int) * (nb2 + 1), st);
+    // xb_count is zero between binnings (zeroed at allocation; the fill counts it back down)
     hipLaunchKernelGGL(k_xybin_count, dim3(nblk(c->npad, 256)), dim3(256), 0, st, c->npad, c->perm, c->pos_s, kl, K,
                        c->xb_count);
     int rc = device_scan(c, nb2, c->xb_count, c->xb_start);
-    if (rc)
+    if (rc) {
+        hipMemsetAsync(c->xb_count, 0, sizeof(int) * (nb2 + 1), st);
         return rc;
-    hipMemsetAsync(c->xb_count, 0, sizeof(int) * (nb2 + 1), st);
+    }
     if (c->mixed)
         hipLaunchKernelGGL(k_xybin_fill<float>, dim3(nblk(c->npad, 256)), dim3(256), 0, st, c->npad, c->perm,
                            c->pos_s, kl, K, c->xb_start, c->xb_count, c->xb_rec, (float4*)c->xb_w);
