@@ -37,12 +37,15 @@ __device__ __forceinline__ double wrap_box(double x, double L)
 }
 
 // Sort key of atom a: column (cz, cy) in a serpentine order, then x within the column (also
-// serpentine), then the atom index; packed as col | xq (16 bits) | a (ib bits) so that a radix
-// sort over the low ib + 16 + colbits bits orders it.  The largest column value is kept for
-// non-finite positions, which sort last (the gather check reports them).
+// serpentine) quantised to kXBits bits (box / 4096, far below the block size); packed as
+// col | xq.  The sort is stable and the values are the atom indices in increasing order, so that
+// equal keys keep index order and the result is deterministic.  The largest column value is kept
+// for non-finite positions, which sort last (the gather check reports them).
 // Also clears the build's status words (error flags, the block extent maxima of k_bbox).
-__global__ void k_sort_keys(int n, const double* __restrict__ pos, double3 box, int ny, int nz, int ib,
-                            int colbits, unsigned long long* __restrict__ keys, int* __restrict__ flags,
+constexpr int kXBits = 12;
+
+__global__ void k_sort_keys(int n, const double* __restrict__ pos, double3 box, int ny, int nz, int colbits,
+                            unsigned* __restrict__ keys, int* __restrict__ vals, int* __restrict__ flags,
                             unsigned long long* __restrict__ extent_bits)
 {
     int a = blockIdx.x * blockDim.x + threadIdx.x;
@@ -55,21 +58,23 @@ __global__ void k_sort_keys(int n, const double* __restrict__ pos, double3 box, 
         return;
     double x = wrap_box(pos[3 * a], box.x), y = wrap_box(pos[3 * a + 1], box.y),
            z = wrap_box(pos[3 * a + 2], box.z);
-    unsigned long long col, xq;
+    unsigned col, xq;
+    const unsigned xmax = (1u << kXBits) - 1u;
     if (!(x == x) || !(y == y) || !(z == z)) {
-        col = (1ull << colbits) - 1ull;
-        xq = 65535ull;
+        col = (1u << colbits) - 1u;
+        xq = xmax;
     } else {
         int cy = min(ny - 1, (int)(y / box.y * ny));
         int cz = min(nz - 1, (int)(z / box.z * nz));
         int cys = (cz & 1) ? ny - 1 - cy : cy;
-        col = (unsigned long long)(cz * ny + cys);
-        unsigned q = min(65535u, (unsigned)(x / box.x * 65536.0));
-        if (col & 1ull)
-            q = 65535u - q;
+        col = (unsigned)(cz * ny + cys);
+        unsigned q = min(xmax, (unsigned)(x / box.x * (double)(1u << kXBits)));
+        if (col & 1u)
+            q = xmax - q;
         xq = q;
     }
-    keys[a] = (col << (16 + ib)) | (xq << ib) | (unsigned long long)a;
+    keys[a] = (col << kXBits) | xq;
+    vals[a] = a;
 }
 
 // Two-phase exclusive scan for long arrays: block sums (1024 per workgroup), then block-local
@@ -142,14 +147,14 @@ __global__ __launch_bounds__(256) void k_scan_apply(int n, const int* __restrict
 }
 
 
-__global__ void k_perm(int n, int npad, const unsigned long long* __restrict__ keys, int ib, int* __restrict__ perm,
+__global__ void k_perm(int n, int npad, const int* __restrict__ sorted_atoms, int* __restrict__ perm,
                        int* __restrict__ slot)
 {
     int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= npad)
         return;
     if (s < n) {
-        int a = (int)(keys[s] & ((1ull << ib) - 1ull));
+        int a = sorted_atoms[s];
         perm[s] = a;
         slot[a] = s;
     } else {
@@ -835,13 +840,15 @@ int build_blocklist(amoeba_ctx* c, const double* pos)
             ++b;
         return b;
     };
-    const int ib = bits_for(n), colbits = bits_for((long long)ny * nz) + 1;
-    const unsigned end_bit = (unsigned)(ib + 16 + colbits);
+    const int colbits = bits_for((long long)ny * nz) + 1;
+    const unsigned end_bit = (unsigned)(kXBits + colbits);
 
     int rc = AMOEBA_OK;
     if (!c->b_keys) {
-        if ((rc = ctx_alloc(c, (void**)&c->b_keys, sizeof(unsigned long long) * n)) ||
-            (rc = ctx_alloc(c, (void**)&c->b_keys2, sizeof(unsigned long long) * n)) ||
+        if ((rc = ctx_alloc(c, (void**)&c->b_keys, sizeof(unsigned) * n)) ||
+            (rc = ctx_alloc(c, (void**)&c->b_keys2, sizeof(unsigned) * n)) ||
+            (rc = ctx_alloc(c, (void**)&c->b_vals, sizeof(int) * n)) ||
+            (rc = ctx_alloc(c, (void**)&c->b_vals2, sizeof(int) * n)) ||
             (rc = ctx_alloc(c, (void**)&c->b_bc, sizeof(double4) * nb)) ||
             (rc = ctx_alloc(c, (void**)&c->b_bh, sizeof(double4) * nb)) ||
             (rc = ctx_alloc(c, (void**)&c->b_rowc, sizeof(int) * nb)) ||
@@ -850,26 +857,28 @@ int build_blocklist(amoeba_ctx* c, const double* pos)
             (rc = ctx_alloc(c, (void**)&c->rev_cnt, sizeof(int) * (npad + 1))))
             return rc;
         size_t tb = 0;
-        if (rocprim::radix_sort_keys(nullptr, tb, c->b_keys, c->b_keys2, n, 0u, end_bit, st) != hipSuccess)
+        if (rocprim::radix_sort_pairs(nullptr, tb, c->b_keys, c->b_keys2, c->b_vals, c->b_vals2, n, 0u, 32u, st) !=
+            hipSuccess)
             return set_error(c, AMOEBA_E_DEVICE, "build_blocklist: radix sort size query failed");
         if ((rc = ctx_alloc(c, &c->b_sort_tmp, tb)))
             return rc;
         c->b_sort_bytes = tb;
     }
-    unsigned long long* keys = c->b_keys;
+    unsigned* keys = c->b_keys;
     double4 *bc = c->b_bc, *bh = c->b_bh;
     int *row_count = c->b_rowc, *row_j = c->b_rowj, *tpb = c->b_tpb, *t0 = c->blk_tile0;
     auto fail = [&](int code) { return code; };
     // build status words, read back with one copy: flags[0] error flags, flags[1] the tile
     // count, flags[4..9] the largest block half-extents (b_extent)
-    hipLaunchKernelGGL(k_sort_keys, dim3(nblk(n, 256)), dim3(256), 0, st, n, pos, box, ny, nz, ib, colbits, keys,
-                       c->flags, (unsigned long long*)c->b_extent);
+    hipLaunchKernelGGL(k_sort_keys, dim3(nblk(n, 256)), dim3(256), 0, st, n, pos, box, ny, nz, colbits, keys,
+                       c->b_vals, c->flags, (unsigned long long*)c->b_extent);
     {
         size_t tb = c->b_sort_bytes;
-        if (rocprim::radix_sort_keys(c->b_sort_tmp, tb, keys, c->b_keys2, n, 0u, end_bit, st) != hipSuccess)
+        if (rocprim::radix_sort_pairs(c->b_sort_tmp, tb, keys, c->b_keys2, c->b_vals, c->b_vals2, n, 0u, end_bit,
+                                      st) != hipSuccess)
             return set_error(c, AMOEBA_E_DEVICE, "build_blocklist: radix sort failed");
     }
-    hipLaunchKernelGGL(k_perm, dim3(nblk(npad, 256)), dim3(256), 0, st, n, npad, c->b_keys2, ib, c->perm, c->slot);
+    hipLaunchKernelGGL(k_perm, dim3(nblk(npad, 256)), dim3(256), 0, st, n, npad, c->b_vals2, c->perm, c->slot);
     if (c->atoms_set && (rc = sort_params(c)) != AMOEBA_OK)
         return fail(rc);
 

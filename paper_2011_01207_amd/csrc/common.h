@@ -233,8 +233,10 @@ struct amoeba_ctx {
     int pcg_seq = 0;                       // direction kernels enqueued since the solve began
 
     // list-build scratch, kept between builds
-    unsigned long long* b_keys = nullptr;  // [n] sort keys
-    unsigned long long* b_keys2 = nullptr; // [n] sorted keys
+    unsigned* b_keys = nullptr;            // [n] sort keys (column | x)
+    unsigned* b_keys2 = nullptr;           // [n] sorted keys
+    int* b_vals = nullptr;                 // [n] atom indices
+    int* b_vals2 = nullptr;                // [n] atom indices in key order
     void* b_sort_tmp = nullptr;            // radix sort scratch
     size_t b_sort_bytes = 0;
     double4* b_bc = nullptr;               // [nb] block box centres
