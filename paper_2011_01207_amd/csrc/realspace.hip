@@ -96,7 +96,7 @@ __device__ __forceinline__ float d_rint(float x) { return rintf(x); }
 __device__ __forceinline__ double d_rint(double x) { return rint(x); }
 
 constexpr int kWavesPerWG = 4;
-constexpr int kTileCost = 128;  // per-tile cost of staging and scanning, in units of pairs
+constexpr int kTileCost = 256;  // per-tile cost of staging and scanning, in units of pairs (measured)
 
 // How a dipole tile gets the radial coefficients of its pairs (the paper's option of storing the
 // real-space matrix elements before the PCG iterations): evaluate them, evaluate and store them,
