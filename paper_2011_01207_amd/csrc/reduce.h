@@ -9,26 +9,29 @@
 
 namespace amoeba {
 
-// Sum of NV values over the 256 threads of a workgroup, fixed tree order; every thread gets
-// the totals.  Must be reached by all threads of the workgroup.
+// Sum of NV values over the 256 threads of a workgroup, in a fixed order; every thread gets
+// the totals.  Each wave folds its 64 values with shuffles (lane 0's association order is the
+// one kept), then the four wave sums are added in wave order.  Must be reached by all threads
+// of the workgroup.
 template <int NV>
 __device__ __forceinline__ void block_sum(double (&v)[NV])
 {
-    __shared__ double sh[NV][256];
-    const int tid = threadIdx.x;
+    __shared__ double sh[NV][4];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+        for (int k = 0; k < NV; ++k)
+            v[k] += __shfl_xor(v[k], off);
+    __syncthreads();   // an earlier call's readers are done with sh
+    if (lane == 0)
+#pragma unroll
+        for (int k = 0; k < NV; ++k)
+            sh[k][w] = v[k];
     __syncthreads();
+#pragma unroll
     for (int k = 0; k < NV; ++k)
-        sh[k][tid] = v[k];
-    __syncthreads();
-    for (int off = 128; off > 0; off >>= 1) {
-        if (tid < off)
-            for (int k = 0; k < NV; ++k)
-                sh[k][tid] += sh[k][tid + off];
-        __syncthreads();
-    }
-    for (int k = 0; k < NV; ++k)
-        v[k] = sh[k][0];
-    __syncthreads();
+        v[k] = (sh[k][0] + sh[k][1]) + (sh[k][2] + sh[k][3]);
 }
 
 // Total of n partials of NV values each (layout [n][NV]), in a fixed order; every thread of
