@@ -20,7 +20,7 @@ constexpr double kCoulomb = 332.0637133;         // kcal*A/(mol e^2)
 constexpr double kDebye = 4.80320;               // D per e*A
 constexpr int kBrick = 8;                        // PME spread brick edge (grid points)
 constexpr int kMaxFiltered = 2048;               // filtered j-atoms per block (list build)
-constexpr int kRedBlocks = 256;                  // workgroups of the deterministic reductions
+constexpr int kRedBlocks = 512;                  // workgroups of the deterministic reductions
 constexpr double kPi = 3.14159265358979323846;
 
 // Device flags written by validation / preparation kernels.
