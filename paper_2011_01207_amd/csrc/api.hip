@@ -323,7 +323,7 @@ int amoeba_create(const amoeba_params* p, void* hip_stream, amoeba_ctx** out)
             (rc = ctx_alloc(c, (void**)&c->v_e, sizeof(double) * n3)) ||
             (rc = ctx_alloc(c, (void**)&c->sc, sizeof(PcgScalars))) ||
             (rc = ctx_alloc(c, (void**)&c->red.part, sizeof(double) * part_n)) ||
-            (rc = ctx_alloc(c, (void**)&c->flags, sizeof(int) * 16)) ||
+            (rc = ctx_alloc(c, (void**)&c->flags, sizeof(int) * 256)) ||
             (rc = ctx_alloc(c, (void**)&c->counter, sizeof(unsigned long long) * 2)) ||
             (rc = ctx_alloc(c, (void**)&c->b_cnt, sizeof(int) * (np + 1))) ||
             (rc = ctx_alloc(c, (void**)&c->b_scan, sizeof(int) * 2 * (np / 1024 + 2))))

@@ -43,17 +43,17 @@ __device__ __forceinline__ double wrap_box(double x, double L)
 // for non-finite positions, which sort last (the gather check reports them).
 // Also clears the build's status words (error flags, the block extent maxima of k_bbox).
 constexpr int kXBits = 12;
+constexpr int kExtSlots = 32;  // block-extent maxima kept in this many slots (less atomic contention)
 
 __global__ void k_sort_keys(int n, const double* __restrict__ pos, double3 box, int ny, int nz, int colbits,
                             unsigned* __restrict__ keys, int* __restrict__ vals, int* __restrict__ flags,
                             unsigned long long* __restrict__ extent_bits)
 {
     int a = blockIdx.x * blockDim.x + threadIdx.x;
-    if (a == 0) {
+    if (a == 0)
         flags[0] = 0;
-        for (int d = 0; d < 3; ++d)
-            extent_bits[d] = 0ull;
-    }
+    if (a < 3 * kExtSlots)
+        extent_bits[a] = 0ull;
     if (a >= n)
         return;
     double x = wrap_box(pos[3 * a], box.x), y = wrap_box(pos[3 * a + 1], box.y),
@@ -351,12 +351,13 @@ __global__ __launch_bounds__(64) void k_bbox(int nb, const int* __restrict__ per
         const double hx = 0.5 * (mxx - mnx), hy = 0.5 * (mxy - mny), hz = 0.5 * (mxz - mnz);
         bc[I] = make_double4(o.x + 0.5 * (mnx + mxx), o.y + 0.5 * (mny + mxy), o.z + 0.5 * (mnz + mxz), 0.0);
         bh[I] = make_double4(hx, hy, hz, 0.0);
-        // largest half-extent per axis over all blocks: non-negative doubles order as their bit
-        // patterns, so an integer maximum is exact and order-independent (NaN, from non-finite
-        // positions, orders above every finite value)
-        atomicMax(&extent_bits[0], (unsigned long long)__double_as_longlong(hx));
-        atomicMax(&extent_bits[1], (unsigned long long)__double_as_longlong(hy));
-        atomicMax(&extent_bits[2], (unsigned long long)__double_as_longlong(hz));
+        // largest half-extent per axis over the blocks of slot I mod kExtSlots (the filter takes
+        // the maximum over the slots): non-negative doubles order as their bit patterns, so an
+        // integer maximum is exact and order-independent
+        unsigned long long* slot = extent_bits + 3 * (I % kExtSlots);
+        atomicMax(&slot[0], (unsigned long long)__double_as_longlong(hx));
+        atomicMax(&slot[1], (unsigned long long)__double_as_longlong(hy));
+        atomicMax(&slot[2], (unsigned long long)__double_as_longlong(hz));
     }
 }
 
@@ -425,7 +426,8 @@ constexpr int kFiltChunk = 256;
 __global__ __launch_bounds__(256) void k_filter(int nb, const int* __restrict__ perm,
                                                 const double4* __restrict__ pos_s,
                                                 const double4* __restrict__ bc, const double4* __restrict__ bh,
-                                                const double* __restrict__ ext, double3 box, double3 binv,
+                                                const unsigned long long* __restrict__ ext_slots,
+                                                double* __restrict__ ext_out, double3 box, double3 binv,
                                                 double rcb, int* __restrict__ row_count, int* __restrict__ row_j,
                                                 int* __restrict__ tpb, int* __restrict__ flags)
 {
@@ -468,6 +470,14 @@ __global__ __launch_bounds__(256) void k_filter(int nb, const int* __restrict__ 
     const float hxf = (float)hi.x + 1e-3f, hyf = (float)hi.y + 1e-3f, hzf = (float)hi.z + 1e-3f;
     const float Lx = (float)box.x, Ly = (float)box.y, Lz = (float)box.z;
     const float Lix = (float)binv.x, Liy = (float)binv.y, Liz = (float)binv.z;
+    // largest block half-extents (workgroup 0 also writes them for the host)
+    double ext[3] = {0.0, 0.0, 0.0};
+    for (int k = 0; k < kExtSlots; ++k)
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+            ext[a] = fmax(ext[a], __longlong_as_double((long long)ext_slots[3 * k + a]));
+    if (I == 0 && tid < 3)
+        ext_out[tid] = ext[tid];
     // pair offsets |q - j| <= h_I + (h_I + rcb + margins) <= 2 h_max + rcb
     const bool mi = !(2.0 * ext[0] + rcb + 0.01 < 0.5 * box.x && 2.0 * ext[1] + rcb + 0.01 < 0.5 * box.y &&
                       2.0 * ext[2] + rcb + 0.01 < 0.5 * box.z);
@@ -869,9 +879,11 @@ int build_blocklist(amoeba_ctx* c, const double* pos)
     int *row_count = c->b_rowc, *row_j = c->b_rowj, *tpb = c->b_tpb, *t0 = c->blk_tile0;
     auto fail = [&](int code) { return code; };
     // build status words, read back with one copy: flags[0] error flags, flags[1] the tile
-    // count, flags[4..9] the largest block half-extents (b_extent)
-    hipLaunchKernelGGL(k_sort_keys, dim3(nblk(n, 256)), dim3(256), 0, st, n, pos, box, ny, nz, colbits, keys,
-                       c->b_vals, c->flags, (unsigned long long*)c->b_extent);
+    // count, flags[4..9] the largest block half-extents (b_extent); flags[64..255] the slots
+    // k_bbox collects the half-extents in
+    unsigned long long* ext_slots = reinterpret_cast<unsigned long long*>(c->flags + 64);
+    hipLaunchKernelGGL(k_sort_keys, dim3(nblk(std::max(n, 3 * kExtSlots), 256)), dim3(256), 0, st, n, pos, box, ny,
+                       nz, colbits, keys, c->b_vals, c->flags, ext_slots);
     {
         size_t tb = c->b_sort_bytes;
         if (rocprim::radix_sort_pairs(c->b_sort_tmp, tb, keys, c->b_keys2, c->b_vals, c->b_vals2, n, 0u, end_bit,
@@ -884,10 +896,10 @@ int build_blocklist(amoeba_ctx* c, const double* pos)
 
     hipLaunchKernelGGL(k_gather_pos, dim3(nblk(npad, 256)), dim3(256), 0, st, npad, c->perm, pos, box, c->pos_s,
                        (const double4*)nullptr, 0.0, c->flags, c->pos_ref);
-    hipLaunchKernelGGL(k_bbox, dim3(nb), dim3(64), 0, st, nb, c->perm, c->pos_s, box, bc, bh,
-                       (unsigned long long*)c->b_extent);
+    hipLaunchKernelGGL(k_bbox, dim3(nb), dim3(64), 0, st, nb, c->perm, c->pos_s, box, bc, bh, ext_slots);
     double3 binv = make_double3(1.0 / box.x, 1.0 / box.y, 1.0 / box.z);
-    hipLaunchKernelGGL(k_filter, dim3(nb), dim3(256), 0, st, nb, c->perm, c->pos_s, bc, bh, c->b_extent, box, binv,
+    hipLaunchKernelGGL(k_filter, dim3(nb), dim3(256), 0, st, nb, c->perm, c->pos_s, bc, bh, ext_slots, c->b_extent,
+                       box, binv,
                        c->prm.cutoff + c->prm.buffer, row_count, row_j, tpb, c->flags);
     if ((rc = device_scan(c, nb, tpb, t0, c->flags + 1)))
         return rc;

@@ -211,7 +211,7 @@ struct amoeba_ctx {
     amoeba::PcgScalars* sc_host = nullptr; // pinned mirror [2] (one per in-flight PCG iteration)
     amoeba::PcgScalars* sc_host_dev = nullptr; // its device-side address
     amoeba::RedScratch red{};
-    int* flags = nullptr;                  // device error flags
+    int* flags = nullptr;                  // device error flags and list-build status words [256]
     int* flags_host = nullptr;             // pinned
     unsigned long long* counter = nullptr; // device counters (pairs)
     unsigned long long* pair_part = nullptr; // per-workgroup pair counts of the mask refresh
