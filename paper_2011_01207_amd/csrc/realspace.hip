@@ -639,6 +639,8 @@ __global__ void k_real_reduce(int npad, const double* __restrict__ eipart, const
                               const int* __restrict__ rev_ptr, const int* __restrict__ rev_idx,
                               double* __restrict__ ereal, const PcgScalars* __restrict__ sc, int use_done)
 {
+    // latency bound and beside the reciprocal passes on the other stream: its waves issue first
+    __builtin_amdgcn_s_setprio(3);
     using R4 = typename V4<R>::T;
     if (use_done && sc->done)
         return;
