@@ -307,11 +307,11 @@ int amoeba_set_pair_store(amoeba_ctx* ctx, int32_t mode);
 int amoeba_get_info(const amoeba_ctx* ctx, amoeba_info* out);
 
 /* Kernel-time accounting (diagnostic; used by the benchmark for its roofline figures).
- * When enabled, every launch of the listed stages is bracketed by HIP events on the context's
- * stream; amoeba_get_timing synchronises the stream and returns the accumulated milliseconds
- * and launch counts per stage since the last amoeba_set_timing.  Launches that return early
- * because the solve already converged are included (as a profiler would count them);
- * `matvecs` counts the matrix-vector products that did work. */
+ * When enabled, every launch of the listed stages is bracketed by HIP events on the stream it
+ * runs on; amoeba_get_timing synchronises the context stream and returns the accumulated
+ * milliseconds and launch counts per stage since the last amoeba_set_timing.  Launches that
+ * return early because the solve already converged are included (as a profiler would count
+ * them); `matvecs` counts the matrix-vector products that did work. */
 typedef enum amoeba_stage {
     AMOEBA_T_LIST = 0,     /* list build and per-configuration mask refresh                 */
     AMOEBA_T_PERM = 1,     /* permanent-field tiles and assembly                            */
@@ -331,7 +331,17 @@ typedef struct amoeba_timing {
     int64_t matvecs;
 } amoeba_timing;
 
-/* enable != 0 turns accounting on, 0 off; both reset the counters. */
+/* enable: AMOEBA_TIMING_OFF, AMOEBA_TIMING_STAGES (every stage alone: the products run
+ * their real-space and reciprocal parts one after the other on the context stream, so that
+ * each stage's time is its own) or AMOEBA_TIMING_LIVE (only AMOEBA_T_REAL, on the second
+ * stream where it runs beside the reciprocal passes; the products keep their overlap, and the
+ * time includes the sharing of the GPU: two events per product, light enough to leave on in a
+ * timed run).  Every call resets the counters; any other value: AMOEBA_E_INVALID. */
+typedef enum amoeba_timing_mode {
+    AMOEBA_TIMING_OFF = 0,
+    AMOEBA_TIMING_STAGES = 1,
+    AMOEBA_TIMING_LIVE = 2
+} amoeba_timing_mode;
 int amoeba_set_timing(amoeba_ctx* ctx, int enable);
 int amoeba_get_timing(amoeba_ctx* ctx, amoeba_timing* out);
 

@@ -25,9 +25,9 @@ int hip_check(amoeba_ctx* c, hipError_t e, const char* what)
     return set_error(c, e == hipErrorOutOfMemory ? AMOEBA_E_NOMEM : AMOEBA_E_DEVICE, m);
 }
 
-StageTimer::StageTimer(amoeba_ctx* ctx, int stage) : c(ctx)
+StageTimer::StageTimer(amoeba_ctx* ctx, int stage, hipStream_t stream) : c(ctx), st(stream ? stream : ctx->stream)
 {
-    if (!c->timing)
+    if (!c->timing && !(c->timing_live && stage == AMOEBA_T_REAL))
         return;
     size_t need = c->trec.size() * 2 + 2;
     while (c->tev.size() < need) {
@@ -38,13 +38,13 @@ StageTimer::StageTimer(amoeba_ctx* ctx, int stage) : c(ctx)
     }
     idx = (int)c->trec.size() * 2;
     c->trec.push_back({stage, idx});
-    hipEventRecord(c->tev[idx], c->stream);
+    hipEventRecord(c->tev[idx], st);
 }
 
 StageTimer::~StageTimer()
 {
     if (idx >= 0)
-        hipEventRecord(c->tev[idx + 1], c->stream);
+        hipEventRecord(c->tev[idx + 1], st);
 }
 
 int ctx_alloc(amoeba_ctx* c, void** p, size_t bytes)
@@ -675,8 +675,11 @@ int amoeba_set_timing(amoeba_ctx* c, int enable)
 {
     if (!c)
         return AMOEBA_E_INVALID;
+    if (enable != AMOEBA_TIMING_OFF && enable != AMOEBA_TIMING_STAGES && enable != AMOEBA_TIMING_LIVE)
+        return set_error(c, AMOEBA_E_INVALID, "amoeba_set_timing: unknown mode");
     hipStreamSynchronize(c->stream);
-    c->timing = enable != 0;
+    c->timing = enable == AMOEBA_TIMING_STAGES;
+    c->timing_live = enable == AMOEBA_TIMING_LIVE;
     c->trec.clear();
     c->matvecs = 0;
     return AMOEBA_OK;

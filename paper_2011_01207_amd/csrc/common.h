@@ -270,7 +270,8 @@ struct amoeba_ctx {
     double last_guess_rms[2] = {0.0, 0.0};
 
     // stage timing (diagnostic)
-    bool timing = false;
+    bool timing = false;           // stage timing with the stages one after the other
+    bool timing_live = false;      // stage timing with the streams as they are
     std::vector<hipEvent_t> tev;                 // event pool
     std::vector<std::pair<int, int>> trec;       // (stage, index of start event in the pool)
     int64_t matvecs = 0;
@@ -286,8 +287,9 @@ int hip_check(amoeba_ctx* c, hipError_t e, const char* what);
 // RAII stage timer: records a start/stop event pair on the context stream when timing is on.
 struct StageTimer {
     amoeba_ctx* c;
+    hipStream_t st;
     int idx = -1;
-    StageTimer(amoeba_ctx* ctx, int stage);
+    StageTimer(amoeba_ctx* ctx, int stage, hipStream_t stream = nullptr);  // null: context stream
     ~StageTimer();
 };
 

@@ -434,7 +434,7 @@ static int capture_iteration(amoeba_ctx* c)
 // direct launches.  A capture that fails leaves the direct launches in use.
 static int enqueue_iteration(amoeba_ctx* c, hipEvent_t fork_ev)
 {
-    const bool graph = c->use_graphs && !c->timing && pme_use_planes(c) && next_coef_mode(c) != 1;
+    const bool graph = c->use_graphs && !c->timing && !c->timing_live && pme_use_planes(c) && next_coef_mode(c) != 1;
     if (graph) {
         if ((!c->it_exec || c->it_key != iteration_key(c)) && capture_iteration(c) != AMOEBA_OK)
             c->use_graphs = false;

@@ -719,7 +719,7 @@ template <bool MI> static void mutual_tiles(amoeba_ctx* c, bool use_done, hipStr
 {
     if (c->ntiles == 0)
         return;
-    StageTimer tm(c, AMOEBA_T_REAL);
+    StageTimer tm(c, AMOEBA_T_REAL, st);
     const int cm = next_coef_mode(c);
     // a recording product runs even when a converged PCG skips the rest of its iteration, so
     // that the store is whole for the products that replay it
@@ -807,7 +807,7 @@ template <bool MI> static void perm_tiles(amoeba_ctx* c, hipStream_t st)
 {
     if (c->ntiles == 0)
         return;
-    StageTimer tm(c, AMOEBA_T_PERM);
+    StageTimer tm(c, AMOEBA_T_PERM, st);
     if (c->mixed)
         hipLaunchKernelGGL((k_block_tiles<float, true, MultipoleKind<float>, MI>), dim3(c->nb), dim3(256), 0,
                            st, c->nb, c->blk_tile0, c->tile_np, c->tile_j, c->tile_mask, c->jrel_f, c->off_f, c->par_f,

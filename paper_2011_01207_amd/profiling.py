@@ -1,7 +1,7 @@
 """Summaries of rocprofv3 output for the committed profiles, and the HBM traffic lookup of the
 benchmark's roofline entry.
 
-  python -m paper_2011_01207_amd.profiling stats <kernel_stats.csv> <title> <command> [top]
+  python -m paper_2011_01207_amd.profiling stats <kernel_stats.csv> <title> <command> [top] [kernel_trace.csv]
   python -m paper_2011_01207_amd.profiling traffic <fetch.csv> <write.csv> <title> <fetch command> <write command>
   python -m paper_2011_01207_amd.profiling counters <counter_collection.csv> <title> <command>
 
@@ -51,6 +51,24 @@ def source_hash(files):
         with open(os.path.join(CSRC, f), "rb") as fh:
             h.update(f.encode() + b"\0" + fh.read())
     return h.hexdigest()[:16]
+
+
+def streams_md(trace_csv, prefixes=("k_block_tiles",), short_us=5.0):
+    """Per-stream durations of the named kernels from a --kernel-trace CSV: all dispatches, and
+    those of at least short_us (the ones that return at entry after convergence excluded)."""
+    d = defaultdict(list)
+    for r in csv.DictReader(open(trace_csv)):
+        k = short(r["Kernel_Name"])
+        if any(k.startswith(p) for p in prefixes):
+            d[(k, r["Stream_Id"])].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+    out = ["\nPer stream (from the kernel trace of the same run; stream 1 is the second stream of the "
+           "products, where the tiles run beside the reciprocal passes, stream 0 the stage pass that runs "
+           f"every stage alone; 'working' excludes dispatches under {short_us:g} us):\n",
+           "| kernel | stream | dispatches | avg us | working dispatches | working avg us |", "|---|---|---|---|---|---|"]
+    for (k, sid), v in sorted(d.items()):
+        w = [x for x in v if x >= short_us]
+        out.append(f"| `{k}` | {sid} | {len(v)} | {st.mean(v):.2f} | {len(w)} | {st.mean(w) if w else 0:.2f} |")
+    return "\n".join(out) + "\n"
 
 
 def stats_md(path, title, cmd, top=30):
@@ -141,6 +159,8 @@ if __name__ == "__main__":
     mode = sys.argv[1]
     if mode == "stats":
         print(stats_md(sys.argv[2], sys.argv[3], sys.argv[4], int(sys.argv[5]) if len(sys.argv) > 5 else 30), end="")
+        if len(sys.argv) > 6:
+            print(streams_md(sys.argv[6]), end="")
     elif mode == "traffic":
         print(traffic_md(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5], sys.argv[6]), end="")
     elif mode == "counters":
