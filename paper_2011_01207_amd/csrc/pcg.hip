@@ -450,12 +450,12 @@ static int enqueue_iteration(amoeba_ctx* c, hipEvent_t fork_ev)
     return enqueue_iteration_direct(c, fork_ev);
 }
 
-// Iterations first..first+budget-1 until the device flag says done.  Host reads lag the device
-// by one queued iteration; *last receives the scalars after the last iteration the host saw
-// (later queued iterations return at entry).  Returns a HIP/rocFFT error code or AMOEBA_OK.
-static int run_iterations(amoeba_ctx* c, int first, int budget, PcgScalars* last)
+// Up to `budget` more iterations until the device flag says done (the device counts the
+// iterations).  Host reads lag the device by one queued iteration; *last receives the scalars
+// after the last iteration the host saw (later queued iterations return at entry).  Returns a
+// HIP/rocFFT error code or AMOEBA_OK.
+static int run_iterations(amoeba_ctx* c, int budget, PcgScalars* last)
 {
-    (void)first;
     hipStream_t st = c->stream;
     const int seq0 = c->pcg_seq;  // the k-th iteration of this call publishes to slot (seq0 + k) & 1
     int enq = 0, chk = 0, rc;
@@ -562,7 +562,7 @@ int pcg_run(amoeba_ctx* c, int max_iter, int start_matvecs, double* mu_out, doub
             // start that is already converged makes the queued kernels return at entry)
             first = false;
             if (max_iter > used) {
-                if ((rc = run_iterations(c, used, max_iter - used, &s)))
+                if ((rc = run_iterations(c, max_iter - used, &s)))
                     return rc;
                 used = s.iters;
             } else if ((rc = read_scalars(c, &s))) {
