@@ -581,7 +581,8 @@ __global__ __launch_bounds__(64) void k_fill_tiles(int nb, const int* __restrict
 }
 
 // Reverse index of the off-diagonal tiles: for every slot, the (tile, lane) entries where it
-// is a j-atom, sorted, so that its j-field contributions are summed in a fixed order.
+// is a j-atom, in the order the fill's atomics give (the sums over them do not depend on it:
+// exact fixed point in mixed precision, see JSum).
 __global__ void k_rev_count(int ntiles, const int* __restrict__ tile_blk, const int* __restrict__ tile0,
                             const int* __restrict__ tile_j, int* __restrict__ cnt)
 {
@@ -607,43 +608,6 @@ __global__ void k_rev_fill(int ntiles, const int* __restrict__ tile_blk, const i
         rev_idx[rev_ptr[sj] + atomicSub(&cursor[sj], 1) - 1] = t * kBlock + k;
 }
 
-// Each slot's reverse entries in increasing order: up to kRevLds entries sorted in LDS (one
-// thread per slot, its own region), longer lists in place in global memory.
-constexpr int kRevLds = 32;
-
-__global__ __launch_bounds__(256) void k_rev_sort(int npad, const int* __restrict__ rev_ptr, int* __restrict__ rev_idx)
-{
-    __shared__ int buf[kRevLds][256];   // column per thread: conflict-free
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= npad)
-        return;
-    const int lo = rev_ptr[s], hi = rev_ptr[s + 1], m = hi - lo;
-    if (m <= kRevLds) {
-        for (int i = 0; i < m; ++i)
-            buf[i][threadIdx.x] = rev_idx[lo + i];
-        for (int i = 1; i < m; ++i) {
-            const int v = buf[i][threadIdx.x];
-            int j = i - 1;
-            while (j >= 0 && buf[j][threadIdx.x] > v) {
-                buf[j + 1][threadIdx.x] = buf[j][threadIdx.x];
-                --j;
-            }
-            buf[j + 1][threadIdx.x] = v;
-        }
-        for (int i = 0; i < m; ++i)
-            rev_idx[lo + i] = buf[i][threadIdx.x];
-        return;
-    }
-    for (int i = lo + 1; i < hi; ++i) {
-        int v = rev_idx[i];
-        int j = i - 1;
-        while (j >= lo && rev_idx[j] > v) {
-            rev_idx[j + 1] = rev_idx[j];
-            --j;
-        }
-        rev_idx[j + 1] = v;
-    }
-}
 
 // Per configuration: in-cutoff bitmasks (strict r < rc, decided as in FP64) and j positions
 // relative to the i-block origin.  The diagonal tile keeps only k > i.  Each pair is first
@@ -962,7 +926,6 @@ int build_blocklist(amoeba_ctx* c, const double* pos)
         }
         hipLaunchKernelGGL(k_rev_fill, dim3(nblk(nthr, 256)), dim3(256), 0, st, total, c->tile_blk, t0, c->tile_j,
                            c->rev_ptr, c->rev_cnt, c->rev_idx);
-        hipLaunchKernelGGL(k_rev_sort, dim3(nblk(npad, 256)), dim3(256), 0, st, npad, c->rev_ptr, c->rev_idx);
     }
     refresh_tiles(c);   // the pair count is read when amoeba_get_info asks for it
     c->list_built = true;

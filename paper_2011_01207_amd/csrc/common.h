@@ -46,6 +46,23 @@ enum : int {
 constexpr double kFixRange = 8192.0;
 __device__ __forceinline__ double fixd(float v) { return rint((double)v * 1099511627776.0); }
 
+// Sums of an atom's i-field (eipart) and its tile j-fields (jbuf, listed by the reverse index).
+// Mixed precision adds every FP32 j-field in the fixed point of the tile accumulators, so the
+// sum is exact and does not depend on the order of the reverse-index entries (which the list
+// build leaves in the order its atomics gave); FP64 adds the terms as they come, as its tile
+// accumulators do.
+template <typename R> struct JSum;
+template <> struct JSum<float> {
+    __device__ static double start(double ei) { return ei * kFixScale; }  // ei: a multiple of 2^-40
+    __device__ static double term(float v) { return fixd(v); }
+    __device__ static double finish(double a) { return a * kFixInv; }
+};
+template <> struct JSum<double> {
+    __device__ static double start(double ei) { return ei; }
+    __device__ static double term(double v) { return v; }
+    __device__ static double finish(double a) { return a; }
+};
+
 // Workgroups are dispatched round-robin over the eight XCDs (workgroup b runs on XCD b mod 8),
 // each with its own L2.  This maps the hardware index to a work item so that every XCD gets a
 // contiguous range of items; consecutive items (neighbouring blocks or bricks, which read the

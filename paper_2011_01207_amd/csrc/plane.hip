@@ -789,10 +789,12 @@ __global__ __launch_bounds__(256) void k_plane_combine(int npad, double3 kl, con
                 pq[0] += pa * qa;
             }
         } else if (perm[s] >= 0) {
-            double er[3] = {eipart[3 * (size_t)s], eipart[3 * (size_t)s + 1], eipart[3 * (size_t)s + 2]};
+            using J = JSum<R>;
+            double er[3] = {J::start(eipart[3 * (size_t)s]), J::start(eipart[3 * (size_t)s + 1]),
+                            J::start(eipart[3 * (size_t)s + 2])};
             const int k1 = rev_ptr[s + 1];
             int k = rev_ptr[s];
-            // four independent loads in flight, added in index order
+            // four independent loads in flight
             for (; k + 4 <= k1; k += 4) {
                 R4 j[4];
 #pragma unroll
@@ -800,17 +802,19 @@ __global__ __launch_bounds__(256) void k_plane_combine(int npad, double3 kl, con
                     j[u] = jbuf[rev_idx[k + u]];
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
-                    er[0] += (double)j[u].x;
-                    er[1] += (double)j[u].y;
-                    er[2] += (double)j[u].z;
+                    er[0] += J::term(j[u].x);
+                    er[1] += J::term(j[u].y);
+                    er[2] += J::term(j[u].z);
                 }
             }
             for (; k < k1; ++k) {
                 const R4 j = jbuf[rev_idx[k]];
-                er[0] += (double)j.x;
-                er[1] += (double)j.y;
-                er[2] += (double)j.z;
+                er[0] += J::term(j.x);
+                er[1] += J::term(j.y);
+                er[2] += J::term(j.z);
             }
+            for (int a = 0; a < 3; ++a)
+                er[a] = J::finish(er[a]);
             const double ainv = par[s].y;
             for (int a = 0; a < 3; ++a) {
                 const size_t i = 3 * (size_t)s + a;

@@ -683,11 +683,12 @@ __global__ __launch_bounds__(256) void k_gather_brick(int3 K, int3 nbr, const in
                 sz = x0[sub] * az;
             } else if (MODE == 1) {
                 const int c = sub - 5;
-                er = eipart[3 * (size_t)s + c];
+                er = JSum<R>::start(eipart[3 * (size_t)s + c]);
                 for (int k = rev_ptr[s]; k < rev_ptr[s + 1]; ++k) {
                     const int e = rev_idx[k];
-                    er += (double)jbuf[4 * (size_t)e + c];
+                    er += JSum<R>::term(jbuf[4 * (size_t)e + c]);
                 }
+                er = JSum<R>::finish(er);
             }
         }
         sx += __shfl_xor(sx, 4);

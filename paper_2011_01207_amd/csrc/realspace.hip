@@ -17,7 +17,8 @@
 // No global atomics: a block writes its i-field once (eipart) and each off-diagonal tile writes
 // its 64 j-fields to its own slot of jbuf; the diagonal tile's j-field goes straight into the
 // block's accumulator.  Every atom's real-space field is then the sum of its eipart and of the
-// jbuf slots listed for it in the reverse index built with the list (fixed order).
+// jbuf slots listed for it in the reverse index built with the list (in mixed precision an
+// exact fixed-point sum, so the order of the list does not matter; see JSum).
 //
 // Pair math (Ewald real space, Thole damping of Ren & Ponder as used by AMOEBA):
 //   B0 = erfc(beta r)/r,  B_n = ((2n-1) B_{n-1} + (2 beta^2)^n e^{-beta^2 r^2} / (beta sqrt(pi))) / r^2
@@ -632,8 +633,8 @@ __global__ __launch_bounds__(256) void k_block_tiles(int nb, const int* __restri
     }
 }
 
-// E_real[s] = eipart[s] + sum of the jbuf slots of s in the reverse index (fixed order; four
-// loads in flight, added in index order).
+// E_real[s] = eipart[s] + sum of the jbuf slots of s in the reverse index (JSum; four loads in
+// flight).
 template <typename R>
 __global__ void k_real_reduce(int npad, const double* __restrict__ eipart, const R* __restrict__ jbuf,
                               const int* __restrict__ rev_ptr, const int* __restrict__ rev_idx,
@@ -647,7 +648,9 @@ __global__ void k_real_reduce(int npad, const double* __restrict__ eipart, const
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= npad)
         return;
-    double e0 = eipart[3 * (size_t)s], e1 = eipart[3 * (size_t)s + 1], e2 = eipart[3 * (size_t)s + 2];
+    using J = JSum<R>;
+    double e0 = J::start(eipart[3 * (size_t)s]), e1 = J::start(eipart[3 * (size_t)s + 1]),
+           e2 = J::start(eipart[3 * (size_t)s + 2]);
     const R4* jb = reinterpret_cast<const R4*>(jbuf);
     const int k1 = rev_ptr[s + 1];
     int k = rev_ptr[s];
@@ -658,20 +661,20 @@ __global__ void k_real_reduce(int npad, const double* __restrict__ eipart, const
             v[u] = jb[rev_idx[k + u]];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            e0 += (double)v[u].x;
-            e1 += (double)v[u].y;
-            e2 += (double)v[u].z;
+            e0 += J::term(v[u].x);
+            e1 += J::term(v[u].y);
+            e2 += J::term(v[u].z);
         }
     }
     for (; k < k1; ++k) {
         const R4 v = jb[rev_idx[k]];
-        e0 += (double)v.x;
-        e1 += (double)v.y;
-        e2 += (double)v.z;
+        e0 += J::term(v.x);
+        e1 += J::term(v.y);
+        e2 += J::term(v.z);
     }
-    ereal[3 * (size_t)s] = e0;
-    ereal[3 * (size_t)s + 1] = e1;
-    ereal[3 * (size_t)s + 2] = e2;
+    ereal[3 * (size_t)s] = J::finish(e0);
+    ereal[3 * (size_t)s + 1] = J::finish(e1);
+    ereal[3 * (size_t)s + 2] = J::finish(e2);
 }
 
 template <typename R, bool FIX, bool MI, int CM>
