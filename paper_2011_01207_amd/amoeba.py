@@ -39,6 +39,8 @@ AMOEBA_PME_PLANES = 1
 AMOEBA_PME_BRICKS = 2
 PME_PATHS = {"auto": 0, "planes": 1, "bricks": 2}
 PAIR_STORE = {"auto": 0, "compute": 1, "stored": 2}
+TIMING_MODES = {"off": 0, "stages": 1, "live": 2}
+STAGE_NAMES = ["list", "perm", "real", "spread", "fft", "gather", "pcg", "guess"]
 
 GUESS_NFEAT = 11
 GUESS_NBASIS = 3
@@ -244,6 +246,18 @@ class Context:
     def set_pair_store(self, mode):
         """mode: "auto", "compute" or "stored" (or the AMOEBA_PAIRS_* value)."""
         self._check(lib().amoeba_set_pair_store(self.h, PAIR_STORE[mode] if isinstance(mode, str) else int(mode)))
+
+    def set_timing(self, mode):
+        """mode: "off", "stages" or "live" (or the AMOEBA_TIMING_* value); resets the counters."""
+        self._check(lib().amoeba_set_timing(self.h, TIMING_MODES[mode] if isinstance(mode, str) else int(mode)))
+
+    def timing(self) -> dict:
+        """Milliseconds and launches per stage since set_timing, and the working products."""
+        t = amoeba_timing()
+        self._check(lib().amoeba_get_timing(self.h, ctypes.byref(t)))
+        return {"ms": {STAGE_NAMES[i]: t.ms[i] for i in range(N_STAGES)},
+                "launches": {STAGE_NAMES[i]: int(t.launches[i]) for i in range(N_STAGES)},
+                "matvecs": int(t.matvecs)}
 
     def set_graphs(self, enable):
         """Run PCG iterations as one captured HIP graph each (True, the default) or as
