@@ -1,5 +1,6 @@
 """GPU tests of the stage timers: AMOEBA_TIMING_STAGES times every stage alone, AMOEBA_TIMING_LIVE
-only the real-space tiles where they run (second stream), and neither changes the results."""
+only the real-space tiles where they run (second stream); live timing leaves the results
+bitwise as they are, the stage pass to rounding."""
 import pytest
 import torch
 
@@ -33,7 +34,10 @@ def test_timing_modes():
         ctx.close()
     mu_l, tl = res["live"]
     mu_s, ts = res["stages"]
-    assert torch.equal(mu_l, ref) and torch.equal(mu_s, ref)
+    # live timing leaves the products as they are; the stage pass runs the real-space and
+    # reciprocal parts one after the other, which may round the last bit of a sum differently
+    assert torch.equal(mu_l, ref)
+    assert float((mu_s - ref).abs().max()) < 1e-12 * float(ref.abs().max())
     assert tl["launches"]["real"] > 0 and tl["ms"]["real"] > 0
     assert all(tl["launches"][k] == 0 for k in tl["launches"] if k != "real")
     for k in ("real", "spread", "fft", "gather", "pcg"):
