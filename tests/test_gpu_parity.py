@@ -198,6 +198,44 @@ def test_near_coincident_atoms(prec):
     ctx.close()
 
 
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_single_atom(prec):
+    """One atom in a 16 A box: no pairs, one block of 63 phantoms, only the reciprocal and self
+    terms act on it (its periodic images)."""
+    import dataclasses
+    s = dataclasses.replace(synth.tiny_cell(1, 16.0, 7), grid=(16, 16, 16))
+    print(f"[gpu] single atom {prec}", flush=True)
+    ctx, t = amoeba.context_for(s, precision=prec, device=DEV)
+    try:
+        assert ctx.info()["n_pairs"] == 0
+        e_ref = O.perm_field(s, "spme")
+        e = ctx.perm_field(t["pos"], t["q"], t["dip"], t["quad"])
+        assert rel_rms(e.cpu().numpy(), e_ref) < (1e-11 if prec == "fp64" else 3e-5)
+        mu = np.full((1, 3), 0.1)
+        q = ctx.dipole_matvec(t["pos"], torch.tensor(mu, device=DEV)).cpu().numpy()
+        assert rel_rms(q, O.matvec(s, mu, "spme")) < (1e-12 if prec == "fp64" else 3e-6)
+        mu_ref, _, _ = O.pcg(s, e_ref, "spme", tol_debye=1e-10)
+        m, ep, it, st = ctx.polarize(t["pos"], e, tol_debye=1e-9 if prec == "fp64" else 1e-7)
+        assert st == amoeba.AMOEBA_OK
+        assert O.rms_debye(m.cpu().numpy() - mu_ref) < (1e-8 if prec == "fp64" else 1e-6)
+    finally:
+        ctx.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_zero_permanent_field_converges_at_the_start(prec):
+    """E_perm = 0: the zero start is the solution, so the solve ends before its first product."""
+    import dataclasses
+    s = dataclasses.replace(synth.tiny_cell(40, 16.0, 8, min_dist=1.2), grid=(20, 20, 20))
+    ctx, t = amoeba.context_for(s, precision=prec, device=DEV)
+    try:
+        mu, ep, it, st = ctx.polarize(t["pos"], torch.zeros_like(t["pos"]), tol_debye=1e-8)
+        assert st == amoeba.AMOEBA_OK and it == 0
+        assert torch.count_nonzero(mu) == 0 and ep == 0.0
+    finally:
+        ctx.close()
+
+
 def test_error_paths(c1):
     p = amoeba.Context(c1.n, c1.box, grid=c1.grid)
     pos = torch.tensor(c1.pos, device=DEV)
