@@ -624,7 +624,7 @@ int amoeba_polarize(amoeba_ctx* c, const double* pos, const double* e_perm, cons
         st = pcg_solve(c, tol_debye, max_iter, true, mu_out, &ep);
         c->last_guess = AMOEBA_GUESS_LEARNED;
     } else {
-        // The judge: the preconditioned initial residual of the fallback (zero or given) and of
+        // Choosing the start: the preconditioned initial residual of the fallback (zero or given) and of
         // the learned guess; PCG starts from the smaller.  The fallback state is kept while
         // the learned one is evaluated.
         if ((rc = guess_compute(c)))

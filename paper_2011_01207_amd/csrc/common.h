@@ -281,7 +281,7 @@ struct amoeba_ctx {
     double* g_radial = nullptr;            // [npad*3] radial neighbour sums
     float* g_feat = nullptr;               // [npad][NFEAT]
     float* g_basis = nullptr;              // [npad][NBASIS*3]
-    double* g_save_mu = nullptr;           // [npad*3] fallback guess kept while the judge runs
+    double* g_save_mu = nullptr;           // [npad*3] fallback guess kept while the starts are compared
     double* g_save_q = nullptr;            // [npad*3] its A mu0
     int last_guess = 0;
     double last_guess_rms[2] = {0.0, 0.0};

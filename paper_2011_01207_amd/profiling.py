@@ -73,7 +73,7 @@ def streams_md(trace_csv, prefixes=("k_block_tiles",), short_us=5.0):
 
 def stats_md(path, title, cmd, top=30):
     rows = list(csv.DictReader(open(path)))
-    out = [f"# {title}\n", f"Command (repository root on the GPU box, R = its path):\n\n```\n{cmd}\n```\n",
+    out = [f"# {title}\n", f"Command (repository root on the profiled machine, R = its path):\n\n```\n{cmd}\n```\n",
            "Kernel durations in microseconds from `rocprofv3 --kernel-trace --stats` (all dispatches of the run).\n",
            "| kernel | calls | total us | avg us | min us | max us | % |", "|---|---|---|---|---|---|---|"]
     for r in rows[:top]:
@@ -109,7 +109,7 @@ def traffic_md(fetch_csv, write_csv, title, fcmd, wcmd, top=20):
         rows.append((k[0], k[1], len(f[k]), fk, wk, fk * 1024 * ff + wk * 1024 * fw))
     rows.sort(key=lambda r: -r[5] * r[2])
     out = [f"# {title}\n",
-           "Commands (repository root on the GPU box, R = its path), FETCH_SIZE and WRITE_SIZE in separate runs:\n",
+           "Commands (repository root on the profiled machine, R = its path), FETCH_SIZE and WRITE_SIZE in separate runs:\n",
            f"```\n{fcmd}\n{wcmd}\n```\n",
            f"Copy calibration (the run's three 256 MiB `{COPY_KERNEL}` dispatches): FETCH_SIZE factor "
            f"{ff:.4f} ({nf} dispatches), WRITE_SIZE factor {fw:.4f} ({nw} dispatches); HBM bytes = "
@@ -130,7 +130,7 @@ def counters_md(path, title, cmd, kernels=None):
     for r in csv.DictReader(open(path)):
         d[short(r["Kernel_Name"])][r["Counter_Name"]].append(float(r["Counter_Value"]))
     names = sorted({c for v in d.values() for c in v})
-    out = [f"# {title}\n", f"Command (repository root on the GPU box, R = its path):\n\n```\n{cmd}\n```\n",
+    out = [f"# {title}\n", f"Command (repository root on the profiled machine, R = its path):\n\n```\n{cmd}\n```\n",
            "Median per dispatch.\n", "| kernel | " + " | ".join(names) + " |", "|---" * (len(names) + 1) + "|"]
     for k, v in sorted(d.items(), key=lambda kv: -st.median(kv[1].get("SQ_WAVES", [0]))):
         if kernels and not any(k.startswith(p) for p in kernels):
