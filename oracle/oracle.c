@@ -93,6 +93,39 @@ static double pair_scale(int i, int j, const int32_t *ptr, const int32_t *sj, co
 }
 
 /*
+ * Partner search of the real-space loops.  Without cells (nc == NULL) every other atom is a
+ * candidate: the plain O(N^2) definition.  With cells, the atoms are binned (by the caller) in a
+ * periodic grid of nc[0] x nc[1] x nc[2] cells, every cell at least rc wide and at least three
+ * per axis; an atom in cell (cx, cy, cz) then finds every partner closer than rc under the
+ * minimum image in the 27 cells (cx + {-1,0,1}, ...) taken modulo nc, each of them visited once.
+ * The candidates are written to buf (room for n - 1) and their count returned.  Both searches
+ * give the same pairs; only the order of the sums differs.
+ */
+static int partners(int i, int n, const int32_t *nc, const int32_t *cell_of, const int32_t *cell_start,
+                    const int32_t *cell_atoms, int32_t *buf)
+{
+    int m = 0;
+    if (!nc) {
+        for (int j = 0; j < n; ++j)
+            if (j != i)
+                buf[m++] = j;
+        return m;
+    }
+    int c = cell_of[i];
+    int cz = c % nc[2], cy = (c / nc[2]) % nc[1], cx = c / (nc[1] * nc[2]);
+    for (int a = -1; a <= 1; ++a)
+        for (int b = -1; b <= 1; ++b)
+            for (int e = -1; e <= 1; ++e) {
+                int x = (cx + a + nc[0]) % nc[0], y = (cy + b + nc[1]) % nc[1], z = (cz + e + nc[2]) % nc[2];
+                int cell = (x * nc[1] + y) * nc[2] + z;
+                for (int k = cell_start[cell]; k < cell_start[cell + 1]; ++k)
+                    if (cell_atoms[k] != i)
+                        buf[m++] = cell_atoms[k];
+            }
+    return m;
+}
+
+/*
  * Real-space field of induced dipoles mu at the requested atoms:
  *   E_i = sum_{j != i, |r| < rc} ( -B1' mu_j + B2' (mu_j . r) r ),  r = r_i - r_j (minimum image),
  *   B1' = B1 - (1-l3)/r^3,  B2' = B2 - 3 (1-l5)/r^5.
@@ -100,15 +133,20 @@ static double pair_scale(int i, int j, const int32_t *ptr, const int32_t *sj, co
  */
 void orc_real_mutual(int n, const double *pos, const double *box, double beta, double rc,
                      const double *alpha, const double *thole, const double *mu,
-                     int n_out, const int32_t *out_idx, double *out)
+                     int n_out, const int32_t *out_idx, double *out,
+                     const int32_t *nc, const int32_t *cell_of, const int32_t *cell_start,
+                     const int32_t *cell_atoms)
 {
-#pragma omp parallel for schedule(dynamic, 8)
+#pragma omp parallel
+    {
+    int32_t *cand = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 1 ? n : 1));
+#pragma omp for schedule(dynamic, 8)
     for (int o = 0; o < n_out; ++o) {
         int i = out_idx ? out_idx[o] : o;
         double e[3] = {0.0, 0.0, 0.0};
-        for (int j = 0; j < n; ++j) {
-            if (j == i)
-                continue;
+        int m = partners(i, n, nc, cell_of, cell_start, cell_atoms, cand);
+        for (int c = 0; c < m; ++c) {
+            int j = cand[c];
             double d[3] = {pos[3 * i] - pos[3 * j], pos[3 * i + 1] - pos[3 * j + 1],
                            pos[3 * i + 2] - pos[3 * j + 2]};
             min_image(d, box);
@@ -131,6 +169,8 @@ void orc_real_mutual(int n, const double *pos, const double *box, double beta, d
         out[3 * o + 1] = e[1];
         out[3 * o + 2] = e[2];
     }
+    free(cand);
+    }
 }
 
 /*
@@ -139,61 +179,84 @@ void orc_real_mutual(int n, const double *pos, const double *box, double beta, d
  *   E_i += q_j B1' r - B1' d_j + B2' (d_j.r) r + (1/3) B3' (Theta_j:rr) r - (2/3) B2' Theta_j r
  * with  Bn' = [r < rc] Bn - c_n (1 - s lambda_{2n+1}) / r^{2n+1},  c = 1, 3, 15,
  * s = the pair's scale (1 unless listed).  A listed pair is corrected even beyond rc,
- * so the reciprocal part's share of it is always removed.
+ * so the reciprocal part's share of it is always removed: the pairs within rc come from the
+ * partner search, the listed pairs at or beyond rc from the atom's row of the CSR.
  */
+static void perm_pair(const double d[3], double r, int in_cut, double s, double beta, int i, int j,
+                      const double *alpha, const double *thole, const double *q, const double *dip,
+                      const double *quad, double e[3])
+{
+    double b[4] = {0.0, 0.0, 0.0, 0.0}, oml[3];
+    if (in_cut)
+        ewald_b(r, beta, b);
+    orc_thole_oml(r, alpha[i], alpha[j], thole[i], thole[j], oml);
+    double r2 = r * r, r3 = r2 * r, r5 = r3 * r2, r7 = r5 * r2;
+    double b1 = b[1] - (1.0 - s * (1.0 - oml[0])) / r3;
+    double b2 = b[2] - 3.0 * (1.0 - s * (1.0 - oml[1])) / r5;
+    double b3 = b[3] - 15.0 * (1.0 - s * (1.0 - oml[2])) / r7;
+    double qj = q ? q[j] : 0.0;
+    double dj[3] = {0.0, 0.0, 0.0};
+    if (dip)
+        for (int a = 0; a < 3; ++a)
+            dj[a] = dip[3 * j + a];
+    double th[3][3] = {{0}};
+    if (quad) {
+        const double *t = quad + 6 * j;
+        th[0][0] = t[0]; th[0][1] = th[1][0] = t[1]; th[0][2] = th[2][0] = t[2];
+        th[1][1] = t[3]; th[1][2] = th[2][1] = t[4]; th[2][2] = t[5];
+    }
+    double dr = dj[0] * d[0] + dj[1] * d[1] + dj[2] * d[2];
+    double thr[3], thrr = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        thr[a] = th[a][0] * d[0] + th[a][1] * d[1] + th[a][2] * d[2];
+        thrr += thr[a] * d[a];
+    }
+    for (int a = 0; a < 3; ++a)
+        e[a] += qj * b1 * d[a] - b1 * dj[a] + b2 * dr * d[a] + b3 * thrr * d[a] / 3.0
+                - 2.0 * b2 * thr[a] / 3.0;
+}
+
 void orc_real_perm(int n, const double *pos, const double *box, double beta, double rc,
                    const double *alpha, const double *thole, const double *q, const double *dip,
                    const double *quad, const int32_t *sc_ptr, const int32_t *sc_j, const double *sc_s,
-                   int n_out, const int32_t *out_idx, double *out)
+                   int n_out, const int32_t *out_idx, double *out,
+                   const int32_t *nc, const int32_t *cell_of, const int32_t *cell_start,
+                   const int32_t *cell_atoms)
 {
-#pragma omp parallel for schedule(dynamic, 8)
+#pragma omp parallel
+    {
+    int32_t *cand = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 1 ? n : 1));
+#pragma omp for schedule(dynamic, 8)
     for (int o = 0; o < n_out; ++o) {
         int i = out_idx ? out_idx[o] : o;
         double e[3] = {0.0, 0.0, 0.0};
-        for (int j = 0; j < n; ++j) {
-            if (j == i)
-                continue;
+        int m = partners(i, n, nc, cell_of, cell_start, cell_atoms, cand);
+        for (int c = 0; c < m; ++c) {
+            int j = cand[c];
             double d[3] = {pos[3 * i] - pos[3 * j], pos[3 * i + 1] - pos[3 * j + 1],
                            pos[3 * i + 2] - pos[3 * j + 2]};
             min_image(d, box);
-            double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
-            double r = sqrt(r2);
-            double s = pair_scale(i, j, sc_ptr, sc_j, sc_s);
-            int in_cut = r < rc;
-            if (!in_cut && s == 1.0)
+            double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+            if (!(r < rc))
                 continue;
-            double b[4] = {0.0, 0.0, 0.0, 0.0}, oml[3];
-            if (in_cut)
-                ewald_b(r, beta, b);
-            orc_thole_oml(r, alpha[i], alpha[j], thole[i], thole[j], oml);
-            double r3 = r2 * r, r5 = r3 * r2, r7 = r5 * r2;
-            double b1 = b[1] - (1.0 - s * (1.0 - oml[0])) / r3;
-            double b2 = b[2] - 3.0 * (1.0 - s * (1.0 - oml[1])) / r5;
-            double b3 = b[3] - 15.0 * (1.0 - s * (1.0 - oml[2])) / r7;
-            double qj = q ? q[j] : 0.0;
-            double dj[3] = {0.0, 0.0, 0.0};
-            if (dip)
-                for (int a = 0; a < 3; ++a)
-                    dj[a] = dip[3 * j + a];
-            double th[3][3] = {{0}};
-            if (quad) {
-                const double *t = quad + 6 * j;
-                th[0][0] = t[0]; th[0][1] = th[1][0] = t[1]; th[0][2] = th[2][0] = t[2];
-                th[1][1] = t[3]; th[1][2] = th[2][1] = t[4]; th[2][2] = t[5];
-            }
-            double dr = dj[0] * d[0] + dj[1] * d[1] + dj[2] * d[2];
-            double thr[3], thrr = 0.0;
-            for (int a = 0; a < 3; ++a) {
-                thr[a] = th[a][0] * d[0] + th[a][1] * d[1] + th[a][2] * d[2];
-                thrr += thr[a] * d[a];
-            }
-            for (int a = 0; a < 3; ++a)
-                e[a] += qj * b1 * d[a] - b1 * dj[a] + b2 * dr * d[a] + b3 * thrr * d[a] / 3.0
-                        - 2.0 * b2 * thr[a] / 3.0;
+            perm_pair(d, r, 1, pair_scale(i, j, sc_ptr, sc_j, sc_s), beta, i, j, alpha, thole, q, dip, quad, e);
         }
+        if (sc_ptr)
+            for (int k = sc_ptr[i]; k < sc_ptr[i + 1]; ++k) {
+                int j = sc_j[k];
+                double d[3] = {pos[3 * i] - pos[3 * j], pos[3 * i + 1] - pos[3 * j + 1],
+                               pos[3 * i + 2] - pos[3 * j + 2]};
+                min_image(d, box);
+                double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+                if (r < rc || sc_s[k] == 1.0)
+                    continue;
+                perm_pair(d, r, 0, sc_s[k], beta, i, j, alpha, thole, q, dip, quad, e);
+            }
         out[3 * o] = e[0];
         out[3 * o + 1] = e[1];
         out[3 * o + 2] = e[2];
+    }
+    free(cand);
     }
 }
 
@@ -381,13 +444,22 @@ void orc_spme_gather(int n, const double *pos, const double *box, const int32_t 
     }
 }
 
-/* Count of real-space pairs 0 < |r| < rc under minimum image (unordered). */
-int64_t orc_count_pairs(int n, const double *pos, const double *box, double rc)
+/* Count of real-space pairs 0 < |r| < rc under minimum image (unordered: each pair once). */
+int64_t orc_count_pairs(int n, const double *pos, const double *box, double rc,
+                        const int32_t *nc, const int32_t *cell_of, const int32_t *cell_start,
+                        const int32_t *cell_atoms)
 {
     int64_t cnt = 0;
-#pragma omp parallel for schedule(dynamic, 16) reduction(+ : cnt)
-    for (int i = 0; i < n; ++i)
-        for (int j = i + 1; j < n; ++j) {
+#pragma omp parallel reduction(+ : cnt)
+    {
+    int32_t *cand = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 1 ? n : 1));
+#pragma omp for schedule(dynamic, 16)
+    for (int i = 0; i < n; ++i) {
+        int m = partners(i, n, nc, cell_of, cell_start, cell_atoms, cand);
+        for (int c = 0; c < m; ++c) {
+            int j = cand[c];
+            if (j <= i)
+                continue;
             double d[3] = {pos[3 * i] - pos[3 * j], pos[3 * i + 1] - pos[3 * j + 1],
                            pos[3 * i + 2] - pos[3 * j + 2]};
             min_image(d, box);
@@ -395,6 +467,9 @@ int64_t orc_count_pairs(int n, const double *pos, const double *box, double rc)
             if (r2 > 0.0 && sqrt(r2) < rc)
                 ++cnt;
         }
+    }
+    free(cand);
+    }
     return cnt;
 }
 

@@ -48,16 +48,16 @@ def lib():
         L.orc_thole_oml.argtypes = [ctypes.c_double] * 5 + [_dp]
         L.orc_ewald_b.argtypes = [ctypes.c_double, ctypes.c_double, _dp]
         L.orc_real_mutual.argtypes = [ctypes.c_int, _dp, _dp, ctypes.c_double, ctypes.c_double, _dp, _dp,
-                                      _dp, ctypes.c_int, _ip, _dp]
+                                      _dp, ctypes.c_int, _ip, _dp, _ip, _ip, _ip, _ip]
         L.orc_real_perm.argtypes = [ctypes.c_int, _dp, _dp, ctypes.c_double, ctypes.c_double, _dp, _dp, _dp,
-                                    _dp, _dp, _ip, _ip, _dp, ctypes.c_int, _ip, _dp]
+                                    _dp, _dp, _ip, _ip, _dp, ctypes.c_int, _ip, _dp, _ip, _ip, _ip, _ip]
         L.orc_ksum_field.argtypes = [ctypes.c_int, _dp, _dp, ctypes.c_double, ctypes.c_double, _dp, _dp, _dp,
                                      ctypes.c_int, _ip, _dp]
         L.orc_bspline.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_int]
         L.orc_bspline.restype = ctypes.c_double
         L.orc_spme_spread.argtypes = [ctypes.c_int, _dp, _dp, _ip, ctypes.c_int, _dp, _dp, _dp, _dp]
         L.orc_spme_gather.argtypes = [ctypes.c_int, _dp, _dp, _ip, ctypes.c_int, _dp, ctypes.c_int, _ip, _dp]
-        L.orc_count_pairs.argtypes = [ctypes.c_int, _dp, _dp, ctypes.c_double]
+        L.orc_count_pairs.argtypes = [ctypes.c_int, _dp, _dp, ctypes.c_double, _ip, _ip, _ip, _ip]
         L.orc_count_pairs.restype = ctypes.c_int64
         L.orc_num_threads.restype = ctypes.c_int
         _LIB = L
@@ -87,6 +87,35 @@ def _outsel(n, idx):
         return n, None, None
     keep, p = _i(idx)
     return len(keep), keep, p
+
+
+def cell_bins(pos, box, rc):
+    """Periodic cell grid for the partner search of the real-space loops: nc[a] = floor(L_a / rc)
+    cells per axis (each at least rc wide), atoms binned by their wrapped position.  Returns the
+    four arrays the C loops take (nc, cell of each atom, cell start offsets, atoms by cell), or
+    None where an axis has fewer than three cells (then every atom is a candidate)."""
+    pos = np.asarray(pos, dtype=np.float64).reshape(-1, 3)
+    box = np.asarray(box, dtype=np.float64)
+    nc = np.floor(box / rc).astype(np.int64)
+    if not np.isfinite(rc) or np.any(nc < 3):
+        return None
+    u = pos - box * np.floor(pos / box)
+    c = np.minimum(np.floor(u / box * nc).astype(np.int64), nc - 1)
+    cid = (c[:, 0] * nc[1] + c[:, 1]) * nc[2] + c[:, 2]
+    order = np.argsort(cid, kind="stable")
+    start = np.searchsorted(cid[order], np.arange(int(np.prod(nc)) + 1))
+    return (nc.astype(np.int32), cid.astype(np.int32), start.astype(np.int32), order.astype(np.int32))
+
+
+def _search_args(s, rc, search):
+    """ctypes arguments of the partner search: 'cells' (when the box allows it) or 'all'."""
+    if search not in ("cells", "all"):
+        raise ValueError(search)
+    cl = cell_bins(s.pos, s.box, rc) if (search == "cells" and np.isfinite(rc)) else None
+    if cl is None:
+        return (), (None, None, None, None)
+    keep = tuple(np.ascontiguousarray(a) for a in cl)
+    return keep, tuple(a.ctypes.data_as(_ip) for a in keep)
 
 
 # ----------------------------------------------------------------------------------------------
@@ -124,9 +153,10 @@ def default_kmax(beta: float, tail: float = 1e-17) -> float:
 # field components
 # ----------------------------------------------------------------------------------------------
 
-def real_mutual(s, mu, idx=None, beta=None, rc=None, free_space=False):
+def real_mutual(s, mu, idx=None, beta=None, rc=None, free_space=False, search="cells"):
     """Real-space (Thole-damped, Ewald-screened) field of dipoles mu at atoms idx (all if None).
-    free_space: no periodic images, no cutoff, beta = 0 (bare damped dipole tensor)."""
+    free_space: no periodic images, no cutoff, beta = 0 (bare damped dipole tensor).
+    search: 'cells' (a periodic cell grid finds the partners within rc) or 'all' (every pair)."""
     pos, pp = _d(s.pos)
     n = pos.shape[0]
     _, ap = _d(s.alpha)
@@ -140,13 +170,15 @@ def real_mutual(s, mu, idx=None, beta=None, rc=None, free_space=False):
         rc = s.cutoff if rc is None else rc
     n_out, _keep, ip = _outsel(n, idx)
     out = np.zeros((n_out, 3))
-    lib().orc_real_mutual(n, pp, bp, beta, rc, ap, tp, mp, n_out, ip, out.ctypes.data_as(_dp))
+    _cl, cl = _search_args(s, rc, search) if not free_space else ((), (None,) * 4)
+    lib().orc_real_mutual(n, pp, bp, beta, rc, ap, tp, mp, n_out, ip, out.ctypes.data_as(_dp), *cl)
     return out
 
 
 def real_perm(s, idx=None, beta=None, rc=None, free_space=False, q=True, dip=True, quad=True,
-              scaled=True):
-    """Real-space permanent field of (q, d, Theta) with the scaled-pair correction."""
+              scaled=True, search="cells"):
+    """Real-space permanent field of (q, d, Theta) with the scaled-pair correction (search as in
+    real_mutual)."""
     pos, pp = _d(s.pos)
     n = pos.shape[0]
     _, ap = _d(s.alpha)
@@ -168,8 +200,9 @@ def real_perm(s, idx=None, beta=None, rc=None, free_space=False, q=True, dip=Tru
         rc = s.cutoff if rc is None else rc
     n_out, _keep, ip = _outsel(n, idx)
     out = np.zeros((n_out, 3))
+    _cl, cl = _search_args(s, rc, search) if not free_space else ((), (None,) * 4)
     lib().orc_real_perm(n, pp, bp, beta, rc, ap, tp, qp, dp, Qp, sp, sjp, ssp, n_out, ip,
-                        out.ctypes.data_as(_dp))
+                        out.ctypes.data_as(_dp), *cl)
     return out
 
 
@@ -321,10 +354,11 @@ def e_pol(mu, e_perm) -> float:
     return -0.5 * COULOMB * float(np.sum(np.asarray(mu) * np.asarray(e_perm)))
 
 
-def pcg(s, rhs, recip='spme', tol_debye=1e-8, mu0=None, max_iter=1000, op=None):
+def pcg(s, rhs, recip='spme', tol_debye=1e-8, mu0=None, max_iter=1000, op=None, on_iterate=None):
     """Preconditioned CG on (alpha^-1 - T) mu = rhs with the diagonal preconditioner z = alpha r.
     Stops when the rms of z (in Debye) drops below tol_debye.  Returns (mu, iterations, history),
-    iterations = number of operator applications after the initial residual."""
+    iterations = number of operator applications after the initial residual.  on_iterate(k, mu,
+    rms_z), if given, observes every iterate (k = 0 for the start); it changes nothing."""
     alpha = np.asarray(s.alpha, dtype=np.float64)[:, None]
     apply = op if op is not None else (lambda v: matvec(s, v, recip))
     rhs = np.asarray(rhs, dtype=np.float64).reshape(-1, 3)
@@ -332,6 +366,8 @@ def pcg(s, rhs, recip='spme', tol_debye=1e-8, mu0=None, max_iter=1000, op=None):
     r = rhs - apply(mu) if mu0 is not None else rhs.copy()
     z = alpha * r
     hist = [rms_debye(z)]
+    if on_iterate is not None:
+        on_iterate(0, mu, hist[-1])
     if hist[-1] < tol_debye:
         return mu, 0, hist
     p = z.copy()
@@ -343,6 +379,8 @@ def pcg(s, rhs, recip='spme', tol_debye=1e-8, mu0=None, max_iter=1000, op=None):
         r -= gamma * q
         z = alpha * r
         hist.append(rms_debye(z))
+        if on_iterate is not None:
+            on_iterate(it, mu, hist[-1])
         if hist[-1] < tol_debye:
             return mu, it, hist
         rz_new = float(np.sum(r * z))
@@ -362,8 +400,10 @@ def dense_operator(s, recip='spme'):
     return a
 
 
-def count_pairs(s, rc=None) -> int:
+def count_pairs(s, rc=None, search="cells") -> int:
+    """Unordered pairs with 0 < |r| < rc under the minimum image."""
     pos, pp = _d(s.pos)
     _box, bp = _d(s.box)
     rc = s.cutoff if rc is None else rc
-    return int(lib().orc_count_pairs(pos.shape[0], pp, bp, rc))
+    _cl, cl = _search_args(s, rc, search)
+    return int(lib().orc_count_pairs(pos.shape[0], pp, bp, rc, *cl))

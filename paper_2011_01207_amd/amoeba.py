@@ -260,8 +260,8 @@ class Context:
                 "matvecs": int(t.matvecs)}
 
     def set_graphs(self, enable):
-        """Run PCG iterations as one captured HIP graph each (True, the default) or as
-        individual kernel launches (False)."""
+        """Run PCG iterations as one captured HIP graph each (True) or as individual kernel
+        launches (False, the library's default)."""
         self._check(lib().amoeba_set_graphs(self.h, 1 if enable else 0))
 
     def info(self) -> dict:

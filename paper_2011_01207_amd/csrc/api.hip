@@ -198,6 +198,14 @@ static int ready(amoeba_ctx* c, const char* who)
     return AMOEBA_OK;
 }
 
+// Queue the range check of a slot-order field (read with the caller's next flags read).
+void launch_check_overflow(amoeba_ctx* c, const double* v_slot)
+{
+    const size_t n3 = 3 * (size_t)c->npad;
+    hipLaunchKernelGGL(k_check_overflow, dim3(nblk(n3, 256)), dim3(256), 0, c->stream, n3, v_slot, kFixRange,
+                       c->flags);
+}
+
 static int check_overflow(amoeba_ctx* c, const double* v_slot)
 {
     if (!c->mixed)

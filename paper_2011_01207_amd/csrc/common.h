@@ -351,6 +351,7 @@ void launch_gather(amoeba_ctx* c, double* out);       // E_rec at atoms from the
 // api.hip
 int read_flags(amoeba_ctx* c, int* out);
 int check_vec_finite(amoeba_ctx* c, const double* v, size_t n, const char* what);
+void launch_check_overflow(amoeba_ctx* c, const double* v_slot);  // |v| < kFixRange, flag on the device
 int begin_config(amoeba_ctx* c, const double* pos, const char* who);
 
 // guess.hip

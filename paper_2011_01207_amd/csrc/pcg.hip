@@ -383,11 +383,16 @@ void iteration_graph_release(amoeba_ctx* c)
 }
 
 // What a captured iteration bakes in besides the context's fixed buffers: the pair kernel's
-// minimum-image variant and coefficient mode, the coefficient store, the p.q partial count.
+// minimum-image variant and coefficient mode, the coefficient store, the p.q partial count, and
+// every buffer address.  A list build that outgrows its tile arrays allocates new ones (tiles,
+// masks, j positions, jbuf, reverse index); the allocation registry only grows, so its size
+// changes with every such allocation and a graph holding the old addresses is captured again.
 static unsigned long long iteration_key(const amoeba_ctx* c)
 {
     unsigned long long k = 1469598103934665603ull;
     auto mix = [&](unsigned long long v) { k = (k ^ v) * 1099511628211ull; };
+    mix((unsigned long long)c->allocs.size());
+    mix((unsigned long long)c->ntiles);
     mix(c->skip_mimg ? 1 : 2);
     mix((unsigned long long)next_coef_mode(c) + 3);
     mix((unsigned long long)(uintptr_t)c->coef);
@@ -581,6 +586,9 @@ int pcg_run(amoeba_ctx* c, int max_iter, int start_matvecs, double* mu_out, doub
             launch_set_direction(c, c->v_mu);
             if ((rc = matvec_slot(c, false, false)))
                 return rc;
+            // A mu = mu/alpha - T mu of the accepted dipoles: its fields must lie in the exact
+            // fixed-point range of the tile accumulators
+            launch_check_overflow(c, c->v_q);
             launch_init_residual(c, c->v_q, used);
         }
         launch_epol(c);
@@ -589,6 +597,9 @@ int pcg_run(amoeba_ctx* c, int max_iter, int start_matvecs, double* mu_out, doub
             return rc;
         if (f & kFlagNonFinite)
             return set_error(c, AMOEBA_E_NUMERIC, "non-finite value in e_perm or mu_guess");
+        if (f & kFlagOverflow)
+            return set_error(c, AMOEBA_E_OVERFLOW,
+                             "amoeba_polarize: field outside the exact fixed-point range (|E| >= 8192 e/A^2)");
         if (check) {
             s.iters = used;
             if (!s.done) {

@@ -7,6 +7,7 @@ import torch
 
 import oracle as O
 from paper_2011_01207_amd import amoeba, synth
+from parity_util import assert_fields  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
@@ -16,8 +17,6 @@ if not torch.cuda.is_available():
 DEV = "cuda:0"
 
 
-def rel_rms(a, b):
-    return float(np.sqrt(np.mean((np.asarray(a) - np.asarray(b)) ** 2)) / np.sqrt(np.mean(np.asarray(b) ** 2)))
 
 
 @pytest.fixture(scope="module")
@@ -42,9 +41,9 @@ def test_water96k_fields_and_solve(c2, c2_ref, prec):
     print(f"[gpu] water_96000 {prec}", flush=True)
     ctx, t = amoeba.context_for(s, precision=prec, device=DEV)
     e = ctx.perm_field(t["pos"], t["q"], t["dip"], t["quad"])
-    assert rel_rms(e.cpu().numpy()[idx], c2_ref["perm"]) < (1e-11 if prec == "fp64" else 3e-5)
+    assert_fields(e.cpu().numpy()[idx], c2_ref["perm"], (1e-11 if prec == "fp64" else 3e-5))
     q = ctx.dipole_matvec(t["pos"], torch.tensor(c2_ref["mu"], device=DEV)).cpu().numpy()[idx]
-    assert rel_rms(q, c2_ref["matvec"]) < (1e-12 if prec == "fp64" else 3e-6)
+    assert_fields(q, c2_ref["matvec"], (1e-12 if prec == "fp64" else 3e-6))
     # solve to 1e-5 D; the oracle's own residual of the GPU solution at the sampled atoms
     mu, ep, it, st = ctx.polarize(t["pos"], e, tol_debye=1e-5)
     assert st == amoeba.AMOEBA_OK and it > 0
@@ -87,7 +86,7 @@ def test_subcell_of_864k_box_dipoles_and_energy(subcell864, prec):
     s, e_ref, mu_ref = subcell864
     ctx, t = amoeba.context_for(s, precision=prec, device=DEV)
     e = ctx.perm_field(t["pos"], t["q"], t["dip"], t["quad"])
-    assert rel_rms(e.cpu().numpy(), e_ref) < (1e-11 if prec == "fp64" else 3e-5)
+    assert_fields(e.cpu().numpy(), e_ref, (1e-11 if prec == "fp64" else 3e-5))
     tol = 1e-9 if prec == "fp64" else 1e-6
     mu, ep, it, st = ctx.polarize(t["pos"], e, tol_debye=tol)
     assert st == amoeba.AMOEBA_OK

@@ -79,3 +79,33 @@ def test_graph_follows_a_change_of_pair_kernel_and_store():
         ctx.close()
     for mu, it in res:
         assert torch.equal(mu, mu_l) and it == it_l
+
+
+def test_graph_follows_a_list_rebuild_that_grows_the_tiles():
+    """A list build whose tile count outgrows the tile arrays allocates new ones: the captured
+    iteration must be captured again with the new addresses, and the solve must stay bitwise
+    equal to the launched one."""
+    print("[gpu] graph after a list rebuild with more tiles", flush=True)
+    s = system()
+    centre = 0.5 * s.box
+    pos_b = np.mod(centre + 0.85 * (s.pos - centre), s.box)   # denser: more j-atoms per block
+    res = {}
+    for graphs in (False, True):
+        ctx, t = amoeba.context_for(s, precision="mixed", device=DEV)
+        try:
+            ctx.set_graphs(graphs)
+            out = []
+            for pos in (t["pos"], torch.tensor(pos_b, device=DEV)):
+                ctx.build_blocklist(pos)
+                e = ctx.perm_field(pos, t["q"], t["dip"], t["quad"])
+                mu, ep, it, st = ctx.polarize(pos, e, tol_debye=1e-7, max_iter=200)
+                assert st == amoeba.AMOEBA_OK
+                torch.cuda.synchronize()
+                out.append((mu.clone(), it, ctx.info()["n_tiles"]))
+            res[graphs] = out
+        finally:
+            ctx.close()
+    (ma, ia, na), (mb, ib, nb) = res[True]
+    assert nb > na, (na, nb)
+    for (m0, i0, _), (m1, i1, _) in zip(res[False], res[True]):
+        assert torch.equal(m0, m1) and i0 == i1

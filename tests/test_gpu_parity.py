@@ -10,6 +10,7 @@ import torch
 
 import oracle as O
 from paper_2011_01207_amd import amoeba, synth
+from parity_util import assert_fields  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
@@ -19,10 +20,6 @@ if not torch.cuda.is_available():
 DEV = "cuda:0"
 
 
-def rel_rms(a, b):
-    a = np.asarray(a)
-    b = np.asarray(b)
-    return float(np.sqrt(np.mean((a - b) ** 2)) / np.sqrt(np.mean(b ** 2)))
 
 
 def tiny_water(n_w, L, K, seed, rc=None):
@@ -71,21 +68,21 @@ def test_real_and_recip_fields(c1, c1_ref, c1_ctx):
     prec, ctx, t = c1_ctx
     mu = torch.tensor(c1_ref["mu"], device=DEV)
     er, ek = ctx.dipole_field_parts(t["pos"], mu)
-    assert rel_rms(er.cpu().numpy(), c1_ref["real"]) < TOL[prec]["real"]
-    assert rel_rms(ek.cpu().numpy(), c1_ref["recip"]) < TOL[prec]["recip"]
+    assert_fields(er.cpu().numpy(), c1_ref["real"], TOL[prec]["real"])
+    assert_fields(ek.cpu().numpy(), c1_ref["recip"], TOL[prec]["recip"])
 
 
 def test_matvec(c1, c1_ref, c1_ctx):
     prec, ctx, t = c1_ctx
     mu = torch.tensor(c1_ref["mu"], device=DEV)
     out = ctx.dipole_matvec(t["pos"], mu).cpu().numpy()
-    assert rel_rms(out, c1_ref["matvec"]) < TOL[prec]["matvec"]
+    assert_fields(out, c1_ref["matvec"], TOL[prec]["matvec"])
 
 
 def test_perm_field(c1, c1_ref, c1_ctx):
     prec, ctx, t = c1_ctx
     e = ctx.perm_field(t["pos"], t["q"], t["dip"], t["quad"]).cpu().numpy()
-    assert rel_rms(e, c1_ref["perm"]) < TOL[prec]["perm"]
+    assert_fields(e, c1_ref["perm"], TOL[prec]["perm"])
 
 
 def test_polarize_c1(c1, c1_ref, c1_ctx):
@@ -137,11 +134,11 @@ def test_solvated_chain_perm_and_matvec(prec):
     e_ref = O.perm_field(s, "spme", idx=idx)
     e = ctx.perm_field(t["pos"], t["q"], t["dip"], t["quad"]).cpu().numpy()[idx]
     tol = 1e-11 if prec == "fp64" else 3e-5
-    assert rel_rms(e, e_ref) < tol
+    assert_fields(e, e_ref, tol)
     mu = rng.standard_normal((s.n, 3)) * 0.05
     q_ref = O.matvec(s, mu, "spme", idx=idx)
     q = ctx.dipole_matvec(t["pos"], torch.tensor(mu, device=DEV)).cpu().numpy()[idx]
-    assert rel_rms(q, q_ref) < (1e-12 if prec == "fp64" else 3e-6)
+    assert_fields(q, q_ref, (1e-12 if prec == "fp64" else 3e-6))
     ctx.close()
 
 
@@ -154,7 +151,7 @@ def test_ragged_single_block_and_no_scaled_pairs():
     ctx, t = amoeba.context_for(s, precision="fp64", device=DEV)
     assert ctx.info()["n_pairs"] == O.count_pairs(s)
     e = ctx.perm_field(t["pos"], t["q"], t["dip"], t["quad"]).cpu().numpy()
-    assert rel_rms(e, O.perm_field(s, "spme")) < 1e-11
+    assert_fields(e, O.perm_field(s, "spme"), 1e-11)
     mu_ref, _, _ = O.pcg(s, O.perm_field(s, "spme"), "spme", tol_debye=1e-10)
     mu, _, _, st = ctx.polarize(t["pos"], torch.tensor(e, device=DEV), tol_debye=1e-9)
     assert st == amoeba.AMOEBA_OK and O.rms_debye(mu.cpu().numpy() - mu_ref) < 1e-8
@@ -181,15 +178,12 @@ def test_near_coincident_atoms(prec):
     # FP64: the direct formulas of both sides cancel at 0.02 A (B2 ~ 3/r^5 ~ 1e9), ~1e-10 relative
     tf = 1e-9 if prec == "fp64" else 2e-6
     er, _ = ctx.dipole_field_parts(t["pos"], mt)
-    err = rel_rms(er.cpu().numpy(), O.real_mutual(s, mu))
-    assert err < tf, err
-    err = rel_rms(ctx.dipole_matvec(t["pos"], mt).cpu().numpy(), O.matvec(s, mu, "spme"))
-    assert err < tf, err
+    assert_fields(er.cpu().numpy(), O.real_mutual(s, mu), tf, what="real field")
+    assert_fields(ctx.dipole_matvec(t["pos"], mt).cpu().numpy(), O.matvec(s, mu, "spme"), tf, what="matvec")
     e_ref = O.perm_field(s, "spme")
     e = ctx.perm_field(t["pos"], t["q"], t["dip"], t["quad"])
-    err = rel_rms(e.cpu().numpy(), e_ref)
     # FP64 permanent field: B3 ~ 15/r^7 ~ 1e13 at 0.02 A cancels in both direct formulas
-    assert err < (1e-7 if prec == "fp64" else 2e-5), err
+    assert_fields(e.cpu().numpy(), e_ref, 1e-7 if prec == "fp64" else 2e-5, what="E_perm")
     mu_ref, _, _ = O.pcg(s, e_ref, "spme", tol_debye=1e-10)
     m, ep, it, st = ctx.polarize(t["pos"], e, tol_debye=1e-7 if prec == "fp64" else 1e-6)
     assert st == amoeba.AMOEBA_OK
@@ -210,10 +204,10 @@ def test_single_atom(prec):
         assert ctx.info()["n_pairs"] == 0
         e_ref = O.perm_field(s, "spme")
         e = ctx.perm_field(t["pos"], t["q"], t["dip"], t["quad"])
-        assert rel_rms(e.cpu().numpy(), e_ref) < (1e-11 if prec == "fp64" else 3e-5)
+        assert_fields(e.cpu().numpy(), e_ref, (1e-11 if prec == "fp64" else 3e-5))
         mu = np.full((1, 3), 0.1)
         q = ctx.dipole_matvec(t["pos"], torch.tensor(mu, device=DEV)).cpu().numpy()
-        assert rel_rms(q, O.matvec(s, mu, "spme")) < (1e-12 if prec == "fp64" else 3e-6)
+        assert_fields(q, O.matvec(s, mu, "spme"), (1e-12 if prec == "fp64" else 3e-6))
         mu_ref, _, _ = O.pcg(s, e_ref, "spme", tol_debye=1e-10)
         m, ep, it, st = ctx.polarize(t["pos"], e, tol_debye=1e-9 if prec == "fp64" else 1e-7)
         assert st == amoeba.AMOEBA_OK
@@ -295,3 +289,33 @@ def test_error_paths(c1):
         ctx.set_atoms(neg, t["thole"], t["sc_ptr"], t["sc_j"], t["sc_s"])
     assert ei.value.status == amoeba.AMOEBA_E_INVALID
     ctx.close()
+
+
+def test_range_and_workspace_errors(c1):
+    """Mixed precision keeps fields as fixed-point integers held in FP64, exact below 8192 e/A^2:
+    the permanent field, the product and the solve report AMOEBA_E_OVERFLOW beyond that range
+    (charges, dipoles or the permanent field scaled up until the host-read check trips), and the
+    context stays usable.  A workspace cap below what a context needs is AMOEBA_E_NOMEM."""
+    print("[gpu] range and workspace errors", flush=True)
+    ctx, t = amoeba.context_for(c1, precision="mixed", device=DEV)
+    try:
+        with pytest.raises(amoeba.AmoebaError) as ei:
+            ctx.perm_field(t["pos"], t["q"] * 4e4, t["dip"], t["quad"])
+        assert ei.value.status == amoeba.AMOEBA_E_OVERFLOW
+        e = ctx.perm_field(t["pos"], t["q"], t["dip"], t["quad"])
+        assert float(e.abs().max()) < 100.0
+        with pytest.raises(amoeba.AmoebaError) as ei:
+            ctx.dipole_matvec(t["pos"], torch.full_like(t["pos"], 2e4))
+        assert ei.value.status == amoeba.AMOEBA_E_OVERFLOW
+        with pytest.raises(amoeba.AmoebaError) as ei:
+            # the tolerance scales with the field, so that the solve converges and its accepted
+            # dipoles reach the range check
+            ctx.polarize(t["pos"], e * 1e5, tol_debye=1.0, max_iter=100)
+        assert ei.value.status == amoeba.AMOEBA_E_OVERFLOW
+        mu, ep, it, st = ctx.polarize(t["pos"], e, tol_debye=1e-5, max_iter=100)
+        assert st == amoeba.AMOEBA_OK and torch.isfinite(mu).all()
+    finally:
+        ctx.close()
+    with pytest.raises(amoeba.AmoebaError) as ei:
+        amoeba.Context(c1.n, c1.box, grid=c1.grid, precision="mixed", max_workspace_bytes=1 << 16)
+    assert ei.value.status == amoeba.AMOEBA_E_NOMEM

@@ -8,6 +8,7 @@ import torch
 
 import oracle as O
 from paper_2011_01207_amd import amoeba, synth
+from parity_util import assert_fields  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
@@ -20,10 +21,6 @@ TOL = {"fp64": 1e-11, "mixed": 2e-5}
 TOL_PATHS = {"fp64": 1e-12, "mixed": 5e-6}
 
 
-def rel_rms(a, b):
-    a = np.asarray(a)
-    b = np.asarray(b)
-    return float(np.sqrt(np.mean((a - b) ** 2)) / np.sqrt(np.mean(b ** 2)))
 
 
 def system(grid, seed=3):
@@ -51,20 +48,17 @@ def test_plane_field_matches_oracle_and_bricks(grid, prec):
         _, ek = ctx.dipole_field_parts(t["pos"], mu_d)
         ek = ek.cpu().numpy()
         q = ctx.dipole_matvec(t["pos"], mu_d).cpu().numpy()
-        err_rec = rel_rms(ek, ref_rec)
-        err_mv = rel_rms(q, ref_mv)
         ctx.set_pme_path("bricks")
         assert ctx.info()["pme_planes"] == 0
         _, ek_b = ctx.dipole_field_parts(t["pos"], mu_d)
+        ek_b = ek_b.cpu().numpy()
         q_b = ctx.dipole_matvec(t["pos"], mu_d).cpu().numpy()
-        err_paths = rel_rms(ek, ek_b.cpu().numpy())
-        err_paths_mv = rel_rms(q, q_b)
     finally:
         ctx.close()
-    assert err_rec < TOL[prec], err_rec
-    assert err_mv < (1e-12 if prec == "fp64" else 2e-6), err_mv
-    assert err_paths < TOL_PATHS[prec], err_paths
-    assert err_paths_mv < TOL_PATHS[prec], err_paths_mv
+    assert_fields(ek, ref_rec, TOL[prec], what="recip field vs oracle")
+    assert_fields(q, ref_mv, 1e-12 if prec == "fp64" else 2e-6, what="matvec vs oracle")
+    assert_fields(ek, ek_b, TOL_PATHS[prec], what="recip field planes vs bricks")
+    assert_fields(q, q_b, TOL_PATHS[prec], what="matvec planes vs bricks")
 
 
 @pytest.mark.parametrize("grid", [(24, 24, 24), (20, 21, 28), (28, 15, 35)], ids=lambda g: "x".join(map(str, g)))
@@ -81,8 +75,8 @@ def test_plane_perm_field_matches_oracle_and_bricks(grid, prec):
         e_b = ctx.perm_field(t["pos"], t["q"], t["dip"], t["quad"]).cpu().numpy()
     finally:
         ctx.close()
-    assert rel_rms(e, ref) < (1e-11 if prec == "fp64" else 2e-5)
-    assert rel_rms(e, e_b) < TOL_PATHS[prec]
+    assert_fields(e, ref, (1e-11 if prec == "fp64" else 2e-5))
+    assert_fields(e, e_b, TOL_PATHS[prec])
 
 
 def test_plane_mixed_is_bitwise_reproducible():
@@ -131,4 +125,4 @@ def test_grid_outside_plane_path_falls_back_to_bricks():
         _, ek = ctx.dipole_field_parts(t["pos"], torch.tensor(mu, device=DEV))
     finally:
         ctx.close()
-    assert rel_rms(ek.cpu().numpy(), ref) < TOL["fp64"]
+    assert_fields(ek.cpu().numpy(), ref, TOL["fp64"])

@@ -1,0 +1,203 @@
+"""Converged induced dipoles against the FP64 oracle, at the stopping tolerance the benchmark
+times (paper, "Performance and Scalability Results": PCG with the diagonal preconditioner to a
+fixed threshold), on the paper-sized workloads.
+
+For every case the oracle computes its exact solution mu* (smooth-PME mode on the same grid,
+order, beta and cutoff, PCG to 1e-9 D) and its own PCG at the benchmark tolerance.  The GPU
+solve must then
+
+  * lie within 1e-5 D rms of mu* (the target), with its per-atom maximum error no worse than
+    the oracle's own PCG at the same tolerance (plus rounding);
+  * need the oracle's iteration count, +-1;
+  * equal, atom by atom, the oracle's PCG iterate after the same number of iterations (FP64 to
+    rounding; mixed precision to the FP32 pair/PME arithmetic);
+  * give E_pol within 1e-6 relative of the oracle's E_pol(mu*).
+
+The non-zero starts of the PCG (given, learned, judged) are checked the same way against the
+oracle's PCG started from the same mu0."""
+import numpy as np
+import pytest
+import torch
+
+import bench
+import oracle as O
+from oracle import guess as G
+from paper_2011_01207_amd import amoeba, synth
+
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+DEV = "cuda:0"
+TOL = bench.TOL_DEBYE       # the benchmark's stopping tolerance (rms of alpha r, Debye)
+MU_BAR = 1e-5               # target: rms |mu - mu*| in Debye
+REF_TOL = 1e-9              # oracle's exact solution
+
+# iterate parity against the oracle's PCG after the same number of iterations (Debye): rms, max
+ITERATE_BAR = {"fp64": (1e-9, 1e-8), "mixed": (1e-5, 1e-4)}
+
+
+def errs(a, b):
+    """(rms, max) over atoms of |a_i - b_i| in Debye."""
+    d = np.linalg.norm(np.asarray(a).reshape(-1, 3) - np.asarray(b).reshape(-1, 3), axis=1)
+    return O.DEBYE * float(np.sqrt(np.mean(d * d))), O.DEBYE * float(np.max(d))
+
+
+CASES = {
+    "water_648": synth.water648,
+    "solvated_chain_23558": synth.solvated_chain,
+    "water_96000": synth.water96k,
+    "water_864000_subcell": lambda: synth.subcell(synth.water864k()),
+}
+_REF = {}
+
+
+def reference(name):
+    """System, oracle E_perm, mu*, E_pol(mu*) and the oracle's iterates up to the benchmark
+    tolerance (computed once per case)."""
+    if name not in _REF:
+        s = CASES[name]()
+        print(f"[gpu] oracle reference {name} (N={s.n})", flush=True)
+        e = O.perm_field(s, "spme")
+        iterates = {}
+        first_tol = []
+
+        def keep(k, mu, rms):
+            iterates[k] = mu.copy()
+            if rms < TOL and not first_tol:
+                first_tol.append(k)
+
+        mu_star, it_star, _ = O.pcg(s, e, "spme", tol_debye=REF_TOL, on_iterate=keep)
+        it_tol = first_tol[0]
+        _REF[name] = {"s": s, "e": e, "mu_star": mu_star, "ep_star": O.e_pol(mu_star, e),
+                      "iterates": iterates, "it_tol": it_tol, "mu_tol": iterates[it_tol]}
+    return _REF[name]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("name", list(CASES))
+def test_zero_start_matches_oracle(name, prec):
+    ref = reference(name)
+    s = ref["s"]
+    print(f"[gpu] solve parity {name} {prec} tol {TOL:g}", flush=True)
+    ctx, t = amoeba.context_for(s, precision=prec, device=DEV)
+    try:
+        e = ctx.perm_field(t["pos"], t["q"], t["dip"], t["quad"])
+        mu, ep, it, st = ctx.polarize(t["pos"], e, tol_debye=TOL, max_iter=200)
+        assert st == amoeba.AMOEBA_OK
+        mu = mu.cpu().numpy()
+    finally:
+        ctx.close()
+    rms, mx = errs(mu, ref["mu_star"])
+    rms_o, mx_o = errs(ref["mu_tol"], ref["mu_star"])
+    k = min(it, max(ref["iterates"]))
+    rms_k, mx_k = errs(mu, ref["iterates"][k])
+    dep = abs(ep - ref["ep_star"]) / abs(ref["ep_star"])
+    print(f"  mu vs mu*: rms {rms:.3e} D, max {mx:.3e} D (oracle PCG at tol: rms {rms_o:.3e}, max {mx_o:.3e}); "
+          f"iterations {it} (oracle {ref['it_tol']}); iterate {k} vs oracle: rms {rms_k:.3e} max {mx_k:.3e} D; "
+          f"E_pol {ep:.6f} vs {ref['ep_star']:.6f} (rel {dep:.2e})", flush=True)
+    assert rms <= MU_BAR
+    assert mx <= 1.5 * mx_o + 10 * ITERATE_BAR[prec][0]
+    assert abs(it - ref["it_tol"]) <= 1
+    assert rms_k <= ITERATE_BAR[prec][0] and mx_k <= ITERATE_BAR[prec][1]
+    assert dep <= 1e-6
+
+
+def noisy(mu, sigma_debye, seed):
+    """mu plus seeded Gaussian noise of sigma_debye rms per atom vector."""
+    rng = np.random.default_rng(seed)
+    return mu + rng.standard_normal(mu.shape) * (sigma_debye / O.DEBYE / np.sqrt(3.0))
+
+
+def oracle_start(ref, mu0):
+    """Iterations and result of the oracle's PCG from mu0 at the benchmark tolerance, and the
+    rms (Debye) of its preconditioned initial residual alpha (E - A mu0)."""
+    s = ref["s"]
+    r0 = []
+    mu, it, hist = O.pcg(s, ref["e"], "spme", tol_debye=TOL, mu0=mu0,
+                         on_iterate=lambda k, m, rz: r0.append(rz) if k == 0 else None)
+    return it, mu, r0[0]
+
+
+def random_model(seed, scale=0.05):
+    """Seeded network weights with a non-zero last layer (a start unlike the plain bases)."""
+    rng = np.random.default_rng(seed)
+    m = synth.guess_init_model(seed=seed).astype(np.float64)
+    m[G.NPARAM - 3 * 64 - 3:G.NPARAM] = rng.standard_normal(3 * 64 + 3) * scale
+    m[G.NPARAM:G.NPARAM + G.NFEAT] = 0.0
+    m[G.NPARAM + G.NFEAT:] = 1.0
+    return m.astype(np.float32)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("name", ["water_648", "solvated_chain_23558"])
+def test_given_start_matches_oracle(name, prec):
+    """A start near the solution (mu* plus 0.01 D of noise) and one far from it (0.1 D)."""
+    ref = reference(name)
+    s = ref["s"]
+    ctx, t = amoeba.context_for(s, precision=prec, device=DEV)
+    try:
+        e = ctx.perm_field(t["pos"], t["q"], t["dip"], t["quad"])
+        for sigma, seed in ((0.01, 31), (0.1, 32)):
+            mu0 = noisy(ref["mu_star"], sigma, seed)
+            print(f"[gpu] given start {name} {prec} sigma {sigma} D", flush=True)
+            mu, ep, it, st = ctx.polarize(t["pos"], e, mu_guess=torch.tensor(mu0, device=DEV), guess_mode="given",
+                                          tol_debye=TOL, max_iter=200)
+            assert st == amoeba.AMOEBA_OK and ctx.info()["last_guess"] == amoeba.AMOEBA_GUESS_GIVEN
+            it_o, mu_o, _ = oracle_start(ref, mu0)
+            rms, mx = errs(mu.cpu().numpy(), ref["mu_star"])
+            rms_k, mx_k = errs(mu.cpu().numpy(), mu_o)
+            print(f"  iterations {it} (oracle {it_o}); mu vs mu*: rms {rms:.3e} max {mx:.3e} D; vs oracle "
+                  f"PCG from mu0: rms {rms_k:.3e} max {mx_k:.3e} D", flush=True)
+            assert abs(it - it_o) <= 1
+            assert rms <= MU_BAR
+            if it == it_o:
+                assert rms_k <= ITERATE_BAR[prec][0] and mx_k <= ITERATE_BAR[prec][1]
+    finally:
+        ctx.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("model_seed", [None, 71])
+def test_learned_and_judged_starts_match_oracle(model_seed, prec):
+    """The learned start with the untrained network (the plain sum of its three bases) and with
+    seeded weights; the oracle computes the same mu0 from its own bases, features and network.
+    The judged start compares the learned guess with a given one by the preconditioned initial
+    residual: the GPU's two residuals equal the oracle's, and it picks the smaller."""
+    ref = reference("water_648")
+    s = ref["s"]
+    # the untrained network (zero last layer) returns v0 + v1 + v2 whatever its normalisation
+    model = synth.guess_init_model(seed=7) if model_seed is None else random_model(model_seed)
+    x, b = G.features(s, ref["e"])
+    mu0_l = G.forward(model.astype(np.float64), x, b)
+    ctx, t = amoeba.context_for(s, precision=prec, device=DEV)
+    try:
+        ctx.guess_set_model(model)
+        e = ctx.perm_field(t["pos"], t["q"], t["dip"], t["quad"])
+        print(f"[gpu] learned start water_648 {prec} model {model_seed}", flush=True)
+        mu, _, it, st = ctx.polarize(t["pos"], e, guess_mode="learned", tol_debye=TOL, max_iter=200)
+        assert st == amoeba.AMOEBA_OK and ctx.info()["last_guess"] == amoeba.AMOEBA_GUESS_LEARNED
+        it_o, mu_o, r0_l = oracle_start(ref, mu0_l)
+        rms, mx = errs(mu.cpu().numpy(), ref["mu_star"])
+        print(f"  iterations {it} (oracle {it_o}); mu vs mu*: rms {rms:.3e} max {mx:.3e} D", flush=True)
+        assert abs(it - it_o) <= 1
+        assert rms <= MU_BAR
+        for sigma, seed in ((0.01, 41), (0.3, 42)):
+            mu0_g = noisy(ref["mu_star"], sigma, seed)
+            _, _, r0_g = oracle_start(ref, mu0_g)
+            mu, _, it, st = ctx.polarize(t["pos"], e, mu_guess=torch.tensor(mu0_g, device=DEV), guess_mode="best",
+                                         tol_debye=TOL, max_iter=200)
+            assert st == amoeba.AMOEBA_OK
+            inf = ctx.info()
+            rf, rl = inf["last_guess_rms_debye"]
+            print(f"  judged start (given {sigma} D): GPU residuals given {rf:.6e} learned {rl:.6e}, oracle "
+                  f"{r0_g:.6e} {r0_l:.6e}; picked {inf['last_guess']}", flush=True)
+            bar = 1e-9 if prec == "fp64" else 1e-4
+            assert abs(rf - r0_g) <= bar * r0_g and abs(rl - r0_l) <= bar * r0_l
+            want = amoeba.AMOEBA_GUESS_LEARNED if r0_l < r0_g else amoeba.AMOEBA_GUESS_GIVEN
+            if abs(r0_l - r0_g) > 0.01 * min(r0_l, r0_g):
+                assert inf["last_guess"] == want
+            assert errs(mu.cpu().numpy(), ref["mu_star"])[0] <= MU_BAR
+    finally:
+        ctx.close()

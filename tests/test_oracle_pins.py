@@ -385,3 +385,71 @@ def test_generator_counts():
     assert c.n == 23558 == 2489 + 3 * 7023
     assert c.sc_ptr[-1] == 2 * 28530
     assert np.count_nonzero(c.sc_s == 0.5) == 2 * 2486
+
+
+# ------------------------------------------------------------------------------------------
+# pair counting and partner search
+# ------------------------------------------------------------------------------------------
+
+# Number of integer vectors (i, j, k) with i^2 + j^2 + k^2 = m (sums of three squares): the
+# coordination shells of the simple cubic lattice.  m = 7 has no representation.
+R3 = {1: 6, 2: 12, 3: 8, 4: 6, 5: 24, 6: 24, 7: 0, 8: 12, 9: 30, 10: 24}
+
+
+def cubic_lattice(n_edge, spacing, seed=0, shift=0.0):
+    s = synth.tiny_cell(2, n_edge * spacing, seed, with_multipoles=False)
+    g = np.arange(n_edge) * spacing + shift
+    s.pos = np.stack(np.meshgrid(g, g, g, indexing="ij"), axis=-1).reshape(-1, 3)
+    s.box = np.full(3, n_edge * spacing)
+    return s
+
+
+@pytest.mark.parametrize("search", ["all", "cells"])
+@pytest.mark.parametrize("rc2, shells", [(6.5, 6), (5.0, 4), (9.5, 9), (2.0, 1)])
+def test_pair_count_on_cubic_lattice(search, rc2, shells):
+    """Unordered pairs within rc of a periodic simple cubic lattice: N/2 times the lattice
+    vectors with |v| < rc.  rc^2 = 5 a^2 puts rc exactly on the fifth shell (sqrt(20) and
+    2 sqrt(5) are the same double), which the strict r < rc must leave out; shells wrapping
+    through the faces are counted only with the minimum image."""
+    a, n_edge = 2.0, 8
+    s = cubic_lattice(n_edge, a, shift=0.375)   # exact in binary: lattice differences stay exact
+    rc = a * math.sqrt(rc2)
+    per_atom = sum(R3[m] for m in R3 if m <= shells and m < rc2)
+    assert O.count_pairs(s, rc=rc, search=search) == n_edge ** 3 * per_atom // 2
+
+
+def test_cell_search_finds_the_same_pairs_as_all_pairs():
+    """The periodic cell grid (at least three cells of width >= rc per axis) finds every pair
+    within rc: same counts, and the same fields up to the order of the sums, on a box with atoms
+    placed on the cell faces and in the solvated chain with its scaled pairs."""
+    s = synth.tiny_cell(300, 22.0, 5, min_dist=0.8)
+    # atoms exactly on the cell boundaries (multiples of L/3) and at the box edge
+    s.pos[:6] = [[0.0, 0.0, 0.0], [22.0 / 3, 5.0, 5.0], [44.0 / 3, 44.0 / 3, 1.0], [21.999999, 3.0, 7.0],
+                 [7.0, 22.0 / 3 + 7.0, 3.0], [11.0, 11.0, 22.0 / 3]]
+    assert O.cell_bins(s.pos, s.box, s.cutoff) is not None
+    assert O.count_pairs(s, search="cells") == O.count_pairs(s, search="all")
+    rng = np.random.default_rng(3)
+    mu = rng.standard_normal((s.n, 3)) * 0.05
+    a = O.real_mutual(s, mu, search="cells")
+    b = O.real_mutual(s, mu, search="all")
+    assert np.max(np.abs(a - b)) <= 1e-13 * np.max(np.abs(b))
+    c = synth.solvated_chain()
+    idx = np.sort(rng.choice(c.n, 1500, replace=False))
+    assert O.count_pairs(c, search="cells") == O.count_pairs(c, search="all")
+    a = O.real_perm(c, idx=idx, search="cells")
+    b = O.real_perm(c, idx=idx, search="all")
+    assert np.max(np.abs(a - b)) <= 1e-13 * np.max(np.abs(b))
+    mu = rng.standard_normal((c.n, 3)) * 0.05
+    a = O.real_mutual(c, mu, idx=idx, search="cells")
+    b = O.real_mutual(c, mu, idx=idx, search="all")
+    assert np.max(np.abs(a - b)) <= 1e-13 * np.max(np.abs(b))
+
+
+def test_unit_constants_from_si():
+    """Debye per e*A and the Coulomb constant in kcal*A/(mol e^2), from the exact SI values of
+    e, c, N_A and the thermochemical calorie, and CODATA 2018 epsilon_0."""
+    e, c, na, eps0 = 1.602176634e-19, 299792458.0, 6.02214076e23, 8.8541878128e-12
+    debye = e * 1e-10 / (1e-21 / c)          # e*A in C*m over 1 D = 1e-21/c C*m
+    assert O.DEBYE == pytest.approx(debye, rel=2e-6)
+    coulomb = e * e / (4 * math.pi * eps0) * 1e10 * na / 4184.0
+    assert O.COULOMB == pytest.approx(coulomb, rel=2e-7)
