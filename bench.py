@@ -1,21 +1,33 @@
 #!/usr/bin/env python
 """Benchmark: induced-dipole solves per second to 1e-5 D rms on one MI355X.
 
-Workload: 32,000 rigid waters (96,000 atoms) in a 98.65 A box, 7 A real-space cutoff with a
-2 A list buffer, Ewald beta 0.545 1/A, PME grid 108^3 of order 5 (synthetic, seeded).  One
-step processes one configuration end to end on the GPU with inputs resident in HBM: block-list
-build, permanent field E_perm, and the PCG solve of (alpha^-1 - T) mu = E_perm from a zero
-guess to 1e-5 D rms of the preconditioned residual.  `value` is steps (= solves) per second in
-mixed precision; the FP64 path is timed the same way and reported beside it.
+Headline workload (the largest single-GPU configuration): 288,000 rigid waters (864,000 atoms)
+in a 205.0 A box, 7 A real-space cutoff with a 2 A list buffer, Ewald beta 0.545 1/A, PME grid
+216^3 of order 5 (synthetic, seeded).  One step processes one configuration end to end on the
+GPU with inputs resident in HBM: block-list build, permanent field E_perm, the learned initial
+guess (bases, features, network) and the mixed-precision PCG solve of (alpha^-1 - T) mu = E_perm
+from that guess to the stopping tolerance, E_pol included.  The configurations are held-out
+frames of a 0.02 A-step trajectory of the box; the network was trained beforehand on the GPU
+(its own kernels) on the solver's converged dipoles of the preceding frames.  `value` is steps
+(= solves) per second over the timed steps; the per-step median, p10 and p90 are reported too.
+Beside it, on the same frames: mixed precision from the zero guess, and the plain FP64 PCG from
+the zero guess (the baseline the speed-ups refer to).
 
-The roofline entry is computed from HIP-event timing of every kernel launch in the timed
-region (library stage timers, same stream); the CPU baseline times the FP64 oracle on a
-bounded sample of the same workload on this host.
+Accuracy: the converged dipoles of every variant on the 864,000-atom box are compared with the
+FP64 GPU solve, and on a periodic ~4,000-atom subcell of the same box with the FP64 oracle's
+exact solution (rms and max |mu - mu*|, E_pol error).  Secondary legs: the 648-, 23,558- and
+96,000-atom workloads (FP64 and mixed), and the 288,000-atom trajectory (train on 150 frames,
+evaluate 50 from the zero, previous-step, learned and judged starts).
+
+The roofline entry is the dominant kernel of the headline leg, timed with HIP events on the
+stream it runs on; the CPU baseline times the FP64 oracle on this host (one full matrix-vector
+product and one permanent field of the headline box, scaled by the iteration count).
 """
 import argparse
 import json
 import math
 import os
+import statistics
 import sys
 import time
 
@@ -27,6 +39,7 @@ METRIC = "induced-dipole solves/s to 1e-5 D rms (FP64 vs mixed vs learned guess)
 # the same for the FP64, mixed and learned-start variants.  The GPU tests check at exactly this
 # tolerance that the converged dipoles lie within 1e-5 D rms of the oracle's exact solution.
 TOL_DEBYE = 1e-5
+DEBYE = 4.80320
 PEAK_FP32_VALU = 157.3     # TFLOP/s, MI355X published FP32 vector peak (packed FMA)
 PEAK_FP32_NONPACKED = 78.6 # TFLOP/s: 256 CUs x 64 lanes x 2 FLOP x 2.4 GHz (packed FP32 is disabled)
 PEAK_HBM = 8000.0          # GB/s
@@ -35,6 +48,8 @@ PEAK_HBM = 8000.0          # GB/s
 # loop control and masked slots not counted.
 FLOPS_PER_PAIR = 80
 STAGES = ["list", "perm", "real", "spread", "fft", "gather", "pcg", "guess"]
+DTYPE = ("f32 pair/PME math; fields summed as integer-valued f64 fixed point (2^-40 e/A^2); f64 PCG "
+         "vectors, dot products and convergence test; f32 network")
 
 
 def log(msg):
@@ -44,312 +59,400 @@ def log(msg):
 def parse():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--tol", type=float, default=TOL_DEBYE)
+    ap.add_argument("--workload", default="water_864000", choices=["water_864000", "water_96000"],
+                    help="headline workload (the other sizes run as secondary legs)")
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle timing leg")
-    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison leg")
-    ap.add_argument("--no-learned", action="store_true", help="skip the learned-guess trajectory leg")
+    ap.add_argument("--no-secondary", action="store_true", help="skip the 648/23,558/96,000-atom legs")
+    ap.add_argument("--no-trajectory", action="store_true", help="skip the 288,000-atom trajectory leg")
+    ap.add_argument("--no-subcell", action="store_true", help="skip the oracle accuracy check on the subcell")
     ap.add_argument("--pair-store", default="auto", choices=["auto", "compute", "stored"],
                     help="how the real-space dipole products get their pair coefficients")
-    ap.add_argument("--trajectory-288k", action="store_true",
-                    help="add the 288,000-atom trajectory leg: 200 configurations, train on 150, "
-                         "evaluate the learned and previous-step guesses on the last 50")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="end with three plain 256 MiB device-to-device copies (the reference dispatch that "
                          "scales the FETCH_SIZE / WRITE_SIZE counters of a profiling run)")
     return ap.parse_args()
 
 
-def timing_dict(ctx):
-    from paper_2011_01207_amd import amoeba
-    import ctypes
-    t = amoeba.amoeba_timing()
-    st = amoeba.lib().amoeba_get_timing(ctx.h, ctypes.byref(t))
-    if st != 0:
-        raise RuntimeError("amoeba_get_timing failed")
-    return {"ms": {STAGES[i]: t.ms[i] for i in range(len(STAGES))},
-            "launches": {STAGES[i]: int(t.launches[i]) for i in range(len(STAGES))}, "matvecs": int(t.matvecs)}
+def pstats(times_ms):
+    """median, p10, p90 and mean of per-step times (ms), linear interpolation between ranks."""
+    v = sorted(times_ms)
+
+    def q(p):
+        x = p * (len(v) - 1)
+        lo = int(math.floor(x))
+        hi = min(lo + 1, len(v) - 1)
+        return v[lo] + (v[hi] - v[lo]) * (x - lo)
+    return {"median_ms": q(0.5), "p10_ms": q(0.1), "p90_ms": q(0.9), "mean_ms": statistics.fmean(v)}
 
 
-def run_variant(s, t, precision, steps, warmup, tol, timing=True, pair_store="auto"):
+def tensors(s, dev="cuda:0"):
     import torch
+    t = {k: torch.tensor(getattr(s, k), device=dev) for k in ("pos", "q", "dip", "quad", "alpha", "thole", "sc_s")}
+    t["sc_ptr"] = torch.tensor(s.sc_ptr, dtype=torch.int32, device=dev)
+    t["sc_j"] = torch.tensor(s.sc_j, dtype=torch.int32, device=dev)
+    return t
+
+
+def new_context(s, t, precision, pair_store="auto"):
     from paper_2011_01207_amd import amoeba
     ctx = amoeba.Context(s.n, s.box, cutoff=s.cutoff, buffer=s.buffer, ewald_alpha=s.ewald_alpha, grid=s.grid,
                          order=s.order, precision=precision)
     ctx.set_pair_store(pair_store)
     ctx.set_atoms(t["alpha"], t["thole"], t["sc_ptr"], t["sc_j"], t["sc_s"])
-    e_perm = torch.empty_like(t["pos"])
-    mu = torch.empty_like(t["pos"])
+    return ctx
 
-    def step():
-        ctx.build_blocklist(t["pos"])
-        ctx.perm_field(t["pos"], t["q"], t["dip"], t["quad"], out=e_perm)
-        _, ep, it, st = ctx.polarize(t["pos"], e_perm, tol_debye=tol, max_iter=1000, out=mu)
+
+def run_steps(ctx, t, frames, steps, warmup, tol, guess="zero", prev=None, timing_live=False, stage_pass=False):
+    """`steps` steps cycling over `frames` (device position tensors): list + E_perm + solve from
+    `guess` ('zero', 'learned', or 'given'/'best' with prev[k] the previous frame's dipoles).
+    Returns per-step times, iterations, the last frame's outputs and the timers."""
+    import torch
+    from paper_2011_01207_amd import amoeba
+    e_perm = torch.empty_like(frames[0])
+    mu = torch.empty_like(frames[0])
+
+    def step(k):
+        pos = frames[k % len(frames)]
+        ctx.build_blocklist(pos)
+        ctx.perm_field(pos, t["q"], t["dip"], t["quad"], out=e_perm)
+        g = prev[k % len(frames)] if guess in ("given", "best") else None
+        _, ep, it, st = ctx.polarize(pos, e_perm, mu_guess=g, guess_mode=guess, tol_debye=tol, max_iter=1000,
+                                     out=mu)
         if st != amoeba.AMOEBA_OK:
-            raise RuntimeError(f"solve did not converge (status {st})")
+            raise RuntimeError(f"{guess} solve did not converge (status {st})")
         return ep, it
 
-    for _ in range(warmup):
-        step()
+    for k in range(warmup):
+        step(k)
     torch.cuda.synchronize()
-    # the timed region, with the real-space tile launches bracketed by HIP events on the stream
-    # they run on (the dominant kernel's live duration for the roofline; two events per product)
-    if timing:
-        amoeba.lib().amoeba_set_timing(ctx.h, 2)
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        ep, it = step()
+    if timing_live:
+        ctx.set_timing("live")
+    times, its, picks, eps = [], [], [], []
+    t_all = time.perf_counter()
+    for k in range(steps):
+        t0 = time.perf_counter()
+        ep, it = step(k)
+        times.append(1e3 * (time.perf_counter() - t0))
+        its.append(it)
+        eps.append(ep)
+        picks.append(ctx.info()["last_guess"])
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    tim = tim_live = None
-    if timing:
-        tim_live = timing_dict(ctx)
-        amoeba.lib().amoeba_set_timing(ctx.h, 0)
-        # a second pass of the same steps with every launch bracketed by HIP events on the
-        # library's stream (the per-stage kernel times of the roofline); not part of `value`
-        amoeba.lib().amoeba_set_timing(ctx.h, 1)
-        for _ in range(steps):
-            step()
-        tim = timing_dict(ctx)
-        amoeba.lib().amoeba_set_timing(ctx.h, 0)
-    # solve-only rate (list and E_perm given), untimed by the stage timers
-    torch.cuda.synchronize()
-    u0 = time.perf_counter()
-    for _ in range(steps):
-        _, ep2, it2, _ = ctx.polarize(t["pos"], e_perm, tol_debye=tol, max_iter=1000, out=mu)
-    torch.cuda.synchronize()
-    u1 = time.perf_counter()
-    info = ctx.info()
-    out = {"step_ms": 1e3 * (t1 - t0) / steps, "solve_only_ms": 1e3 * (u1 - u0) / steps, "iterations": it,
-           "e_pol_kcal": ep, "n_pairs": info["n_pairs"], "n_tiles": info["n_tiles"], "n_blocks": info["n_blocks"],
-           "pme_planes": info["pme_planes"], "pair_min_image": info["pair_min_image"],
-           "pair_store": info["pair_store"], "pair_store_bytes": info["pair_store_bytes"],
-           "timing": tim, "timing_live": tim_live, "mu": mu.clone(), "e_perm": e_perm.clone()}
-    ctx.close()
+    total = time.perf_counter() - t_all
+    out = {"step_ms": 1e3 * total / steps, "solves_per_s": steps / total, **pstats(times),
+           "iterations": its[-1], "mean_iterations": statistics.fmean(its), "e_pol_kcal": eps[-1],
+           "learned_picked": sum(1 for p in picks if p == amoeba.AMOEBA_GUESS_LEARNED),
+           # real-space products per pass of `steps` steps besides the PCG products: the learned
+           # guess's two basis products per step
+           "extra_real_products": 2 * steps if guess in ("learned", "best") else 0}
+    out["timing_live"] = ctx.timing() if timing_live else None
+    ctx.set_timing("off")
+    if stage_pass:
+        # the same steps again with every launch bracketed by HIP events on the library's stream
+        # (each stage alone): the per-stage kernel times; not part of `value`
+        ctx.set_timing("stages")
+        for k in range(steps):
+            step(k)
+        out["timing"] = ctx.timing()
+        ctx.set_timing("off")
+        out["kernel_ms_per_step"] = {k: v / steps for k, v in out["timing"]["ms"].items()}
+        out["matvecs_per_step"] = out["timing"]["matvecs"] / steps
+    inf = ctx.info()
+    out.update({k: inf[k] for k in ("n_pairs", "n_tiles", "n_blocks", "pme_planes", "pair_min_image", "pair_store",
+                                    "pair_store_bytes")})
+    # outputs of the last timed frame (for the accuracy comparisons)
+    ep, _ = step(steps - 1)
+    out["e_pol_kcal"] = ep
+    out["mu"] = mu.clone()
     return out
 
 
-def learned_leg(s, t, steps, tol, n_train=8, n_eval=4, train_steps=600, batch=16384, seed=204):
-    """Mixed precision on a 0.02 A-step trajectory of the same box: the network is trained on
-    the solver's own converged dipoles of the first n_train configurations (GPU kernels), then
-    the next n_eval configurations are solved from the zero, previous-step, learned and judged
-    (learned vs previous-step) starts, `steps` solves per start cycling over them.  One step =
-    list + E_perm + solve, as in the main leg."""
-    import numpy as np
-    import torch
-    from paper_2011_01207_amd import amoeba, synth
-    frames = list(synth.trajectory(s, n_train + n_eval + 1, 0.02, seed=seed))
-    ctx = amoeba.Context(s.n, s.box, cutoff=s.cutoff, buffer=s.buffer, ewald_alpha=s.ewald_alpha, grid=s.grid,
-                         order=s.order, precision="mixed")
-    ctx.set_atoms(t["alpha"], t["thole"], t["sc_ptr"], t["sc_j"], t["sc_s"])
+def reference_data(ctx, t, frames, tol_ref=1e-6):
+    """Training data from the solver itself: per frame the converged dipoles (to tol_ref) and the
+    network's features and bases (GPU kernels)."""
+    from paper_2011_01207_amd import amoeba
     data = []
-    t0 = time.perf_counter()
-    for p in frames:
-        pos = torch.tensor(p, device=t["pos"].device)
+    for pos in frames:
         ctx.build_blocklist(pos)
         e = ctx.perm_field(pos, t["q"], t["dip"], t["quad"])
-        mu, _, _, st = ctx.polarize(pos, e, tol_debye=1e-6, max_iter=1000)
+        mu, _, _, st = ctx.polarize(pos, e, tol_debye=tol_ref, max_iter=1000)
         if st != amoeba.AMOEBA_OK:
             raise RuntimeError("reference solve did not converge")
         feat, basis = ctx.guess_features(pos, e)
         data.append({"pos": pos, "e": e, "mu": mu.clone(), "feat": feat, "basis": basis})
-    torch.cuda.synchronize()
-    t_data = time.perf_counter() - t0
-    tr = data[1:n_train + 1]
-    feat = torch.cat([d["feat"] for d in tr])
-    basis = torch.cat([d["basis"] for d in tr])
-    target = torch.cat([d["mu"] for d in tr]).float()
+    return data
+
+
+def train(ctx, data, train_steps, batch, lr=2e-3, seed=5):
+    """Fit the network on the GPU: feature statistics, then Adam steps on random batches."""
+    import numpy as np
+    import torch
+    from paper_2011_01207_amd import synth
+    feat = torch.cat([d["feat"] for d in data])
+    basis = torch.cat([d["basis"] for d in data])
+    target = torch.cat([d["mu"] for d in data]).float()
     ctx.guess_set_model(synth.guess_init_model(seed=7))
     ctx.guess_fit_norm(feat)
-    rng = np.random.default_rng(5)
+    rng = np.random.default_rng(seed)
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
     losses = []
     for k in range(train_steps):
         idx = torch.tensor(rng.integers(0, feat.shape[0], batch).astype(np.int32), device=feat.device)
-        losses.append(ctx.guess_train_step(feat, basis, target, 2e-3, idx=idx))
+        losses.append(ctx.guess_train_step(feat, basis, target, lr, idx=idx))
     torch.cuda.synchronize()
-    t_train = time.perf_counter() - t0
-    ev = data[n_train + 1:]
-    prevs = [data[n_train + k]["mu"] for k in range(n_eval)]
-    out = {"train_configs": n_train, "eval_configs": n_eval, "train_samples": int(feat.shape[0]),
-           "train_steps": train_steps, "batch": batch, "loss_first_d2": float(np.mean(losses[:20])),
-           "loss_last_d2": float(np.mean(losses[-20:])), "reference_solves_s": t_data, "train_s": t_train,
-           "guess_rms_err_debye": float(np.mean([
-               4.80320 * float(torch.sqrt(torch.sum((ctx.guess_forward(d["feat"], d["basis"]).double() - d["mu"]) ** 2)
-                                          / s.n)) for d in ev])),
-           "prev_rms_err_debye": float(np.mean([
-               4.80320 * float(torch.sqrt(torch.sum((prevs[k] - ev[k]["mu"]) ** 2) / s.n)) for k in range(n_eval)])),
-           "modes": {}}
-    mu = torch.empty_like(t["pos"])
-    e_buf = torch.empty_like(t["pos"])
-    for mode in ("zero", "given", "learned", "best"):
-        def step(k):
-            d = ev[k % n_eval]
-            ctx.build_blocklist(d["pos"])
-            ctx.perm_field(d["pos"], t["q"], t["dip"], t["quad"], out=e_buf)
-            g = prevs[k % n_eval] if mode in ("given", "best") else None
-            _, _, it, st = ctx.polarize(d["pos"], e_buf, mu_guess=g, guess_mode=mode, tol_debye=tol, max_iter=1000,
-                                        out=mu)
-            if st != amoeba.AMOEBA_OK:
-                raise RuntimeError(f"{mode} solve did not converge")
-            return it
-        for k in range(2):
-            step(k)
-        torch.cuda.synchronize()
-        its, picks = [], []
-        t0 = time.perf_counter()
-        for k in range(steps):
-            its.append(step(k))
-            picks.append(ctx.info()["last_guess"])
-        torch.cuda.synchronize()
-        ms = 1e3 * (time.perf_counter() - t0) / steps
-        amoeba.lib().amoeba_set_timing(ctx.h, 1)
-        for k in range(steps):
-            step(k)
-        tim = timing_dict(ctx)
-        amoeba.lib().amoeba_set_timing(ctx.h, 0)
-        name = {"given": "previous_step"}.get(mode, mode)
-        out["modes"][name] = {"step_ms": ms, "solves_per_s": 1e3 / ms, "mean_iterations": float(np.mean(its)),
-                              "learned_picked": int(sum(1 for p in picks if p == amoeba.AMOEBA_GUESS_LEARNED)),
-                              "kernel_ms_per_step": {k: v / steps for k, v in tim["ms"].items()},
-                              "matvecs_per_step": tim["matvecs"] / steps}
+    return {"train_samples": int(feat.shape[0]), "train_steps": train_steps, "batch": batch,
+            "loss_first_d2": float(np.mean(losses[:20])), "loss_last_d2": float(np.mean(losses[-20:])),
+            "train_s": time.perf_counter() - t0}
+
+
+def mu_errors(a, b):
+    """rms and max over atoms of |a_i - b_i| in Debye (device or host arrays)."""
+    import numpy as np
+    a = a.cpu().numpy() if hasattr(a, "cpu") else np.asarray(a)
+    b = b.cpu().numpy() if hasattr(b, "cpu") else np.asarray(b)
+    d = np.linalg.norm(a.reshape(-1, 3) - b.reshape(-1, 3), axis=1)
+    return {"mu_rms_debye": float(DEBYE * np.sqrt(np.mean(d * d))), "mu_max_debye": float(DEBYE * np.max(d))}
+
+
+def strip(res):
+    return {k: v for k, v in res.items() if k not in ("mu", "timing")}
+
+
+def headline(s, t, a):
+    """The headline box: training, then mixed + learned, mixed (zero) and FP64 (zero) on the
+    same held-out frames."""
+    import torch
+    from paper_2011_01207_amd import synth
+    n_train, n_eval = 8, 4
+    frames = [torch.tensor(p, device="cuda:0") for p in synth.trajectory(s, n_train + n_eval + 1, 0.02, seed=504)]
+    train_frames, eval_frames = frames[1:n_train + 1], frames[n_train + 1:]
+    log(f"{s.name}: training the learned guess on {n_train} frames")
+    ctx = new_context(s, t, "mixed", a.pair_store)
+    t0 = time.perf_counter()
+    data = reference_data(ctx, t, train_frames)
+    t_ref = time.perf_counter() - t0
+    tr = train(ctx, data, train_steps=600, batch=65536)
+    del data
+    tr.update({"reference_solves_s": t_ref, "train_configs": n_train, "eval_configs": n_eval})
+    model = ctx.guess_get_model()
+    held = reference_data(ctx, t, eval_frames)
+    tr["guess_rms_err_debye"] = statistics.fmean(
+        mu_errors(ctx.guess_forward(d["feat"], d["basis"]).double(), d["mu"])["mu_rms_debye"] for d in held)
+    del held
+    log(f"{s.name}: mixed + learned guess")
+    learned = run_steps(ctx, t, eval_frames, a.steps, a.warmup, a.tol, guess="learned", timing_live=True,
+                        stage_pass=True)
     ctx.close()
+    log(f"{s.name}: mixed + learned {learned['step_ms']:.3f} ms/step (median {learned['median_ms']:.3f}), "
+        f"{learned['mean_iterations']:.1f} it")
+    ctx = new_context(s, t, "mixed", a.pair_store)
+    mixed = run_steps(ctx, t, eval_frames, a.steps, a.warmup, a.tol, guess="zero", stage_pass=True)
+    ctx.close()
+    log(f"{s.name}: mixed {mixed['step_ms']:.3f} ms/step, {mixed['mean_iterations']:.1f} it")
+    ctx = new_context(s, t, "fp64", a.pair_store)
+    fp64 = run_steps(ctx, t, eval_frames, a.steps, a.warmup, a.tol, guess="zero")
+    ctx.close()
+    log(f"{s.name}: fp64 {fp64['step_ms']:.3f} ms/step, {fp64['mean_iterations']:.1f} it")
+    acc = {}
+    for name, r in (("mixed_learned", learned), ("mixed", mixed)):
+        acc[name] = mu_errors(r["mu"], fp64["mu"])
+        acc[name]["e_pol_abs_kcal"] = abs(r["e_pol_kcal"] - fp64["e_pol_kcal"])
+        acc[name]["e_pol_rel"] = acc[name]["e_pol_abs_kcal"] / abs(fp64["e_pol_kcal"])
+    return learned, mixed, fp64, acc, tr, model
+
+
+def subcell_accuracy(parent, model, tol):
+    """Every variant against the FP64 oracle's exact solution on the periodic subcell of the
+    headline box (full oracle solve: smooth PME on the same grid spacing, PCG to 1e-9 D)."""
+    import oracle as O
+    from paper_2011_01207_amd import synth
+    s = synth.subcell(parent)
+    e_ref = O.perm_field(s, "spme")
+    mu_ref, _, _ = O.pcg(s, e_ref, "spme", tol_debye=1e-9)
+    ep_ref = O.e_pol(mu_ref, e_ref)
+    t = tensors(s)
+    out = {"workload": f"{s.name}: periodic {s.box[0]:.2f} A cube of the headline box, PME {s.grid[0]}^3",
+           "n_atoms": s.n, "e_pol_oracle_kcal": ep_ref}
+    for name, prec, guess in (("fp64", "fp64", "zero"), ("mixed", "mixed", "zero"),
+                              ("mixed_learned", "mixed", "learned")):
+        ctx = new_context(s, t, prec)
+        if guess == "learned":
+            ctx.guess_set_model(model)
+        ctx.build_blocklist(t["pos"])
+        e = ctx.perm_field(t["pos"], t["q"], t["dip"], t["quad"])
+        mu, ep, it, st = ctx.polarize(t["pos"], e, guess_mode=guess, tol_debye=tol, max_iter=1000)
+        ctx.close()
+        r = mu_errors(mu, mu_ref)
+        r.update({"iterations": it, "e_pol_kcal": ep, "e_pol_abs_kcal": abs(ep - ep_ref),
+                  "e_pol_rel": abs(ep - ep_ref) / abs(ep_ref)})
+        out[name] = r
     return out
 
 
-def roofline(s, res, K):
-    """Per-stage achieved rates over the timed region; the dominant stage is reported."""
+def secondary(a):
+    """FP64 and mixed zero-guess steps of the smaller workloads, with the oracle's exact solution
+    where it is cheap (648 and 23,558 atoms)."""
+    import oracle as O
+    from paper_2011_01207_amd import synth
+    out = {}
+    for s in (synth.water648(), synth.solvated_chain(), synth.water96k()):
+        t = tensors(s)
+        res = {}
+        for prec in ("fp64", "mixed"):
+            ctx = new_context(s, t, prec, a.pair_store)
+            res[prec] = run_steps(ctx, t, [t["pos"]], a.steps, a.warmup, a.tol)
+            ctx.close()
+        entry = {p: strip(r) for p, r in res.items()}
+        entry["speedup_mixed_vs_fp64"] = res["fp64"]["step_ms"] / res["mixed"]["step_ms"]
+        if s.n <= 30000:
+            e_ref = O.perm_field(s, "spme")
+            mu_ref, _, _ = O.pcg(s, e_ref, "spme", tol_debye=1e-9)
+            ep_ref = O.e_pol(mu_ref, e_ref)
+            for p, r in res.items():
+                entry[p]["vs_oracle"] = {**mu_errors(r["mu"], mu_ref),
+                                         "e_pol_rel": abs(r["e_pol_kcal"] - ep_ref) / abs(ep_ref)}
+        else:
+            entry["mixed"]["vs_fp64_gpu"] = mu_errors(res["mixed"]["mu"], res["fp64"]["mu"])
+        out[s.name] = entry
+        log(f"{s.name}: fp64 {res['fp64']['step_ms']:.3f} ms, mixed {res['mixed']['step_ms']:.3f} ms")
+        del t
+    return out
+
+
+def trajectory_leg(a, n_train=150, n_eval=50):
+    """288,000 atoms, 201 configurations of cumulative 0.02 A steps: train on frames 1..150, then
+    solve frames 151..200 once each from the zero, previous-step, learned and judged starts."""
+    import torch
+    from paper_2011_01207_amd import synth
+    s = synth.water288k()
+    t = tensors(s)
+    frames = [torch.tensor(p, device="cuda:0") for p in synth.trajectory(s, n_train + n_eval + 1, 0.02, seed=304)]
+    ctx = new_context(s, t, "mixed", a.pair_store)
+    t0 = time.perf_counter()
+    data = reference_data(ctx, t, frames[1:n_train + 1])
+    t_ref = time.perf_counter() - t0
+    tr = train(ctx, data, train_steps=2000, batch=65536)
+    tr["reference_solves_s"] = t_ref
+    del data
+    ev = frames[n_train + 1:]
+    refs = reference_data(ctx, t, frames[n_train:])   # converged dipoles of frames 150..200
+    prevs = [d["mu"] for d in refs[:-1]]
+    tr["guess_rms_err_debye"] = statistics.fmean(
+        mu_errors(ctx.guess_forward(d["feat"], d["basis"]).double(), d["mu"])["mu_rms_debye"] for d in refs[1:])
+    tr["prev_rms_err_debye"] = statistics.fmean(
+        mu_errors(prevs[k], refs[k + 1]["mu"])["mu_rms_debye"] for k in range(n_eval))
+    del refs
+    modes = {}
+    for mode in ("zero", "given", "learned", "best"):
+        r = run_steps(ctx, t, ev, n_eval, 2, a.tol, guess=mode, prev=prevs, stage_pass=True)
+        modes[{"given": "previous_step"}.get(mode, mode)] = strip(r)
+        log(f"288k trajectory {mode}: {r['step_ms']:.3f} ms, {r['mean_iterations']:.2f} it")
+    ctx.close()
+    return {"workload": "water_288000: 96,000 waters, 142.3 A box, PME 144^3; 201 configurations of cumulative "
+                        "0.02 A per-atom steps; train on 1-150, evaluate 151-200 once per start",
+            **tr, "modes": modes}
+
+
+def roofline(s, res):
+    """Per-stage achieved rates of a leg's stage pass; the dominant stage is reported, with the
+    real-space tiles timed live in the timed region when they dominate."""
     tim = res["timing"]
     n = s.n
-    k3 = K[0] * K[1] * K[2]
+    K = s.grid
     mv = tim["matvecs"]
     stages = {}
-    # real-space dipole tiles: FP32 VALU bound
+    # real-space dipole tiles: FP32 VALU bound; the productive launches are the PCG products and
+    # the learned guess's basis products (launches queued after convergence return at entry)
+    extra = res.get("extra_real_products", 0)
+    n_real = mv + extra
     ms = tim["ms"]["real"]
-    flops = FLOPS_PER_PAIR * res["n_pairs"] * mv
+    flops = FLOPS_PER_PAIR * res["n_pairs"] * n_real
     mi = "true" if res.get("pair_min_image") else "false"
-    # coefficient mode of the timed products: 0 evaluates every pair, 2 replays stored
-    # coefficients (the one recording launch per configuration is timed with them)
     cm = 2 if res.get("pair_store") else 0
     stages["real"] = {"bound": "alu", "achieved": flops / (ms * 1e-3) / 1e12, "peak": PEAK_FP32_VALU,
                       "unit": "TFLOP/s", "ms_total": ms, "launches": tim["launches"]["real"],
+                      "productive_launches": n_real,
                       "kernel": f"k_block_tiles<float, true, DipoleKind<float>, {mi}, {cm}>",
                       "algorithmic_per_launch": FLOPS_PER_PAIR * res["n_pairs"],
                       "peak_nonpacked": PEAK_FP32_NONPACKED,
                       "frac_nonpacked": flops / (ms * 1e-3) / 1e12 / PEAK_FP32_NONPACKED}
     kh = K[2] // 2 + 1
     nc = K[0] * K[1] * kh
-    if res.get("pme_planes"):
-        # plane path.  spread stage = k_pme_spread_z: per atom its binned record (16 B), spline
-        # arguments (16 B) and FP32 dipole (16 B) read once, the z half spectra (8 B per point)
-        # written once
-        b_spread = n * 48 + nc * 8
-        k_spread = "k_pme_spread_z<float, true, false>"
-        # fft stage = forward y-lines, x-lines with the influence function, inverse y-lines: the
-        # half grid read and written by each pass, the influence function read once
-        b_fft = 3 * nc * (8 + 8) + nc * 4
-        k_fft = "k_pme_ylines<float, -1> + k_pme_xconv<float> + k_pme_ylines<float, 1>"
-        # gather stage = k_pme_z_gather + k_plane_combine: half grid read once, atom records read,
-        # five field shares written and read (16 B each); combine: i-field 24 B, direction 24 B,
-        # 1/alpha 8 B read and A p 24 B written per atom, every tile j-field slot (16 B) read
-        b_gather = nc * 8 + n * (32 + 2 * 80 + 24 + 24 + 8 + 24) + res["n_tiles"] * 64 * 16
-        k_gather = "k_pme_z_gather<float> + k_plane_combine<float, 1>"
-    else:
-        # PME spread: position (12 B) + dipole (12 B) per atom read, FP32 grid written once
-        b_spread = n * 24 + k3 * 4
-        k_spread = "k_spread_dip<float, true>"
-        # FFT pair + influence product: each 3-D FFT reads and writes the grid once (real K^3 x
-        # 4 B, half-complex K^3 x 4 B); the product reads/writes the half grid and reads theta
-        b_fft = 2 * (k3 * 4 + k3 * 4) + (k3 * 4 * 2 + k3 * 2)
-        k_fft = "rocFFT r2c + k_convolve + rocFFT c2r"
-        # gather + operator assembly: grid read once; per atom position 12, real-space field 24,
-        # direction 24, 1/alpha 8 read and A p 24 written (FP64 vectors)
-        b_gather = k3 * 4 + n * (12 + 24 + 24 + 8 + 24)
-        k_gather = "k_gather_brick<float, 1>"
-    ms = tim["ms"]["spread"]
-    stages["spread"] = {"bound": "hbm", "achieved": b_spread * mv / (ms * 1e-3) / 1e9, "peak": PEAK_HBM,
-                        "unit": "GB/s", "ms_total": ms, "launches": tim["launches"]["spread"],
-                        "kernel": k_spread, "algorithmic_per_launch": b_spread}
-    ms = tim["ms"]["gather"]
-    stages["gather"] = {"bound": "hbm", "achieved": b_gather * mv / (ms * 1e-3) / 1e9, "peak": PEAK_HBM,
-                        "unit": "GB/s", "ms_total": ms, "launches": tim["launches"]["gather"],
-                        "kernel": k_gather, "algorithmic_per_launch": b_gather}
-    ms = tim["ms"]["fft"]
-    stages["fft"] = {"bound": "hbm", "achieved": b_fft * mv / (ms * 1e-3) / 1e9, "peak": PEAK_HBM,
-                     "unit": "GB/s", "ms_total": ms, "launches": tim["launches"]["fft"],
-                     "kernel": k_fft, "algorithmic_per_launch": b_fft}
+    # plane path.  spread stage = k_pme_spread_z: per atom its binned record (16 B), spline
+    # arguments (16 B) and FP32 dipole (16 B) read once, the z half spectra (8 B per point) written
+    b_spread = n * 48 + nc * 8
+    # fft stage = forward y-lines, x-lines with the influence function, inverse y-lines: the half
+    # grid read and written by each pass, the influence function read once
+    b_fft = 3 * nc * (8 + 8) + nc * 4
+    # gather stage = k_pme_z_gather + k_plane_combine: half grid read once, atom records read,
+    # five field shares written and read (16 B each); combine: i-field 24 B, direction 24 B,
+    # 1/alpha 8 B read and A p 24 B written per atom, every tile j-field slot (16 B) read
+    b_gather = nc * 8 + n * (32 + 2 * 80 + 24 + 24 + 8 + 24) + res["n_tiles"] * 64 * 16
+    for name, b, kern in (("spread", b_spread, "k_pme_spread_z<float, true, false>"),
+                          ("fft", b_fft, "k_pme_ylines<float, -1> + k_pme_xconv<float> + k_pme_ylines<float, 1>"),
+                          ("gather", b_gather, "k_pme_z_gather<float> + k_plane_combine<float, 1>")):
+        ms = tim["ms"][name]
+        stages[name] = {"bound": "hbm", "achieved": b * mv / (ms * 1e-3) / 1e9, "peak": PEAK_HBM, "unit": "GB/s",
+                        "ms_total": ms, "launches": tim["launches"][name], "kernel": kern,
+                        "algorithmic_per_launch": b}
     for v in stages.values():
         v["frac"] = v["achieved"] / v["peak"]
     dom = max(["real", "spread", "gather", "fft"], key=lambda k: stages[k]["ms_total"])
     d = stages[dom]
-    # HBM bytes per launch of the dominant kernel from the committed FETCH_SIZE / WRITE_SIZE
-    # summary (copy-calibrated), or None once the kernel's sources changed since it was taken
     from paper_2011_01207_amd import profiling
-    traffic = profiling.traffic_lookup(os.path.join(ROOT, "profiles", "hbm_traffic_water_96000_mixed.md"),
-                                       d["kernel"])
+    traffic = profiling.traffic_lookup(os.path.join(ROOT, "profiles", f"hbm_traffic_{s.name}_mixed.md"), d["kernel"])
     avg_us = 1e3 * d["ms_total"] / max(1, d["launches"])
     top = {"bound": d["bound"], "achieved": d["achieved"], "peak": d["peak"], "unit": d["unit"],
            "frac": d["frac"], "traffic": traffic, "kernel": d["kernel"], "stage": dom,
-           "avg_launch_us": avg_us, "productive_launches": mv, "launches": d["launches"],
+           "avg_launch_us": avg_us, "launches": d["launches"], "productive_launches": d.get("productive_launches", mv),
            "timed_in": "stage pass (each stage alone on one stream)"}
     live = res.get("timing_live")
     if dom == "real" and live and live["launches"]["real"]:
         # the tiles as they run in the timed region: on the second stream beside the reciprocal
         # passes (HIP events on that stream); the stage-pass figures are kept beside them
-        ms_l, n_l, mv_l = live["ms"]["real"], live["launches"]["real"], live["matvecs"]
-        ach = d["algorithmic_per_launch"] * mv_l / (ms_l * 1e-3) / 1e12
+        ms_l, n_l = live["ms"]["real"], live["launches"]["real"]
+        prod_l = live["matvecs"] + extra
+        ach = d["algorithmic_per_launch"] * prod_l / (ms_l * 1e-3) / 1e12
         top.update({"achieved_alone": top["achieved"], "frac_alone": top["frac"], "avg_launch_us_alone": avg_us,
-                    "achieved": ach, "frac": ach / d["peak"], "avg_launch_us": 1e3 * ms_l / n_l,
-                    "productive_launches": mv_l, "launches": n_l,
+                    "achieved": ach, "frac": ach / d["peak"], "avg_launch_us": 1e3 * ms_l / n_l, "launches": n_l,
+                    "productive_launches": prod_l,
                     "timed_in": "timed region (second stream, beside the reciprocal passes)"})
         avg_us = top["avg_launch_us"]
-        if "peak_nonpacked" in d:
-            d = dict(d, frac_nonpacked=ach / d["peak_nonpacked"])
+        d = dict(d, frac_nonpacked=ach / d["peak_nonpacked"])
     if traffic is not None:
         top["traffic_unit"] = "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)"
         top["traffic_rate_gbs"] = traffic / (avg_us * 1e-6) / 1e9
     for k in ("peak_nonpacked", "frac_nonpacked"):
         if k in d:
             top[k] = d[k]
+    top["algorithmic_unit"] = (f"{FLOPS_PER_PAIR} FLOP per in-cutoff pair x {res['n_pairs']} pairs per launch"
+                               if dom == "real" else "bytes per launch")
     return top, stages
 
 
-def cpu_baseline(s, iters, target_s=12.0):
-    """FP64 oracle on this host: one matrix-vector product = O(N^2) real space (timed on a
-    sample of output atoms and scaled to all N) + full smooth-PME reciprocal field; the
-    permanent field likewise; a solve = iterations x matvec + permanent field."""
+def cpu_baseline(s, iters):
+    """FP64 oracle on this host: one full matrix-vector product (real space over the cell grid +
+    smooth-PME reciprocal field + self) and one permanent field of the headline box; a solve =
+    iterations x matvec + permanent field."""
     import numpy as np
     import oracle as O
     rng = np.random.default_rng(0)
     mu = rng.standard_normal((s.n, 3)) * 0.05
     n_thr = O.num_threads()
-    # calibrate the sample so the real-space part takes a few seconds
-    probe = np.sort(rng.choice(s.n, 200, replace=False))
     t0 = time.perf_counter()
-    O.real_mutual(s, mu, idx=probe)
-    per_atom = (time.perf_counter() - t0) / 200
-    n_samp = int(min(s.n, max(500, 0.35 * target_s / per_atom)))
-    idx = np.sort(rng.choice(s.n, n_samp, replace=False))
+    O.matvec(s, mu, "spme")
+    t_mv = time.perf_counter() - t0
     t0 = time.perf_counter()
-    O.real_mutual(s, mu, idx=idx)
-    t_real = (time.perf_counter() - t0) * s.n / n_samp
-    t0 = time.perf_counter()
-    O.spme_field(s, dip=mu)
-    t_rec = time.perf_counter() - t0
-    idxp = idx[: max(100, n_samp // 2)]
-    t0 = time.perf_counter()
-    O.real_perm(s, idx=idxp)
-    t_preal = (time.perf_counter() - t0) * s.n / len(idxp)
-    t0 = time.perf_counter()
-    O.spme_field(s, s.q, s.dip, s.quad)
-    t_prec = time.perf_counter() - t0
-    t_step = iters * (t_real + t_rec) + t_preal + t_prec
+    O.perm_field(s, "spme")
+    t_perm = time.perf_counter() - t0
+    t_step = iters * t_mv + t_perm
     return {"value": 1.0 / t_step, "unit": "solves/s", "cores": n_thr, "kind": "oracle",
-            "sample": (f"water_96000: oracle real-space dipole field at {n_samp} of {s.n} atoms "
-                       f"(O(N^2) minimum image) scaled x{s.n / n_samp:.1f} + full smooth-PME field per "
-                       f"matvec ({t_real + t_rec:.2f} s), permanent field likewise "
-                       f"({t_preal + t_prec:.2f} s); solve = {iters} PCG iterations x matvec + E_perm"),
+            "sample": (f"{s.name}: one full oracle matrix-vector product ({t_mv:.2f} s: real space over a cell "
+                       f"grid, smooth-PME field, self) and one permanent field ({t_perm:.2f} s), timed; solve = "
+                       f"{iters} PCG iterations x matvec + E_perm"),
             "seconds_per_solve": t_step}
 
 
@@ -359,7 +462,6 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 (multi-GPU sharding is "
                                    "a design note, not implemented)"}))
         sys.exit(2)
-    import numpy as np
     import torch
     from paper_2011_01207_amd import synth
 
@@ -367,83 +469,58 @@ def main():
         print(json.dumps({"error": "no GPU available"}))
         sys.exit(1)
     torch.cuda.set_device(0)
-    s = synth.water96k()
+    s = synth.water864k() if a.workload == "water_864000" else synth.water96k()
     log(f"workload {s.name}: N={s.n} box={s.box[0]} grid={s.grid} rc={s.cutoff}+{s.buffer}")
-    dev = "cuda:0"
-    t = {k: torch.tensor(getattr(s, k), device=dev) for k in ("pos", "q", "dip", "quad", "alpha", "thole", "sc_s")}
-    t["sc_ptr"] = torch.tensor(s.sc_ptr, dtype=torch.int32, device=dev)
-    t["sc_j"] = torch.tensor(s.sc_j, dtype=torch.int32, device=dev)
-
-    log("mixed precision leg")
-    mixed = run_variant(s, t, "mixed", a.steps, a.warmup, a.tol, pair_store=a.pair_store)
-    log(f"mixed: {mixed['step_ms']:.3f} ms/step, solve {mixed['solve_only_ms']:.3f} ms, {mixed['iterations']} it")
-    fp64 = None
-    if not a.no_fp64:
-        log("fp64 leg")
-        fp64 = run_variant(s, t, "fp64", a.steps, a.warmup, a.tol, timing=False, pair_store=a.pair_store)
-        log(f"fp64: {fp64['step_ms']:.3f} ms/step, solve {fp64['solve_only_ms']:.3f} ms, {fp64['iterations']} it")
-
-    top, stages = roofline(s, mixed, s.grid)
+    t = tensors(s)
+    learned, mixed, fp64, acc, tr, model = headline(s, t, a)
+    top, stages = roofline(s, learned)
     res = {
         "metric": METRIC,
-        "value": 1e3 / mixed["step_ms"],
+        "value": learned["solves_per_s"],
         "unit": "solves/s",
         "n_gpus": 1,
         "steps": a.steps,
         "warmup": a.warmup,
-        "ms_per_step": mixed["step_ms"],
+        "ms_per_step": learned["step_ms"],
+        "median_ms": learned["median_ms"], "p10_ms": learned["p10_ms"], "p90_ms": learned["p90_ms"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 pair/PME math + i64 fixed-point fields + f64 PCG",
+        "dtype": DTYPE,
         "data": "synthetic",
-        "config": {"workload": "water_96000: 32,000 rigid waters (96,000 atoms), 98.65 A cubic box, rc 7 A "
-                               "+ 2 A list buffer, beta 0.545/A, PME 108^3 order 5; one step = block list + "
-                               "E_perm + PCG from zero guess to 1e-5 D rms",
-                   "precision": "mixed", "tol_debye": a.tol},
+        "config": {"workload": (f"{s.name}: {s.n // 3:,} rigid waters ({s.n:,} atoms), {s.box[0]:.2f} A cubic box, "
+                                f"rc 7 A + 2 A list buffer, beta 0.545/A, PME {s.grid[0]}^3 order 5; one step = "
+                                "block list + E_perm + learned initial guess + mixed-precision PCG to the tolerance, "
+                                "on held-out frames of a 0.02 A-step trajectory"),
+                   "precision": "mixed", "guess": "learned", "tol_debye": a.tol},
         "roofline": top,
         "roofline_stages": stages,
-        "mixed": {k: v for k, v in mixed.items() if k not in ("mu", "e_perm")},
+        "mixed_learned": strip(learned),
+        "mixed": strip(mixed),
+        "fp64": strip(fp64),
+        "speedup_vs_fp64": {"mixed_learned": fp64["step_ms"] / learned["step_ms"],
+                            "mixed": fp64["step_ms"] / mixed["step_ms"]},
+        "accuracy_vs_fp64_gpu": acc,
+        "learned_guess_training": tr,
     }
-    if fp64 is not None:
-        res["fp64"] = {k: v for k, v in fp64.items() if k not in ("mu", "e_perm", "timing")}
-        res["speedup_mixed_vs_fp64"] = {"step": fp64["step_ms"] / mixed["step_ms"],
-                                        "solve_only": fp64["solve_only_ms"] / mixed["solve_only_ms"]}
-        dmu = (mixed["mu"] - fp64["mu"]).cpu().numpy()
-        res["accuracy_mixed_vs_fp64_gpu"] = {
-            "mu_rms_debye": float(4.80320 * np.sqrt(np.sum(dmu ** 2) / s.n)),
-            "mu_max_debye": float(4.80320 * np.max(np.linalg.norm(dmu, axis=1))),
-            "e_pol_abs_kcal": abs(mixed["e_pol_kcal"] - fp64["e_pol_kcal"]),
-            "e_pol_rel": abs(mixed["e_pol_kcal"] - fp64["e_pol_kcal"]) / abs(fp64["e_pol_kcal"]),
-        }
-    if not a.no_learned:
-        log("learned-guess leg (trajectory, training on the GPU)")
-        lg = learned_leg(s, t, a.steps, a.tol)
-        if fp64 is not None:
-            for v in lg["modes"].values():
-                v["speedup_vs_fp64_zero_guess"] = fp64["step_ms"] / v["step_ms"]
-        res["learned_guess"] = lg
-        log("learned: " + ", ".join(f"{k} {v['step_ms']:.3f} ms {v['mean_iterations']:.1f} it"
-                                    for k, v in lg["modes"].items()))
-    if a.trajectory_288k:
+    if not a.no_subcell:
+        log("subcell accuracy against the oracle")
+        res["accuracy_vs_oracle_subcell"] = subcell_accuracy(s, model, a.tol)
+    fp64_iters = fp64["iterations"]
+    del t, learned, mixed, fp64
+    torch.cuda.empty_cache()
+    if not a.no_secondary:
+        log("secondary workloads")
+        res["secondary"] = secondary(a)
+    if not a.no_trajectory:
         log("288,000-atom trajectory leg")
-        s4 = synth.water288k()
-        t4 = {k: torch.tensor(getattr(s4, k), device=dev) for k in ("pos", "q", "dip", "quad", "alpha", "thole",
-                                                                    "sc_s")}
-        t4["sc_ptr"] = torch.tensor(s4.sc_ptr, dtype=torch.int32, device=dev)
-        t4["sc_j"] = torch.tensor(s4.sc_j, dtype=torch.int32, device=dev)
-        lg4 = learned_leg(s4, t4, 50, a.tol, n_train=150, n_eval=50, train_steps=2000, batch=65536, seed=304)
-        lg4["workload"] = ("water_288000: 96,000 waters, 142.3 A box, PME 144^3; 200 configurations of "
-                           "cumulative 0.02 A per-atom steps; train on 1-150, evaluate 151-200 once per start")
-        res["trajectory_288000"] = lg4
-        log("288k: " + ", ".join(f"{k} {v['step_ms']:.3f} ms {v['mean_iterations']:.1f} it"
-                                 for k, v in lg4["modes"].items()))
-        del t4
+        res["trajectory_288000"] = trajectory_leg(a)
+        torch.cuda.empty_cache()
     if not a.no_cpu_baseline:
         log("cpu baseline (oracle)")
-        res["cpu_baseline"] = cpu_baseline(s, fp64["iterations"] if fp64 else mixed["iterations"])
+        res["cpu_baseline"] = cpu_baseline(s, fp64_iters)
     if a.copy_calibration:
-        src = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device=dev)
+        src = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device="cuda:0")
         dst = torch.empty_like(src)
         for _ in range(3):
             dst.copy_(src)

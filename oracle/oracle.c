@@ -345,7 +345,9 @@ double orc_bspline(int n, double x, int deriv)
         return bspline(n, x);
     if (deriv == 1)
         return bspline(n - 1, x) - bspline(n - 1, x - 1.0);
-    return bspline(n - 2, x) - 2.0 * bspline(n - 2, x - 1.0) + bspline(n - 2, x - 2.0);
+    if (deriv == 2)
+        return bspline(n - 2, x) - 2.0 * bspline(n - 2, x - 1.0) + bspline(n - 2, x - 2.0);
+    return bspline(n - 3, x) - 3.0 * bspline(n - 3, x - 1.0) + 3.0 * bspline(n - 3, x - 2.0) - bspline(n - 3, x - 3.0);
 }
 
 /* For one coordinate: scaled fractional u = K x / L wrapped into [0, K); the n grid lines that
@@ -471,6 +473,257 @@ int64_t orc_count_pairs(int n, const double *pos, const double *box, double rc,
     free(cand);
     }
     return cnt;
+}
+
+/* ------------------------------------------------------------------------------------------
+ * Gradient of the polarization energy with respect to the atom positions.
+ *
+ * At the converged dipoles mu = A^-1 E_perm the energy E_pol = -1/2 C mu.E_perm is stationary in
+ * mu, so (with A = alpha^-1 - T)
+ *     dE_pol/dr_k = C [ -1/2 mu . (dT/dr_k) mu  -  mu . dE_perm/dr_k ].
+ * Real space, per pair (r = r_i - r_j): the mutual term u = mu_i . T_ij mu_j
+ * (T_ij = -B1' I + B2' r r^T, unscaled), and the two permanent terms w_ij(r) = mu_i . E_{j->i}(r)
+ * and w_ji(-r) = mu_j . E_{i->j}(-r) with the pair's p-scale.  Every radial function obeys
+ * dB_n'/dr = -r B_{n+1}' (the Ewald B_n by construction, the Thole-damped parts because the
+ * lambdas come from one smeared charge, lambda9 included), so grad_r B_n' = -B_{n+1}' r.  Then
+ *     dE_pol/dr_i = -C sum_j G_ij,   G = grad u(r) + grad w_ij(r) - (grad w_ji)(-r),
+ * and dE_pol/dr_j = +C G_ij.
+ * ------------------------------------------------------------------------------------------ */
+
+/* 1 - lambda_k for k = 3, 5, 7, 9 (Thole damping of the 1/r^3 .. 105/r^9 tensors). */
+static void thole_oml4(double r, double alpha_i, double alpha_j, double a_i, double a_j, double oml[4])
+{
+    double damp = pow(alpha_i * alpha_j, 1.0 / 6.0);
+    if (damp == 0.0) {
+        oml[0] = oml[1] = oml[2] = oml[3] = 0.0;
+        return;
+    }
+    double a = a_i < a_j ? a_i : a_j;
+    double u = r / damp;
+    double eps = a * u * u * u;
+    double e = exp(-eps);
+    oml[0] = e;
+    oml[1] = (1.0 + eps) * e;
+    oml[2] = (1.0 + eps + 0.6 * eps * eps) * e;
+    oml[3] = (1.0 + eps + (18.0 / 35.0) * eps * eps + (9.0 / 35.0) * eps * eps * eps) * e;
+}
+
+/* B1'..B4' of a pair (b[1..4]): Ewald B_n when in_cut, minus c_n (1 - s lambda) / r^(2n+1). */
+static void damped_b(double r, double beta, int in_cut, double s, const double oml[4], double b[5])
+{
+    double eb[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    if (in_cut) {
+        double r2 = r * r;
+        double g = beta > 0.0 ? 2.0 * beta / sqrt(ORC_PI) * exp(-beta * beta * r2) : 0.0;
+        double t = 2.0 * beta * beta;
+        eb[0] = erfc(beta * r) / r;
+        eb[1] = (eb[0] + g) / r2;
+        eb[2] = (3.0 * eb[1] + t * g) / r2;
+        eb[3] = (5.0 * eb[2] + t * t * g) / r2;
+        eb[4] = (7.0 * eb[3] + t * t * t * g) / r2;
+    }
+    const double c[5] = {0.0, 1.0, 3.0, 15.0, 105.0};
+    double rp = r * r * r;   /* r^(2n+1) */
+    b[0] = 0.0;
+    for (int k = 1; k <= 4; ++k) {
+        double lam = 1.0 - oml[k - 1];
+        b[k] = eb[k] - c[k] * (1.0 - s * lam) / rp;
+        rp *= r * r;
+    }
+}
+
+static double dot3(const double *a, const double *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+
+/* grad_r of w = mu . E_mp(r), E_mp(r) the field at displacement r from a multipole (q, d, Theta):
+ *   E_mp = q B1' r - B1' d + B2' (d.r) r + 1/3 B3' (Theta:rr) r - 2/3 B2' Theta r. */
+static void grad_w(const double mu[3], double q, const double d[3], const double th[3][3], const double r[3],
+                   const double b[5], double g[3])
+{
+    double mr = dot3(mu, r), dr = dot3(d, r), md = dot3(mu, d);
+    double thr[3], thmu[3];
+    for (int a = 0; a < 3; ++a) {
+        thr[a] = th[a][0] * r[0] + th[a][1] * r[1] + th[a][2] * r[2];
+        thmu[a] = th[a][0] * mu[0] + th[a][1] * mu[1] + th[a][2] * mu[2];
+    }
+    double thrr = dot3(thr, r), mthr = dot3(mu, thr);
+    for (int a = 0; a < 3; ++a)
+        g[a] = q * (b[1] * mu[a] - b[2] * mr * r[a])
+               + b[2] * md * r[a]
+               + b[2] * (d[a] * mr + mu[a] * dr) - b[3] * dr * mr * r[a]
+               + (b[3] * (2.0 * thr[a] * mr + thrr * mu[a]) - b[4] * thrr * mr * r[a]) / 3.0
+               - 2.0 * (b[2] * thmu[a] - b[3] * mthr * r[a]) / 3.0;
+}
+
+/* grad_r of u = mu_i . T(r) mu_j = -B1' mu_i.mu_j + B2' (mu_i.r)(mu_j.r). */
+static void grad_u(const double mi[3], const double mj[3], const double r[3], const double b[5], double g[3])
+{
+    double mm = dot3(mi, mj), mir = dot3(mi, r), mjr = dot3(mj, r);
+    for (int a = 0; a < 3; ++a)
+        g[a] = b[2] * mm * r[a] - b[3] * mir * mjr * r[a] + b[2] * (mi[a] * mjr + mj[a] * mir);
+}
+
+static void mpole_of(int j, const double *q, const double *dip, const double *quad, double *qj, double d[3],
+                     double th[3][3])
+{
+    *qj = q ? q[j] : 0.0;
+    for (int a = 0; a < 3; ++a)
+        d[a] = dip ? dip[3 * j + a] : 0.0;
+    for (int a = 0; a < 3; ++a)
+        for (int c = 0; c < 3; ++c)
+            th[a][c] = 0.0;
+    if (quad) {
+        const double *t = quad + 6 * j;
+        th[0][0] = t[0]; th[0][1] = th[1][0] = t[1]; th[0][2] = th[2][0] = t[2];
+        th[1][1] = t[3]; th[1][2] = th[2][1] = t[4]; th[2][2] = t[5];
+    }
+}
+
+/* G_ij of one pair (see above); mutual = 0 leaves out u (listed pairs beyond rc). */
+static void pair_grad(int i, int j, const double r[3], double rn, int in_cut, double s, double beta,
+                      const double *alpha, const double *thole, const double *q, const double *dip,
+                      const double *quad, const double *mu, double G[3])
+{
+    double oml[4], bp[5], bt[5], g[3], mr[3];
+    thole_oml4(rn, alpha[i], alpha[j], thole[i], thole[j], oml);
+    damped_b(rn, beta, in_cut, s, oml, bp);
+    double qi, qj, di[3], dj[3], thi[3][3], thj[3][3];
+    mpole_of(i, q, dip, quad, &qi, di, thi);
+    mpole_of(j, q, dip, quad, &qj, dj, thj);
+    G[0] = G[1] = G[2] = 0.0;
+    if (in_cut) {
+        damped_b(rn, beta, 1, 1.0, oml, bt);
+        grad_u(mu + 3 * i, mu + 3 * j, r, bt, g);
+        for (int a = 0; a < 3; ++a)
+            G[a] += g[a];
+    }
+    grad_w(mu + 3 * i, qj, dj, thj, r, bp, g);
+    for (int a = 0; a < 3; ++a)
+        G[a] += g[a];
+    for (int a = 0; a < 3; ++a)
+        mr[a] = -r[a];
+    grad_w(mu + 3 * j, qi, di, thi, mr, bp, g);
+    for (int a = 0; a < 3; ++a)
+        G[a] -= g[a];
+}
+
+/* out[o] = sum_j G_ij for the requested atoms (so that dE_pol,real/dr_i = -C out_i): the pairs
+ * within rc from the partner search, the listed pairs at or beyond rc from the CSR (permanent
+ * terms only, bare tensors with the pair's scale). */
+void orc_polar_grad_real(int n, const double *pos, const double *box, double beta, double rc,
+                         const double *alpha, const double *thole, const double *q, const double *dip,
+                         const double *quad, const double *mu, const int32_t *sc_ptr, const int32_t *sc_j,
+                         const double *sc_s, int n_out, const int32_t *out_idx, double *out,
+                         const int32_t *nc, const int32_t *cell_of, const int32_t *cell_start,
+                         const int32_t *cell_atoms)
+{
+#pragma omp parallel
+    {
+    int32_t *cand = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 1 ? n : 1));
+#pragma omp for schedule(dynamic, 8)
+    for (int o = 0; o < n_out; ++o) {
+        int i = out_idx ? out_idx[o] : o;
+        double acc[3] = {0.0, 0.0, 0.0}, G[3];
+        int m = partners(i, n, nc, cell_of, cell_start, cell_atoms, cand);
+        for (int c = 0; c < m; ++c) {
+            int j = cand[c];
+            double d[3] = {pos[3 * i] - pos[3 * j], pos[3 * i + 1] - pos[3 * j + 1],
+                           pos[3 * i + 2] - pos[3 * j + 2]};
+            min_image(d, box);
+            double r = sqrt(dot3(d, d));
+            if (!(r < rc))
+                continue;
+            pair_grad(i, j, d, r, 1, pair_scale(i, j, sc_ptr, sc_j, sc_s), beta, alpha, thole, q, dip, quad, mu, G);
+            for (int a = 0; a < 3; ++a)
+                acc[a] += G[a];
+        }
+        if (sc_ptr)
+            for (int k = sc_ptr[i]; k < sc_ptr[i + 1]; ++k) {
+                int j = sc_j[k];
+                double d[3] = {pos[3 * i] - pos[3 * j], pos[3 * i + 1] - pos[3 * j + 1],
+                               pos[3 * i + 2] - pos[3 * j + 2]};
+                min_image(d, box);
+                double r = sqrt(dot3(d, d));
+                if (r < rc || sc_s[k] == 1.0)
+                    continue;
+                pair_grad(i, j, d, r, 0, sc_s[k], beta, alpha, thole, q, dip, quad, mu, G);
+                for (int a = 0; a < 3; ++a)
+                    acc[a] += G[a];
+            }
+        for (int a = 0; a < 3; ++a)
+            out[3 * o + a] = acc[a];
+    }
+    free(cand);
+    }
+}
+
+/*
+ * Smooth-PME part of the gradient.  With Q_mu the spread of the dipoles (Q_mu(k) = sum_i
+ * mu_i . grad_i W(k; r_i)), Q_p that of the permanent multipoles, and psi_x = theta * Q_x the grid
+ * potentials (theta symmetric), the reciprocal energy terms are mu.T_rec mu = -sum_k Q_mu psi_mu
+ * and mu.E_perm,rec = -sum_k Q_mu psi_p = -sum_k Q_p psi_mu, so
+ *     dE_pol,rec/dr_m = C sum_k [ dQ_mu(k)/dr_m (psi_mu + psi_p)(k) + dQ_p(k)/dr_m psi_mu(k) ],
+ *     dQ_mu/dr_m,a = sum_b mu_m,b d_a d_b W,
+ *     dQ_p/dr_m,a  = q_m d_a W + sum_b d_m,b d_a d_b W + 1/3 sum_bc Theta_m,bc d_a d_b d_c W.
+ * out[o] = the bracket (psi_a = psi_mu + psi_p, psi_b = psi_mu).
+ */
+void orc_spme_grad(int n, const double *pos, const double *box, const int32_t *kdim, int order,
+                   const double *psi_a, const double *psi_b, const double *mu, const double *q,
+                   const double *dip, const double *quad, int n_out, const int32_t *out_idx, double *out)
+{
+    (void)n;
+#pragma omp parallel for schedule(static)
+    for (int o = 0; o < n_out; ++o) {
+        int i = out_idx ? out_idx[o] : o;
+        int kk[3][8];
+        double m[3][4][8];   /* axis, derivative order, support point */
+        for (int ax = 0; ax < 3; ++ax) {
+            double len = box[ax];
+            int K = kdim[ax];
+            double u = K * (pos[3 * i + ax] / len);
+            u -= K * floor(u / K);
+            double fl = floor(u), fr = u - fl;
+            for (int t = 0; t < order; ++t) {
+                int k = (int)fl - t;
+                kk[ax][t] = ((k % K) + K) % K;
+                double sc = 1.0;
+                for (int dv = 0; dv < 4; ++dv) {
+                    m[ax][dv][t] = orc_bspline(order, fr + t, dv) * sc;
+                    sc *= K / len;
+                }
+            }
+        }
+        double qi, di[3], th[3][3];
+        mpole_of(i, q, dip, quad, &qi, di, th);
+        const double *mi = mu + 3 * i;
+        double acc[3] = {0.0, 0.0, 0.0};
+        for (int a = 0; a < order; ++a)
+            for (int b = 0; b < order; ++b)
+                for (int c = 0; c < order; ++c) {
+                    size_t idx = ((size_t)kk[0][a] * kdim[1] + kk[1][b]) * kdim[2] + kk[2][c];
+                    double pa = psi_a[idx], pb = psi_b[idx];
+                    int sup[3] = {a, b, c};
+                    /* derivative of W of orders (dx, dy, dz) */
+#define WD(dx, dy, dz) (m[0][dx][sup[0]] * m[1][dy][sup[1]] * m[2][dz][sup[2]])
+                    for (int x = 0; x < 3; ++x) {
+                        int e1[3] = {x == 0, x == 1, x == 2};
+                        double hmu = 0.0, hd = 0.0, t3 = 0.0;
+                        for (int y = 0; y < 3; ++y) {
+                            int e2[3] = {e1[0] + (y == 0), e1[1] + (y == 1), e1[2] + (y == 2)};
+                            double h = WD(e2[0], e2[1], e2[2]);
+                            hmu += h * mi[y];
+                            hd += h * di[y];
+                            for (int z = 0; z < 3; ++z) {
+                                int e3[3] = {e2[0] + (z == 0), e2[1] + (z == 1), e2[2] + (z == 2)};
+                                t3 += th[y][z] * WD(e3[0], e3[1], e3[2]);
+                            }
+                        }
+                        acc[x] += pa * hmu + pb * (qi * WD(e1[0], e1[1], e1[2]) + hd + t3 / 3.0);
+                    }
+#undef WD
+                }
+        for (int a = 0; a < 3; ++a)
+            out[3 * o + a] = acc[a];
+    }
 }
 
 #ifdef _OPENMP

@@ -58,6 +58,11 @@ def lib():
         L.orc_spme_spread.argtypes = [ctypes.c_int, _dp, _dp, _ip, ctypes.c_int, _dp, _dp, _dp, _dp]
         L.orc_spme_gather.argtypes = [ctypes.c_int, _dp, _dp, _ip, ctypes.c_int, _dp, ctypes.c_int, _ip, _dp]
         L.orc_count_pairs.argtypes = [ctypes.c_int, _dp, _dp, ctypes.c_double, _ip, _ip, _ip, _ip]
+        L.orc_polar_grad_real.argtypes = [ctypes.c_int, _dp, _dp, ctypes.c_double, ctypes.c_double, _dp, _dp,
+                                          _dp, _dp, _dp, _dp, _ip, _ip, _dp, ctypes.c_int, _ip, _dp,
+                                          _ip, _ip, _ip, _ip]
+        L.orc_spme_grad.argtypes = [ctypes.c_int, _dp, _dp, _ip, ctypes.c_int, _dp, _dp, _dp, _dp, _dp, _dp,
+                                    ctypes.c_int, _ip, _dp]
         L.orc_count_pairs.restype = ctypes.c_int64
         L.orc_num_threads.restype = ctypes.c_int
         _LIB = L
@@ -407,3 +412,63 @@ def count_pairs(s, rc=None, search="cells") -> int:
     rc = s.cutoff if rc is None else rc
     _cl, cl = _search_args(s, rc, search)
     return int(lib().orc_count_pairs(pos.shape[0], pp, bp, rc, *cl))
+
+
+# ----------------------------------------------------------------------------------------------
+# polarization energy gradient (forces = -gradient)
+# ----------------------------------------------------------------------------------------------
+
+def polar_gradient(s, mu, recip='spme', idx=None, search="cells"):
+    """dE_pol/dr (kcal/mol/A) at the converged dipoles mu (E_pol stationary in mu): the real-space
+    pair terms (mutual, permanent with the scaled-pair correction) and, with recip='spme', the
+    smooth-PME terms; recip=None is free space (no images, no cutoff, beta = 0).  The dipole
+    self terms do not depend on the positions."""
+    pos, pp = _d(s.pos)
+    n = pos.shape[0]
+    _, ap = _d(s.alpha)
+    _, tp = _d(s.thole)
+    _, qp = _d(s.q)
+    _, dp = _d(s.dip)
+    _, Qp = _d(s.quad)
+    mu = np.ascontiguousarray(np.asarray(mu, dtype=np.float64).reshape(-1, 3))
+    mp = mu.ctypes.data_as(_dp)
+    _, sp = _i(s.sc_ptr)
+    _, sjp = _i(s.sc_j if len(s.sc_j) else np.zeros(1, np.int32))
+    _, ssp = _d(s.sc_s if len(s.sc_s) else np.zeros(1))
+    if recip is None:
+        bp, beta, rc = None, 0.0, math.inf
+        cl = (None,) * 4
+    else:
+        _box, bp = _d(s.box)
+        beta, rc = s.ewald_alpha, s.cutoff
+        _cl, cl = _search_args(s, rc, search)
+    n_out, _keep, ip = _outsel(n, idx)
+    g = np.zeros((n_out, 3))
+    lib().orc_polar_grad_real(n, pp, bp, beta, rc, ap, tp, qp, dp, Qp, mp, sp, sjp, ssp, n_out, ip,
+                              g.ctypes.data_as(_dp), *cl)
+    out = -COULOMB * g
+    if recip == 'spme':
+        psi_mu = spme_potential(s, spme_spread(s, dip=mu))
+        psi_p = spme_potential(s, spme_spread(s, s.q, s.dip, s.quad))
+        grid = tuple(s.grid)
+        _g, gp = _i(np.asarray(grid, np.int32))
+        _box, bp = _d(s.box)
+        psa, psap = _d(psi_mu + psi_p)
+        psb, psbp = _d(psi_mu)
+        r = np.zeros((n_out, 3))
+        lib().orc_spme_grad(n, pp, bp, gp, int(s.order), psap, psbp, mp, qp, dp, Qp, n_out, ip,
+                            r.ctypes.data_as(_dp))
+        out += COULOMB * r
+    elif recip is not None:
+        raise ValueError(recip)
+    return out
+
+
+def polar_energy(s, recip='spme', tol_debye=1e-12, dense=False):
+    """E_pol (kcal/mol) at the exact dipoles of configuration s, and those dipoles."""
+    e = perm_field(s, recip)
+    if dense:
+        mu = np.linalg.solve(dense_operator(s, recip), e.ravel()).reshape(-1, 3)
+    else:
+        mu, _, _ = pcg(s, e, recip, tol_debye=tol_debye, max_iter=5000)
+    return e_pol(mu, e), mu

@@ -85,19 +85,32 @@ def test_roofline_uses_the_live_tile_time():
 
     class S:
         n = 1000
+        grid = (8, 8, 8)
+        name = "test_box"
 
-    res = {"timing": timing(10.0, 110, 100), "timing_live": timing(12.5, 110, 100, other_ms=0.0),
-           "n_pairs": 1_000_000, "n_tiles": 100, "pme_planes": 1, "pair_min_image": 0, "pair_store": 0}
-    top, stages = bench.roofline(S, res, (8, 8, 8))
-    flops = bench.FLOPS_PER_PAIR * 1_000_000 * 100
+    # 100 PCG products and 10 basis products of a learned start are productive; the other
+    # launches returned at entry after convergence
+    res = {"timing": timing(10.0, 120, 100), "timing_live": timing(12.5, 120, 100, other_ms=0.0),
+           "n_pairs": 1_000_000, "n_tiles": 100, "pme_planes": 1, "pair_min_image": 0, "pair_store": 0,
+           "extra_real_products": 10}
+    top, stages = bench.roofline(S, res)
+    flops = bench.FLOPS_PER_PAIR * 1_000_000 * 110
     assert top["stage"] == "real" and top["kernel"] == TILES
     assert top["achieved"] == pytest.approx(flops / 12.5e-3 / 1e12)
     assert top["achieved_alone"] == pytest.approx(flops / 10.0e-3 / 1e12)
-    assert top["avg_launch_us"] == pytest.approx(12.5e3 / 110)
+    assert top["avg_launch_us"] == pytest.approx(12.5e3 / 120)
+    assert top["productive_launches"] == 110
     assert top["frac"] == pytest.approx(top["achieved"] / bench.PEAK_FP32_VALU)
     assert top["frac_nonpacked"] == pytest.approx(top["achieved"] / bench.PEAK_FP32_NONPACKED)
     # without a live timing the stage pass is reported
     res.pop("timing_live")
-    top2, _ = bench.roofline(S, res, (8, 8, 8))
+    top2, _ = bench.roofline(S, res)
     assert top2["achieved"] == pytest.approx(flops / 10.0e-3 / 1e12)
     assert "achieved_alone" not in top2
+
+
+def test_step_statistics():
+    bench = load_bench()
+    st = bench.pstats([5.0, 1.0, 2.0, 4.0, 3.0])
+    assert st["median_ms"] == 3.0 and st["mean_ms"] == 3.0
+    assert st["p10_ms"] == pytest.approx(1.4) and st["p90_ms"] == pytest.approx(4.6)
