@@ -208,6 +208,24 @@ int amoeba_polarize(amoeba_ctx* ctx, const double* pos, const double* e_perm,
                     const double* mu_guess, int32_t guess_mode, double tol_debye, int32_t max_iter,
                     double* mu_out, double* e_pol_out, int32_t* iters_out);
 
+/* Gradient of the polarization energy with respect to the positions, grad_out[N][3] =
+ * dE_pol/dr (device FP64, kcal/mol/A; the polarization forces are its negative), for the
+ * permanent multipoles (q, dip, quad, as for amoeba_perm_field) and the induced dipoles mu[N][3]
+ * (device, e*A) at positions pos (paper "Global scheme": the polarization solve and its forces
+ * make the non-bonded step; "Real space scheme": scaled pairs corrected separately).  The result
+ * is the gradient of E_pol = -1/2 C mu.E_perm at dipoles that solve the system, where E_pol is
+ * stationary in mu:
+ *     dE_pol/dr_k = C [ -1/2 mu.(dT/dr_k) mu - mu.(dE_perm/dr_k) ],
+ * with the real-space pairs (Thole damping up to lambda9 for the quadrupole terms, the p-scale of
+ * the listed pairs in the permanent terms, unscaled mutual terms) and the smooth-PME terms
+ * (second and third B-spline derivatives on the grid potentials of the dipoles and of the
+ * multipoles).  For dipoles that do not solve the system it is the partial derivative at fixed
+ * mu.  Mixed precision: FP32 pair and PME arithmetic (near-coincident pairs below 0.5 A in FP64),
+ * fixed-point pair sums; the grid uses the brick spread and rocFFT in either precision.
+ * Errors as for amoeba_perm_field (traceless check, non-finite inputs, the fixed-point range). */
+int amoeba_polarization_gradient(amoeba_ctx* ctx, const double* pos, const double* q, const double* dip,
+                                 const double* quad, const double* mu, double* grad_out);
+
 /* ------------------------------------------------------------------------------------------
  * Learned initial guess (an addition to the paper's method: the paper starts PCG from a plain
  * guess).  A small per-atom network over neighbour-list environment features predicts the

@@ -101,6 +101,7 @@ def lib() -> ctypes.CDLL:
         L.amoeba_perm_field.argtypes = [_P, _P, _P, _P, _P, _P]
         L.amoeba_dipole_matvec.argtypes = [_P, _P, _P, _P]
         L.amoeba_dipole_field_parts.argtypes = [_P, _P, _P, _P, _P]
+        L.amoeba_polarization_gradient.argtypes = [_P, _P, _P, _P, _P, _P, _P]
         L.amoeba_polarize.argtypes = [_P, _P, _P, _P, ctypes.c_int32, ctypes.c_double, ctypes.c_int32, _P,
                                       ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32)]
         L.amoeba_get_info.argtypes = [_P, ctypes.POINTER(amoeba_info)]
@@ -238,6 +239,16 @@ class Context:
             _ptr(out, torch.float64, (n, 3), "mu_out"), ctypes.byref(ep), ctypes.byref(it)),
             ok=(AMOEBA_OK, AMOEBA_NOT_CONVERGED))
         return out, ep.value, it.value, st
+
+    def polarization_gradient(self, pos, q, dip, quad, mu, out=None):
+        """dE_pol/dr (kcal/mol/A, N x 3 on the device) at the induced dipoles mu."""
+        n = self.n
+        out = torch.empty((n, 3), dtype=torch.float64, device=pos.device) if out is None else out
+        self._check(lib().amoeba_polarization_gradient(
+            self.h, _ptr(pos, torch.float64, (n, 3), "pos"), _ptr(q, torch.float64, (n,), "q"),
+            _ptr(dip, torch.float64, (n, 3), "dip"), _ptr(quad, torch.float64, (n, 6), "quad"),
+            _ptr(mu, torch.float64, (n, 3), "mu"), _ptr(out, torch.float64, (n, 3), "grad_out")))
+        return out
 
     def set_pme_path(self, path):
         """path: "auto", "planes" or "bricks" (or the AMOEBA_PME_* value)."""

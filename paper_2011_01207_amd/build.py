@@ -14,7 +14,7 @@ LIB = os.path.join(HERE, "libamoeba.so")
 OBJ = os.path.join(HERE, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
-SOURCES = ["api.hip", "blocklist.hip", "realspace.hip", "pme.hip", "plane.hip", "pcg.hip", "guess.hip"]
+SOURCES = ["api.hip", "blocklist.hip", "realspace.hip", "pme.hip", "plane.hip", "pcg.hip", "guess.hip", "force.hip"]
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-munsafe-fp-atomics",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wno-unused-command-line-argument", "-Wno-unused-value", "-Wno-unused-result",

@@ -679,6 +679,46 @@ int amoeba_polarize(amoeba_ctx* c, const double* pos, const double* e_perm, cons
     return st;
 }
 
+int amoeba_polarization_gradient(amoeba_ctx* c, const double* pos, const double* q, const double* dip,
+                                 const double* quad, const double* mu, double* grad_out)
+{
+    if (!c)
+        return AMOEBA_E_INVALID;
+    c->err.clear();
+    if (!q || !dip || !quad || !mu || !grad_out)
+        return set_error(c, AMOEBA_E_INVALID, "amoeba_polarization_gradient: NULL argument");
+    int rc = begin_config(c, pos, "amoeba_polarization_gradient");
+    if (rc)
+        return rc;
+    if (!c->mp_d) {
+        if ((rc = ctx_alloc(c, (void**)&c->mp_d, sizeof(double4) * 3 * c->npad)))
+            return rc;
+        if (c->mixed && (rc = ctx_alloc(c, (void**)&c->mp_f, sizeof(float4) * 3 * c->npad)))
+            return rc;
+    }
+    hipStream_t st = c->stream;
+    hipMemsetAsync(c->flags, 0, sizeof(int), st);
+    hipLaunchKernelGGL(k_gather_mpole, dim3(nblk(c->npad, 256)), dim3(256), 0, st, c->npad, c->perm, q, dip, quad,
+                       c->mp_d, c->mixed ? c->mp_f : nullptr, c->flags);
+    launch_gather_vec_checked(c, mu, c->v_mu);
+    if ((rc = polar_gradient_slot(c)))
+        return rc;
+    if (c->mixed)
+        launch_check_overflow(c, c->ereal);   // the fixed-point pair sums
+    launch_scatter(c, c->v_q, grad_out);
+    int f = 0;
+    if ((rc = read_flags(c, &f)))
+        return rc;
+    if (f & kFlagBadCsr)
+        return set_error(c, AMOEBA_E_INVALID, "amoeba_polarization_gradient: quadrupole not traceless (|tr| > 1e-10)");
+    if (f & kFlagNonFinite)
+        return set_error(c, AMOEBA_E_NUMERIC, "amoeba_polarization_gradient: non-finite multipole, dipole or sum");
+    if (f & kFlagOverflow)
+        return set_error(c, AMOEBA_E_OVERFLOW,
+                         "amoeba_polarization_gradient: pair sum outside the exact fixed-point range (8192)");
+    return AMOEBA_OK;
+}
+
 int amoeba_set_timing(amoeba_ctx* c, int enable)
 {
     if (!c)

@@ -223,6 +223,8 @@ struct amoeba_ctx {
     float4* pv_f = nullptr;                // [npad] (FP32)
     double4* mp_d = nullptr;               // [npad*3] (q,dx,dy,dz),(Txx,Txy,Txz,Tyy),(Tyz,Tzz,0,0)
     float4* mp_f = nullptr;                // same in FP32 (mixed mode)
+    void* f_src = nullptr;                 // [npad*4] (R4) multipoles + dipoles of the gradient tiles
+    void* f_psi = nullptr;                 // [K0*K1*K2] (R) grid potential of the multipoles (gradient)
 
     amoeba::PcgScalars* sc = nullptr;      // device scalars
     amoeba::PcgScalars* sc_host = nullptr; // pinned mirror [2] (one per in-flight PCG iteration)
@@ -329,6 +331,7 @@ int next_coef_mode(const amoeba_ctx* c);  // the next dipole product: 0 evaluate
 void launch_real_reduce(amoeba_ctx* c, double* ereal, hipStream_t st = nullptr, bool use_done = false);
 void launch_perm_tiles(amoeba_ctx* c, hipStream_t st = nullptr);
 void launch_perm_assemble(amoeba_ctx* c, double* out_slot);
+void launch_force_tiles(amoeba_ctx* c, const void* src, double* out);  // real-space gradient pair sums
 
 // pme.hip
 int pme_setup(amoeba_ctx* c);
@@ -347,6 +350,10 @@ void plane_gather(amoeba_ctx* c, double* out);          // E_rec from the plane 
 int plane_combine(amoeba_ctx* c, bool use_done, bool dot_pq, bool reduced);  // PCG product; returns its partial count
 bool pme_use_planes(const amoeba_ctx* c);
 void launch_gather(amoeba_ctx* c, double* out);       // E_rec at atoms from the potential grid
+int pme_brick_potential(amoeba_ctx* c, bool perm);    // psi of the multipoles (perm) or of pv, brick path
+
+// force.hip
+int polar_gradient_slot(amoeba_ctx* c);               // dE_pol/dr (slot order) into v_q
 
 // api.hip
 int read_flags(amoeba_ctx* c, int* out);

@@ -985,6 +985,39 @@ int pme_perm_potential(amoeba_ctx* c)
     return convolve_and_back(c, false);
 }
 
+// Grid potential psi = theta * Q on the brick path, into grid_r: Q the spread of the permanent
+// multipoles (mp) or of the dipoles in the pair kernels' copy of the direction (pv).
+int pme_brick_potential(amoeba_ctx* c, bool perm)
+{
+    ensure_brick_bins(c);
+    int3 K = make_int3(c->K[0], c->K[1], c->K[2]);
+    int3 nbr = make_int3(c->nbr[0], c->nbr[1], c->nbr[2]);
+    double3 kl = make_double3(c->K[0] / c->prm.box[0], c->K[1] / c->prm.box[1], c->K[2] / c->prm.box[2]);
+    if (c->mixed) {
+        if (perm)
+            hipLaunchKernelGGL((k_spread<float, true, true>), dim3(c->nbricks), dim3(256), 0, c->stream, K, nbr,
+                               c->bin_start, c->bin_atoms, c->pos_s, kl, (const float4*)c->mp_f, (float*)c->grid_r,
+                               c->sc, 0);
+        else
+            hipLaunchKernelGGL((k_spread<float, true, false>), dim3(c->nbricks), dim3(256), 0, c->stream, K, nbr,
+                               c->bin_start, c->bin_atoms, c->pos_s, kl, (const float4*)c->pv_f, (float*)c->grid_r,
+                               c->sc, 0);
+    } else {
+        if (perm)
+            hipLaunchKernelGGL((k_spread<double, false, true>), dim3(c->nbricks), dim3(256), 0, c->stream, K, nbr,
+                               c->bin_start, c->bin_atoms, c->pos_s, kl, (const double4*)c->mp_d,
+                               (double*)c->grid_r, c->sc, 0);
+        else
+            hipLaunchKernelGGL((k_spread<double, false, false>), dim3(c->nbricks), dim3(256), 0, c->stream, K,
+                               nbr, c->bin_start, c->bin_atoms, c->pos_s, kl, (const double4*)c->pv_d,
+                               (double*)c->grid_r, c->sc, 0);
+    }
+    int rc = run_fft(c, nullptr, false);
+    if (rc)
+        return rc;
+    return convolve_and_back(c, false);
+}
+
 void launch_gather(amoeba_ctx* c, double* out)
 {
     if (c->rec_plane) {

@@ -408,6 +408,128 @@ template <typename R> struct MultipoleKind {
     }
 };
 
+// Gradient of the polarization energy (paper, "Global scheme": the polarization forces of the
+// non-bonded step).  At converged dipoles E_pol = -1/2 C mu.E_perm is stationary in mu, so per
+// pair (r = r_i - r_j) only the explicit position dependence enters:
+//   G = grad_r u(r) + grad_r w_ij(r) - (grad w_ji)(-r),
+//   u = mu_i . T(r) mu_j = -B1' mu_i.mu_j + B2' (mu_i.r)(mu_j.r)           (mutual, unscaled)
+//   w_ij(r) = mu_i . E_j(r), E_j(r) = q_j B1' r - B1' d_j + B2' (d_j.r) r
+//             + 1/3 B3' (Theta_j:rr) r - 2/3 B2' Theta_j r                      (permanent)
+// with grad_r B_n' = -B_{n+1}' r for the screened and Thole-damped radial functions alike
+// (lambda9 = 1 - (1 + eps + 18/35 eps^2 + 9/35 eps^3) e^-eps continues lambda3..7); then
+// dE_pol/dr_i = -C sum_j G and dE_pol/dr_j = +C G.  The tiles use the unscaled pair (p-scale 1);
+// the scaled pairs are corrected in a separate pass.  pair() adds G to the i-sum and returns -G.
+// Per atom: d[0] = (q, dx, dy, dz), d[1] = (Txx, Txy, Txz, Tyy), d[2] = (Tyz, Tzz, Thole a, 0),
+// d[3] = (mu_x, mu_y, mu_z, 0).
+template <typename T, typename R4>
+__device__ __forceinline__ void grad_w(T mx, T my, T mz, const R4* m, T rx, T ry, T rz, T b1, T b2, T b3, T b4,
+                                       T& gx, T& gy, T& gz)
+{
+    const T q = (T)m[0].x, dx = (T)m[0].y, dy = (T)m[0].z, dz = (T)m[0].w;
+    const T txx = (T)m[1].x, txy = (T)m[1].y, txz = (T)m[1].z, tyy = (T)m[1].w, tyz = (T)m[2].x, tzz = (T)m[2].y;
+    const T mr = mx * rx + my * ry + mz * rz, dr = dx * rx + dy * ry + dz * rz, md = mx * dx + my * dy + mz * dz;
+    const T thx = txx * rx + txy * ry + txz * rz, thy = txy * rx + tyy * ry + tyz * rz,
+            thz = txz * rx + tyz * ry + tzz * rz;
+    const T tmx = txx * mx + txy * my + txz * mz, tmy = txy * mx + tyy * my + tyz * mz,
+            tmz = txz * mx + tyz * my + tzz * mz;
+    const T thrr = thx * rx + thy * ry + thz * rz, mthr = mx * thx + my * thy + mz * thz;
+    const T third = (T)1 / (T)3;
+    // coefficient of r, of mu, of d, of Theta r and of Theta mu
+    const T cr = -q * b2 * mr + b2 * md - b3 * dr * mr - third * b4 * thrr * mr + (T)2 * third * b3 * mthr;
+    const T cm = q * b1 + b2 * dr + third * b3 * thrr;
+    const T cd = b2 * mr;
+    const T ct = (T)2 * third * b3 * mr;
+    const T cu = -(T)2 * third * b2;
+    gx = cr * rx + cm * mx + cd * dx + ct * thx + cu * tmx;
+    gy = cr * ry + cm * my + cd * dy + ct * thy + cu * tmy;
+    gz = cr * rz + cm * mz + cd * dz + ct * thz + cu * tmz;
+}
+
+// G of one pair from its displacement, in precision T (FP64 evaluation of an FP32 tile's close
+// pair included).  aij = min(a_i, a_j), wij = (alpha_i alpha_j)^(-1/6).
+template <typename T, typename R4>
+__device__ __forceinline__ void force_pair(T rx, T ry, T rz, T aij, T wij, const R4* di, const R4* dj, T beta,
+                                           T gfac, T* G)
+{
+    const T r2 = rx * rx + ry * ry + rz * rz;
+    const T rinv = d_rsqrt(r2);
+    const T r = r2 * rinv, rinv2 = rinv * rinv;
+    const T gauss = d_exp(-beta * beta * r2);
+    const T gb = gfac * gauss;       // 2 beta / sqrt(pi) e^{-beta^2 r^2}
+    const T t = (T)2 * beta * beta;
+    const T b0 = d_erfc_g(beta * r, gauss) * rinv;
+    const T b1 = (b0 + gb) * rinv2;
+    const T b2 = ((T)3 * b1 + t * gb) * rinv2;
+    const T b3 = ((T)5 * b2 + t * t * gb) * rinv2;
+    const T b4 = ((T)7 * b3 + t * t * t * gb) * rinv2;
+    const T u = r * wij;
+    const T eps = aij * u * u * u;
+    const T ex = d_exp(-eps);
+    const T r3 = rinv * rinv2, r5 = r3 * rinv2, r7 = r5 * rinv2, r9 = r7 * rinv2;
+    const T b1p = b1 - ex * r3;
+    const T b2p = b2 - (T)3 * ((T)1 + eps) * ex * r5;
+    const T b3p = b3 - (T)15 * ((T)1 + eps + (T)0.6 * eps * eps) * ex * r7;
+    const T b4p = b4 - (T)105 * ((T)1 + eps + ((T)18 / (T)35) * eps * eps + ((T)9 / (T)35) * eps * eps * eps) * ex * r9;
+    const T mix = (T)di[3].x, miy = (T)di[3].y, miz = (T)di[3].z;
+    const T mjx = (T)dj[3].x, mjy = (T)dj[3].y, mjz = (T)dj[3].z;
+    // mutual: grad u = B2' (mu_i.mu_j) r - B3' (mu_i.r)(mu_j.r) r + B2' (mu_i (mu_j.r) + mu_j (mu_i.r))
+    const T mm = mix * mjx + miy * mjy + miz * mjz;
+    const T mir = mix * rx + miy * ry + miz * rz, mjr = mjx * rx + mjy * ry + mjz * rz;
+    const T cu = b2p * mm - b3p * mir * mjr;
+    G[0] = cu * rx + b2p * (mix * mjr + mjx * mir);
+    G[1] = cu * ry + b2p * (miy * mjr + mjy * mir);
+    G[2] = cu * rz + b2p * (miz * mjr + mjz * mir);
+    T gx, gy, gz;
+    grad_w<T, R4>(mix, miy, miz, dj, rx, ry, rz, b1p, b2p, b3p, b4p, gx, gy, gz);
+    G[0] += gx;
+    G[1] += gy;
+    G[2] += gz;
+    grad_w<T, R4>(mjx, mjy, mjz, di, -rx, -ry, -rz, b1p, b2p, b3p, b4p, gx, gy, gz);
+    G[0] -= gx;
+    G[1] -= gy;
+    G[2] -= gz;
+}
+
+template <typename R> struct ForceKind {
+    using R4 = typename V4<R>::T;
+    static constexpr int NV = 4;
+    __device__ static void load(const R4* src, size_t s, R a, R4* d)
+    {
+        d[0] = src[4 * s];
+        d[1] = src[4 * s + 1];
+        const R4 m2 = src[4 * s + 2];
+        d[2] = R4{m2.x, m2.y, a, 0};
+        d[3] = src[4 * s + 3];
+    }
+    template <bool MI>
+    __device__ static void pair(const R4& ip, const R4* di, const R4& jp, const R4* dj, const EwaldArgs<R>& ew,
+                                R* ei, R* ej)
+    {
+        R dx, dy, dz;
+        pair_disp<R, MI>(ip, jp, ew, dx, dy, dz);
+        const R aij = di[2].z < dj[2].z ? di[2].z : dj[2].z;
+        const R wij = ip.w * jp.w;
+        R G[3];
+        if (sizeof(R) == 4 && dx * dx + dy * dy + dz * dz < kCloseR2) {
+            // FP32 cannot resolve B_n' of a near-coincident pair (see close_pair_series): such a
+            // pair is evaluated in FP64 from the same displacement
+            double Gd[3];
+            force_pair<double, R4>((double)dx, (double)dy, (double)dz, (double)aij, (double)wij, di, dj,
+                                   (double)ew.beta, (double)ew.g, Gd);
+            G[0] = (R)Gd[0];
+            G[1] = (R)Gd[1];
+            G[2] = (R)Gd[2];
+        } else {
+            force_pair<R, R4>(dx, dy, dz, aij, wij, di, dj, ew.beta, ew.g, G);
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            ei[c] += G[c];
+            ej[c] = -G[c];
+        }
+    }
+};
+
 // ------------------------------------------------------------------------------------------
 // K3 / K3p: one workgroup per i-block over all the block's tiles.
 // jbuf layout: [tile * 64 + lane] (x, y, z, 0) (R);  eipart: [slot][3] (FP64).
@@ -821,6 +943,35 @@ template <bool MI> static void perm_tiles(amoeba_ctx* c, hipStream_t st)
                            st, c->nb, c->blk_tile0, c->tile_np, c->tile_j, c->tile_mask, c->jrel_d, c->off_d, c->par_d,
                            (const double4*)c->mp_d, make_ewald<double>(c), c->eipart, (double*)c->jbuf, c->sc, 0,
                            (const int*)nullptr, 0ll, (double2*)nullptr);
+}
+
+template <bool MI> static void force_tiles(amoeba_ctx* c, const void* src)
+{
+    if (c->mixed)
+        hipLaunchKernelGGL((k_block_tiles<float, true, ForceKind<float>, MI>), dim3(c->nb), dim3(256), 0,
+                           c->stream, c->nb, c->blk_tile0, c->tile_np, c->tile_j, c->tile_mask, c->jrel_f, c->off_f,
+                           c->par_f, (const float4*)src, make_ewald<float>(c), c->eipart, (float*)c->jbuf, c->sc, 0,
+                           (const int*)nullptr, 0ll, (float2*)nullptr);
+    else
+        hipLaunchKernelGGL((k_block_tiles<double, false, ForceKind<double>, MI>), dim3(c->nb), dim3(256), 0,
+                           c->stream, c->nb, c->blk_tile0, c->tile_np, c->tile_j, c->tile_mask, c->jrel_d, c->off_d,
+                           c->par_d, (const double4*)src, make_ewald<double>(c), c->eipart, (double*)c->jbuf, c->sc,
+                           0, (const int*)nullptr, 0ll, (double2*)nullptr);
+}
+
+// Real-space pair sums of the polarization gradient, sum_j G_ij per slot, into out (FP64 N x 3);
+// src: [npad][4] (R4) multipoles and dipoles in the ForceKind layout.
+void launch_force_tiles(amoeba_ctx* c, const void* src, double* out)
+{
+    if (c->ntiles > 0) {
+        if (c->skip_mimg)
+            force_tiles<false>(c, src);
+        else
+            force_tiles<true>(c, src);
+        launch_real_reduce(c, out, c->stream);
+    } else {
+        hipMemsetAsync(out, 0, sizeof(double) * 3 * (size_t)c->npad, c->stream);
+    }
 }
 
 void launch_perm_tiles(amoeba_ctx* c, hipStream_t st)
