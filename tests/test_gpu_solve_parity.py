@@ -193,8 +193,11 @@ def test_learned_and_judged_starts_match_oracle(model_seed, prec):
             rf, rl = inf["last_guess_rms_debye"]
             print(f"  judged start (given {sigma} D): GPU residuals given {rf:.6e} learned {rl:.6e}, oracle "
                   f"{r0_g:.6e} {r0_l:.6e}; picked {inf['last_guess']}", flush=True)
+            # the given start's residual to the product's rounding; the learned start's also to
+            # the network's, which runs in FP32 in both precisions (its mu0 differs from the
+            # oracle's FP64 network by FP32 rounding)
             bar = 1e-9 if prec == "fp64" else 1e-4
-            assert abs(rf - r0_g) <= bar * r0_g and abs(rl - r0_l) <= bar * r0_l
+            assert abs(rf - r0_g) <= bar * r0_g and abs(rl - r0_l) <= max(bar, 1e-6) * r0_l
             want = amoeba.AMOEBA_GUESS_LEARNED if r0_l < r0_g else amoeba.AMOEBA_GUESS_GIVEN
             if abs(r0_l - r0_g) > 0.01 * min(r0_l, r0_g):
                 assert inf["last_guess"] == want
