@@ -5,19 +5,21 @@ Headline workload (the largest single-GPU configuration): 288,000 rigid waters (
 in a 205.0 A box, 7 A real-space cutoff with a 2 A list buffer, Ewald beta 0.545 1/A, PME grid
 216^3 of order 5 (synthetic, seeded).  One step processes one configuration end to end on the
 GPU with inputs resident in HBM: block-list build, permanent field E_perm, the learned initial
-guess (bases, features, network) and the mixed-precision PCG solve of (alpha^-1 - T) mu = E_perm
-from that guess to the stopping tolerance, E_pol included.  The configurations are held-out
-frames of a 0.02 A-step trajectory of the box; the network was trained beforehand on the GPU
-(its own kernels) on the solver's converged dipoles of the preceding frames.  `value` is steps
-(= solves) per second over the timed steps; the per-step median, p10 and p90 are reported too.
-Beside it, on the same frames: mixed precision from the zero guess, and the plain FP64 PCG from
-the zero guess (the baseline the speed-ups refer to).
+guess (features and network of its delta kind: the previous configuration's converged dipoles
+corrected by the network's response to the change of the permanent field) and the
+mixed-precision PCG solve of (alpha^-1 - T) mu = E_perm from that guess to the stopping
+tolerance, E_pol included.  The configurations are held-out frames of a 0.02 A-step trajectory
+of the box; the network was trained beforehand on the GPU (its own kernels) on the solver's
+converged dipoles of the preceding frames.  `value` is steps (= solves) per second over the
+timed steps; the per-step median, p10 and p90 are reported too.  Beside it, on the same frames:
+mixed precision from the previous step's dipoles (the method without the network), from the
+zero guess, and the plain FP64 PCG from the zero guess (the baseline the speed-ups refer to).
 
 Accuracy: the converged dipoles of every variant on the 864,000-atom box are compared with the
 FP64 GPU solve, and on a periodic ~4,000-atom subcell of the same box with the FP64 oracle's
 exact solution (rms and max |mu - mu*|, E_pol error).  Secondary legs: the 648-, 23,558- and
 96,000-atom workloads (FP64 and mixed), and the 288,000-atom trajectory (train on 150 frames,
-evaluate 50 from the zero, previous-step, learned and judged starts).
+evaluate 50 from the zero, previous-step, learned and judged starts, with both network kinds).
 
 The roofline entry is the dominant kernel of the headline leg, timed with HIP events on the
 stream it runs on; the CPU baseline times the FP64 oracle on this host (one full matrix-vector
@@ -107,18 +109,23 @@ def new_context(s, t, precision, pair_store="auto"):
 
 def run_steps(ctx, t, frames, steps, warmup, tol, guess="zero", prev=None, timing_live=False, stage_pass=False):
     """`steps` steps cycling over `frames` (device position tensors): list + E_perm + solve from
-    `guess` ('zero', 'learned', or 'given'/'best' with prev[k] the previous frame's dipoles).
-    Returns per-step times, iterations, the last frame's outputs and the timers."""
+    `guess` ('zero'; 'given' with prev[k] = (dipoles, field) of the frame before frame k;
+    'learned' with the network of the context's kind, whose delta kind takes prev[k] as its
+    reference; 'best' judges the learned guess against the given one).  Returns per-step
+    times, iterations, the last frame's outputs and the timers."""
     import torch
     from paper_2011_01207_amd import amoeba
     e_perm = torch.empty_like(frames[0])
     mu = torch.empty_like(frames[0])
+    delta = guess in ("learned", "best") and ctx.guess_kind == "delta"
 
     def step(k):
         pos = frames[k % len(frames)]
         ctx.build_blocklist(pos)
         ctx.perm_field(pos, t["q"], t["dip"], t["quad"], out=e_perm)
-        g = prev[k % len(frames)] if guess in ("given", "best") else None
+        g = prev[k % len(frames)][0] if guess in ("given", "best") else None
+        if delta:
+            ctx.guess_set_reference(*prev[k % len(frames)])
         _, ep, it, st = ctx.polarize(pos, e_perm, mu_guess=g, guess_mode=guess, tol_debye=tol, max_iter=1000,
                                      out=mu)
         if st != amoeba.AMOEBA_OK:
@@ -144,9 +151,9 @@ def run_steps(ctx, t, frames, steps, warmup, tol, guess="zero", prev=None, timin
     out = {"step_ms": 1e3 * total / steps, "solves_per_s": steps / total, **pstats(times),
            "iterations": its[-1], "mean_iterations": statistics.fmean(its), "e_pol_kcal": eps[-1],
            "learned_picked": sum(1 for p in picks if p == amoeba.AMOEBA_GUESS_LEARNED),
-           # real-space products per pass of `steps` steps besides the PCG products: the learned
-           # guess's two basis products per step
-           "extra_real_products": 2 * steps if guess in ("learned", "best") else 0}
+           # real-space products per pass of `steps` steps besides the PCG products: the
+           # Neumann-kind guess's two basis products per step (the delta kind needs none)
+           "extra_real_products": 2 * steps if guess in ("learned", "best") and not delta else 0}
     out["timing_live"] = ctx.timing() if timing_live else None
     ctx.set_timing("off")
     if stage_pass:
@@ -169,19 +176,32 @@ def run_steps(ctx, t, frames, steps, warmup, tol, guess="zero", prev=None, timin
     return out
 
 
-def reference_data(ctx, t, frames, tol_ref=1e-6):
-    """Training data from the solver itself: per frame the converged dipoles (to tol_ref) and the
-    network's features and bases (GPU kernels)."""
+def reference_solves(ctx, t, frames, tol_ref=1e-6):
+    """The solver's own converged dipoles (to tol_ref) and permanent field of every frame."""
     from paper_2011_01207_amd import amoeba
-    data = []
+    out = []
     for pos in frames:
         ctx.build_blocklist(pos)
         e = ctx.perm_field(pos, t["q"], t["dip"], t["quad"])
         mu, _, _, st = ctx.polarize(pos, e, tol_debye=tol_ref, max_iter=1000)
         if st != amoeba.AMOEBA_OK:
             raise RuntimeError("reference solve did not converge")
-        feat, basis = ctx.guess_features(pos, e)
-        data.append({"pos": pos, "e": e, "mu": mu.clone(), "feat": feat, "basis": basis})
+        out.append({"pos": pos, "e": e, "mu": mu.clone()})
+    return out
+
+
+def with_features(ctx, sol, first, last):
+    """Training data of frames first..last-1: the network's features and bases of each frame
+    (GPU kernels; the delta kind takes the frame before as its reference) and its converged
+    dipoles as the target."""
+    data = []
+    for k in range(first, last):
+        d = sol[k]
+        ctx.build_blocklist(d["pos"])
+        if ctx.guess_kind == "delta":
+            ctx.guess_set_reference(sol[k - 1]["mu"], sol[k - 1]["e"])
+        feat, basis = ctx.guess_features(d["pos"], d["e"])
+        data.append({**d, "feat": feat, "basis": basis})
     return data
 
 
@@ -221,33 +241,47 @@ def strip(res):
     return {k: v for k, v in res.items() if k not in ("mu", "timing")}
 
 
+def guess_errors(ctx, data):
+    """Mean rms error (Debye) of the network's guess and of the previous-step guess against the
+    converged dipoles of held-out frames."""
+    err_l = statistics.fmean(
+        mu_errors(ctx.guess_forward(d["feat"], d["basis"]).double(), d["mu"])["mu_rms_debye"] for d in data)
+    return err_l
+
+
 def headline(s, t, a):
-    """The headline box: training, then mixed + learned, mixed (zero) and FP64 (zero) on the
-    same held-out frames."""
+    """The headline box: the delta-kind network trained on the GPU, then mixed + learned,
+    mixed + previous step, mixed (zero) and FP64 (zero) on the same held-out frames."""
     import torch
     from paper_2011_01207_amd import synth
     n_train, n_eval = 8, 4
     frames = [torch.tensor(p, device="cuda:0") for p in synth.trajectory(s, n_train + n_eval + 1, 0.02, seed=504)]
-    train_frames, eval_frames = frames[1:n_train + 1], frames[n_train + 1:]
+    eval_frames = frames[n_train + 1:]
     log(f"{s.name}: training the learned guess on {n_train} frames")
     ctx = new_context(s, t, "mixed", a.pair_store)
+    ctx.guess_set_kind("delta")
     t0 = time.perf_counter()
-    data = reference_data(ctx, t, train_frames)
+    sol = reference_solves(ctx, t, frames)
     t_ref = time.perf_counter() - t0
+    data = with_features(ctx, sol, 1, n_train + 1)
     tr = train(ctx, data, train_steps=600, batch=65536)
     del data
-    tr.update({"reference_solves_s": t_ref, "train_configs": n_train, "eval_configs": n_eval})
-    model = ctx.guess_get_model()
-    held = reference_data(ctx, t, eval_frames)
-    tr["guess_rms_err_debye"] = statistics.fmean(
-        mu_errors(ctx.guess_forward(d["feat"], d["basis"]).double(), d["mu"])["mu_rms_debye"] for d in held)
+    tr.update({"kind": "delta", "reference_solves_s": t_ref, "train_configs": n_train, "eval_configs": n_eval})
+    held = with_features(ctx, sol, n_train + 1, n_train + n_eval + 1)
+    tr["guess_rms_err_debye"] = guess_errors(ctx, held)
+    tr["prev_rms_err_debye"] = statistics.fmean(
+        mu_errors(sol[k - 1]["mu"], sol[k]["mu"])["mu_rms_debye"] for k in range(n_train + 1, n_train + n_eval + 1))
     del held
+    model = ctx.guess_save()
+    prev = [(sol[k - 1]["mu"], sol[k - 1]["e"]) for k in range(n_train + 1, n_train + n_eval + 1)]
     log(f"{s.name}: mixed + learned guess")
-    learned = run_steps(ctx, t, eval_frames, a.steps, a.warmup, a.tol, guess="learned", timing_live=True,
-                        stage_pass=True)
-    ctx.close()
+    learned = run_steps(ctx, t, eval_frames, a.steps, a.warmup, a.tol, guess="learned", prev=prev,
+                        timing_live=True, stage_pass=True)
     log(f"{s.name}: mixed + learned {learned['step_ms']:.3f} ms/step (median {learned['median_ms']:.3f}), "
         f"{learned['mean_iterations']:.1f} it")
+    given = run_steps(ctx, t, eval_frames, a.steps, a.warmup, a.tol, guess="given", prev=prev)
+    log(f"{s.name}: mixed + previous step {given['step_ms']:.3f} ms/step, {given['mean_iterations']:.1f} it")
+    ctx.close()
     ctx = new_context(s, t, "mixed", a.pair_store)
     mixed = run_steps(ctx, t, eval_frames, a.steps, a.warmup, a.tol, guess="zero", stage_pass=True)
     ctx.close()
@@ -256,31 +290,44 @@ def headline(s, t, a):
     fp64 = run_steps(ctx, t, eval_frames, a.steps, a.warmup, a.tol, guess="zero")
     ctx.close()
     log(f"{s.name}: fp64 {fp64['step_ms']:.3f} ms/step, {fp64['mean_iterations']:.1f} it")
+    del sol, prev
     acc = {}
-    for name, r in (("mixed_learned", learned), ("mixed", mixed)):
+    for name, r in (("mixed_learned", learned), ("mixed_previous_step", given), ("mixed", mixed)):
         acc[name] = mu_errors(r["mu"], fp64["mu"])
         acc[name]["e_pol_abs_kcal"] = abs(r["e_pol_kcal"] - fp64["e_pol_kcal"])
         acc[name]["e_pol_rel"] = acc[name]["e_pol_abs_kcal"] / abs(fp64["e_pol_kcal"])
-    return learned, mixed, fp64, acc, tr, model
+    return learned, given, mixed, fp64, acc, tr, model
 
 
 def subcell_accuracy(parent, model, tol):
     """Every variant against the FP64 oracle's exact solution on the periodic subcell of the
-    headline box (full oracle solve: smooth PME on the same grid spacing, PCG to 1e-9 D)."""
+    headline box (full oracle solve: smooth PME on the same grid spacing, PCG to 1e-9 D).  The
+    subcell takes one 0.02 A trajectory step; the learned start (the headline's delta network)
+    uses the GPU's converged solution of the configuration before the step as its reference."""
+    import dataclasses
+    import torch
     import oracle as O
     from paper_2011_01207_amd import synth
-    s = synth.subcell(parent)
+    s0 = synth.subcell(parent)
+    p0, p1 = list(synth.trajectory(s0, 2, 0.02, seed=604))
+    s = dataclasses.replace(s0, pos=p1)
     e_ref = O.perm_field(s, "spme")
     mu_ref, _, _ = O.pcg(s, e_ref, "spme", tol_debye=1e-9)
     ep_ref = O.e_pol(mu_ref, e_ref)
     t = tensors(s)
-    out = {"workload": f"{s.name}: periodic {s.box[0]:.2f} A cube of the headline box, PME {s.grid[0]}^3",
+    pos0 = torch.tensor(p0, device="cuda:0")
+    out = {"workload": f"{s.name}: periodic {s.box[0]:.2f} A cube of the headline box, PME {s.grid[0]}^3, one "
+                       "0.02 A step after the reference configuration",
            "n_atoms": s.n, "e_pol_oracle_kcal": ep_ref}
     for name, prec, guess in (("fp64", "fp64", "zero"), ("mixed", "mixed", "zero"),
                               ("mixed_learned", "mixed", "learned")):
         ctx = new_context(s, t, prec)
         if guess == "learned":
-            ctx.guess_set_model(model)
+            ctx.guess_load(model)
+            ctx.build_blocklist(pos0)
+            e0 = ctx.perm_field(pos0, t["q"], t["dip"], t["quad"])
+            mu0, _, _, _ = ctx.polarize(pos0, e0, tol_debye=1e-6, max_iter=1000)
+            ctx.guess_set_reference(mu0, e0)
         ctx.build_blocklist(t["pos"])
         e = ctx.perm_field(t["pos"], t["q"], t["dip"], t["quad"])
         mu, ep, it, st = ctx.polarize(t["pos"], e, guess_mode=guess, tol_debye=tol, max_iter=1000)
@@ -323,8 +370,10 @@ def secondary(a):
 
 
 def trajectory_leg(a, n_train=150, n_eval=50):
-    """288,000 atoms, 201 configurations of cumulative 0.02 A steps: train on frames 1..150, then
-    solve frames 151..200 once each from the zero, previous-step, learned and judged starts."""
+    """288,000 atoms, 201 configurations of cumulative 0.02 A steps: the network of each kind
+    trained on frames 1..150 (the solver's own converged dipoles; the delta kind with each
+    frame's predecessor as its reference), then frames 151..200 solved once each from the zero,
+    previous-step, learned and judged starts."""
     import torch
     from paper_2011_01207_amd import synth
     s = synth.water288k()
@@ -332,28 +381,38 @@ def trajectory_leg(a, n_train=150, n_eval=50):
     frames = [torch.tensor(p, device="cuda:0") for p in synth.trajectory(s, n_train + n_eval + 1, 0.02, seed=304)]
     ctx = new_context(s, t, "mixed", a.pair_store)
     t0 = time.perf_counter()
-    data = reference_data(ctx, t, frames[1:n_train + 1])
-    t_ref = time.perf_counter() - t0
-    tr = train(ctx, data, train_steps=2000, batch=65536)
-    tr["reference_solves_s"] = t_ref
-    del data
+    sol = reference_solves(ctx, t, frames)
+    out = {"workload": "water_288000: 96,000 waters, 142.3 A box, PME 144^3; 201 configurations of cumulative "
+                       "0.02 A per-atom steps; train on 1-150, evaluate 151-200 once per start",
+           "reference_solves_s": time.perf_counter() - t0,
+           "prev_rms_err_debye": statistics.fmean(
+               mu_errors(sol[k - 1]["mu"], sol[k]["mu"])["mu_rms_debye"]
+               for k in range(n_train + 1, n_train + n_eval + 1))}
     ev = frames[n_train + 1:]
-    refs = reference_data(ctx, t, frames[n_train:])   # converged dipoles of frames 150..200
-    prevs = [d["mu"] for d in refs[:-1]]
-    tr["guess_rms_err_debye"] = statistics.fmean(
-        mu_errors(ctx.guess_forward(d["feat"], d["basis"]).double(), d["mu"])["mu_rms_debye"] for d in refs[1:])
-    tr["prev_rms_err_debye"] = statistics.fmean(
-        mu_errors(prevs[k], refs[k + 1]["mu"])["mu_rms_debye"] for k in range(n_eval))
-    del refs
+    prev = [(sol[k - 1]["mu"], sol[k - 1]["e"]) for k in range(n_train + 1, n_train + n_eval + 1)]
     modes = {}
-    for mode in ("zero", "given", "learned", "best"):
-        r = run_steps(ctx, t, ev, n_eval, 2, a.tol, guess=mode, prev=prevs, stage_pass=True)
+    for mode in ("zero", "given"):
+        r = run_steps(ctx, t, ev, n_eval, 2, a.tol, guess=mode, prev=prev, stage_pass=True)
         modes[{"given": "previous_step"}.get(mode, mode)] = strip(r)
         log(f"288k trajectory {mode}: {r['step_ms']:.3f} ms, {r['mean_iterations']:.2f} it")
+    for kind in ("neumann", "delta"):
+        ctx.guess_set_kind(kind)
+        data = with_features(ctx, sol, 1, n_train + 1)
+        tr = train(ctx, data, train_steps=2000, batch=65536)
+        del data
+        held = with_features(ctx, sol, n_train + 1, n_train + n_eval + 1)
+        tr["guess_rms_err_debye"] = guess_errors(ctx, held)
+        del held
+        out[f"training_{kind}"] = tr
+        for mode in ("learned", "best"):
+            r = run_steps(ctx, t, ev, n_eval, 2, a.tol, guess=mode, prev=prev, stage_pass=True)
+            modes[f"{mode}_{kind}"] = strip(r)
+            log(f"288k trajectory {mode} ({kind}): {r['step_ms']:.3f} ms, {r['mean_iterations']:.2f} it, "
+                f"learned picked {r['learned_picked']}")
     ctx.close()
-    return {"workload": "water_288000: 96,000 waters, 142.3 A box, PME 144^3; 201 configurations of cumulative "
-                        "0.02 A per-atom steps; train on 1-150, evaluate 151-200 once per start",
-            **tr, "modes": modes}
+    del sol, prev
+    out["modes"] = modes
+    return out
 
 
 def roofline(s, res):
@@ -472,7 +531,7 @@ def main():
     s = synth.water864k() if a.workload == "water_864000" else synth.water96k()
     log(f"workload {s.name}: N={s.n} box={s.box[0]} grid={s.grid} rc={s.cutoff}+{s.buffer}")
     t = tensors(s)
-    learned, mixed, fp64, acc, tr, model = headline(s, t, a)
+    learned, given, mixed, fp64, acc, tr, model = headline(s, t, a)
     top, stages = roofline(s, learned)
     res = {
         "metric": METRIC,
@@ -492,13 +551,15 @@ def main():
                                 f"rc 7 A + 2 A list buffer, beta 0.545/A, PME {s.grid[0]}^3 order 5; one step = "
                                 "block list + E_perm + learned initial guess + mixed-precision PCG to the tolerance, "
                                 "on held-out frames of a 0.02 A-step trajectory"),
-                   "precision": "mixed", "guess": "learned", "tol_debye": a.tol},
+                   "precision": "mixed", "guess": "learned (delta kind)", "tol_debye": a.tol},
         "roofline": top,
         "roofline_stages": stages,
         "mixed_learned": strip(learned),
+        "mixed_previous_step": strip(given),
         "mixed": strip(mixed),
         "fp64": strip(fp64),
         "speedup_vs_fp64": {"mixed_learned": fp64["step_ms"] / learned["step_ms"],
+                            "mixed_previous_step": fp64["step_ms"] / given["step_ms"],
                             "mixed": fp64["step_ms"] / mixed["step_ms"]},
         "accuracy_vs_fp64_gpu": acc,
         "learned_guess_training": tr,
@@ -507,7 +568,7 @@ def main():
         log("subcell accuracy against the oracle")
         res["accuracy_vs_oracle_subcell"] = subcell_accuracy(s, model, a.tol)
     fp64_iters = fp64["iterations"]
-    del t, learned, mixed, fp64
+    del t, learned, given, mixed, fp64
     torch.cuda.empty_cache()
     if not a.no_secondary:
         log("secondary workloads")

@@ -243,7 +243,8 @@ int amoeba_polarization_gradient(amoeba_ctx* ctx, const double* pos, const doubl
  *     cos(v0,v1), cos(v0,v2), cos(v1,v2) with cos(a,b) = a.b / sqrt(|a|^2 |b|^2 + 1e-20),
  *     sum over in-cutoff neighbours of exp(-((r - c_k) / 0.6 A)^2) for c_k = 1, 2, 3 A.
  * Network (FP32): xh = (x - mean) * inv_std; h1 = silu(W1 xh + b1); h2 = silu(W2 h1 + b2);
- * y = W3 h2 + b3; mu0 = sum_k (1 + y_k) v_k.  Loss of a batch of n samples:
+ * y = W3 h2 + b3; mu0 = sum_k (s_k + y_k) v_k, s = (1, 1, 1) for these bases (the DELTA kind
+ * below has its own bases and offsets).  Loss of a batch of n samples:
  * L = D^2 / n * sum_i |mu0_i - target_i|^2 (Debye^2).  Optimiser: Adam (beta1 0.9, beta2 0.999,
  * eps 1e-8, bias-corrected).
  *
@@ -263,6 +264,34 @@ int amoeba_polarization_gradient(amoeba_ctx* ctx, const double* pos, const doubl
 #define AMOEBA_GUESS_NPARAM 5123   /* 64*11 + 64 + 64*64 + 64 + 3*64 + 3 */
 #define AMOEBA_GUESS_NMODEL 5145   /* NPARAM + 2*NFEAT                   */
 
+/* Which bases the network combines (the kind is a setting of the context, kept across
+ * amoeba_guess_set_model; the default is NEUMANN):
+ *   AMOEBA_GUESS_KIND_NEUMANN  the bases above, offsets s = (1, 1, 1); needs only the
+ *                              configuration (two real-space products per guess).
+ *   AMOEBA_GUESS_KIND_DELTA    for a configuration that follows a solved one, whose converged
+ *                              dipoles mu_ref and permanent field E_ref are given by
+ *                              amoeba_guess_set_reference: v0 = mu_ref, v1 = alpha (E_perm -
+ *                              E_ref), v2 = alpha E_perm, offsets s = (1, 0, 0), so that the
+ *                              untrained network returns mu_ref (the previous-step guess); no
+ *                              real-space product.  The three radial features are zero (left
+ *                              out: the walk over the tiles costs more than the guess saves).
+ * mu0 = sum_k (s_k + y_k) v_k in both; the other features are the same functions of the bases. */
+typedef enum amoeba_guess_kind {
+    AMOEBA_GUESS_KIND_NEUMANN = 0,
+    AMOEBA_GUESS_KIND_DELTA = 1
+} amoeba_guess_kind;
+
+/* Select the kind for later features, predictions, training steps and learned starts.
+ * Unknown kind: AMOEBA_E_INVALID. */
+int amoeba_guess_set_kind(amoeba_ctx* ctx, int32_t kind);
+
+/* Reference configuration of the DELTA kind: mu_ref[N][3] (e*A) and e_ref[N][3] (e/A^2),
+ * device FP64 in caller atom order, copied into the context on its stream (the caller may
+ * reuse its arrays once the stream has passed the copy; no host wait).  Needed before any
+ * DELTA feature, prediction or learned start (else AMOEBA_E_STATE); a non-finite entry makes
+ * the call that uses it return AMOEBA_E_NUMERIC. */
+int amoeba_guess_set_reference(amoeba_ctx* ctx, const double* mu_ref, const double* e_ref);
+
 /* Load a model (host array of n_floats == AMOEBA_GUESS_NMODEL floats); resets the Adam
  * moments and step count.  The first call allocates the guess workspace. */
 int amoeba_guess_set_model(amoeba_ctx* ctx, const float* model, int64_t n_floats);
@@ -270,8 +299,24 @@ int amoeba_guess_set_model(amoeba_ctx* ctx, const float* model, int64_t n_floats
 /* Copy the current model to a host array of n_floats == AMOEBA_GUESS_NMODEL floats. */
 int amoeba_guess_get_model(amoeba_ctx* ctx, float* model, int64_t n_floats);
 
+/* Checkpoint of the learned guess: a versioned host blob holding the kind, the model, the
+ * Adam moments and the Adam step count, so that training resumes exactly where it stopped.
+ * Layout (little-endian): char magic[8] = "AMGUESS" (NUL-terminated); uint32 version
+ * (AMOEBA_GUESS_BLOB_VERSION); int32 kind; int32 NFEAT, NBASIS, HIDDEN, NPARAM, NMODEL;
+ * int32 0; int64 Adam step count; float model[NMODEL]; float adam_m[NPARAM];
+ * float adam_v[NPARAM]  (AMOEBA_GUESS_BLOB_BYTES bytes in all).
+ * amoeba_guess_save: blob NULL -> *bytes = the size needed; else *bytes must be at least
+ * that size (AMOEBA_E_INVALID otherwise) and receives the size written.  Needs a loaded model.
+ * amoeba_guess_load: a blob of another version, kind, shape or size, or with non-finite
+ * entries, is rejected (AMOEBA_E_INVALID / AMOEBA_E_NUMERIC) and leaves the context as it was. */
+#define AMOEBA_GUESS_BLOB_VERSION 1
+#define AMOEBA_GUESS_BLOB_BYTES (48 + 4 * (AMOEBA_GUESS_NMODEL + 2 * AMOEBA_GUESS_NPARAM))
+int amoeba_guess_save(amoeba_ctx* ctx, void* blob, int64_t* bytes);
+int amoeba_guess_load(amoeba_ctx* ctx, const void* blob, int64_t bytes);
+
 /* Bases and features of one configuration (positions pos, permanent field e_perm, the list
- * built): feat_out[N][NFEAT] and basis_out[N][NBASIS][3] (device FP32, caller atom order). */
+ * built; the reference set for the DELTA kind): feat_out[N][NFEAT] and basis_out[N][NBASIS][3]
+ * (device FP32, caller atom order). */
 int amoeba_guess_features(amoeba_ctx* ctx, const double* pos, const double* e_perm,
                           float* feat_out, float* basis_out);
 

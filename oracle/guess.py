@@ -18,8 +18,16 @@ Invariant features (NFEAT = 11):
     x5, x6, x7 = cos(v0, v1), cos(v0, v2), cos(v1, v2) with cos(a, b) = a.b / sqrt(|a|^2 |b|^2 + 1e-20),
     x8..x10 = sum over in-cutoff neighbours j of exp(-((r_ij - c_k) / 0.6)^2), c_k = 1, 2, 3 A.
 
+Bases of the second kind, the "delta" guess for a configuration that follows a solved one
+(mu_ref its converged dipoles, E_ref its permanent field):
+    v0 = mu_ref,   v1 = alpha (E_perm - E_ref),   v2 = alpha E_perm
+with the same invariant features computed from them, except x8..x10 (the radial sums), which
+this kind leaves at zero.
+
 Network: xh = (x - mean) * inv_std; h1 = silu(W1 xh + b1); h2 = silu(W2 h1 + b2);
-y = W3 h2 + b3; mu0 = sum_k (1 + y_k) v_k.  silu(a) = a / (1 + exp(-a)).
+y = W3 h2 + b3; mu0 = sum_k (s_k + y_k) v_k with the fixed offsets s = (1, 1, 1) for the
+Neumann bases (an untrained network returns their sum) and s = (1, 0, 0) for the delta bases
+(an untrained network returns mu_ref).  silu(a) = a / (1 + exp(-a)).
 Loss over a batch of n atoms: L = Debye^2 / n * sum_i |mu0_i - mu*_i|^2 (D^2).
 Optimiser: Adam (Kingma & Ba 2015) with beta1 = 0.9, beta2 = 0.999, eps = 1e-8 and the bias
 corrections of the published algorithm.
@@ -45,6 +53,7 @@ RADIAL_CENTERS = (1.0, 2.0, 3.0)
 RADIAL_WIDTH = 0.6
 COS_EPS = 1e-20
 ADAM_B1, ADAM_B2, ADAM_EPS = 0.9, 0.999, 1e-8
+OFFSETS = {"neumann": (1.0, 1.0, 1.0), "delta": (1.0, 0.0, 0.0)}
 
 
 # ----------------------------------------------------------------------------------------------
@@ -98,6 +107,15 @@ def bases(s, e_perm, idx=None):
     return np.stack([v0[idx], v1[idx], v2], axis=1)
 
 
+def bases_delta(s, e_perm, mu_ref, e_ref, idx=None):
+    """(mu_ref, alpha (E - E_ref), alpha E) at atoms idx (all if None), shape [n][3][3]."""
+    idx = np.arange(s.n) if idx is None else np.asarray(idx)
+    alpha = np.asarray(s.alpha, dtype=np.float64)[idx][:, None]
+    e = np.asarray(e_perm, dtype=np.float64)[idx]
+    return np.stack([np.asarray(mu_ref, dtype=np.float64)[idx],
+                     alpha * (e - np.asarray(e_ref, dtype=np.float64)[idx]), alpha * e], axis=1)
+
+
 def features_from(s, basis, radial, idx=None):
     idx = np.arange(s.n) if idx is None else np.asarray(idx)
     nrm = np.sqrt(np.sum(basis * basis, axis=2))            # [n][3]
@@ -120,6 +138,13 @@ def features(s, e_perm, idx=None):
     """(x [n][NFEAT], basis [n][3][3]) at atoms idx (all if None)."""
     b = bases(s, e_perm, idx)
     return features_from(s, b, radial_sums(s, idx), idx), b
+
+
+def features_delta(s, e_perm, mu_ref, e_ref, idx=None):
+    """(x [n][NFEAT], basis [n][3][3]) of the delta bases at atoms idx (all if None)."""
+    b = bases_delta(s, e_perm, mu_ref, e_ref, idx)
+    n = s.n if idx is None else len(idx)
+    return features_from(s, b, np.zeros((n, len(RADIAL_CENTERS))), idx), b
 
 
 # ----------------------------------------------------------------------------------------------
@@ -161,7 +186,7 @@ def _sigmoid(a):
     return 1.0 / (1.0 + np.exp(-a))
 
 
-def forward(model, x, basis, return_cache=False):
+def forward(model, x, basis, return_cache=False, offsets=OFFSETS["neumann"]):
     """mu0 [n][3] for features x [n][NFEAT] and bases [n][3][3]."""
     w = unpack(model)
     xh = (np.asarray(x, dtype=np.float64) - w["mean"]) * w["inv_std"]
@@ -170,18 +195,19 @@ def forward(model, x, basis, return_cache=False):
     a2 = h1 @ w["W2"].T + w["b2"]
     h2 = a2 * _sigmoid(a2)
     y = h2 @ w["W3"].T + w["b3"]
-    mu0 = np.sum((1.0 + y)[:, :, None] * np.asarray(basis, dtype=np.float64), axis=1)
+    mu0 = np.sum((np.asarray(offsets, dtype=np.float64) + y)[:, :, None] * np.asarray(basis, dtype=np.float64),
+                 axis=1)
     if return_cache:
         return mu0, (xh, a1, h1, a2, h2, y)
     return mu0
 
 
-def loss_grad(model, x, basis, target):
+def loss_grad(model, x, basis, target, offsets=OFFSETS["neumann"]):
     """(L, dL/dparams [NPARAM]) by backpropagation through the network above."""
     w = unpack(model)
     basis = np.asarray(basis, dtype=np.float64)
     n = x.shape[0]
-    mu0, (xh, a1, h1, a2, h2, y) = forward(model, x, basis, return_cache=True)
+    mu0, (xh, a1, h1, a2, h2, y) = forward(model, x, basis, return_cache=True, offsets=offsets)
     diff = mu0 - np.asarray(target, dtype=np.float64)
     dd = O.DEBYE ** 2
     loss = dd / n * float(np.sum(diff * diff))
@@ -200,8 +226,8 @@ def loss_grad(model, x, basis, target):
     return loss, pack(dW1, db1, dW2, db2, dW3, db3)
 
 
-def loss(model, x, basis, target):
-    mu0 = forward(model, x, basis)
+def loss(model, x, basis, target, offsets=OFFSETS["neumann"]):
+    mu0 = forward(model, x, basis, offsets=offsets)
     return O.DEBYE ** 2 / x.shape[0] * float(np.sum((mu0 - np.asarray(target)) ** 2))
 
 

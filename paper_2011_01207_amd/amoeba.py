@@ -47,6 +47,9 @@ GUESS_NBASIS = 3
 GUESS_HIDDEN = 64
 GUESS_NPARAM = 5123
 GUESS_NMODEL = 5145
+GUESS_KINDS = {"neumann": 0, "delta": 1}
+GUESS_BLOB_VERSION = 1
+GUESS_BLOB_BYTES = 48 + 4 * (GUESS_NMODEL + 2 * GUESS_NPARAM)
 N_STAGES = 8
 
 
@@ -116,6 +119,10 @@ def lib() -> ctypes.CDLL:
         L.amoeba_guess_train_step.argtypes = [_P, _P, _P, _P, ctypes.c_int64, _P, ctypes.c_int64, ctypes.c_float,
                                               ctypes.POINTER(ctypes.c_double)]
         L.amoeba_guess_predict.argtypes = [_P, _P, _P, _P]
+        L.amoeba_guess_set_kind.argtypes = [_P, ctypes.c_int32]
+        L.amoeba_guess_set_reference.argtypes = [_P, _P, _P]
+        L.amoeba_guess_save.argtypes = [_P, _P, ctypes.POINTER(ctypes.c_int64)]
+        L.amoeba_guess_load.argtypes = [_P, _P, ctypes.c_int64]
         L.amoeba_set_pme_path.argtypes = [_P, ctypes.c_int32]
         L.amoeba_set_pair_store.argtypes = [_P, ctypes.c_int32]
         L.amoeba_set_graphs.argtypes = [_P, ctypes.c_int32]
@@ -165,6 +172,7 @@ class Context:
         self.h = h
         self.n = int(n_atoms)
         self.params = p
+        self.guess_kind = "neumann"    # mirrors the context's learned-guess kind
 
     def _check(self, st, ok=(AMOEBA_OK,)):
         if st not in ok:
@@ -295,6 +303,33 @@ class Context:
         m = np.empty(GUESS_NMODEL, dtype=np.float32)
         self._check(lib().amoeba_guess_get_model(self.h, m.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), m.size))
         return m
+
+    def guess_set_kind(self, kind):
+        """'neumann' (bases from two real-space products) or 'delta' (previous-configuration
+        reference, no product)."""
+        self._check(lib().amoeba_guess_set_kind(self.h, GUESS_KINDS[kind]))
+        self.guess_kind = kind
+
+    def guess_set_reference(self, mu_ref, e_ref):
+        """Converged dipoles and permanent field of the previous configuration (device FP64,
+        caller order), copied into the context for the delta kind."""
+        n = self.n
+        return self._check(lib().amoeba_guess_set_reference(
+            self.h, _ptr(mu_ref, torch.float64, (n, 3), "mu_ref"), _ptr(e_ref, torch.float64, (n, 3), "e_ref")))
+
+    def guess_save(self) -> bytes:
+        """Versioned checkpoint (kind, model, Adam moments and step count) as bytes."""
+        size = ctypes.c_int64(0)
+        self._check(lib().amoeba_guess_save(self.h, None, ctypes.byref(size)))
+        buf = ctypes.create_string_buffer(size.value)
+        self._check(lib().amoeba_guess_save(self.h, ctypes.cast(buf, ctypes.c_void_p), ctypes.byref(size)))
+        return buf.raw[:size.value]
+
+    def guess_load(self, blob: bytes):
+        buf = ctypes.create_string_buffer(bytes(blob), len(blob))
+        self._check(lib().amoeba_guess_load(self.h, ctypes.cast(buf, ctypes.c_void_p), len(blob)))
+        kind = int.from_bytes(bytes(blob)[12:16], "little", signed=True)
+        self.guess_kind = {v: k for k, v in GUESS_KINDS.items()}[kind]
 
     def guess_features(self, pos, e_perm, feat=None, basis=None):
         """(feat [N][NFEAT], basis [N][NBASIS][3]) FP32 on the device, caller order."""

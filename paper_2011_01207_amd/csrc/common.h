@@ -285,6 +285,9 @@ struct amoeba_ctx {
     float* g_basis = nullptr;              // [npad][NBASIS*3]
     double* g_save_mu = nullptr;           // [npad*3] fallback guess kept while the starts are compared
     double* g_save_q = nullptr;            // [npad*3] its A mu0
+    int g_kind = AMOEBA_GUESS_KIND_NEUMANN; // which bases the network combines
+    double* g_ref = nullptr;               // [2][n*3] reference dipoles and field (caller order)
+    bool g_ref_set = false;
     int last_guess = 0;
     double last_guess_rms[2] = {0.0, 0.0};
 

@@ -7,7 +7,13 @@
 // and c the Ewald self coefficient.  Invariant features: alpha, Thole a, |v_k| in Debye, the
 // three cosines between the bases, and three Gaussian-weighted neighbour counts over the
 // in-cutoff pairs of the tile list.  Network: SiLU MLP NFEAT -> 64 -> 64 -> NBASIS on the
-// vector ALU in FP32, mu0 = sum_k (1 + y_k) v_k.
+// vector ALU in FP32, mu0 = sum_k (s_k + y_k) v_k with s = (1, 1, 1).
+//
+// Delta kind, for a configuration that follows a solved one (converged dipoles mu_ref and
+// permanent field E_ref of that one, held by the context in caller order): v0 = mu_ref,
+// v1 = alpha (E_perm - E_ref), v2 = alpha E_perm, s = (1, 0, 0), the radial sums left out (zero).
+// The untrained network returns mu_ref, the previous-step guess; trained, it adds the local
+// response to the change of the permanent field, with no real-space product and no tile walk.
 //
 // Weights are read at addresses that are the same for every lane, so they come through the
 // scalar unit and stay in the scalar cache; activations live in vector registers.  Training
@@ -15,6 +21,7 @@
 // the workgroups in index order, so gradients, losses and updates are bitwise reproducible.
 #include <algorithm>
 #include <cmath>
+#include <vector>
 
 #include "common.h"
 #include "reduce.h"
@@ -47,6 +54,11 @@ constexpr int kOffInv = kNP + kNF;
 static_assert(kOffB3 + kNB == kNP, "parameter layout");
 static_assert(kNP + 2 * kNF == kNM, "model layout");
 constexpr int kGuessWG = 512;          // workgroups of the gradient kernel (at most)
+
+// fixed offsets s_k of mu0 = sum_k (s_k + y_k) v_k
+struct GuessOffsets {
+    float s[kNB];
+};
 constexpr float kRadialC[3] = {1.0f, 2.0f, 3.0f};
 constexpr float kRadialInvW = 1.0f / 0.6f;
 
@@ -171,6 +183,24 @@ __global__ void k_guess_basis(int npad, const double4* __restrict__ par, const d
     pv[s] = Cast4G<R4T>::make(v[0], v[1], v[2]);
 }
 
+// delta bases: on entry v1 holds E_ref and v0 mu_ref in slot order (e the permanent field);
+// v1 = alpha (e - E_ref), v2 = alpha e
+__global__ void k_guess_delta_bases(int npad, const double4* __restrict__ par, const double* __restrict__ e,
+                                    double* __restrict__ v1, double* __restrict__ v2)
+{
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= npad)
+        return;
+    const double al = par[s].x;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const size_t i = 3 * (size_t)s + c;
+        const double x = e[i];
+        v1[i] = al * (x - v1[i]);
+        v2[i] = al * x;
+    }
+}
+
 // features and FP32 bases of every real atom, written at its slot (perm_out NULL) or at its
 // caller index (perm_out = perm); phantom slots get zeros in slot order
 __global__ void k_guess_features(int npad, const int* __restrict__ perm, const double4* __restrict__ par,
@@ -219,7 +249,7 @@ __global__ void k_guess_features(int npad, const int* __restrict__ perm, const d
     }
 #pragma unroll
     for (int c = 0; c < 3; ++c)
-        x[8 + c] = (float)radial[3 * (size_t)s + c];
+        x[8 + c] = radial ? (float)radial[3 * (size_t)s + c] : 0.0f;
 }
 
 // ------------------------------------------------------------------------------------------
@@ -256,8 +286,9 @@ __device__ __forceinline__ float mlp_unit2(const float* __restrict__ w, int k, c
 
 __global__ __launch_bounds__(256) void k_guess_forward(int64_t n, const float* __restrict__ w,
                                                        const float* __restrict__ feat,
-                                                       const float* __restrict__ basis, const int* __restrict__ perm,
-                                                       double* __restrict__ out64, float* __restrict__ out32)
+                                                       const float* __restrict__ basis, GuessOffsets so,
+                                                       const int* __restrict__ perm, double* __restrict__ out64,
+                                                       float* __restrict__ out32)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n)
@@ -288,7 +319,7 @@ __global__ __launch_bounds__(256) void k_guess_forward(int64_t n, const float* _
     for (int k = 0; k < kNB; ++k)
 #pragma unroll
         for (int c = 0; c < 3; ++c)
-            mu[c] = fmaf(1.0f + y[k], basis[i * kNB * 3 + k * 3 + c], mu[c]);
+            mu[c] = fmaf(so.s[k] + y[k], basis[i * kNB * 3 + k * 3 + c], mu[c]);
     if (out64) {
 #pragma unroll
         for (int c = 0; c < 3; ++c)
@@ -311,7 +342,7 @@ constexpr int kRow = kH + 4;     // LDS row stride of the per-sample activations
 
 __global__ __launch_bounds__(64) void k_guess_grad(int64_t n_batch, int64_t n_rows, const int* __restrict__ idx,
                                                    const float* __restrict__ w, const float* __restrict__ feat,
-                                                   const float* __restrict__ basis,
+                                                   const float* __restrict__ basis, GuessOffsets so,
                                                    const float* __restrict__ target, float lscale,
                                                    float* __restrict__ part, double* __restrict__ lossp,
                                                    int* __restrict__ flags)
@@ -399,7 +430,7 @@ __global__ __launch_bounds__(64) void k_guess_grad(int64_t n_batch, int64_t n_ro
             float m = 0.f;
 #pragma unroll
             for (int k = 0; k < kNB; ++k)
-                m = fmaf(1.0f + y[k], v[k][c], m);
+                m = fmaf(so.s[k] + y[k], v[k][c], m);
             const float dlt = m - tg[c];
             l = fmaf(dlt, dlt, l);
             gmu[c] = 2.0f * lscale * dlt;
@@ -595,16 +626,35 @@ static int guess_alloc_config(amoeba_ctx* c)
     return AMOEBA_OK;
 }
 
+static GuessOffsets guess_offsets(const amoeba_ctx* c)
+{
+    if (c->g_kind == AMOEBA_GUESS_KIND_DELTA)
+        return GuessOffsets{{1.0f, 0.0f, 0.0f}};
+    return GuessOffsets{{1.0f, 1.0f, 1.0f}};
+}
+
 // Bases and features of the configuration whose permanent field is in v_e (slot order).
 int guess_compute(amoeba_ctx* c)
 {
+    if (c->g_kind == AMOEBA_GUESS_KIND_DELTA && !c->g_ref_set)
+        return set_error(c, AMOEBA_E_STATE, "learned guess of the delta kind: no reference configuration "
+                                            "(amoeba_guess_set_reference)");
     int rc = guess_alloc_config(c);
     if (rc)
         return rc;
     const size_t n3 = 3 * (size_t)c->npad;
     const double cself = 4.0 * pow(c->prm.ewald_alpha, 3) / (3.0 * sqrt(kPi));
     const int g = nblk64(c->npad, 256);
-    for (int k = 0; k < kNB; ++k) {
+    if (c->g_kind == AMOEBA_GUESS_KIND_DELTA) {
+        const size_t na3 = 3 * (size_t)c->n;
+        // non-finite reference entries raise the flag read with the caller's next flag read
+        launch_gather_vec_checked(c, c->g_ref, c->g_v);
+        launch_gather_vec_checked(c, c->g_ref + na3, c->g_v + n3);
+        StageTimer tm(c, AMOEBA_T_GUESS);
+        hipLaunchKernelGGL(k_guess_delta_bases, dim3(g), dim3(256), 0, c->stream, c->npad, c->par_d, c->v_e,
+                           c->g_v + n3, c->g_v + 2 * n3);
+    }
+    for (int k = 0; k < kNB && c->g_kind == AMOEBA_GUESS_KIND_NEUMANN; ++k) {
         const double* prev = k ? c->g_v + (k - 1) * n3 : c->v_e;
         const double* er = k ? c->ereal : nullptr;
         {
@@ -621,22 +671,27 @@ int guess_compute(amoeba_ctx* c)
             launch_real_reduce(c, c->ereal);
         }
     }
-    {
-        StageTimer tm(c, AMOEBA_T_GUESS);
-        if (c->ntiles > 0) {
-            if (c->mixed)
-                launch_radial<float>(c, (float*)c->jbuf, c->jrel_f, c->off_f);
-            else
-                launch_radial<double>(c, (double*)c->jbuf, c->jrel_d, c->off_d);
+    // the radial sums (a walk over every tile) only for the Neumann kind; the delta kind's
+    // features leave them out (zero)
+    const bool radial = c->g_kind == AMOEBA_GUESS_KIND_NEUMANN;
+    if (radial) {
+        {
+            StageTimer tm(c, AMOEBA_T_GUESS);
+            if (c->ntiles > 0) {
+                if (c->mixed)
+                    launch_radial<float>(c, (float*)c->jbuf, c->jrel_f, c->off_f);
+                else
+                    launch_radial<double>(c, (double*)c->jbuf, c->jrel_d, c->off_d);
+            }
         }
+        if (c->ntiles > 0)
+            launch_real_reduce(c, c->g_radial);
+        else
+            hipMemsetAsync(c->g_radial, 0, sizeof(double) * n3, c->stream);
     }
-    if (c->ntiles > 0)
-        launch_real_reduce(c, c->g_radial);
-    else
-        hipMemsetAsync(c->g_radial, 0, sizeof(double) * n3, c->stream);
     StageTimer tm(c, AMOEBA_T_GUESS);
     hipLaunchKernelGGL(k_guess_features, dim3(g), dim3(256), 0, c->stream, c->npad, c->perm, c->par_d, c->g_v,
-                       c->g_radial, 0, c->g_feat, c->g_basis);
+                       radial ? c->g_radial : nullptr, 0, c->g_feat, c->g_basis);
     return AMOEBA_OK;
 }
 
@@ -645,7 +700,7 @@ void guess_forward_slot(amoeba_ctx* c, double* mu_slot)
 {
     StageTimer tm(c, AMOEBA_T_GUESS);
     hipLaunchKernelGGL(k_guess_forward, dim3(nblk64(c->npad, 256)), dim3(256), 0, c->stream, (int64_t)c->npad,
-                       c->g_model, c->g_feat, c->g_basis, c->perm, mu_slot, (float*)nullptr);
+                       c->g_model, c->g_feat, c->g_basis, guess_offsets(c), c->perm, mu_slot, (float*)nullptr);
 }
 
 static int guess_alloc_model(amoeba_ctx* c)
@@ -666,6 +721,18 @@ static int guess_alloc_model(amoeba_ctx* c)
         c->g_scal_host = nullptr;
         return set_error(c, AMOEBA_E_NOMEM, "pinned host allocation failed");
     }
+    return AMOEBA_OK;
+}
+
+// end of a features / predict call: the flag word (cleared by the e_perm check) reports a
+// non-finite reference of the delta kind
+static int guess_flags(amoeba_ctx* c, const char* who)
+{
+    int f = 0, rc = read_flags(c, &f);
+    if (rc)
+        return rc;
+    if (f & kFlagNonFinite)
+        return set_error(c, AMOEBA_E_NUMERIC, std::string(who) + ": non-finite value in the guess reference");
     return AMOEBA_OK;
 }
 
@@ -701,7 +768,7 @@ static int guess_grad(amoeba_ctx* c, const float* feat, const float* basis, cons
         StageTimer tm(c, AMOEBA_T_GUESS);
         const float lscale = (float)(kDebye * kDebye / (double)n_batch);
         hipLaunchKernelGGL(k_guess_grad, dim3(nwg), dim3(64), 0, st, n_batch, n_rows, idx, c->g_model, feat, basis,
-                           target, lscale, c->g_part, c->g_lossp, c->flags);
+                           guess_offsets(c), target, lscale, c->g_part, c->g_lossp, c->flags);
         hipLaunchKernelGGL(k_guess_reduce, dim3((kNP + 63) / 64), dim3(256), 0, st, nwg, c->g_part, c->g_lossp,
                            grad_out, c->g_model, c->g_adam_m, c->g_adam_v, adam ? 1 : 0, lr, bc1, bc2, c->g_scal,
                            c->flags);
@@ -764,6 +831,135 @@ int amoeba_guess_get_model(amoeba_ctx* c, float* model, int64_t n_floats)
     return hip_check(c, hipStreamSynchronize(c->stream), "amoeba_guess_get_model");
 }
 
+int amoeba_guess_set_kind(amoeba_ctx* c, int32_t kind)
+{
+    if (!c)
+        return AMOEBA_E_INVALID;
+    c->err.clear();
+    if (kind != AMOEBA_GUESS_KIND_NEUMANN && kind != AMOEBA_GUESS_KIND_DELTA)
+        return set_error(c, AMOEBA_E_INVALID, "amoeba_guess_set_kind: unknown kind");
+    c->g_kind = kind;
+    return AMOEBA_OK;
+}
+
+int amoeba_guess_set_reference(amoeba_ctx* c, const double* mu_ref, const double* e_ref)
+{
+    if (!c)
+        return AMOEBA_E_INVALID;
+    c->err.clear();
+    if (!mu_ref || !e_ref)
+        return set_error(c, AMOEBA_E_INVALID, "amoeba_guess_set_reference: NULL argument");
+    const size_t n3 = 3 * (size_t)c->n;
+    int rc;
+    if (!c->g_ref && (rc = ctx_alloc(c, (void**)&c->g_ref, sizeof(double) * 2 * n3)))
+        return rc;
+    // copied on the stream, no host wait; the entries are checked for NaN/Inf where they are
+    // used (AMOEBA_E_NUMERIC from that call)
+    hipMemcpyAsync(c->g_ref, mu_ref, sizeof(double) * n3, hipMemcpyDeviceToDevice, c->stream);
+    hipMemcpyAsync(c->g_ref + n3, e_ref, sizeof(double) * n3, hipMemcpyDeviceToDevice, c->stream);
+    c->g_ref_set = true;
+    return AMOEBA_OK;
+}
+
+// Checkpoint blob: header (48 bytes), model, Adam moments.
+namespace {
+struct GuessBlobHeader {
+    char magic[8];
+    uint32_t version;
+    int32_t kind;
+    int32_t nfeat, nbasis, hidden, nparam, nmodel, zero;
+    int64_t step;
+};
+static_assert(sizeof(GuessBlobHeader) == 48, "blob header layout");
+constexpr char kBlobMagic[8] = {'A', 'M', 'G', 'U', 'E', 'S', 'S', 0};
+constexpr int64_t kBlobBytes = AMOEBA_GUESS_BLOB_BYTES;
+static_assert(kBlobBytes == (int64_t)sizeof(GuessBlobHeader) + 4 * (kNM + 2 * kNP), "blob size");
+}  // namespace
+
+int amoeba_guess_save(amoeba_ctx* c, void* blob, int64_t* bytes)
+{
+    if (!c)
+        return AMOEBA_E_INVALID;
+    c->err.clear();
+    if (!bytes)
+        return set_error(c, AMOEBA_E_INVALID, "amoeba_guess_save: NULL bytes");
+    if (!blob) {
+        *bytes = kBlobBytes;
+        return AMOEBA_OK;
+    }
+    if (*bytes < kBlobBytes)
+        return set_error(c, AMOEBA_E_INVALID, "amoeba_guess_save: blob smaller than AMOEBA_GUESS_BLOB_BYTES");
+    int rc = guess_ready(c, "amoeba_guess_save");
+    if (rc)
+        return rc;
+    GuessBlobHeader h;
+    std::copy(kBlobMagic, kBlobMagic + 8, h.magic);
+    h.version = AMOEBA_GUESS_BLOB_VERSION;
+    h.kind = c->g_kind;
+    h.nfeat = kNF;
+    h.nbasis = kNB;
+    h.hidden = kH;
+    h.nparam = kNP;
+    h.nmodel = kNM;
+    h.zero = 0;
+    h.step = c->g_step;
+    char* out = static_cast<char*>(blob);
+    std::copy(reinterpret_cast<const char*>(&h), reinterpret_cast<const char*>(&h) + sizeof(h), out);
+    float* f = reinterpret_cast<float*>(out + sizeof(h));
+    hipStream_t st = c->stream;
+    hipMemcpyAsync(f, c->g_model, sizeof(float) * kNM, hipMemcpyDeviceToHost, st);
+    hipMemcpyAsync(f + kNM, c->g_adam_m, sizeof(float) * kNP, hipMemcpyDeviceToHost, st);
+    hipMemcpyAsync(f + kNM + kNP, c->g_adam_v, sizeof(float) * kNP, hipMemcpyDeviceToHost, st);
+    if ((rc = hip_check(c, hipStreamSynchronize(st), "amoeba_guess_save")))
+        return rc;
+    *bytes = kBlobBytes;
+    return AMOEBA_OK;
+}
+
+int amoeba_guess_load(amoeba_ctx* c, const void* blob, int64_t bytes)
+{
+    if (!c)
+        return AMOEBA_E_INVALID;
+    c->err.clear();
+    if (!blob || bytes != kBlobBytes)
+        return set_error(c, AMOEBA_E_INVALID, "amoeba_guess_load: need a blob of AMOEBA_GUESS_BLOB_BYTES bytes");
+    GuessBlobHeader h;
+    const char* in = static_cast<const char*>(blob);
+    std::copy(in, in + sizeof(h), reinterpret_cast<char*>(&h));
+    if (!std::equal(kBlobMagic, kBlobMagic + 8, h.magic))
+        return set_error(c, AMOEBA_E_INVALID, "amoeba_guess_load: not a learned-guess checkpoint");
+    if (h.version != AMOEBA_GUESS_BLOB_VERSION)
+        return set_error(c, AMOEBA_E_INVALID, "amoeba_guess_load: unsupported checkpoint version");
+    if (h.nfeat != kNF || h.nbasis != kNB || h.hidden != kH || h.nparam != kNP || h.nmodel != kNM || h.zero != 0)
+        return set_error(c, AMOEBA_E_INVALID, "amoeba_guess_load: network shape differs from this library's");
+    if (h.kind != AMOEBA_GUESS_KIND_NEUMANN && h.kind != AMOEBA_GUESS_KIND_DELTA)
+        return set_error(c, AMOEBA_E_INVALID, "amoeba_guess_load: unknown kind");
+    if (h.step < 0)
+        return set_error(c, AMOEBA_E_INVALID, "amoeba_guess_load: negative step count");
+    // the payload may be unaligned in the caller's buffer: copy it out before use
+    std::vector<float> f(kNM + 2 * kNP);
+    std::copy(in + sizeof(h), in + kBlobBytes, reinterpret_cast<char*>(f.data()));
+    for (float x : f)
+        if (!std::isfinite(x))
+            return set_error(c, AMOEBA_E_NUMERIC, "amoeba_guess_load: non-finite entry");
+    for (int i = 0; i < kNP; ++i)
+        if (f[kNM + kNP + i] < 0.0f)
+            return set_error(c, AMOEBA_E_INVALID, "amoeba_guess_load: negative Adam second moment");
+    int rc = guess_alloc_model(c);
+    if (rc)
+        return rc;
+    hipStream_t st = c->stream;
+    hipMemcpyAsync(c->g_model, f.data(), sizeof(float) * kNM, hipMemcpyHostToDevice, st);
+    hipMemcpyAsync(c->g_adam_m, f.data() + kNM, sizeof(float) * kNP, hipMemcpyHostToDevice, st);
+    hipMemcpyAsync(c->g_adam_v, f.data() + kNM + kNP, sizeof(float) * kNP, hipMemcpyHostToDevice, st);
+    if ((rc = hip_check(c, hipStreamSynchronize(st), "amoeba_guess_load")))
+        return rc;
+    c->g_step = h.step;
+    c->g_kind = h.kind;
+    c->guess_loaded = true;
+    return AMOEBA_OK;
+}
+
 int amoeba_guess_features(amoeba_ctx* c, const double* pos, const double* e_perm, float* feat_out, float* basis_out)
 {
     if (!c)
@@ -782,9 +978,10 @@ int amoeba_guess_features(amoeba_ctx* c, const double* pos, const double* e_perm
     {
         StageTimer tm(c, AMOEBA_T_GUESS);
         hipLaunchKernelGGL(k_guess_features, dim3(nblk64(c->npad, 256)), dim3(256), 0, c->stream, c->npad, c->perm,
-                           c->par_d, c->g_v, c->g_radial, 1, feat_out, basis_out);
+                           c->par_d, c->g_v, c->g_kind == AMOEBA_GUESS_KIND_NEUMANN ? c->g_radial : nullptr, 1,
+                           feat_out, basis_out);
     }
-    return hip_check(c, hipStreamSynchronize(c->stream), "amoeba_guess_features");
+    return guess_flags(c, "amoeba_guess_features");
 }
 
 int amoeba_guess_fit_norm(amoeba_ctx* c, const float* feat, int64_t n_rows)
@@ -822,7 +1019,7 @@ int amoeba_guess_forward(amoeba_ctx* c, const float* feat, const float* basis, i
     {
         StageTimer tm(c, AMOEBA_T_GUESS);
         hipLaunchKernelGGL(k_guess_forward, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, n,
-                           c->g_model, feat, basis, (const int*)nullptr, (double*)nullptr, mu_out);
+                           c->g_model, feat, basis, guess_offsets(c), (const int*)nullptr, (double*)nullptr, mu_out);
     }
     return hip_check(c, hipStreamSynchronize(c->stream), "amoeba_guess_forward");
 }
@@ -874,7 +1071,7 @@ int amoeba_guess_predict(amoeba_ctx* c, const double* pos, const double* e_perm,
         return rc;
     guess_forward_slot(c, c->v_q);
     launch_scatter(c, c->v_q, mu0_out);
-    return hip_check(c, hipStreamSynchronize(c->stream), "amoeba_guess_predict");
+    return guess_flags(c, "amoeba_guess_predict");
 }
 
 }  // extern "C"

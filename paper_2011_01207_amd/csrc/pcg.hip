@@ -502,7 +502,7 @@ static int read_scalars(amoeba_ctx* c, PcgScalars* out)
     int f = 0;
     int rc = read_state(c, out, &f);
     if (!rc && (f & kFlagNonFinite))
-        return set_error(c, AMOEBA_E_NUMERIC, "non-finite value in e_perm or mu_guess");
+        return set_error(c, AMOEBA_E_NUMERIC, "non-finite value in e_perm, mu_guess or the guess reference");
     return rc;
 }
 
@@ -596,7 +596,7 @@ int pcg_run(amoeba_ctx* c, int max_iter, int start_matvecs, double* mu_out, doub
         if ((rc = read_state(c, &s, &f)))
             return rc;
         if (f & kFlagNonFinite)
-            return set_error(c, AMOEBA_E_NUMERIC, "non-finite value in e_perm or mu_guess");
+            return set_error(c, AMOEBA_E_NUMERIC, "non-finite value in e_perm, mu_guess or the guess reference");
         if (f & kFlagOverflow)
             return set_error(c, AMOEBA_E_OVERFLOW,
                              "amoeba_polarize: field outside the exact fixed-point range (|E| >= 8192 e/A^2)");
@@ -615,7 +615,7 @@ int pcg_run(amoeba_ctx* c, int max_iter, int start_matvecs, double* mu_out, doub
         if ((rc = read_state(c, &s, &fl)))
             return rc;
         if (fl & kFlagNonFinite)
-            return set_error(c, AMOEBA_E_NUMERIC, "non-finite value in e_perm or mu_guess");
+            return set_error(c, AMOEBA_E_NUMERIC, "non-finite value in e_perm, mu_guess or the guess reference");
         return set_error(c, AMOEBA_E_NUMERIC, "PCG breakdown (non-positive curvature or non-finite residual)");
     }
     c->last_iters = used;

@@ -28,11 +28,13 @@ def random_batch(rng, n=7):
     return x, b, t
 
 
-def test_gradient_matches_central_differences():
+@pytest.mark.parametrize("kind", ["neumann", "delta"])
+def test_gradient_matches_central_differences(kind):
     rng = np.random.default_rng(21)
     model = random_model(rng)
     x, b, t = random_batch(rng)
-    _, g = G.loss_grad(model, x, b, t)
+    off = G.OFFSETS[kind]
+    _, g = G.loss_grad(model, x, b, t, offsets=off)
     h = 1e-6
     num = np.empty(G.NPARAM)
     for k in range(G.NPARAM):
@@ -40,7 +42,7 @@ def test_gradient_matches_central_differences():
         mm = model.copy()
         mp[k] += h
         mm[k] -= h
-        num[k] = (G.loss(mp, x, b, t) - G.loss(mm, x, b, t)) / (2 * h)
+        num[k] = (G.loss(mp, x, b, t, offsets=off) - G.loss(mm, x, b, t, offsets=off)) / (2 * h)
     rel = np.linalg.norm(g - num) / np.linalg.norm(num)
     assert rel < 1e-6, rel
     # every block of the parameter vector carries gradient (no dead branch)
@@ -70,6 +72,38 @@ def test_untrained_network_returns_sum_of_bases():
     rng = np.random.default_rng(4)
     x, b, _ = random_batch(rng)
     assert np.allclose(G.forward(model, x, b), b.sum(axis=1), atol=0, rtol=1e-15)
+
+
+def test_untrained_delta_network_returns_the_reference():
+    """With the delta offsets (1, 0, 0) and a zero last layer, mu0 is the first basis, the
+    reference dipoles, exactly."""
+    model = synth.guess_init_model(seed=7).astype(np.float64)
+    rng = np.random.default_rng(14)
+    x, b, _ = random_batch(rng)
+    assert np.array_equal(G.forward(model, x, b, offsets=G.OFFSETS["delta"]), b[:, 0])
+
+
+def test_delta_bases_special_cases():
+    """The delta bases are (mu_ref, alpha (E - E_ref), alpha E): the second vanishes when the
+    configuration's field equals the reference's, and the first is mu_ref whatever the field."""
+    s = synth.tiny_cell(6, 12.0, seed=134, min_dist=1.0)
+    rng = np.random.default_rng(15)
+    e = rng.standard_normal((s.n, 3)) * 0.05
+    mu_ref = rng.standard_normal((s.n, 3)) * 0.02
+    b = G.bases_delta(s, e, mu_ref, e)
+    assert np.array_equal(b[:, 0], mu_ref) and np.all(b[:, 1] == 0.0)
+    for i in range(s.n):
+        for c in range(3):
+            assert b[i, 2, c] == s.alpha[i] * e[i, c]
+    e_ref = e + rng.standard_normal((s.n, 3)) * 0.01
+    b2 = G.bases_delta(s, e, mu_ref, e_ref)
+    assert np.allclose(b2[:, 1], s.alpha[:, None] * (e - e_ref), rtol=1e-15, atol=0)
+    # the cosine of the second and third basis is that of (E - E_ref) and E: alpha drops out
+    x, _ = G.features_delta(s, e, mu_ref, e_ref)
+    d = e - e_ref
+    cos = np.sum(d * e, axis=1) / np.linalg.norm(d, axis=1) / np.linalg.norm(e, axis=1)
+    assert np.allclose(x[:, 7], cos, rtol=1e-12)
+    assert np.all(x[:, 8:] == 0.0)      # the delta kind leaves the radial sums out
 
 
 def test_constant_last_layer():
@@ -198,6 +232,13 @@ def test_features_rotation_and_permutation_symmetry():
     xp, bp = G.features(sp, e[perm])
     assert np.allclose(xp, x[perm], rtol=1e-12, atol=1e-14)
     assert np.allclose(bp, b[perm], rtol=1e-12, atol=1e-16)
+    # the delta bases and features: invariant and equivariant in the same way
+    mu_ref = rng.standard_normal((s.n, 3)) * 0.02
+    e_ref = e + rng.standard_normal((s.n, 3)) * 0.01
+    xd, bd = G.features_delta(s, e, mu_ref, e_ref)
+    xdr, bdr = G.features_delta(sr, e @ rot.T, mu_ref @ rot.T, e_ref @ rot.T)
+    assert np.allclose(xdr, xd, rtol=1e-11, atol=1e-12)
+    assert np.allclose(bdr, bd @ rot.T, rtol=1e-11, atol=1e-14)
 
 
 def test_sampled_features_equal_full():
