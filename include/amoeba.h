@@ -334,6 +334,19 @@ int amoeba_guess_gradient(amoeba_ctx* ctx, const float* feat, const float* basis
                           const float* target, int64_t n_rows, const int32_t* idx, int64_t n_batch,
                           float* grad_out, double* loss_out);
 
+/* amoeba_guess_gradient for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same kernels and the same
+ * result, bitwise, but the per-workgroup partials, the loss and the flag word live in a
+ * library-owned static device array of about 2.5 MiB per GPU (held from the first
+ * amoeba_create on that GPU until the process ends) instead of context memory; no allocation,
+ * no memset node.  n_batch at most AMOEBA_GUESS_NOALLOC_MAX_BATCH, else AMOEBA_E_INVALID.
+ * Every call on a GPU shares that GPU's array: calls that overlap on one GPU (several host
+ * threads, several streams) race, so the caller serialises them.  Needs a loaded model. */
+#define AMOEBA_GUESS_NOALLOC_MAX_BATCH 8192
+int amoeba_guess_gradient_noalloc(amoeba_ctx* ctx, const float* feat, const float* basis,
+                                  const float* target, int64_t n_rows, const int32_t* idx,
+                                  int64_t n_batch, float* grad_out, double* loss_out);
+
 /* One Adam step with learning rate lr on a batch; *loss_out (host, may be NULL) is the batch
  * loss before the step. */
 int amoeba_guess_train_step(amoeba_ctx* ctx, const float* feat, const float* basis,

@@ -50,6 +50,7 @@ GUESS_NMODEL = 5145
 GUESS_KINDS = {"neumann": 0, "delta": 1}
 GUESS_BLOB_VERSION = 1
 GUESS_BLOB_BYTES = 48 + 4 * (GUESS_NMODEL + 2 * GUESS_NPARAM)
+GUESS_NOALLOC_MAX_BATCH = 8192
 N_STAGES = 8
 
 
@@ -119,6 +120,8 @@ def lib() -> ctypes.CDLL:
         L.amoeba_guess_train_step.argtypes = [_P, _P, _P, _P, ctypes.c_int64, _P, ctypes.c_int64, ctypes.c_float,
                                               ctypes.POINTER(ctypes.c_double)]
         L.amoeba_guess_predict.argtypes = [_P, _P, _P, _P]
+        L.amoeba_guess_gradient_noalloc.argtypes = [_P, _P, _P, _P, ctypes.c_int64, _P, ctypes.c_int64, _P,
+                                                     ctypes.POINTER(ctypes.c_double)]
         L.amoeba_guess_set_kind.argtypes = [_P, ctypes.c_int32]
         L.amoeba_guess_set_reference.argtypes = [_P, _P, _P]
         L.amoeba_guess_save.argtypes = [_P, _P, ctypes.POINTER(ctypes.c_int64)]
@@ -374,6 +377,16 @@ class Context:
         loss = ctypes.c_double(0.0)
         self._check(lib().amoeba_guess_gradient(self.h, *self._batch_args(feat, basis, target, idx, n_batch),
                                                 g.data_ptr(), ctypes.byref(loss)))
+        return loss.value, g
+
+    def guess_gradient_noalloc(self, feat, basis, target, idx=None, n_batch=None, out=None):
+        """guess_gradient through the entry point that allocates nothing (library scratch); the
+        caller passes the gradient tensor (FP32 [NPARAM] on the device) to stay allocation-free."""
+        g = torch.empty(GUESS_NPARAM, dtype=torch.float32, device=feat.device) if out is None else out
+        loss = ctypes.c_double(0.0)
+        self._check(lib().amoeba_guess_gradient_noalloc(
+            self.h, *self._batch_args(feat, basis, target, idx, n_batch),
+            _ptr(g, torch.float32, (GUESS_NPARAM,), "grad_out"), ctypes.byref(loss)))
         return loss.value, g
 
     def guess_train_step(self, feat, basis, target, lr, idx=None, n_batch=None):

@@ -363,7 +363,7 @@ int amoeba_create(const amoeba_params* p, void* hip_stream, amoeba_ctx** out)
             rc = set_error(c, AMOEBA_E_DEVICE, "hipEventCreate failed");
             break;
         }
-        if ((rc = pme_setup(c)))
+        if ((rc = pme_setup(c)) || (rc = guess_scratch_init(c)))
             break;
         rc = hip_check(c, hipStreamSynchronize(c->stream), "amoeba_create");
     } while (false);

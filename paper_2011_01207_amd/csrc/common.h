@@ -285,6 +285,7 @@ struct amoeba_ctx {
     float* g_basis = nullptr;              // [npad][NBASIS*3]
     double* g_save_mu = nullptr;           // [npad*3] fallback guess kept while the starts are compared
     double* g_save_q = nullptr;            // [npad*3] its A mu0
+    void* g_scratch = nullptr;             // this device's address of the no-allocation scratch array
     int g_kind = AMOEBA_GUESS_KIND_NEUMANN; // which bases the network combines
     double* g_ref = nullptr;               // [2][n*3] reference dipoles and field (caller order)
     bool g_ref_set = false;
@@ -366,6 +367,7 @@ int begin_config(amoeba_ctx* c, const double* pos, const char* who);
 
 // guess.hip
 int guess_compute(amoeba_ctx* c);                     // bases + features of v_e (slot order)
+int guess_scratch_init(amoeba_ctx* c);                // device address of the no-allocation scratch
 void guess_forward_slot(amoeba_ctx* c, double* mu_slot);
 
 // pcg.hip

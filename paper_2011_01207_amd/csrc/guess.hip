@@ -21,6 +21,8 @@
 // the workgroups in index order, so gradients, losses and updates are bitwise reproducible.
 #include <algorithm>
 #include <cmath>
+#include <map>
+#include <mutex>
 #include <vector>
 
 #include "common.h"
@@ -54,6 +56,19 @@ constexpr int kOffInv = kNP + kNF;
 static_assert(kOffB3 + kNB == kNP, "parameter layout");
 static_assert(kNP + 2 * kNF == kNM, "model layout");
 constexpr int kGuessWG = 512;          // workgroups of the gradient kernel (at most)
+
+// Scratch of amoeba_guess_gradient_noalloc: per-workgroup gradient and loss partials, the loss
+// and the flag word, for batches of at most kScratchWG chunks of 64 samples, in one file-scope
+// device array (each device holds its own copy until the process ends).  Host code never uses
+// the array's name as an address: guess_scratch_init looks up each device's address once.
+constexpr int kScratchWG = 128;
+constexpr size_t kScratchPart = sizeof(float) * (size_t)kNP * kScratchWG;
+constexpr size_t kScratchLoss = kScratchPart;
+constexpr size_t kScratchScal = kScratchLoss + sizeof(double) * kScratchWG;
+constexpr size_t kScratchFlags = kScratchScal + sizeof(double) * 4;
+constexpr size_t kScratchBytes = (kScratchFlags + sizeof(int) + 255) / 256 * 256;
+static_assert(kScratchLoss % 8 == 0, "scratch layout");
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
 
 // fixed offsets s_k of mu0 = sum_k (s_k + y_k) v_k
 struct GuessOffsets {
@@ -743,10 +758,57 @@ static int guess_ready(amoeba_ctx* c, const char* who)
     return AMOEBA_OK;
 }
 
+// device buffers of a gradient evaluation: the context's, or the no-allocation scratch
+struct GradWork {
+    float* part;     // [nwg][NPARAM]
+    double* lossp;   // [nwg]
+    double* scal;    // [4]
+    int* flags;
+    bool fill_flags; // clear the flag word with a kernel instead of a memset node
+};
+
+__global__ void k_zero_flag(int* __restrict__ flags)
+{
+    if (threadIdx.x == 0)
+        flags[0] = 0;
+}
+
+int guess_scratch_init(amoeba_ctx* c)
+{
+    // once per device, with that device current (amoeba_create runs on the caller's device)
+    static std::mutex mu;
+    static std::map<int, void*> addr;
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = addr.find(c->device);
+    if (it == addr.end()) {
+        void* ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
+            (void)hipGetLastError();
+            return set_error(c, AMOEBA_E_DEVICE, "hipGetSymbolAddress of the guess scratch failed");
+        }
+        it = addr.emplace(c->device, ptr).first;
+    }
+    c->g_scratch = it->second;
+    return AMOEBA_OK;
+}
+
+static GradWork ctx_work(amoeba_ctx* c)
+{
+    return GradWork{c->g_part, c->g_lossp, c->g_scal, c->flags, false};
+}
+
+static GradWork scratch_work(amoeba_ctx* c)
+{
+    unsigned char* base = static_cast<unsigned char*>(c->g_scratch);
+    return GradWork{reinterpret_cast<float*>(base), reinterpret_cast<double*>(base + kScratchLoss),
+                    reinterpret_cast<double*>(base + kScratchScal), reinterpret_cast<int*>(base + kScratchFlags),
+                    true};
+}
+
 // loss and gradient partials of a batch, then the reduction (Adam step when adam != 0)
 static int guess_grad(amoeba_ctx* c, const float* feat, const float* basis, const float* target, int64_t n_rows,
                       const int32_t* idx, int64_t n_batch, float* grad_out, bool adam, float lr, double* loss_out,
-                      const char* who)
+                      const char* who, const GradWork& ws)
 {
     if (!feat || !basis || !target)
         return set_error(c, AMOEBA_E_INVALID, std::string(who) + ": NULL feat, basis or target");
@@ -757,7 +819,10 @@ static int guess_grad(amoeba_ctx* c, const float* feat, const float* basis, cons
     hipStream_t st = c->stream;
     const int64_t nchunk = (n_batch + kBlock - 1) / kBlock;
     const int nwg = (int)std::min<int64_t>(nchunk, kGuessWG);
-    hipMemsetAsync(c->flags, 0, sizeof(int), st);
+    if (ws.fill_flags)
+        hipLaunchKernelGGL(k_zero_flag, dim3(1), dim3(64), 0, st, ws.flags);
+    else
+        hipMemsetAsync(ws.flags, 0, sizeof(int), st);
     float bc1 = 1.f, bc2 = 1.f;
     if (adam) {
         const int64_t t = c->g_step + 1;
@@ -768,13 +833,13 @@ static int guess_grad(amoeba_ctx* c, const float* feat, const float* basis, cons
         StageTimer tm(c, AMOEBA_T_GUESS);
         const float lscale = (float)(kDebye * kDebye / (double)n_batch);
         hipLaunchKernelGGL(k_guess_grad, dim3(nwg), dim3(64), 0, st, n_batch, n_rows, idx, c->g_model, feat, basis,
-                           guess_offsets(c), target, lscale, c->g_part, c->g_lossp, c->flags);
-        hipLaunchKernelGGL(k_guess_reduce, dim3((kNP + 63) / 64), dim3(256), 0, st, nwg, c->g_part, c->g_lossp,
-                           grad_out, c->g_model, c->g_adam_m, c->g_adam_v, adam ? 1 : 0, lr, bc1, bc2, c->g_scal,
-                           c->flags);
+                           guess_offsets(c), target, lscale, ws.part, ws.lossp, ws.flags);
+        hipLaunchKernelGGL(k_guess_reduce, dim3((kNP + 63) / 64), dim3(256), 0, st, nwg, ws.part, ws.lossp,
+                           grad_out, c->g_model, c->g_adam_m, c->g_adam_v, adam ? 1 : 0, lr, bc1, bc2, ws.scal,
+                           ws.flags);
     }
-    hipMemcpyAsync(c->flags_host, c->flags, sizeof(int), hipMemcpyDeviceToHost, st);
-    hipMemcpyAsync(c->g_scal_host, c->g_scal, sizeof(double), hipMemcpyDeviceToHost, st);
+    hipMemcpyAsync(c->flags_host, ws.flags, sizeof(int), hipMemcpyDeviceToHost, st);
+    hipMemcpyAsync(c->g_scal_host, ws.scal, sizeof(double), hipMemcpyDeviceToHost, st);
     int rc = hip_check(c, hipStreamSynchronize(st), who);
     if (rc)
         return rc;
@@ -1036,7 +1101,28 @@ int amoeba_guess_gradient(amoeba_ctx* c, const float* feat, const float* basis, 
     if (rc)
         return rc;
     return guess_grad(c, feat, basis, target, n_rows, idx, n_batch, grad_out, false, 0.0f, loss_out,
-                      "amoeba_guess_gradient");
+                      "amoeba_guess_gradient", ctx_work(c));
+}
+
+int amoeba_guess_gradient_noalloc(amoeba_ctx* c, const float* feat, const float* basis, const float* target,
+                                  int64_t n_rows, const int32_t* idx, int64_t n_batch, float* grad_out,
+                                  double* loss_out)
+{
+    if (!c)
+        return AMOEBA_E_INVALID;
+    c->err.clear();
+    if (!grad_out)
+        return set_error(c, AMOEBA_E_INVALID, "amoeba_guess_gradient_noalloc: NULL grad_out");
+    if (n_batch > (int64_t)kScratchWG * kBlock)
+        return set_error(c, AMOEBA_E_INVALID, "amoeba_guess_gradient_noalloc: n_batch above "
+                                              "AMOEBA_GUESS_NOALLOC_MAX_BATCH (8192)");
+    int rc = guess_ready(c, "amoeba_guess_gradient_noalloc");
+    if (rc)
+        return rc;
+    if (!c->g_scratch)
+        return set_error(c, AMOEBA_E_STATE, "amoeba_guess_gradient_noalloc: scratch address unknown");
+    return guess_grad(c, feat, basis, target, n_rows, idx, n_batch, grad_out, false, 0.0f, loss_out,
+                      "amoeba_guess_gradient_noalloc", scratch_work(c));
 }
 
 int amoeba_guess_train_step(amoeba_ctx* c, const float* feat, const float* basis, const float* target,
@@ -1049,7 +1135,7 @@ int amoeba_guess_train_step(amoeba_ctx* c, const float* feat, const float* basis
     if (rc)
         return rc;
     return guess_grad(c, feat, basis, target, n_rows, idx, n_batch, nullptr, true, lr, loss_out,
-                      "amoeba_guess_train_step");
+                      "amoeba_guess_train_step", ctx_work(c));
 }
 
 int amoeba_guess_predict(amoeba_ctx* c, const double* pos, const double* e_perm, double* mu0_out)
