@@ -41,7 +41,9 @@ template <> struct PlT<double> { using C = double2; using R4 = double4; };
 
 constexpr int kPlThreads = 512;         // threads per workgroup of the row-chunk passes (spread, gather)
 constexpr int kPlColThreads = 256;      // threads per workgroup of the column passes (y and x lines)
-constexpr int kPlMaxB = 1;              // butterflies per thread in one FFT round
+constexpr int kPlMaxB = 1;              // butterflies per thread in one FFT round (row passes)
+constexpr int kPlColMaxB = 2;           // the same in the column passes: a stage's lines in one round
+constexpr int kPlLoads = 8;             // global loads a thread keeps in flight when filling LDS
 constexpr int kPlConv = 16;             // fixed-point values per thread in the conversion
 constexpr int kPlSplit = 4;             // split / combine items per thread in one round
 constexpr size_t kPlLdsMax = 64 * 1024; // LDS of one workgroup
@@ -167,12 +169,12 @@ template <int RAD, int SIGN, typename C> __device__ __forceinline__ void dft(C (
 // (w = exp(SIGN 2 pi i / N), tw[m] = exp(-2 pi i m / N)), applies the RAD-point DFT and writes
 // output q to (j div Ns) Ns RAD + (j mod Ns) + q Ns.  Whole lines are processed per round, so
 // each round reads all its points into registers before the barrier and writes after it.
-template <int RAD, int SIGN, int NT, typename C>
+template <int RAD, int SIGN, int NT, int MB, typename C>
 __device__ __forceinline__ void fft_stage(C* buf, int nl, int N, int Ns, const C* tw, LineMap am)
 {
     const int nb = N / RAD;
     const int tstep = N / (Ns * RAD);
-    const int lpr = max(1, NT * kPlMaxB / nb);
+    const int lpr = max(1, NT * MB / nb);
     const SmallDiv dnb(nb), dns(Ns);
     // an opaque copy of the thread index: keeps the compiler from hoisting every stage's index
     // arithmetic out of the stage loop (which would hold all of it in registers at once)
@@ -180,10 +182,10 @@ __device__ __forceinline__ void fft_stage(C* buf, int nl, int N, int Ns, const C
     asm volatile("" : "+v"(tid));
     for (int l0 = 0; l0 < nl; l0 += lpr) {
         const int cnt = min(lpr, nl - l0) * nb;
-        C v[kPlMaxB][RAD];
-        int dst[kPlMaxB];
+        C v[MB][RAD];
+        int dst[MB];
 #pragma unroll
-        for (int m = 0; m < kPlMaxB; ++m) {
+        for (int m = 0; m < MB; ++m) {
             const int it = tid + m * NT;
             dst[m] = -1;
             if (it < cnt) {
@@ -206,7 +208,7 @@ __device__ __forceinline__ void fft_stage(C* buf, int nl, int N, int Ns, const C
         }
         __syncthreads();
 #pragma unroll
-        for (int m = 0; m < kPlMaxB; ++m) {
+        for (int m = 0; m < MB; ++m) {
             if (dst[m] >= 0) {
                 const int it = tid + m * NT;
                 const int lq = dnb.quot(it), l = l0 + lq, j = it - lq * nb, k = j - dns.quot(j) * Ns;
@@ -220,22 +222,46 @@ __device__ __forceinline__ void fft_stage(C* buf, int nl, int N, int Ns, const C
     }
 }
 
-// FFT (SIGN -1 forward, +1 unnormalised inverse) of nl lines of length d.n.  All threads of
-// the workgroup call it after a barrier; it ends with one.
-template <int SIGN, int NT = kPlThreads, typename C>
+// FFT (SIGN -1 forward, +1 unnormalised inverse) of nl lines of length d.n, up to MB
+// butterflies per thread in one round.  All threads of the workgroup call it after a barrier;
+// it ends with one.
+template <int SIGN, int NT = kPlThreads, int MB = kPlMaxB, typename C>
 __device__ __forceinline__ void fft_lines(C* buf, int nl, const PlaneDim& d, const C* tw, LineMap am)
 {
     int Ns = 1;
     for (int s = 0; s < d.nr; ++s) {
         switch (d.rad[s]) {
-        case 2: fft_stage<2, SIGN, NT>(buf, nl, d.n, Ns, tw, am); break;
-        case 3: fft_stage<3, SIGN, NT>(buf, nl, d.n, Ns, tw, am); break;
-        case 4: fft_stage<4, SIGN, NT>(buf, nl, d.n, Ns, tw, am); break;
-        case 5: fft_stage<5, SIGN, NT>(buf, nl, d.n, Ns, tw, am); break;
-        case 6: fft_stage<6, SIGN, NT>(buf, nl, d.n, Ns, tw, am); break;
-        default: fft_stage<7, SIGN, NT>(buf, nl, d.n, Ns, tw, am); break;
+        case 2: fft_stage<2, SIGN, NT, MB>(buf, nl, d.n, Ns, tw, am); break;
+        case 3: fft_stage<3, SIGN, NT, MB>(buf, nl, d.n, Ns, tw, am); break;
+        case 4: fft_stage<4, SIGN, NT, MB>(buf, nl, d.n, Ns, tw, am); break;
+        case 5: fft_stage<5, SIGN, NT, MB>(buf, nl, d.n, Ns, tw, am); break;
+        case 6: fft_stage<6, SIGN, NT, MB>(buf, nl, d.n, Ns, tw, am); break;
+        default: fft_stage<7, SIGN, NT, MB>(buf, nl, d.n, Ns, tw, am); break;
         }
         Ns *= d.rad[s];
+    }
+}
+
+// LDS fill: element i of n goes from src[sidx(i)] to dst[didx(i)].  Each thread issues
+// kPlLoads global loads before it stores any of them, so that many loads are in flight per
+// wave instead of one round trip per element.
+template <int NT, typename T, typename SI, typename DI>
+__device__ __forceinline__ void fill_lds(int n, const T* __restrict__ src, SI sidx, T* dst, DI didx)
+{
+    for (int i0 = threadIdx.x; i0 < n; i0 += kPlLoads * NT) {
+        T v[kPlLoads];
+#pragma unroll
+        for (int u = 0; u < kPlLoads; ++u) {
+            const int i = i0 + u * NT;
+            if (i < n)
+                v[u] = src[sidx(i)];
+        }
+#pragma unroll
+        for (int u = 0; u < kPlLoads; ++u) {
+            const int i = i0 + u * NT;
+            if (i < n)
+                dst[didx(i)] = v[u];
+        }
     }
 }
 
@@ -538,12 +564,19 @@ __global__ __launch_bounds__(kPlColThreads) void k_pme_ylines(PlaneGeom g, Plane
     for (int i = tid; i < g.K1; i += kPlColThreads)
         tw[i] = roots_y[i];
     C* base = gc + (size_t)x * g.K1 * g.kh + kz0;
-    for (int i = tid; i < g.K1 * ncol; i += kPlColThreads) {
-        const int y = dnc.quot(i), cc = i - y * ncol;
-        buf[y * g.kc + cc] = base[(size_t)y * g.kh + cc];
-    }
+    fill_lds<kPlColThreads>(
+        g.K1 * ncol, base,
+        [&](int i) {
+            const int y = dnc.quot(i);
+            return (size_t)y * g.kh + (i - y * ncol);
+        },
+        buf,
+        [&](int i) {
+            const int y = dnc.quot(i);
+            return y * g.kc + (i - y * ncol);
+        });
     __syncthreads();
-    fft_lines<SIGN, kPlColThreads>(buf, ncol, dy, tw, LineMap{1, 2 * g.kc, g.kc});
+    fft_lines<SIGN, kPlColThreads, kPlColMaxB>(buf, ncol, dy, tw, LineMap{1, 2 * g.kc, g.kc});
     for (int i = tid; i < g.K1 * ncol; i += kPlColThreads) {
         const int y = dnc.quot(i), cc = i - y * ncol;
         base[(size_t)y * g.kh + cc] = buf[y * g.kc + cc];
@@ -575,23 +608,45 @@ __global__ __launch_bounds__(kPlColThreads) void k_pme_xconv(PlaneGeom g, PlaneD
         tw[i] = roots_x[i];
     const size_t xs = (size_t)g.K1 * g.kh;   // stride of x in G
     const size_t off = (size_t)ky * g.kh + kz0;
-    for (int i = tid; i < g.K0 * ncol; i += kPlColThreads) {
-        const int xx = dnc.quot(i), cc = i - xx * ncol;
-        buf[xx * g.kc + cc] = gc[xx * xs + off + cc];
-    }
+    fill_lds<kPlColThreads>(
+        g.K0 * ncol, gc,
+        [&](int i) {
+            const int xx = dnc.quot(i);
+            return xx * xs + off + (i - xx * ncol);
+        },
+        buf,
+        [&](int i) {
+            const int xx = dnc.quot(i);
+            return xx * g.kc + (i - xx * ncol);
+        });
     __syncthreads();
     const LineMap am{1, 2 * g.kc, g.kc};
-    fft_lines<-1, kPlColThreads>(buf, ncol, dx, tw, am);
-    for (int i = tid; i < g.K0 * ncol; i += kPlColThreads) {
-        const int kx = dnc.quot(i), cc = i - kx * ncol;
-        const R th = theta[kx * xs + off + cc];
-        C v = buf[kx * g.kc + cc];
-        v.x *= th;
-        v.y *= th;
-        buf[kx * g.kc + cc] = v;
+    fft_lines<-1, kPlColThreads, kPlColMaxB>(buf, ncol, dx, tw, am);
+    // product with the influence function; its loads issued kPlLoads at a time
+    for (int i0 = tid; i0 < g.K0 * ncol; i0 += kPlLoads * kPlColThreads) {
+        R th[kPlLoads];
+#pragma unroll
+        for (int u = 0; u < kPlLoads; ++u) {
+            const int i = i0 + u * kPlColThreads;
+            if (i < g.K0 * ncol) {
+                const int kx = dnc.quot(i);
+                th[u] = theta[kx * xs + off + (i - kx * ncol)];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kPlLoads; ++u) {
+            const int i = i0 + u * kPlColThreads;
+            if (i < g.K0 * ncol) {
+                const int kx = dnc.quot(i), cc = i - kx * ncol;
+                C v = buf[kx * g.kc + cc];
+                v.x *= th[u];
+                v.y *= th[u];
+                buf[kx * g.kc + cc] = v;
+            }
+        }
     }
     __syncthreads();
-    fft_lines<+1, kPlColThreads>(buf, ncol, dx, tw, am);
+    fft_lines<+1, kPlColThreads, kPlColMaxB>(buf, ncol, dx, tw, am);
     for (int i = tid; i < g.K0 * ncol; i += kPlColThreads) {
         const int xx = dnc.quot(i), cc = i - xx * ncol;
         gc[xx * xs + off + cc] = buf[xx * g.kc + cc];
@@ -632,12 +687,19 @@ __global__ __launch_bounds__(kPlThreads) void k_pme_z_gather(PlaneGeom g, PlaneD
     for (int i = tid; i < g.K2; i += kPlThreads)
         tw_z[i] = roots_z[i];
     const SmallDiv dkh(g.kh);
-    for (int i = tid; i < nrows * g.kh; i += kPlThreads) {
-        const int r = dkh.quot(i), k = i - r * g.kh;
-        int gy = rc.ya - 4 + r;
-        gy += gy < 0 ? g.K1 : 0;
-        pl[(r >> 1) * g.S + (r & 1) * g.kh + k] = gc[((size_t)x * g.K1 + gy) * g.kh + k];
-    }
+    fill_lds<kPlThreads>(
+        nrows * g.kh, gc,
+        [&](int i) {
+            const int r = dkh.quot(i), k = i - r * g.kh;
+            int gy = rc.ya - 4 + r;
+            gy += gy < 0 ? g.K1 : 0;
+            return ((size_t)x * g.K1 + gy) * g.kh + k;
+        },
+        pl,
+        [&](int i) {
+            const int r = dkh.quot(i), k = i - r * g.kh;
+            return (r >> 1) * g.S + (r & 1) * g.kh + k;
+        });
     if (nrows & 1)  // the last line holds one row only
         for (int k = tid; k < g.kh; k += kPlThreads)
             pl[(npl - 1) * g.S + g.kh + k] = C{(R)0, (R)0};
