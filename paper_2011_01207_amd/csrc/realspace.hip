@@ -9,10 +9,10 @@
 // and every lane evaluates an equal contiguous share of them by walking the set bits of the
 // masks, so masked-out pair slots cost nothing.  Each pair is evaluated once (Newton's third
 // law): the field at i accumulates in registers while the lane stays on a row and is then added
-// to the block's LDS accumulator, which collects all tiles of the block; the field at j is added
-// to the tile's LDS accumulator.  In mixed precision every LDS addition is a fixed-point integer
-// (40 fraction bits) held exactly in FP64, so the sums do not depend on the order of the lanes'
-// atomics and the product is bitwise reproducible; FP64 mode accumulates in FP64.
+// to the block's LDS accumulator, which collects all tiles of the block; the field at j is added,
+// per pair, to the tile's LDS accumulator.  In mixed precision every LDS addition is a 64-bit
+// fixed-point integer (38 fraction bits; see LdsAcc), so the sums do not depend on the order of
+// the lanes' atomics and the product is bitwise reproducible; FP64 mode accumulates in FP64.
 //
 // No global atomics: a block writes its i-field once (eipart) and each off-diagonal tile writes
 // its 64 j-fields to its own slot of jbuf; the diagonal tile's j-field goes straight into the
@@ -104,16 +104,29 @@ constexpr int kTileCost = 256;  // per-tile cost of staging and scanning, in uni
 // or read the stored ones back.
 enum CoefMode { kCoefCompute = 0, kCoefRecord = 1, kCoefReplay = 2 };
 
-// LDS field accumulators: fixed point with 40 fraction bits held as integer-valued FP64
-// (mixed; see fixd) or plain FP64.
-template <bool FIX> struct LdsField;
-template <> struct LdsField<true> {
-    using T = double;
-    __device__ static void add(T* p, float v) { atomicAdd(p, fixd(v)); }
-    __device__ static void add_raw(T* p, T v) { atomicAdd(p, v); }
-    __device__ static double value(T v) { return v * kFixInv; }
+// LDS field accumulators: the block's i-field (all tiles of the block, added to by the four
+// waves on row changes) and each tile's j-field (added to per pair by the wave that walks the
+// tile).  Mixed precision: 64-bit integers in units of 2^-38 e/A^2, added with the LDS's
+// integer atomics (which measured far faster than its FP64 and FP32 adds on gfx950), so every
+// sum is exact and independent of the order of the additions.  A pair's FP32 field becomes an
+// integer without an FP64-to-integer instruction: adding 1.5 * 2^52 to v * 2^38 in FP64 rounds
+// it to the nearest integer (the sum's unit in the last place is 1), and the sum's bits minus
+// those of 1.5 * 2^52 are that integer, exact for |v| < 2^13 e/A^2 (the range of the fields).
+// FP64 mode adds FP64 values.
+template <bool FIX> struct LdsAcc;
+template <> struct LdsAcc<true> {
+    using T = unsigned long long;
+    static constexpr double kScale = 274877906944.0;     // 2^38
+    static constexpr double kMagic = 6755399441055744.0; // 1.5 * 2^52
+    __device__ static void add(T* p, float v)
+    {
+        const double y = fma((double)v, kScale, kMagic);
+        atomicAdd(p, (T)(__double_as_longlong(y) - __double_as_longlong(kMagic)));
+    }
+    __device__ static void add_raw(T* p, T q) { atomicAdd(p, q); }
+    __device__ static double value(T q) { return (double)(long long)q * (1.0 / kScale); }
 };
-template <> struct LdsField<false> {
+template <> struct LdsAcc<false> {
     using T = double;
     __device__ static void add(T* p, double v) { atomicAdd(p, v); }
     __device__ static void add_raw(T* p, T v) { atomicAdd(p, v); }
@@ -555,7 +568,7 @@ __global__ __launch_bounds__(256) void k_block_tiles(int nb, const int* __restri
 {
     using R4 = typename V4<R>::T;
     using R2 = typename V2<R>::T;
-    using LT = typename LdsField<FIX>::T;
+    using LT = typename LdsAcc<FIX>::T;
     constexpr int NV = K::NV;
     __shared__ R4 s_ip[kBlock];                      // i offset from the block origin, w = alpha^-1/6
     __shared__ R4 s_id[NV][kBlock];                  // i source data
@@ -659,29 +672,31 @@ __global__ __launch_bounds__(256) void k_block_tiles(int nb, const int* __restri
             int i;
             unsigned long long rem;
             walk_start(s_off[w], s_mask[w], p0, i, rem);
-            int cur = -1;
-            R4 ip{0, 0, 0, 0};
+            R4 ip = s_ip[i];
             R4 di[NV];
-            R ea[3] = {0, 0, 0};
-            // one pair of the walk: the next set bit (a new row first adds the finished row's
-            // i-field to the block accumulator), the pair's field from eval, the j-field added
-            auto visit = [&](auto&& eval) {
-                while (rem == 0ull)
-                    rem = s_mask[w][++i];
-                const int k = __ffsll((long long)rem) - 1;
-                rem &= rem - 1ull;
-                if (i != cur) {
-                    if (cur >= 0)
 #pragma unroll
-                        for (int c = 0; c < 3; ++c)
-                            LdsField<FIX>::add(&s_ei[c][cur], ea[c]);
-                    cur = i;
+            for (int v = 0; v < NV; ++v)
+                di[v] = s_id[v][i];
+            R ea[3] = {0, 0, 0};
+            // one pair of the walk: the next set bit (when the row is used up, its i-field goes
+            // to the block accumulator and the lane moves to the next row with pairs), the
+            // pair's field from eval, the j-field added
+            auto visit = [&](auto&& eval) {
+                if (rem == 0ull) {
+#pragma unroll
+                    for (int c = 0; c < 3; ++c)
+                        LdsAcc<FIX>::add(&s_ei[c][i], ea[c]);
+                    ea[0] = ea[1] = ea[2] = 0;
+                    do {
+                        rem = s_mask[w][++i];
+                    } while (rem == 0ull);
                     ip = s_ip[i];
 #pragma unroll
                     for (int v = 0; v < NV; ++v)
                         di[v] = s_id[v][i];
-                    ea[0] = ea[1] = ea[2] = 0;
                 }
+                const int k = __ffsll((long long)rem) - 1;
+                rem &= rem - 1ull;
                 R4 dj[NV];
 #pragma unroll
                 for (int v = 0; v < NV; ++v)
@@ -690,7 +705,7 @@ __global__ __launch_bounds__(256) void k_block_tiles(int nb, const int* __restri
                 eval(s_jp[w][k], dj, ej);
 #pragma unroll
                 for (int c = 0; c < 3; ++c)
-                    LdsField<FIX>::add(&s_ej[w][c][k], ej[c]);
+                    LdsAcc<FIX>::add(&s_ej[w][c][k], ej[c]);
             };
             const int n = p1 - p0;
             bool replayed = false;
@@ -729,7 +744,7 @@ __global__ __launch_bounds__(256) void k_block_tiles(int nb, const int* __restri
             }
 #pragma unroll
             for (int c = 0; c < 3; ++c)
-                LdsField<FIX>::add(&s_ei[c][cur], ea[c]);
+                LdsAcc<FIX>::add(&s_ei[c][i], ea[c]);
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
@@ -738,11 +753,11 @@ __global__ __launch_bounds__(256) void k_block_tiles(int nb, const int* __restri
             // diagonal tile: its j-atoms are the block's own atoms
 #pragma unroll
             for (int c = 0; c < 3; ++c)
-                LdsField<FIX>::add_raw(&s_ei[c][lane], s_ej[w][c][lane]);
+                LdsAcc<FIX>::add_raw(&s_ei[c][lane], s_ej[w][c][lane]);
         } else {
             reinterpret_cast<R4*>(jbuf)[(size_t)t * kBlock + lane] =
-                R4{(R)LdsField<FIX>::value(s_ej[w][0][lane]), (R)LdsField<FIX>::value(s_ej[w][1][lane]),
-                   (R)LdsField<FIX>::value(s_ej[w][2][lane]), (R)0};
+                R4{(R)LdsAcc<FIX>::value(s_ej[w][0][lane]), (R)LdsAcc<FIX>::value(s_ej[w][1][lane]),
+                   (R)LdsAcc<FIX>::value(s_ej[w][2][lane]), (R)0};
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
@@ -751,7 +766,7 @@ __global__ __launch_bounds__(256) void k_block_tiles(int nb, const int* __restri
     __syncthreads();
     if (tid < 3 * kBlock) {
         const int c = tid / kBlock, l = tid % kBlock;
-        eipart[3 * ((size_t)I * kBlock + l) + c] = LdsField<FIX>::value(s_ei[c][l]);
+        eipart[3 * ((size_t)I * kBlock + l) + c] = LdsAcc<FIX>::value(s_ei[c][l]);
     }
 }
 
