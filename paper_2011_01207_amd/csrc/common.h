@@ -46,6 +46,21 @@ enum : int {
 constexpr double kFixRange = 8192.0;
 __device__ __forceinline__ double fixd(float v) { return rint((double)v * 1099511627776.0); }
 
+// LDS sums of the pair and spread kernels: 64-bit integers in units of 2^-38, added with the
+// LDS's integer atomics (on gfx950 these measured far faster than its FP64 and FP32 adds).  An
+// FP32 value becomes its integer without an FP64-to-integer instruction: adding 1.5 * 2^52 to
+// v * 2^38 in FP64 rounds it to the nearest integer (the sum's unit in the last place is 1), and
+// the sum's bits minus those of 1.5 * 2^52 are that integer, exact for |v| < 2^13 (the range of
+// the fields).  Integer sums are exact, so their order does not matter.
+constexpr double kFixQScale = 274877906944.0;      // 2^38
+constexpr double kFixQMagic = 6755399441055744.0;  // 1.5 * 2^52
+__device__ __forceinline__ unsigned long long fixq(float v)
+{
+    const double y = fma((double)v, kFixQScale, kFixQMagic);
+    return (unsigned long long)(__double_as_longlong(y) - __double_as_longlong(kFixQMagic));
+}
+__device__ __forceinline__ double fixq_value(unsigned long long q) { return (double)(long long)q * (1.0 / kFixQScale); }
+
 // Sums of an atom's i-field (eipart) and its tile j-fields (jbuf, listed by the reverse index).
 // Mixed precision adds every FP32 j-field in the fixed point of the tile accumulators, so the
 // sum is exact and does not depend on the order of the reverse-index entries (which the list

@@ -473,7 +473,7 @@ __global__ __launch_bounds__(kPlThreads) void k_pme_spread_z(PlaneGeom g, PlaneD
                     if (PERM)
                         v += c2 * z2[tz];
                     if (FIX)
-                        atomicAdd(row + zi[tz], fixd((float)v));
+                        atomicAdd(reinterpret_cast<unsigned long long*>(row + zi[tz]), fixq((float)v));
                     else
                         atomicAdd(row + zi[tz], (double)v);
                 }
@@ -488,7 +488,7 @@ __global__ __launch_bounds__(kPlThreads) void k_pme_spread_z(PlaneGeom g, PlaneD
 #pragma unroll
         for (int m = 0; m < kPlConv; ++m) {
             const int i = tid + m * kPlThreads;
-            f[m] = i < n2 ? (float)(acc[i] * kFixInv) : 0.0f;
+            f[m] = i < n2 ? (float)fixq_value(reinterpret_cast<const unsigned long long*>(acc)[i]) : 0.0f;
         }
         __syncthreads();
         float* fp = reinterpret_cast<float*>(pl_smem);

@@ -106,25 +106,14 @@ enum CoefMode { kCoefCompute = 0, kCoefRecord = 1, kCoefReplay = 2 };
 
 // LDS field accumulators: the block's i-field (all tiles of the block, added to by the four
 // waves on row changes) and each tile's j-field (added to per pair by the wave that walks the
-// tile).  Mixed precision: 64-bit integers in units of 2^-38 e/A^2, added with the LDS's
-// integer atomics (which measured far faster than its FP64 and FP32 adds on gfx950), so every
-// sum is exact and independent of the order of the additions.  A pair's FP32 field becomes an
-// integer without an FP64-to-integer instruction: adding 1.5 * 2^52 to v * 2^38 in FP64 rounds
-// it to the nearest integer (the sum's unit in the last place is 1), and the sum's bits minus
-// those of 1.5 * 2^52 are that integer, exact for |v| < 2^13 e/A^2 (the range of the fields).
-// FP64 mode adds FP64 values.
+// tile).  Mixed precision: 64-bit fixed-point integers (fixq: 2^-38 e/A^2) added with integer
+// atomics, exact and independent of the order of the additions; FP64 mode adds FP64 values.
 template <bool FIX> struct LdsAcc;
 template <> struct LdsAcc<true> {
     using T = unsigned long long;
-    static constexpr double kScale = 274877906944.0;     // 2^38
-    static constexpr double kMagic = 6755399441055744.0; // 1.5 * 2^52
-    __device__ static void add(T* p, float v)
-    {
-        const double y = fma((double)v, kScale, kMagic);
-        atomicAdd(p, (T)(__double_as_longlong(y) - __double_as_longlong(kMagic)));
-    }
+    __device__ static void add(T* p, float v) { atomicAdd(p, fixq(v)); }
     __device__ static void add_raw(T* p, T q) { atomicAdd(p, q); }
-    __device__ static double value(T q) { return (double)(long long)q * (1.0 / kScale); }
+    __device__ static double value(T q) { return fixq_value(q); }
 };
 template <> struct LdsAcc<false> {
     using T = double;
