@@ -450,9 +450,10 @@ def roofline(s, res):
     # five field shares written and read (16 B each); combine: i-field 24 B, direction 24 B,
     # 1/alpha 8 B read and A p 24 B written per atom, every tile j-field slot (16 B) read
     b_gather = nc * 8 + n * (32 + 2 * 80 + 24 + 24 + 8 + 24) + res["n_tiles"] * 64 * 16
-    for name, b, kern in (("spread", b_spread, "k_pme_spread_z<float, true, false>"),
+    nt = "256" if K[0] >= 200 else "512"   # threads of the row passes (their shapes follow the grid)
+    for name, b, kern in (("spread", b_spread, f"k_pme_spread_z<float, true, false, {nt}>"),
                           ("fft", b_fft, "k_pme_ylines<float, -1> + k_pme_xconv<float> + k_pme_ylines<float, 1>"),
-                          ("gather", b_gather, "k_pme_z_gather<float> + k_plane_combine<float, 1>")):
+                          ("gather", b_gather, f"k_pme_z_gather<float, {nt}> + k_plane_combine<float, 1>")):
         ms = tim["ms"][name]
         stages[name] = {"bound": "hbm", "achieved": b * mv / (ms * 1e-3) / 1e9, "peak": PEAK_HBM, "unit": "GB/s",
                         "ms_total": ms, "launches": tim["launches"][name], "kernel": kern,

@@ -40,11 +40,15 @@ template <> struct PlT<float> { using C = float2; using R4 = float4; };
 template <> struct PlT<double> { using C = double2; using R4 = double4; };
 
 constexpr int kPlThreads = 512;         // threads per workgroup of the row-chunk passes (spread, gather)
+constexpr int kPlThreadsLarge = 256;    // the same on large grids, in smaller row chunks
+constexpr int kPlLargeWG = 1024;        // row-chunk workgroups of 512 threads above which a grid is large
+constexpr int kPlTargetWGLarge = 3456;  // row-chunk workgroups the chunking aims at on a large grid
+constexpr int kPlColMaxKc = 14;         // columns per column chunk at most on a large grid
 constexpr int kPlColThreads = 256;      // threads per workgroup of the column passes (y and x lines)
 constexpr int kPlMaxB = 1;              // butterflies per thread in one FFT round (row passes)
 constexpr int kPlColMaxB = 2;           // the same in the column passes: a stage's lines in one round
 constexpr int kPlLoads = 8;             // global loads a thread keeps in flight when filling LDS
-constexpr int kPlConv = 16;             // fixed-point values per thread in the conversion
+constexpr int kPlConvTotal = 8192;      // fixed-point values a row-chunk workgroup converts at most
 constexpr int kPlSplit = 4;             // split / combine items per thread in one round
 constexpr size_t kPlLdsMax = 64 * 1024; // LDS of one workgroup
 constexpr int kPlTargetWG = 432;        // workgroups per row-chunk pass the chunking aims at
@@ -270,6 +274,7 @@ __device__ __forceinline__ void fill_lds(int n, const T* __restrict__ src, SI si
 // spread and the interpolation work on chunks of Pc consecutive pairs, the y and x transforms
 // on chunks of kc consecutive kz columns.
 struct PlaneGeom {
+    int nt;       // threads per workgroup of the row-chunk passes
     int K0, K1, K2;
     int kh;       // K2 / 2 + 1
     int S;        // line stride of a pair (complex values): 2 kh
@@ -349,8 +354,8 @@ __device__ __forceinline__ void entry_splines(const typename PlT<R>::R4& w, int 
 // (src then holds three R4 per atom: (q, d), (Txx, Txy, Txz, Tyy), (Tyz, Tzz, 0, 0)).
 // Then every row pair is transformed along z, separated into the two rows' half spectra, and
 // the rows are written to G[x][y][0, kh).
-template <typename R, bool FIX, bool PERM>
-__global__ __launch_bounds__(kPlThreads) void k_pme_spread_z(PlaneGeom g, PlaneDim dz,
+template <typename R, bool FIX, bool PERM, int NT>
+__global__ __launch_bounds__(NT) void k_pme_spread_z(PlaneGeom g, PlaneDim dz,
                                                              const int* __restrict__ xy_start,
                                                              const int4* __restrict__ xb_rec,
                                                              const typename PlT<R>::R4* __restrict__ xb_w,
@@ -371,9 +376,9 @@ __global__ __launch_bounds__(kPlThreads) void k_pme_spread_z(PlaneGeom g, PlaneD
     const int n2 = 2 * rc.np * g.S;                    // doubles of the chunk's accumulation
     double* acc = pl_smem;
     C* tw_z = reinterpret_cast<C*>(pl_smem + 2 * g.Pc * g.S);
-    for (int i = tid; i < n2; i += kPlThreads)
+    for (int i = tid; i < n2; i += NT)
         acc[i] = 0.0;
-    for (int i = tid; i < g.K2; i += kPlThreads)
+    for (int i = tid; i < g.K2; i += NT)
         tw_z[i] = roots_z[i];
     BinRanges<10> br;
     {
@@ -398,14 +403,14 @@ __global__ __launch_bounds__(kPlThreads) void k_pme_spread_z(PlaneGeom g, PlaneD
     const R klx = (R)g.klx, kly = (R)g.kly, klz = (R)g.klz;
     const int nyr = rc.yb - rc.ya;
     // two atoms per thread and round, their loads issued together
-    for (int i0 = tid; i0 < br.total(); i0 += 2 * kPlThreads) {
+    for (int i0 = tid; i0 < br.total(); i0 += 2 * NT) {
         int tq[2];
         int4 rec[2];
         R4 w[2], m[2][PERM ? 3 : 1];
         bool ok[2];
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
-            const int i = i0 + u * kPlThreads;
+            const int i = i0 + u * NT;
             ok[u] = i < br.total();
             const int e = br.entry(ok[u] ? i : i0, tq[u]);
             rec[u] = xb_rec[e];
@@ -484,33 +489,33 @@ __global__ __launch_bounds__(kPlThreads) void k_pme_spread_z(PlaneGeom g, PlaneD
     C* pl = reinterpret_cast<C*>(pl_smem);
     if (FIX) {
         // fixed point -> FP32 in place (value k keeps its index)
-        float f[kPlConv];
+        float f[kPlConvTotal / NT];
 #pragma unroll
-        for (int m = 0; m < kPlConv; ++m) {
-            const int i = tid + m * kPlThreads;
+        for (int m = 0; m < kPlConvTotal / NT; ++m) {
+            const int i = tid + m * NT;
             f[m] = i < n2 ? (float)fixq_value(reinterpret_cast<const unsigned long long*>(acc)[i]) : 0.0f;
         }
         __syncthreads();
         float* fp = reinterpret_cast<float*>(pl_smem);
 #pragma unroll
-        for (int m = 0; m < kPlConv; ++m) {
-            const int i = tid + m * kPlThreads;
+        for (int m = 0; m < kPlConvTotal / NT; ++m) {
+            const int i = tid + m * NT;
             if (i < n2)
                 fp[i] = f[m];
         }
         __syncthreads();
     }
-    fft_lines<-1>(pl, rc.np, dz, tw_z, LineMap{g.S, 2, 1});
+    fft_lines<-1, NT>(pl, rc.np, dz, tw_z, LineMap{g.S, 2, 1});
     // separate the two rows of every pair into half spectra at [0, kh) and [kh, 2 kh)
     {
-        const int lpr = max(1, kPlThreads * kPlSplit / g.kh);
+        const int lpr = max(1, NT * kPlSplit / g.kh);
         const SmallDiv dkh(g.kh);
         for (int p0 = 0; p0 < rc.np; p0 += lpr) {
             const int cnt = min(lpr, rc.np - p0) * g.kh;
             C a[kPlSplit], b[kPlSplit];
 #pragma unroll
             for (int m = 0; m < kPlSplit; ++m) {
-                const int it = tid + m * kPlThreads;
+                const int it = tid + m * NT;
                 if (it < cnt) {
                     const int pq = dkh.quot(it), p = p0 + pq, k = it - pq * g.kh;
                     const C z = pl[p * g.S + k];
@@ -523,7 +528,7 @@ __global__ __launch_bounds__(kPlThreads) void k_pme_spread_z(PlaneGeom g, PlaneD
             __syncthreads();
 #pragma unroll
             for (int m = 0; m < kPlSplit; ++m) {
-                const int it = tid + m * kPlThreads;
+                const int it = tid + m * NT;
                 if (it < cnt) {
                     const int pq = dkh.quot(it), p = p0 + pq, k = it - pq * g.kh;
                     pl[p * g.S + k] = a[m];
@@ -535,7 +540,7 @@ __global__ __launch_bounds__(kPlThreads) void k_pme_spread_z(PlaneGeom g, PlaneD
     }
     C* out = gout + ((size_t)x * g.K1 + rc.ya) * g.kh;
     const SmallDiv dkh(g.kh);
-    for (int i = tid; i < nyr * g.kh; i += kPlThreads) {
+    for (int i = tid; i < nyr * g.kh; i += NT) {
         const int yl = dkh.quot(i), k = i - yl * g.kh;
         out[i] = pl[(yl >> 1) * g.S + (yl & 1) * g.kh + k];
     }
@@ -661,8 +666,8 @@ __global__ __launch_bounds__(kPlColThreads) void k_pme_xconv(PlaneGeom g, PlaneD
 // share of the field from plane x: part[5 s + t] = (M'_x M_y M_z psi, M_x M'_y M_z psi,
 // M_x M_y M'_z psi) over its 25 (y, z) points, t its weight index for the plane (the K/L
 // factors and the sign are applied by the combine).
-template <typename R>
-__global__ __launch_bounds__(kPlThreads) void k_pme_z_gather(PlaneGeom g, PlaneDim dz,
+template <typename R, int NT>
+__global__ __launch_bounds__(NT) void k_pme_z_gather(PlaneGeom g, PlaneDim dz,
                                                              const typename PlT<R>::C* __restrict__ gc,
                                                              const int* __restrict__ xy_start,
                                                              const int4* __restrict__ xb_rec,
@@ -684,10 +689,10 @@ __global__ __launch_bounds__(kPlThreads) void k_pme_z_gather(PlaneGeom g, PlaneD
     const int nrows = rc.yb - rc.ya + 4, npl = (nrows + 1) / 2;
     C* pl = reinterpret_cast<C*>(pl_smem);
     C* tw_z = pl + (g.Pc + 2) * g.S;
-    for (int i = tid; i < g.K2; i += kPlThreads)
+    for (int i = tid; i < g.K2; i += NT)
         tw_z[i] = roots_z[i];
     const SmallDiv dkh(g.kh);
-    fill_lds<kPlThreads>(
+    fill_lds<NT>(
         nrows * g.kh, gc,
         [&](int i) {
             const int r = dkh.quot(i), k = i - r * g.kh;
@@ -701,18 +706,18 @@ __global__ __launch_bounds__(kPlThreads) void k_pme_z_gather(PlaneGeom g, PlaneD
             return (r >> 1) * g.S + (r & 1) * g.kh + k;
         });
     if (nrows & 1)  // the last line holds one row only
-        for (int k = tid; k < g.kh; k += kPlThreads)
+        for (int k = tid; k < g.kh; k += NT)
             pl[(npl - 1) * g.S + g.kh + k] = C{(R)0, (R)0};
     __syncthreads();
     {
-        const int lpr = max(1, kPlThreads * kPlSplit / g.K2);
+        const int lpr = max(1, NT * kPlSplit / g.K2);
         const SmallDiv dk2(g.K2);
         for (int p0 = 0; p0 < npl; p0 += lpr) {
             const int cnt = min(lpr, npl - p0) * g.K2;
             C zv[kPlSplit];
 #pragma unroll
             for (int m = 0; m < kPlSplit; ++m) {
-                const int it = tid + m * kPlThreads;
+                const int it = tid + m * NT;
                 if (it < cnt) {
                     const int pq = dk2.quot(it), p = p0 + pq, k = it - pq * g.K2;
                     const bool up = k >= g.kh;
@@ -732,7 +737,7 @@ __global__ __launch_bounds__(kPlThreads) void k_pme_z_gather(PlaneGeom g, PlaneD
             __syncthreads();
 #pragma unroll
             for (int m = 0; m < kPlSplit; ++m) {
-                const int it = tid + m * kPlThreads;
+                const int it = tid + m * NT;
                 if (it < cnt) {
                     const int pq = dk2.quot(it), p = p0 + pq, k = it - pq * g.K2;
                     pl[p * g.S + k] = zv[m];
@@ -741,7 +746,7 @@ __global__ __launch_bounds__(kPlThreads) void k_pme_z_gather(PlaneGeom g, PlaneD
             __syncthreads();
         }
     }
-    fft_lines<+1>(pl, npl, dz, tw_z, LineMap{g.S, 2, 1});
+    fft_lines<+1, NT>(pl, npl, dz, tw_z, LineMap{g.S, 2, 1});
     // potential of local row r (global row ya - 4 + r), point z: component r mod 2 of
     // pl[(r div 2) S + z]
     const R* psi = reinterpret_cast<const R*>(pl_smem);
@@ -758,14 +763,14 @@ __global__ __launch_bounds__(kPlThreads) void k_pme_z_gather(PlaneGeom g, PlaneD
     }
     const int yorg = rc.ya - 4;
     // two atoms per thread and round, their loads issued together
-    for (int i0 = tid; i0 < br.total(); i0 += 2 * kPlThreads) {
+    for (int i0 = tid; i0 < br.total(); i0 += 2 * NT) {
         int tq[2];
         int4 rec[2];
         R4 w[2];
         bool ok[2];
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
-            const int i = i0 + u * kPlThreads;
+            const int i = i0 + u * NT;
             ok[u] = i < br.total();
             const int e = br.entry(ok[u] ? i : i0, tq[u]);
             rec[u] = xb_rec[e];
@@ -986,16 +991,30 @@ static PlaneGeom plane_geom(const amoeba_ctx* c)
     g.S = 2 * g.kh;
     g.P = (g.K1 + 1) / 2;
     const size_t cs = c->mixed ? sizeof(float2) : sizeof(double2);
-    // row chunks: about kPlTargetWG workgroups, within the LDS and conversion limits
-    g.nyc = std::min(g.P, std::max(1, cdiv(kPlTargetWG, g.K0)));
-    g.Pc = cdiv(g.P, g.nyc);
-    while (g.Pc > 1 && (lds_spread(g, cs) > kPlLdsMax || lds_gather(g, cs) > kPlLdsMax ||
-                        2 * g.Pc * g.S > kPlThreads * kPlConv))
-        g.Pc = cdiv(g.Pc, 2);
-    g.nyc = cdiv(g.P, g.Pc);
-    // column chunks likewise
+    // row chunks: about kPlTargetWG workgroups of 512 threads, within the LDS and conversion
+    // limits; a grid that needs more than kPlLargeWG of them (two 512-thread workgroups fit a CU)
+    // takes 256-thread workgroups on smaller chunks, so that more of them are resident at once
+    // and the chip is not left with a partial last round (measured at 216^3)
+    auto rows = [&](int target) {
+        g.nyc = std::min(g.P, std::max(1, cdiv(target, g.K0)));
+        g.Pc = cdiv(g.P, g.nyc);
+        while (g.Pc > 1 && (lds_spread(g, cs) > kPlLdsMax || lds_gather(g, cs) > kPlLdsMax ||
+                            2 * g.Pc * g.S > kPlConvTotal))
+            g.Pc = cdiv(g.Pc, 2);
+        g.nyc = cdiv(g.P, g.Pc);
+    };
+    g.nt = kPlThreads;
+    rows(kPlTargetWG);
+    const bool large = g.K0 * g.nyc > kPlLargeWG;
+    if (large) {
+        g.nt = kPlThreadsLarge;
+        rows(kPlTargetWGLarge);
+    }
+    // column chunks likewise (on a large grid at most kPlColMaxKc columns, for the same reason)
     g.nkc = std::min(g.kh, std::max(1, cdiv(kPlColTargetWG, std::min(g.K0, g.K1))));
     g.kc = cdiv(g.kh, g.nkc);
+    if (large)
+        g.kc = std::min(g.kc, kPlColMaxKc);
     while (g.kc > 1 && (lds_lines(g.K0, g.kc, cs) > kPlLdsMax || lds_lines(g.K1, g.kc, cs) > kPlLdsMax))
         g.kc = cdiv(g.kc, 2);
     g.nkc = cdiv(g.kh, g.kc);
@@ -1015,8 +1034,8 @@ bool plane_eligible(const amoeba_ctx* c)
     const size_t cs = c->mixed ? sizeof(float2) : sizeof(double2);
     return lds_spread(g, cs) <= kPlLdsMax && lds_gather(g, cs) <= kPlLdsMax &&
            lds_lines(g.K0, g.kc, cs) <= kPlLdsMax && lds_lines(g.K1, g.kc, cs) <= kPlLdsMax &&
-           2 * g.Pc * g.S <= kPlThreads * kPlConv && g.kh <= kPlThreads * kPlSplit &&
-           g.K2 <= kPlThreads * kPlSplit && (size_t)g.K0 * g.K1 <= 65536;
+           2 * g.Pc * g.S <= kPlConvTotal && g.kh <= g.nt * kPlSplit && g.K2 <= g.nt * kPlSplit &&
+           (size_t)g.K0 * g.K1 <= 65536;
 }
 
 int plane_setup(amoeba_ctx* c)
@@ -1086,19 +1105,18 @@ template <typename R> static void plane_field_t(amoeba_ctx* c, bool use_done, in
     const int ud = use_done ? 1 : 0;
     const C* const* roots = (const C* const*)c->pl_roots;
     C* gc = (C*)c->grid_c;
-    const dim3 nt(kPlThreads), ntc(kPlColThreads);
+    const dim3 nt(g.nt), ntc(kPlColThreads);
+    const bool small = g.nt == kPlThreads;
     constexpr bool FIX = std::is_same<R, float>::value;
     if (parts & 1) {
         StageTimer tm(c, perm ? AMOEBA_T_PERM : AMOEBA_T_SPREAD);
-        if (perm) {
-            const R4* src = c->mixed ? (const R4*)c->mp_f : (const R4*)c->mp_d;
-            hipLaunchKernelGGL((k_pme_spread_z<R, FIX, true>), dim3(g.K0 * g.nyc), nt, lds_spread(g, cs), st, g, d[2],
-                               c->xb_start, c->xb_rec, (const R4*)c->xb_w, src, roots[2], gc, c->sc, 0);
-        } else {
-            const R4* src = c->mixed ? (const R4*)c->pv_f : (const R4*)c->pv_d;
-            hipLaunchKernelGGL((k_pme_spread_z<R, FIX, false>), dim3(g.K0 * g.nyc), nt, lds_spread(g, cs), st, g,
-                               d[2], c->xb_start, c->xb_rec, (const R4*)c->xb_w, src, roots[2], gc, c->sc, ud);
-        }
+        const R4* src = perm ? (c->mixed ? (const R4*)c->mp_f : (const R4*)c->mp_d)
+                             : (c->mixed ? (const R4*)c->pv_f : (const R4*)c->pv_d);
+        auto k = perm ? (small ? k_pme_spread_z<R, FIX, true, kPlThreads> : k_pme_spread_z<R, FIX, true, kPlThreadsLarge>)
+                      : (small ? k_pme_spread_z<R, FIX, false, kPlThreads>
+                               : k_pme_spread_z<R, FIX, false, kPlThreadsLarge>);
+        hipLaunchKernelGGL(k, dim3(g.K0 * g.nyc), nt, lds_spread(g, cs), st, g, d[2], c->xb_start, c->xb_rec,
+                           (const R4*)c->xb_w, src, roots[2], gc, c->sc, perm ? 0 : ud);
     }
     if (!(parts & 2))
         return;
@@ -1113,8 +1131,9 @@ template <typename R> static void plane_field_t(amoeba_ctx* c, bool use_done, in
     }
     {
         StageTimer tm(c, perm ? AMOEBA_T_PERM : AMOEBA_T_GATHER);
-        hipLaunchKernelGGL(k_pme_z_gather<R>, dim3(g.K0 * g.nyc), nt, lds_gather(g, cs), st, g, d[2], (const C*)gc,
-                           c->xb_start, c->xb_rec, (const R4*)c->xb_w, roots[2], (R4*)c->rec_part, c->sc, ud);
+        auto k = small ? k_pme_z_gather<R, kPlThreads> : k_pme_z_gather<R, kPlThreadsLarge>;
+        hipLaunchKernelGGL(k, dim3(g.K0 * g.nyc), nt, lds_gather(g, cs), st, g, d[2], (const C*)gc, c->xb_start,
+                           c->xb_rec, (const R4*)c->xb_w, roots[2], (R4*)c->rec_part, c->sc, ud);
     }
 }
 
