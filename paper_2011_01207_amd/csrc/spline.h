@@ -5,34 +5,37 @@
 
 namespace amoeba {
 
-// Order-5 weights m0[t] = M5(w+t), first derivatives m1 and (optionally) second derivatives m2.
+// Order-5 weights m0[t] = M5(w+t), first derivatives m1 and (optionally) second derivatives m2,
+// for w in [0, 1).  Each is a polynomial piece of the cardinal B-spline in w (or in v = 1 - w,
+// by the symmetry M5(u) = M5(5 - u)), in Horner form:
+//   M5(w) = w^4/24,  M5(w+1) = P1(w),  M5(w+2) = P2(w),  M5(w+3) = P1(v),  M5(w+4) = v^4/24,
+//   P1(x) = (-4x^4 + 4x^3 + 6x^2 + 4x + 1)/24,  P2(x) = (6x^4 - 12x^3 - 6x^2 + 12x + 11)/24.
 template <typename R, bool SECOND>
 __device__ __forceinline__ void spline5(R w, R* m0, R* m1, R* m2)
 {
-    R a[5] = {w, (R)1 - w, 0, 0, 0};
-    R a3[5], a4[5];
-#pragma unroll
-    for (int k = 3; k <= 5; ++k) {
-        if (k == 4)
-#pragma unroll
-            for (int t = 0; t < 5; ++t)
-                a3[t] = a[t];
-        if (k == 5)
-#pragma unroll
-            for (int t = 0; t < 5; ++t)
-                a4[t] = a[t];
-        const R inv = (R)1 / (R)(k - 1);
-#pragma unroll
-        for (int t = k - 1; t >= 1; --t)
-            a[t] = ((w + (R)t) * a[t] + ((R)k - w - (R)t) * a[t - 1]) * inv;
-        a[0] = w * a[0] * inv;
-    }
-#pragma unroll
-    for (int t = 0; t < 5; ++t) {
-        m0[t] = a[t];
-        m1[t] = a4[t] - (t > 0 ? a4[t - 1] : (R)0);
-        if (SECOND)
-            m2[t] = a3[t] - (t > 0 ? (R)2 * a3[t - 1] : (R)0) + (t > 1 ? a3[t - 2] : (R)0);
+    const R v = (R)1 - w;
+    const R w2 = w * w, v2 = v * v;
+    auto p1 = [](R x) { return (((-x * (R)(1.0 / 6.0) + (R)(1.0 / 6.0)) * x + (R)0.25) * x + (R)(1.0 / 6.0)) * x +
+                               (R)(1.0 / 24.0); };
+    auto p2 = [](R x) { return ((((R)0.25 * x - (R)0.5) * x - (R)0.25) * x + (R)0.5) * x + (R)(11.0 / 24.0); };
+    auto d1 = [](R x) { return ((-x * (R)(2.0 / 3.0) + (R)0.5) * x + (R)0.5) * x + (R)(1.0 / 6.0); };
+    auto d2 = [](R x) { return ((x - (R)1.5) * x - (R)0.5) * x + (R)0.5; };
+    m0[0] = w2 * w2 * (R)(1.0 / 24.0);
+    m0[1] = p1(w);
+    m0[2] = p2(w);
+    m0[3] = p1(v);
+    m0[4] = v2 * v2 * (R)(1.0 / 24.0);
+    m1[0] = w2 * w * (R)(1.0 / 6.0);
+    m1[1] = d1(w);
+    m1[2] = d2(w);
+    m1[3] = -d1(v);
+    m1[4] = -v2 * v * (R)(1.0 / 6.0);
+    if (SECOND) {
+        m2[0] = (R)0.5 * w2;
+        m2[1] = ((R)-2 * w + (R)1) * w + (R)0.5;
+        m2[2] = ((R)3 * w - (R)3) * w - (R)0.5;
+        m2[3] = ((R)-2 * v + (R)1) * v + (R)0.5;
+        m2[4] = (R)0.5 * v2;
     }
 }
 
