@@ -50,8 +50,9 @@ PEAK_HBM = 8000.0          # GB/s
 # loop control and masked slots not counted.
 FLOPS_PER_PAIR = 80
 STAGES = ["list", "perm", "real", "spread", "fft", "gather", "pcg", "guess"]
-DTYPE = ("f32 pair/PME math; fields summed as integer-valued f64 fixed point (2^-40 e/A^2); f64 PCG "
-         "vectors, dot products and convergence test; f32 network")
+DTYPE = ("f32 pair/PME math; tile and grid-row sums as 64-bit integer fixed point (2^-38 e/A^2) in LDS, "
+         "per-atom fields as integer-valued f64 fixed point (2^-40 e/A^2); f64 PCG vectors, dot products "
+         "and convergence test; f32 network")
 
 
 def log(msg):

@@ -11,15 +11,19 @@
 //      padded with phantom atoms;
 //   3. every block gets a bounding box; block pairs whose boxes come within cutoff + buffer
 //      are candidates (the adjacency of the paper's block matrix; each unordered pair once,
-//      block I taking J = I + 1 .. I + nb/2 circularly, so all blocks scan equally many);
+//      block I taking the J with J - I mod nb in 1 .. nb/2).  The blocks are binned by their
+//      box centres into a grid whose cells are at least twice the largest half-extent plus
+//      cutoff + buffer wide, so the candidates of a block lie in the 27 cells around its own;
+//      a box too small for three cells per axis scans all blocks J = I + 1 .. I + nb/2;
 //   4. list filtering: the atoms of candidate blocks that lie within cutoff + buffer of ANY
-//      atom of block I are kept, in (J, slot) order, and packed into 64-atom tiles; each block
-//      also owns its diagonal tile (I, I).
+//      atom of block I are kept, in a fixed order (neighbour cell, J, slot; or J, slot), and
+//      packed into 64-atom tiles; each block also owns its diagonal tile (I, I).
 // Per configuration (every call that takes positions):
 //   5. positions are gathered into slot order, checked for NaN and for list staleness, each
 //      block gets an FP64 origin and FP32/FP64 offsets, and every tile gets its in-cutoff
 //      bitmasks (bit k of row i: |r_i - r_jk| < rc) and the j positions relative to the
 //      i-block origin, computed in FP64.
+#include <algorithm>
 #include <cmath>
 
 #include <rocprim/device/device_radix_sort.hpp>
@@ -41,19 +45,15 @@ __device__ __forceinline__ double wrap_box(double x, double L)
 // col | xq.  The sort is stable and the values are the atom indices in increasing order, so that
 // equal keys keep index order and the result is deterministic.  The largest column value is kept
 // for non-finite positions, which sort last (the gather check reports them).
-// Also clears the build's status words (error flags, the block extent maxima of k_bbox).
+// Also clears the build's error flags.
 constexpr int kXBits = 12;
-constexpr int kExtSlots = 32;  // block-extent maxima kept in this many slots (less atomic contention)
 
 __global__ void k_sort_keys(int n, const double* __restrict__ pos, double3 box, int ny, int nz, int colbits,
-                            unsigned* __restrict__ keys, int* __restrict__ vals, int* __restrict__ flags,
-                            unsigned long long* __restrict__ extent_bits)
+                            unsigned* __restrict__ keys, int* __restrict__ vals, int* __restrict__ flags)
 {
     int a = blockIdx.x * blockDim.x + threadIdx.x;
     if (a == 0)
         flags[0] = 0;
-    if (a < 3 * kExtSlots)
-        extent_bits[a] = 0ull;
     if (a >= n)
         return;
     double x = wrap_box(pos[3 * a], box.x), y = wrap_box(pos[3 * a + 1], box.y),
@@ -260,43 +260,60 @@ __global__ void k_csr_fill(int npad, const int* __restrict__ perm, const int* __
     }
 }
 
-// Gather caller positions into slot order, wrap into the box, flag NaN/Inf and (if a reference
-// exists) atoms that moved more than buffer/2 since the list build.
+// Caller positions into slot order (one thread per atom, reading in the caller's order and
+// writing its slot), wrapped into the box; flags NaN/Inf, a changed configuration and (if a
+// reference exists) atoms that moved more than buffer/2 since the list build.
 // ref_out (list build): also keep the positions as the reference of the staleness test.
-__global__ void k_gather_pos(int npad, const int* __restrict__ perm, const double* __restrict__ pos,
-                             double3 box, double4* __restrict__ pos_s, const double4* __restrict__ ref,
-                             double half_buf2, int* __restrict__ flags, double4* __restrict__ ref_out)
+// Flags go to one device word that every workgroup may set; same-address device atomics are
+// serialized, so each workgroup ORs its flags in LDS first and issues at most one atomic, and
+// the grid is capped at kScatterWG workgroups (grid-stride loop).
+constexpr int kScatterWG = 1024;
+
+__global__ __launch_bounds__(256) void k_scatter_pos(int n, int npad, const int* __restrict__ slot,
+                                                     const double* __restrict__ pos, double3 box,
+                                                     double4* __restrict__ pos_s, const double4* __restrict__ ref,
+                                                     double half_buf2, int* __restrict__ flags,
+                                                     double4* __restrict__ ref_out)
 {
-    int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= npad)
-        return;
-    int a = perm[s];
-    if (a < 0) {
-        pos_s[s] = make_double4(0.0, 0.0, 0.0, 0.0);
-        if (ref_out)
-            ref_out[s] = make_double4(0.0, 0.0, 0.0, 0.0);
-        return;
+    __shared__ int s_f;
+    if (threadIdx.x == 0)
+        s_f = 0;
+    __syncthreads();
+    int f = 0;
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < npad; t += gridDim.x * blockDim.x) {
+        if (t < n) {
+            const int s = slot[t];
+            double x = pos[3 * t], y = pos[3 * t + 1], z = pos[3 * t + 2];
+            if (!isfinite(x) || !isfinite(y) || !isfinite(z)) {
+                f |= kFlagNonFinite;
+                x = y = z = 0.0;
+            }
+            x = wrap_box(x, box.x);
+            y = wrap_box(y, box.y);
+            z = wrap_box(z, box.z);
+            const double4 old = pos_s[s];
+            if (old.x != x || old.y != y || old.z != z)
+                f |= kFlagChanged;
+            if (ref) {
+                const double4 r0 = ref[s];
+                const double dx = mimg(x - r0.x, box.x), dy = mimg(y - r0.y, box.y), dz = mimg(z - r0.z, box.z);
+                if (dx * dx + dy * dy + dz * dz > half_buf2)
+                    f |= kFlagStale;
+            }
+            pos_s[s] = make_double4(x, y, z, 0.0);
+            if (ref_out)
+                ref_out[s] = make_double4(x, y, z, 0.0);
+        } else {  // phantom slots n .. npad-1
+            pos_s[t] = make_double4(0.0, 0.0, 0.0, 0.0);
+            if (ref_out)
+                ref_out[t] = make_double4(0.0, 0.0, 0.0, 0.0);
+        }
     }
-    double x = pos[3 * a], y = pos[3 * a + 1], z = pos[3 * a + 2];
-    if (!isfinite(x) || !isfinite(y) || !isfinite(z)) {
-        atomicOr(flags, kFlagNonFinite);
-        x = y = z = 0.0;
-    }
-    x = wrap_box(x, box.x);
-    y = wrap_box(y, box.y);
-    z = wrap_box(z, box.z);
-    double4 old = pos_s[s];
-    if (old.x != x || old.y != y || old.z != z)
-        atomicOr(flags, kFlagChanged);
-    pos_s[s] = make_double4(x, y, z, 0.0);
-    if (ref_out)
-        ref_out[s] = make_double4(x, y, z, 0.0);
-    if (ref) {
-        double4 r0 = ref[s];
-        double dx = mimg(x - r0.x, box.x), dy = mimg(y - r0.y, box.y), dz = mimg(z - r0.z, box.z);
-        if (dx * dx + dy * dy + dz * dz > half_buf2)
-            atomicOr(flags, kFlagStale);
-    }
+    if (f != 0)
+        atomicOr(&s_f, f);
+    __syncthreads();
+    if (threadIdx.x == 0 && s_f != 0)
+        atomicOr(flags, s_f);
 }
 
 // Block origin = FP64 position of the block's first atom; per-atom minimum-image offsets.
@@ -325,8 +342,7 @@ __global__ void k_block_frame(int npad, const int* __restrict__ perm, const doub
 // Bounding box of each block in coordinates unwrapped around its first atom.
 __global__ __launch_bounds__(64) void k_bbox(int nb, const int* __restrict__ perm,
                                              const double4* __restrict__ pos_s, double3 box,
-                                             double4* __restrict__ bc, double4* __restrict__ bh,
-                                             unsigned long long* __restrict__ extent_bits)
+                                             double4* __restrict__ bc, double4* __restrict__ bh)
 {
     int I = blockIdx.x, lane = threadIdx.x;
     int s = I * kBlock + lane;
@@ -351,14 +367,98 @@ __global__ __launch_bounds__(64) void k_bbox(int nb, const int* __restrict__ per
         const double hx = 0.5 * (mxx - mnx), hy = 0.5 * (mxy - mny), hz = 0.5 * (mxz - mnz);
         bc[I] = make_double4(o.x + 0.5 * (mnx + mxx), o.y + 0.5 * (mny + mxy), o.z + 0.5 * (mnz + mxz), 0.0);
         bh[I] = make_double4(hx, hy, hz, 0.0);
-        // largest half-extent per axis over the blocks of slot I mod kExtSlots (the filter takes
-        // the maximum over the slots): non-negative doubles order as their bit patterns, so an
-        // integer maximum is exact and order-independent
-        unsigned long long* slot = extent_bits + 3 * (I % kExtSlots);
-        atomicMax(&slot[0], (unsigned long long)__double_as_longlong(hx));
-        atomicMax(&slot[1], (unsigned long long)__double_as_longlong(hy));
-        atomicMax(&slot[2], (unsigned long long)__double_as_longlong(hz));
     }
+}
+
+// Block grid of the candidate search.  grid[0] = 1 when it is used, grid[1..3] = cells per
+// axis.  A cell is at least 2 h_max + rcb (+ a margin) wide on every axis, h_max the largest
+// block half-extent on that axis, so two blocks whose boxes come within rcb have centres
+// closer than one cell (periodically) and sit in the same or adjacent cells; with three or more
+// cells per axis the 27 cells around a block are distinct.
+constexpr double kCellMargin = 0.01;  // A
+
+__device__ __forceinline__ int cell_of(double v, double L, int n)
+{
+    const double y = wrap_box(v, L) * (double)n / L;
+    const int c = (y == y) ? (int)y : 0;  // a non-finite centre (reported by the build) goes to cell 0
+    return min(max(c, 0), n - 1);
+}
+
+// One workgroup: the largest half-extent per axis (ext_out, read by the host after the build),
+// and the grid shape.
+__global__ __launch_bounds__(1024) void k_block_grid(int nb, const double4* __restrict__ bh, double3 box,
+                                                     double rcb, int3 ncap, double* __restrict__ ext_out,
+                                                     int* __restrict__ grid)
+{
+    __shared__ double s_m[3][16];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    double m[3] = {0.0, 0.0, 0.0};
+    for (int b = tid; b < nb; b += 1024) {
+        const double4 h = bh[b];
+        m[0] = fmax(m[0], h.x);
+        m[1] = fmax(m[1], h.y);
+        m[2] = fmax(m[2], h.z);
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        for (int off = 32; off > 0; off >>= 1)
+            m[a] = fmax(m[a], __shfl_xor(m[a], off));
+        if (lane == 0)
+            s_m[a][w] = m[a];
+    }
+    __syncthreads();
+    if (tid == 0) {
+        const double L[3] = {box.x, box.y, box.z};
+        const int cap[3] = {ncap.x, ncap.y, ncap.z};
+        bool use = true;
+        for (int a = 0; a < 3; ++a) {
+            double e = 0.0;
+            for (int k = 0; k < 16; ++k)
+                e = fmax(e, s_m[a][k]);
+            ext_out[a] = e;
+            const double cells = floor(L[a] / (2.0 * e + rcb + kCellMargin));
+            const int nc = cells >= (double)cap[a] ? cap[a] : (int)fmax(cells, 1.0);
+            grid[1 + a] = nc;
+            use = use && nc >= 3;
+        }
+        grid[0] = use ? 1 : 0;
+    }
+}
+
+// Sort key of block b: its cell (x fastest), or 0 when the grid is not used.
+__global__ void k_block_cell(int nb, const double4* __restrict__ bc, double3 box, const int* __restrict__ grid,
+                             unsigned* __restrict__ keys, int* __restrict__ vals)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nb)
+        return;
+    unsigned key = 0u;
+    if (grid[0]) {
+        const double4 c = bc[b];
+        const int nx = grid[1], ny = grid[2], nz = grid[3];
+        key = (unsigned)((cell_of(c.z, box.z, nz) * ny + cell_of(c.y, box.y, ny)) * nx + cell_of(c.x, box.x, nx));
+    }
+    keys[b] = key;
+    vals[b] = b;
+}
+
+// cell_start[c] = the first position of cell c in the sorted keys (c = 0 .. number of cells).
+__global__ void k_cell_start(int nb, int ncell_cap, const unsigned* __restrict__ skeys, const int* __restrict__ grid,
+                             int* __restrict__ cell_start)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    const int ncell = grid[0] ? grid[1] * grid[2] * grid[3] : 0;
+    if (c > ncell || c > ncell_cap)
+        return;
+    int lo = 0, hi = nb;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (skeys[mid] < (unsigned)c)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    cell_start[c] = lo;
 }
 
 
@@ -413,21 +513,23 @@ __device__ __forceinline__ bool near_block(const float4* s_i, const float4* s_gc
     return keep;
 }
 
-// List filtering: for block I, the atoms of the blocks J = I + d (mod nb), d = 1 .. floor(nb/2)
-// (d = nb/2 only for I < nb/2), within rcb of any atom of I, in (d, slot) order.  Every
-// unordered block pair is examined exactly once and every block scans the same number of
-// candidates.  Chunks of 256 candidates: each thread tests one candidate's bounding box, the
-// waves test the candidates' atoms against the block's atoms (FP32 distances with a 1e-3 A
-// margin: the filter only has to keep a superset, the masks of every configuration decide at
-// rc in FP64), and the kept atoms are written at offsets from an ordered scan, so the list
-// does not depend on scheduling.
+// List filtering: for block I, the atoms of the blocks J with J - I mod nb = d in 1 .. nb/2
+// (d = nb/2 only for I < nb/2) that lie within rcb of any atom of I.  Every unordered block
+// pair is examined exactly once.  The candidate blocks J are those of the 27 grid cells around
+// I's cell (k_block_grid), in (cell, J) order, or all J = I + 1 .. I + nb/2 in d order when
+// the grid is not used.  Chunks of 256 candidates: each thread tests one candidate's bounding
+// box, the waves test the candidates' atoms against the block's atoms (FP32 distances with a
+// 1e-3 A margin: the filter only has to keep a superset, the masks of every configuration
+// decide at rc in FP64), and the kept atoms are written at offsets from an ordered scan, so
+// the list does not depend on scheduling.
 constexpr int kFiltChunk = 256;
 
 __global__ __launch_bounds__(256) void k_filter(int nb, const int* __restrict__ perm,
                                                 const double4* __restrict__ pos_s,
                                                 const double4* __restrict__ bc, const double4* __restrict__ bh,
-                                                const unsigned long long* __restrict__ ext_slots,
-                                                double* __restrict__ ext_out, double3 box, double3 binv,
+                                                const double* __restrict__ ext_in, const int* __restrict__ grid,
+                                                const int* __restrict__ cell_blk,
+                                                const int* __restrict__ cell_start, double3 box, double3 binv,
                                                 double rcb, int* __restrict__ row_count, int* __restrict__ row_j,
                                                 int* __restrict__ tpb, int* __restrict__ flags)
 {
@@ -437,8 +539,22 @@ __global__ __launch_bounds__(256) void k_filter(int nb, const int* __restrict__ 
     __shared__ int s_off[kFiltChunk + 1];
     __shared__ int s_wn[4], s_wk[4];
     __shared__ float4 s_gc[8], s_gh[8];                  // boxes of the eight 8-atom groups
+    __shared__ int s_cs[27], s_cp[28];                   // neighbour cells: first entry, prefix of sizes
     const int I = blockIdx.x, tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
     const double4 ci = bc[I], hi = bh[I];
+    const bool cells = grid[0] != 0;
+    if (cells && tid < 27) {
+        const int nx = grid[1], ny = grid[2], nz = grid[3];
+        const int cx = cell_of(ci.x, box.x, nx), cy = cell_of(ci.y, box.y, ny), cz = cell_of(ci.z, box.z, nz);
+        int x = cx + tid % 3 - 1, y = cy + (tid / 3) % 3 - 1, z = cz + tid / 9 - 1;
+        x += x < 0 ? nx : (x >= nx ? -nx : 0);
+        y += y < 0 ? ny : (y >= ny ? -ny : 0);
+        z += z < 0 ? nz : (z >= nz ? -nz : 0);
+        const int c = (z * ny + y) * nx + x;
+        const int a = cell_start[c];
+        s_cs[tid] = a;
+        s_cp[tid + 1] = cell_start[c + 1] - a;
+    }
     if (tid < kBlock) {
         const int si = I * kBlock + tid;
         const double4 pi = pos_s[si];
@@ -470,27 +586,42 @@ __global__ __launch_bounds__(256) void k_filter(int nb, const int* __restrict__ 
     const float hxf = (float)hi.x + 1e-3f, hyf = (float)hi.y + 1e-3f, hzf = (float)hi.z + 1e-3f;
     const float Lx = (float)box.x, Ly = (float)box.y, Lz = (float)box.z;
     const float Lix = (float)binv.x, Liy = (float)binv.y, Liz = (float)binv.z;
-    // largest block half-extents (workgroup 0 also writes them for the host)
-    double ext[3] = {0.0, 0.0, 0.0};
-    for (int k = 0; k < kExtSlots; ++k)
-#pragma unroll
-        for (int a = 0; a < 3; ++a)
-            ext[a] = fmax(ext[a], __longlong_as_double((long long)ext_slots[3 * k + a]));
-    if (I == 0 && tid < 3)
-        ext_out[tid] = ext[tid];
-    // pair offsets |q - j| <= h_I + (h_I + rcb + margins) <= 2 h_max + rcb
+    // largest block half-extents; pair offsets |q - j| <= h_I + (h_I + rcb + margins) <= 2 h_max + rcb
+    const double ext[3] = {ext_in[0], ext_in[1], ext_in[2]};
     const bool mi = !(2.0 * ext[0] + rcb + 0.01 < 0.5 * box.x && 2.0 * ext[1] + rcb + 0.01 < 0.5 * box.y &&
                       2.0 * ext[2] + rcb + 0.01 < 0.5 * box.z);
     const int dmax = (nb % 2 == 0 && I < nb / 2) ? nb / 2 : (nb - 1) / 2;
+    __syncthreads();
+    if (cells && tid == 0) {
+        s_cp[0] = 0;
+        for (int k = 1; k <= 27; ++k)
+            s_cp[k] += s_cp[k - 1];
+    }
+    __syncthreads();
+    const int ncand = cells ? s_cp[27] : dmax;
     int count = 0;
-    for (int d0 = 1; d0 <= dmax; d0 += kFiltChunk) {
+    for (int g0 = 0; g0 < ncand; g0 += kFiltChunk) {
         __syncthreads();
         {
-            const int d = d0 + tid;
-            int J = I + d;
-            J -= J >= nb ? nb : 0;
+            const int g = g0 + tid;
+            int J = 0;
+            bool inwin = false;
+            if (g < ncand) {
+                if (cells) {
+                    int k = 0;
+                    while (s_cp[k + 1] <= g)
+                        ++k;
+                    J = cell_blk[s_cs[k] + g - s_cp[k]];
+                    const int d = J - I + (J < I ? nb : 0);
+                    inwin = d >= 1 && d <= dmax;
+                } else {
+                    J = I + 1 + g;
+                    J -= J >= nb ? nb : 0;
+                    inwin = true;
+                }
+            }
             bool cand = false;
-            if (d <= dmax) {
+            if (inwin) {
                 const double4 cj = bc[J], hj = bh[J];
                 double dx = fabs(mimg_fp64(ci.x - cj.x, box.x, binv.x)) - hi.x - hj.x;
                 double dy = fabs(mimg_fp64(ci.y - cj.y, box.y, binv.y)) - hi.y - hj.y;
@@ -798,7 +929,8 @@ static int refresh_tiles(amoeba_ctx* c)
     return AMOEBA_OK;
 }
 
-int build_blocklist(amoeba_ctx* c, const double* pos)
+// Steps 1-4 of the build (everything before the first mask refresh).
+static int build_tiles(amoeba_ctx* c, const double* pos)
 {
     hipStream_t st = c->stream;
     const int n = c->n, nb = c->nb, npad = c->npad;
@@ -830,10 +962,28 @@ int build_blocklist(amoeba_ctx* c, const double* pos)
             (rc = ctx_alloc(c, (void**)&c->b_tpb, sizeof(int) * (nb + 1))) ||
             (rc = ctx_alloc(c, (void**)&c->rev_cnt, sizeof(int) * (npad + 1))))
             return rc;
-        size_t tb = 0;
+        // block grid: at most floor(L / rcb) cells per axis (the cell width is at least rcb),
+        // and not many more cells than blocks
+        const double rcb = c->prm.cutoff + c->prm.buffer;
+        for (int a = 0; a < 3; ++a)
+            c->b_ncap[a] = (int)std::max(1.0, std::min(1024.0, std::floor(c->prm.box[a] / rcb)));
+        auto ncells = [&]() { return (long long)c->b_ncap[0] * c->b_ncap[1] * c->b_ncap[2]; };
+        while (ncells() > 2ll * nb + 27) {
+            int* big = std::max_element(c->b_ncap, c->b_ncap + 3);
+            if (*big <= 3)
+                break;
+            --*big;
+        }
+        c->b_ncell_cap = (int)ncells();
+        if ((rc = ctx_alloc(c, (void**)&c->b_cell_start, sizeof(int) * ((size_t)c->b_ncell_cap + 1))))
+            return rc;
+        size_t tb = 0, tb2 = 0;
         if (rocprim::radix_sort_pairs(nullptr, tb, c->b_keys, c->b_keys2, c->b_vals, c->b_vals2, n, 0u, 32u, st) !=
-            hipSuccess)
+                hipSuccess ||
+            rocprim::radix_sort_pairs(nullptr, tb2, c->b_keys, c->b_keys2, c->b_vals, c->b_vals2, nb, 0u, 32u, st) !=
+                hipSuccess)
             return set_error(c, AMOEBA_E_DEVICE, "build_blocklist: radix sort size query failed");
+        tb = std::max(tb, tb2);
         if ((rc = ctx_alloc(c, &c->b_sort_tmp, tb)))
             return rc;
         c->b_sort_bytes = tb;
@@ -843,11 +993,11 @@ int build_blocklist(amoeba_ctx* c, const double* pos)
     int *row_count = c->b_rowc, *row_j = c->b_rowj, *tpb = c->b_tpb, *t0 = c->blk_tile0;
     auto fail = [&](int code) { return code; };
     // build status words, read back with one copy: flags[0] error flags, flags[1] the tile
-    // count, flags[4..9] the largest block half-extents (b_extent); flags[64..255] the slots
-    // k_bbox collects the half-extents in
-    unsigned long long* ext_slots = reinterpret_cast<unsigned long long*>(c->flags + 64);
-    hipLaunchKernelGGL(k_sort_keys, dim3(nblk(std::max(n, 3 * kExtSlots), 256)), dim3(256), 0, st, n, pos, box, ny,
-                       nz, colbits, keys, c->b_vals, c->flags, ext_slots);
+    // count, flags[4..9] the largest block half-extents (b_extent); flags[16..19] the block grid
+    // (device only)
+    int* grid = c->flags + 16;
+    hipLaunchKernelGGL(k_sort_keys, dim3(nblk(n, 256)), dim3(256), 0, st, n, pos, box, ny, nz, colbits, keys,
+                       c->b_vals, c->flags);
     {
         size_t tb = c->b_sort_bytes;
         if (rocprim::radix_sort_pairs(c->b_sort_tmp, tb, keys, c->b_keys2, c->b_vals, c->b_vals2, n, 0u, end_bit,
@@ -858,13 +1008,28 @@ int build_blocklist(amoeba_ctx* c, const double* pos)
     if (c->atoms_set && (rc = sort_params(c)) != AMOEBA_OK)
         return fail(rc);
 
-    hipLaunchKernelGGL(k_gather_pos, dim3(nblk(npad, 256)), dim3(256), 0, st, npad, c->perm, pos, box, c->pos_s,
-                       (const double4*)nullptr, 0.0, c->flags, c->pos_ref);
-    hipLaunchKernelGGL(k_bbox, dim3(nb), dim3(64), 0, st, nb, c->perm, c->pos_s, box, bc, bh, ext_slots);
+    hipLaunchKernelGGL(k_scatter_pos, dim3(std::min(nblk(npad, 256), kScatterWG)), dim3(256), 0, st, n, npad,
+                       c->slot, pos, box,
+                       c->pos_s, (const double4*)nullptr, 0.0, c->flags, c->pos_ref);
+    hipLaunchKernelGGL(k_bbox, dim3(nb), dim3(64), 0, st, nb, c->perm, c->pos_s, box, bc, bh);
+    const double rcb = c->prm.cutoff + c->prm.buffer;
+    hipLaunchKernelGGL(k_block_grid, dim3(1), dim3(1024), 0, st, nb, bh, box, rcb,
+                       make_int3(c->b_ncap[0], c->b_ncap[1], c->b_ncap[2]), c->b_extent, grid);
+    hipLaunchKernelGGL(k_block_cell, dim3(nblk(nb, 256)), dim3(256), 0, st, nb, bc, box, grid, c->b_keys,
+                       c->b_vals);
+    {
+        // stable: the blocks of a cell stay in index order
+        size_t tb = c->b_sort_bytes;
+        const unsigned cell_bits = (unsigned)bits_for((long long)c->b_ncell_cap + 1);
+        if (rocprim::radix_sort_pairs(c->b_sort_tmp, tb, c->b_keys, c->b_keys2, c->b_vals, c->b_vals2, nb, 0u,
+                                      cell_bits, st) != hipSuccess)
+            return set_error(c, AMOEBA_E_DEVICE, "build_blocklist: block sort failed");
+    }
+    hipLaunchKernelGGL(k_cell_start, dim3(nblk(c->b_ncell_cap + 1, 256)), dim3(256), 0, st, nb, c->b_ncell_cap,
+                       c->b_keys2, grid, c->b_cell_start);
     double3 binv = make_double3(1.0 / box.x, 1.0 / box.y, 1.0 / box.z);
-    hipLaunchKernelGGL(k_filter, dim3(nb), dim3(256), 0, st, nb, c->perm, c->pos_s, bc, bh, ext_slots, c->b_extent,
-                       box, binv,
-                       c->prm.cutoff + c->prm.buffer, row_count, row_j, tpb, c->flags);
+    hipLaunchKernelGGL(k_filter, dim3(nb), dim3(256), 0, st, nb, c->perm, c->pos_s, bc, bh, c->b_extent, grid,
+                       c->b_vals2, c->b_cell_start, box, binv, rcb, row_count, row_j, tpb, c->flags);
     if ((rc = device_scan(c, nb, tpb, t0, c->flags + 1)))
         return rc;
     hipMemcpyAsync(c->flags_host, c->flags, 4 * sizeof(int) + 3 * sizeof(double), hipMemcpyDeviceToHost, st);
@@ -927,6 +1092,18 @@ int build_blocklist(amoeba_ctx* c, const double* pos)
         hipLaunchKernelGGL(k_rev_fill, dim3(nblk(nthr, 256)), dim3(256), 0, st, total, c->tile_blk, t0, c->tile_j,
                            c->rev_ptr, c->rev_cnt, c->rev_idx);
     }
+    return AMOEBA_OK;
+}
+
+int build_blocklist(amoeba_ctx* c, const double* pos)
+{
+    int rc;
+    {
+        StageTimer tm(c, AMOEBA_T_LIST);
+        rc = build_tiles(c, pos);
+    }
+    if (rc != AMOEBA_OK)
+        return rc;
     refresh_tiles(c);   // the pair count is read when amoeba_get_info asks for it
     c->list_built = true;
     c->cfg_valid = true;
@@ -939,7 +1116,8 @@ int prepare_config(amoeba_ctx* c, const double* pos)
     double3 box = make_double3(c->prm.box[0], c->prm.box[1], c->prm.box[2]);
     double hb = 0.5 * c->prm.buffer;
     hipMemsetAsync(c->flags, 0, sizeof(int), st);
-    hipLaunchKernelGGL(k_gather_pos, dim3(nblk(c->npad, 256)), dim3(256), 0, st, c->npad, c->perm, pos, box,
+    hipLaunchKernelGGL(k_scatter_pos, dim3(std::min(nblk(c->npad, 256), kScatterWG)), dim3(256), 0, st, c->n,
+                       c->npad, c->slot, pos, box,
                        c->pos_s, (const double4*)c->pos_ref, hb * hb, c->flags, (double4*)nullptr);
     hipMemcpyAsync(c->flags_host, c->flags, sizeof(int), hipMemcpyDeviceToHost, st);
     int rc = hip_check(c, hipStreamSynchronize(st), "prepare_config");

@@ -275,6 +275,9 @@ struct amoeba_ctx {
     size_t b_sort_bytes = 0;
     double4* b_bc = nullptr;               // [nb] block box centres
     double4* b_bh = nullptr;               // [nb] block box half-extents
+    int* b_cell_start = nullptr;           // [b_ncell_cap + 1] first entry of each cell (block grid)
+    int b_ncap[3] = {1, 1, 1};             // largest block-grid cell count per axis
+    int b_ncell_cap = 0;                   // their product
     int* b_rowc = nullptr;                 // [nb] filtered j count per block
     int* b_rowj = nullptr;                 // [nb * kMaxFiltered]
     int* b_tpb = nullptr;                  // [nb + 1] tiles per block
