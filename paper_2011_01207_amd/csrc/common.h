@@ -59,6 +59,14 @@ __device__ __forceinline__ unsigned long long fixq(float v)
     const double y = fma((double)v, kFixQScale, kFixQMagic);
     return (unsigned long long)(__double_as_longlong(y) - __double_as_longlong(kFixQMagic));
 }
+// The same for a value already multiplied by 2^38 in FP32 (a power-of-two scaling, exact): the
+// widening is exact too, so one FP64 add rounds it exactly as fixq does, to the same integer.
+constexpr float kFixQScaleF = 274877906944.0f;    // 2^38
+__device__ __forceinline__ unsigned long long fixq_scaled(float vs)
+{
+    const double y = (double)vs + kFixQMagic;
+    return (unsigned long long)(__double_as_longlong(y) - __double_as_longlong(kFixQMagic));
+}
 __device__ __forceinline__ double fixq_value(unsigned long long q) { return (double)(long long)q * (1.0 / kFixQScale); }
 
 // Sums of an atom's i-field (eipart) and its tile j-fields (jbuf, listed by the reverse index).

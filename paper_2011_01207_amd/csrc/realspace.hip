@@ -112,6 +112,7 @@ template <bool FIX> struct LdsAcc;
 template <> struct LdsAcc<true> {
     using T = unsigned long long;
     __device__ static void add(T* p, float v) { atomicAdd(p, fixq(v)); }
+    __device__ static void add_scaled(T* p, float vs) { atomicAdd(p, fixq_scaled(vs)); }  // vs = v 2^38
     __device__ static void add_raw(T* p, T q) { atomicAdd(p, q); }
     __device__ static double value(T q) { return fixq_value(q); }
 };
@@ -319,6 +320,9 @@ __device__ __forceinline__ double fma_r(double a, double b, double c) { return f
 template <typename R> struct DipoleKind {
     using R4 = typename V4<R>::T;
     static constexpr int NV = 1;
+    // the j-field is linear in the i dipole (d[0].xyz) and nothing else of the pair uses it, so
+    // with integer sums the i dipoles are held times 2^38 and the j-field comes out scaled
+    static constexpr bool kScaledJ = true;
     __device__ static void load(const R4* src, size_t s, R a, R4* d)
     {
         R4 m = src[s];
@@ -370,6 +374,7 @@ template <typename R> struct DipoleKind {
 // d[2] = (Tyz, Tzz, Thole a, 0).
 template <typename R> struct MultipoleKind {
     using R4 = typename V4<R>::T;
+    static constexpr bool kScaledJ = false;
     static constexpr int NV = 3;
     __device__ static void load(const R4* src, size_t s, R a, R4* d)
     {
@@ -494,6 +499,7 @@ __device__ __forceinline__ void force_pair(T rx, T ry, T rz, T aij, T wij, const
 
 template <typename R> struct ForceKind {
     using R4 = typename V4<R>::T;
+    static constexpr bool kScaledJ = false;
     static constexpr int NV = 4;
     __device__ static void load(const R4* src, size_t s, R a, R4* d)
     {
@@ -559,6 +565,7 @@ __global__ __launch_bounds__(256) void k_block_tiles(int nb, const int* __restri
     using R2 = typename V2<R>::T;
     using LT = typename LdsAcc<FIX>::T;
     constexpr int NV = K::NV;
+    constexpr bool SJ = FIX && K::kScaledJ;  // i dipoles held times 2^38, j-fields added pre-scaled
     __shared__ R4 s_ip[kBlock];                      // i offset from the block origin, w = alpha^-1/6
     __shared__ R4 s_id[NV][kBlock];                  // i source data
     __shared__ R4 s_jp[kWavesPerWG][kBlock];         // j offset from the i-block origin, w = alpha^-1/6
@@ -578,6 +585,11 @@ __global__ __launch_bounds__(256) void k_block_tiles(int nb, const int* __restri
         s_ip[tid] = R4{oi.x, oi.y, oi.z, pi.z};
         R4 d[NV];
         K::load(src, si, pi.w, d);
+        if constexpr (SJ) {
+            d[0].x *= kFixQScaleF;
+            d[0].y *= kFixQScaleF;
+            d[0].z *= kFixQScaleF;
+        }
 #pragma unroll
         for (int v = 0; v < NV; ++v)
             s_id[v][tid] = d[v];
@@ -693,8 +705,12 @@ __global__ __launch_bounds__(256) void k_block_tiles(int nb, const int* __restri
                 R ej[3];
                 eval(s_jp[w][k], dj, ej);
 #pragma unroll
-                for (int c = 0; c < 3; ++c)
-                    LdsAcc<FIX>::add(&s_ej[w][c][k], ej[c]);
+                for (int c = 0; c < 3; ++c) {
+                    if constexpr (SJ)
+                        LdsAcc<FIX>::add_scaled(&s_ej[w][c][k], ej[c]);
+                    else
+                        LdsAcc<FIX>::add(&s_ej[w][c][k], ej[c]);
+                }
             };
             const int n = p1 - p0;
             bool replayed = false;
