@@ -192,7 +192,8 @@ struct amoeba_ctx {
     int nbricks = 0;
     size_t ngrid = 0, ncgrid = 0;
     void* grid_r = nullptr;        // real grid (float or double) [K0][K1][K2]
-    void* grid_c = nullptr;        // complex half grid [K0][K1][K2/2+1]
+    void* grid_c = nullptr;        // complex half grid [K0][K1][K2/2+1] (plane path: rows padded)
+    void* theta_pl = nullptr;      // influence function in the plane path's column-chunk layout
     void* theta = nullptr;         // influence function on the half grid (float or double)
     int32_t* bin_start = nullptr;  // [nbricks+1] atoms binned by the brick of their base point
     int32_t* bin_atoms = nullptr;  // [npad]
@@ -372,6 +373,8 @@ void pme_scan_excl(amoeba_ctx* c, int n, const int* in, int* out);
 
 // plane.hip
 bool plane_eligible(const amoeba_ctx* c);
+int plane_row_stride(const amoeba_ctx* c);  // row stride of the plane path's half grid (complex values)
+void plane_column_chunks(const amoeba_ctx* c, int* kc, int* nkc);  // its column chunks (width, count)
 int plane_setup(amoeba_ctx* c);
 int plane_bin_atoms(amoeba_ctx* c);
 void plane_dipole_field(amoeba_ctx* c, bool use_done, int parts);  // 1 spread, 2 the rest, 3 all

@@ -43,7 +43,7 @@ constexpr int kPlThreads = 512;         // threads per workgroup of the row-chun
 constexpr int kPlThreadsLarge = 256;    // the same on large grids, in smaller row chunks
 constexpr int kPlLargeWG = 1024;        // row-chunk workgroups of 512 threads above which a grid is large
 constexpr int kPlTargetWGLarge = 3456;  // row-chunk workgroups the chunking aims at on a large grid
-constexpr int kPlColMaxKc = 14;         // columns per column chunk at most on a large grid
+constexpr int kPlColMaxKc = 16;         // columns per column chunk at most on a large grid
 constexpr int kPlColThreads = 256;      // threads per workgroup of the column passes (y and x lines)
 constexpr int kPlMaxB = 1;              // butterflies per thread in one FFT round (row passes)
 constexpr int kPlColMaxB = 2;           // the same in the column passes: a stage's lines in one round
@@ -277,10 +277,13 @@ struct PlaneGeom {
     int nt;       // threads per workgroup of the row-chunk passes
     int K0, K1, K2;
     int kh;       // K2 / 2 + 1
+    int ks;       // row stride of G (complex values): kh rounded up to whole 128-byte lines
     int S;        // line stride of a pair (complex values): 2 kh
     int P;        // row pairs: ceil(K1 / 2)
     int Pc, nyc;  // pairs per row chunk, row chunks
     int kc, nkc;  // columns per column chunk, column chunks
+    int kl;       // LDS line stride of a column chunk (kc made odd: whole-line strides put every
+                  // point of a transform stage in one LDS bank)
     double klx, kly, klz;
 };
 
@@ -538,11 +541,11 @@ __global__ __launch_bounds__(NT) void k_pme_spread_z(PlaneGeom g, PlaneDim dz,
             __syncthreads();
         }
     }
-    C* out = gout + ((size_t)x * g.K1 + rc.ya) * g.kh;
+    C* out = gout + ((size_t)x * g.K1 + rc.ya) * g.ks;
     const SmallDiv dkh(g.kh);
     for (int i = tid; i < nyr * g.kh; i += NT) {
         const int yl = dkh.quot(i), k = i - yl * g.kh;
-        out[i] = pl[(yl >> 1) * g.S + (yl & 1) * g.kh + k];
+        out[yl * g.ks + k] = pl[(yl >> 1) * g.S + (yl & 1) * g.kh + k];
     }
 }
 
@@ -565,31 +568,31 @@ __global__ __launch_bounds__(kPlColThreads) void k_pme_ylines(PlaneGeom g, Plane
     const int ncol = min(g.kc, g.kh - kz0);
     const SmallDiv dnc(ncol);
     C* buf = reinterpret_cast<C*>(pl_smem);
-    C* tw = buf + g.K1 * g.kc;
+    C* tw = buf + g.K1 * g.kl;
     for (int i = tid; i < g.K1; i += kPlColThreads)
         tw[i] = roots_y[i];
-    C* base = gc + (size_t)x * g.K1 * g.kh + kz0;
+    C* base = gc + (size_t)x * g.K1 * g.ks + kz0;
     fill_lds<kPlColThreads>(
         g.K1 * ncol, base,
         [&](int i) {
             const int y = dnc.quot(i);
-            return (size_t)y * g.kh + (i - y * ncol);
+            return (size_t)y * g.ks + (i - y * ncol);
         },
         buf,
         [&](int i) {
             const int y = dnc.quot(i);
-            return y * g.kc + (i - y * ncol);
+            return y * g.kl + (i - y * ncol);
         });
     __syncthreads();
-    fft_lines<SIGN, kPlColThreads, kPlColMaxB>(buf, ncol, dy, tw, LineMap{1, 2 * g.kc, g.kc});
+    fft_lines<SIGN, kPlColThreads, kPlColMaxB>(buf, ncol, dy, tw, LineMap{1, 2 * g.kl, g.kl});
     for (int i = tid; i < g.K1 * ncol; i += kPlColThreads) {
         const int y = dnc.quot(i), cc = i - y * ncol;
-        base[(size_t)y * g.kh + cc] = buf[y * g.kc + cc];
+        base[(size_t)y * g.ks + cc] = buf[y * g.kl + cc];
     }
 }
 
 // Pass 3: workgroup (ky, column chunk): the x-lines of G for kz in the chunk: FFT, product with
-// the influence function theta[kx][ky][kz], inverse FFT, in place.
+// the influence function theta (column-chunk layout), inverse FFT, in place.
 template <typename R>
 __global__ __launch_bounds__(kPlColThreads) void k_pme_xconv(PlaneGeom g, PlaneDim dx,
                                                           typename PlT<R>::C* __restrict__ gc,
@@ -608,11 +611,11 @@ __global__ __launch_bounds__(kPlColThreads) void k_pme_xconv(PlaneGeom g, PlaneD
     const int ncol = min(g.kc, g.kh - kz0);
     const SmallDiv dnc(ncol);
     C* buf = reinterpret_cast<C*>(pl_smem);
-    C* tw = buf + g.K0 * g.kc;
+    C* tw = buf + g.K0 * g.kl;
     for (int i = tid; i < g.K0; i += kPlColThreads)
         tw[i] = roots_x[i];
-    const size_t xs = (size_t)g.K1 * g.kh;   // stride of x in G
-    const size_t off = (size_t)ky * g.kh + kz0;
+    const size_t xs = (size_t)g.K1 * g.ks;   // stride of x in G (and theta)
+    const size_t off = (size_t)ky * g.ks + kz0;
     fill_lds<kPlColThreads>(
         g.K0 * ncol, gc,
         [&](int i) {
@@ -622,12 +625,14 @@ __global__ __launch_bounds__(kPlColThreads) void k_pme_xconv(PlaneGeom g, PlaneD
         buf,
         [&](int i) {
             const int xx = dnc.quot(i);
-            return xx * g.kc + (i - xx * ncol);
+            return xx * g.kl + (i - xx * ncol);
         });
     __syncthreads();
-    const LineMap am{1, 2 * g.kc, g.kc};
+    const LineMap am{1, 2 * g.kl, g.kl};
     fft_lines<-1, kPlColThreads, kPlColMaxB>(buf, ncol, dx, tw, am);
-    // product with the influence function; its loads issued kPlLoads at a time
+    // product with the influence function (stored chunk by chunk: this workgroup's block is
+    // contiguous); its loads issued kPlLoads at a time
+    const R* th_blk = theta + (size_t)item * g.K0 * g.kc;
     for (int i0 = tid; i0 < g.K0 * ncol; i0 += kPlLoads * kPlColThreads) {
         R th[kPlLoads];
 #pragma unroll
@@ -635,7 +640,7 @@ __global__ __launch_bounds__(kPlColThreads) void k_pme_xconv(PlaneGeom g, PlaneD
             const int i = i0 + u * kPlColThreads;
             if (i < g.K0 * ncol) {
                 const int kx = dnc.quot(i);
-                th[u] = theta[kx * xs + off + (i - kx * ncol)];
+                th[u] = th_blk[kx * g.kc + (i - kx * ncol)];
             }
         }
 #pragma unroll
@@ -643,10 +648,10 @@ __global__ __launch_bounds__(kPlColThreads) void k_pme_xconv(PlaneGeom g, PlaneD
             const int i = i0 + u * kPlColThreads;
             if (i < g.K0 * ncol) {
                 const int kx = dnc.quot(i), cc = i - kx * ncol;
-                C v = buf[kx * g.kc + cc];
+                C v = buf[kx * g.kl + cc];
                 v.x *= th[u];
                 v.y *= th[u];
-                buf[kx * g.kc + cc] = v;
+                buf[kx * g.kl + cc] = v;
             }
         }
     }
@@ -654,7 +659,7 @@ __global__ __launch_bounds__(kPlColThreads) void k_pme_xconv(PlaneGeom g, PlaneD
     fft_lines<+1, kPlColThreads, kPlColMaxB>(buf, ncol, dx, tw, am);
     for (int i = tid; i < g.K0 * ncol; i += kPlColThreads) {
         const int xx = dnc.quot(i), cc = i - xx * ncol;
-        gc[xx * xs + off + cc] = buf[xx * g.kc + cc];
+        gc[xx * xs + off + cc] = buf[xx * g.kl + cc];
     }
 }
 
@@ -698,7 +703,7 @@ __global__ __launch_bounds__(NT) void k_pme_z_gather(PlaneGeom g, PlaneDim dz,
             const int r = dkh.quot(i), k = i - r * g.kh;
             int gy = rc.ya - 4 + r;
             gy += gy < 0 ? g.K1 : 0;
-            return ((size_t)x * g.K1 + gy) * g.kh + k;
+            return ((size_t)x * g.K1 + gy) * g.ks + k;
         },
         pl,
         [&](int i) {
@@ -979,7 +984,7 @@ static bool plane_factor(int n, PlaneDim& d)
 
 static size_t lds_spread(const PlaneGeom& g, size_t cs) { return 16 * (size_t)g.Pc * g.S + cs * g.K2; }
 static size_t lds_gather(const PlaneGeom& g, size_t cs) { return cs * ((size_t)(g.Pc + 2) * g.S + g.K2); }
-static size_t lds_lines(int N, int kc, size_t cs) { return cs * ((size_t)N * kc + N); }
+static size_t lds_lines(int N, int kc, size_t cs) { return cs * ((size_t)N * (kc | 1) + N); }
 
 static PlaneGeom plane_geom(const amoeba_ctx* c)
 {
@@ -988,9 +993,13 @@ static PlaneGeom plane_geom(const amoeba_ctx* c)
     g.K1 = c->K[1];
     g.K2 = c->K[2];
     g.kh = g.K2 / 2 + 1;
+    const size_t cs = c->mixed ? sizeof(float2) : sizeof(double2);
+    // rows of G start on 128-byte lines and column chunks are whole lines, so the column passes
+    // move whole lines (unaligned rows of a chunk cost about twice the bytes: measured)
+    const int line = (int)(128 / cs);
+    g.ks = cdiv(g.kh, line) * line;
     g.S = 2 * g.kh;
     g.P = (g.K1 + 1) / 2;
-    const size_t cs = c->mixed ? sizeof(float2) : sizeof(double2);
     // row chunks: about kPlTargetWG workgroups of 512 threads, within the LDS and conversion
     // limits; a grid that needs more than kPlLargeWG of them (two 512-thread workgroups fit a CU)
     // takes 256-thread workgroups on smaller chunks, so that more of them are resident at once
@@ -1015,13 +1024,24 @@ static PlaneGeom plane_geom(const amoeba_ctx* c)
     g.kc = cdiv(g.kh, g.nkc);
     if (large)
         g.kc = std::min(g.kc, kPlColMaxKc);
+    g.kc = std::min(cdiv(g.kc, line) * line, g.ks);
     while (g.kc > 1 && (lds_lines(g.K0, g.kc, cs) > kPlLdsMax || lds_lines(g.K1, g.kc, cs) > kPlLdsMax))
         g.kc = cdiv(g.kc, 2);
     g.nkc = cdiv(g.kh, g.kc);
+    g.kl = g.kc | 1;
     g.klx = c->K[0] / c->prm.box[0];
     g.kly = c->K[1] / c->prm.box[1];
     g.klz = c->K[2] / c->prm.box[2];
     return g;
+}
+
+int plane_row_stride(const amoeba_ctx* c) { return plane_geom(c).ks; }
+
+void plane_column_chunks(const amoeba_ctx* c, int* kc, int* nkc)
+{
+    const PlaneGeom g = plane_geom(c);
+    *kc = g.kc;
+    *nkc = g.nkc;
 }
 
 bool plane_eligible(const amoeba_ctx* c)
@@ -1125,7 +1145,7 @@ template <typename R> static void plane_field_t(amoeba_ctx* c, bool use_done, in
         hipLaunchKernelGGL((k_pme_ylines<R, -1>), dim3(g.K0 * g.nkc), ntc, lds_lines(g.K1, g.kc, cs), st, g, d[1], gc,
                            roots[1], c->sc, ud);
         hipLaunchKernelGGL(k_pme_xconv<R>, dim3(g.K1 * g.nkc), ntc, lds_lines(g.K0, g.kc, cs), st, g, d[0], gc,
-                           (const R*)c->theta, roots[0], c->sc, ud);
+                           (const R*)c->theta_pl, roots[0], c->sc, ud);
         hipLaunchKernelGGL((k_pme_ylines<R, 1>), dim3(g.K0 * g.nkc), ntc, lds_lines(g.K1, g.kc, cs), st, g, d[1], gc,
                            roots[1], c->sc, ud);
     }

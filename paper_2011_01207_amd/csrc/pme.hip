@@ -91,9 +91,13 @@ __global__ void k_bsmod(int K, double* __restrict__ mod)
     mod[m] = v;
 }
 
+// theta on the half grid i2 < K2/2 + 1: at (i0 K1 + i1) (K2/2 + 1) + i2 (kc = 0), or in column
+// chunks of kc (the plane path's x pass reads one chunk of one i1 for all i0 in a block):
+// ((i1 nkc + i2 / kc) K0 + i0) kc + i2 mod kc
 template <typename R>
 __global__ void k_theta(int3 K, double3 box, double beta, const double* __restrict__ mx,
-                        const double* __restrict__ my, const double* __restrict__ mz, R* __restrict__ theta)
+                        const double* __restrict__ my, const double* __restrict__ mz, int kc, int nkc,
+                        R* __restrict__ theta)
 {
     int kh = K.z / 2 + 1;
     size_t n = (size_t)K.x * K.y * kh;
@@ -111,7 +115,9 @@ __global__ void k_theta(int3 K, double3 box, double beta, const double* __restri
     double v = 0.0;
     if (i != 0)
         v = exp(-kPi * kPi * msq / (beta * beta)) / (kPi * vol * msq) / (mx[i0] * my[i1] * mz[i2]);
-    theta[i] = (R)v;
+    const size_t at = kc == 0 ? i
+                              : (((size_t)i1 * nkc + i2 / kc) * K.x + i0) * kc + i2 % kc;
+    theta[at] = (R)v;
 }
 
 // ------------------------------------------------------------------------------------------
@@ -762,9 +768,20 @@ int pme_setup(amoeba_ctx* c)
     c->ngrid = (size_t)c->K[0] * c->K[1] * c->K[2];
     c->ncgrid = (size_t)c->K[0] * c->K[1] * (c->K[2] / 2 + 1);
     size_t rs = c->mixed ? sizeof(float) : sizeof(double);
+    // the plane path keeps the half grid with padded rows (its own theta, the shared complex grid
+    // large enough for either layout)
+    const bool planes = plane_eligible(c);
+    const int kh = c->K[2] / 2 + 1, ks = planes ? plane_row_stride(c) : kh;
+    const size_t npl = (size_t)c->K[0] * c->K[1] * ks;
+    int th_kc = 0, th_nkc = 0;
+    if (planes)
+        plane_column_chunks(c, &th_kc, &th_nkc);
+    const size_t nth = (size_t)c->K[0] * c->K[1] * th_kc * th_nkc;
     int rc;
-    if ((rc = ctx_alloc(c, &c->grid_r, rs * c->ngrid)) || (rc = ctx_alloc(c, &c->grid_c, 2 * rs * c->ncgrid)) ||
+    if ((rc = ctx_alloc(c, &c->grid_r, rs * c->ngrid)) ||
+        (rc = ctx_alloc(c, &c->grid_c, 2 * rs * std::max(c->ncgrid, npl))) ||
         (rc = ctx_alloc(c, &c->theta, rs * c->ncgrid)) ||
+        (planes && (rc = ctx_alloc(c, &c->theta_pl, rs * nth))) ||
         (rc = ctx_alloc(c, (void**)&c->sp_base, sizeof(int4) * c->npad)) ||
         (rc = ctx_alloc(c, &c->sp_w, rs * kSpStride * c->npad)) ||
         (rc = ctx_alloc(c, (void**)&c->bin_start, sizeof(int) * (c->nbricks + 1))) ||
@@ -782,12 +799,16 @@ int pme_setup(amoeba_ctx* c)
         hipLaunchKernelGGL(k_bsmod, dim3(nblk(c->K[a], 64)), dim3(64), 0, c->stream, c->K[a], md[a]);
     int3 K = make_int3(c->K[0], c->K[1], c->K[2]);
     double3 box = make_double3(c->prm.box[0], c->prm.box[1], c->prm.box[2]);
-    if (c->mixed)
-        hipLaunchKernelGGL(k_theta<float>, dim3(nblk(c->ncgrid, 256)), dim3(256), 0, c->stream, K, box,
-                           c->prm.ewald_alpha, md[0], md[1], md[2], (float*)c->theta);
-    else
-        hipLaunchKernelGGL(k_theta<double>, dim3(nblk(c->ncgrid, 256)), dim3(256), 0, c->stream, K, box,
-                           c->prm.ewald_alpha, md[0], md[1], md[2], (double*)c->theta);
+    for (int layout = 0; layout < (planes ? 2 : 1); ++layout) {
+        void* th = layout == 0 ? c->theta : c->theta_pl;
+        const int kc = layout == 0 ? 0 : th_kc;
+        if (c->mixed)
+            hipLaunchKernelGGL(k_theta<float>, dim3(nblk(c->ncgrid, 256)), dim3(256), 0, c->stream, K, box,
+                               c->prm.ewald_alpha, md[0], md[1], md[2], kc, th_nkc, (float*)th);
+        else
+            hipLaunchKernelGGL(k_theta<double>, dim3(nblk(c->ncgrid, 256)), dim3(256), 0, c->stream, K, box,
+                               c->prm.ewald_alpha, md[0], md[1], md[2], kc, th_nkc, (double*)th);
+    }
     rc = hip_check(c, hipStreamSynchronize(c->stream), "pme_setup theta");
     hipFree(mods);
     if (rc)
