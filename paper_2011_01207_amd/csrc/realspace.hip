@@ -323,6 +323,12 @@ template <typename R> struct DipoleKind {
     // the j-field is linear in the i dipole (d[0].xyz) and nothing else of the pair uses it, so
     // with integer sums the i dipoles are held times 2^38 and the j-field comes out scaled
     static constexpr bool kScaledJ = true;
+    __device__ static void scale_i(R4* d, R f)
+    {
+        d[0].x *= f;
+        d[0].y *= f;
+        d[0].z *= f;
+    }
     __device__ static void load(const R4* src, size_t s, R a, R4* d)
     {
         R4 m = src[s];
@@ -374,7 +380,22 @@ template <typename R> struct DipoleKind {
 // d[2] = (Tyz, Tzz, Thole a, 0).
 template <typename R> struct MultipoleKind {
     using R4 = typename V4<R>::T;
-    static constexpr bool kScaledJ = false;
+    // the j-field is linear in the i multipoles (everything but the Thole factor d[2].z), which
+    // nothing else of the pair uses: held times 2^38 with integer sums, as for the dipoles
+    static constexpr bool kScaledJ = true;
+    __device__ static void scale_i(R4* d, R f)
+    {
+        d[0].x *= f;
+        d[0].y *= f;
+        d[0].z *= f;
+        d[0].w *= f;
+        d[1].x *= f;
+        d[1].y *= f;
+        d[1].z *= f;
+        d[1].w *= f;
+        d[2].x *= f;
+        d[2].y *= f;
+    }
     static constexpr int NV = 3;
     __device__ static void load(const R4* src, size_t s, R a, R4* d)
     {
@@ -500,6 +521,7 @@ __device__ __forceinline__ void force_pair(T rx, T ry, T rz, T aij, T wij, const
 template <typename R> struct ForceKind {
     using R4 = typename V4<R>::T;
     static constexpr bool kScaledJ = false;
+    __device__ static void scale_i(R4*, R) {}
     static constexpr int NV = 4;
     __device__ static void load(const R4* src, size_t s, R a, R4* d)
     {
@@ -565,7 +587,7 @@ __global__ __launch_bounds__(256) void k_block_tiles(int nb, const int* __restri
     using R2 = typename V2<R>::T;
     using LT = typename LdsAcc<FIX>::T;
     constexpr int NV = K::NV;
-    constexpr bool SJ = FIX && K::kScaledJ;  // i dipoles held times 2^38, j-fields added pre-scaled
+    constexpr bool SJ = FIX && K::kScaledJ;  // i sources held times 2^38, j-fields added pre-scaled
     __shared__ R4 s_ip[kBlock];                      // i offset from the block origin, w = alpha^-1/6
     __shared__ R4 s_id[NV][kBlock];                  // i source data
     __shared__ R4 s_jp[kWavesPerWG][kBlock];         // j offset from the i-block origin, w = alpha^-1/6
@@ -585,11 +607,8 @@ __global__ __launch_bounds__(256) void k_block_tiles(int nb, const int* __restri
         s_ip[tid] = R4{oi.x, oi.y, oi.z, pi.z};
         R4 d[NV];
         K::load(src, si, pi.w, d);
-        if constexpr (SJ) {
-            d[0].x *= kFixQScaleF;
-            d[0].y *= kFixQScaleF;
-            d[0].z *= kFixQScaleF;
-        }
+        if constexpr (SJ)
+            K::scale_i(d, (R)kFixQScaleF);
 #pragma unroll
         for (int v = 0; v < NV; ++v)
             s_id[v][tid] = d[v];
