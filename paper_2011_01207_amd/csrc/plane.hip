@@ -456,6 +456,16 @@ __global__ __launch_bounds__(NT) void k_pme_spread_z(PlaneGeom g, PlaneDim dz,
                 a1 = m[u][0].y * X0;
                 b0 = m[u][0].z * X0;
             }
+            if (FIX) {
+                // every point's value is linear in these: scaled by 2^38 (exactly), the values
+                // arrive in the units of the fixed-point sums
+                a0 *= (R)kFixQScaleF;
+                a1 *= (R)kFixQScaleF;
+                a2 *= (R)kFixQScaleF;
+                b0 *= (R)kFixQScaleF;
+                b1 *= (R)kFixQScaleF;
+                e0 *= (R)kFixQScaleF;
+            }
 #pragma unroll
             for (int ty = 0; ty < 5; ++ty) {
                 int yy = rec[u].z - ty;
@@ -481,7 +491,7 @@ __global__ __launch_bounds__(NT) void k_pme_spread_z(PlaneGeom g, PlaneDim dz,
                     if (PERM)
                         v += c2 * z2[tz];
                     if (FIX)
-                        atomicAdd(reinterpret_cast<unsigned long long*>(row + zi[tz]), fixq((float)v));
+                        atomicAdd(reinterpret_cast<unsigned long long*>(row + zi[tz]), fixq_scaled((float)v));
                     else
                         atomicAdd(row + zi[tz], (double)v);
                 }
