@@ -513,15 +513,38 @@ __device__ __forceinline__ bool near_block(const float4* s_i, const float4* s_gc
     return keep;
 }
 
+// Position of the r-th set bit (from 0) of m, r < popcount(m).
+__device__ __forceinline__ int nth_set_bit(unsigned long long m, int r)
+{
+    unsigned v = (unsigned)m;
+    int base = 0, c = __popc(v);
+    if (r >= c) {
+        r -= c;
+        v = (unsigned)(m >> 32);
+        base = 32;
+    }
+#pragma unroll
+    for (int width = 16; width >= 1; width >>= 1) {
+        c = __popc(v & ((1u << width) - 1u));
+        if (r >= c) {
+            r -= c;
+            v >>= width;
+            base += width;
+        }
+    }
+    return base;
+}
+
 // List filtering: for block I, the atoms of the blocks J with J - I mod nb = d in 1 .. nb/2
 // (d = nb/2 only for I < nb/2) that lie within rcb of any atom of I.  Every unordered block
 // pair is examined exactly once.  The candidate blocks J are those of the 27 grid cells around
 // I's cell (k_block_grid), in (cell, J) order, or all J = I + 1 .. I + nb/2 in d order when
 // the grid is not used.  Chunks of 256 candidates: each thread tests one candidate's bounding
-// box, the waves test the candidates' atoms against the block's atoms (FP32 distances with a
-// 1e-3 A margin: the filter only has to keep a superset, the masks of every configuration
-// decide at rc in FP64), and the kept atoms are written at offsets from an ordered scan, so
-// the list does not depend on scheduling.
+// box; the waves test the candidates' atoms against the block's box, and the atoms within reach
+// of it are queued densely and tested one per thread against the block's atoms (FP32 distances
+// with a 1e-3 A margin: the filter only has to keep a superset, the masks of every
+// configuration decide at rc in FP64); the kept atoms are written at offsets from an ordered
+// scan, so the list does not depend on scheduling.
 constexpr int kFiltChunk = 256;
 
 __global__ __launch_bounds__(256) void k_filter(int nb, const int* __restrict__ perm,
@@ -540,6 +563,8 @@ __global__ __launch_bounds__(256) void k_filter(int nb, const int* __restrict__ 
     __shared__ int s_wn[4], s_wk[4];
     __shared__ float4 s_gc[8], s_gh[8];                  // boxes of the eight 8-atom groups
     __shared__ int s_cs[27], s_cp[28];                   // neighbour cells: first entry, prefix of sizes
+    __shared__ unsigned long long s_inb[kFiltChunk];     // atoms of each candidate within reach of the box
+    __shared__ int s_qoff[kFiltChunk + 1];
     const int I = blockIdx.x, tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
     const double4 ci = bc[I], hi = bh[I];
     const bool cells = grid[0] != 0;
@@ -641,24 +666,62 @@ __global__ __launch_bounds__(256) void k_filter(int nb, const int* __restrict__ 
         }
         const int nc = s_wn[0] + s_wn[1] + s_wn[2] + s_wn[3];
         __syncthreads();
+        // the candidates' atoms within reach of the block's box (one wave per candidate); an
+        // atom outside it is outside reach of every atom in it
         for (int k = w; k < nc; k += 4) {
             const int sj = s_cand[k] * kBlock + lane;
-            bool keep = false;
+            bool inb = false;
             if (perm[sj] >= 0) {
                 const double4 pj = pos_s[sj];
                 const float jx = (float)mimg_fp64(pj.x - ci.x, box.x, binv.x);
                 const float jy = (float)mimg_fp64(pj.y - ci.y, box.y, binv.y);
                 const float jz = (float)mimg_fp64(pj.z - ci.z, box.z, binv.z);
-                // outside rcb of the block's box: outside rcb of every atom in it
                 const float bx = fmaxf(fabsf(jx) - hxf, 0.0f), by = fmaxf(fabsf(jy) - hyf, 0.0f),
                             bz = fmaxf(fabsf(jz) - hzf, 0.0f);
-                if (bx * bx + by * by + bz * bz < rf2)
-                    keep = mi ? near_block<true>(s_i, s_gc, s_gh, jx, jy, jz, rf2, Lx, Ly, Lz, Lix, Liy, Liz)
-                              : near_block<false>(s_i, s_gc, s_gh, jx, jy, jz, rf2, Lx, Ly, Lz, Lix, Liy, Liz);
+                inb = bx * bx + by * by + bz * bz < rf2;
             }
-            const unsigned long long km = __ballot(keep);
+            const unsigned long long m = __ballot(inb);
+            if (lane == 0) {
+                s_inb[k] = m;
+                s_keep[k] = 0ull;
+            }
+        }
+        __syncthreads();
+        {
+            // queue of those atoms: candidate k owns entries s_qoff[k] .. s_qoff[k+1]-1
+            const int k = tid;
+            int tot;
+            const int ex = wave_excl_scan_i(k < nc ? __popcll(s_inb[k]) : 0, lane, tot);
             if (lane == 0)
-                s_keep[k] = km;
+                s_wk[w] = tot;
+            __syncthreads();
+            const int wbase = (w > 0 ? s_wk[0] : 0) + (w > 1 ? s_wk[1] : 0) + (w > 2 ? s_wk[2] : 0);
+            s_qoff[k] = wbase + ex;
+            if (tid == 0)
+                s_qoff[kFiltChunk] = s_wk[0] + s_wk[1] + s_wk[2] + s_wk[3];
+        }
+        __syncthreads();
+        // one queued atom per thread against the block's atoms (dense waves: the atoms outside
+        // the box no longer hold lanes)
+        const int nq = s_qoff[kFiltChunk];
+        for (int e = tid; e < nq; e += kFiltChunk) {
+            int lo = 0, hi = nc - 1;  // the last candidate whose entries start at or before e
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (s_qoff[mid] <= e)
+                    lo = mid;
+                else
+                    hi = mid - 1;
+            }
+            const int bit = nth_set_bit(s_inb[lo], e - s_qoff[lo]);
+            const double4 pj = pos_s[s_cand[lo] * kBlock + bit];
+            const float jx = (float)mimg_fp64(pj.x - ci.x, box.x, binv.x);
+            const float jy = (float)mimg_fp64(pj.y - ci.y, box.y, binv.y);
+            const float jz = (float)mimg_fp64(pj.z - ci.z, box.z, binv.z);
+            const bool keep = mi ? near_block<true>(s_i, s_gc, s_gh, jx, jy, jz, rf2, Lx, Ly, Lz, Lix, Liy, Liz)
+                                 : near_block<false>(s_i, s_gc, s_gh, jx, jy, jz, rf2, Lx, Ly, Lz, Lix, Liy, Liz);
+            if (keep)
+                atomicOr(&s_keep[lo], 1ull << bit);
         }
         __syncthreads();
         {

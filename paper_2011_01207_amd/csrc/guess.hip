@@ -77,7 +77,8 @@ struct GuessOffsets {
 constexpr float kRadialC[3] = {1.0f, 2.0f, 3.0f};
 constexpr float kRadialInvW = 1.0f / 0.6f;
 
-__device__ __forceinline__ float sigm(float a) { return 1.0f / (1.0f + __expf(-a)); }
+// logistic function with the hardware reciprocal (1 ulp) instead of an IEEE division sequence
+__device__ __forceinline__ float sigm(float a) { return __builtin_amdgcn_rcpf(1.0f + __expf(-a)); }
 
 static inline int nblk64(int64_t n, int b) { return (int)((n + b - 1) / b); }
 
@@ -299,51 +300,174 @@ __device__ __forceinline__ float mlp_unit2(const float* __restrict__ w, int k, c
     return a;
 }
 
+// Inference over many samples (the whole box per configuration): the two dense layers are
+// matrix products over tiles of 16 samples on the matrix cores (FP32 in and out,
+// v_mfma_f32_16x16x4f32: A 16x4 with lane l holding A[l mod 16][l div 16], B 4x16 with lane l
+// holding B[l div 16][l mod 16], D 16x16 with lane l holding D[4 (l div 16) + v][l mod 16] in
+// its v-th register).  Layer 1: A = normalised features (11 padded to 12), B = W1^T (in
+// registers).  Its output goes through LDS to become the A operand of layer 2 (B = W2^T, read
+// from LDS, which keeps the register count at three waves per SIMD).  The output layer and the
+// basis combination run on the vector units, each lane summing its units and the 16 lanes of a
+// group adding their partial sums.  The next tile's inputs are loaded during the current one.
+typedef float mfma_f4 __attribute__((ext_vector_type(4)));
+constexpr int kFwdTile = 16;        // samples per tile (one wave)
+constexpr int kFwdMaxWG = 768;      // workgroups at most (grid-stride over the tiles; measured)
+
 __global__ __launch_bounds__(256) void k_guess_forward(int64_t n, const float* __restrict__ w,
                                                        const float* __restrict__ feat,
                                                        const float* __restrict__ basis, GuessOffsets so,
                                                        const int* __restrict__ perm, double* __restrict__ out64,
                                                        float* __restrict__ out32)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n)
-        return;
-    if (perm && perm[i] < 0) {
-        out64[3 * i] = out64[3 * i + 1] = out64[3 * i + 2] = 0.0;
-        return;
+    static_assert(kH == 64 && kNF <= 12 && kNB == 3, "tile shapes of the matrix-core forward");
+    __shared__ float s_h[4][kFwdTile][kH + 1];
+    __shared__ float s_w2t[kH][72];  // W2 transposed: [input unit][output unit]
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int lr = lane & 15, lg = lane >> 4;
+    // operands that every tile uses: B of layer 1 (k = feature 4 s + lg, n = unit 16 nt + lr),
+    // W2 for B of layer 2 (k = input unit 4 s + lg, n = unit 16 nt + lr), biases and output
+    // weights of this lane's units, normalisation of its features
+    float w1b[4][3], bias1[4], bias2[4], w3l[kNB][4], mean[3], inv[3];
+    for (int i = threadIdx.x; i < kH * kH; i += 256)
+        s_w2t[i % kH][i / kH] = w[kOffW2 + i];
+#pragma unroll
+    for (int s3 = 0; s3 < 3; ++s3) {
+        const int f = 4 * s3 + lg;
+        mean[s3] = f < kNF ? w[kOffMean + f] : 0.0f;
+        inv[s3] = f < kNF ? w[kOffInv + f] : 0.0f;
     }
-    float x[kNF];
 #pragma unroll
-    for (int f = 0; f < kNF; ++f)
-        x[f] = feat[i * kNF + f];
-    float a1[kH], h1[kH];
-    mlp_layer1(w, x, a1, h1);
-    float y[kNB];
+    for (int nt = 0; nt < 4; ++nt) {
+        const int u = 16 * nt + lr;
 #pragma unroll
-    for (int c = 0; c < kNB; ++c)
-        y[c] = w[kOffB3 + c];
-    for (int k = 0; k < kH; ++k) {
-        const float a = mlp_unit2(w, k, h1);
-        const float h = a * sigm(a);
+        for (int s3 = 0; s3 < 3; ++s3) {
+            const int f = 4 * s3 + lg;
+            w1b[nt][s3] = f < kNF ? w[u * kNF + f] : 0.0f;
+        }
+        bias1[nt] = w[kOffB1 + u];
+        bias2[nt] = w[kOffB2 + u];
 #pragma unroll
         for (int c = 0; c < kNB; ++c)
-            y[c] = fmaf(w[kOffW3 + c * kH + k], h, y[c]);
+            w3l[c][nt] = w[kOffW3 + c * kH + u];
     }
-    float mu[3] = {0.f, 0.f, 0.f};
+    __syncthreads();
+    const int64_t ntiles = (n + kFwdTile - 1) / kFwdTile;
+    const int64_t stride = (int64_t)gridDim.x * 4;
+    // this lane's inputs of a tile: features (A of layer 1) and, for the lanes that write an
+    // output component, the basis vectors and the slot's phantom flag; the next tile's are
+    // loaded while the current one is computed
+    const int ov = lr / kNB, oc = lr - (lr / kNB) * kNB;  // output sample 4 lg + ov, component oc
+    auto load_tile = [&](int64_t tile, float (&x)[3], float (&bs)[kNB], bool& live) {
+        const int64_t ai = tile * kFwdTile + lr, ao = tile * kFwdTile + 4 * lg + ov;
 #pragma unroll
-    for (int k = 0; k < kNB; ++k)
+        for (int s3 = 0; s3 < 3; ++s3) {
+            const int f = 4 * s3 + lg;
+            x[s3] = (tile < ntiles && ai < n && f < kNF) ? feat[ai * kNF + f] : 0.0f;
+        }
+        live = tile < ntiles && lr < 4 * kNB && ao < n && !(perm && perm[ao] < 0);
 #pragma unroll
-        for (int c = 0; c < 3; ++c)
-            mu[c] = fmaf(so.s[k] + y[k], basis[i * kNB * 3 + k * 3 + c], mu[c]);
-    if (out64) {
+        for (int k = 0; k < kNB; ++k)
+            bs[k] = live ? basis[ao * kNB * 3 + k * 3 + oc] : 0.0f;
+    };
+    float xn[3], bn[kNB];
+    bool ln;
+    load_tile((int64_t)blockIdx.x * 4 + wv, xn, bn, ln);
+    for (int64_t tile = (int64_t)blockIdx.x * 4 + wv; tile < ntiles; tile += stride) {
+        const int64_t a0 = tile * kFwdTile;
+        float xc[3], bc[kNB];
+        const bool lc = ln;
 #pragma unroll
-        for (int c = 0; c < 3; ++c)
-            out64[3 * i + c] = (double)mu[c];
-    } else {
+        for (int k = 0; k < 3; ++k) {
+            xc[k] = xn[k];
+            bc[k] = bn[k];
+        }
+        load_tile(tile + stride, xn, bn, ln);
+        // layer 1
+        mfma_f4 d1[4];
 #pragma unroll
-        for (int c = 0; c < 3; ++c)
-            out32[3 * i + c] = mu[c];
+        for (int nt = 0; nt < 4; ++nt)
+            d1[nt] = mfma_f4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int s3 = 0; s3 < 3; ++s3) {
+            const float xa = (xc[s3] - mean[s3]) * inv[s3];
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt)
+                d1[nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(xa, w1b[nt][s3], d1[nt], 0, 0, 0);
+        }
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const float a = d1[nt][v] + bias1[nt];
+                s_h[wv][4 * lg + v][16 * nt + lr] = a * sigm(a);
+            }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        // layer 2
+        mfma_f4 d2[4];
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt)
+            d2[nt] = mfma_f4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int s16 = 0; s16 < 16; ++s16) {
+            const float ha = s_h[wv][lr][4 * s16 + lg];
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt)
+                d2[nt] = __builtin_amdgcn_mfma_f32_16x16x4f32(ha, s_w2t[4 * s16 + lg][16 * nt + lr], d2[nt], 0, 0, 0);
+        }
+        // output layer: partial sums over this lane's units for the samples 4 lg + v
+        float y[4][kNB];
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+#pragma unroll
+            for (int c = 0; c < kNB; ++c)
+                y[v][c] = 0.0f;
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const float a = d2[nt][v] + bias2[nt];
+                const float h = a * sigm(a);
+#pragma unroll
+                for (int c = 0; c < kNB; ++c)
+                    y[v][c] = fmaf(w3l[c][nt], h, y[v][c]);
+            }
+#pragma unroll
+        for (int off = 1; off < 16; off <<= 1)
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+#pragma unroll
+                for (int c = 0; c < kNB; ++c)
+                    y[v][c] += __shfl_xor(y[v][c], off);
+        // lane lr < 12 of group lg writes component oc of sample 4 lg + ov (phantom slots: 0)
+        const int64_t a = a0 + 4 * lg + ov;
+        if (lr < 4 * kNB && a < n) {
+            float yk[kNB];
+#pragma unroll
+            for (int c = 0; c < kNB; ++c)
+                yk[c] = ov == 0 ? y[0][c] : ov == 1 ? y[1][c] : ov == 2 ? y[2][c] : y[3][c];
+            float mu = 0.0f;
+            if (lc) {
+#pragma unroll
+                for (int k = 0; k < kNB; ++k)
+                    mu = fmaf(so.s[k] + (w[kOffB3 + k] + yk[k]), bc[k], mu);
+            }
+            if (out64)
+                out64[3 * a + oc] = (double)mu;
+            else
+                out32[3 * a + oc] = mu;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
+}
+
+static unsigned forward_grid(int64_t n)
+{
+    const int64_t tiles = (n + kFwdTile - 1) / kFwdTile;
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>((tiles + 3) / 4, kFwdMaxWG));
 }
 
 // ------------------------------------------------------------------------------------------
@@ -714,7 +838,7 @@ int guess_compute(amoeba_ctx* c)
 void guess_forward_slot(amoeba_ctx* c, double* mu_slot)
 {
     StageTimer tm(c, AMOEBA_T_GUESS);
-    hipLaunchKernelGGL(k_guess_forward, dim3(nblk64(c->npad, 256)), dim3(256), 0, c->stream, (int64_t)c->npad,
+    hipLaunchKernelGGL(k_guess_forward, dim3(forward_grid(c->npad)), dim3(256), 0, c->stream, (int64_t)c->npad,
                        c->g_model, c->g_feat, c->g_basis, guess_offsets(c), c->perm, mu_slot, (float*)nullptr);
 }
 
@@ -1083,7 +1207,7 @@ int amoeba_guess_forward(amoeba_ctx* c, const float* feat, const float* basis, i
         return rc;
     {
         StageTimer tm(c, AMOEBA_T_GUESS);
-        hipLaunchKernelGGL(k_guess_forward, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, n,
+        hipLaunchKernelGGL(k_guess_forward, dim3(forward_grid(n)), dim3(256), 0, c->stream, n,
                            c->g_model, feat, basis, guess_offsets(c), (const int*)nullptr, (double*)nullptr, mu_out);
     }
     return hip_check(c, hipStreamSynchronize(c->stream), "amoeba_guess_forward");
