@@ -100,7 +100,7 @@ __global__ __launch_bounds__(256) void k_scan_blocksum(int n, const int* __restr
 }
 
 __global__ __launch_bounds__(256) void k_scan_apply(int n, const int* __restrict__ in, const int* __restrict__ bsum,
-                                                    int* __restrict__ out)
+                                                    int* __restrict__ out, int* __restrict__ total_copy)
 {
     __shared__ int sh[256];
     __shared__ int s_boff;
@@ -142,8 +142,11 @@ __global__ __launch_bounds__(256) void k_scan_apply(int n, const int* __restrict
             out[i] = run;
         run += v[u];
     }
-    if (blockIdx.x == gridDim.x - 1 && t == 255)
+    if (blockIdx.x == gridDim.x - 1 && t == 255) {
         out[n] = run;
+        if (total_copy)
+            *total_copy = run;
+    }
 }
 
 
@@ -915,20 +918,24 @@ __global__ __launch_bounds__(256) void k_sum_pairs(int n, const unsigned long lo
 
 static inline int nblk(long n, int b) { return (int)((n + b - 1) / b); }
 
+constexpr int kScanOneWG = 8192;  // longest array scanned by one workgroup (measured)
+
 int device_scan(amoeba_ctx* c, int n, const int* in, int* out, int* total_copy)
 {
+    // one workgroup walks short arrays in tiles of 4096; longer ones take the two launches
+    // (block sums, then block-local scans), whose latency does not grow with the length
     hipStream_t st = c->stream;
-    if (n <= 65536) {
+    const int cap = c->npad / 1024 + 2;
+    const int nbk = nblk(n, 1024);
+    if (n <= kScanOneWG || (n <= 65536 && nbk + 1 > cap)) {
         hipLaunchKernelGGL(k_scan_excl, dim3(1), dim3(1024), 0, st, n, in, out, total_copy);
         return AMOEBA_OK;
     }
-    const int cap = c->npad / 1024 + 2;
-    int nbk = nblk(n, 1024);
-    if (nbk + 1 > cap || total_copy)
+    if (nbk + 1 > cap)
         return set_error(c, AMOEBA_E_INVALID, "device_scan: scratch too small");
     int* bsum = c->b_scan;
     hipLaunchKernelGGL(k_scan_blocksum, dim3(nbk), dim3(256), 0, st, n, in, bsum);
-    hipLaunchKernelGGL(k_scan_apply, dim3(nbk), dim3(256), 0, st, n, in, bsum, out);
+    hipLaunchKernelGGL(k_scan_apply, dim3(nbk), dim3(256), 0, st, n, in, bsum, out, total_copy);
     return AMOEBA_OK;
 }
 

@@ -344,7 +344,7 @@ struct StageTimer {
 };
 
 // blocklist.hip
-// exclusive, out[n] = total; total_copy (n <= 65536 only): a second place for the total
+// exclusive, out[n] = total; total_copy: a second place for the total
 int device_scan(amoeba_ctx* c, int n, const int* in, int* out, int* total_copy = nullptr);
 void coef_scan_rows(amoeba_ctx* c);       // rows of the coefficient store for the current masks
 void launch_sum_pairs(amoeba_ctx* c);     // pair count of the last mask refresh into counter[0]
