@@ -819,7 +819,8 @@ __global__ __launch_bounds__(256) void k_tile_refresh(int ntiles, const int* __r
                                                       const int* __restrict__ perm,
                                                       const double4* __restrict__ pos_s,
                                                       const double4* __restrict__ org,
-                                                      const float4* __restrict__ off_f, double3 box, double3 binv,
+                                                      const float4* __restrict__ off_f,
+                                                      const double4* __restrict__ par, double3 box, double3 binv,
                                                       double rc2, unsigned long long* __restrict__ mask,
                                                       double4* __restrict__ jrel_d, float4* __restrict__ jrel_f,
                                                       int* __restrict__ tile_np, int* __restrict__ tile_rows,
@@ -848,10 +849,11 @@ __global__ __launch_bounds__(256) void k_tile_refresh(int ntiles, const int* __r
     unsigned long long m = 0;
     if (act) {
         // the pair kernels of the context's precision read one of the two
+        const double wj = sj >= 0 ? par[sj].z : 0.0;  // the j atom's polarizability factor
         if (jrel_d)
-            jrel_d[(size_t)t * kBlock + lane] = make_double4(jx, jy, jz, 0.0);
+            jrel_d[(size_t)t * kBlock + lane] = make_double4(jx, jy, jz, wj);
         if (jrel_f)
-            jrel_f[(size_t)t * kBlock + lane] = make_float4((float)jx, (float)jy, (float)jz, 0.0f);
+            jrel_f[(size_t)t * kBlock + lane] = make_float4((float)jx, (float)jy, (float)jz, (float)wj);
         bool diag = tile_j[(size_t)t * kBlock] == I * kBlock;
         const float lo2 = (float)(rc2 * (1.0 - 1e-5)), hi2 = (float)(rc2 * (1.0 + 1e-5));
         const float Lx = (float)box.x, Ly = (float)box.y, Lz = (float)box.z;
@@ -939,6 +941,16 @@ int device_scan(amoeba_ctx* c, int n, const int* in, int* out, int* total_copy)
     return AMOEBA_OK;
 }
 
+// Thole factor of every slot into w of the dipole tiles' source copy (the vector kernels that
+// fill it write x, y, z only), so that the tiles read a j atom's dipole and factor in one load.
+template <typename R>
+__global__ void k_pv_thole(int npad, const double4* __restrict__ par, R* __restrict__ pv)
+{
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < npad)
+        pv[4 * (size_t)s + 3] = (R)par[s].w;
+}
+
 int sort_params(amoeba_ctx* c)
 {
     hipStream_t st = c->stream;
@@ -953,6 +965,15 @@ int sort_params(amoeba_ctx* c)
     if (c->n_scaled > 0)
         hipLaunchKernelGGL(k_csr_fill, dim3(nblk(c->npad, 256)), dim3(256), 0, st, c->npad, c->perm, c->slot,
                            c->sc_ptr_in, c->sc_j_in, c->sc_s_in, c->sc_ptr, c->sc_j, c->sc_s);
+    if (c->mixed)
+        hipLaunchKernelGGL(k_pv_thole<float>, dim3(nblk(c->npad, 256)), dim3(256), 0, st, c->npad, c->par_d,
+                           (float*)c->pv_f);
+    else
+        hipLaunchKernelGGL(k_pv_thole<double>, dim3(nblk(c->npad, 256)), dim3(256), 0, st, c->npad, c->par_d,
+                           (double*)c->pv_d);
+    // the tiles' j records carry the slots' polarizability factors: refresh them before the
+    // next product
+    c->cfg_valid = false;
     return AMOEBA_OK;
 }
 
@@ -987,7 +1008,8 @@ static int refresh_tiles(amoeba_ctx* c)
     const int nwg = nblk((long)c->ntiles * kBlock, 256);
     hipLaunchKernelGGL(c->skip_mimg ? k_tile_refresh<false> : k_tile_refresh<true>, dim3(nwg), dim3(256), 0, st,
                        c->ntiles, c->tile_blk, c->tile_j, c->perm,
-                       c->pos_s, c->blk_org, c->off_f, box, binv, c->prm.cutoff * c->prm.cutoff, c->tile_mask,
+                       c->pos_s, c->blk_org, c->off_f, c->par_d, box, binv, c->prm.cutoff * c->prm.cutoff,
+                       c->tile_mask,
                        c->jrel_d, c->jrel_f, c->tile_np, c->tile_rows, c->pair_part);
     c->pair_nwg = nwg;
     c->pairs_pending = true;  // summed (k_sum_pairs) when amoeba_get_info asks for the count

@@ -35,10 +35,13 @@ template <> struct V4R<float> { using T = float4; };
 template <> struct V4R<double> { using T = double4; };
 template <typename R4T> struct Cast4G;
 template <> struct Cast4G<float4> {
-    __device__ static float4 make(double x, double y, double z) { return make_float4((float)x, (float)y, (float)z, 0.f); }
+    __device__ static float4 make(double x, double y, double z, double w)
+    {
+        return make_float4((float)x, (float)y, (float)z, (float)w);
+    }
 };
 template <> struct Cast4G<double4> {
-    __device__ static double4 make(double x, double y, double z) { return make_double4(x, y, z, 0.0); }
+    __device__ static double4 make(double x, double y, double z, double w) { return make_double4(x, y, z, w); }
 };
 
 constexpr int kNF = AMOEBA_GUESS_NFEAT;
@@ -196,7 +199,7 @@ __global__ void k_guess_basis(int npad, const double4* __restrict__ par, const d
         v[c] = ereal ? al * (ereal[3 * (size_t)s + c] + cself * x) : al * x;
         vnext[3 * (size_t)s + c] = v[c];
     }
-    pv[s] = Cast4G<R4T>::make(v[0], v[1], v[2]);
+    pv[s] = Cast4G<R4T>::make(v[0], v[1], v[2], par[s].w);  // w: Thole factor, read by the dipole tiles
 }
 
 // delta bases: on entry v1 holds E_ref and v0 mu_ref in slot order (e the permanent field);

@@ -17,10 +17,13 @@ namespace amoeba {
 
 template <typename R4T> struct Cast4;
 template <> struct Cast4<float4> {
-    __device__ static float4 make(double x, double y, double z) { return make_float4((float)x, (float)y, (float)z, 0.f); }
+    __device__ static float4 make(double x, double y, double z, double w)
+    {
+        return make_float4((float)x, (float)y, (float)z, (float)w);
+    }
 };
 template <> struct Cast4<double4> {
-    __device__ static double4 make(double x, double y, double z) { return make_double4(x, y, z, 0.0); }
+    __device__ static double4 make(double x, double y, double z, double w) { return make_double4(x, y, z, w); }
 };
 
 __global__ void k_gather_vec(int npad, const int* __restrict__ perm, const double* __restrict__ src,
@@ -72,9 +75,10 @@ __global__ void k_scatter_vec(int npad, const int* __restrict__ perm, const doub
         dst[3 * (size_t)a + c] = src[3 * (size_t)s + c];
 }
 
-// p = src; pair-kernel copy pv = p
+// p = src; pair-kernel copy pv = p (w: the slot's Thole factor, read by the dipole tiles)
 template <typename R4T>
-__global__ void k_set_dir(int npad, const double* __restrict__ src, double* __restrict__ p, R4T* __restrict__ pv)
+__global__ void k_set_dir(int npad, const double4* __restrict__ par, const double* __restrict__ src,
+                          double* __restrict__ p, R4T* __restrict__ pv)
 {
     int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= npad)
@@ -85,7 +89,7 @@ __global__ void k_set_dir(int npad, const double* __restrict__ src, double* __re
         p[3 * (size_t)s + 1] = y;
         p[3 * (size_t)s + 2] = z;
     }
-    pv[s] = Cast4<R4T>::make(x, y, z);
+    pv[s] = Cast4<R4T>::make(x, y, z, par[s].w);
 }
 
 // The vector kernels below use a fixed grid of kRedBlocks workgroups striding over the
@@ -296,11 +300,11 @@ void launch_scatter(amoeba_ctx* c, const double* v_slot, double* out_caller)
 void launch_set_direction(amoeba_ctx* c, const double* src)
 {
     if (c->mixed)
-        hipLaunchKernelGGL(k_set_dir<float4>, dim3(nblk(c->npad, 256)), dim3(256), 0, c->stream, c->npad, src,
-                           c->v_p, c->pv_f);
+        hipLaunchKernelGGL(k_set_dir<float4>, dim3(nblk(c->npad, 256)), dim3(256), 0, c->stream, c->npad,
+                           c->par_d, src, c->v_p, c->pv_f);
     else
-        hipLaunchKernelGGL(k_set_dir<double4>, dim3(nblk(c->npad, 256)), dim3(256), 0, c->stream, c->npad, src,
-                           c->v_p, c->pv_d);
+        hipLaunchKernelGGL(k_set_dir<double4>, dim3(nblk(c->npad, 256)), dim3(256), 0, c->stream, c->npad,
+                           c->par_d, src, c->v_p, c->pv_d);
 }
 
 // Partial buffers: the p.Ap partials of the operator product first (one per PME brick or per

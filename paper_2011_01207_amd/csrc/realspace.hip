@@ -329,11 +329,10 @@ template <typename R> struct DipoleKind {
         d[0].y *= f;
         d[0].z *= f;
     }
-    __device__ static void load(const R4* src, size_t s, R a, R4* d)
-    {
-        R4 m = src[s];
-        d[0] = R4{m.x, m.y, m.z, a};
-    }
+    // the source copy carries the Thole factor in w and the tile's j records the polarizability
+    // factor, so a j atom needs no parameter load
+    static constexpr bool kParamsInSrc = true;
+    __device__ static void load(const R4* src, size_t s, R, R4* d) { d[0] = src[s]; }  // w: Thole factor
     using C = typename V2<R>::T;  // stored radial coefficients (B1', B2')
     // the field of the pair from its displacement and radial coefficients
     __device__ static __forceinline__ void apply(R dx, R dy, R dz, R b1p, R b2p, const R4* di, const R4* dj, R* ei,
@@ -383,6 +382,7 @@ template <typename R> struct MultipoleKind {
     // the j-field is linear in the i multipoles (everything but the Thole factor d[2].z), which
     // nothing else of the pair uses: held times 2^38 with integer sums, as for the dipoles
     static constexpr bool kScaledJ = true;
+    static constexpr bool kParamsInSrc = false;
     __device__ static void scale_i(R4* d, R f)
     {
         d[0].x *= f;
@@ -521,6 +521,7 @@ __device__ __forceinline__ void force_pair(T rx, T ry, T rz, T aij, T wij, const
 template <typename R> struct ForceKind {
     using R4 = typename V4<R>::T;
     static constexpr bool kScaledJ = false;
+    static constexpr bool kParamsInSrc = false;
     __device__ static void scale_i(R4*, R) {}
     static constexpr int NV = 4;
     __device__ static void load(const R4* src, size_t s, R a, R4* d)
@@ -666,10 +667,15 @@ __global__ __launch_bounds__(256) void k_block_tiles(int nb, const int* __restri
             for (int v = 0; v < NV; ++v)
                 d[v] = R4{0, 0, 0, 0};
             if (sj >= 0) {
-                const R4 pj = par[sj];
-                dj = pj.z;
-                aj = pj.w;
-                K::load(src, sj, aj, d);
+                if constexpr (K::kParamsInSrc) {
+                    dj = jr.w;
+                    K::load(src, sj, (R)0, d);
+                } else {
+                    const R4 pj = par[sj];
+                    dj = pj.z;
+                    aj = pj.w;
+                    K::load(src, sj, aj, d);
+                }
             }
             s_jp[w][lane] = R4{jr.x, jr.y, jr.z, dj};
 #pragma unroll
