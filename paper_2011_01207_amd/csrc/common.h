@@ -210,7 +210,7 @@ struct amoeba_ctx {
     int32_t* xb_count = nullptr;   // [K0+1]
     int4* xb_rec = nullptr;        // [npad] per binned atom: (slot, fx, fy, fz)
     void* xb_w = nullptr;          // [npad] (R4) spline arguments (wx, wy, wz, 0)
-    void* rec_part = nullptr;      // [npad][5] (R4) field share of each of an atom's five x-planes
+    void* rec_part = nullptr;      // [5][npad] (R4) field share of each of an atom's five x-planes
     void* pl_roots[3] = {nullptr, nullptr, nullptr};  // roots of unity exp(-2 pi i m / K) (R complex)
     int npq = 0;                   // p.q partials written by the last PCG product
     int npq_cap = 0;               // room for them at the start of red.part

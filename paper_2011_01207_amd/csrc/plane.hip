@@ -275,6 +275,7 @@ __device__ __forceinline__ void fill_lds(int n, const T* __restrict__ src, SI si
 // on chunks of kc consecutive kz columns.
 struct PlaneGeom {
     int nt;       // threads per workgroup of the row-chunk passes
+    int npad;     // slots (the plane shares are [5][npad])
     int K0, K1, K2;
     int kh;       // K2 / 2 + 1
     int ks;       // row stride of G (complex values): kh rounded up to whole 128-byte lines
@@ -678,7 +679,7 @@ __global__ __launch_bounds__(kPlColThreads) void k_pme_xconv(PlaneGeom g, PlaneD
 // Z[k] = A[k] + i B[k] with the Hermitian extension A[k] = conj A[K2 - k] for k >= kh, the
 // imaginary parts of the real terms k = 0 and K2/2 dropped as a real inverse transform does)
 // and transformed back along z; then every atom with fx in x..x+4 and fy in [ya, yb) adds up its
-// share of the field from plane x: part[5 s + t] = (M'_x M_y M_z psi, M_x M'_y M_z psi,
+// share of the field from plane x: part[t npad + s] = (M'_x M_y M_z psi, M_x M'_y M_z psi,
 // M_x M_y M'_z psi) over its 25 (y, z) points, t its weight index for the plane (the K/L
 // factors and the sign are applied by the combine).
 template <typename R, int NT>
@@ -815,12 +816,12 @@ __global__ __launch_bounds__(NT) void k_pme_z_gather(PlaneGeom g, PlaneDim dz,
                 az += y0[ty] * s1;
             }
             const R tx0 = pick5(x0, tq[u]), tx1 = pick5(x1, tq[u]);
-            part[5 * (size_t)rec[u].x + tq[u]] = R4{tx1 * ax, tx0 * ay, tx0 * az, (R)0};
+            part[(size_t)tq[u] * g.npad + rec[u].x] = R4{tx1 * ax, tx0 * ay, tx0 * az, (R)0};
         }
     }
 }
 
-// Per-atom combine of the plane shares: E_rec = -(K/L) sum_t part[5 s + t] (fixed order).
+// Per-atom combine of the plane shares: E_rec = -(K/L) sum_t part[t npad + s] (fixed order).
 // MODE 0 writes E_rec (slot order, FP64).  MODE 1 assembles the PCG operator product
 // q = p / alpha - (E_real + E_rec + self p): the real-space field is the atom's block i-field
 // plus the tile j-fields listed in the reverse index, in index order (or, MODE 2, the same sum
@@ -849,7 +850,7 @@ __global__ __launch_bounds__(256) void k_plane_combine(int npad, double3 kl, con
             double sx = 0.0, sy = 0.0, sz = 0.0;
 #pragma unroll
             for (int t = 0; t < 5; ++t) {
-                const R4 v = part[5 * (size_t)s + t];
+                const R4 v = part[(size_t)t * npad + s];
                 sx += (double)v.x;
                 sy += (double)v.y;
                 sz += (double)v.z;
@@ -999,6 +1000,7 @@ static size_t lds_lines(int N, int kc, size_t cs) { return cs * ((size_t)N * (kc
 static PlaneGeom plane_geom(const amoeba_ctx* c)
 {
     PlaneGeom g;
+    g.npad = c->npad;
     g.K0 = c->K[0];
     g.K1 = c->K[1];
     g.K2 = c->K[2];
