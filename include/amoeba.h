@@ -208,6 +208,38 @@ int amoeba_polarize(amoeba_ctx* ctx, const double* pos, const double* e_perm,
                     const double* mu_guess, int32_t guess_mode, double tol_debye, int32_t max_iter,
                     double* mu_out, double* e_pol_out, int32_t* iters_out);
 
+/* ------------------------------------------------------------------------------------------
+ * Two induced-dipole sets (AMOEBA's full polarization model; paper "Real space scheme": every
+ * AMOEBA polarization interaction carries three scaling factors).  mu_d answers the permanent
+ * field with the direct scales d, mu_p the field with the polarization scales p (the scales of
+ * amoeba_set_atoms); the mutual operator (alpha^-1 - T) is the same for both (u-scale 1:
+ * every pair Thole-damped, unscaled), and E_pol = -1/2 C mu_d . e_p (= -1/2 C mu_p . e_d, the
+ * operator being symmetric).
+ * ------------------------------------------------------------------------------------------ */
+
+/* Direct scales sc_s_d[n_scaled] of the pairs listed by amoeba_set_atoms, in the same CSR order
+ * (device FP64); n_scaled must equal the count given there.  Validated like the p-scales
+ * (finite, both directions of a pair equal).  Without this call (or after a new
+ * amoeba_set_atoms, which drops them) the direct scales equal the p-scales. */
+int amoeba_set_direct_scales(amoeba_ctx* ctx, const double* sc_s_d, int64_t n_scaled);
+
+/* The two permanent fields e_d[N][3] (direct scales) and e_p[N][3] (p-scales) of one set of
+ * multipoles, as amoeba_perm_field computes e_perm (which equals e_p): the unscaled real-space
+ * tiles, the reciprocal part and the self field are shared, the scaled-pair corrections differ.
+ * Errors as for amoeba_perm_field. */
+int amoeba_perm_field_dp(amoeba_ctx* ctx, const double* pos, const double* q, const double* dip,
+                         const double* quad, double* e_d, double* e_p);
+
+/* Both sets: (alpha^-1 - T) mu_d = e_d and (alpha^-1 - T) mu_p = e_p, each by the PCG of
+ * amoeba_polarize from zero to tol_debye (the same stopping rule; in mixed precision with its
+ * true-residual check).  Outputs: mu_d_out, mu_p_out [N][3] (device, e*A); *e_pol_out =
+ * -1/2 C sum_i mu_d,i . e_p,i (host, kcal/mol; may be NULL); iters_out[2] (host; may be NULL):
+ * the iterations of the d and the p solve.  AMOEBA_NOT_CONVERGED if either stopped at max_iter
+ * (both outputs are then the last iterates).  Errors as for amoeba_polarize. */
+int amoeba_polarize_dp(amoeba_ctx* ctx, const double* pos, const double* e_d, const double* e_p,
+                       double tol_debye, int32_t max_iter, double* mu_d_out, double* mu_p_out,
+                       double* e_pol_out, int32_t* iters_out);
+
 /* Gradient of the polarization energy with respect to the positions, grad_out[N][3] =
  * dE_pol/dr (device FP64, kcal/mol/A; the polarization forces are its negative), for the
  * permanent multipoles (q, dip, quad, as for amoeba_perm_field) and the induced dipoles mu[N][3]

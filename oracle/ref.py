@@ -16,10 +16,12 @@ Results") is the textbook preconditioned conjugate gradient; dense Cholesky is
 the exact solution of the same linear system for small cases.
 
 Inputs are duck-typed: any object with pos, box, alpha, thole, q, dip, quad,
-sc_ptr, sc_j, sc_s, cutoff, ewald_alpha, grid, order.
+sc_ptr, sc_j, sc_s, cutoff, ewald_alpha, grid, order (and, for the two-set model,
+sc_s_d: the direct scales of the same pairs).
 """
 from __future__ import annotations
 
+import copy
 import ctypes
 import math
 import os
@@ -347,6 +349,29 @@ def perm_field(s, recip='spme', idx=None, beta=None):
     e += recip_field(s, q=s.q, dip=s.dip, quad=s.quad, idx=idx, recip=recip, beta=beta)
     e += self_coeff(beta) * _sel(np.asarray(s.dip), idx)
     return e
+
+
+def with_scales(s, sc_s):
+    """A shallow copy of the system whose listed pairs carry the scales sc_s instead."""
+    t = copy.copy(s)
+    t.sc_s = np.asarray(sc_s, dtype=np.float64)
+    return t
+
+
+def perm_field_dp(s, recip='spme', idx=None, beta=None):
+    """(E_d, E_p) of AMOEBA's two induced-dipole sets (paper "Real space scheme": a polarization
+    interaction carries three scaling kinds): the permanent field with the direct scales
+    s.sc_s_d (the p-scales when the system has none) and with the p-scales s.sc_s.  Each is
+    perm_field of the system with that scale array."""
+    sd = getattr(s, 'sc_s_d', None)
+    e_p = perm_field(s, recip, idx, beta)
+    e_d = e_p.copy() if sd is None else perm_field(with_scales(s, sd), recip, idx, beta)
+    return e_d, e_p
+
+
+def e_pol_dp(mu_d, e_p) -> float:
+    """Two-set polarization energy -1/2 C sum_i mu_d,i . E_p,i in kcal/mol."""
+    return e_pol(mu_d, e_p)
 
 
 def rms_debye(v) -> float:

@@ -103,6 +103,10 @@ def lib() -> ctypes.CDLL:
         L.amoeba_set_atoms.argtypes = [_P, _P, _P, _P, _P, _P, ctypes.c_int64]
         L.amoeba_build_blocklist.argtypes = [_P, _P]
         L.amoeba_perm_field.argtypes = [_P, _P, _P, _P, _P, _P]
+        L.amoeba_set_direct_scales.argtypes = [_P, _P, ctypes.c_int64]
+        L.amoeba_perm_field_dp.argtypes = [_P, _P, _P, _P, _P, _P, _P]
+        L.amoeba_polarize_dp.argtypes = [_P, _P, _P, _P, ctypes.c_double, ctypes.c_int32, _P, _P,
+                                         ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32)]
         L.amoeba_dipole_matvec.argtypes = [_P, _P, _P, _P]
         L.amoeba_dipole_field_parts.argtypes = [_P, _P, _P, _P, _P]
         L.amoeba_polarization_gradient.argtypes = [_P, _P, _P, _P, _P, _P, _P]
@@ -203,6 +207,12 @@ class Context:
             _ptr(sc_j, torch.int32, (nnz,), "sc_j") if nnz else None,
             _ptr(sc_s, torch.float64, (nnz,), "sc_s") if nnz else None, nnz))
 
+    def set_direct_scales(self, sc_s_d):
+        """Direct (d) scales of the pairs given to set_atoms, in the same order."""
+        nnz = int(sc_s_d.numel())
+        return self._check(lib().amoeba_set_direct_scales(
+            self.h, _ptr(sc_s_d, torch.float64, (nnz,), "sc_s_d") if nnz else None, nnz))
+
     def build_blocklist(self, pos):
         return self._check(lib().amoeba_build_blocklist(self.h, _ptr(pos, torch.float64, (self.n, 3), "pos")))
 
@@ -214,6 +224,32 @@ class Context:
             _ptr(dip, torch.float64, (n, 3), "dip"), _ptr(quad, torch.float64, (n, 6), "quad"),
             _ptr(out, torch.float64, (n, 3), "e_perm")))
         return out
+
+    def perm_field_dp(self, pos, q, dip, quad):
+        """Returns (e_d, e_p): the permanent field with the direct and with the p-scales."""
+        n = self.n
+        e_d = torch.empty((n, 3), dtype=torch.float64, device=pos.device)
+        e_p = torch.empty((n, 3), dtype=torch.float64, device=pos.device)
+        self._check(lib().amoeba_perm_field_dp(
+            self.h, _ptr(pos, torch.float64, (n, 3), "pos"), _ptr(q, torch.float64, (n,), "q"),
+            _ptr(dip, torch.float64, (n, 3), "dip"), _ptr(quad, torch.float64, (n, 6), "quad"),
+            _ptr(e_d, torch.float64, (n, 3), "e_d"), _ptr(e_p, torch.float64, (n, 3), "e_p")))
+        return e_d, e_p
+
+    def polarize_dp(self, pos, e_d, e_p, tol_debye=1e-5, max_iter=500):
+        """Returns (mu_d, mu_p, e_pol kcal/mol, (iterations d, p), status)."""
+        n = self.n
+        mu_d = torch.empty((n, 3), dtype=torch.float64, device=pos.device)
+        mu_p = torch.empty((n, 3), dtype=torch.float64, device=pos.device)
+        ep = ctypes.c_double(0.0)
+        its = (ctypes.c_int32 * 2)(0, 0)
+        st = self._check(lib().amoeba_polarize_dp(
+            self.h, _ptr(pos, torch.float64, (n, 3), "pos"), _ptr(e_d, torch.float64, (n, 3), "e_d"),
+            _ptr(e_p, torch.float64, (n, 3), "e_p"), float(tol_debye), int(max_iter),
+            _ptr(mu_d, torch.float64, (n, 3), "mu_d_out"), _ptr(mu_p, torch.float64, (n, 3), "mu_p_out"),
+            ctypes.byref(ep), ctypes.cast(its, ctypes.POINTER(ctypes.c_int32))),
+            ok=(AMOEBA_OK, AMOEBA_NOT_CONVERGED))
+        return mu_d, mu_p, ep.value, (its[0], its[1]), st
 
     def dipole_matvec(self, pos, mu, out=None):
         n = self.n
@@ -422,5 +458,8 @@ def context_for(system, precision="fp64", device="cuda", **kw):
     ctx = Context(system.n, system.box, cutoff=system.cutoff, buffer=system.buffer,
                   ewald_alpha=system.ewald_alpha, grid=system.grid, order=system.order, precision=precision, **kw)
     ctx.set_atoms(t["alpha"], t["thole"], t["sc_ptr"], t["sc_j"], t["sc_s"])
+    if getattr(system, "sc_s_d", None) is not None:
+        t["sc_s_d"] = torch.tensor(system.sc_s_d, dtype=torch.float64, device=device)
+        ctx.set_direct_scales(t["sc_s_d"])
     ctx.build_blocklist(t["pos"])
     return ctx, t

@@ -466,6 +466,7 @@ int amoeba_set_atoms(amoeba_ctx* c, const double* alpha, const double* thole, co
     }
     c->n_scaled = n_scaled;
     c->atoms_set = true;
+    c->dscales_set = false;  // direct scales belong to a pair list: set them again after this
     if (c->list_built && (rc = sort_params(c)))
         return rc;
     return hip_check(c, hipStreamSynchronize(st), "amoeba_set_atoms");
@@ -484,15 +485,12 @@ int amoeba_build_blocklist(amoeba_ctx* c, const double* pos)
     return rc;
 }
 
-int amoeba_perm_field(amoeba_ctx* c, const double* pos, const double* q, const double* dip, const double* quad,
-                      double* e_perm)
+// The parts of E_perm shared by the scale sets (multipoles in slot order, the unscaled tiles'
+// sums in ereal, the reciprocal field in erec), leaving the flags unread.
+static int perm_field_parts(amoeba_ctx* c, const double* pos, const double* q, const double* dip,
+                            const double* quad, const char* what)
 {
-    if (!c)
-        return AMOEBA_E_INVALID;
-    c->err.clear();
-    if (!q || !dip || !quad || !e_perm)
-        return set_error(c, AMOEBA_E_INVALID, "amoeba_perm_field: NULL argument");
-    int rc = begin_config(c, pos, "amoeba_perm_field");
+    int rc = begin_config(c, pos, what);
     if (rc)
         return rc;
     if (!c->mp_d) {
@@ -502,7 +500,7 @@ int amoeba_perm_field(amoeba_ctx* c, const double* pos, const double* q, const d
             return rc;
     }
     // The multipole checks (finite, traceless) and the range check of the result are flags
-    // written on the device and read once at the end; on an error e_perm is unspecified.
+    // written on the device and read once at the end; on an error the fields are unspecified.
     hipStream_t st = c->stream;
     hipMemsetAsync(c->flags, 0, sizeof(int), st);
     hipLaunchKernelGGL(k_gather_mpole, dim3(nblk(c->npad, 256)), dim3(256), 0, st, c->npad, c->perm, q, dip, quad,
@@ -523,22 +521,102 @@ int amoeba_perm_field(amoeba_ctx* c, const double* pos, const double* q, const d
             return rc;
         launch_gather(c, c->erec);
     }
-    launch_perm_assemble(c, c->v_q);
+    return AMOEBA_OK;
+}
+
+// Assembles E_perm with the given slot-order scales into v_q and writes it in caller order.
+static void perm_field_out(amoeba_ctx* c, const double* scales, double* out)
+{
+    launch_perm_assemble(c, c->v_q, scales);
     if (c->mixed)
-        hipLaunchKernelGGL(k_check_overflow, dim3(nblk(3 * (size_t)c->npad, 256)), dim3(256), 0, st,
+        hipLaunchKernelGGL(k_check_overflow, dim3(nblk(3 * (size_t)c->npad, 256)), dim3(256), 0, c->stream,
                            3 * (size_t)c->npad, c->v_q, kFixRange, c->flags);
-    launch_scatter(c, c->v_q, e_perm);
-    int f = 0;
+    launch_scatter(c, c->v_q, out);
+}
+
+static int perm_field_status(amoeba_ctx* c, const char* what)
+{
+    int f = 0, rc;
     if ((rc = read_flags(c, &f)))
         return rc;
     if (f & kFlagBadCsr)
-        return set_error(c, AMOEBA_E_INVALID, "amoeba_perm_field: quadrupole not traceless (|tr| > 1e-10)");
+        return set_error(c, AMOEBA_E_INVALID, std::string(what) + ": quadrupole not traceless (|tr| > 1e-10)");
     if (f & kFlagNonFinite)
-        return set_error(c, AMOEBA_E_NUMERIC, "amoeba_perm_field: non-finite multipole or field");
+        return set_error(c, AMOEBA_E_NUMERIC, std::string(what) + ": non-finite multipole or field");
     if (f & kFlagOverflow)
         return set_error(c, AMOEBA_E_OVERFLOW,
-                         "amoeba_perm_field: field outside the exact fixed-point range (|E| >= 8192 e/A^2)");
+                         std::string(what) + ": field outside the exact fixed-point range (|E| >= 8192 e/A^2)");
     return AMOEBA_OK;
+}
+
+int amoeba_perm_field(amoeba_ctx* c, const double* pos, const double* q, const double* dip, const double* quad,
+                      double* e_perm)
+{
+    if (!c)
+        return AMOEBA_E_INVALID;
+    c->err.clear();
+    if (!q || !dip || !quad || !e_perm)
+        return set_error(c, AMOEBA_E_INVALID, "amoeba_perm_field: NULL argument");
+    int rc = perm_field_parts(c, pos, q, dip, quad, "amoeba_perm_field");
+    if (rc)
+        return rc;
+    perm_field_out(c, c->sc_s, e_perm);
+    return perm_field_status(c, "amoeba_perm_field");
+}
+
+int amoeba_set_direct_scales(amoeba_ctx* c, const double* sc_s_d, int64_t n_scaled)
+{
+    if (!c)
+        return AMOEBA_E_INVALID;
+    c->err.clear();
+    if (!c->atoms_set)
+        return set_error(c, AMOEBA_E_STATE, "amoeba_set_direct_scales: call amoeba_set_atoms first");
+    if (n_scaled != c->n_scaled)
+        return set_error(c, AMOEBA_E_INVALID, "amoeba_set_direct_scales: n_scaled differs from amoeba_set_atoms'");
+    if (n_scaled > 0 && !sc_s_d)
+        return set_error(c, AMOEBA_E_INVALID, "amoeba_set_direct_scales: NULL sc_s_d with n_scaled > 0");
+    hipStream_t st = c->stream;
+    int rc;
+    if (n_scaled > c->sc_sd_cap) {
+        if ((rc = ctx_alloc(c, (void**)&c->sc_sd_in, sizeof(double) * n_scaled)) ||
+            (rc = ctx_alloc(c, (void**)&c->sc_sd, sizeof(double) * n_scaled)))
+            return rc;
+        c->sc_sd_cap = n_scaled;
+    }
+    if (n_scaled > 0) {
+        // the same validation as the p-scales: finite, and equal for both directions of a pair
+        hipMemsetAsync(c->flags, 0, sizeof(int), st);
+        hipLaunchKernelGGL(k_validate_atoms, dim3(nblk(c->n + 1, 256)), dim3(256), 0, st, c->n, c->alpha_in,
+                           c->thole_in, c->sc_ptr_in, c->sc_j_in, sc_s_d, (long long)n_scaled, c->flags);
+        int f = 0;
+        if ((rc = read_flags(c, &f)))
+            return rc;
+        if (f & kFlagBadCsr)
+            return set_error(c, AMOEBA_E_INVALID,
+                             "amoeba_set_direct_scales: a non-finite scale, or a pair whose two directions "
+                             "have different scales");
+        hipMemcpyAsync(c->sc_sd_in, sc_s_d, sizeof(double) * n_scaled, hipMemcpyDeviceToDevice, st);
+    }
+    c->dscales_set = true;
+    if (c->list_built && (rc = sort_params(c)))
+        return rc;
+    return hip_check(c, hipStreamSynchronize(st), "amoeba_set_direct_scales");
+}
+
+int amoeba_perm_field_dp(amoeba_ctx* c, const double* pos, const double* q, const double* dip, const double* quad,
+                         double* e_d, double* e_p)
+{
+    if (!c)
+        return AMOEBA_E_INVALID;
+    c->err.clear();
+    if (!q || !dip || !quad || !e_d || !e_p)
+        return set_error(c, AMOEBA_E_INVALID, "amoeba_perm_field_dp: NULL argument");
+    int rc = perm_field_parts(c, pos, q, dip, quad, "amoeba_perm_field_dp");
+    if (rc)
+        return rc;
+    perm_field_out(c, c->sc_s, e_p);
+    perm_field_out(c, c->dscales_set ? c->sc_sd : c->sc_s, e_d);
+    return perm_field_status(c, "amoeba_perm_field_dp");
 }
 
 int amoeba_dipole_matvec(amoeba_ctx* c, const double* pos, const double* mu, double* out)
@@ -677,6 +755,49 @@ int amoeba_polarize(amoeba_ctx* c, const double* pos, const double* e_perm, cons
     if (st == AMOEBA_NOT_CONVERGED)
         set_error(c, AMOEBA_NOT_CONVERGED, "PCG did not reach the tolerance within max_iter");
     return st;
+}
+
+int amoeba_polarize_dp(amoeba_ctx* c, const double* pos, const double* e_d, const double* e_p, double tol_debye,
+                       int32_t max_iter, double* mu_d_out, double* mu_p_out, double* e_pol_out, int32_t* iters_out)
+{
+    if (!c)
+        return AMOEBA_E_INVALID;
+    c->err.clear();
+    if (!e_d || !e_p || !mu_d_out || !mu_p_out)
+        return set_error(c, AMOEBA_E_INVALID, "amoeba_polarize_dp: NULL e_d, e_p, mu_d_out or mu_p_out");
+    if (!(tol_debye > 0.0) || !std::isfinite(tol_debye))
+        return set_error(c, AMOEBA_E_INVALID, "amoeba_polarize_dp: tol_debye must be positive");
+    if (max_iter < 0)
+        return set_error(c, AMOEBA_E_INVALID, "amoeba_polarize_dp: max_iter must be >= 0");
+    int rc = begin_config(c, pos, "amoeba_polarize_dp");
+    if (rc)
+        return rc;
+    // the d set, then the p set, each from zero with the same operator; the inputs are checked
+    // for NaN/Inf by the gathers (read with each solve's first host wait)
+    int st[2], it[2];
+    const double* rhs[2] = {e_d, e_p};
+    double* out[2] = {mu_d_out, mu_p_out};
+    for (int k = 0; k < 2; ++k) {
+        hipMemsetAsync(c->flags, 0, sizeof(int), c->stream);
+        launch_gather_vec_checked(c, rhs[k], c->v_e);
+        st[k] = pcg_solve(c, tol_debye, max_iter, false, out[k], nullptr);
+        if (st[k] < 0)
+            return st[k];
+        it[k] = c->last_iters;
+    }
+    // E_pol = -1/2 C mu_d . e_p (v_e holds e_p now)
+    launch_gather_vec(c, mu_d_out, c->v_mu);
+    double acc = 0.0;
+    if ((rc = pcg_dot_mu_e(c, &acc)))
+        return rc;
+    if (e_pol_out)
+        *e_pol_out = -0.5 * kCoulomb * acc;
+    if (iters_out) {
+        iters_out[0] = it[0];
+        iters_out[1] = it[1];
+    }
+    c->last_guess = AMOEBA_GUESS_ZERO;
+    return st[0] == AMOEBA_OK && st[1] == AMOEBA_OK ? AMOEBA_OK : AMOEBA_NOT_CONVERGED;
 }
 
 int amoeba_polarization_gradient(amoeba_ctx* c, const double* pos, const double* q, const double* dip,

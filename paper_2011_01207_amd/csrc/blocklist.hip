@@ -965,6 +965,9 @@ int sort_params(amoeba_ctx* c)
     if (c->n_scaled > 0)
         hipLaunchKernelGGL(k_csr_fill, dim3(nblk(c->npad, 256)), dim3(256), 0, st, c->npad, c->perm, c->slot,
                            c->sc_ptr_in, c->sc_j_in, c->sc_s_in, c->sc_ptr, c->sc_j, c->sc_s);
+    if (c->n_scaled > 0 && c->dscales_set)  // the same pairs, their direct scales (sc_j rewritten alike)
+        hipLaunchKernelGGL(k_csr_fill, dim3(nblk(c->npad, 256)), dim3(256), 0, st, c->npad, c->perm, c->slot,
+                           c->sc_ptr_in, c->sc_j_in, c->sc_sd_in, c->sc_ptr, c->sc_j, c->sc_sd);
     if (c->mixed)
         hipLaunchKernelGGL(k_pv_thole<float>, dim3(nblk(c->npad, 256)), dim3(256), 0, st, c->npad, c->par_d,
                            (float*)c->pv_f);

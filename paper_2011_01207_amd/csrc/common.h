@@ -165,6 +165,11 @@ struct amoeba_ctx {
     int32_t* sc_ptr_in = nullptr;  // caller-order CSR copy (validation / re-sorting)
     int32_t* sc_j_in = nullptr;
     double* sc_s_in = nullptr;
+    // direct-field (d) scales of the same pairs (two-set solve); without them d = p
+    bool dscales_set = false;
+    int64_t sc_sd_cap = 0;
+    double* sc_sd_in = nullptr;    // caller CSR order
+    double* sc_sd = nullptr;       // slot order
     double* alpha_in = nullptr;    // caller-order parameters
     double* thole_in = nullptr;
 
@@ -361,7 +366,7 @@ bool coef_store_on(const amoeba_ctx* c);  // the requested mode uses the store
 int next_coef_mode(const amoeba_ctx* c);  // the next dipole product: 0 evaluates, 1 records, 2 replays
 void launch_real_reduce(amoeba_ctx* c, double* ereal, hipStream_t st = nullptr, bool use_done = false);
 void launch_perm_tiles(amoeba_ctx* c, hipStream_t st = nullptr);
-void launch_perm_assemble(amoeba_ctx* c, double* out_slot);
+void launch_perm_assemble(amoeba_ctx* c, double* out_slot, const double* scales);  // scales in slot order
 void launch_force_tiles(amoeba_ctx* c, const void* src, double* out);  // real-space gradient pair sums
 
 // pme.hip
@@ -406,6 +411,7 @@ void launch_matvec_combine(amoeba_ctx* c, bool use_done, bool dot_pq, bool reduc
 void launch_set_direction(amoeba_ctx* c, const double* src);
 void launch_gather_vec_checked(amoeba_ctx* c, const double* src_caller, double* dst_slot); // + NaN flag
 int pcg_solve(amoeba_ctx* c, double tol, int max_iter, bool have_guess, double* mu_out, double* e_pol);
+int pcg_dot_mu_e(amoeba_ctx* c, double* acc);                      // sum of v_mu . v_e (waits)
 void pcg_begin(amoeba_ctx* c, double tol);                         // initial device scalars
 int pcg_start(amoeba_ctx* c, bool have_guess, double* rms_debye);   // r0, z0, p0 from v_mu
 int pcg_start_from(amoeba_ctx* c, const double* q0);                // same, A mu0 given

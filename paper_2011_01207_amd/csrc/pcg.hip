@@ -517,6 +517,18 @@ static void launch_epol(amoeba_ctx* c)
     hipLaunchKernelGGL(k_epol_finalize, dim3(1), dim3(256), 0, c->stream, kRedBlocks, part_vec(c), c->sc);
 }
 
+// Sum over slots of v_mu . v_e (FP64, fixed order), waited for.
+int pcg_dot_mu_e(amoeba_ctx* c, double* acc)
+{
+    launch_epol(c);
+    PcgScalars s;
+    int rc = read_scalars(c, &s);
+    if (rc)
+        return rc;
+    *acc = s.epol_acc;
+    return AMOEBA_OK;
+}
+
 // Initial device scalars of a solve (tolerance; everything else zero); no host wait.
 void pcg_begin(amoeba_ctx* c, double tol)
 {

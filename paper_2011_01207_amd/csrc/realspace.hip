@@ -1099,14 +1099,14 @@ __global__ void k_perm_assemble(int npad, const int* __restrict__ perm, const do
     }
 }
 
-void launch_perm_assemble(amoeba_ctx* c, double* out_slot)
+void launch_perm_assemble(amoeba_ctx* c, double* out_slot, const double* scales)
 {
     StageTimer tm(c, AMOEBA_T_PERM);
     double3 box = make_double3(c->prm.box[0], c->prm.box[1], c->prm.box[2]);
     double b = c->prm.ewald_alpha;
     double self = 4.0 * b * b * b / (3.0 * sqrt(kPi));
     hipLaunchKernelGGL(k_perm_assemble, dim3((c->npad + 255) / 256), dim3(256), 0, c->stream, c->npad, c->perm,
-                       c->pos_s, c->par_d, (const double4*)c->mp_d, c->sc_ptr, c->sc_j, c->sc_s, c->ereal, c->erec,
+                       c->pos_s, c->par_d, (const double4*)c->mp_d, c->sc_ptr, c->sc_j, scales, c->ereal, c->erec,
                        box, make_double3(1.0 / box.x, 1.0 / box.y, 1.0 / box.z), c->prm.cutoff * c->prm.cutoff, self,
                        out_slot, c->flags);
 }

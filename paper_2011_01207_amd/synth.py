@@ -56,6 +56,7 @@ class System:
     tol_debye: float = 1e-5
     seed: int = 0
     meta: dict = field(default_factory=dict)
+    sc_s_d: np.ndarray = None  # direct (d) scales of the same CSR pairs (two-set model); None: d = p
 
     @property
     def n(self) -> int:
@@ -209,15 +210,17 @@ def chain_solute(n_chain: int, box_len: float, rng: np.random.Generator) -> np.n
     return np.mod(pos, box_len)
 
 
-def solvated_chain(seed: int = 3) -> System:
-    """2,489-atom chain + 7,023 waters = 23,558 atoms in a 62.23 A box, PME grid 64^3."""
-    box_len, n_chain, n_w = 62.23, 2489, 7023
+def solvated_chain(seed: int = 3, box_len: float = 62.23, n_chain: int = 2489, n_w: int = 7023,
+                   lattice: int = 20, grid: int = 64, name: str = "solvated_chain_23558") -> System:
+    """2,489-atom chain + 7,023 waters = 23,558 atoms in a 62.23 A box, PME grid 64^3 (the
+    defaults); other sizes for tests.  Polarization groups for the direct (d) scales: chain atoms
+    3g, 3g+1, 3g+2 form group g (d = 0 inside a group, 1 otherwise), a water is one group."""
     rng = _rng(seed)
     chain = chain_solute(n_chain, box_len, rng)
     types = rng.integers(0, 4, n_chain)
     q_chain = rng.uniform(-0.5, 0.5, n_chain)
     q_chain -= q_chain.mean()
-    sites = lattice_sites(20, box_len)
+    sites = lattice_sites(lattice, box_len)
     dmin = np.empty(sites.shape[0])
     for s0 in range(0, sites.shape[0], 500):
         d = _min_image(sites[s0:s0 + 500, None, :] - chain[None, :, :], box_len)
@@ -240,11 +243,23 @@ def solvated_chain(seed: int = 3) -> System:
     pairs = np.concatenate([p12, p13, p14, wp])
     scales = np.concatenate([np.zeros(len(p12)), np.zeros(len(p13)), np.full(len(p14), 0.5), ws])
     ptr, sj, ss = _csr_from_arrays(n, pairs, scales)
+    # direct scales of the same pairs: 0 inside a polarization group, 1 between groups
+    chain_pairs = np.concatenate([p12, p13, p14])
+    d_chain = np.where(chain_pairs[:, 0] // 3 == chain_pairs[:, 1] // 3, 0.0, 1.0)
+    _, sj_d, ss_d = _csr_from_arrays(n, pairs, np.concatenate([d_chain, np.zeros(len(wp))]))
+    assert np.array_equal(sj_d, sj)
     mol = np.concatenate([np.zeros(n_chain, np.int32), 1 + np.repeat(np.arange(n_w, dtype=np.int32), 3)])
-    return System(name="solvated_chain_23558", pos=pos, box=np.full(3, box_len), q=q, dip=dip, quad=quad,
+    return System(name=name, pos=pos, box=np.full(3, box_len), q=q, dip=dip, quad=quad,
                   alpha=alpha, thole=thole, sc_ptr=ptr, sc_j=sj, sc_s=ss, mol=mol, buffer=0.0,
-                  grid=(64, 64, 64), tol_debye=1e-5, seed=seed,
-                  meta={"n_chain": n_chain, "n_waters": n_w, "types": types.astype(np.int32)})
+                  grid=(grid, grid, grid), tol_debye=1e-5, seed=seed,
+                  meta={"n_chain": n_chain, "n_waters": n_w, "types": types.astype(np.int32)}, sc_s_d=ss_d)
+
+
+def solvated_chain_small(seed: int = 11) -> System:
+    """A 240-atom chain + 500 waters (1,740 atoms) in a 26 A box, PME grid 30^3: the two-set
+    tests' workload, small enough for the oracle's exact solves."""
+    return solvated_chain(seed=seed, box_len=26.0, n_chain=240, n_w=500, lattice=8, grid=30,
+                          name="solvated_chain_1740")
 
 
 def water648(seed: int = 1) -> System:
