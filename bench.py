@@ -108,21 +108,29 @@ def new_context(s, t, precision, pair_store="auto"):
     return ctx
 
 
-def run_steps(ctx, t, frames, steps, warmup, tol, guess="zero", prev=None, timing_live=False, stage_pass=False):
+def run_steps(ctx, t, frames, steps, warmup, tol, guess="zero", prev=None, timing_live=False, stage_pass=False,
+              rebuild_each_step=False):
     """`steps` steps cycling over `frames` (device position tensors): list + E_perm + solve from
     `guess` ('zero'; 'given' with prev[k] = (dipoles, field) of the frame before frame k;
     'learned' with the network of the context's kind, whose delta kind takes prev[k] as its
-    reference; 'best' judges the learned guess against the given one).  Returns per-step
-    times, iterations, the last frame's outputs and the timers."""
+    reference; 'best' judges the learned guess against the given one).  The list is kept while
+    every atom stays within buffer/2 of its position at the last build (the masks are refreshed
+    for each frame) and rebuilt otherwise, or rebuilt at every step with rebuild_each_step.
+    Returns per-step times, iterations, list rebuilds, the last frame's outputs and the timers."""
     import torch
     from paper_2011_01207_amd import amoeba
     e_perm = torch.empty_like(frames[0])
     mu = torch.empty_like(frames[0])
     delta = guess in ("learned", "best") and ctx.guess_kind == "delta"
+    rebuilds = [0]
 
     def step(k):
         pos = frames[k % len(frames)]
-        ctx.build_blocklist(pos)
+        if rebuild_each_step:
+            ctx.build_blocklist(pos)
+            rebuilds[0] += 1
+        else:
+            rebuilds[0] += int(ctx.update_blocklist(pos))
         ctx.perm_field(pos, t["q"], t["dip"], t["quad"], out=e_perm)
         g = prev[k % len(frames)][0] if guess in ("given", "best") else None
         if delta:
@@ -139,6 +147,7 @@ def run_steps(ctx, t, frames, steps, warmup, tol, guess="zero", prev=None, timin
     if timing_live:
         ctx.set_timing("live")
     times, its, picks, eps = [], [], [], []
+    rebuilds[0] = 0
     t_all = time.perf_counter()
     for k in range(steps):
         t0 = time.perf_counter()
@@ -150,6 +159,7 @@ def run_steps(ctx, t, frames, steps, warmup, tol, guess="zero", prev=None, timin
     torch.cuda.synchronize()
     total = time.perf_counter() - t_all
     out = {"step_ms": 1e3 * total / steps, "solves_per_s": steps / total, **pstats(times),
+           "list_rebuilds": rebuilds[0],
            "iterations": its[-1], "mean_iterations": statistics.fmean(its), "e_pol_kcal": eps[-1],
            "learned_picked": sum(1 for p in picks if p == amoeba.AMOEBA_GUESS_LEARNED),
            # real-space products per pass of `steps` steps besides the PCG products: the
@@ -282,6 +292,12 @@ def headline(s, t, a):
         f"{learned['mean_iterations']:.1f} it")
     given = run_steps(ctx, t, eval_frames, a.steps, a.warmup, a.tol, guess="given", prev=prev)
     log(f"{s.name}: mixed + previous step {given['step_ms']:.3f} ms/step, {given['mean_iterations']:.1f} it")
+    rebuilt = run_steps(ctx, t, eval_frames, a.steps, a.warmup, a.tol, guess="learned", prev=prev,
+                        rebuild_each_step=True)
+    learned["rebuild_each_step"] = {k: rebuilt[k] for k in ("step_ms", "solves_per_s", "median_ms", "p10_ms",
+                                                             "p90_ms", "mean_iterations", "list_rebuilds")}
+    log(f"{s.name}: mixed + learned, list rebuilt every step {rebuilt['step_ms']:.3f} ms/step")
+    del rebuilt
     ctx.close()
     ctx = new_context(s, t, "mixed", a.pair_store)
     mixed = run_steps(ctx, t, eval_frames, a.steps, a.warmup, a.tol, guess="zero", stage_pass=True)
@@ -341,8 +357,9 @@ def subcell_accuracy(parent, model, tol):
 
 
 def secondary(a):
-    """FP64 and mixed zero-guess steps of the smaller workloads, with the oracle's exact solution
-    where it is cheap (648 and 23,558 atoms)."""
+    """FP64 and mixed zero-guess steps of the smaller workloads (one configuration, the list
+    rebuilt at every step), with the oracle's exact solution where it is cheap (648 and 23,558
+    atoms)."""
     import oracle as O
     from paper_2011_01207_amd import synth
     out = {}
@@ -351,7 +368,7 @@ def secondary(a):
         res = {}
         for prec in ("fp64", "mixed"):
             ctx = new_context(s, t, prec, a.pair_store)
-            res[prec] = run_steps(ctx, t, [t["pos"]], a.steps, a.warmup, a.tol)
+            res[prec] = run_steps(ctx, t, [t["pos"]], a.steps, a.warmup, a.tol, rebuild_each_step=True)
             ctx.close()
         entry = {p: strip(r) for p, r in res.items()}
         entry["speedup_mixed_vs_fp64"] = res["fp64"]["step_ms"] / res["mixed"]["step_ms"]
@@ -551,8 +568,11 @@ def main():
         "data": "synthetic",
         "config": {"workload": (f"{s.name}: {s.n // 3:,} rigid waters ({s.n:,} atoms), {s.box[0]:.2f} A cubic box, "
                                 f"rc 7 A + 2 A list buffer, beta 0.545/A, PME {s.grid[0]}^3 order 5; one step = "
-                                "block list + E_perm + learned initial guess + mixed-precision PCG to the tolerance, "
+                                "block list (kept while every atom stays within buffer/2 of its position at the last "
+                                "build, tested on the device at every step; the in-cutoff masks refreshed for the "
+                                "frame) + E_perm + learned initial guess + mixed-precision PCG to the tolerance, "
                                 "on held-out frames of a 0.02 A-step trajectory"),
+                   "list_rebuilds_timed": learned["list_rebuilds"],
                    "precision": "mixed", "guess": "learned (delta kind)", "tol_debye": a.tol},
         "roofline": top,
         "roofline_stages": stages,

@@ -179,6 +179,14 @@ int amoeba_set_atoms(amoeba_ctx* ctx, const double* alpha, const double* thole,
  * outside the box (they are wrapped). */
 int amoeba_build_blocklist(amoeba_ctx* ctx, const double* pos);
 
+/* Keep the blocked neighbour list valid for positions pos[N][3] (paper "Neighbor list": the
+ * list holds the pairs within cutoff + buffer so that it need not be rebuilt at every time
+ * step).  The list is rebuilt (as amoeba_build_blocklist) only when none exists or when an atom
+ * has moved more than buffer/2 from where it was at the last build; otherwise only the
+ * per-configuration in-cutoff masks are refreshed for pos.  *rebuilt_out (may be NULL) is set
+ * to 1 when the list was rebuilt, else 0.  Errors as amoeba_build_blocklist. */
+int amoeba_update_blocklist(amoeba_ctx* ctx, const double* pos, int32_t* rebuilt_out);
+
 /* Permanent field E_perm[N][3] (e/A^2) of charges q[N], dipoles dip[N][3] and traceless
  * quadrupoles quad[N][6] at positions pos (paper "Global scheme": real space + reciprocal
  * space): real-space tiles with Thole damping lambda3/5/7, the scaled-pair correction at any

@@ -102,6 +102,7 @@ def lib() -> ctypes.CDLL:
         L.amoeba_create_error.restype = ctypes.c_char_p
         L.amoeba_set_atoms.argtypes = [_P, _P, _P, _P, _P, _P, ctypes.c_int64]
         L.amoeba_build_blocklist.argtypes = [_P, _P]
+        L.amoeba_update_blocklist.argtypes = [_P, _P, ctypes.POINTER(ctypes.c_int32)]
         L.amoeba_perm_field.argtypes = [_P, _P, _P, _P, _P, _P]
         L.amoeba_set_direct_scales.argtypes = [_P, _P, ctypes.c_int64]
         L.amoeba_perm_field_dp.argtypes = [_P, _P, _P, _P, _P, _P, _P]
@@ -215,6 +216,14 @@ class Context:
 
     def build_blocklist(self, pos):
         return self._check(lib().amoeba_build_blocklist(self.h, _ptr(pos, torch.float64, (self.n, 3), "pos")))
+
+    def update_blocklist(self, pos):
+        """Rebuild the list only if none exists or an atom moved more than buffer/2 since the
+        last build, else refresh the masks; returns True when it rebuilt."""
+        r = ctypes.c_int32(0)
+        self._check(lib().amoeba_update_blocklist(self.h, _ptr(pos, torch.float64, (self.n, 3), "pos"),
+                                                  ctypes.byref(r)))
+        return bool(r.value)
 
     def perm_field(self, pos, q, dip, quad, out=None):
         n = self.n

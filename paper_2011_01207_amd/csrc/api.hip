@@ -485,6 +485,32 @@ int amoeba_build_blocklist(amoeba_ctx* c, const double* pos)
     return rc;
 }
 
+int amoeba_update_blocklist(amoeba_ctx* c, const double* pos, int32_t* rebuilt_out)
+{
+    if (!c)
+        return AMOEBA_E_INVALID;
+    c->err.clear();
+    if (rebuilt_out)
+        *rebuilt_out = 0;
+    if (!pos)
+        return set_error(c, AMOEBA_E_INVALID, "amoeba_update_blocklist: NULL pos");
+    if (c->atoms_set && c->list_built) {
+        // the displacement test of every configuration change; a stale list is rebuilt below
+        int rc = begin_config(c, pos, "amoeba_update_blocklist");
+        if (rc != AMOEBA_E_LIST)
+            return rc;
+        c->err.clear();
+    }
+    int rc = build_blocklist(c, pos);
+    if (rc) {
+        c->list_built = false;
+        return rc;
+    }
+    if (rebuilt_out)
+        *rebuilt_out = 1;
+    return AMOEBA_OK;
+}
+
 // The parts of E_perm shared by the scale sets (multipoles in slot order, the unscaled tiles'
 // sums in ereal, the reciprocal field in erec), leaving the flags unread.
 static int perm_field_parts(amoeba_ctx* c, const double* pos, const double* q, const double* dip,

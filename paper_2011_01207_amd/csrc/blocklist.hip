@@ -263,30 +263,34 @@ __global__ void k_csr_fill(int npad, const int* __restrict__ perm, const int* __
     }
 }
 
-// Caller positions into slot order (one thread per atom, reading in the caller's order and
-// writing its slot), wrapped into the box; flags NaN/Inf, a changed configuration and (if a
-// reference exists) atoms that moved more than buffer/2 since the list build.
-// ref_out (list build): also keep the positions as the reference of the staleness test.
+// Caller positions into slot order (one thread per slot: the slot's reads and writes are
+// coalesced, the only scattered access is the read of its atom's caller-order position), wrapped
+// into the box; flags NaN/Inf, a changed configuration and (if a reference exists) atoms that
+// moved more than buffer/2 since the list build.  ref_out (list build): also keep the positions
+// as the reference of the staleness test.  Phantom slots (perm < 0) hold zeros.
 // Flags go to one device word that every workgroup may set; same-address device atomics are
 // serialized, so each workgroup ORs its flags in LDS first and issues at most one atomic, and
 // the grid is capped at kScatterWG workgroups (grid-stride loop).
 constexpr int kScatterWG = 1024;
 
-__global__ __launch_bounds__(256) void k_scatter_pos(int n, int npad, const int* __restrict__ slot,
-                                                     const double* __restrict__ pos, double3 box,
-                                                     double4* __restrict__ pos_s, const double4* __restrict__ ref,
-                                                     double half_buf2, int* __restrict__ flags,
-                                                     double4* __restrict__ ref_out)
+__global__ __launch_bounds__(256) void k_gather_pos(int npad, const int* __restrict__ perm,
+                                                    const double* __restrict__ pos, double3 box,
+                                                    double4* __restrict__ pos_s, const double4* __restrict__ ref,
+                                                    double half_buf2, int* __restrict__ flags,
+                                                    double4* __restrict__ ref_out)
 {
     __shared__ int s_f;
     if (threadIdx.x == 0)
         s_f = 0;
     __syncthreads();
     int f = 0;
-    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < npad; t += gridDim.x * blockDim.x) {
-        if (t < n) {
-            const int s = slot[t];
-            double x = pos[3 * t], y = pos[3 * t + 1], z = pos[3 * t + 2];
+    for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < npad; s += gridDim.x * blockDim.x) {
+        const int a = perm[s];
+        double x = 0.0, y = 0.0, z = 0.0;
+        if (a >= 0) {
+            x = pos[3 * (size_t)a];
+            y = pos[3 * (size_t)a + 1];
+            z = pos[3 * (size_t)a + 2];
             if (!isfinite(x) || !isfinite(y) || !isfinite(z)) {
                 f |= kFlagNonFinite;
                 x = y = z = 0.0;
@@ -303,14 +307,10 @@ __global__ __launch_bounds__(256) void k_scatter_pos(int n, int npad, const int*
                 if (dx * dx + dy * dy + dz * dz > half_buf2)
                     f |= kFlagStale;
             }
-            pos_s[s] = make_double4(x, y, z, 0.0);
-            if (ref_out)
-                ref_out[s] = make_double4(x, y, z, 0.0);
-        } else {  // phantom slots n .. npad-1
-            pos_s[t] = make_double4(0.0, 0.0, 0.0, 0.0);
-            if (ref_out)
-                ref_out[t] = make_double4(0.0, 0.0, 0.0, 0.0);
         }
+        pos_s[s] = make_double4(x, y, z, 0.0);
+        if (ref_out)
+            ref_out[s] = make_double4(x, y, z, 0.0);
     }
     if (f != 0)
         atomicOr(&s_f, f);
@@ -1103,9 +1103,8 @@ static int build_tiles(amoeba_ctx* c, const double* pos)
     if (c->atoms_set && (rc = sort_params(c)) != AMOEBA_OK)
         return fail(rc);
 
-    hipLaunchKernelGGL(k_scatter_pos, dim3(std::min(nblk(npad, 256), kScatterWG)), dim3(256), 0, st, n, npad,
-                       c->slot, pos, box,
-                       c->pos_s, (const double4*)nullptr, 0.0, c->flags, c->pos_ref);
+    hipLaunchKernelGGL(k_gather_pos, dim3(std::min(nblk(npad, 256), kScatterWG)), dim3(256), 0, st, npad, c->perm,
+                       pos, box, c->pos_s, (const double4*)nullptr, 0.0, c->flags, c->pos_ref);
     hipLaunchKernelGGL(k_bbox, dim3(nb), dim3(64), 0, st, nb, c->perm, c->pos_s, box, bc, bh);
     const double rcb = c->prm.cutoff + c->prm.buffer;
     hipLaunchKernelGGL(k_block_grid, dim3(1), dim3(1024), 0, st, nb, bh, box, rcb,
@@ -1211,9 +1210,9 @@ int prepare_config(amoeba_ctx* c, const double* pos)
     double3 box = make_double3(c->prm.box[0], c->prm.box[1], c->prm.box[2]);
     double hb = 0.5 * c->prm.buffer;
     hipMemsetAsync(c->flags, 0, sizeof(int), st);
-    hipLaunchKernelGGL(k_scatter_pos, dim3(std::min(nblk(c->npad, 256), kScatterWG)), dim3(256), 0, st, c->n,
-                       c->npad, c->slot, pos, box,
-                       c->pos_s, (const double4*)c->pos_ref, hb * hb, c->flags, (double4*)nullptr);
+    hipLaunchKernelGGL(k_gather_pos, dim3(std::min(nblk(c->npad, 256), kScatterWG)), dim3(256), 0, st, c->npad,
+                       c->perm, pos, box, c->pos_s, (const double4*)c->pos_ref, hb * hb, c->flags,
+                       (double4*)nullptr);
     hipMemcpyAsync(c->flags_host, c->flags, sizeof(int), hipMemcpyDeviceToHost, st);
     int rc = hip_check(c, hipStreamSynchronize(st), "prepare_config");
     if (rc)
