@@ -320,8 +320,9 @@ __device__ __forceinline__ double fma_r(double a, double b, double c) { return f
 template <typename R> struct DipoleKind {
     using R4 = typename V4<R>::T;
     static constexpr int NV = 1;
-    // the j-field is linear in the i dipole (d[0].xyz) and nothing else of the pair uses it, so
-    // with integer sums the i dipoles are held times 2^38 and the j-field comes out scaled
+    // the j-field is linear in the i dipole (d[0].xyz) and the i-field in the j dipole, and
+    // nothing else of the pair uses them, so with integer sums both are held times 2^38 and
+    // both fields come out scaled
     static constexpr bool kScaledJ = true;
     __device__ static void scale_i(R4* d, R f)
     {
@@ -379,8 +380,9 @@ template <typename R> struct DipoleKind {
 // d[2] = (Tyz, Tzz, Thole a, 0).
 template <typename R> struct MultipoleKind {
     using R4 = typename V4<R>::T;
-    // the j-field is linear in the i multipoles (everything but the Thole factor d[2].z), which
-    // nothing else of the pair uses: held times 2^38 with integer sums, as for the dipoles
+    // the j-field is linear in the i multipoles (everything but the Thole factor d[2].z) and
+    // the i-field in the j multipoles, which nothing else of the pair uses: held times 2^38
+    // with integer sums, as for the dipoles
     static constexpr bool kScaledJ = true;
     static constexpr bool kParamsInSrc = false;
     __device__ static void scale_i(R4* d, R f)
@@ -588,7 +590,7 @@ __global__ __launch_bounds__(256) void k_block_tiles(int nb, const int* __restri
     using R2 = typename V2<R>::T;
     using LT = typename LdsAcc<FIX>::T;
     constexpr int NV = K::NV;
-    constexpr bool SJ = FIX && K::kScaledJ;  // i sources held times 2^38, j-fields added pre-scaled
+    constexpr bool SJ = FIX && K::kScaledJ;  // sources held times 2^38, fields added pre-scaled
     __shared__ R4 s_ip[kBlock];                      // i offset from the block origin, w = alpha^-1/6
     __shared__ R4 s_id[NV][kBlock];                  // i source data
     __shared__ R4 s_jp[kWavesPerWG][kBlock];         // j offset from the i-block origin, w = alpha^-1/6
@@ -678,6 +680,11 @@ __global__ __launch_bounds__(256) void k_block_tiles(int nb, const int* __restri
                 }
             }
             s_jp[w][lane] = R4{jr.x, jr.y, jr.z, dj};
+            // with integer sums the i-field of a row is linear in the j sources, so they are held
+            // times 2^38 as the i sources are, and a row's i-field goes to the accumulator
+            // pre-scaled too
+            if constexpr (SJ)
+                K::scale_i(d, (R)kFixQScaleF);
 #pragma unroll
             for (int v = 0; v < NV; ++v)
                 s_jd[w][v][lane] = d[v];
@@ -689,6 +696,7 @@ __global__ __launch_bounds__(256) void k_block_tiles(int nb, const int* __restri
         s_mask[w][lane] = m;
         int P;
         s_off[w][lane] = wave_excl_scan(__popcll(m), lane, P);
+        const unsigned long long rows_used = __ballot(m != 0ull);  // rows with pairs (wave-uniform)
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -707,15 +715,22 @@ __global__ __launch_bounds__(256) void k_block_tiles(int nb, const int* __restri
             // one pair of the walk: the next set bit (when the row is used up, its i-field goes
             // to the block accumulator and the lane moves to the next row with pairs), the
             // pair's field from eval, the j-field added
+            auto flush_row = [&]() {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    if constexpr (SJ)
+                        LdsAcc<FIX>::add_scaled(&s_ei[c][i], ea[c]);
+                    else
+                        LdsAcc<FIX>::add(&s_ei[c][i], ea[c]);
+                }
+            };
             auto visit = [&](auto&& eval) {
                 if (rem == 0ull) {
-#pragma unroll
-                    for (int c = 0; c < 3; ++c)
-                        LdsAcc<FIX>::add(&s_ei[c][i], ea[c]);
+                    flush_row();
                     ea[0] = ea[1] = ea[2] = 0;
-                    do {
-                        rem = s_mask[w][++i];
-                    } while (rem == 0ull);
+                    // the next row with pairs (one exists: the lane's share is not used up)
+                    i = __builtin_ctzll(rows_used & (~1ull << i));
+                    rem = s_mask[w][i];
                     ip = s_ip[i];
 #pragma unroll
                     for (int v = 0; v < NV; ++v)
@@ -772,9 +787,7 @@ __global__ __launch_bounds__(256) void k_block_tiles(int nb, const int* __restri
                         }
                     });
             }
-#pragma unroll
-            for (int c = 0; c < 3; ++c)
-                LdsAcc<FIX>::add(&s_ei[c][i], ea[c]);
+            flush_row();
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
