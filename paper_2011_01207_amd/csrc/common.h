@@ -158,6 +158,7 @@ struct amoeba_ctx {
     int32_t* perm = nullptr;       // [npad] slot -> original atom (-1 phantom)
     int32_t* slot = nullptr;       // [n] original atom -> slot
     double4* par_d = nullptr;      // [npad] (alpha, 1/alpha, alpha^-1/6, thole)
+    double* alpha_s = nullptr;     // [npad] alpha (the PCG preconditioner; 1 on phantom slots)
     float4* par_f = nullptr;       // same in FP32
     int32_t* sc_ptr = nullptr;     // [npad+1] CSR of scaled pairs in slot order
     int32_t* sc_j = nullptr;       // [n_scaled] partner slot
@@ -244,7 +245,6 @@ struct amoeba_ctx {
     double* erec = nullptr;                // [npad*3] reciprocal field scratch
     double* v_mu = nullptr;
     double* v_r = nullptr;
-    double* v_z = nullptr;
     double* v_p = nullptr;
     double* v_q = nullptr;
     double* v_e = nullptr;                 // E_perm in slot order

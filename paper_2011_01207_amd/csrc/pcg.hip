@@ -106,20 +106,18 @@ template <> struct Comp<double4> {
 
 // r = e - q (q may be NULL: zero guess), z = alpha r, p = z; partials of r.z and z.z
 template <typename R4T>
-__global__ __launch_bounds__(256) void k_init_residual(int npad, const double4* __restrict__ par,
+__global__ __launch_bounds__(256) void k_init_residual(int npad, const double* __restrict__ alpha,
                                                        const double* __restrict__ e, const double* __restrict__ q,
-                                                       double* __restrict__ r, double* __restrict__ z,
-                                                       double* __restrict__ p, R4T* __restrict__ pv,
-                                                       double* __restrict__ part)
+                                                       double* __restrict__ r, double* __restrict__ p,
+                                                       R4T* __restrict__ pv, double* __restrict__ part)
 {
     double acc[2] = {0.0, 0.0};
     const size_t n3 = 3 * (size_t)npad;
     for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n3; i += (size_t)gridDim.x * 256) {
-        double al = par[i / 3].x;
+        double al = alpha[i / 3];
         double rv = e[i] - (q ? q[i] : 0.0);
         double zv = al * rv;
         r[i] = rv;
-        z[i] = zv;
         p[i] = zv;
         Comp<R4T>::set(pv, i, zv);
         acc[0] += rv * zv;
@@ -156,10 +154,10 @@ __global__ __launch_bounds__(256) void k_init_finalize(int nparts, const double*
 // z = alpha r; partials of the new r.z and z.z
 // The iteration index is the device's count of completed iterations, so that the launches of
 // an iteration take no per-iteration argument (one captured iteration serves them all).
-__global__ __launch_bounds__(256) void k_update(int npad, const double4* __restrict__ par,
+__global__ __launch_bounds__(256) void k_update(int npad, const double* __restrict__ alpha,
                                                 const double* __restrict__ p, const double* __restrict__ q,
                                                 double* __restrict__ mu, double* __restrict__ r,
-                                                double* __restrict__ z, PcgScalars* __restrict__ sc,
+                                                PcgScalars* __restrict__ sc,
                                                 const double* __restrict__ part_pq, int n_pq,
                                                 double* __restrict__ part)
 {
@@ -188,12 +186,11 @@ __global__ __launch_bounds__(256) void k_update(int npad, const double4* __restr
     double acc[2] = {0.0, 0.0};
     const size_t n3 = 3 * (size_t)npad;
     for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n3; i += (size_t)gridDim.x * 256) {
-        double al = par[i / 3].x;
+        double al = alpha[i / 3];
         mu[i] += g * p[i];
         double rv = r[i] - g * q[i];
-        double zv = al * rv;
+        double zv = al * rv;   // z = alpha r, formed again by the direction kernel
         r[i] = rv;
-        z[i] = zv;
         acc[0] += rv * zv;
         acc[1] += zv * zv;
     }
@@ -206,8 +203,9 @@ __global__ __launch_bounds__(256) void k_update(int npad, const double4* __restr
 
 // convergence test on rms(z); unless converged: beta = r.z(new) / r.z(old), p = z + beta p
 template <typename R4T>
-__global__ __launch_bounds__(256) void k_direction(int npad, int n, const double* __restrict__ z,
-                                                   double* __restrict__ p, R4T* __restrict__ pv,
+__global__ __launch_bounds__(256) void k_direction(int npad, int n, const double* __restrict__ alpha,
+                                                   const double* __restrict__ r, double* __restrict__ p,
+                                                   R4T* __restrict__ pv,
                                                    PcgScalars* __restrict__ sc, const double* __restrict__ part,
                                                    PcgScalars* __restrict__ pub)
 {
@@ -250,7 +248,7 @@ __global__ __launch_bounds__(256) void k_direction(int npad, int n, const double
         return;
     const size_t n3 = 3 * (size_t)npad;
     for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n3; i += (size_t)gridDim.x * 256) {
-        double v = z[i] + beta * p[i];
+        double v = alpha[i / 3] * r[i] + beta * p[i];
         p[i] = v;
         Comp<R4T>::set(pv, i, v);
     }
@@ -350,11 +348,11 @@ static void launch_init_residual(amoeba_ctx* c, const double* q, int it)
 {
     StageTimer tm(c, AMOEBA_T_PCG);
     if (c->mixed)
-        hipLaunchKernelGGL(k_init_residual<float4>, dim3(kRedBlocks), dim3(256), 0, c->stream, c->npad, c->par_d,
-                           c->v_e, q, c->v_r, c->v_z, c->v_p, c->pv_f, part_vec(c));
+        hipLaunchKernelGGL(k_init_residual<float4>, dim3(kRedBlocks), dim3(256), 0, c->stream, c->npad, c->alpha_s,
+                           c->v_e, q, c->v_r, c->v_p, c->pv_f, part_vec(c));
     else
-        hipLaunchKernelGGL(k_init_residual<double4>, dim3(kRedBlocks), dim3(256), 0, c->stream, c->npad, c->par_d,
-                           c->v_e, q, c->v_r, c->v_z, c->v_p, c->pv_d, part_vec(c));
+        hipLaunchKernelGGL(k_init_residual<double4>, dim3(kRedBlocks), dim3(256), 0, c->stream, c->npad, c->alpha_s,
+                           c->v_e, q, c->v_r, c->v_p, c->pv_d, part_vec(c));
     hipLaunchKernelGGL(k_init_finalize, dim3(1), dim3(256), 0, c->stream, kRedBlocks, part_vec(c), c->n, it, c->sc);
 }
 
@@ -364,14 +362,14 @@ static int enqueue_iteration_direct(amoeba_ctx* c, hipEvent_t fork_ev)
     if (rc)
         return rc;
     StageTimer tm(c, AMOEBA_T_PCG);
-    hipLaunchKernelGGL(k_update, dim3(kRedBlocks), dim3(256), 0, c->stream, c->npad, c->par_d, c->v_p, c->v_q,
-                       c->v_mu, c->v_r, c->v_z, c->sc, part_pq(c), c->npq, part_vec(c));
+    hipLaunchKernelGGL(k_update, dim3(kRedBlocks), dim3(256), 0, c->stream, c->npad, c->alpha_s, c->v_p, c->v_q,
+                       c->v_mu, c->v_r, c->sc, part_pq(c), c->npq, part_vec(c));
     if (c->mixed)
-        hipLaunchKernelGGL(k_direction<float4>, dim3(kRedBlocks), dim3(256), 0, c->stream, c->npad, c->n, c->v_z,
-                           c->v_p, c->pv_f, c->sc, part_vec(c), c->sc_host_dev);
+        hipLaunchKernelGGL(k_direction<float4>, dim3(kRedBlocks), dim3(256), 0, c->stream, c->npad, c->n,
+                           c->alpha_s, c->v_r, c->v_p, c->pv_f, c->sc, part_vec(c), c->sc_host_dev);
     else
-        hipLaunchKernelGGL(k_direction<double4>, dim3(kRedBlocks), dim3(256), 0, c->stream, c->npad, c->n, c->v_z,
-                           c->v_p, c->pv_d, c->sc, part_vec(c), c->sc_host_dev);
+        hipLaunchKernelGGL(k_direction<double4>, dim3(kRedBlocks), dim3(256), 0, c->stream, c->npad, c->n,
+                           c->alpha_s, c->v_r, c->v_p, c->pv_d, c->sc, part_vec(c), c->sc_host_dev);
     return AMOEBA_OK;
 }
 
