@@ -466,17 +466,23 @@ __global__ void k_cell_start(int nb, int ncell_cap, const unsigned* __restrict__
 }
 
 
+// Exclusive prefix sum over the 64 lanes of a wave (all lanes active) and the wave total, by
+// data-parallel primitives: shifts by 1, 2, 4, 8 lanes within each row of 16, then row 0's total
+// into row 1 and row 2's into row 3 (broadcast of lane 15 of the row before), then the first two
+// rows' total into rows 2 and 3 (broadcast of lane 31).  Lanes a shift or broadcast does not
+// reach add 0.
 __device__ __forceinline__ int wave_excl_scan_i(int x, int lane, int& total)
 {
-    int incl = x;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        int y = __shfl_up(incl, d);
-        if (lane >= d)
-            incl += y;
-    }
-    total = __shfl(incl, 63);
-    return incl - x;
+    (void)lane;
+    int v = x;
+    v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, false);  // row_shr:1
+    v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, false);  // row_shr:2
+    v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, false);  // row_shr:4
+    v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, false);  // row_shr:8
+    v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false);  // row_bcast:15 -> rows 1, 3
+    v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false);  // row_bcast:31 -> rows 2, 3
+    total = __builtin_amdgcn_readlane(v, 63);
+    return v - x;
 }
 
 // Whether j (offset from the i-block centre, inside rcb of the block's box) lies within rf2 of an
@@ -825,11 +831,14 @@ __global__ __launch_bounds__(256) void k_tile_refresh(int ntiles, const int* __r
                                                       double rc2, unsigned long long* __restrict__ mask,
                                                       double4* __restrict__ jrel_d, float4* __restrict__ jrel_f,
                                                       int* __restrict__ tile_np, int* __restrict__ tile_rows,
+                                                      uint16_t* __restrict__ walk,
                                                       unsigned long long* __restrict__ pair_part)
 {
     __shared__ double4 s_jd[4][kBlock];
     __shared__ float4 s_jf[4][kBlock];
     __shared__ unsigned long long s_cnt[4];
+    __shared__ unsigned long long s_m[4][kBlock];
+    __shared__ int s_off[4][kBlock];
     int gt = blockIdx.x * blockDim.x + threadIdx.x;
     int t = gt >> 6, lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     bool act = t < ntiles;
@@ -883,6 +892,35 @@ __global__ __launch_bounds__(256) void k_tile_refresh(int ntiles, const int* __r
             }
         }
         mask[(size_t)t * kBlock + lane] = m;
+    }
+    // The pair kernels split a tile's in-cutoff pairs (row-major) among the 64 lanes of a wave,
+    // lane l taking pairs [l B, (l + 1) B) with B = ceil(P / 64).  Its first pair, row i (the
+    // last row whose exclusive pair offset is <= l B) and that row's bit, is found here once
+    // per configuration instead of by every product.
+    {
+        int P;
+        const int off = wave_excl_scan_i(__popcll(m), lane, P);
+        s_off[w][lane] = off;
+        s_m[w][lane] = m;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (act) {
+            const int Bs = (P + 63) >> 6, p0 = lane * Bs;
+            uint16_t ws = 0xffff;
+            if (p0 < P) {
+                int lo = 0, hi = kBlock - 1;
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (s_off[w][mid] <= p0)
+                        lo = mid;
+                    else
+                        hi = mid - 1;
+                }
+                ws = (uint16_t)(lo | nth_set_bit(s_m[w][lo], p0 - s_off[w][lo]) << 8);
+            }
+            walk[(size_t)t * kBlock + lane] = ws;
+        }
     }
     // pairs of the workgroup's tiles: one partial per workgroup, summed in order by
     // k_sum_pairs (no global atomics)
@@ -1014,7 +1052,7 @@ static int refresh_tiles(amoeba_ctx* c)
                        c->ntiles, c->tile_blk, c->tile_j, c->perm,
                        c->pos_s, c->blk_org, c->off_f, c->par_d, box, binv, c->prm.cutoff * c->prm.cutoff,
                        c->tile_mask,
-                       c->jrel_d, c->jrel_f, c->tile_np, c->tile_rows, c->pair_part);
+                       c->jrel_d, c->jrel_f, c->tile_np, c->tile_rows, c->tile_walk, c->pair_part);
     c->pair_nwg = nwg;
     c->pairs_pending = true;  // summed (k_sum_pairs) when amoeba_get_info asks for the count
     coef_invalidate(c);
@@ -1162,6 +1200,7 @@ static int build_tiles(amoeba_ctx* c, const double* pos)
             (rc = ctx_alloc(c, (void**)&c->tile_j, sizeof(int) * tb)) ||
             (rc = ctx_alloc(c, (void**)&c->tile_mask, sizeof(unsigned long long) * tb)) ||
             (rc = ctx_alloc(c, (void**)&c->tile_np, sizeof(int) * total)) ||
+            (rc = ctx_alloc(c, (void**)&c->tile_walk, sizeof(uint16_t) * tb)) ||
             (rc = ctx_alloc(c, (void**)&c->tile_rows, sizeof(int) * total)) ||
             (rc = ctx_alloc(c, (void**)&c->coef_row0, sizeof(int) * (total + 1))) ||
             (c->mixed && (rc = ctx_alloc(c, (void**)&c->jrel_f, sizeof(float4) * tb))) ||

@@ -186,6 +186,8 @@ struct amoeba_ctx {
     int32_t* tile_j = nullptr;     // [ntiles*64] j slot or -1
     unsigned long long* tile_mask = nullptr; // [ntiles*64] bit k of row i: pair (i, j_k) within rc
     int32_t* tile_np = nullptr;    // [ntiles] in-cutoff pairs of each tile (per configuration)
+    uint16_t* tile_walk = nullptr; // [ntiles*64] first pair of lane l's share of the tile's pairs:
+                                   // row | bit << 8, 0xffff for no pairs (per configuration)
     int32_t* tile_rows = nullptr;  // [ntiles] ceil(tile_np / 64): rows of 64 stored pair coefficients
     int32_t* coef_row0 = nullptr;  // [ntiles+1] first stored-coefficient row of each tile (exclusive scan)
     double4* jrel_d = nullptr;     // [ntiles*64] j position relative to the i-block origin

@@ -123,60 +123,6 @@ template <> struct LdsAcc<false> {
     __device__ static double value(T v) { return v; }
 };
 
-__device__ __forceinline__ int wave_excl_scan(int x, int lane, int& total)
-{
-    int incl = x;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        int y = __shfl_up(incl, d);
-        if (lane >= d)
-            incl += y;
-    }
-    total = __shfl(incl, 63);
-    return incl - x;
-}
-
-// Position of set bit number n (0-based) of m, n < popcount(m): a binary search on the
-// popcounts of halves, quarters, ...
-__device__ __forceinline__ int nth_set_bit(unsigned long long m, int n)
-{
-    unsigned w = (unsigned)m;
-    int base = 0;
-    int c = __popc(w);
-    if (n >= c) {
-        n -= c;
-        w = (unsigned)(m >> 32);
-        base = 32;
-    }
-#pragma unroll
-    for (int half = 16; half >= 1; half >>= 1) {
-        c = __popc(w & ((1u << half) - 1u));
-        if (n >= c) {
-            n -= c;
-            w >>= half;
-            base += half;
-        }
-    }
-    return base;
-}
-
-// first pair of a lane's range: row i (largest with off[i] <= p0) and its mask with the first
-// (p0 - off[i]) set bits cleared
-__device__ __forceinline__ void walk_start(const int* s_off, const unsigned long long* s_mask, int p0, int& i,
-                                           unsigned long long& rem)
-{
-    int lo = 0, hi = 63;
-    while (lo < hi) {
-        int mid = (lo + hi + 1) >> 1;
-        if (s_off[mid] <= p0)
-            lo = mid;
-        else
-            hi = mid - 1;
-    }
-    i = lo;
-    const unsigned long long m = s_mask[i];
-    rem = m & (~0ull << nth_set_bit(m, p0 - s_off[i]));
-}
 
 // Very close pairs: B_n ~ (2n-1)!!/r^(2n+1) and its Thole term cancel to an O(1) B_n', which the
 // direct formula cannot resolve once the rounding of the two terms exceeds the result (in FP32
@@ -577,6 +523,7 @@ __global__ __launch_bounds__(256) void k_block_tiles(int nb, const int* __restri
                                                      const int* __restrict__ tile_np,
                                                      const int* __restrict__ tile_j,
                                                      const unsigned long long* __restrict__ tile_mask,
+                                                     const uint16_t* __restrict__ tile_walk,
                                                      const typename V4<R>::T* __restrict__ jrel,
                                                      const typename V4<R>::T* __restrict__ off,
                                                      const typename V4<R>::T* __restrict__ par,
@@ -598,7 +545,6 @@ __global__ __launch_bounds__(256) void k_block_tiles(int nb, const int* __restri
     __shared__ LT s_ei[3][kBlock];                   // block i-field over all tiles
     __shared__ LT s_ej[kWavesPerWG][3][kBlock];      // tile j-field
     __shared__ unsigned long long s_mask[kWavesPerWG][kBlock];
-    __shared__ int s_off[kWavesPerWG][kBlock];
     if (use_done && sc->done)
         return;
     const int I = blockIdx.x;
@@ -629,8 +575,9 @@ __global__ __launch_bounds__(256) void k_block_tiles(int nb, const int* __restri
     int load0 = 0, load1 = 0, load2 = 0, load3 = 0;
     for (int tt = 0; tt < nt; ++tt) {
         const int t = t0 + tt;
+        const int P = tile_np[t];  // the tile's pairs
         {
-            const int cost = tile_np[t] + kTileCost;
+            const int cost = P + kTileCost;
             int wm = 0, lm = load0;
             wm = load1 < lm ? 1 : wm;
             lm = min(lm, load1);
@@ -693,9 +640,8 @@ __global__ __launch_bounds__(256) void k_block_tiles(int nb, const int* __restri
         for (int c = 0; c < 3; ++c)
             s_ej[w][c][lane] = (LT)0;
         const unsigned long long m = tile_mask[(size_t)t * kBlock + lane];
+        const unsigned ws = tile_walk[(size_t)t * kBlock + lane];  // first pair of the lane's share
         s_mask[w][lane] = m;
-        int P;
-        s_off[w][lane] = wave_excl_scan(__popcll(m), lane, P);
         const unsigned long long rows_used = __ballot(m != 0ull);  // rows with pairs (wave-uniform)
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
@@ -703,9 +649,8 @@ __global__ __launch_bounds__(256) void k_block_tiles(int nb, const int* __restri
         const int B = (P + 63) >> 6;
         const int p0 = lane * B, p1 = min(p0 + B, P);
         if (p0 < p1) {
-            int i;
-            unsigned long long rem;
-            walk_start(s_off[w], s_mask[w], p0, i, rem);
+            int i = (int)(ws & 63u);
+            unsigned long long rem = s_mask[w][i] & (~0ull << (ws >> 8));
             R4 ip = s_ip[i];
             R4 di[NV];
 #pragma unroll
@@ -862,7 +807,8 @@ static void dipole_tiles(amoeba_ctx* c, bool use_done, hipStream_t st, const typ
                          const typename V4<R>::T* off, const typename V4<R>::T* par, const typename V4<R>::T* pv)
 {
     hipLaunchKernelGGL((k_block_tiles<R, FIX, DipoleKind<R>, MI, CM>), dim3(c->nb), dim3(256), 0, st, c->nb,
-                       c->blk_tile0, c->tile_np, c->tile_j, c->tile_mask, jrel, off, par, pv, make_ewald<R>(c),
+                       c->blk_tile0, c->tile_np, c->tile_j, c->tile_mask, c->tile_walk, jrel, off, par, pv,
+                       make_ewald<R>(c),
                        c->eipart, (R*)c->jbuf, c->sc, (int)use_done, c->coef_row0, (long long)c->coef_cap_rows,
                        (typename V2<R>::T*)c->coef);
 }
@@ -993,12 +939,14 @@ template <bool MI> static void perm_tiles(amoeba_ctx* c, hipStream_t st)
     StageTimer tm(c, AMOEBA_T_PERM, st);
     if (c->mixed)
         hipLaunchKernelGGL((k_block_tiles<float, true, MultipoleKind<float>, MI>), dim3(c->nb), dim3(256), 0,
-                           st, c->nb, c->blk_tile0, c->tile_np, c->tile_j, c->tile_mask, c->jrel_f, c->off_f, c->par_f,
+                           st, c->nb, c->blk_tile0, c->tile_np, c->tile_j, c->tile_mask, c->tile_walk, c->jrel_f,
+                           c->off_f, c->par_f,
                            (const float4*)c->mp_f, make_ewald<float>(c), c->eipart, (float*)c->jbuf, c->sc, 0,
                            (const int*)nullptr, 0ll, (float2*)nullptr);
     else
         hipLaunchKernelGGL((k_block_tiles<double, false, MultipoleKind<double>, MI>), dim3(c->nb), dim3(256), 0,
-                           st, c->nb, c->blk_tile0, c->tile_np, c->tile_j, c->tile_mask, c->jrel_d, c->off_d, c->par_d,
+                           st, c->nb, c->blk_tile0, c->tile_np, c->tile_j, c->tile_mask, c->tile_walk, c->jrel_d,
+                           c->off_d, c->par_d,
                            (const double4*)c->mp_d, make_ewald<double>(c), c->eipart, (double*)c->jbuf, c->sc, 0,
                            (const int*)nullptr, 0ll, (double2*)nullptr);
 }
@@ -1007,12 +955,14 @@ template <bool MI> static void force_tiles(amoeba_ctx* c, const void* src)
 {
     if (c->mixed)
         hipLaunchKernelGGL((k_block_tiles<float, true, ForceKind<float>, MI>), dim3(c->nb), dim3(256), 0,
-                           c->stream, c->nb, c->blk_tile0, c->tile_np, c->tile_j, c->tile_mask, c->jrel_f, c->off_f,
+                           c->stream, c->nb, c->blk_tile0, c->tile_np, c->tile_j, c->tile_mask, c->tile_walk,
+                           c->jrel_f, c->off_f,
                            c->par_f, (const float4*)src, make_ewald<float>(c), c->eipart, (float*)c->jbuf, c->sc, 0,
                            (const int*)nullptr, 0ll, (float2*)nullptr);
     else
         hipLaunchKernelGGL((k_block_tiles<double, false, ForceKind<double>, MI>), dim3(c->nb), dim3(256), 0,
-                           c->stream, c->nb, c->blk_tile0, c->tile_np, c->tile_j, c->tile_mask, c->jrel_d, c->off_d,
+                           c->stream, c->nb, c->blk_tile0, c->tile_np, c->tile_j, c->tile_mask, c->tile_walk,
+                           c->jrel_d, c->off_d,
                            c->par_d, (const double4*)src, make_ewald<double>(c), c->eipart, (double*)c->jbuf, c->sc,
                            0, (const int*)nullptr, 0ll, (double2*)nullptr);
 }
