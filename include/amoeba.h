@@ -216,6 +216,21 @@ int amoeba_polarize(amoeba_ctx* ctx, const double* pos, const double* e_perm,
                     const double* mu_guess, int32_t guess_mode, double tol_debye, int32_t max_iter,
                     double* mu_out, double* e_pol_out, int32_t* iters_out);
 
+/* One configuration of a trajectory in one call (paper "Global scheme": the permanent field,
+ * then the induced dipoles, at every step; "Neighbor list": the list kept while the buffer
+ * allows): amoeba_update_blocklist(pos), amoeba_perm_field(pos, q, dip, quad) and
+ * amoeba_polarize(pos, E_perm, mu_guess, guess_mode, ...) with the same meaning of every
+ * argument and output, with E_perm handed to the solve in the library's own atom order and
+ * without the host waits between the three.  e_perm_out[N][3] (may be NULL) receives E_perm;
+ * *rebuilt_out (may be NULL) is 1 when the list was rebuilt.  The DELTA kind of the learned
+ * start uses the reference set by amoeba_guess_set_reference.  Errors of the permanent field
+ * (a quadrupole not traceless, a non-finite multipole, the fixed-point range) are reported in
+ * preference to the solve's; on any error the outputs are unspecified. */
+int amoeba_polarize_configuration(amoeba_ctx* ctx, const double* pos, const double* q, const double* dip,
+                                  const double* quad, const double* mu_guess, int32_t guess_mode,
+                                  double tol_debye, int32_t max_iter, double* e_perm_out, double* mu_out,
+                                  double* e_pol_out, int32_t* iters_out, int32_t* rebuilt_out);
+
 /* ------------------------------------------------------------------------------------------
  * Two induced-dipole sets (AMOEBA's full polarization model; paper "Real space scheme": every
  * AMOEBA polarization interaction carries three scaling factors).  mu_d answers the permanent

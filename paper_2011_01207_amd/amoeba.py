@@ -111,6 +111,9 @@ def lib() -> ctypes.CDLL:
         L.amoeba_dipole_matvec.argtypes = [_P, _P, _P, _P]
         L.amoeba_dipole_field_parts.argtypes = [_P, _P, _P, _P, _P]
         L.amoeba_polarization_gradient.argtypes = [_P, _P, _P, _P, _P, _P, _P]
+        L.amoeba_polarize_configuration.argtypes = [_P, _P, _P, _P, _P, _P, ctypes.c_int32, ctypes.c_double,
+                                                    ctypes.c_int32, _P, _P, ctypes.POINTER(ctypes.c_double),
+                                                    ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
         L.amoeba_polarize.argtypes = [_P, _P, _P, _P, ctypes.c_int32, ctypes.c_double, ctypes.c_int32, _P,
                                       ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32)]
         L.amoeba_get_info.argtypes = [_P, ctypes.POINTER(amoeba_info)]
@@ -295,6 +298,28 @@ class Context:
             _ptr(out, torch.float64, (n, 3), "mu_out"), ctypes.byref(ep), ctypes.byref(it)),
             ok=(AMOEBA_OK, AMOEBA_NOT_CONVERGED))
         return out, ep.value, it.value, st
+
+    def polarize_configuration(self, pos, q, dip, quad, mu_guess=None, guess_mode=None, tol_debye=1e-5,
+                               max_iter=500, out=None, e_perm_out=None):
+        """update_blocklist + perm_field + polarize in one call.  Returns (mu, e_perm, e_pol
+        kcal/mol, iterations, status, rebuilt); e_perm is None unless e_perm_out is given."""
+        n = self.n
+        if isinstance(guess_mode, str):
+            guess_mode = {v: k for k, v in GUESS_NAMES.items()}[guess_mode]
+        if guess_mode is None:
+            guess_mode = AMOEBA_GUESS_ZERO if mu_guess is None else AMOEBA_GUESS_GIVEN
+        out = torch.empty((n, 3), dtype=torch.float64, device=pos.device) if out is None else out
+        ep = ctypes.c_double(0.0)
+        it = ctypes.c_int32(0)
+        rb = ctypes.c_int32(0)
+        st = self._check(lib().amoeba_polarize_configuration(
+            self.h, _ptr(pos, torch.float64, (n, 3), "pos"), _ptr(q, torch.float64, (n,), "q"),
+            _ptr(dip, torch.float64, (n, 3), "dip"), _ptr(quad, torch.float64, (n, 6), "quad"),
+            _ptr(mu_guess, torch.float64, (n, 3), "mu_guess"), int(guess_mode), float(tol_debye), int(max_iter),
+            _ptr(e_perm_out, torch.float64, (n, 3), "e_perm_out"), _ptr(out, torch.float64, (n, 3), "mu_out"),
+            ctypes.byref(ep), ctypes.byref(it), ctypes.byref(rb)),
+            ok=(AMOEBA_OK, AMOEBA_NOT_CONVERGED))
+        return out, e_perm_out, ep.value, it.value, st, bool(rb.value)
 
     def polarization_gradient(self, pos, q, dip, quad, mu, out=None):
         """dE_pol/dr (kcal/mol/A, N x 3 on the device) at the induced dipoles mu."""

@@ -332,7 +332,6 @@ int amoeba_create(const amoeba_params* p, void* hip_stream, amoeba_ctx** out)
             (rc = ctx_alloc(c, (void**)&c->sc, sizeof(PcgScalars))) ||
             (rc = ctx_alloc(c, (void**)&c->red.part, sizeof(double) * part_n)) ||
             (rc = ctx_alloc(c, (void**)&c->flags, sizeof(int) * 256)) ||
-            (rc = ctx_alloc(c, (void**)&c->counter, sizeof(unsigned long long) * 2)) ||
             (rc = ctx_alloc(c, (void**)&c->b_cnt, sizeof(int) * (np + 1))) ||
             (rc = ctx_alloc(c, (void**)&c->b_scan, sizeof(int) * 2 * (np / 1024 + 2))))
             break;
@@ -350,7 +349,9 @@ int amoeba_create(const amoeba_params* p, void* hip_stream, amoeba_ctx** out)
         }
         if (hipHostMalloc((void**)&c->sc_host, sizeof(PcgScalars) * 2, hipHostMallocDefault) != hipSuccess ||
             hipHostGetDevicePointer((void**)&c->sc_host_dev, c->sc_host, 0) != hipSuccess ||
-            hipHostMalloc((void**)&c->flags_host, 64, hipHostMallocDefault) != hipSuccess) {
+            hipHostMalloc((void**)&c->flags_host, 64, hipHostMallocDefault) != hipSuccess ||
+            hipHostMalloc((void**)&c->pairs_host, 64, hipHostMallocDefault) != hipSuccess ||
+            hipHostGetDevicePointer((void**)&c->pairs_host_dev, c->pairs_host, 0) != hipSuccess) {
             rc = set_error(c, AMOEBA_E_NOMEM, "pinned host allocation failed");
             break;
         }
@@ -358,6 +359,7 @@ int amoeba_create(const amoeba_params* p, void* hip_stream, amoeba_ctx** out)
             hipEventCreateWithFlags(&c->ev[1], hipEventDisableTiming) != hipSuccess ||
             hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
             hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&c->ev_pairs, hipEventDisableTiming) != hipSuccess ||
             hipStreamCreateWithFlags(&c->stream2, hipStreamNonBlocking) != hipSuccess ||
             hipStreamCreateWithFlags(&c->gstream, hipStreamNonBlocking) != hipSuccess) {
             rc = set_error(c, AMOEBA_E_DEVICE, "hipEventCreate failed");
@@ -402,6 +404,8 @@ int amoeba_destroy(amoeba_ctx* c)
         rocfft_execution_info_destroy(c->exec_bwd);
     if (c->flags_host)
         hipHostFree(c->flags_host);
+    if (c->pairs_host)
+        hipHostFree(c->pairs_host);
     coef_release(c);
     if (c->g_scal_host)
         hipHostFree(c->g_scal_host);
@@ -412,6 +416,8 @@ int amoeba_destroy(amoeba_ctx* c)
         hipEventDestroy(c->ev_fork);
     if (c->ev_join)
         hipEventDestroy(c->ev_join);
+    if (c->ev_pairs)
+        hipEventDestroy(c->ev_pairs);
     for (auto& e : c->tev)
         hipEventDestroy(e);
     delete c;
@@ -514,9 +520,11 @@ int amoeba_update_blocklist(amoeba_ctx* c, const double* pos, int32_t* rebuilt_o
 // The parts of E_perm shared by the scale sets (multipoles in slot order, the unscaled tiles'
 // sums in ereal, the reciprocal field in erec), leaving the flags unread.
 static int perm_field_parts(amoeba_ctx* c, const double* pos, const double* q, const double* dip,
-                            const double* quad, const char* what)
+                            const double* quad, const char* what, int* flags = nullptr)
 {
-    int rc = begin_config(c, pos, what);
+    // flags: the word the multipole checks go to (the context's flag word, cleared here, when
+    // NULL); a caller that passes its own has prepared the configuration already
+    int rc = flags ? AMOEBA_OK : begin_config(c, pos, what);
     if (rc)
         return rc;
     if (!c->mp_d) {
@@ -528,9 +536,12 @@ static int perm_field_parts(amoeba_ctx* c, const double* pos, const double* q, c
     // The multipole checks (finite, traceless) and the range check of the result are flags
     // written on the device and read once at the end; on an error the fields are unspecified.
     hipStream_t st = c->stream;
-    hipMemsetAsync(c->flags, 0, sizeof(int), st);
+    if (!flags) {
+        flags = c->flags;
+        hipMemsetAsync(flags, 0, sizeof(int), st);
+    }
     hipLaunchKernelGGL(k_gather_mpole, dim3(nblk(c->npad, 256)), dim3(256), 0, st, c->npad, c->perm, q, dip, quad,
-                       c->mp_d, c->mixed ? c->mp_f : nullptr, c->flags);
+                       c->mp_d, c->mixed ? c->mp_f : nullptr, flags);
     if (pme_use_planes(c) && !c->timing) {
         // the multipole tiles (VALU bound) on the second stream beside the reciprocal passes
         hipEventRecord(c->ev_fork, st);
@@ -560,11 +571,8 @@ static void perm_field_out(amoeba_ctx* c, const double* scales, double* out)
     launch_scatter(c, c->v_q, out);
 }
 
-static int perm_field_status(amoeba_ctx* c, const char* what)
+static int perm_flags_status(amoeba_ctx* c, int f, const char* what)
 {
-    int f = 0, rc;
-    if ((rc = read_flags(c, &f)))
-        return rc;
     if (f & kFlagBadCsr)
         return set_error(c, AMOEBA_E_INVALID, std::string(what) + ": quadrupole not traceless (|tr| > 1e-10)");
     if (f & kFlagNonFinite)
@@ -573,6 +581,14 @@ static int perm_field_status(amoeba_ctx* c, const char* what)
         return set_error(c, AMOEBA_E_OVERFLOW,
                          std::string(what) + ": field outside the exact fixed-point range (|E| >= 8192 e/A^2)");
     return AMOEBA_OK;
+}
+
+static int perm_field_status(amoeba_ctx* c, const char* what)
+{
+    int f = 0, rc;
+    if ((rc = read_flags(c, &f)))
+        return rc;
+    return perm_flags_status(c, f, what);
 }
 
 int amoeba_perm_field(amoeba_ctx* c, const double* pos, const double* q, const double* dip, const double* quad,
@@ -693,6 +709,27 @@ int amoeba_dipole_field_parts(amoeba_ctx* c, const double* pos, const double* mu
     return hip_check(c, hipStreamSynchronize(c->stream), "amoeba_dipole_field_parts");
 }
 
+// Argument checks of the solve entry points.
+static int solve_args(amoeba_ctx* c, const char* who, const double* mu_guess, int32_t guess_mode, double tol_debye,
+                      int32_t max_iter)
+{
+    if (!(tol_debye > 0.0) || !std::isfinite(tol_debye))
+        return set_error(c, AMOEBA_E_INVALID, std::string(who) + ": tol_debye must be positive");
+    if (max_iter < 0)
+        return set_error(c, AMOEBA_E_INVALID, std::string(who) + ": max_iter must be >= 0");
+    if (guess_mode < AMOEBA_GUESS_ZERO || guess_mode > AMOEBA_GUESS_BEST)
+        return set_error(c, AMOEBA_E_INVALID, std::string(who) + ": unknown guess_mode");
+    if (guess_mode == AMOEBA_GUESS_GIVEN && !mu_guess)
+        return set_error(c, AMOEBA_E_INVALID, std::string(who) + ": AMOEBA_GUESS_GIVEN needs mu_guess");
+    if ((guess_mode == AMOEBA_GUESS_LEARNED || guess_mode == AMOEBA_GUESS_BEST) && !c->guess_loaded)
+        return set_error(c, AMOEBA_E_STATE,
+                         std::string(who) + ": no learned guess model loaded (amoeba_guess_set_model)");
+    return AMOEBA_OK;
+}
+
+static int polarize_body(amoeba_ctx* c, const double* mu_guess, int32_t guess_mode, double tol_debye,
+                         int32_t max_iter, double* mu_out, double* e_pol_out, int32_t* iters_out);
+
 int amoeba_polarize(amoeba_ctx* c, const double* pos, const double* e_perm, const double* mu_guess,
                     int32_t guess_mode, double tol_debye, int32_t max_iter, double* mu_out, double* e_pol_out,
                     int32_t* iters_out)
@@ -702,24 +739,23 @@ int amoeba_polarize(amoeba_ctx* c, const double* pos, const double* e_perm, cons
     c->err.clear();
     if (!e_perm || !mu_out)
         return set_error(c, AMOEBA_E_INVALID, "amoeba_polarize: NULL e_perm or mu_out");
-    if (!(tol_debye > 0.0) || !std::isfinite(tol_debye))
-        return set_error(c, AMOEBA_E_INVALID, "amoeba_polarize: tol_debye must be positive");
-    if (max_iter < 0)
-        return set_error(c, AMOEBA_E_INVALID, "amoeba_polarize: max_iter must be >= 0");
-    if (guess_mode < AMOEBA_GUESS_ZERO || guess_mode > AMOEBA_GUESS_BEST)
-        return set_error(c, AMOEBA_E_INVALID, "amoeba_polarize: unknown guess_mode");
-    if (guess_mode == AMOEBA_GUESS_GIVEN && !mu_guess)
-        return set_error(c, AMOEBA_E_INVALID, "amoeba_polarize: AMOEBA_GUESS_GIVEN needs mu_guess");
-    if ((guess_mode == AMOEBA_GUESS_LEARNED || guess_mode == AMOEBA_GUESS_BEST) && !c->guess_loaded)
-        return set_error(c, AMOEBA_E_STATE,
-                         "amoeba_polarize: no learned guess model loaded (amoeba_guess_set_model)");
-    int rc = begin_config(c, pos, "amoeba_polarize");
+    int rc = solve_args(c, "amoeba_polarize", mu_guess, guess_mode, tol_debye, max_iter);
     if (rc)
+        return rc;
+    if ((rc = begin_config(c, pos, "amoeba_polarize")))
         return rc;
     // the inputs are checked for NaN/Inf by the gathers; the flag is read with the solve's
     // first host wait (AMOEBA_E_NUMERIC, outputs unspecified)
     hipMemsetAsync(c->flags, 0, sizeof(int), c->stream);
     launch_gather_vec_checked(c, e_perm, c->v_e);
+    return polarize_body(c, mu_guess, guess_mode, tol_debye, max_iter, mu_out, e_pol_out, iters_out);
+}
+
+// The solve from the slot-order right side in v_e (the current configuration prepared).
+static int polarize_body(amoeba_ctx* c, const double* mu_guess, int32_t guess_mode, double tol_debye,
+                         int32_t max_iter, double* mu_out, double* e_pol_out, int32_t* iters_out)
+{
+    int rc;
     const bool given = mu_guess != nullptr && (guess_mode == AMOEBA_GUESS_GIVEN || guess_mode == AMOEBA_GUESS_BEST);
     c->last_guess_rms[0] = c->last_guess_rms[1] = 0.0;
     double ep = 0.0;
@@ -780,6 +816,56 @@ int amoeba_polarize(amoeba_ctx* c, const double* pos, const double* e_perm, cons
         *iters_out = c->last_iters;
     if (st == AMOEBA_NOT_CONVERGED)
         set_error(c, AMOEBA_NOT_CONVERGED, "PCG did not reach the tolerance within max_iter");
+    return st;
+}
+
+int amoeba_polarize_configuration(amoeba_ctx* c, const double* pos, const double* q, const double* dip,
+                                  const double* quad, const double* mu_guess, int32_t guess_mode, double tol_debye,
+                                  int32_t max_iter, double* e_perm_out, double* mu_out, double* e_pol_out,
+                                  int32_t* iters_out, int32_t* rebuilt_out)
+{
+    static const char* who = "amoeba_polarize_configuration";
+    if (!c)
+        return AMOEBA_E_INVALID;
+    c->err.clear();
+    if (rebuilt_out)
+        *rebuilt_out = 0;
+    if (!pos || !q || !dip || !quad || !mu_out)
+        return set_error(c, AMOEBA_E_INVALID, std::string(who) + ": NULL pos, q, dip, quad or mu_out");
+    int rc = solve_args(c, who, mu_guess, guess_mode, tol_debye, max_iter);
+    if (rc)
+        return rc;
+    if (!c->atoms_set)
+        return set_error(c, AMOEBA_E_STATE, std::string(who) + ": amoeba_set_atoms has not been called");
+    // the list kept valid for pos (one host wait for the displacement test), as
+    // amoeba_update_blocklist
+    int32_t rebuilt = 0;
+    if ((rc = amoeba_update_blocklist(c, pos, &rebuilt)))
+        return rc;
+    if (rebuilt_out)
+        *rebuilt_out = rebuilt;
+    // E_perm straight into the slot-order right side; its checks go to the second flag word,
+    // read once at the end, the solve's to the first
+    hipMemsetAsync(c->flags, 0, 2 * sizeof(int), c->stream);
+    int* pflags = c->flags + 1;
+    if ((rc = perm_field_parts(c, pos, q, dip, quad, who, pflags)))
+        return rc;
+    launch_perm_assemble(c, c->v_e, c->sc_s);
+    if (c->mixed)
+        hipLaunchKernelGGL(k_check_overflow, dim3(nblk(3 * (size_t)c->npad, 256)), dim3(256), 0, c->stream,
+                           3 * (size_t)c->npad, c->v_e, kFixRange, pflags);
+    if (e_perm_out)
+        launch_scatter(c, c->v_e, e_perm_out);
+    const int st = polarize_body(c, mu_guess, guess_mode, tol_debye, max_iter, mu_out, e_pol_out, iters_out);
+    // an error of the permanent field explains any of the solve's
+    hipMemcpyAsync(c->flags_host + 1, pflags, sizeof(int), hipMemcpyDeviceToHost, c->stream);
+    if ((rc = hip_check(c, hipStreamSynchronize(c->stream), who)))
+        return rc;
+    const int f = c->flags_host[1];
+    if (f) {
+        c->err.clear();
+        return perm_flags_status(c, f, who);
+    }
     return st;
 }
 
@@ -939,15 +1025,13 @@ int amoeba_get_info(const amoeba_ctx* cc, amoeba_info* out)
 {
     if (!cc || !out)
         return AMOEBA_E_INVALID;
-    amoeba_ctx* c = const_cast<amoeba_ctx*>(cc);  // the pair count of the last refresh is read lazily
+    amoeba_ctx* c = const_cast<amoeba_ctx*>(cc);
     if (c->pairs_pending) {
-        unsigned long long np = 0;
-        launch_sum_pairs(c);
-        hipMemcpyAsync(c->flags_host + 2, c->counter, sizeof(unsigned long long), hipMemcpyDeviceToHost, c->stream);
-        if (hipStreamSynchronize(c->stream) != hipSuccess)
+        // the pair count of the last refresh, written to pinned memory by the refresh's last
+        // kernel (complete already when a call has waited for the stream since)
+        if (hipEventSynchronize(c->ev_pairs) != hipSuccess)
             return AMOEBA_E_DEVICE;
-        np = *(unsigned long long*)(c->flags_host + 2);
-        c->n_pairs = (int64_t)np;
+        c->n_pairs = (int64_t)*c->pairs_host;
         c->pairs_pending = false;
     }
     out->n_atoms = c->n;

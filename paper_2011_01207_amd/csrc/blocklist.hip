@@ -940,7 +940,7 @@ __global__ __launch_bounds__(256) void k_tile_refresh(int ntiles, const int* __r
 }
 
 __global__ __launch_bounds__(256) void k_sum_pairs(int n, const unsigned long long* __restrict__ part,
-                                                   unsigned long long* __restrict__ total)
+                                                   unsigned long long* __restrict__ total)  // pinned host word
 {
     __shared__ unsigned long long sh[256];
     unsigned long long s = 0;
@@ -1033,10 +1033,12 @@ void coef_scan_rows(amoeba_ctx* c)
     }
 }
 
-// Sum of the mask refresh's per-workgroup pair counts into counter[0] (read by amoeba_get_info).
+// Sum of the mask refresh's per-workgroup pair counts, written to pinned host memory (read by
+// amoeba_get_info after ev_pairs).
 void launch_sum_pairs(amoeba_ctx* c)
 {
-    hipLaunchKernelGGL(k_sum_pairs, dim3(1), dim3(256), 0, c->stream, c->pair_nwg, c->pair_part, c->counter);
+    hipLaunchKernelGGL(k_sum_pairs, dim3(1), dim3(256), 0, c->stream, c->pair_nwg, c->pair_part, c->pairs_host_dev);
+    hipEventRecord(c->ev_pairs, c->stream);
 }
 
 static int refresh_tiles(amoeba_ctx* c)
@@ -1054,7 +1056,8 @@ static int refresh_tiles(amoeba_ctx* c)
                        c->tile_mask,
                        c->jrel_d, c->jrel_f, c->tile_np, c->tile_rows, c->tile_walk, c->pair_part);
     c->pair_nwg = nwg;
-    c->pairs_pending = true;  // summed (k_sum_pairs) when amoeba_get_info asks for the count
+    launch_sum_pairs(c);
+    c->pairs_pending = true;  // read by amoeba_get_info
     coef_invalidate(c);
     c->coef_rows_ok = false;
     if (coef_store_on(c))

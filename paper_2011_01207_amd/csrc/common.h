@@ -260,18 +260,20 @@ struct amoeba_ctx {
     amoeba::PcgScalars* sc = nullptr;      // device scalars
     amoeba::PcgScalars* sc_host = nullptr; // pinned mirror [2] (one per in-flight PCG iteration)
     amoeba::PcgScalars* sc_host_dev = nullptr; // its device-side address
+    unsigned long long* pairs_host = nullptr;     // pinned: in-cutoff pair count of the last refresh
+    unsigned long long* pairs_host_dev = nullptr; // its device-side address
     amoeba::RedScratch red{};
     int* flags = nullptr;                  // device error flags and list-build status words [256]
     int* flags_host = nullptr;             // pinned
-    unsigned long long* counter = nullptr; // device counters (pairs)
     unsigned long long* pair_part = nullptr; // per-workgroup pair counts of the mask refresh
-    bool pairs_pending = false;            // pair_part holds a pair count not yet read to n_pairs
+    bool pairs_pending = false;            // pairs_host receives a pair count (ev_pairs) not yet in n_pairs
     int pair_nwg = 0;                      // pair_part entries of the last mask refresh
     hipEvent_t ev[2] = {nullptr, nullptr};
     // the real-space tiles of a PCG product run on a second stream (default priority), beside
     // the reciprocal passes on the context stream: forked and joined with events
     hipStream_t stream2 = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    hipEvent_t ev_pairs = nullptr;         // recorded after the pair count of a refresh is written
     // one PCG iteration (product on both streams, update, direction) as a HIP graph: captured on
     // gstream, replayed on the context stream; recaptured when a launch parameter it bakes in
     // changes (key).  Off unless the caller asks: measured slower than the direct launches.
@@ -354,7 +356,7 @@ struct StageTimer {
 // exclusive, out[n] = total; total_copy: a second place for the total
 int device_scan(amoeba_ctx* c, int n, const int* in, int* out, int* total_copy = nullptr);
 void coef_scan_rows(amoeba_ctx* c);       // rows of the coefficient store for the current masks
-void launch_sum_pairs(amoeba_ctx* c);     // pair count of the last mask refresh into counter[0]
+void launch_sum_pairs(amoeba_ctx* c);     // pair count of the last mask refresh into pairs_host
 int build_blocklist(amoeba_ctx* c, const double* pos);
 int prepare_config(amoeba_ctx* c, const double* pos);
 

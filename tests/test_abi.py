@@ -73,6 +73,8 @@ def test_calls_on_null_context_are_rejected():
     L = amoeba.lib()
     assert L.amoeba_build_blocklist(None, None) == amoeba.AMOEBA_E_INVALID
     assert L.amoeba_update_blocklist(None, None, None) == amoeba.AMOEBA_E_INVALID
+    assert L.amoeba_polarize_configuration(None, None, None, None, None, None, 0, 1e-5, 10, None, None, None, None,
+                                           None) == amoeba.AMOEBA_E_INVALID
     assert L.amoeba_dipole_matvec(None, None, None, None) == amoeba.AMOEBA_E_INVALID
     assert L.amoeba_last_error(None) == b"NULL context"
 
