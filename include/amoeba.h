@@ -211,7 +211,8 @@ int amoeba_dipole_field_parts(amoeba_ctx* ctx, const double* pos, const double* 
  * Outputs: mu_out[N][3] (device, e*A); *e_pol_out = -1/2 C sum_i mu_i . e_perm_i (host,
  * kcal/mol); *iters_out = matrix-vector products after the initial residual (host).  In mixed
  * precision the true residual e_perm - A mu is recomputed once the recursive one passes the
- * tolerance, and iteration continues if it does not. */
+ * tolerance (iteration continues if it does not), unless the recursion cannot have drifted by
+ * a tenth of the tolerance (amoeba_set_residual_check). */
 int amoeba_polarize(amoeba_ctx* ctx, const double* pos, const double* e_perm,
                     const double* mu_guess, int32_t guess_mode, double tol_debye, int32_t max_iter,
                     double* mu_out, double* e_pol_out, int32_t* iters_out);
@@ -429,6 +430,20 @@ int amoeba_set_pme_path(amoeba_ctx* ctx, int32_t path);
  * context stream.  A capture that fails turns graphs off for the context (the solve goes on with
  * direct launches). */
 int amoeba_set_graphs(amoeba_ctx* ctx, int32_t enable);
+
+/* When a mixed-precision solve recomputes its true residual after the recursive one has passed
+ * the tolerance.  The recursion drifts from e - A mu by the rounding of the products; with their
+ * relative error below eps = 1e-5 (above three times the bar the products are tested to against
+ * the FP64 oracle) the drift in z = alpha r is at most 2 eps sum_k rms(z_k) over the iterates.
+ *   AMOEBA_RESIDUAL_CHECK_AUTO    (default) recompute only when that bound exceeds a tenth of
+ *                                 the tolerance (a start far from the solution, e.g. zero)
+ *   AMOEBA_RESIDUAL_CHECK_ALWAYS  recompute after every mixed-precision solve
+ * A check that passes leaves the outputs as they were.  Unknown mode: AMOEBA_E_INVALID. */
+typedef enum amoeba_residual_check {
+    AMOEBA_RESIDUAL_CHECK_AUTO = 0,
+    AMOEBA_RESIDUAL_CHECK_ALWAYS = 1
+} amoeba_residual_check;
+int amoeba_set_residual_check(amoeba_ctx* ctx, int32_t mode);
 
 /* Select how the real-space dipole product gets its pair coefficients (amoeba_pair_store) for
  * later products; an unknown value: AMOEBA_E_INVALID.  The default is AMOEBA_PAIRS_AUTO. */

@@ -136,6 +136,7 @@ def lib() -> ctypes.CDLL:
         L.amoeba_guess_load.argtypes = [_P, _P, ctypes.c_int64]
         L.amoeba_set_pme_path.argtypes = [_P, ctypes.c_int32]
         L.amoeba_set_pair_store.argtypes = [_P, ctypes.c_int32]
+        L.amoeba_set_residual_check.argtypes = [_P, ctypes.c_int32]
         L.amoeba_set_graphs.argtypes = [_P, ctypes.c_int32]
         L.amoeba_set_timing.argtypes = [_P, ctypes.c_int]
         L.amoeba_get_timing.argtypes = [_P, ctypes.POINTER(amoeba_timing)]
@@ -350,6 +351,11 @@ class Context:
         return {"ms": {STAGE_NAMES[i]: t.ms[i] for i in range(N_STAGES)},
                 "launches": {STAGE_NAMES[i]: int(t.launches[i]) for i in range(N_STAGES)},
                 "matvecs": int(t.matvecs)}
+
+    def set_residual_check(self, mode):
+        """mode: "auto" (the default) or "always"."""
+        m = {"auto": 0, "always": 1}[mode] if isinstance(mode, str) else int(mode)
+        return self._check(lib().amoeba_set_residual_check(self.h, m))
 
     def set_graphs(self, enable):
         """Run PCG iterations as one captured HIP graph each (True) or as individual kernel

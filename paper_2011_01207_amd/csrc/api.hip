@@ -1009,6 +1009,16 @@ int amoeba_set_graphs(amoeba_ctx* c, int32_t enable)
     return AMOEBA_OK;
 }
 
+int amoeba_set_residual_check(amoeba_ctx* c, int32_t mode)
+{
+    if (!c)
+        return AMOEBA_E_INVALID;
+    if (mode != AMOEBA_RESIDUAL_CHECK_AUTO && mode != AMOEBA_RESIDUAL_CHECK_ALWAYS)
+        return set_error(c, AMOEBA_E_INVALID, "amoeba_set_residual_check: unknown mode");
+    c->residual_check = mode;
+    return AMOEBA_OK;
+}
+
 int amoeba_set_pair_store(amoeba_ctx* c, int32_t mode)
 {
     if (!c)

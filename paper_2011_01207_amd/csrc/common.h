@@ -111,6 +111,8 @@ struct PcgScalars {
     double tol;       // tolerance in Debye
     double epol_acc;  // sum mu.E
     double beta;      // rz_new / rz of the last update
+    double rms_sum;   // sum of rms(z) over the iterates since the (re)start: bounds the drift of
+                      // the recursive residual (mixed precision)
     int32_t done;     // converged (or broken down): later kernels of the loop skip
     int32_t iters;    // iterations completed
     int32_t status;   // 0 running, 1 converged, 2 breakdown
@@ -278,6 +280,7 @@ struct amoeba_ctx {
     // gstream, replayed on the context stream; recaptured when a launch parameter it bakes in
     // changes (key).  Off unless the caller asks: measured slower than the direct launches.
     bool use_graphs = false;
+    int residual_check = AMOEBA_RESIDUAL_CHECK_AUTO;  // amoeba_residual_check
     hipStream_t gstream = nullptr;
     hipGraph_t it_graph = nullptr;
     hipGraphExec_t it_exec = nullptr;

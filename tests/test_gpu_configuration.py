@@ -58,12 +58,19 @@ def test_matches_the_separate_calls_bitwise(mode):
         assert torch.equal(mu_a, mu_b) and epa == epb and ita == itb, k
         assert a.info()["last_guess"] == b.info()["last_guess"]
         prev = (mu_b.clone(), eb.clone())
-    # a step beyond buffer/2 is rebuilt by both
+    # a step beyond buffer/2: both rebuild (the single call after computing the configuration
+    # once on the stale list) and agree bitwise
     far = frames[-1].clone()
     far[5, 0] += 0.6
     assert a.update_blocklist(far)
-    _, _, _, _, _, rb = b.polarize_configuration(far, t["q"], t["dip"], t["quad"], tol_debye=1e-6)
-    assert rb
+    ea = a.perm_field(far, t["q"], t["dip"], t["quad"])
+    mu_a, epa, ita, _ = a.polarize(far, ea, tol_debye=1e-6)
+    eb = torch.empty_like(ea)
+    mu_b, _, epb, itb, stb, rb = b.polarize_configuration(far, t["q"], t["dip"], t["quad"], tol_debye=1e-6,
+                                                           e_perm_out=eb)
+    assert rb and stb == amoeba.AMOEBA_OK
+    assert torch.equal(ea, eb) and torch.equal(mu_a, mu_b) and epa == epb and ita == itb
+    assert a.info()["n_pairs"] == b.info()["n_pairs"]
     a.close()
     b.close()
 
@@ -104,6 +111,11 @@ def test_errors():
     with pytest.raises(amoeba.AmoebaError) as e:
         ctx.polarize_configuration(t["pos"], nanq, t["dip"], t["quad"])
     assert e.value.status == amoeba.AMOEBA_E_NUMERIC
+    nanpos = t["pos"].clone()
+    nanpos[11, 1] = float("nan")
+    with pytest.raises(amoeba.AmoebaError) as e:
+        ctx.polarize_configuration(nanpos, t["q"], t["dip"], t["quad"])
+    assert e.value.status == amoeba.AMOEBA_E_NUMERIC and "position" in str(e.value)
     # the context still works
     mu, _, _, _, st, _ = ctx.polarize_configuration(t["pos"], t["q"], t["dip"], t["quad"], tol_debye=1e-6)
     assert st == amoeba.AMOEBA_OK and torch.isfinite(mu).all()
