@@ -94,7 +94,18 @@ def test_fp64_against_the_oracle():
 
 def test_errors():
     s = synth.water648()
+    bare = amoeba.Context(s.n, s.box, cutoff=s.cutoff, ewald_alpha=s.ewald_alpha, grid=s.grid, precision="mixed")
+    tp = torch.tensor(s.pos, device=DEV)
+    with pytest.raises(amoeba.AmoebaError) as e:                # no amoeba_set_atoms yet
+        bare.polarize_configuration(tp, tp[:, 0].contiguous(), tp, torch.zeros((s.n, 6), dtype=torch.float64,
+                                                                               device=DEV))
+    assert e.value.status == amoeba.AMOEBA_E_STATE
+    bare.close()
     ctx, t = amoeba.context_for(s, precision="mixed", device=DEV)
+    # an iteration budget too small: NOT_CONVERGED with the last iterate
+    mu, _, _, it, st, _ = ctx.polarize_configuration(t["pos"], t["q"], t["dip"], t["quad"], tol_debye=1e-9,
+                                                     max_iter=2)
+    assert st == amoeba.AMOEBA_NOT_CONVERGED and it == 2 and torch.isfinite(mu).all()
     with pytest.raises(amoeba.AmoebaError) as e:
         ctx.polarize_configuration(t["pos"], t["q"], t["dip"], t["quad"], guess_mode="learned")
     assert e.value.status == amoeba.AMOEBA_E_STATE            # no model loaded
