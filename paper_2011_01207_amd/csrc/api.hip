@@ -312,6 +312,7 @@ int amoeba_create(const amoeba_params* p, void* hip_stream, amoeba_ctx** out)
             (rc = ctx_alloc(c, (void**)&c->slot, sizeof(int) * c->n)) ||
             (rc = ctx_alloc(c, (void**)&c->par_d, sizeof(double4) * np)) ||
             (rc = ctx_alloc(c, (void**)&c->alpha_s, sizeof(double) * np)) ||
+            (rc = ctx_alloc(c, (void**)&c->alpha_inv_s, sizeof(double) * np)) ||
             (rc = ctx_alloc(c, (void**)&c->par_f, sizeof(float4) * np)) ||
             (rc = ctx_alloc(c, (void**)&c->sc_ptr, sizeof(int) * (np + 1))) ||
             (rc = ctx_alloc(c, (void**)&c->sc_ptr_in, sizeof(int) * (c->n + 1))) ||

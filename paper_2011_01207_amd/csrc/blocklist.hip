@@ -168,7 +168,8 @@ __global__ void k_perm(int n, int npad, const int* __restrict__ sorted_atoms, in
 // Per-slot parameters and the slot's count of scaled pairs (the CSR in slot order).
 __global__ void k_params(int npad, const int* __restrict__ perm, const double* __restrict__ alpha,
                          const double* __restrict__ thole, double4* __restrict__ pd, float4* __restrict__ pf,
-                         double* __restrict__ as, const int* __restrict__ ptr_in, int* __restrict__ cnt)
+                         double* __restrict__ as, double* __restrict__ ais, const int* __restrict__ ptr_in,
+                         int* __restrict__ cnt)
 {
     int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= npad)
@@ -180,6 +181,7 @@ __global__ void k_params(int npad, const int* __restrict__ perm, const double* _
     double dinv = pow(al, -1.0 / 6.0);
     pd[s] = make_double4(al, 1.0 / al, dinv, th);
     as[s] = al;
+    ais[s] = 1.0 / al;
     pf[s] = make_float4((float)al, (float)(1.0 / al), (float)dinv, (float)th);
 }
 
@@ -997,7 +999,7 @@ int sort_params(amoeba_ctx* c)
     // parameters and the scaled-pair CSR in slot order
     int* cnt = c->b_cnt;
     hipLaunchKernelGGL(k_params, dim3(nblk(c->npad, 256)), dim3(256), 0, st, c->npad, c->perm, c->alpha_in,
-                       c->thole_in, c->par_d, c->par_f, c->alpha_s, c->sc_ptr_in, cnt);
+                       c->thole_in, c->par_d, c->par_f, c->alpha_s, c->alpha_inv_s, c->sc_ptr_in, cnt);
     int rcs = device_scan(c, c->npad, cnt, c->sc_ptr);
     if (rcs)
         return rcs;

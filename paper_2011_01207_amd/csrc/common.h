@@ -161,6 +161,7 @@ struct amoeba_ctx {
     int32_t* slot = nullptr;       // [n] original atom -> slot
     double4* par_d = nullptr;      // [npad] (alpha, 1/alpha, alpha^-1/6, thole)
     double* alpha_s = nullptr;     // [npad] alpha (the PCG preconditioner; 1 on phantom slots)
+    double* alpha_inv_s = nullptr; // [npad] 1/alpha (the operator's diagonal)
     float4* par_f = nullptr;       // same in FP32
     int32_t* sc_ptr = nullptr;     // [npad+1] CSR of scaled pairs in slot order
     int32_t* sc_j = nullptr;       // [n_scaled] partner slot

@@ -829,7 +829,7 @@ __global__ __launch_bounds__(NT) void k_pme_z_gather(PlaneGeom g, PlaneDim dz,
 template <typename R, int MODE>
 __global__ __launch_bounds__(256) void k_plane_combine(int npad, double3 kl, const int* __restrict__ perm,
                                                        const typename PlT<R>::R4* __restrict__ part,
-                                                       const double4* __restrict__ par,
+                                                       const double* __restrict__ alpha_inv,
                                                        const double* __restrict__ p, double self,
                                                        const double* __restrict__ eipart,
                                                        const typename PlT<R>::R4* __restrict__ jbuf,
@@ -863,7 +863,7 @@ __global__ __launch_bounds__(256) void k_plane_combine(int npad, double3 kl, con
             for (int a = 0; a < 3; ++a)
                 out[3 * (size_t)s + a] = e[a];
         } else if (perm[s] >= 0 && MODE == 2) {
-            const double ainv = par[s].y;
+            const double ainv = alpha_inv[s];
             for (int a = 0; a < 3; ++a) {
                 const size_t i = 3 * (size_t)s + a;
                 const double pa = p[i];
@@ -898,7 +898,7 @@ __global__ __launch_bounds__(256) void k_plane_combine(int npad, double3 kl, con
             }
             for (int a = 0; a < 3; ++a)
                 er[a] = J::finish(er[a]);
-            const double ainv = par[s].y;
+            const double ainv = alpha_inv[s];
             for (int a = 0; a < 3; ++a) {
                 const size_t i = 3 * (size_t)s + a;
                 const double pa = p[i];
@@ -1191,12 +1191,12 @@ void plane_gather(amoeba_ctx* c, double* out)
     double3 kl = make_double3(c->K[0] / c->prm.box[0], c->K[1] / c->prm.box[1], c->K[2] / c->prm.box[2]);
     if (c->mixed)
         hipLaunchKernelGGL((k_plane_combine<float, 0>), dim3(nblk(c->npad, 256)), dim3(256), 0, c->stream, c->npad,
-                           kl, c->perm, (const float4*)c->rec_part, c->par_d, (const double*)nullptr, 0.0,
+                           kl, c->perm, (const float4*)c->rec_part, c->alpha_inv_s, (const double*)nullptr, 0.0,
                            (const double*)nullptr, (const float4*)nullptr, (const int*)nullptr, (const int*)nullptr,
                            (const double*)nullptr, out, c->sc, (double*)nullptr, 0, 0);
     else
         hipLaunchKernelGGL((k_plane_combine<double, 0>), dim3(nblk(c->npad, 256)), dim3(256), 0, c->stream,
-                           c->npad, kl, c->perm, (const double4*)c->rec_part, c->par_d, (const double*)nullptr, 0.0,
+                           c->npad, kl, c->perm, (const double4*)c->rec_part, c->alpha_inv_s, (const double*)nullptr, 0.0,
                            (const double*)nullptr, (const double4*)nullptr, (const int*)nullptr,
                            (const int*)nullptr, (const double*)nullptr, out, c->sc, (double*)nullptr, 0, 0);
 }
@@ -1211,12 +1211,12 @@ int plane_combine(amoeba_ctx* c, bool use_done, bool dot_pq, bool reduced)
     if (c->mixed) {
         auto k = reduced ? k_plane_combine<float, 2> : k_plane_combine<float, 1>;
         hipLaunchKernelGGL(k, dim3(nwg), dim3(256), 0, c->stream, c->npad, kl, c->perm, (const float4*)c->rec_part,
-                           c->par_d, c->v_p, self, c->eipart, (const float4*)c->jbuf, c->rev_ptr, c->rev_idx,
+                           c->alpha_inv_s, c->v_p, self, c->eipart, (const float4*)c->jbuf, c->rev_ptr, c->rev_idx,
                            c->ereal, c->v_q, c->sc, c->red.part, (int)use_done, (int)dot_pq);
     } else {
         auto k = reduced ? k_plane_combine<double, 2> : k_plane_combine<double, 1>;
         hipLaunchKernelGGL(k, dim3(nwg), dim3(256), 0, c->stream, c->npad, kl, c->perm, (const double4*)c->rec_part,
-                           c->par_d, c->v_p, self, c->eipart, (const double4*)c->jbuf, c->rev_ptr, c->rev_idx,
+                           c->alpha_inv_s, c->v_p, self, c->eipart, (const double4*)c->jbuf, c->rev_ptr, c->rev_idx,
                            c->ereal, c->v_q, c->sc, c->red.part, (int)use_done, (int)dot_pq);
     }
     return nwg;
