@@ -29,6 +29,7 @@
 #include <rocprim/device/device_radix_sort.hpp>
 
 #include "common.h"
+#include <type_traits>
 
 namespace amoeba {
 
@@ -815,10 +816,23 @@ __global__ void k_rev_fill(int ntiles, const int* __restrict__ tile_blk, const i
 }
 
 
+// lane l of (lo, hi) = the two halves of x (x and l uniform: scalar registers; the lane select
+// goes through m0, which the one scalar operand read of the instruction leaves free)
+__device__ __forceinline__ void write_lane2(unsigned& lo, unsigned& hi, unsigned long long x, int l)
+{
+    asm("s_mov_b32 m0, %4\n\tv_writelane_b32 %0, %2, m0\n\tv_writelane_b32 %1, %3, m0"
+        : "+v"(lo), "+v"(hi)
+        : "s"((unsigned)x), "s"((unsigned)(x >> 32)), "s"(l)
+        : "m0");
+}
+
 // Per configuration: in-cutoff bitmasks (strict r < rc, decided as in FP64) and j positions
 // relative to the i-block origin.  The diagonal tile keeps only k > i.  Each pair is first
 // classified from FP32 offsets; only pairs within a relative 1e-5 of rc^2 (far above the FP32
 // error of the offsets) are decided by the FP64 distance, so every bit equals the FP64 test.
+// Lane k of a wave holds j-atom k of its tile and the wave walks the 64 rows: row i's mask is
+// the wave's vote on its 64 pairs, written into lane i (two lane writes per row instead of a
+// per-pair shift and or).
 // MI: minimum image per pair offset; without it the block-relative offsets are used as they are
 // (valid when the list build proved that no tile offset can reach half the box, as for the
 // pair kernels).
@@ -836,63 +850,83 @@ __global__ __launch_bounds__(256) void k_tile_refresh(int ntiles, const int* __r
                                                       uint16_t* __restrict__ walk,
                                                       unsigned long long* __restrict__ pair_part)
 {
-    __shared__ double4 s_jd[4][kBlock];
-    __shared__ float4 s_jf[4][kBlock];
+    __shared__ double4 s_id[4][kBlock];
+    __shared__ float4 s_if[4][kBlock];
     __shared__ unsigned long long s_cnt[4];
     __shared__ unsigned long long s_m[4][kBlock];
     __shared__ int s_off[4][kBlock];
-    int gt = blockIdx.x * blockDim.x + threadIdx.x;
-    int t = gt >> 6, lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    // one tile per wave: its index and everything derived from it are wave-uniform
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int t = blockIdx.x * 4 + w;
     bool act = t < ntiles;
     int I = act ? tile_blk[t] : 0;
     int si = I * kBlock + lane;
     bool ivalid = act && perm[si] >= 0;
     double4 pi = pos_s[si];
-    float4 oi = off_f[si];
     int sj = act ? tile_j[(size_t)t * kBlock + lane] : -1;
     double4 pj = sj >= 0 ? pos_s[sj] : pi;
     bool jvalid = sj >= 0 && perm[sj] >= 0;
     double4 o = org[I];
     double jx = mimg_fp64(pj.x - o.x, box.x, binv.x), jy = mimg_fp64(pj.y - o.y, box.y, binv.y),
            jz = mimg_fp64(pj.z - o.z, box.z, binv.z);
-    s_jd[w][lane] = make_double4(pj.x, pj.y, pj.z, 0.0);
-    s_jf[w][lane] = make_float4((float)jx, (float)jy, (float)jz, jvalid ? 1.0f : 0.0f);
+    // absent atoms (no i-atom, no j-atom, phantom slots) take infinite offsets: every FP32
+    // distance test involving one is false (an infinite or NaN r^2), with no per-row masks
+    const float inf = __builtin_inff();
+    s_id[w][lane] = make_double4(pi.x, pi.y, pi.z, 0.0);
+    s_if[w][lane] = ivalid ? off_f[si] : make_float4(inf, inf, inf, 0.0f);
     __syncthreads();
     unsigned long long m = 0;
-    if (act) {
+    if (act) {  // uniform: one tile per wave
         // the pair kernels of the context's precision read one of the two
         const double wj = sj >= 0 ? par[sj].z : 0.0;  // the j atom's polarizability factor
         if (jrel_d)
             jrel_d[(size_t)t * kBlock + lane] = make_double4(jx, jy, jz, wj);
         if (jrel_f)
             jrel_f[(size_t)t * kBlock + lane] = make_float4((float)jx, (float)jy, (float)jz, (float)wj);
-        bool diag = tile_j[(size_t)t * kBlock] == I * kBlock;
         const float lo2 = (float)(rc2 * (1.0 - 1e-5)), hi2 = (float)(rc2 * (1.0 + 1e-5));
         const float Lx = (float)box.x, Ly = (float)box.y, Lz = (float)box.z;
         const float Lix = (float)binv.x, Liy = (float)binv.y, Liz = (float)binv.z;
-        if (ivalid) {
-            const int k0 = diag ? lane + 1 : 0;
+        const float qx = jvalid ? (float)jx : inf, qy = jvalid ? (float)jy : inf, qz = jvalid ? (float)jz : inf;
+        unsigned mlo = 0, mhi = 0;
+        // DIAG: the block with itself, row i keeps the lanes k > i
+        auto rows = [&](auto diag_tag) {
+            constexpr bool DIAG = decltype(diag_tag)::value;
 #pragma unroll 8
-            for (int k = 0; k < kBlock; ++k) {
-                const float4 q = s_jf[w][k];
-                float dx = oi.x - q.x, dy = oi.y - q.y, dz = oi.z - q.z;
+            for (int i = 0; i < kBlock; ++i) {
+                const float4 oi = s_if[w][i];
+                float dx = oi.x - qx, dy = oi.y - qy, dz = oi.z - qz;
                 if (MI) {
                     dx -= Lx * rintf(dx * Lix);
                     dy -= Ly * rintf(dy * Liy);
                     dz -= Lz * rintf(dz * Liz);
                 }
                 const float r2 = dx * dx + dy * dy + dz * dz;
-                const bool use = k >= k0 && q.w != 0.0f;
-                bool in = use && r2 < lo2;
-                if (use && !(r2 < lo2) && r2 < hi2) {
-                    const double4 p = s_jd[w][k];
-                    const double ex = mimg_fp64(pi.x - p.x, box.x, binv.x), ey = mimg_fp64(pi.y - p.y, box.y, binv.y),
-                                 ez = mimg_fp64(pi.z - p.z, box.z, binv.z);
-                    in = ex * ex + ey * ey + ez * ez < rc2;
+                unsigned long long in = __ballot(r2 < lo2);
+                unsigned long long band = __ballot(r2 < hi2) & ~in;
+                if (DIAG) {
+                    const unsigned long long upper = i == kBlock - 1 ? 0ull : ~0ull << (i + 1);
+                    in &= upper;
+                    band &= upper;
                 }
-                m |= (unsigned long long)in << k;
+                if (band) {  // rare: decided by the FP64 distance
+                    bool fin = false;
+                    if ((band >> lane) & 1) {
+                        const double4 p = s_id[w][i];
+                        const double ex = mimg_fp64(p.x - pj.x, box.x, binv.x),
+                                     ey = mimg_fp64(p.y - pj.y, box.y, binv.y),
+                                     ez = mimg_fp64(p.z - pj.z, box.z, binv.z);
+                        fin = ex * ex + ey * ey + ez * ez < rc2;
+                    }
+                    in |= __ballot(fin);
+                }
+                write_lane2(mlo, mhi, in, i);
             }
-        }
+        };
+        if (tile_j[(size_t)t * kBlock] == I * kBlock)
+            rows(std::true_type{});
+        else
+            rows(std::false_type{});
+        m = ((unsigned long long)mhi << 32) | mlo;
         mask[(size_t)t * kBlock + lane] = m;
     }
     // The pair kernels split a tile's in-cutoff pairs (row-major) among the 64 lanes of a wave,
@@ -941,22 +975,32 @@ __global__ __launch_bounds__(256) void k_tile_refresh(int ntiles, const int* __r
         pair_part[blockIdx.x] = s_cnt[0] + s_cnt[1] + s_cnt[2] + s_cnt[3];
 }
 
-__global__ __launch_bounds__(256) void k_sum_pairs(int n, const unsigned long long* __restrict__ part,
-                                                   unsigned long long* __restrict__ total)  // pinned host word
+__global__ __launch_bounds__(1024) void k_sum_pairs(int n, const unsigned long long* __restrict__ part,
+                                                    unsigned long long* __restrict__ total)  // pinned host word
 {
-    __shared__ unsigned long long sh[256];
-    unsigned long long s = 0;
-    for (int i = threadIdx.x; i < n; i += 256)
-        s += part[i];
-    sh[threadIdx.x] = s;
-    __syncthreads();
-    for (int off = 128; off > 0; off >>= 1) {
-        if (threadIdx.x < off)
-            sh[threadIdx.x] += sh[threadIdx.x + off];
-        __syncthreads();
+    // integer sums: exact in any order; eight loads in flight per thread
+    __shared__ unsigned long long sh[16];
+    unsigned long long a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int i0 = threadIdx.x; i0 < n; i0 += 8 * 1024) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int i = i0 + u * 1024;
+            if (i < n)
+                a[u] += part[i];
+        }
     }
-    if (threadIdx.x == 0)
-        total[0] = sh[0];
+    unsigned long long s = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+    for (int off = 32; off > 0; off >>= 1)
+        s += __shfl_xor(s, off);
+    if ((threadIdx.x & 63) == 0)
+        sh[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long tot = 0;
+        for (int k = 0; k < 16; ++k)
+            tot += sh[k];
+        total[0] = tot;
+    }
 }
 
 static inline int nblk(long n, int b) { return (int)((n + b - 1) / b); }
@@ -1039,7 +1083,7 @@ void coef_scan_rows(amoeba_ctx* c)
 // amoeba_get_info after ev_pairs).
 void launch_sum_pairs(amoeba_ctx* c)
 {
-    hipLaunchKernelGGL(k_sum_pairs, dim3(1), dim3(256), 0, c->stream, c->pair_nwg, c->pair_part, c->pairs_host_dev);
+    hipLaunchKernelGGL(k_sum_pairs, dim3(1), dim3(1024), 0, c->stream, c->pair_nwg, c->pair_part, c->pairs_host_dev);
     hipEventRecord(c->ev_pairs, c->stream);
 }
 
