@@ -288,33 +288,56 @@ __global__ __launch_bounds__(256) void k_gather_pos(int npad, const int* __restr
         s_f = 0;
     __syncthreads();
     int f = 0;
-    for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < npad; s += gridDim.x * blockDim.x) {
-        const int a = perm[s];
-        double x = 0.0, y = 0.0, z = 0.0;
-        if (a >= 0) {
-            x = pos[3 * (size_t)a];
-            y = pos[3 * (size_t)a + 1];
-            z = pos[3 * (size_t)a + 2];
-            if (!isfinite(x) || !isfinite(y) || !isfinite(z)) {
-                f |= kFlagNonFinite;
-                x = y = z = 0.0;
-            }
-            x = wrap_box(x, box.x);
-            y = wrap_box(y, box.y);
-            z = wrap_box(z, box.z);
-            const double4 old = pos_s[s];
-            if (old.x != x || old.y != y || old.z != z)
-                f |= kFlagChanged;
-            if (ref) {
-                const double4 r0 = ref[s];
-                const double dx = mimg(x - r0.x, box.x), dy = mimg(y - r0.y, box.y), dz = mimg(z - r0.z, box.z);
-                if (dx * dx + dy * dy + dz * dz > half_buf2)
-                    f |= kFlagStale;
-            }
+    // four slots per thread and round, every round's loads issued before they are used (the
+    // caller-order reads wait on the slot's atom index)
+    constexpr int U = 4;
+    const int stride = gridDim.x * blockDim.x;
+    for (int s0 = blockIdx.x * blockDim.x + threadIdx.x; s0 < npad; s0 += U * stride) {
+        int a[U];
+        double4 old[U], r0[U];
+        double p[U][3];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int s = s0 + u * stride;
+            a[u] = s < npad ? perm[s] : -1;
+            old[u] = s < npad ? pos_s[s] : make_double4(0.0, 0.0, 0.0, 0.0);
+            r0[u] = (ref && s < npad) ? ref[s] : make_double4(0.0, 0.0, 0.0, 0.0);
         }
-        pos_s[s] = make_double4(x, y, z, 0.0);
-        if (ref_out)
-            ref_out[s] = make_double4(x, y, z, 0.0);
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+                p[u][k] = a[u] >= 0 ? pos[3 * (size_t)a[u] + k] : 0.0;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int s = s0 + u * stride;
+            if (s >= npad)
+                break;
+            double x = 0.0, y = 0.0, z = 0.0;
+            if (a[u] >= 0) {
+                x = p[u][0];
+                y = p[u][1];
+                z = p[u][2];
+                if (!isfinite(x) || !isfinite(y) || !isfinite(z)) {
+                    f |= kFlagNonFinite;
+                    x = y = z = 0.0;
+                }
+                x = wrap_box(x, box.x);
+                y = wrap_box(y, box.y);
+                z = wrap_box(z, box.z);
+                if (old[u].x != x || old[u].y != y || old[u].z != z)
+                    f |= kFlagChanged;
+                if (ref) {
+                    const double dx = mimg(x - r0[u].x, box.x), dy = mimg(y - r0[u].y, box.y),
+                                 dz = mimg(z - r0[u].z, box.z);
+                    if (dx * dx + dy * dy + dz * dz > half_buf2)
+                        f |= kFlagStale;
+                }
+            }
+            pos_s[s] = make_double4(x, y, z, 0.0);
+            if (ref_out)
+                ref_out[s] = make_double4(x, y, z, 0.0);
+        }
     }
     if (f != 0)
         atomicOr(&s_f, f);
